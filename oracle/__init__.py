@@ -1,0 +1,176 @@
+"""FP64 CPU oracle for the population likelihood (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark are the only callers. The product path never imports this
+package. The arithmetic lives in ``smcx_oracle.c`` (plain C, double
+precision, index-order sums); this module only marshals numpy arrays.
+
+Parity status of each function (what pins it is listed in the tests under
+``tests/test_oracle_*.py``):
+
+* ``template_sum``, ``logl``: pinned by the Gaussian overlap closed form,
+  the Dirichlet-kernel closed form of sinusoid products, mpmath brute force
+  and the K=0 / zero-residual / scaling invariants.
+* ``logl_grad``: pinned by analytic differentiation of the closed forms and
+  by central finite differences of ``logl``.
+* ``delta_logl_birth_death``: pinned by the exact birth/death zero sum and by
+  differences of ``logl`` between the two particle states.
+* ``reweight_extend``: pinned by the segment factorisation of the white-noise
+  likelihood and by textbook ESS / log-sum-exp special cases.
+* ``leapfrog``: pinned by time reversibility and by the O(eps^2) energy
+  error of the symplectic integrator.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "smcx_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PULSE = 0
+GBSINE = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        I = ctypes.c_int
+        lib.oracle_n_params.argtypes = [I]
+        lib.oracle_set_threads.argtypes = [I]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_get_threads.restype = I
+        lib.oracle_template_sum.argtypes = [I, I64, P, I64, D, D, P]
+        lib.oracle_logl.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P]
+        lib.oracle_logl_grad.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_delta_logl_birth_death.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, P, P]
+        lib.oracle_reweight_extend.argtypes = [I, P, D, D, D, I64, I64, I64, P, P, D, P, P, P, P, P]
+        lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        raise ValueError(f"oracle {name} rejected its arguments (code {rc})")
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
+
+
+def n_params(model: int) -> int:
+    return int(_load().oracle_n_params(int(model)))
+
+
+def template_sum(model: int, theta: np.ndarray, T: int, t_start: float, dt: float) -> np.ndarray:
+    """sum_k h_k(t_s) for s = 0..T-1 (theta is [K, P])."""
+    theta = _f64(theta).reshape(-1, n_params(model))
+    out = np.empty(T, dtype=np.float64)
+    _check(_load().oracle_template_sum(model, theta.shape[0], _p(theta), T, t_start, dt, _p(out)),
+           "template_sum")
+    return out
+
+
+def logl(model, d, t_start, dt, sigma, offsets, theta, beta=None) -> np.ndarray:
+    d, offsets, theta, beta = _f64(d), _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    out = np.empty(N, dtype=np.float64)
+    _check(_load().oracle_logl(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                               _p(theta), _p(beta), _p(out)), "logl")
+    return out
+
+
+def logl_grad(model, d, t_start, dt, sigma, offsets, theta, beta=None):
+    d, offsets, theta, beta = _f64(d), _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    P = n_params(model)
+    out = np.empty(N, dtype=np.float64)
+    grad = np.empty((int(offsets[-1]), P), dtype=np.float64)
+    _check(_load().oracle_logl_grad(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                                    _p(theta), _p(beta), _p(out), _p(grad)), "logl_grad")
+    return out, grad
+
+
+def delta_logl_birth_death(model, d, t_start, dt, sigma, offsets, theta, beta, theta_birth,
+                           death_idx):
+    d, offsets, theta, beta, theta_birth = _f64(d), _i64(offsets), _f64(theta), _f64(beta), \
+        _f64(theta_birth)
+    death_idx = None if death_idx is None else np.ascontiguousarray(death_idx, dtype=np.int32)
+    N = offsets.shape[0] - 1
+    db = np.zeros(N, dtype=np.float64)
+    dd = np.zeros(N, dtype=np.float64)
+    _check(_load().oracle_delta_logl_birth_death(model, _p(d), d.shape[0], t_start, dt, sigma, N,
+                                                 _p(offsets), _p(theta), _p(beta), _p(theta_birth),
+                                                 _p(death_idx), _p(db), _p(dd)),
+           "delta_logl_birth_death")
+    return db, dd
+
+
+def reweight_extend(model, d, t_start, dt, sigma, T1, T2, offsets, theta, delta_beta,
+                    logw_prev=None):
+    d, offsets, theta, logw_prev = _f64(d), _i64(offsets), _f64(theta), _f64(logw_prev)
+    N = offsets.shape[0] - 1
+    logl_ext = np.empty(N)
+    logw = np.empty(N)
+    w = np.empty(N)
+    scal = np.empty(3)
+    _check(_load().oracle_reweight_extend(model, _p(d), t_start, dt, sigma, T1, T2, N, _p(offsets),
+                                          _p(theta), delta_beta, _p(logw_prev), _p(logl_ext),
+                                          _p(logw), _p(w), _p(scal)), "reweight_extend")
+    return logl_ext, logw, w, scal
+
+
+def leapfrog(model, d, t_start, dt, sigma, offsets, q, p, beta, eps, active=None):
+    d, offsets, q, p, beta = _f64(d), _i64(offsets), _f64(q), _f64(p), _f64(beta)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    N = offsets.shape[0] - 1
+    qo = np.empty_like(q)
+    po = np.empty_like(p)
+    lo = np.empty(N)
+    go = np.empty_like(q)
+    _check(_load().oracle_leapfrog(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                                   _p(q), _p(p), _p(beta), eps, _p(act), _p(qo), _p(po), _p(lo),
+                                   _p(go)), "leapfrog")
+    return qo, po, lo, go

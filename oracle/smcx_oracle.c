@@ -1,0 +1,373 @@
+/*
+ * Plain FP64 CPU oracle for the population likelihood of a transdimensional
+ * SMC sampler (Demasi & Del Pozzo, "Massively parallel transdimensional
+ * sampling with data assimilation").
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the checker, not the product: only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it. It shares no code, header, table or helper with the GPU
+ * library. Every quantity is the plain definition, written out in double
+ * precision and summed in index order; there is no blocking, fusion or
+ * reordering. OpenMP only distributes whole particles over threads, so the
+ * result of a particle does not depend on the thread count.
+ *
+ * Conventions (readings of the paper, stated once here):
+ *  - sample times are t_s = t_start + s*dt, s = 0..T-1;
+ *  - a particle is (K, theta_K) in the disjoint union over K of the
+ *    K-component parameter spaces (Sec. "Reversible Jump MCMC"), stored as
+ *    CSR rows: components of particle i are rows offsets[i]..offsets[i+1]-1
+ *    of theta[M][P];
+ *  - the residual is r_s = d_s - (h_0(t_s) + h_1(t_s) + ... + h_{K-1}(t_s)),
+ *    the template sum accumulated left to right;
+ *  - log L = -(1/(2 sigma^2)) sum_s r_s^2 for white noise of standard
+ *    deviation sigma (the time-domain form of the noise-weighted inner
+ *    product, eq. gw_likelihood with a uniform PSD); the constant
+ *    -(T/2) log(2 pi sigma^2) is dropped;
+ *  - every per-particle output is tempered: the tempered bridge
+ *    (eq. prior_bridge) raises L to beta, so outputs are beta * (.).
+ *
+ * Models:
+ *  - MODEL_PULSE (P=3, theta = A, t0, w):
+ *        h(t) = A exp(-(t - t0)^2 / (2 w^2))           (Sec. Gaussian pulses)
+ *    w is read as a standard deviation.
+ *  - MODEL_GBSINE (P=4, theta = A', f0, fdot, phi0):
+ *        h(t) = A' sin(2 pi f0 t + pi fdot t^2 + phi0)
+ *    a single-channel, time-domain stand-in for the Galactic-binary signal
+ *    of Sec. "LISA Galactic binaries" (parameters f0, fdot, A, phi0 of the
+ *    source list there; sky position, polarisation and inclination are not
+ *    modelled).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <omp.h>
+
+#define MODEL_PULSE 0
+#define MODEL_GBSINE 1
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+static const double PI = 3.141592653589793238462643383279;
+
+int oracle_n_params(int model) {
+  if (model == MODEL_PULSE) return 3;
+  if (model == MODEL_GBSINE) return 4;
+  return -1;
+}
+
+void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int oracle_get_threads(void) { return omp_get_max_threads(); }
+
+/* One component template h(t) (model definitions above). */
+static double template_value(int model, const double* th, double t) {
+  if (model == MODEL_PULSE) {
+    double A = th[0], t0 = th[1], w = th[2];
+    double x = t - t0;
+    return A * exp(-(x * x) / (2.0 * w * w));
+  } else {
+    double A = th[0], f0 = th[1], fdot = th[2], phi0 = th[3];
+    double phase = TWO_PI * f0 * t + PI * fdot * t * t + phi0;
+    return A * sin(phase);
+  }
+}
+
+/* Analytic partial derivatives dh/dtheta_p of one template at time t.
+ * Pulse:  dh/dA = e, dh/dt0 = A e x / w^2, dh/dw = A e x^2 / w^3 with
+ *         e = exp(-x^2/(2w^2)), x = t - t0.
+ * GB:     dh/dA' = sin(Phi), dh/df0 = 2 pi t A' cos(Phi),
+ *         dh/dfdot = pi t^2 A' cos(Phi), dh/dphi0 = A' cos(Phi). */
+static void template_partials(int model, const double* th, double t, double* dh) {
+  if (model == MODEL_PULSE) {
+    double A = th[0], t0 = th[1], w = th[2];
+    double x = t - t0;
+    double e = exp(-(x * x) / (2.0 * w * w));
+    dh[0] = e;
+    dh[1] = A * e * x / (w * w);
+    dh[2] = A * e * x * x / (w * w * w);
+  } else {
+    double A = th[0], f0 = th[1], fdot = th[2], phi0 = th[3];
+    double phase = TWO_PI * f0 * t + PI * fdot * t * t + phi0;
+    double s = sin(phase), c = cos(phase);
+    dh[0] = s;
+    dh[1] = TWO_PI * t * A * c;
+    dh[2] = PI * t * t * A * c;
+    dh[3] = A * c;
+  }
+}
+
+/* Sum of K templates at every sample: out[s] = sum_k h_k(t_s). */
+int oracle_template_sum(int model, int64_t K, const double* theta, int64_t T, double t_start,
+                        double dt, double* out) {
+  int P = oracle_n_params(model);
+  if (P < 0 || K < 0 || T < 0 || (K > 0 && !theta) || (T > 0 && !out)) return OR_EINVAL;
+  for (int64_t s = 0; s < T; ++s) {
+    double t = t_start + (double)s * dt;
+    double hs = 0.0;
+    for (int64_t k = 0; k < K; ++k) hs += template_value(model, theta + k * P, t);
+    out[s] = hs;
+  }
+  return OR_OK;
+}
+
+static int check_population(int model, int64_t N, const int64_t* offsets, const double* theta) {
+  if (oracle_n_params(model) < 0 || N < 0 || (N > 0 && !offsets)) return OR_EINVAL;
+  if (N == 0) return OR_OK;
+  if (offsets[0] != 0) return OR_EINVAL;
+  for (int64_t i = 0; i < N; ++i)
+    if (offsets[i + 1] < offsets[i]) return OR_EINVAL;
+  if (offsets[N] > 0 && !theta) return OR_EINVAL;
+  return OR_OK;
+}
+
+/* Residual at sample s for the components of one particle, skipping the
+ * component with local index `skip` (pass -1 to skip none). */
+static double residual_at(int model, const double* d, double t_start, double dt, int64_t s,
+                          int64_t K, const double* th, int P, int64_t skip) {
+  double t = t_start + (double)s * dt;
+  double hs = 0.0;
+  for (int64_t k = 0; k < K; ++k)
+    if (k != skip) hs += template_value(model, th + k * P, t);
+  return d[s] - hs;
+}
+
+/* Tempered log-likelihood of every particle (eq. prior_bridge applied to
+ * the white-noise likelihood of eq. gw_likelihood). */
+int oracle_logl(int model, const double* d, int64_t T, double t_start, double dt, double sigma,
+                int64_t N, const int64_t* offsets, const double* theta, const double* beta,
+                double* logl) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d) ||
+      (N > 0 && !logl))
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double ss = 0.0;
+    for (int64_t s = 0; s < T; ++s) {
+      double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+      ss += r * r;
+    }
+    double b = beta ? beta[i] : 1.0;
+    logl[i] = b * (-0.5 * ss / (sigma * sigma));
+  }
+  return OR_OK;
+}
+
+/* Tempered log-likelihood and its gradient with respect to every component
+ * parameter: grad[m][p] = beta * (1/sigma^2) sum_s r_s dh_m(t_s)/dtheta_p.
+ * The gradient is what the NUTS kernel of Sec. "No-U-Turn-Sampler" needs
+ * (Hamilton's equations use the gradient of the potential). `logl` may be
+ * NULL. */
+int oracle_logl_grad(int model, const double* d, int64_t T, double t_start, double dt,
+                     double sigma, int64_t N, const int64_t* offsets, const double* theta,
+                     const double* beta, double* logl, double* grad) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d))
+    return OR_EINVAL;
+  if (N > 0 && offsets[N] > 0 && !grad) return OR_EINVAL;
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double* g = grad ? grad + offsets[i] * P : NULL;
+    double b = beta ? beta[i] : 1.0;
+    double ss = 0.0;
+    for (int64_t k = 0; k < K * P; ++k) g[k] = 0.0;
+    for (int64_t s = 0; s < T; ++s) {
+      double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+      ss += r * r;
+      double t = t_start + (double)s * dt;
+      for (int64_t k = 0; k < K; ++k) {
+        double dh[4];
+        template_partials(model, th + k * P, t, dh);
+        for (int p = 0; p < P; ++p) g[k * P + p] += r * dh[p];
+      }
+    }
+    for (int64_t k = 0; k < K * P; ++k) g[k] = b * (g[k] / (sigma * sigma));
+    if (logl) logl[i] = b * (-0.5 * ss / (sigma * sigma));
+  }
+  return OR_OK;
+}
+
+/* Change of tempered log-likelihood for the nested birth/death moves of
+ * Sec. "Reversible Jump MCMC" (k' = k +- 1, unit Jacobian):
+ *   birth of theta_new appended at index K:
+ *     D_birth = beta [ <r, h_new> - 0.5 <h_new, h_new> ] / sigma^2
+ *   death of local index j:
+ *     D_death = -beta [ <r_not_j, h_j> - 0.5 <h_j, h_j> ] / sigma^2
+ * where r is the residual of the current particle and r_not_j the residual
+ * with component j left out of the index-order sum. Both follow from
+ * expanding -|r'|^2/(2 sigma^2) + |r|^2/(2 sigma^2). death_idx[i] = -1
+ * gives D_death = 0; theta_birth or death_idx may be NULL (that output is
+ * then not written). */
+int oracle_delta_logl_birth_death(int model, const double* d, int64_t T, double t_start,
+                                  double dt, double sigma, int64_t N, const int64_t* offsets,
+                                  const double* theta, const double* beta,
+                                  const double* theta_birth, const int32_t* death_idx,
+                                  double* d_birth, double* d_death) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d))
+    return OR_EINVAL;
+  if (N > 0 && ((theta_birth && !d_birth) || (death_idx && !d_death))) return OR_EINVAL;
+  for (int64_t i = 0; death_idx && i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    if (death_idx[i] < -1 || death_idx[i] >= K) return OR_EINVAL;
+  }
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double b = beta ? beta[i] : 1.0;
+    if (theta_birth) {
+      const double* tb = theta_birth + i * P;
+      double x = 0.0, y = 0.0;
+      for (int64_t s = 0; s < T; ++s) {
+        double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+        double h = template_value(model, tb, t_start + (double)s * dt);
+        x += r * h;
+        y += h * h;
+      }
+      d_birth[i] = b * (x - 0.5 * y) / (sigma * sigma);
+    }
+    if (death_idx) {
+      int64_t j = death_idx[i];
+      if (j < 0) {
+        d_death[i] = 0.0;
+      } else {
+        double x = 0.0, y = 0.0;
+        for (int64_t s = 0; s < T; ++s) {
+          double r = residual_at(model, d, t_start, dt, s, K, th, P, j);
+          double h = template_value(model, th + j * P, t_start + (double)s * dt);
+          x += r * h;
+          y += h * h;
+        }
+        d_death[i] = -(b * (x - 0.5 * y) / (sigma * sigma));
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* Data-assimilation reweighting (eq. reuse_bridge with the incremental
+ * weight of eq. incremental_weight, the ESS of eq. ess and the evidence
+ * ratio Z_t/Z_{t-1} of Sec. "Sequential Monte Carlo").
+ *
+ * For white noise the likelihood factorises over samples, so the ratio
+ * p(theta|d2)/p(theta|d1) of eq. reuse_bridge equals, up to a constant,
+ * exp(logl_ext) with logl_ext the untempered log-likelihood of the new
+ * samples [T1, T2) only:
+ *   logl_ext_i = -(1/(2 sigma^2)) sum_{s=T1}^{T2-1} r_s^2
+ * (templates at the absolute times t_s of the longer segment d, which has
+ * T2 samples). Raising the ratio to beta and stepping beta by delta_beta
+ * gives the log incremental weight
+ *   logw_i = logw_prev_i + delta_beta * logl_ext_i
+ * (logw_prev = 0 when NULL, i.e. uniform previous weights). Then, with
+ * m = max_i logw_i:
+ *   w_norm_i = exp(logw_i - m) / sum_j exp(logw_j - m)
+ *   ESS = (sum w)^2 / sum w^2 = 1 / sum_i w_norm_i^2
+ *   logZ increment = log sum_i exp(logw_i) - log sum_i exp(logw_prev_i)
+ *                  (= ... - log N for uniform previous weights).
+ * scalars = {ESS, logZ increment, m}. N = 0 gives {0, 0, -inf}. */
+int oracle_reweight_extend(int model, const double* d, double t_start, double dt, double sigma,
+                           int64_t T1, int64_t T2, int64_t N, const int64_t* offsets,
+                           const double* theta, double delta_beta, const double* logw_prev,
+                           double* logl_ext, double* logw, double* w_norm, double* scalars) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T1 < 0 || T2 < T1 ||
+      (T2 > 0 && !d) || !scalars)
+    return OR_EINVAL;
+  if (N > 0 && (!logl_ext || !logw || !w_norm)) return OR_EINVAL;
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double ss = 0.0;
+    for (int64_t s = T1; s < T2; ++s) {
+      double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+      ss += r * r;
+    }
+    logl_ext[i] = -0.5 * ss / (sigma * sigma);
+  }
+  if (N == 0) {
+    scalars[0] = 0.0;
+    scalars[1] = 0.0;
+    scalars[2] = -INFINITY;
+    return OR_OK;
+  }
+  double m = -INFINITY;
+  for (int64_t i = 0; i < N; ++i) {
+    logw[i] = (logw_prev ? logw_prev[i] : 0.0) + delta_beta * logl_ext[i];
+    if (logw[i] > m) m = logw[i];
+  }
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    double e = exp(logw[i] - m);
+    s1 += e;
+    s2 += e * e;
+  }
+  for (int64_t i = 0; i < N; ++i) w_norm[i] = exp(logw[i] - m) / s1;
+  double lse_prev;
+  if (logw_prev) {
+    double mp = -INFINITY, sp = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+      if (logw_prev[i] > mp) mp = logw_prev[i];
+    for (int64_t i = 0; i < N; ++i) sp += exp(logw_prev[i] - mp);
+    lse_prev = mp + log(sp);
+  } else {
+    lse_prev = log((double)N);
+  }
+  scalars[0] = s1 * s1 / s2;
+  scalars[1] = m + log(s1) - lse_prev;
+  scalars[2] = m;
+  return OR_OK;
+}
+
+/* One leapfrog step of Hamiltonian dynamics (Sec. "No-U-Turn-Sampler"),
+ * H = -log p(theta) + 0.5 r^T r with an identity mass matrix, for the
+ * tempered target whose log density is beta * logL (uniform prior: zero
+ * gradient inside its box):
+ *   p_half = p + (eps/2) grad(beta logL)(q)
+ *   q'     = q + eps p_half
+ *   p'     = p_half + (eps/2) grad(beta logL)(q')
+ * Particles with active[i] == 0 (active may be NULL = all active) are copied
+ * unchanged. Outputs q', p' and the tempered logL and gradient at q'. */
+int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, double dt,
+                    double sigma, int64_t N, const int64_t* offsets, const double* q,
+                    const double* p, const double* beta, double eps, const uint8_t* active,
+                    double* q_out, double* p_out, double* logl_out, double* grad_out) {
+  if (check_population(model, N, offsets, q) != OR_OK || T < 0 || (T > 0 && !d)) return OR_EINVAL;
+  int64_t M = N > 0 ? offsets[N] : 0;
+  if (M > 0 && (!p || !q_out || !p_out || !grad_out)) return OR_EINVAL;
+  if (N > 0 && !logl_out) return OR_EINVAL;
+  int P = oracle_n_params(model);
+  /* gradient at the start point, into grad_out as scratch */
+  int rc = oracle_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q, beta, logl_out,
+                            grad_out);
+  if (rc != OR_OK) return rc;
+  for (int64_t i = 0; i < N; ++i) {
+    int on = active ? active[i] != 0 : 1;
+    for (int64_t m = offsets[i] * P; m < offsets[i + 1] * P; ++m) {
+      if (on) {
+        double ph = p[m] + 0.5 * eps * grad_out[m];
+        p_out[m] = ph;
+        q_out[m] = q[m] + eps * ph;
+      } else {
+        p_out[m] = p[m];
+        q_out[m] = q[m];
+      }
+    }
+  }
+  rc = oracle_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q_out, beta, logl_out,
+                        grad_out);
+  if (rc != OR_OK) return rc;
+  for (int64_t i = 0; i < N; ++i) {
+    int on = active ? active[i] != 0 : 1;
+    if (!on) continue;
+    for (int64_t m = offsets[i] * P; m < offsets[i + 1] * P; ++m)
+      p_out[m] = p_out[m] + 0.5 * eps * grad_out[m];
+  }
+  return OR_OK;
+}

@@ -1,0 +1,208 @@
+"""Seeded synthetic workloads for the population likelihood.
+
+This module only draws random numbers: injection parameters, white noise,
+particle populations (ragged component counts and per-component parameters
+drawn from the uniform priors), tempering values and birth/death proposals.
+It contains none of the likelihood arithmetic. The data vector is assembled
+by the caller as ``noise + sum of injected templates``; the templates come
+from whichever implementation the caller is exercising.
+
+Workload recipes follow the paper's two toy problems:
+
+* Gaussian pulses (Sec. "Sequence of gaussian pulses"): components with
+  parameters (amplitude, centre, width) drawn from uniform priors, analysed
+  in the time domain.
+* Simplified Galactic binaries (Sec. "LISA Galactic binaries"): a chirping
+  sinusoid per source, A' sin(2 pi f0 t + pi fdot t^2 + phi0), with the
+  amplitude prior uniform in log10 A and the data rescaled by 1e21 so that
+  A' = A * 1e21 is O(1).
+
+The configurations (sizes, priors, seeds) are:
+
+=====  =====================================================================
+pulse_small   T=1000 on t in [0,1], 3 injections, N=256, K~U{0..10}, beta=1
+pulse_batch   T=4096 on t in [0,1], 8 injections, N=16384, K~U{0..20},
+              beta~U[0,1] per particle
+gb_grad       T=2^17 at dt=15 s, 10 injections, N=4096, K~U{0..30}, beta=1
+pulse_mutate  pulse_batch data, N=8192, K~U{0..20}, common beta=0.5, one
+              birth (prior draw) and one death (uniform index) per particle
+gb_extend     T=2^18 at dt=15 s, 20 injections, first 2^17 samples are the
+              earlier segment, N=65536, K~U{0..50}
+=====  =====================================================================
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+PULSE = 0
+GBSINE = 1
+
+N_PARAMS = {PULSE: 3, GBSINE: 4}
+
+# Uniform prior boxes, one row per parameter: (low, high).
+PULSE_PRIOR = np.array([[2.0, 6.0],      # amplitude A
+                        [0.1, 0.9],      # centre t0
+                        [0.01, 0.05]])   # width w (a standard deviation)
+GB_PRIOR = np.array([[-22.0, -21.0],     # log10 A (before the 1e21 rescale)
+                     [1.000e-3, 1.010e-3],  # f0 [Hz]
+                     [1e-18, 1e-16],     # fdot [Hz/s]
+                     [0.0, 2.0 * np.pi]])   # phi0 [rad]
+GB_RESCALE_LOG10 = 21.0
+
+CONFIG_NAMES = ("pulse_small", "pulse_batch", "gb_grad", "pulse_mutate", "gb_extend")
+CONFIG_SEEDS = (101, 102, 103, 104, 105)
+
+_BASE = {
+    "pulse_small": dict(model=PULSE, T=1000, t_start=0.0, dt=1.0 / 999.0, sigma=1.0,
+                        n_inj=3, N=256, k_lo=0, k_hi=10, beta="one"),
+    "pulse_batch": dict(model=PULSE, T=4096, t_start=0.0, dt=1.0 / 4095.0, sigma=1.0,
+                        n_inj=8, N=16384, k_lo=0, k_hi=20, beta="uniform"),
+    "gb_grad": dict(model=GBSINE, T=1 << 17, t_start=0.0, dt=15.0, sigma=1.0,
+                    n_inj=10, N=4096, k_lo=0, k_hi=30, beta="one"),
+    "pulse_mutate": dict(model=PULSE, T=4096, t_start=0.0, dt=1.0 / 4095.0, sigma=1.0,
+                         n_inj=8, N=8192, k_lo=0, k_hi=20, beta="half",
+                         rj=True, eps=1e-3, max_depth=8),
+    "gb_extend": dict(model=GBSINE, T=1 << 18, t_start=0.0, dt=15.0, sigma=1.0,
+                      n_inj=20, N=65536, k_lo=0, k_hi=50, beta="one",
+                      T1=1 << 17, T2=1 << 18),
+}
+
+
+@dataclass
+class Workload:
+    """One seeded synthetic problem instance (host arrays, FP64 / int64)."""
+
+    name: str
+    model: int
+    T: int
+    t_start: float
+    dt: float
+    sigma: float
+    inj: np.ndarray            # [n_inj, P] injected component parameters
+    noise: np.ndarray          # [T] white noise, N(0, sigma^2)
+    offsets: np.ndarray        # [N+1] int64 prefix sums of K_i
+    theta: np.ndarray          # [M, P] component parameters, CSR rows
+    beta: np.ndarray           # [N] inverse temperatures
+    k_max: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def M(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def P(self) -> int:
+        return N_PARAMS[self.model]
+
+    @property
+    def K(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+
+def draw_components(model: int, n: int, rng: np.random.Generator) -> np.ndarray:
+    """Draw ``n`` component parameter rows from the uniform prior box.
+
+    Pulses: (A, t0, w). Galactic binaries: (A', f0, fdot, phi0) with
+    A' = 10**(log10 A + 21) and log10 A uniform.
+    """
+    if model == PULSE:
+        u = rng.random((n, 3))
+        return PULSE_PRIOR[:, 0] + u * (PULSE_PRIOR[:, 1] - PULSE_PRIOR[:, 0])
+    u = rng.random((n, 4))
+    raw = GB_PRIOR[:, 0] + u * (GB_PRIOR[:, 1] - GB_PRIOR[:, 0])
+    out = raw.copy()
+    out[:, 0] = 10.0 ** (raw[:, 0] + GB_RESCALE_LOG10)
+    return out
+
+
+def draw_counts(n: int, k_lo: int, k_hi: int, rng: np.random.Generator) -> np.ndarray:
+    """Inclusive discrete-uniform component counts K_i in {k_lo..k_hi}."""
+    return rng.integers(k_lo, k_hi + 1, size=n).astype(np.int64)
+
+
+def counts_to_offsets(K: np.ndarray) -> np.ndarray:
+    off = np.zeros(K.shape[0] + 1, dtype=np.int64)
+    np.cumsum(K, out=off[1:])
+    return off
+
+
+def make_config(name_or_idx, seed: Optional[int] = None, **overrides) -> Workload:
+    """Build one named workload.
+
+    ``overrides`` may replace any size field (``T``, ``N``, ``n_inj``,
+    ``k_lo``, ``k_hi``, ``T1``, ``T2``, ``beta`` mode ...) so that tests can
+    run the same recipe at reduced sizes.
+    """
+    if isinstance(name_or_idx, int):
+        name = CONFIG_NAMES[name_or_idx]
+    else:
+        name = name_or_idx
+    cfg = dict(_BASE[name])
+    if "T" in overrides and "dt" not in overrides and cfg["model"] == PULSE:
+        # keep the time axis on [0, 1] as for the full-size pulse problems
+        overrides["dt"] = 1.0 / (overrides["T"] - 1)
+    cfg.update(overrides)
+    if seed is None:
+        seed = CONFIG_SEEDS[CONFIG_NAMES.index(name)]
+    s_inj, s_noise, s_part, s_beta, s_rj, s_mom = np.random.SeedSequence(seed).spawn(6)
+    r_inj = np.random.default_rng(s_inj)
+    r_noise = np.random.default_rng(s_noise)
+    r_part = np.random.default_rng(s_part)
+    r_beta = np.random.default_rng(s_beta)
+
+    model = cfg["model"]
+    T = int(cfg["T"])
+    inj = draw_components(model, int(cfg["n_inj"]), r_inj)
+    noise = cfg["sigma"] * r_noise.standard_normal(T)
+    K = draw_counts(int(cfg["N"]), int(cfg["k_lo"]), int(cfg["k_hi"]), r_part)
+    offsets = counts_to_offsets(K)
+    theta = draw_components(model, int(offsets[-1]), r_part)
+    N = K.shape[0]
+    mode = cfg["beta"]
+    if mode == "one":
+        beta = np.ones(N)
+    elif mode == "half":
+        beta = np.full(N, 0.5)
+    elif mode == "uniform":
+        beta = r_beta.random(N)
+    else:
+        beta = np.full(N, float(mode))
+
+    extra = {"seed": seed}
+    for key in ("T1", "T2", "eps", "max_depth"):
+        if key in cfg:
+            extra[key] = cfg[key]
+    if cfg.get("rj") or overrides.get("rj"):
+        r_rj = np.random.default_rng(s_rj)
+        extra["theta_birth"] = draw_components(model, N, r_rj)
+        u = r_rj.random(N)
+        death = np.where(K > 0, np.floor(u * np.maximum(K, 1)).astype(np.int64), -1)
+        extra["death_idx"] = np.minimum(death, K - 1).astype(np.int32)
+        extra["momentum_rng"] = np.random.default_rng(s_mom)
+    return Workload(name=name, model=model, T=T, t_start=float(cfg["t_start"]),
+                    dt=float(cfg["dt"]), sigma=float(cfg["sigma"]), inj=inj, noise=noise,
+                    offsets=offsets, theta=theta, beta=beta, k_max=int(cfg["k_hi"]), extra=extra)
+
+
+def subsample(w: Workload, idx: np.ndarray) -> Workload:
+    """Return the workload restricted to particles ``idx`` (in that order)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    K = w.K[idx]
+    off = counts_to_offsets(K)
+    rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx]) if len(idx) else \
+        np.zeros(0, dtype=np.int64)
+    theta = w.theta[rows].reshape(-1, w.P)
+    extra = dict(w.extra)
+    for key in ("theta_birth", "death_idx"):
+        if key in extra:
+            extra[key] = extra[key][idx]
+    return Workload(name=w.name + "_sub", model=w.model, T=w.T, t_start=w.t_start, dt=w.dt,
+                    sigma=w.sigma, inj=w.inj, noise=w.noise, offsets=off, theta=theta,
+                    beta=w.beta[idx], k_max=w.k_max, extra=extra)
