@@ -1,0 +1,206 @@
+/*
+ * smcx.h — C ABI of the population likelihood library for transdimensional
+ * Sequential Monte Carlo (Demasi & Del Pozzo, "Massively parallel
+ * transdimensional sampling with data assimilation").
+ *
+ * What the library computes. A population of N particles, particle i being
+ * (K_i, theta_i) with K_i components of P parameters each (the disjoint
+ * union over k of {k} x theta_k, Sec. "Reversible Jump MCMC"). Data d are T
+ * samples at times t_s = t_start + s*dt with white noise of standard
+ * deviation sigma. For each particle the library synthesises the summed
+ * template, forms the residual
+ *     r_s = d_s - sum_{k=0}^{K_i-1} h_k(t_s)
+ * and reduces the noise-weighted inner product into the log-likelihood
+ *     log L_i = -(1/(2 sigma^2)) sum_s r_s^2
+ * (the time-domain white-noise form of eq. gw_likelihood; the constant
+ * -(T/2) log(2 pi sigma^2) is dropped). All per-particle outputs are
+ * tempered, i.e. multiplied by the particle's inverse temperature beta_i
+ * (eq. prior_bridge raises the likelihood to beta).
+ *
+ * Models (component templates):
+ *   SMCX_PULSE  (P=3, theta = A, t0, w):  h = A exp(-(t-t0)^2 / (2 w^2))
+ *               (Sec. "Sequence of gaussian pulses"; w is a standard
+ *               deviation).
+ *   SMCX_GBSINE (P=4, theta = A', f0 [Hz], fdot [Hz/s], phi0 [rad]):
+ *               h = A' sin(2 pi f0 t + pi fdot t^2 + phi0)
+ *               (single-channel time-domain stand-in for the Galactic
+ *               binaries of Sec. "LISA Galactic binaries"; A' is the
+ *               amplitude after rescaling the data by 1e21).
+ *
+ * Layout. The population is CSR: offsets[N+1] (int64, offsets[0] = 0,
+ * non-decreasing, K_i = offsets[i+1]-offsets[i]), theta[M][P] (FP64,
+ * row-major, M = offsets[N]); gradients use the layout of theta.
+ *
+ * Ownership and streams. Every array argument is a DEVICE pointer owned by
+ * the caller (for example torch.Tensor.data_ptr()). The library owns only
+ * the problem handle and the device workspace it allocates in
+ * smcx_problem_create. Compute calls allocate nothing, never synchronise
+ * the host, and run asynchronously on `hip_stream` (a hipStream_t; NULL is
+ * the default stream); results are valid in stream order. Calls that share
+ * one problem handle must be ordered on one stream (they share workspace).
+ *
+ * Precision. Template synthesis and residual arithmetic run in FP32; the
+ * Galactic-binary phase is formed and reduced modulo one cycle in FP64; the
+ * per-particle inner products are accumulated in FP64 and all outputs are
+ * FP64.
+ *
+ * Errors. Every call returns SMCX_OK or a negative code and never throws
+ * across the ABI; smcx_last_error() gives a message for the calling thread.
+ * Argument errors the host can see (null pointers, negative sizes, sizes
+ * above what the handle was created for, empty sample ranges) are reported
+ * before any launch and leave all outputs untouched. Errors that depend on
+ * device data (non-monotone offsets, offsets[N] != M, K_i > k_max, a death index
+ * >= K_i) cannot be seen by the host: the kernels write NaN into the
+ * affected particle's outputs and raise a device flag that
+ * smcx_device_status() reports (and clears). NaN or Inf parameters only
+ * affect their own particle's per-particle outputs.
+ */
+#ifndef SMCX_H
+#define SMCX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smcx_problem smcx_problem;
+
+enum {
+  SMCX_OK = 0,
+  SMCX_EINVAL = -1,   /* bad argument, detected before launch */
+  SMCX_ENOMEM = -2,   /* device allocation failed (create only) */
+  SMCX_EDEVICE = -3,  /* HIP runtime error, or a device-side flag was raised */
+  SMCX_ECAPTURE = -4  /* call not allowed while the stream is being captured */
+};
+
+enum { SMCX_PULSE = 0, SMCX_GBSINE = 1 };
+
+/* Create a problem handle for one data vector.
+ *   model      SMCX_PULSE or SMCX_GBSINE
+ *   d_dev      [T] FP64 device data; copied (to FP32, plus FP64 energy
+ *              prefix sums) during the call, need not outlive the handle
+ *   T          number of samples, 1 <= T <= 2^22
+ *   t_start,dt time of sample 0 and sample spacing (dt > 0)
+ *   sigma      white-noise standard deviation (> 0)
+ *   k_max      largest K_i any call will pass (1..512)
+ *   n_max      largest N any call will pass (>= 0)
+ *   m_max      largest M = offsets[N] any call will pass (>= 0)
+ *   hip_stream stream used for the set-up copies; the call synchronises it
+ *   out        receives the handle
+ * Returns SMCX_EINVAL for bad sizes, SMCX_ENOMEM if the workspace cannot be
+ * allocated. This is the only call that allocates or synchronises. */
+int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_start, double dt,
+                        double sigma, int32_t k_max, int64_t n_max, int64_t m_max,
+                        void* hip_stream, smcx_problem** out);
+
+/* Free the handle and its workspace (after synchronising its last stream).
+ * NULL is accepted. */
+int smcx_problem_destroy(smcx_problem* prob);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* smcx_last_error(void);
+
+/* Synchronise `hip_stream`, then report and clear the device-side error
+ * flag: SMCX_OK if no kernel saw invalid device data since the last call,
+ * SMCX_EDEVICE otherwise (smcx_last_error() names the first cause). */
+int smcx_device_status(smcx_problem* prob, void* hip_stream);
+
+/* Tempered log-likelihood of every particle.
+ *   logl[i] = beta_i * ( -(1/(2 sigma^2)) sum_{s<T} r_s^2 )
+ * (eq. prior_bridge with the white-noise likelihood of eq. gw_likelihood).
+ *   N          number of particles, 0 <= N <= n_max
+ *   offsets    [N+1] int64 CSR offsets
+ *   M          rows of theta, 0 <= M <= m_max; the kernels check
+ *              offsets[N] == M on the device and touch no row >= M
+ *   theta      [M][P] FP64
+ *   beta       [N] FP64 inverse temperatures, or NULL for beta = 1
+ *   logl       [N] FP64 output
+ * A particle with K_i = 0 gets beta_i * (-||d||^2 / (2 sigma^2)), with
+ * ||d||^2 taken in FP64 at create. */
+int logl_batch(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+               const double* theta, const double* beta, double* logl, void* hip_stream);
+
+/* Tempered log-likelihood and its gradient with respect to every component
+ * parameter, in one fused forward + adjoint pass that recomputes templates
+ * instead of storing them:
+ *   grad[m][p] = beta_i * (1/sigma^2) sum_s r_s dh_m(t_s)/dtheta_p
+ * for the rows m of particle i. Hamilton's equations of the NUTS kernel
+ * (Sec. "No-U-Turn-Sampler") need this gradient of the log target.
+ *   logl       [N] FP64 output, or NULL to skip it
+ *   grad       [M][P] FP64 output (may be NULL only if M = 0)
+ * Other arguments as logl_batch. */
+int logl_grad_batch(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                    const double* theta, const double* beta, double* logl, double* grad,
+                    void* hip_stream);
+
+/* Change of the tempered log-likelihood under the nested birth and death
+ * moves of Sec. "Reversible Jump MCMC" (k' = k +- 1, unit Jacobian; the
+ * acceptance ratio of eq. rj_acceptance needs exactly this change):
+ *   birth of theta_birth[i] appended after the K_i existing components:
+ *     dlogl_birth[i] =  beta_i (<r, h_new> - <h_new, h_new>/2) / sigma^2
+ *   death of the component with local index j = death_idx[i]:
+ *     dlogl_death[i] = -beta_i (<r_-j, h_j> - <h_j, h_j>/2) / sigma^2
+ * where r_-j is the residual with component j left out of the index-order
+ * template sum. Both are computed in one pass over the data. A birth
+ * followed by the death of the appended component gives exactly
+ * dlogl_birth + dlogl_death = 0 (same arithmetic on both sides).
+ *   theta_birth [N][P] FP64, or NULL (then dlogl_birth is not written)
+ *   death_idx   [N] int32 local index in [0, K_i) or -1 for "no death"
+ *               (dlogl_death[i] = 0), or NULL (dlogl_death not written)
+ *   dlogl_birth, dlogl_death  [N] FP64 outputs (NULL allowed only together
+ *               with a NULL theta_birth / death_idx respectively) */
+int delta_logl_birth_death(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                           const double* theta, const double* beta, const double* theta_birth,
+                           const int32_t* death_idx, double* dlogl_birth, double* dlogl_death,
+                           void* hip_stream);
+
+/* Data-assimilation reweighting (eq. reuse_bridge, eq. incremental_weight,
+ * eq. ess and the evidence ratio of Sec. "Sequential Monte Carlo").
+ * The handle is built over the longer data segment d2; samples [0, T1) are
+ * the earlier segment d1 and [T1, T2) the new samples. For white noise the
+ * ratio p(theta|d2)/p(theta|d1) of eq. reuse_bridge is, up to a constant,
+ * exp(logl_ext) with the untempered log-likelihood of the new samples
+ *   logl_ext[i] = -(1/(2 sigma^2)) sum_{s=T1}^{T2-1} r_s^2
+ * (templates at the absolute times of d2), so the log incremental weight
+ * for a step delta_beta is
+ *   logw[i] = logw_prev[i] + delta_beta * logl_ext[i]
+ * and, with m = max_i logw[i],
+ *   w_norm[i]  = exp(logw[i] - m) / sum_j exp(logw[j] - m)
+ *   scalars[0] = ESS = (sum w)^2 / sum w^2
+ *   scalars[1] = log Z_t/Z_{t-1} = log sum exp(logw) - log sum exp(logw_prev)
+ *                (log N for uniform previous weights)
+ *   scalars[2] = m
+ *   T1, T2     0 <= T1 < T2 <= T (the handle's T)
+ *   logw_prev  [N] FP64 previous log weights, or NULL for uniform
+ *   logl_ext, logw, w_norm [N] FP64 outputs, scalars [3] FP64 output
+ * The population reductions are done in a fixed order (deterministic).
+ * N = 0 gives scalars {0, 0, -inf}. */
+int reweight_extend(smcx_problem* prob, int64_t T1, int64_t T2, int64_t N, const int64_t* offsets,
+                    int64_t M, const double* theta, double delta_beta, const double* logw_prev,
+                    double* logl_ext, double* logw, double* w_norm, double* scalars,
+                    void* hip_stream);
+
+/* Synthesise a noise-free signal: out[s] = sum_{k<K} h_k(t_s), s < T, in
+ * FP64 (device libm exp/sin), for building injected data sets.
+ *   theta [K][P] FP64 device, out [T] FP64 device. K >= 0, T >= 0. */
+int smcx_template_sum(int model, int64_t K, const double* theta, int64_t T, double t_start,
+                      double dt, double* out, void* hip_stream);
+
+/* Plain reference form of logl_grad_batch, the comparison point for the
+ * batched kernels: one particle per pair of launches (a forward kernel that
+ * stores the FP64 residual, then an adjoint kernel), FP64 arithmetic and
+ * FP64 device-libm exp/sin/cos throughout, block reductions, no batching.
+ * Same outputs as logl_grad_batch (logl may not be NULL here), but the CSR
+ * offsets are a HOST array (offsets_host[N+1]) because the host loop over
+ * particles needs each K_i to size its launches. It is a baseline, not a
+ * production path. */
+int smcx_plain_logl_grad(smcx_problem* prob, int64_t N, const int64_t* offsets_host, int64_t M,
+                         const double* theta, const double* beta, double* logl, double* grad,
+                         void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMCX_H */

@@ -1,0 +1,436 @@
+// C ABI of libsmcx: problem handle, argument checks, workspace, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/smcx.h"
+#include "smcx_internal.h"
+
+using smcx::Tiling;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SMCX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus s = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &s) != hipSuccess) return false;
+  return s != hipStreamCaptureStatusNone;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+enum Kind { kFwd = 0, kGrad = 1, kDelta = 2, kNumKinds = 3 };
+
+// Default tiling per (model, kind, T). It depends only on the model and the
+// length of the sample axis, never on N, so a particle's arithmetic (and
+// hence its result bit pattern) does not depend on the batch it is in.
+Tiling default_tiling(int model, int kind, int64_t T) {
+  Tiling t;
+  if (model == SMCX_PULSE) {
+    if (kind == kDelta)
+      t.S = 16;
+    else
+      t.S = T >= 2048 ? 64 : (T >= 512 ? 16 : 8);
+    const int64_t tile = 64 * (int64_t)t.S;
+    t.chunk_len = T <= 8192 ? round_up(T, tile) : round_up(8192, tile);
+  } else {
+    t.S = kind == kDelta ? 16 : 32;
+    t.chunk_len = 8192;
+  }
+  t.nch = (int)((T + t.chunk_len - 1) / t.chunk_len);
+  return t;
+}
+
+Tiling with_range(Tiling t, int64_t len) {
+  t.nch = len <= 0 ? 0 : (int)((len + t.chunk_len - 1) / t.chunk_len);
+  return t;
+}
+
+}  // namespace
+
+struct smcx_problem {
+  int model = 0;
+  int P = 0;
+  int64_t T = 0;
+  double t_start = 0, dt = 0, sigma = 0, inv_sigma2 = 0;
+  int32_t k_max = 0;
+  int64_t n_max = 0, m_max = 0;
+  int device = 0;
+  float* d32 = nullptr;
+  double* d64 = nullptr;
+  std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
+  Tiling tiling[kNumKinds];
+  int max_nch = 0;
+  int32_t* order = nullptr;
+  int32_t* n_active = nullptr;
+  int* flag = nullptr;
+  double* part = nullptr;   // [max_nch][n_max][4]
+  double* part_g = nullptr; // [nch_grad][m_max][P]
+  double* rbuf = nullptr;   // plain form residual [T]
+  double* bpart = nullptr;  // plain form block partials
+};
+
+namespace {
+
+void free_problem(smcx_problem* p) {
+  if (!p) return;
+  (void)hipFree(p->d32);
+  (void)hipFree(p->d64);
+  (void)hipFree(p->order);
+  (void)hipFree(p->n_active);
+  (void)hipFree(p->flag);
+  (void)hipFree(p->part);
+  (void)hipFree(p->part_g);
+  (void)hipFree(p->rbuf);
+  (void)hipFree(p->bpart);
+  delete p;
+}
+
+int check_pop(const smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+              const double* theta) {
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (N < 0) return fail(SMCX_EINVAL, "N = %lld is negative", (long long)N);
+  if (N > p->n_max)
+    return fail(SMCX_EINVAL, "N = %lld exceeds n_max = %lld of the handle", (long long)N,
+                (long long)p->n_max);
+  if (M < 0) return fail(SMCX_EINVAL, "M = %lld is negative", (long long)M);
+  if (M > p->m_max)
+    return fail(SMCX_EINVAL, "M = %lld exceeds m_max = %lld of the handle", (long long)M,
+                (long long)p->m_max);
+  if (N > 0 && !offsets) return fail(SMCX_EINVAL, "offsets is NULL");
+  if (M > 0 && !theta) return fail(SMCX_EINVAL, "theta is NULL");
+  return SMCX_OK;
+}
+
+smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, const double* theta,
+                        const double* beta, const Tiling& t, int64_t s_lo, int64_t s_hi) {
+  smcx::PopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.d32 = p->d32;
+  a.s_lo = s_lo;
+  a.s_hi = s_hi;
+  a.t_start = p->t_start;
+  a.dt = p->dt;
+  a.inv_sigma2 = p->inv_sigma2;
+  a.offsets = offsets;
+  a.theta = theta;
+  a.beta = beta;
+  a.N = N;
+  a.k_max = p->k_max;
+  a.m_max = p->m_max;
+  a.order = p->order;
+  a.n_active = p->n_active;
+  a.nch = t.nch;
+  a.chunk_len = t.chunk_len;
+  a.part = p->part;
+  a.part_g = p->part_g;
+  a.flag = p->flag;
+  return a;
+}
+
+smcx::PrepArgs prep_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                         const double* beta, double k0, int tempered) {
+  smcx::PrepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.offsets = offsets;
+  a.beta = beta;
+  a.N = N;
+  a.M = M;
+  a.k_max = p->k_max;
+  a.m_max = p->m_max;
+  a.k0_value = k0;
+  a.P = p->P;
+  a.order = p->order;
+  a.n_active = p->n_active;
+  a.flag = p->flag;
+  a.tempered = tempered;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* smcx_last_error(void) { return g_last_error.c_str(); }
+
+int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_start, double dt,
+                        double sigma, int32_t k_max, int64_t n_max, int64_t m_max,
+                        void* hip_stream, smcx_problem** out) {
+  g_last_error.clear();
+  if (!out) return fail(SMCX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (model != SMCX_PULSE && model != SMCX_GBSINE)
+    return fail(SMCX_EINVAL, "unknown model %d", model);
+  if (!d_dev) return fail(SMCX_EINVAL, "d_dev is NULL");
+  if (T < 1 || T > (int64_t(1) << 22)) return fail(SMCX_EINVAL, "T = %lld outside [1, 2^22]", (long long)T);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SMCX_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(t_start)) return fail(SMCX_EINVAL, "t_start must be finite");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(SMCX_EINVAL, "sigma must be finite and > 0");
+  if (k_max < 1 || k_max > 512) return fail(SMCX_EINVAL, "k_max = %d outside [1, 512]", k_max);
+  if (n_max < 0 || n_max > (int64_t(1) << 30)) return fail(SMCX_EINVAL, "n_max = %lld out of range", (long long)n_max);
+  if (m_max < 0 || m_max > (int64_t(1) << 34)) return fail(SMCX_EINVAL, "m_max = %lld out of range", (long long)m_max);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (capturing(st)) return fail(SMCX_ECAPTURE, "smcx_problem_create called during stream capture");
+
+  smcx_problem* p = new smcx_problem();
+  p->model = model;
+  p->P = smcx::n_params(model);
+  p->T = T;
+  p->t_start = t_start;
+  p->dt = dt;
+  p->sigma = sigma;
+  p->inv_sigma2 = 1.0 / (sigma * sigma);
+  p->k_max = k_max;
+  p->n_max = n_max;
+  p->m_max = m_max;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
+
+  for (int k = 0; k < kNumKinds; ++k) {
+    p->tiling[k] = default_tiling(model, k, T);
+    if (p->tiling[k].nch > p->max_nch) p->max_nch = p->tiling[k].nch;
+  }
+  // data: FP64 copy (plain form), FP32 copy (batched kernels), FP64 energy prefix sums (host)
+  std::vector<double> h(T);
+  e = hipMemcpyAsync(h.data(), d_dev, T * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "copy of d"); }
+  std::vector<float> h32(T);
+  p->prefix.assign(T + 1, 0.0);
+  for (int64_t s = 0; s < T; ++s) {
+    h32[s] = (float)h[s];
+    p->prefix[s + 1] = p->prefix[s] + h[s] * h[s];
+  }
+  const size_t part_elems = (size_t)p->max_nch * (size_t)std::max<int64_t>(n_max, 1) * 4;
+  const size_t partg_elems = p->tiling[kGrad].nch > 1
+                                 ? (size_t)p->tiling[kGrad].nch * (size_t)std::max<int64_t>(m_max, 1) * p->P
+                                 : 1;
+  const int nb = (int)((T + 255) / 256);
+  struct { void** ptr; size_t bytes; } allocs[] = {
+      {(void**)&p->d32, T * sizeof(float)},
+      {(void**)&p->d64, T * sizeof(double)},
+      {(void**)&p->order, (size_t)std::max<int64_t>(n_max, 1) * sizeof(int32_t)},
+      {(void**)&p->n_active, sizeof(int32_t)},
+      {(void**)&p->flag, sizeof(int)},
+      {(void**)&p->part, part_elems * sizeof(double)},
+      {(void**)&p->part_g, partg_elems * sizeof(double)},
+      {(void**)&p->rbuf, T * sizeof(double)},
+      {(void**)&p->bpart, nb * sizeof(double)},
+  };
+  for (auto& al : allocs) {
+    e = hipMalloc(al.ptr, al.bytes);
+    if (e != hipSuccess) {
+      free_problem(p);
+      return fail(SMCX_ENOMEM, "hipMalloc of %zu bytes failed: %s", al.bytes, hipGetErrorString(e));
+    }
+  }
+  const int zero = 0;
+  e = hipMemcpyAsync(p->d32, h32.data(), T * sizeof(float), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->d64, d_dev, T * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->n_active, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "upload of d"); }
+  *out = p;
+  return SMCX_OK;
+}
+
+int smcx_problem_destroy(smcx_problem* prob) {
+  g_last_error.clear();
+  if (!prob) return SMCX_OK;
+  (void)hipDeviceSynchronize();
+  free_problem(prob);
+  return SMCX_OK;
+}
+
+int smcx_device_status(smcx_problem* p, void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (capturing(st)) return fail(SMCX_ECAPTURE, "smcx_device_status called during stream capture");
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  int flag = 0;
+  const int zero = 0;
+  e = hipMemcpy(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "device flag read");
+  if (flag == 0) return SMCX_OK;
+  std::string msg = "device-side argument errors:";
+  if (flag & smcx::kFlagOffsets) msg += " offsets not a valid CSR prefix sum;";
+  if (flag & smcx::kFlagKMax) msg += " a particle has K > k_max;";
+  if (flag & smcx::kFlagMMax) msg += " offsets[N] > m_max;";
+  if (flag & smcx::kFlagDeath) msg += " death index outside [-1, K);";
+  if (flag & smcx::kFlagPhase) msg += " sinusoid frequency too high for the sample spacing;";
+  return fail(SMCX_EDEVICE, "%s", msg.c_str());
+}
+
+int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+               const double* theta, const double* beta, double* logl, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N > 0 && !logl) return fail(SMCX_EINVAL, "logl is NULL");
+  if (N == 0) return SMCX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+  pa.logl = logl;
+  hipError_t e = smcx::launch_prep(pa, st);
+  if (e != hipSuccess) return hip_fail(e, "prep launch");
+  const Tiling& t = p->tiling[kFwd];
+  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  a.logl = logl;
+  e = smcx::launch_forward(p->model, t, a, st);
+  if (e != hipSuccess) return hip_fail(e, "logl launch");
+  return SMCX_OK;
+}
+
+int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                    const double* theta, const double* beta, double* logl, double* grad,
+                    void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (M > 0 && !grad) return fail(SMCX_EINVAL, "grad is NULL");
+  if (N == 0) return SMCX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+  pa.logl = logl;
+  pa.grad = grad;
+  hipError_t e = smcx::launch_prep(pa, st);
+  if (e != hipSuccess) return hip_fail(e, "prep launch");
+  const Tiling& t = p->tiling[kGrad];
+  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  a.logl = logl;
+  a.grad = grad;
+  e = smcx::launch_fused(p->model, t, a, st);
+  if (e != hipSuccess) return hip_fail(e, "logl_grad launch");
+  return SMCX_OK;
+}
+
+int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                           const double* theta, const double* beta, const double* theta_birth,
+                           const int32_t* death_idx, double* dlogl_birth, double* dlogl_death,
+                           void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N > 0 && theta_birth && !dlogl_birth) return fail(SMCX_EINVAL, "dlogl_birth is NULL");
+  if (N > 0 && death_idx && !dlogl_death) return fail(SMCX_EINVAL, "dlogl_death is NULL");
+  if (N == 0 || (!theta_birth && !death_idx)) return SMCX_OK;
+  if (p->k_max + 1 > 513) return fail(SMCX_EINVAL, "k_max too large for the birth slot");
+  hipStream_t st = (hipStream_t)hip_stream;
+  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, 0.0, 1);
+  pa.include_k0 = 1;
+  pa.death_idx = death_idx;
+  pa.dlogl_birth = theta_birth ? dlogl_birth : nullptr;
+  pa.dlogl_death = death_idx ? dlogl_death : nullptr;
+  hipError_t e = smcx::launch_prep(pa, st);
+  if (e != hipSuccess) return hip_fail(e, "prep launch");
+  const Tiling& t = p->tiling[kDelta];
+  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  a.theta_birth = theta_birth;
+  a.death_idx = death_idx;
+  a.dlogl_birth = dlogl_birth;
+  a.dlogl_death = dlogl_death;
+  e = smcx::launch_delta(p->model, t, a, st);
+  if (e != hipSuccess) return hip_fail(e, "delta launch");
+  return SMCX_OK;
+}
+
+int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const int64_t* offsets,
+                    int64_t M, const double* theta, double delta_beta, const double* logw_prev,
+                    double* logl_ext, double* logw, double* w_norm, double* scalars,
+                    void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (T1 < 0 || T2 <= T1 || T2 > p->T)
+    return fail(SMCX_EINVAL, "sample range [%lld, %lld) not inside [0, %lld)", (long long)T1,
+                (long long)T2, (long long)p->T);
+  if (!std::isfinite(delta_beta)) return fail(SMCX_EINVAL, "delta_beta must be finite");
+  if (!scalars) return fail(SMCX_EINVAL, "scalars is NULL");
+  if (N > 0 && (!logl_ext || !logw || !w_norm)) return fail(SMCX_EINVAL, "an output array is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (N > 0) {
+    const double k0 = -0.5 * (p->prefix[T2] - p->prefix[T1]) * p->inv_sigma2;
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, nullptr, k0, 0);
+    pa.logl = logl_ext;
+    hipError_t e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+    const Tiling t = with_range(p->tiling[kFwd], T2 - T1);
+    smcx::PopArgs a = base_args(p, N, offsets, theta, nullptr, t, T1, T2);
+    a.logl = logl_ext;
+    e = smcx::launch_forward(p->model, t, a, st);
+    if (e != hipSuccess) return hip_fail(e, "segment logl launch");
+  }
+  hipError_t e = smcx::launch_reweight_reduce(N, delta_beta, logl_ext, logw_prev, logw, w_norm,
+                                              scalars, nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "reweight launch");
+  return SMCX_OK;
+}
+
+int smcx_template_sum(int model, int64_t K, const double* theta, int64_t T, double t_start,
+                      double dt, double* out, void* hip_stream) {
+  g_last_error.clear();
+  if (model != SMCX_PULSE && model != SMCX_GBSINE) return fail(SMCX_EINVAL, "unknown model %d", model);
+  if (K < 0 || T < 0) return fail(SMCX_EINVAL, "negative size");
+  if (K > 0 && !theta) return fail(SMCX_EINVAL, "theta is NULL");
+  if (T > 0 && !out) return fail(SMCX_EINVAL, "out is NULL");
+  hipError_t e = smcx::launch_template_sum(model, K, theta, T, t_start, dt, out,
+                                           (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "template_sum launch");
+  return SMCX_OK;
+}
+
+int smcx_plain_logl_grad(smcx_problem* p, int64_t N, const int64_t* offsets_host, int64_t M,
+                         const double* theta, const double* beta, double* logl, double* grad,
+                         void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets_host, M, theta);
+  if (rc) return rc;
+  if (N > 0 && !logl) return fail(SMCX_EINVAL, "logl is NULL");
+  if (N == 0) return SMCX_OK;
+  if (offsets_host[0] != 0) return fail(SMCX_EINVAL, "offsets[0] != 0");
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t K = offsets_host[i + 1] - offsets_host[i];
+    if (K < 0 || K > p->k_max) return fail(SMCX_EINVAL, "particle %lld has K = %lld", (long long)i, (long long)K);
+  }
+  if (offsets_host[N] != M) return fail(SMCX_EINVAL, "offsets[N] != M");
+  if (offsets_host[N] > 0 && !grad) return fail(SMCX_EINVAL, "grad is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t m0 = offsets_host[i];
+    const int K = (int)(offsets_host[i + 1] - m0);
+    hipError_t e = smcx::launch_plain_particle(p->model, p->d64, p->T, p->t_start, p->dt,
+                                               p->inv_sigma2, theta + m0 * p->P, K, beta, i,
+                                               p->rbuf, p->bpart, logl, grad + m0 * p->P, st);
+    if (e != hipSuccess) return hip_fail(e, "plain launch");
+  }
+  return SMCX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP translation units of libsmcx.
+// Device helpers (wave reductions on gfx950 DPP), kernel argument blocks and
+// the launch entry points the C ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/smcx.h"
+
+namespace smcx {
+
+constexpr int kWave = 64;
+
+// Device-side error flag bits (see smcx_device_status).
+enum : int {
+  kFlagOffsets = 1,   // offsets not monotone / offsets[0] != 0
+  kFlagKMax = 2,      // a particle has K_i > k_max
+  kFlagMMax = 4,      // offsets[N] != M (rows of theta passed by the caller)
+  kFlagDeath = 8,     // death index outside [-1, K_i)
+  kFlagPhase = 16,    // GB phase increment too large for the per-tile reduction
+};
+
+// Number of parameters per component.
+__host__ __device__ constexpr int n_params(int model) { return model == SMCX_PULSE ? 3 : 4; }
+
+// ---------------------------------------------------------------------------
+// Tiling of the sample axis. A wave owns one work item = (particle, chunk);
+// a chunk is walked in tiles of 64*S samples, lane l holding samples
+// tile + 64*j + l, j < S, so that every load of the data is one coalesced
+// 256-byte line per j. Chunks split long sample ranges across waves; their
+// per-chunk partial sums are combined in a fixed order afterwards.
+struct Tiling {
+  int S;              // samples per lane per tile (8, 16, 32 or 64)
+  int64_t chunk_len;  // samples per chunk (multiple of 64*S)
+  int nch;            // chunks covering [s_lo, s_hi)
+};
+
+// Arguments of the batched population kernels (forward, fused forward +
+// adjoint, birth/death, segment forward).
+struct PopArgs {
+  const float* d32;        // [T] data in FP32
+  int64_t s_lo, s_hi;      // sample range [s_lo, s_hi)
+  double t_start, dt, inv_sigma2;
+  const int64_t* offsets;  // [N+1]
+  const double* theta;     // [M][P]
+  const double* beta;      // [N] or nullptr (beta = 1)
+  int64_t N;
+  int32_t k_max;
+  int64_t m_max;
+  const int32_t* order;    // [N] particles with K > 0, sorted by K descending
+  const int32_t* n_active; // device scalar: number of entries of order
+  int nch;
+  int64_t chunk_len;
+  // outputs
+  double* logl;            // [N] or nullptr
+  double* grad;            // [M][P] or nullptr
+  double* part;            // [nch][N][n_part] chunk partials when nch > 1
+  double* part_g;          // [nch][m_max][P] chunk gradient partials when nch > 1
+  // birth / death
+  const double* theta_birth;  // [N][P] or nullptr
+  const int32_t* death_idx;   // [N] or nullptr
+  double* dlogl_birth;
+  double* dlogl_death;
+  int* flag;
+};
+
+// Sort particles by K (descending) and settle K = 0 / invalid particles.
+struct PrepArgs {
+  const int64_t* offsets;
+  const double* beta;
+  int64_t N;
+  int32_t k_max;
+  int64_t m_max;
+  int64_t M;           // rows of theta: offsets[N] must equal it
+  double k0_value;     // untempered logL of a particle with no components
+  double* logl;        // written for K = 0 (tempered) and invalid (NaN) particles
+  double* logl2;       // optional second output set to the K=0 value (nullptr)
+  int P;
+  double* grad;        // NaN rows for invalid particles (nullptr to skip)
+  double* dlogl_birth; // birth/death outputs for invalid particles (nullptr to skip)
+  double* dlogl_death;
+  const int32_t* death_idx;  // validated against [-1, K_i) when dlogl_death is set
+  int32_t* order;
+  int32_t* n_active;
+  int* flag;
+  int tempered;        // 1: K=0 value times beta_i, 0: untempered
+  int include_k0;      // 1: K = 0 particles stay in the work list (birth pass)
+};
+
+// Host launchers (defined in smcx_kernels.hip / smcx_plain.hip).
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
+hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
+hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
+hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
+                                  const double* logw_prev, double* logw, double* w_norm,
+                                  double* scalars, double* scratch, hipStream_t st);
+hipError_t launch_template_sum(int model, int64_t K, const double* theta, int64_t T,
+                               double t_start, double dt, double* out, hipStream_t st);
+hipError_t launch_plain_particle(int model, const double* d64, int64_t T, double t_start,
+                                 double dt, double inv_sigma2, const double* theta_rows, int K,
+                                 const double* beta, int64_t i, double* rbuf, double* bpart,
+                                 double* logl, double* grad_rows, hipStream_t st);
+
+size_t pop_lds_bytes_per_wave(int model, int32_t k_max, bool grad);
+
+}  // namespace smcx

@@ -1,0 +1,853 @@
+// Batched population kernels for gfx950.
+//
+// One wave64 owns one work item (particle, chunk of samples). The particle's
+// component parameters are turned into per-component FP32/FP64 constants by
+// the wave's lanes in parallel and parked in the wave's LDS slice; the wave
+// then walks its chunk in tiles of 64*S samples (lane l owns samples
+// tile + 64 j + l), keeps the tile's residual in registers, synthesises the
+// templates of all components in index order, and reduces.
+//
+// Precision scheme (the residual and templates are FP32):
+//  * Pulses: the pulse centre is split in FP64 into an integer sample index n
+//    and a fraction f, so x = (s - n) - f is formed exactly up to one FP32
+//    rounding of x itself; the exponent uses one pre-scaled coefficient so
+//    the Gaussian is a single hardware exp2.
+//  * Sinusoids: the phase in cycles is a quadratic in the sample index. Per
+//    component and lane it is re-expanded around the lane's first sample,
+//    the constant term is reduced modulo one cycle in FP64, and the
+//    per-sample phase is evaluated in FP64 on top of the magic constant
+//    1.5 * 2^20, whose unit in the last place is 2^-32 cycles: the low 32 bits
+//    of the FP64 result are then the phase modulo one cycle as a signed
+//    fixed-point number, which is converted to FP32 revolutions for the
+//    hardware sin/cos (they take revolutions).
+//  * Sums of r^2 and the birth/death inner products are accumulated per lane
+//    in FP64 (products of FP32 values are exact in FP64); gradient sums are
+//    FP32 per lane per tile, reduced across the wave in FP32 and accumulated
+//    across tiles in FP64.
+// All reductions have a fixed order: a particle's results do not depend on
+// the other particles in the batch, their order, or the run.
+#include "smcx_internal.h"
+
+#include <math.h>
+
+namespace smcx {
+namespace {
+
+// sqrt(log2(e) / 2): exp(-x^2 / (2 w^2)) = exp2(-(a x)^2) with a = this / w.
+constexpr double kSqrtHalfLog2e = 0.84932180028801904272150283410289;
+// 1.5 * 2^20: doubles in [2^20, 2^21) have a unit in the last place of 2^-32.
+constexpr double kPhaseMagic = 1572864.0;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.141592653589793238462643383279;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------- DPP sums
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL, ROW_MASK>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i<CTRL, ROW_MASK>((int)(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL, ROW_MASK>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63. The steps pair lanes
+// within quads, half rows and rows, then carry row sums up with the row
+// broadcasts (rows 1,3 add row 0,2; rows 2,3 add rows 0..1).
+__device__ __forceinline__ float wave_sum_f(float v) {
+  v += dpp_f<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);       // row_half_mirror
+  v += dpp_f<0x140>(v);       // row_mirror
+  v += dpp_f<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_f<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  v += dpp_d<0x142, 0xA>(v);
+  v += dpp_d<0x143, 0xC>(v);
+  return v;
+}
+__device__ __forceinline__ double lane63_d(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---------------------------------------------------------------- models
+// Gaussian pulse h = A exp(-(t - t0)^2 / (2 w^2)).
+struct PulseC {
+  float nf;  // integer part of the centre in samples, as an exact float
+  float a;   // sqrt(log2 e / 2) / (w / dt)
+  float fa;  // (fractional part of the centre) * a
+  float A;
+};
+static_assert(sizeof(PulseC) == 16, "pulse constants are one float4");
+
+__device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, double dt) {
+  const double A = th[0], t0 = th[1], w = th[2];
+  const double c = (t0 - t_start) / dt;
+  double n = floor(c);
+  n = fmin(fmax(n, -4194304.0), 4194304.0);  // keep s - n exact in FP32
+  const double f = c - n;
+  const double a = kSqrtHalfLog2e * dt / w;
+  PulseC r;
+  r.nf = (float)n;
+  r.a = (float)a;
+  r.fa = (float)(f * a);
+  r.A = (float)A;
+  return r;
+}
+
+// Chirping sinusoid h = A sin(2 pi (a0 + a1 s + a2 s^2)) in sample index s.
+struct GbC {
+  double a0, a1, a2;  // phase polynomial in cycles
+  float A;
+  float pad;
+};
+static_assert(sizeof(GbC) == 32, "GB constants are 32 bytes");
+
+__device__ __forceinline__ GbC gb_make(const double* th, double t_start, double dt, int64_t s_lo,
+                                       int64_t s_hi, int S, int* flag) {
+  const double A = th[0], f0 = th[1], fd = th[2], phi0 = th[3];
+  GbC r;
+  r.a0 = f0 * t_start + 0.5 * fd * t_start * t_start + phi0 / kTwoPi;
+  r.a1 = (f0 + fd * t_start) * dt;
+  r.a2 = 0.5 * fd * dt * dt;
+  r.A = (float)A;
+  r.pad = 0.f;
+  // The per-sample phase is evaluated relative to the lane's first sample of
+  // the tile; the offset must stay well inside the 2^19-cycle window of the
+  // magic-constant reduction.
+  const double p1a = fabs(64.0 * (r.a1 + 2.0 * r.a2 * (double)s_lo));
+  const double p1b = fabs(64.0 * (r.a1 + 2.0 * r.a2 * (double)s_hi));
+  const double span = fmax(p1a, p1b) * S + fabs(4096.0 * r.a2) * (double)S * S;
+  if (!(span < 262144.0)) {
+    if (span == span) atomicOr(flag, kFlagPhase);
+    r.A = __builtin_nanf("");
+  }
+  return r;
+}
+
+// Phase (revolutions, in [-0.5, 0.5)) from the reduced FP64 value y.
+__device__ __forceinline__ float rev_of(double y) {
+  const int lo = (int)(__builtin_bit_cast(long long, y) & 0xffffffffll);
+  return (float)lo * 0x1p-32f;
+}
+
+struct GbTile {
+  double Y0, P1, P2;
+};
+__device__ __forceinline__ GbTile gb_tile(const GbC& c, double u) {
+  GbTile t;
+  const double P0 = fma(fma(c.a2, u, c.a1), u, c.a0);
+  t.Y0 = (P0 - rint(P0)) + kPhaseMagic;
+  t.P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
+  t.P2 = 4096.0 * c.a2;
+  return t;
+}
+template <int J>
+__device__ __forceinline__ double gb_y(const GbTile& t) {
+  if (J == 0) return t.Y0;
+  const double q = fma(t.P2, (double)J, t.P1);
+  return fma(q, (double)J, t.Y0);
+}
+
+// ---------------------------------------------------------------- tile bodies
+template <int S, int J = 0>
+__device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S]) {
+  if constexpr (J < S) {
+    const float dj = base + (float)(64 * J);
+    const float z = __builtin_fmaf(dj, c.a, -c.fa);
+    const float e = __builtin_amdgcn_exp2f(-(z * z));
+    r[J] = __builtin_fmaf(-c.A, e, r[J]);
+    pulse_fwd_j<S, J + 1>(c, base, r);
+  }
+}
+
+template <int S, int J = 0>
+__device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const float (&r)[S],
+                                            float& s0, float& s1, float& s2) {
+  if constexpr (J < S) {
+    const float dj = base + (float)(64 * J);
+    const float z = __builtin_fmaf(dj, c.a, -c.fa);
+    const float e = __builtin_amdgcn_exp2f(-(z * z));
+    const float re = r[J] * e;
+    s0 += re;
+    const float rz = re * z;
+    s1 += rz;
+    s2 = __builtin_fmaf(rz, z, s2);
+    pulse_adj_j<S, J + 1>(c, base, r, s0, s1, s2);
+  }
+}
+
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_fwd_j(const GbTile& t, float A, float (&r)[S]) {
+  if constexpr (J < S) {
+    const float s = __builtin_amdgcn_sinf(rev_of(gb_y<J>(t)));
+    r[J] = __builtin_fmaf(-A, s, r[J]);
+    gb_fwd_j<S, J + 1>(t, A, r);
+  }
+}
+
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_adj_j(const GbTile& t, const float (&r)[S], float& as,
+                                         float& c0, float& c1, float& c2) {
+  if constexpr (J < S) {
+    const float ph = rev_of(gb_y<J>(t));
+    const float s = __builtin_amdgcn_sinf(ph);
+    const float c = __builtin_amdgcn_cosf(ph);
+    as = __builtin_fmaf(r[J], s, as);
+    const float rc = r[J] * c;
+    c0 += rc;
+    c1 = __builtin_fmaf(rc, (float)J, c1);
+    c2 = __builtin_fmaf(rc, (float)(J * J), c2);
+    gb_adj_j<S, J + 1>(t, r, as, c0, c1, c2);
+  }
+}
+
+template <int MODEL>
+struct Model;
+
+template <>
+struct Model<SMCX_PULSE> {
+  using C = PulseC;
+  static constexpr int P = 3;
+  __device__ static C make(const double* th, const PopArgs& a, int /*S*/) {
+    return pulse_make(th, a.t_start, a.dt);
+  }
+  template <int S>
+  __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
+    const float sf0 = (float)(tile + lane);
+    for (int k = 0; k < K; ++k) {
+      const C c = cst[k];
+      pulse_fwd_j<S>(c, sf0 - c.nf, r);
+    }
+  }
+  template <int S>
+  __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
+                                 const float (&r)[S]) {
+    const float sf0 = (float)(tile + lane);
+    for (int k = 0; k < K; ++k) {
+      const C c = cst[k];
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2);
+      s0 = wave_sum_f(s0);
+      s1 = wave_sum_f(s1);
+      s2 = wave_sum_f(s2);
+      if (lane == 63) {
+        acc[3 * k + 0] += (double)s0;
+        acc[3 * k + 1] += (double)s1;
+        acc[3 * k + 2] += (double)s2;
+      }
+    }
+  }
+  // Template values of one component on the tile (for birth/death).
+  template <int S>
+  __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
+    const float base = (float)(tile + lane) - c.nf;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const float dj = base + (float)(64 * j);
+      const float z = __builtin_fmaf(dj, c.a, -c.fa);
+      h[j] = c.A * __builtin_amdgcn_exp2f(-(z * z));
+    }
+  }
+  template <int S>
+  __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
+    const float base = (float)(tile + lane) - c.nf;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const float dj = base + (float)(64 * j);
+      const float z = __builtin_fmaf(dj, c.a, -c.fa);
+      const float e = __builtin_amdgcn_exp2f(-(z * z));
+      r1[j] = __builtin_fmaf(-c.A, e, r1[j]);
+      r2[j] = __builtin_fmaf(-c.A, e, r2[j]);
+    }
+  }
+  // g = beta/sigma^2 * sum_s r_s dh/dtheta from the accumulated sums
+  // S0 = sum r e, S1 = sum r e z, S2 = sum r e z^2 with z = a x (x in samples).
+  __device__ static void scale(const double* th, const double* sums, double bs, const PopArgs& a,
+                               double* g) {
+    const double A = th[0], w = th[2];
+    const double af = (double)pulse_make(th, a.t_start, a.dt).a;
+    g[0] = bs * sums[0];
+    g[1] = bs * (A * a.dt / (af * w * w)) * sums[1];
+    g[2] = bs * (A * a.dt * a.dt / (af * af * w * w * w)) * sums[2];
+  }
+};
+
+template <>
+struct Model<SMCX_GBSINE> {
+  using C = GbC;
+  static constexpr int P = 4;
+  __device__ static C make(const double* th, const PopArgs& a, int S) {
+    return gb_make(th, a.t_start, a.dt, a.s_lo, a.s_hi, S, a.flag);
+  }
+  template <int S>
+  __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
+    const double u = (double)(tile + lane);
+    for (int k = 0; k < K; ++k) {
+      const C c = cst[k];
+      const GbTile t = gb_tile(c, u);
+      gb_fwd_j<S>(t, c.A, r);
+    }
+  }
+  template <int S>
+  __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
+                                 const float (&r)[S]) {
+    const double u = (double)(tile + lane);
+    const float uf = (float)(tile + lane);
+    for (int k = 0; k < K; ++k) {
+      const C c = cst[k];
+      const GbTile t = gb_tile(c, u);
+      float as = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+      gb_adj_j<S>(t, r, as, c0, c1, c2);
+      // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
+      const float b1 = __builtin_fmaf(uf, c0, 64.f * c1);
+      const float b2 = __builtin_fmaf(uf * uf, c0, __builtin_fmaf(128.f * uf, c1, 4096.f * c2));
+      as = wave_sum_f(as);
+      c0 = wave_sum_f(c0);
+      const float r1 = wave_sum_f(b1);
+      const float r2 = wave_sum_f(b2);
+      if (lane == 63) {
+        acc[4 * k + 0] += (double)as;
+        acc[4 * k + 1] += (double)c0;
+        acc[4 * k + 2] += (double)r1;
+        acc[4 * k + 3] += (double)r2;
+      }
+    }
+  }
+  template <int S>
+  __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
+    const GbTile t = gb_tile(c, (double)(tile + lane));
+    float z[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) z[j] = 0.f;
+    gb_fwd_j<S>(t, -c.A, z);  // z = 0 + A sin  (fma(-(-A), s, 0))
+#pragma unroll
+    for (int j = 0; j < S; ++j) h[j] = z[j];
+  }
+  template <int S>
+  __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
+    const GbTile t = gb_tile(c, (double)(tile + lane));
+    gb_sub2_j<S>(t, c.A, r1, r2);
+  }
+  template <int S, int J = 0>
+  __device__ static void gb_sub2_j(const GbTile& t, float A, float (&r1)[S], float (&r2)[S]) {
+    if constexpr (J < S) {
+      const float s = __builtin_amdgcn_sinf(rev_of(gb_y<J>(t)));
+      r1[J] = __builtin_fmaf(-A, s, r1[J]);
+      r2[J] = __builtin_fmaf(-A, s, r2[J]);
+      gb_sub2_j<S, J + 1>(t, A, r1, r2);
+    }
+  }
+  // sums: S_sin = sum r sin, C0 = sum r cos, C1 = sum r cos s, C2 = sum r cos s^2.
+  __device__ static void scale(const double* th, const double* sums, double bs, const PopArgs& a,
+                               double* g) {
+    const double A = th[0];
+    const double ts = a.t_start, dt = a.dt;
+    const double c0 = sums[1], c1 = sums[2], c2 = sums[3];
+    g[0] = bs * sums[0];
+    g[1] = bs * (kTwoPi * A) * (ts * c0 + dt * c1);
+    g[2] = bs * (kPi * A) * (ts * ts * c0 + 2.0 * ts * dt * c1 + dt * dt * c2);
+    g[3] = bs * A * c0;
+  }
+};
+
+__host__ __device__ inline size_t const_bytes(int model) {
+  return model == SMCX_PULSE ? sizeof(PulseC) : sizeof(GbC);
+}
+
+__device__ __forceinline__ size_t lds_wave_bytes(int model, int32_t k_max, bool grad) {
+  const size_t per = const_bytes(model) + (grad ? (size_t)n_params(model) * 8 : 0);
+  return ((size_t)(k_max + 1) * per + 15) & ~(size_t)15;
+}
+
+// ---------------------------------------------------------------- prep
+__global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a) {
+  extern __shared__ int sh[];
+  int* hist = sh;                  // [k_max + 1]
+  int* start = sh + (a.k_max + 1); // [k_max + 1]
+  __shared__ int bad_global;
+  for (int k = threadIdx.x; k <= a.k_max; k += blockDim.x) hist[k] = 0;
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    if (a.N > 0 && (a.offsets[0] != 0 || a.offsets[a.N] != a.M)) bad = 1;
+    bad_global = bad;
+    if (bad) atomicOr(a.flag, a.offsets[0] != 0 ? kFlagOffsets : kFlagMMax);
+  }
+  __syncthreads();
+  const double nan = __builtin_nan("");
+  for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x) {
+    const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+    const int64_t K = o1 - o0;
+    int bits = 0;
+    if (bad_global) bits |= kFlagOffsets;
+    if (K < 0) bits |= kFlagOffsets;
+    if (K > a.k_max) bits |= kFlagKMax;
+    if (a.dlogl_death && a.death_idx) {
+      const int32_t j = a.death_idx[i];
+      if (j < -1 || (int64_t)j >= K) bits |= kFlagDeath;
+    }
+    if (bits) {
+      if (!bad_global) atomicOr(a.flag, bits);
+      if (a.logl) a.logl[i] = nan;
+      if (a.dlogl_birth) a.dlogl_birth[i] = nan;
+      if (a.dlogl_death) a.dlogl_death[i] = nan;
+      if (a.grad && !bad_global && K > 0) {
+        for (int64_t m = o0 < 0 ? 0 : o0; m < o1 && m < a.M; ++m)
+          for (int p = 0; p < a.P; ++p) a.grad[m * a.P + p] = nan;
+      }
+      continue;
+    }
+    if (K == 0 && !a.include_k0) {
+      const double b = (a.tempered && a.beta) ? a.beta[i] : 1.0;
+      if (a.logl) a.logl[i] = b * a.k0_value;
+      continue;
+    }
+    atomicAdd(&hist[K], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int pos = 0;
+    for (int k = a.k_max; k >= 0; --k) {
+      start[k] = pos;
+      pos += hist[k];
+      hist[k] = 0;
+    }
+    *a.n_active = pos;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x) {
+    const int64_t K = a.offsets[i + 1] - a.offsets[i];
+    if (bad_global || K < 0 || K > a.k_max) continue;
+    if (a.dlogl_death && a.death_idx) {
+      const int32_t j = a.death_idx[i];
+      if (j < -1 || (int64_t)j >= K) continue;
+    }
+    if (K == 0 && !a.include_k0) continue;
+    const int slot = start[K] + atomicAdd(&hist[K], 1);
+    a.order[slot] = (int32_t)i;
+  }
+}
+
+// ---------------------------------------------------------------- population kernel
+// GRAD = false: logL only (also the data-assimilation segment pass).
+// GRAD = true : fused forward + adjoint.
+template <int MODEL, int S, bool GRAD>
+__global__ __launch_bounds__(256) void pop_kernel(PopArgs a) {
+  using M = Model<MODEL>;
+  using C = typename M::C;
+  constexpr int P = M::P;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
+  const int64_t n_items = (int64_t)(*a.n_active) * a.nch;
+  if (item >= n_items) return;
+  const int64_t rank = item / a.nch;
+  const int c = (int)(item - rank * a.nch);
+  const int i = a.order[rank];
+  const int64_t m0 = a.offsets[i];
+  const int K = (int)(a.offsets[i + 1] - m0);
+
+  unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
+  C* cst = reinterpret_cast<C*>(base);
+  double* acc = reinterpret_cast<double*>(base + (size_t)(a.k_max + 1) * sizeof(C));
+  for (int k = lane; k < K; k += 64) {
+    cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
+    if (GRAD)
+      for (int p = 0; p < P; ++p) acc[k * P + p] = 0.0;
+  }
+  wave_sync();
+
+  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
+  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
+  double ss = 0.0;
+  for (int64_t tile = cs; tile < ce; tile += 64 * S) {
+    float r[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int64_t s = tile + 64 * j + lane;
+      r[j] = s < ce ? a.d32[s] : 0.f;
+    }
+    M::template forward<S>(cst, K, tile, lane, r);
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int64_t s = tile + 64 * j + lane;
+      r[j] = s < ce ? r[j] : 0.f;
+      const double rd = (double)r[j];
+      ss = fma(rd, rd, ss);
+    }
+    if constexpr (GRAD) M::template adjoint<S>(cst, acc, K, tile, lane, r);
+  }
+  ss = lane63_d(wave_sum_d(ss));
+
+  if (a.nch == 1) {
+    const double b = a.beta ? a.beta[i] : 1.0;
+    if (lane == 0 && a.logl) a.logl[i] = b * (-0.5 * ss * a.inv_sigma2);
+    if constexpr (GRAD) {
+      wave_sync();
+      const double bs = b * a.inv_sigma2;
+      for (int k = lane; k < K; k += 64) {
+        double g[P];
+        M::scale(a.theta + (m0 + k) * P, acc + k * P, bs, a, g);
+        for (int p = 0; p < P; ++p) a.grad[(m0 + k) * P + p] = g[p];
+      }
+    }
+  } else {
+    if (lane == 0) a.part[(size_t)c * a.N + i] = ss;
+    if constexpr (GRAD) {
+      wave_sync();
+      double* dst = a.part_g + ((size_t)c * a.m_max + m0) * P;
+      for (int idx = lane; idx < K * P; idx += 64) dst[idx] = acc[idx];
+    }
+  }
+}
+
+// Combine chunk partials in chunk order; one wave per particle.
+template <int MODEL, bool GRAD>
+__global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
+  using M = Model<MODEL>;
+  constexpr int P = M::P;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+  if (rank >= *a.n_active) return;
+  const int i = a.order[rank];
+  const int64_t m0 = a.offsets[i];
+  const int K = (int)(a.offsets[i + 1] - m0);
+  const double b = a.beta ? a.beta[i] : 1.0;
+  if (lane == 0 && a.logl) {
+    double ss = 0.0;
+    for (int c = 0; c < a.nch; ++c) ss += a.part[(size_t)c * a.N + i];
+    a.logl[i] = b * (-0.5 * ss * a.inv_sigma2);
+  }
+  if constexpr (GRAD) {
+    const double bs = b * a.inv_sigma2;
+    for (int k = lane; k < K; k += 64) {
+      double sums[P];
+      for (int p = 0; p < P; ++p) sums[p] = 0.0;
+      for (int c = 0; c < a.nch; ++c) {
+        const double* src = a.part_g + ((size_t)c * a.m_max + m0 + k) * P;
+        for (int p = 0; p < P; ++p) sums[p] += src[p];
+      }
+      double g[P];
+      M::scale(a.theta + (m0 + k) * P, sums, bs, a, g);
+      for (int p = 0; p < P; ++p) a.grad[(m0 + k) * P + p] = g[p];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- birth / death
+// One pass per (particle, chunk): r (all components) and r_-j (all but j)
+// in index order, the templates of the death candidate j and of the birth
+// candidate, and four FP64 inner products per lane.
+template <int MODEL, int S>
+__global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
+  using M = Model<MODEL>;
+  using C = typename M::C;
+  constexpr int P = M::P;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
+  const int64_t n_items = (int64_t)(*a.n_active) * a.nch;
+  if (item >= n_items) return;
+  const int64_t rank = item / a.nch;
+  const int c = (int)(item - rank * a.nch);
+  const int i = a.order[rank];
+  const int64_t m0 = a.offsets[i];
+  const int K = (int)(a.offsets[i + 1] - m0);
+  const int j_death = a.death_idx ? a.death_idx[i] : -1;
+  const bool birth = a.theta_birth != nullptr;
+
+  C* cst = reinterpret_cast<C*>(lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, false));
+  for (int k = lane; k < K; k += 64) cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
+  if (birth && lane == 0) cst[K] = M::make(a.theta_birth + (int64_t)i * P, a, S);
+  wave_sync();
+
+  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
+  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
+  double xb = 0.0, yb = 0.0, xd = 0.0, yd = 0.0;
+  for (int64_t tile = cs; tile < ce; tile += 64 * S) {
+    float rf[S], rn[S], hj[S];
+#pragma unroll
+    for (int jj = 0; jj < S; ++jj) {
+      const int64_t s = tile + 64 * jj + lane;
+      rf[jj] = s < ce ? a.d32[s] : 0.f;
+      rn[jj] = rf[jj];
+      hj[jj] = 0.f;
+    }
+    for (int k = 0; k < K; ++k) {
+      const C cc = cst[k];
+      if (k == j_death) {
+        M::template values<S>(cc, tile, lane, hj);
+        // r (all components) still subtracts h_j, with the same fma as below
+        float dummy[S];
+#pragma unroll
+        for (int jj = 0; jj < S; ++jj) dummy[jj] = 0.f;
+        M::template sub2<S>(cc, tile, lane, rf, dummy);
+      } else {
+        M::template sub2<S>(cc, tile, lane, rf, rn);
+      }
+    }
+    float hn[S];
+    if (birth) {
+      M::template values<S>(cst[K], tile, lane, hn);
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < S; ++jj) hn[jj] = 0.f;
+    }
+#pragma unroll
+    for (int jj = 0; jj < S; ++jj) {
+      const int64_t s = tile + 64 * jj + lane;
+      const bool ok = s < ce;
+      const double r1 = ok ? (double)rf[jj] : 0.0;
+      const double r2 = ok ? (double)rn[jj] : 0.0;
+      const double h1 = ok ? (double)hn[jj] : 0.0;
+      const double h2 = ok ? (double)hj[jj] : 0.0;
+      xb = fma(r1, h1, xb);
+      yb = fma(h1, h1, yb);
+      xd = fma(r2, h2, xd);
+      yd = fma(h2, h2, yd);
+    }
+  }
+  xb = lane63_d(wave_sum_d(xb));
+  yb = lane63_d(wave_sum_d(yb));
+  xd = lane63_d(wave_sum_d(xd));
+  yd = lane63_d(wave_sum_d(yd));
+  if (lane != 0) return;
+  if (a.nch == 1) {
+    const double b = a.beta ? a.beta[i] : 1.0;
+    if (birth) a.dlogl_birth[i] = b * (xb - 0.5 * yb) * a.inv_sigma2;
+    if (a.death_idx) a.dlogl_death[i] = j_death < 0 ? 0.0 : -(b * (xd - 0.5 * yd) * a.inv_sigma2);
+  } else {
+    double* dst = a.part + ((size_t)c * a.N + i) * 4;
+    dst[0] = xb;
+    dst[1] = yb;
+    dst[2] = xd;
+    dst[3] = yd;
+  }
+}
+
+__global__ __launch_bounds__(256) void delta_finalize_kernel(PopArgs a) {
+  const int64_t rank = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rank >= *a.n_active) return;
+  const int i = a.order[rank];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < a.nch; ++c) {
+    const double* src = a.part + ((size_t)c * a.N + i) * 4;
+    for (int q = 0; q < 4; ++q) s[q] += src[q];
+  }
+  const double b = a.beta ? a.beta[i] : 1.0;
+  if (a.theta_birth) a.dlogl_birth[i] = b * (s[0] - 0.5 * s[1]) * a.inv_sigma2;
+  if (a.death_idx) {
+    const int j = a.death_idx[i];
+    a.dlogl_death[i] = j < 0 ? 0.0 : -(b * (s[2] - 0.5 * s[3]) * a.inv_sigma2);
+  }
+}
+
+// ---------------------------------------------------------------- reweighting
+// Single-block, fixed-order reductions over the population.
+__global__ __launch_bounds__(1024) void reweight_kernel(int64_t N, double delta_beta,
+                                                        const double* logl_ext,
+                                                        const double* logw_prev, double* logw,
+                                                        double* w_norm, double* scalars) {
+  __shared__ double red[1024];
+  __shared__ double red2[1024];
+  const int t = threadIdx.x;
+  const int nt = blockDim.x;
+  const int64_t per = (N + nt - 1) / nt;
+  const int64_t lo = min((int64_t)t * per, N), hi = min(lo + per, N);
+  auto tree = [&](double v, double v2, bool is_max) {
+    red[t] = v;
+    red2[t] = v2;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        red[t] = is_max ? fmax(red[t], red[t + w]) : red[t] + red[t + w];
+        red2[t] = red2[t] + red2[t + w];
+      }
+      __syncthreads();
+    }
+    double r0 = red[0];
+    double r1 = red2[0];
+    __syncthreads();
+    return make_double2(r0, r1);
+  };
+  double m = -INFINITY;
+  for (int64_t i = lo; i < hi; ++i) {
+    const double v = (logw_prev ? logw_prev[i] : 0.0) + delta_beta * logl_ext[i];
+    logw[i] = v;
+    m = fmax(m, v);
+  }
+  m = tree(m, 0.0, true).x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = lo; i < hi; ++i) {
+    const double e = exp(logw[i] - m);
+    s1 += e;
+    s2 += e * e;
+  }
+  const double2 S = tree(s1, s2, false);
+  for (int64_t i = lo; i < hi; ++i) w_norm[i] = exp(logw[i] - m) / S.x;
+  double lse_prev = log((double)N);
+  if (logw_prev) {
+    double mp = -INFINITY;
+    for (int64_t i = lo; i < hi; ++i) mp = fmax(mp, logw_prev[i]);
+    mp = tree(mp, 0.0, true).x;
+    double sp = 0.0;
+    for (int64_t i = lo; i < hi; ++i) sp += exp(logw_prev[i] - mp);
+    sp = tree(sp, 0.0, false).x;
+    lse_prev = mp + log(sp);
+  }
+  if (t == 0) {
+    if (N == 0) {
+      scalars[0] = 0.0;
+      scalars[1] = 0.0;
+      scalars[2] = -INFINITY;
+    } else {
+      scalars[0] = S.x * S.x / S.y;
+      scalars[1] = m + log(S.x) - lse_prev;
+      scalars[2] = m;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- synthesis
+__global__ __launch_bounds__(256) void template_sum_kernel(int model, int64_t K,
+                                                           const double* theta, int64_t T,
+                                                           double t_start, double dt,
+                                                           double* out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= T) return;
+  const double t = t_start + (double)s * dt;
+  double acc = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const double* th = theta + k * n_params(model);
+    if (model == SMCX_PULSE) {
+      const double x = t - th[1];
+      acc += th[0] * exp(-(x * x) / (2.0 * th[2] * th[2]));
+    } else {
+      acc += th[0] * sin(kTwoPi * th[1] * t + kPi * th[2] * t * t + th[3]);
+    }
+  }
+  out[s] = acc;
+}
+
+int waves_per_block(int model, int32_t k_max, bool grad) {
+  const size_t per = ((size_t)(k_max + 1) * (const_bytes(model) + (grad ? n_params(model) * 8 : 0)) +
+                      15) & ~(size_t)15;
+  int w = 4;
+  while (w > 1 && per * w > 65536) --w;
+  return w;
+}
+
+template <int MODEL, bool GRAD>
+hipError_t launch_pop_model(const Tiling& t, const PopArgs& a, hipStream_t st) {
+  const int wpb = waves_per_block(MODEL, a.k_max, GRAD);
+  const size_t lds = pop_lds_bytes_per_wave(MODEL, a.k_max, GRAD) * wpb;
+  const int64_t items = a.N * (int64_t)a.nch;
+  if (items == 0) return hipSuccess;
+  const dim3 grid((unsigned)((items + wpb - 1) / wpb));
+  const dim3 block(64 * wpb);
+  switch (t.S) {
+    case 8: hipLaunchKernelGGL((pop_kernel<MODEL, 8, GRAD>), grid, block, lds, st, a); break;
+    case 16: hipLaunchKernelGGL((pop_kernel<MODEL, 16, GRAD>), grid, block, lds, st, a); break;
+    case 32: hipLaunchKernelGGL((pop_kernel<MODEL, 32, GRAD>), grid, block, lds, st, a); break;
+    case 64: hipLaunchKernelGGL((pop_kernel<MODEL, 64, GRAD>), grid, block, lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nch == 1) return e;
+  const dim3 fgrid((unsigned)((a.N + 3) / 4));
+  hipLaunchKernelGGL((finalize_kernel<MODEL, GRAD>), fgrid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int MODEL>
+hipError_t launch_delta_model(const Tiling& t, const PopArgs& a, hipStream_t st) {
+  const int wpb = waves_per_block(MODEL, a.k_max, false);
+  const size_t lds = pop_lds_bytes_per_wave(MODEL, a.k_max, false) * wpb;
+  const int64_t items = a.N * (int64_t)a.nch;
+  if (items == 0) return hipSuccess;
+  const dim3 grid((unsigned)((items + wpb - 1) / wpb));
+  const dim3 block(64 * wpb);
+  switch (t.S) {
+    case 8: hipLaunchKernelGGL((delta_kernel<MODEL, 8>), grid, block, lds, st, a); break;
+    case 16: hipLaunchKernelGGL((delta_kernel<MODEL, 16>), grid, block, lds, st, a); break;
+    case 32: hipLaunchKernelGGL((delta_kernel<MODEL, 32>), grid, block, lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.nch == 1) return e;
+  hipLaunchKernelGGL(delta_finalize_kernel, dim3((unsigned)((a.N + 255) / 256)), dim3(256), 0, st,
+                     a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t pop_lds_bytes_per_wave(int model, int32_t k_max, bool grad) {
+  const size_t per = const_bytes(model) + (grad ? (size_t)n_params(model) * 8 : 0);
+  return ((size_t)(k_max + 1) * per + 15) & ~(size_t)15;
+}
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
+  const size_t lds = 2 * (size_t)(a.k_max + 1) * sizeof(int);
+  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(1024), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  return model == SMCX_PULSE ? launch_pop_model<SMCX_PULSE, false>(t, a, st)
+                             : launch_pop_model<SMCX_GBSINE, false>(t, a, st);
+}
+
+hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  return model == SMCX_PULSE ? launch_pop_model<SMCX_PULSE, true>(t, a, st)
+                             : launch_pop_model<SMCX_GBSINE, true>(t, a, st);
+}
+
+hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  return model == SMCX_PULSE ? launch_delta_model<SMCX_PULSE>(t, a, st)
+                             : launch_delta_model<SMCX_GBSINE>(t, a, st);
+}
+
+hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
+                                  const double* logw_prev, double* logw, double* w_norm,
+                                  double* scalars, double* /*scratch*/, hipStream_t st) {
+  hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(1024), 0, st, N, delta_beta, logl_ext,
+                     logw_prev, logw, w_norm, scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_template_sum(int model, int64_t K, const double* theta, int64_t T,
+                               double t_start, double dt, double* out, hipStream_t st) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(template_sum_kernel, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st,
+                     model, K, theta, T, t_start, dt, out);
+  return hipGetLastError();
+}
+
+}  // namespace smcx

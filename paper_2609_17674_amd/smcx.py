@@ -1,0 +1,264 @@
+"""Python binding of libsmcx (ctypes; argument marshalling only).
+
+Every function here checks dtypes / devices / shapes, allocates outputs with
+torch when the caller did not pass them, and forwards raw device pointers
+and the current HIP stream to the C ABI declared in ``include/smcx.h``. All
+arithmetic of the path runs in the library's kernels. There is no fallback:
+if ``libsmcx.so`` is missing or cannot be loaded, importing the library
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmcx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "smcx.h")
+
+SMCX_OK, SMCX_EINVAL, SMCX_ENOMEM, SMCX_EDEVICE, SMCX_ECAPTURE = 0, -1, -2, -3, -4
+PULSE, GBSINE = 0, 1
+N_PARAMS = {PULSE: 3, GBSINE: 4}
+
+
+class SmcxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"smcx error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsmcx.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, D, I, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_int32
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "smcx_problem_create": [I, P, I64, D, D, D, I32, I64, I64, P, PP],
+        "smcx_problem_destroy": [P],
+        "smcx_device_status": [P, P],
+        "logl_batch": [P, I64, P, I64, P, P, P, P],
+        "logl_grad_batch": [P, I64, P, I64, P, P, P, P, P],
+        "delta_logl_birth_death": [P, I64, P, I64, P, P, P, P, P, P, P],
+        "reweight_extend": [P, I64, I64, I64, P, I64, P, D, P, P, P, P, P, P],
+        "smcx_template_sum": [I, I64, P, I64, D, D, P, P],
+        "smcx_plain_logl_grad": [P, I64, P, I64, P, P, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.smcx_last_error.argtypes = []
+    lib.smcx_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def header_functions() -> list:
+    """Names of the functions ``include/smcx.h`` declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def last_error() -> str:
+    return load_library().smcx_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != SMCX_OK:
+        raise SmcxError(rc, last_error())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Problem:
+    """Owning wrapper of an ``smcx_problem`` handle (smcx_problem_create)."""
+
+    def __init__(self, model: int, d: torch.Tensor, t_start: float, dt: float, sigma: float,
+                 k_max: int, n_max: int, m_max: int, stream=None):
+        lib = load_library()
+        d = _dev(d, torch.float64, "d")
+        self.model, self.P = int(model), N_PARAMS[int(model)]
+        self.T, self.t_start, self.dt, self.sigma = int(d.numel()), float(t_start), float(dt), float(sigma)
+        self.k_max, self.n_max, self.m_max = int(k_max), int(n_max), int(m_max)
+        h = ctypes.c_void_p()
+        _check(lib.smcx_problem_create(self.model, _ptr(d), self.T, self.t_start, self.dt, self.sigma,
+                                       self.k_max, self.n_max, self.m_max, _stream(stream),
+                                       ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().smcx_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_status(self, stream=None) -> None:
+        _check(load_library().smcx_device_status(self.handle, _stream(stream)))
+
+
+def _pop(prob: Problem, offsets, theta, beta):
+    offsets = _dev(offsets, torch.int64, "offsets")
+    N = offsets.numel() - 1
+    theta = _dev(theta, torch.float64, "theta")
+    if theta.dim() != 2 or theta.shape[1] != prob.P:
+        raise ValueError(f"theta must be [M, {prob.P}]")
+    if beta is not None:
+        beta = _dev(beta, torch.float64, "beta", (N,))
+    return offsets, N, theta, beta
+
+
+def logl_batch(prob: Problem, offsets, theta, beta=None, logl=None, stream=None) -> torch.Tensor:
+    offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
+    if logl is None:
+        logl = torch.empty(N, dtype=torch.float64, device=theta.device)
+    logl = _dev(logl, torch.float64, "logl", (N,))
+    _check(load_library().logl_batch(prob.handle, N, _ptr(offsets), theta.shape[0], _ptr(theta),
+                                     _ptr(beta), _ptr(logl), _stream(stream)))
+    return logl
+
+
+def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=None, stream=None,
+                    want_logl=True):
+    offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
+    if logl is None and want_logl:
+        logl = torch.empty(N, dtype=torch.float64, device=theta.device)
+    if logl is not None:
+        logl = _dev(logl, torch.float64, "logl", (N,))
+    if grad is None:
+        grad = torch.empty_like(theta)
+    grad = _dev(grad, torch.float64, "grad", tuple(theta.shape))
+    _check(load_library().logl_grad_batch(prob.handle, N, _ptr(offsets), theta.shape[0],
+                                          _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
+                                          _stream(stream)))
+    return logl, grad
+
+
+def delta_logl_birth_death(prob: Problem, offsets, theta, beta=None, theta_birth=None,
+                           death_idx=None, dlogl_birth=None, dlogl_death=None, stream=None):
+    offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
+    dev = theta.device
+    if theta_birth is not None:
+        theta_birth = _dev(theta_birth, torch.float64, "theta_birth", (N, prob.P))
+        if dlogl_birth is None:
+            dlogl_birth = torch.empty(N, dtype=torch.float64, device=dev)
+        dlogl_birth = _dev(dlogl_birth, torch.float64, "dlogl_birth", (N,))
+    if death_idx is not None:
+        death_idx = _dev(death_idx, torch.int32, "death_idx", (N,))
+        if dlogl_death is None:
+            dlogl_death = torch.empty(N, dtype=torch.float64, device=dev)
+        dlogl_death = _dev(dlogl_death, torch.float64, "dlogl_death", (N,))
+    _check(load_library().delta_logl_birth_death(prob.handle, N, _ptr(offsets), theta.shape[0],
+                                                 _ptr(theta), _ptr(beta), _ptr(theta_birth), _ptr(death_idx),
+                                                 _ptr(dlogl_birth), _ptr(dlogl_death),
+                                                 _stream(stream)))
+    return dlogl_birth, dlogl_death
+
+
+def reweight_extend(prob: Problem, T1: int, T2: int, offsets, theta, delta_beta: float,
+                    logw_prev=None, out=None, stream=None):
+    """Returns (logl_ext, logw, w_norm, scalars[ESS, logZ increment, max logw])."""
+    offsets, N, theta, _ = _pop(prob, offsets, theta, None)
+    dev = theta.device
+    if logw_prev is not None:
+        logw_prev = _dev(logw_prev, torch.float64, "logw_prev", (N,))
+    if out is None:
+        out = tuple(torch.empty(n, dtype=torch.float64, device=dev) for n in (N, N, N, 3))
+    le, lw, wn, sc = (_dev(t, torch.float64, nm, (n,)) for t, nm, n in
+                      zip(out, ("logl_ext", "logw", "w_norm", "scalars"), (N, N, N, 3)))
+    _check(load_library().reweight_extend(prob.handle, int(T1), int(T2), N, _ptr(offsets),
+                                          theta.shape[0], _ptr(theta), float(delta_beta), _ptr(logw_prev),
+                                          _ptr(le), _ptr(lw), _ptr(wn), _ptr(sc), _stream(stream)))
+    return le, lw, wn, sc
+
+
+def template_sum(model: int, theta, T: int, t_start: float, dt: float, out=None, stream=None):
+    theta = _dev(theta, torch.float64, "theta")
+    K = theta.shape[0] if theta.numel() else 0
+    if out is None:
+        out = torch.empty(T, dtype=torch.float64, device=theta.device)
+    out = _dev(out, torch.float64, "out", (T,))
+    _check(load_library().smcx_template_sum(int(model), K, _ptr(theta), int(T), float(t_start),
+                                            float(dt), _ptr(out), _stream(stream)))
+    return out
+
+
+def plain_logl_grad(prob: Problem, offsets_host, theta, beta=None, logl=None, grad=None,
+                    stream=None):
+    """One-particle-per-launch FP64 reference form; offsets are a host array."""
+    off = np.ascontiguousarray(np.asarray(offsets_host, dtype=np.int64))
+    N = off.shape[0] - 1
+    theta = _dev(theta, torch.float64, "theta")
+    if beta is not None:
+        beta = _dev(beta, torch.float64, "beta", (N,))
+    if logl is None:
+        logl = torch.empty(N, dtype=torch.float64, device=theta.device)
+    if grad is None:
+        grad = torch.empty_like(theta)
+    _check(load_library().smcx_plain_logl_grad(prob.handle, N, off.ctypes.data_as(ctypes.c_void_p),
+                                               theta.shape[0], _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
+                                               _stream(stream)))
+    return logl, grad
+
+
+class LogLGrad(torch.autograd.Function):
+    """Tempered population log-likelihood with the hand-written adjoint.
+
+    forward(theta [M,P], offsets [N+1], beta [N] or None, prob) -> logl [N]
+    runs the fused forward + adjoint kernel once and keeps the gradient; the
+    backward pass only applies the chain rule, scaling each particle's rows
+    by the incoming gradient of its log-likelihood.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, offsets, beta, prob):
+        logl, grad = logl_grad_batch(prob, offsets, theta.detach().contiguous(), beta)
+        ctx.save_for_backward(grad, offsets)
+        return logl
+
+    @staticmethod
+    def backward(ctx, g_logl):
+        grad, offsets = ctx.saved_tensors
+        counts = offsets[1:] - offsets[:-1]
+        rows = torch.repeat_interleave(g_logl.contiguous(), counts, output_size=grad.shape[0])
+        return grad * rows.unsqueeze(1), None, None, None

@@ -1,0 +1,368 @@
+"""Parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Small and medium cases compare every output element; full-size workloads
+compare a seeded sample of particles that the oracle evaluates one by one.
+Each case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import parity as pm
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PULSE, GB = wl.PULSE, wl.GBSINE
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+class Setup:
+    """A workload on the device with its problem handle."""
+
+    def __init__(self, lib, w, k_max=None, n_max=None, m_max=None, data=None):
+        self.w = w
+        self.d = pm.data_of(w) if data is None else data
+        self.prob = lib.Problem(w.model, pm.to_dev(self.d), w.t_start, w.dt, w.sigma,
+                                k_max or w.k_max, n_max or w.N, m_max or max(w.M, 1))
+        self.off = pm.to_dev(w.offsets)
+        self.th = pm.to_dev(w.theta.reshape(-1, w.P))
+        self.beta = pm.to_dev(w.beta)
+
+
+def run_grad(lib, s):
+    logl, grad = lib.logl_grad_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    s.prob.device_status()
+    return logl.cpu().numpy(), grad.cpu().numpy()
+
+
+GRAD_CASES = [
+    # name, model, overrides
+    ("pulse_small_full", "pulse_small", {}),                       # one 1024-sample tile, ragged 24
+    ("pulse_two_tiles", "pulse_batch", dict(N=300, T=5000)),      # 2 tiles of 4096, ragged tail
+    ("pulse_three_chunks", "pulse_batch", dict(N=120, T=20000)),  # 3 chunks + finalize pass
+    ("pulse_tiny_T", "pulse_small", dict(N=50, T=37)),             # T below one tile
+    ("gb_two_chunks", "gb_grad", dict(N=160, T=(1 << 13) + 777, k_hi=12)),
+    ("gb_one_chunk", "gb_grad", dict(N=90, T=3000, k_hi=30)),
+]
+
+
+@pytest.mark.parametrize("name,cfg,ov", GRAD_CASES, ids=[c[0] for c in GRAD_CASES])
+def test_logl_grad_parity(lib, orc, name, cfg, ov):
+    w = wl.make_config(cfg, **ov)
+    if w.model == PULSE:
+        w.beta = np.random.default_rng(5).random(w.N)
+        w.beta[::17] = 0.0
+    say(name, "N", w.N, "T", w.T, "M", w.M)
+    s = Setup(lib, w)
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+    # logl_batch (forward only) agrees with the oracle too
+    l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    pm.assert_logl(l2.cpu().numpy(), ref_l)
+
+
+def test_gb_nonzero_start_time(lib, orc):
+    w = wl.make_config("gb_grad", N=64, T=4000, k_hi=8)
+    w.t_start = 3.9e6
+    say("gb_t_start", w.t_start)
+    s = Setup(lib, w)
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+
+
+def test_sigma_and_no_beta(lib, orc):
+    w = wl.make_config("pulse_small", N=40, T=700, sigma=2.5)
+    w.noise *= 2.5
+    say("sigma2.5")
+    s = Setup(lib, w)
+    logl, grad = lib.logl_grad_batch(s.prob, s.off, s.th, None)
+    torch.cuda.synchronize()
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta)
+    pm.assert_logl(logl.cpu().numpy(), ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad.cpu().numpy(), ref_g, w.T, w.dt)
+
+
+def test_k0_and_empty(lib, orc):
+    w = wl.make_config("pulse_small", N=30, k_lo=0, k_hi=2)
+    say("k0")
+    s = Setup(lib, w)
+    logl, grad = run_grad(lib, s)
+    ref_l = orc.logl(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    k0 = w.K == 0
+    assert np.any(k0)
+    e0 = -0.5 * float(np.sum(s.d * s.d)) / w.sigma ** 2
+    assert np.allclose(logl[k0], w.beta[k0] * e0, rtol=1e-13)
+    # N = 0 is a no-op
+    off0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    th0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    l0, g0 = lib.logl_grad_batch(s.prob, off0, th0, None)
+    assert l0.numel() == 0 and g0.numel() == 0
+
+
+def test_batch_independence_and_determinism(lib, orc):
+    """A particle's result is bitwise the same in any batch, order and run."""
+    w = wl.make_config("pulse_batch", N=400, T=4096)
+    say("batch_independence")
+    s = Setup(lib, w)
+    l1, g1 = run_grad(lib, s)
+    l1b, g1b = run_grad(lib, s)
+    assert np.array_equal(l1, l1b) and np.array_equal(g1, g1b)
+    idx = np.random.default_rng(1).permutation(w.N)[:150]
+    sub = wl.subsample(w, idx)
+    s2 = Setup(lib, sub, k_max=w.k_max)
+    l2, g2 = run_grad(lib, s2)
+    assert np.array_equal(l2, l1[idx])
+    rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
+    assert np.array_equal(g2, g1[rows])
+
+
+def test_nan_parameters_stay_confined(lib, orc):
+    w = wl.make_config("pulse_small", N=20, k_lo=1, k_hi=4)
+    say("nan_confined")
+    s = Setup(lib, w)
+    l_ok, g_ok = run_grad(lib, s)
+    th = w.theta.copy()
+    th[w.offsets[3], 1] = np.nan
+    s.th = pm.to_dev(th)
+    l_bad, g_bad = run_grad(lib, s)
+    assert np.isnan(l_bad[3])
+    keep = np.arange(w.N) != 3
+    assert np.array_equal(l_bad[keep], l_ok[keep])
+    rows = np.ones(w.M, dtype=bool)
+    rows[w.offsets[3]:w.offsets[4]] = False
+    assert np.array_equal(g_bad[rows], g_ok[rows])
+
+
+def test_device_flag_for_k_above_kmax(lib, orc):
+    w = wl.make_config("pulse_small", N=12, k_lo=1, k_hi=6)
+    say("device_flag")
+    s = Setup(lib, w, k_max=4)
+    logl, _ = lib.logl_grad_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError) as ei:
+        s.prob.device_status()
+    assert "k_max" in str(ei.value)
+    ln = logl.cpu().numpy()
+    big = w.K > 4
+    assert np.all(np.isnan(ln[big])) and np.all(np.isfinite(ln[~big]))
+    ref = orc.logl(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(ln[~big], ref[~big])
+    s.prob.device_status()  # cleared
+
+
+def test_host_argument_errors(lib):
+    w = wl.make_config("pulse_small", N=8)
+    say("host_errors")
+    s = Setup(lib, w)
+    big = torch.zeros(w.N + 10, dtype=torch.int64, device="cuda")
+    with pytest.raises(lib.SmcxError) as ei:
+        lib.logl_batch(s.prob, big, s.th)
+    assert ei.value.code == lib.SMCX_EINVAL and "n_max" in str(ei.value)
+    with pytest.raises(lib.SmcxError):
+        lib.reweight_extend(s.prob, 10, 5, s.off, s.th, 0.1)
+    with pytest.raises(lib.SmcxError):
+        lib.reweight_extend(s.prob, 0, w.T + 1, s.off, s.th, 0.1)
+
+
+# ---------------------------------------------------------------- birth / death
+@pytest.mark.parametrize("cfg,ov", [("pulse_mutate", dict(N=300, T=4096)),
+                                    ("pulse_mutate", dict(N=64, T=9000)),
+                                    ("gb_grad", dict(N=80, T=(1 << 13) + 100, k_hi=10, rj=True))],
+                         ids=["pulse_4096", "pulse_two_chunks", "gb"])
+def test_birth_death_parity(lib, orc, cfg, ov):
+    w = wl.make_config(cfg, **ov)
+    say("birth_death", cfg, ov)
+    s = Setup(lib, w)
+    tb = w.extra["theta_birth"]
+    di = w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta, pm.to_dev(tb),
+                                        pm.to_dev(di))
+    torch.cuda.synchronize()
+    s.prob.device_status()
+    db, dd = db.cpu().numpy(), dd.cpu().numpy()
+    rb, rd = orc.delta_logl_birth_death(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta,
+                                        w.beta, tb, di)
+    sb = pm.delta_scale(w.model, w, list(tb), w.beta, w.sigma, rb)
+    rows = [w.theta[w.offsets[i] + di[i]] if di[i] >= 0 else None for i in range(w.N)]
+    sd = pm.delta_scale(w.model, w, rows, w.beta, w.sigma, rd)
+    assert np.all(np.abs(db - rb) <= 1e-6 * sb), np.max(np.abs(db - rb) / np.maximum(sb, 1e-300))
+    assert np.all(np.abs(dd - rd) <= 1e-6 * sd), np.max(np.abs(dd - rd) / np.maximum(sd, 1e-300))
+    assert np.all(dd[di < 0] == 0.0)
+
+
+@pytest.mark.parametrize("model", [PULSE, GB])
+def test_birth_then_death_is_bitwise_zero(lib, orc, model):
+    w = wl.make_config("pulse_mutate" if model == PULSE else "gb_grad", N=200, T=4096, k_hi=8,
+                       rj=True)
+    say("birth_death_zero", model)
+    s = Setup(lib, w, k_max=w.k_max + 1, m_max=w.M + w.N)
+    tb = w.extra["theta_birth"]
+    db, _ = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta, pm.to_dev(tb), None)
+    K2 = w.K + 1
+    off2 = wl.counts_to_offsets(K2)
+    th2 = np.zeros((int(off2[-1]), w.P))
+    for i in range(w.N):
+        th2[off2[i]:off2[i] + w.K[i]] = w.theta[w.offsets[i]:w.offsets[i + 1]]
+        th2[off2[i] + w.K[i]] = tb[i]
+    _, dd = lib.delta_logl_birth_death(s.prob, pm.to_dev(off2), pm.to_dev(th2), s.beta, None,
+                                       pm.to_dev(w.K.astype(np.int32)))
+    torch.cuda.synchronize()
+    s.prob.device_status()
+    assert np.all(db.cpu().numpy() + dd.cpu().numpy() == 0.0)
+    # and the birth matches the change of the batched logL within tolerance
+    l1 = lib.logl_batch(s.prob, s.off, s.th, s.beta).cpu().numpy()
+    l2 = lib.logl_batch(s.prob, pm.to_dev(off2), pm.to_dev(th2), s.beta).cpu().numpy()
+    scale = np.abs(l1) + np.abs(l2)
+    assert np.all(np.abs(db.cpu().numpy() - (l2 - l1)) <= 2e-6 * scale)
+
+
+# ---------------------------------------------------------------- reweighting
+@pytest.mark.parametrize("ov", [dict(N=500, T=20000, T1=12000, T2=20000, k_hi=8, n_inj=6),
+                                dict(N=100, T=3000, T1=1000, T2=2999, k_hi=20, n_inj=3)],
+                         ids=["two_chunks", "ragged"])
+def test_reweight_parity(lib, orc, ov):
+    w = wl.make_config("gb_extend", **ov)
+    T1, T2 = ov["T1"], ov["T2"]
+    say("reweight", ov)
+    s = Setup(lib, w)
+    for db_, prev in ((0.05, None), (0.3, np.random.default_rng(2).normal(size=w.N))):
+        le, lw, wn, sc = lib.reweight_extend(s.prob, T1, T2, s.off, s.th, db_,
+                                             None if prev is None else pm.to_dev(prev))
+        torch.cuda.synchronize()
+        s.prob.device_status()
+        rle, rlw, rwn, rsc = orc.reweight_extend(w.model, s.d, w.t_start, w.dt, w.sigma, T1, T2,
+                                                 w.offsets, w.theta, db_, prev)
+        le, lw, wn, sc = (x.cpu().numpy() for x in (le, lw, wn, sc))
+        pm.assert_logl(le, rle, what="logl_ext")
+        tol = abs(db_) * np.max(np.abs(rle)) * 1e-6 * 2 + 1e-12
+        assert np.all(np.abs(lw - rlw) <= tol)
+        assert np.all(np.abs(np.log(wn) - np.log(rwn)) <= 2 * tol + 1e-12)
+        assert abs(np.log(sc[0]) - np.log(rsc[0])) <= 4 * tol + 1e-12
+        assert abs(sc[1] - rsc[1]) <= 2 * tol + 1e-12
+        assert abs(sc[2] - rsc[2]) <= tol
+        assert abs(wn.sum() - 1.0) <= 1e-12
+
+
+def test_reweight_zero_step_textbook(lib):
+    w = wl.make_config("gb_extend", N=333, T=5000, T1=2500, T2=5000, k_hi=5, n_inj=2)
+    say("reweight_textbook")
+    s = Setup(lib, w)
+    le, lw, wn, sc = lib.reweight_extend(s.prob, 2500, 5000, s.off, s.th, 0.0)
+    torch.cuda.synchronize()
+    sc = sc.cpu().numpy()
+    assert sc[0] == pytest.approx(w.N, rel=1e-13) and abs(sc[1]) <= 1e-13
+    assert np.allclose(wn.cpu().numpy(), 1.0 / w.N, rtol=1e-13)
+
+
+# ---------------------------------------------------------------- other entry points
+def test_template_sum_matches_oracle(lib, orc):
+    for model, cfg in ((PULSE, "pulse_batch"), (GB, "gb_grad")):
+        w = wl.make_config(cfg, T=5000)
+        say("template_sum", model)
+        out = lib.template_sum(model, pm.to_dev(w.inj), w.T, w.t_start, w.dt)
+        torch.cuda.synchronize()
+        ref = orc.template_sum(model, w.inj, w.T, w.t_start, w.dt)
+        assert np.allclose(out.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("cfg", ["pulse_small", "gb_grad"])
+def test_plain_form_parity(lib, orc, cfg):
+    w = wl.make_config(cfg, N=24, T=3000 if cfg == "gb_grad" else 1000, k_hi=8)
+    say("plain", cfg)
+    s = Setup(lib, w)
+    logl, grad = lib.plain_logl_grad(s.prob, w.offsets, s.th, s.beta)
+    torch.cuda.synchronize()
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl.cpu().numpy(), ref_l, rtol=1e-10)
+    rel, _ = pm.grad_errors(w.model, w.offsets, w.theta, grad.cpu().numpy(), ref_g, w.T, w.dt)
+    assert np.all(rel <= 1e-9)
+
+
+def test_autograd_function(lib, orc):
+    w = wl.make_config("pulse_small", N=16, k_lo=1, k_hi=5)
+    say("autograd")
+    s = Setup(lib, w)
+    th = s.th.clone().requires_grad_(True)
+    logl = lib.LogLGrad.apply(th, s.off, s.beta, s.prob)
+    wts = torch.linspace(0.5, 2.0, w.N, device="cuda", dtype=torch.float64)
+    (logl * wts).sum().backward()
+    _, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    rows = np.repeat(wts.cpu().numpy(), w.K)[:, None]
+    pm.assert_grad(w.model, w.offsets, w.theta, th.grad.cpu().numpy(), ref_g * rows, w.T, w.dt)
+
+
+# ---------------------------------------------------------------- full-size workloads
+def _sample(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False))
+
+
+@pytest.mark.parametrize("cfg,n_check", [("pulse_batch", 256), ("gb_grad", 24)])
+def test_full_size_grad_sampled(lib, orc, cfg, n_check):
+    w = wl.make_config(cfg)
+    say("full_size_grad", cfg, "N", w.N, "T", w.T, "M", w.M)
+    s = Setup(lib, w)
+    logl, grad = run_grad(lib, s)
+    assert np.all(np.isfinite(logl)) and np.all(np.isfinite(grad))
+    idx = _sample(w.N, n_check, 9)
+    sub = wl.subsample(w, idx)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, sub.offsets, sub.theta,
+                                 sub.beta)
+    pm.assert_logl(logl[idx], ref_l)
+    rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
+    pm.assert_grad(w.model, sub.offsets, sub.theta, grad[rows], ref_g, w.T, w.dt)
+
+
+def test_full_size_birth_death_sampled(lib, orc):
+    w = wl.make_config("pulse_mutate")
+    say("full_size_delta", w.N)
+    s = Setup(lib, w)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta, pm.to_dev(tb), pm.to_dev(di))
+    torch.cuda.synchronize()
+    s.prob.device_status()
+    idx = _sample(w.N, 128, 10)
+    sub = wl.subsample(w, idx)
+    rb, rd = orc.delta_logl_birth_death(w.model, s.d, w.t_start, w.dt, w.sigma, sub.offsets,
+                                        sub.theta, sub.beta, tb[idx], di[idx])
+    db, dd = db.cpu().numpy()[idx], dd.cpu().numpy()[idx]
+    sb = pm.delta_scale(w.model, w, list(tb[idx]), sub.beta, w.sigma, rb)
+    rows = [sub.theta[sub.offsets[q] + di[i]] if di[i] >= 0 else None for q, i in enumerate(idx)]
+    sd = pm.delta_scale(w.model, w, rows, sub.beta, w.sigma, rd)
+    assert np.all(np.abs(db - rb) <= 1e-6 * sb)
+    assert np.all(np.abs(dd - rd) <= 1e-6 * sd)
+
+
+def test_full_size_reweight_sampled(lib, orc):
+    w = wl.make_config("gb_extend")
+    T1, T2 = w.extra["T1"], w.extra["T2"]
+    say("full_size_reweight", w.N, w.M)
+    s = Setup(lib, w)
+    le, lw, wn, sc = lib.reweight_extend(s.prob, T1, T2, s.off, s.th, 1.0)
+    torch.cuda.synchronize()
+    s.prob.device_status()
+    le = le.cpu().numpy()
+    idx = _sample(w.N, 24, 11)
+    sub = wl.subsample(w, idx)
+    rle, _, _, _ = orc.reweight_extend(w.model, s.d, w.t_start, w.dt, w.sigma, T1, T2, sub.offsets,
+                                       sub.theta, 1.0)
+    pm.assert_logl(le[idx], rle, what="logl_ext")
+    # population reductions, checked against float64 numpy on the GPU's own logl_ext
+    lw_ref = le
+    m = lw_ref.max()
+    e = np.exp(lw_ref - m)
+    assert sc.cpu().numpy()[0] == pytest.approx(e.sum() ** 2 / (e * e).sum(), rel=1e-10)
+    assert np.allclose(wn.cpu().numpy(), e / e.sum(), rtol=1e-10, atol=0)
