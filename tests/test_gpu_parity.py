@@ -250,7 +250,9 @@ def test_reweight_parity(lib, orc, ov):
         pm.assert_logl(le, rle, what="logl_ext")
         tol = abs(db_) * np.max(np.abs(rle)) * 1e-6 * 2 + 1e-12
         assert np.all(np.abs(lw - rlw) <= tol)
-        assert np.all(np.abs(np.log(wn) - np.log(rwn)) <= 2 * tol + 1e-12)
+        big = rwn > 1e-250  # below that the weights underflow towards 0 on both sides
+        assert np.all(np.abs(np.log(wn[big]) - np.log(rwn[big])) <= 2 * tol + 1e-12)
+        assert np.all(wn[~big] <= 1e-249)
         assert abs(np.log(sc[0]) - np.log(rsc[0])) <= 4 * tol + 1e-12
         assert abs(sc[1] - rsc[1]) <= 2 * tol + 1e-12
         assert abs(sc[2] - rsc[2]) <= tol
