@@ -199,6 +199,39 @@ int smcx_plain_logl_grad(smcx_problem* prob, int64_t N, const int64_t* offsets_h
                          const double* theta, const double* beta, double* logl, double* grad,
                          void* hip_stream);
 
+/* Tiling of the sample axis, per call kind: SMCX_KIND_LOGL (logl_batch and
+ * the segment pass of reweight_extend), SMCX_KIND_GRAD (logl_grad_batch),
+ * SMCX_KIND_DELTA (delta_logl_birth_death). A wave owns one (particle,
+ * chunk) work item and walks the chunk in tiles of 64*S samples.
+ *   S          samples per lane per tile: 8, 16, 32 or 64 (DELTA: 8 or 16)
+ *   chunk_len  samples per chunk, a positive multiple of 64*S; the number of
+ *              chunks ceil(T / chunk_len) must fit the workspace sized at
+ *              create (at most min(64, ceil(T/1024)) chunks, and for GRAD
+ *              with more than one chunk at most min(32, ceil(T/4096)))
+ *   sorted     1: an ordering pass schedules particles longest-K first;
+ *              0: particles are scheduled in index order
+ * The tiling fixes the summation order inside a particle, so results are
+ * bitwise reproducible for a fixed tiling (and independent of N and of the
+ * other particles), and change only within rounding when it changes. The
+ * defaults depend on the model and T only. Returns SMCX_EINVAL for values
+ * outside these ranges. */
+enum { SMCX_KIND_LOGL = 0, SMCX_KIND_GRAD = 1, SMCX_KIND_DELTA = 2 };
+int smcx_set_tiling(smcx_problem* prob, int32_t kind, int32_t S, int64_t chunk_len,
+                    int32_t sorted);
+int smcx_get_tiling(smcx_problem* prob, int32_t kind, int32_t* S, int64_t* chunk_len,
+                    int32_t* sorted);
+
+/* Measurement hooks. Between smcx_profile_begin and smcx_profile_end every
+ * compute call on the handle brackets its batched kernel launches (the
+ * population kernel and, for split sample ranges, its combine pass; not the
+ * ordering pass) with a pair of HIP events recorded on the call's stream,
+ * for at most max_launches calls. smcx_profile_end synchronises those
+ * events and returns the summed elapsed time and the number of bracketed
+ * calls. Calls made while the stream is being captured are not bracketed.
+ * begin creates the events (host-side HIP objects, no device memory). */
+int smcx_profile_begin(smcx_problem* prob, int32_t max_launches);
+int smcx_profile_end(smcx_problem* prob, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,16 +51,22 @@ Tiling default_tiling(int model, int kind, int64_t T) {
     if (kind == kDelta)
       t.S = 16;
     else
-      t.S = T >= 2048 ? 64 : (T >= 512 ? 16 : 8);
+      t.S = T >= 2048 ? 32 : (T >= 512 ? 16 : 8);
     const int64_t tile = 64 * (int64_t)t.S;
     t.chunk_len = T <= 8192 ? round_up(T, tile) : round_up(8192, tile);
   } else {
-    t.S = kind == kDelta ? 16 : 32;
-    t.chunk_len = 8192;
+    t.S = 16;
+    t.chunk_len = 4096;
   }
   t.nch = (int)((T + t.chunk_len - 1) / t.chunk_len);
+  t.sorted = 1;
   return t;
 }
+
+// Workspace capacities fixed at create: any tiling with at most this many
+// chunks per particle fits the partial-sum buffers.
+int cap_chunks(int64_t T) { return (int)std::min<int64_t>(64, (T + 1023) / 1024); }
+int cap_chunks_grad(int64_t T) { return (int)std::min<int64_t>(32, (T + 4095) / 4096); }
 
 Tiling with_range(Tiling t, int64_t len) {
   t.nch = len <= 0 ? 0 : (int)((len + t.chunk_len - 1) / t.chunk_len);
@@ -81,7 +87,8 @@ struct smcx_problem {
   double* d64 = nullptr;
   std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
   Tiling tiling[kNumKinds];
-  int max_nch = 0;
+  int max_nch = 0;       // capacity of part (chunks per particle)
+  int max_nch_grad = 0;  // capacity of part_g
   int32_t* order = nullptr;
   int32_t* n_active = nullptr;
   int* flag = nullptr;
@@ -89,12 +96,17 @@ struct smcx_problem {
   double* part_g = nullptr; // [nch_grad][m_max][P]
   double* rbuf = nullptr;   // plain form residual [T]
   double* bpart = nullptr;  // plain form block partials
+  // measurement hooks
+  bool prof_on = false;
+  int prof_n = 0;
+  std::vector<hipEvent_t> prof_ev;  // [2 * capacity]
 };
 
 namespace {
 
 void free_problem(smcx_problem* p) {
   if (!p) return;
+  for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
   (void)hipFree(p->d32);
   (void)hipFree(p->d64);
   (void)hipFree(p->order);
@@ -123,10 +135,28 @@ int check_pop(const smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   return SMCX_OK;
 }
 
-smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, const double* theta,
-                        const double* beta, const Tiling& t, int64_t s_lo, int64_t s_hi) {
+// Bracket the batched kernels of one call with events when profiling is on.
+struct ProfScope {
+  smcx_problem* p;
+  hipStream_t st;
+  bool on;
+  ProfScope(smcx_problem* p_, hipStream_t st_) : p(p_), st(st_), on(false) {
+    if (p->prof_on && 2 * (size_t)p->prof_n + 1 < p->prof_ev.size() && !capturing(st)) {
+      on = hipEventRecord(p->prof_ev[2 * p->prof_n], st) == hipSuccess;
+    }
+  }
+  ~ProfScope() {
+    if (on && hipEventRecord(p->prof_ev[2 * p->prof_n + 1], st) == hipSuccess) ++p->prof_n;
+  }
+};
+
+smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                        const double* theta, const double* beta, const Tiling& t, int64_t s_lo,
+                        int64_t s_hi, double k0) {
   smcx::PopArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.M = M;
+  a.k0 = k0;
   a.d32 = p->d32;
   a.s_lo = s_lo;
   a.s_hi = s_hi;
@@ -139,7 +169,7 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, cons
   a.N = N;
   a.k_max = p->k_max;
   a.m_max = p->m_max;
-  a.order = p->order;
+  a.order = t.sorted ? p->order : nullptr;
   a.n_active = p->n_active;
   a.nch = t.nch;
   a.chunk_len = t.chunk_len;
@@ -207,28 +237,33 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
 
+  p->max_nch = cap_chunks(T);
+  p->max_nch_grad = cap_chunks_grad(T);
   for (int k = 0; k < kNumKinds; ++k) {
     p->tiling[k] = default_tiling(model, k, T);
-    if (p->tiling[k].nch > p->max_nch) p->max_nch = p->tiling[k].nch;
+    p->max_nch = std::max(p->max_nch, p->tiling[k].nch);
   }
+  p->max_nch_grad = std::max(p->max_nch_grad, p->tiling[kGrad].nch);
   // data: FP64 copy (plain form), FP32 copy (batched kernels), FP64 energy prefix sums (host)
   std::vector<double> h(T);
   e = hipMemcpyAsync(h.data(), d_dev, T * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "copy of d"); }
-  std::vector<float> h32(T);
+  // FP32 copy zero-padded by one full 4096-sample tile past T (tile loads need no guard)
+  const int64_t T_pad = round_up(T, 4096) + 4096;
+  std::vector<float> h32(T_pad, 0.0f);
   p->prefix.assign(T + 1, 0.0);
   for (int64_t s = 0; s < T; ++s) {
     h32[s] = (float)h[s];
     p->prefix[s + 1] = p->prefix[s] + h[s] * h[s];
   }
   const size_t part_elems = (size_t)p->max_nch * (size_t)std::max<int64_t>(n_max, 1) * 4;
-  const size_t partg_elems = p->tiling[kGrad].nch > 1
-                                 ? (size_t)p->tiling[kGrad].nch * (size_t)std::max<int64_t>(m_max, 1) * p->P
+  const size_t partg_elems = p->max_nch_grad > 1
+                                 ? (size_t)p->max_nch_grad * (size_t)std::max<int64_t>(m_max, 1) * p->P
                                  : 1;
   const int nb = (int)((T + 255) / 256);
   struct { void** ptr; size_t bytes; } allocs[] = {
-      {(void**)&p->d32, T * sizeof(float)},
+      {(void**)&p->d32, T_pad * sizeof(float)},
       {(void**)&p->d64, T * sizeof(double)},
       {(void**)&p->order, (size_t)std::max<int64_t>(n_max, 1) * sizeof(int32_t)},
       {(void**)&p->n_active, sizeof(int32_t)},
@@ -246,7 +281,7 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
     }
   }
   const int zero = 0;
-  e = hipMemcpyAsync(p->d32, h32.data(), T * sizeof(float), hipMemcpyHostToDevice, st);
+  e = hipMemcpyAsync(p->d32, h32.data(), T_pad * sizeof(float), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(p->d64, d_dev, T * sizeof(double), hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(p->n_active, &zero, sizeof(int), hipMemcpyHostToDevice, st);
@@ -295,14 +330,20 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   if (N == 0) return SMCX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
-  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
-  pa.logl = logl;
-  hipError_t e = smcx::launch_prep(pa, st);
-  if (e != hipSuccess) return hip_fail(e, "prep launch");
   const Tiling& t = p->tiling[kFwd];
-  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  hipError_t e = hipSuccess;
+  if (t.sorted) {
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.logl = logl;
+    e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+  }
+  smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, k0);
   a.logl = logl;
-  e = smcx::launch_forward(p->model, t, a, st);
+  {
+    ProfScope ps(p, st);
+    e = smcx::launch_forward(p->model, t, a, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "logl launch");
   return SMCX_OK;
 }
@@ -317,16 +358,22 @@ int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   if (N == 0) return SMCX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
   const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
-  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
-  pa.logl = logl;
-  pa.grad = grad;
-  hipError_t e = smcx::launch_prep(pa, st);
-  if (e != hipSuccess) return hip_fail(e, "prep launch");
   const Tiling& t = p->tiling[kGrad];
-  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  hipError_t e = hipSuccess;
+  if (t.sorted) {
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.logl = logl;
+    pa.grad = grad;
+    e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+  }
+  smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, k0);
   a.logl = logl;
   a.grad = grad;
-  e = smcx::launch_fused(p->model, t, a, st);
+  {
+    ProfScope ps(p, st);
+    e = smcx::launch_fused(p->model, t, a, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "logl_grad launch");
   return SMCX_OK;
 }
@@ -343,20 +390,26 @@ int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, i
   if (N == 0 || (!theta_birth && !death_idx)) return SMCX_OK;
   if (p->k_max + 1 > 513) return fail(SMCX_EINVAL, "k_max too large for the birth slot");
   hipStream_t st = (hipStream_t)hip_stream;
-  smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, 0.0, 1);
-  pa.include_k0 = 1;
-  pa.death_idx = death_idx;
-  pa.dlogl_birth = theta_birth ? dlogl_birth : nullptr;
-  pa.dlogl_death = death_idx ? dlogl_death : nullptr;
-  hipError_t e = smcx::launch_prep(pa, st);
-  if (e != hipSuccess) return hip_fail(e, "prep launch");
   const Tiling& t = p->tiling[kDelta];
-  smcx::PopArgs a = base_args(p, N, offsets, theta, beta, t, 0, p->T);
+  hipError_t e = hipSuccess;
+  if (t.sorted) {
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, 0.0, 1);
+    pa.include_k0 = 1;
+    pa.death_idx = death_idx;
+    pa.dlogl_birth = theta_birth ? dlogl_birth : nullptr;
+    pa.dlogl_death = death_idx ? dlogl_death : nullptr;
+    e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+  }
+  smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, 0.0);
   a.theta_birth = theta_birth;
   a.death_idx = death_idx;
   a.dlogl_birth = dlogl_birth;
   a.dlogl_death = dlogl_death;
-  e = smcx::launch_delta(p->model, t, a, st);
+  {
+    ProfScope ps(p, st);
+    e = smcx::launch_delta(p->model, t, a, st);
+  }
   if (e != hipSuccess) return hip_fail(e, "delta launch");
   return SMCX_OK;
 }
@@ -377,14 +430,20 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
   hipStream_t st = (hipStream_t)hip_stream;
   if (N > 0) {
     const double k0 = -0.5 * (p->prefix[T2] - p->prefix[T1]) * p->inv_sigma2;
-    smcx::PrepArgs pa = prep_args(p, N, offsets, M, nullptr, k0, 0);
-    pa.logl = logl_ext;
-    hipError_t e = smcx::launch_prep(pa, st);
-    if (e != hipSuccess) return hip_fail(e, "prep launch");
     const Tiling t = with_range(p->tiling[kFwd], T2 - T1);
-    smcx::PopArgs a = base_args(p, N, offsets, theta, nullptr, t, T1, T2);
+    hipError_t e = hipSuccess;
+    if (t.sorted) {
+      smcx::PrepArgs pa = prep_args(p, N, offsets, M, nullptr, k0, 0);
+      pa.logl = logl_ext;
+      e = smcx::launch_prep(pa, st);
+      if (e != hipSuccess) return hip_fail(e, "prep launch");
+    }
+    smcx::PopArgs a = base_args(p, N, offsets, M, theta, nullptr, t, T1, T2, k0);
     a.logl = logl_ext;
-    e = smcx::launch_forward(p->model, t, a, st);
+    {
+      ProfScope ps(p, st);
+      e = smcx::launch_forward(p->model, t, a, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "segment logl launch");
   }
   hipError_t e = smcx::launch_reweight_reduce(N, delta_beta, logl_ext, logw_prev, logw, w_norm,
@@ -430,6 +489,71 @@ int smcx_plain_logl_grad(smcx_problem* p, int64_t N, const int64_t* offsets_host
                                                p->rbuf, p->bpart, logl, grad + m0 * p->P, st);
     if (e != hipSuccess) return hip_fail(e, "plain launch");
   }
+  return SMCX_OK;
+}
+
+int smcx_set_tiling(smcx_problem* p, int32_t kind, int32_t S, int64_t chunk_len, int32_t sorted) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (kind < 0 || kind >= kNumKinds) return fail(SMCX_EINVAL, "unknown call kind %d", kind);
+  const bool s_ok = kind == kDelta ? (S == 8 || S == 16) : (S == 8 || S == 16 || S == 32 || S == 64);
+  if (!s_ok) return fail(SMCX_EINVAL, "S = %d not supported for this call kind", S);
+  if (chunk_len <= 0 || chunk_len % (64 * (int64_t)S) != 0)
+    return fail(SMCX_EINVAL, "chunk_len must be a positive multiple of 64*S");
+  if (sorted != 0 && sorted != 1) return fail(SMCX_EINVAL, "sorted must be 0 or 1");
+  Tiling t;
+  t.S = S;
+  t.chunk_len = chunk_len;
+  t.nch = (int)((p->T + chunk_len - 1) / chunk_len);
+  t.sorted = sorted;
+  if (t.nch > p->max_nch) return fail(SMCX_EINVAL, "%d chunks exceed the workspace (%d)", t.nch, p->max_nch);
+  if (kind == kGrad && t.nch > 1 && t.nch > p->max_nch_grad)
+    return fail(SMCX_EINVAL, "%d gradient chunks exceed the workspace (%d)", t.nch, p->max_nch_grad);
+  p->tiling[kind] = t;
+  return SMCX_OK;
+}
+
+int smcx_get_tiling(smcx_problem* p, int32_t kind, int32_t* S, int64_t* chunk_len, int32_t* sorted) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (kind < 0 || kind >= kNumKinds) return fail(SMCX_EINVAL, "unknown call kind %d", kind);
+  if (S) *S = p->tiling[kind].S;
+  if (chunk_len) *chunk_len = p->tiling[kind].chunk_len;
+  if (sorted) *sorted = p->tiling[kind].sorted;
+  return SMCX_OK;
+}
+
+int smcx_profile_begin(smcx_problem* p, int32_t max_launches) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (max_launches < 1 || max_launches > (1 << 16)) return fail(SMCX_EINVAL, "max_launches out of range");
+  const size_t need = 2 * (size_t)max_launches;
+  while (p->prof_ev.size() < need) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    p->prof_ev.push_back(e);
+  }
+  p->prof_n = 0;
+  p->prof_on = true;
+  return SMCX_OK;
+}
+
+int smcx_profile_end(smcx_problem* p, double* total_ms, int64_t* launches) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  p->prof_on = false;
+  double tot = 0.0;
+  for (int i = 0; i < p->prof_n; ++i) {
+    hipError_t e = hipEventSynchronize(p->prof_ev[2 * i + 1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "profile event");
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = p->prof_n;
+  p->prof_n = 0;
   return SMCX_OK;
 }
 

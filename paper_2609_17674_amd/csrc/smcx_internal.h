@@ -34,6 +34,7 @@ struct Tiling {
   int S;              // samples per lane per tile (8, 16, 32 or 64)
   int64_t chunk_len;  // samples per chunk (multiple of 64*S)
   int nch;            // chunks covering [s_lo, s_hi)
+  int sorted;         // 1: items ordered by K descending (ordering pass), 0: particle order
 };
 
 // Arguments of the batched population kernels (forward, fused forward +
@@ -46,10 +47,12 @@ struct PopArgs {
   const double* theta;     // [M][P]
   const double* beta;      // [N] or nullptr (beta = 1)
   int64_t N;
+  int64_t M;               // rows of theta (offsets[N] must equal it)
   int32_t k_max;
   int64_t m_max;
-  const int32_t* order;    // [N] particles with K > 0, sorted by K descending
-  const int32_t* n_active; // device scalar: number of entries of order
+  double k0;               // untempered logL of a particle without components
+  const int32_t* order;    // [N] particles sorted by K descending, or nullptr: particle order
+  const int32_t* n_active; // device scalar: number of entries of order (sorted mode)
   int nch;
   int64_t chunk_len;
   // outputs

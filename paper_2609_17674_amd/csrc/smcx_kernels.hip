@@ -120,7 +120,7 @@ __device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, d
 struct GbC {
   double a0, a1, a2;  // phase polynomial in cycles
   float A;
-  float pad;
+  float c2;  // 4096 a2 in units of 2^-32 cycles: the chirp per (sample step of 64)^2
 };
 static_assert(sizeof(GbC) == 32, "GB constants are 32 bytes");
 
@@ -132,53 +132,73 @@ __device__ __forceinline__ GbC gb_make(const double* th, double t_start, double 
   r.a1 = (f0 + fd * t_start) * dt;
   r.a2 = 0.5 * fd * dt * dt;
   r.A = (float)A;
-  r.pad = 0.f;
-  // The per-sample phase is evaluated relative to the lane's first sample of
-  // the tile; the offset must stay well inside the 2^19-cycle window of the
-  // magic-constant reduction.
-  const double p1a = fabs(64.0 * (r.a1 + 2.0 * r.a2 * (double)s_lo));
-  const double p1b = fabs(64.0 * (r.a1 + 2.0 * r.a2 * (double)s_hi));
-  const double span = fmax(p1a, p1b) * S + fabs(4096.0 * r.a2) * (double)S * S;
-  if (!(span < 262144.0)) {
-    if (span == span) atomicOr(flag, kFlagPhase);
+  r.c2 = (float)(4096.0 * r.a2 * 4294967296.0);
+  // The phase must stay small enough that FP64 resolves it to well below
+  // 2^-32 cycles (|phase| < 2^20 cycles), and the in-tile chirp correction
+  // must stay a small fraction of a cycle.
+  const double sh = (double)s_hi;
+  const double pmax = fabs(r.a0) + fabs(r.a1) * sh + fabs(r.a2) * sh * sh;
+  const double chirp = fabs(4096.0 * r.a2) * (double)S * S;
+  if (!(pmax < 1048576.0 && chirp < 0.015625)) {
+    if (pmax == pmax && chirp == chirp) atomicOr(flag, kFlagPhase);
     r.A = __builtin_nanf("");
   }
   return r;
 }
 
-// Phase (revolutions, in [-0.5, 0.5)) from the reduced FP64 value y.
-__device__ __forceinline__ float rev_of(double y) {
-  const int lo = (int)(__builtin_bit_cast(long long, y) & 0xffffffffll);
-  return (float)lo * 0x1p-32f;
+// Low 32 bits of y + 1.5*2^20: for |y| < 2^19 this is y mod 1 cycle as a
+// fixed-point number in units of 2^-32 cycles (the sum is rounded to that unit).
+__device__ __forceinline__ unsigned int fixed_cycles(double y) {
+  return (unsigned int)(__builtin_bit_cast(long long, y + kPhaseMagic) & 0xffffffffll);
 }
 
+// Per (component, lane, tile): the lane's samples are s = u + 64 j, so the
+// phase is P0 + P1 j + P2 j^2 with P0 = a0 + a1 u + a2 u^2, P1 = 64 a1 +
+// 128 a2 u, P2 = 4096 a2. P0 and P1 are reduced modulo one cycle in FP64 and
+// carried as 32-bit fixed point (wrap-around is the modulo); P0 + P1 j is an
+// exact integer recurrence up to the rounding of P1 to 2^-32 (at most j/2
+// units), and P2 j^2 (a tiny chirp correction) is added in FP32.
 struct GbTile {
-  double Y0, P1, P2;
+  unsigned int F0;  // P0 mod 1, fixed point
+  unsigned int D;   // P1 mod 1, fixed point
+  float c2;         // P2 in fixed-point units
 };
 __device__ __forceinline__ GbTile gb_tile(const GbC& c, double u) {
-  GbTile t;
   const double P0 = fma(fma(c.a2, u, c.a1), u, c.a0);
-  t.Y0 = (P0 - rint(P0)) + kPhaseMagic;
-  t.P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
-  t.P2 = 4096.0 * c.a2;
+  const double P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
+  GbTile t;
+  t.F0 = fixed_cycles(P0 - rint(P0));
+  t.D = fixed_cycles(P1 - rint(P1));
+  t.c2 = c.c2;
   return t;
 }
+// Phase of sample j in revolutions (about [-0.5, 0.5)), F = F0 + j D mod 2^32.
 template <int J>
-__device__ __forceinline__ double gb_y(const GbTile& t) {
-  if (J == 0) return t.Y0;
-  const double q = fma(t.P2, (double)J, t.P1);
-  return fma(q, (double)J, t.Y0);
+__device__ __forceinline__ float gb_rev(const GbTile& t, unsigned int F) {
+  float y = (float)(int)F;
+  if (J > 0) y = __builtin_fmaf((float)(J * J), t.c2, y);
+  return y * 0x1p-32f;
 }
 
 // ---------------------------------------------------------------- tile bodies
+// Pulse forward, two samples per step so that each exp has independent work
+// behind it before its result is consumed.
 template <int S, int J = 0>
 __device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S]) {
-  if constexpr (J < S) {
-    const float dj = base + (float)(64 * J);
-    const float z = __builtin_fmaf(dj, c.a, -c.fa);
-    const float e = __builtin_amdgcn_exp2f(-(z * z));
-    r[J] = __builtin_fmaf(-c.A, e, r[J]);
-    pulse_fwd_j<S, J + 1>(c, base, r);
+  if constexpr (J + 1 < S) {
+    const float d0 = base + (float)(64 * J);
+    const float d1 = base + (float)(64 * (J + 1));
+    const float z0 = __builtin_fmaf(d0, c.a, -c.fa);
+    const float z1 = __builtin_fmaf(d1, c.a, -c.fa);
+    const float e0 = __builtin_amdgcn_exp2f(-(z0 * z0));
+    const float e1 = __builtin_amdgcn_exp2f(-(z1 * z1));
+    r[J] = __builtin_fmaf(-c.A, e0, r[J]);
+    r[J + 1] = __builtin_fmaf(-c.A, e1, r[J + 1]);
+    pulse_fwd_j<S, J + 2>(c, base, r);
+  } else if constexpr (J < S) {
+    const float d0 = base + (float)(64 * J);
+    const float z0 = __builtin_fmaf(d0, c.a, -c.fa);
+    r[J] = __builtin_fmaf(-c.A, __builtin_amdgcn_exp2f(-(z0 * z0)), r[J]);
   }
 }
 
@@ -199,19 +219,24 @@ __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const f
 }
 
 template <int S, int J = 0>
-__device__ __forceinline__ void gb_fwd_j(const GbTile& t, float A, float (&r)[S]) {
-  if constexpr (J < S) {
-    const float s = __builtin_amdgcn_sinf(rev_of(gb_y<J>(t)));
-    r[J] = __builtin_fmaf(-A, s, r[J]);
-    gb_fwd_j<S, J + 1>(t, A, r);
+__device__ __forceinline__ void gb_fwd_j(const GbTile& t, unsigned int F, float A, float (&r)[S]) {
+  if constexpr (J + 1 < S) {
+    const unsigned int F1 = F + t.D;
+    const float s0 = __builtin_amdgcn_sinf(gb_rev<J>(t, F));
+    const float s1 = __builtin_amdgcn_sinf(gb_rev<J + 1>(t, F1));
+    r[J] = __builtin_fmaf(-A, s0, r[J]);
+    r[J + 1] = __builtin_fmaf(-A, s1, r[J + 1]);
+    gb_fwd_j<S, J + 2>(t, F1 + t.D, A, r);
+  } else if constexpr (J < S) {
+    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(gb_rev<J>(t, F)), r[J]);
   }
 }
 
 template <int S, int J = 0>
-__device__ __forceinline__ void gb_adj_j(const GbTile& t, const float (&r)[S], float& as,
-                                         float& c0, float& c1, float& c2) {
+__device__ __forceinline__ void gb_adj_j(const GbTile& t, unsigned int F, const float (&r)[S],
+                                         float& as, float& c0, float& c1, float& c2) {
   if constexpr (J < S) {
-    const float ph = rev_of(gb_y<J>(t));
+    const float ph = gb_rev<J>(t, F);
     const float s = __builtin_amdgcn_sinf(ph);
     const float c = __builtin_amdgcn_cosf(ph);
     as = __builtin_fmaf(r[J], s, as);
@@ -219,7 +244,26 @@ __device__ __forceinline__ void gb_adj_j(const GbTile& t, const float (&r)[S], f
     c0 += rc;
     c1 = __builtin_fmaf(rc, (float)J, c1);
     c2 = __builtin_fmaf(rc, (float)(J * J), c2);
-    gb_adj_j<S, J + 1>(t, r, as, c0, c1, c2);
+    gb_adj_j<S, J + 1>(t, F + t.D, r, as, c0, c1, c2);
+  }
+}
+
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_sub2_j(const GbTile& t, unsigned int F, float A, float (&r1)[S],
+                                          float (&r2)[S]) {
+  if constexpr (J < S) {
+    const float s = __builtin_amdgcn_sinf(gb_rev<J>(t, F));
+    r1[J] = __builtin_fmaf(-A, s, r1[J]);
+    r2[J] = __builtin_fmaf(-A, s, r2[J]);
+    gb_sub2_j<S, J + 1>(t, F + t.D, A, r1, r2);
+  }
+}
+
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_val_j(const GbTile& t, unsigned int F, float A, float (&h)[S]) {
+  if constexpr (J < S) {
+    h[J] = A * __builtin_amdgcn_sinf(gb_rev<J>(t, F));
+    gb_val_j<S, J + 1>(t, F + t.D, A, h);
   }
 }
 
@@ -235,7 +279,7 @@ struct Model<SMCX_PULSE> {
   }
   template <int S>
   __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
-    const float sf0 = (float)(tile + lane);
+    const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
       pulse_fwd_j<S>(c, sf0 - c.nf, r);
@@ -244,7 +288,7 @@ struct Model<SMCX_PULSE> {
   template <int S>
   __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
                                  const float (&r)[S]) {
-    const float sf0 = (float)(tile + lane);
+    const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
@@ -262,7 +306,7 @@ struct Model<SMCX_PULSE> {
   // Template values of one component on the tile (for birth/death).
   template <int S>
   __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
-    const float base = (float)(tile + lane) - c.nf;
+    const float base = (float)(int)(tile + lane) - c.nf;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
       const float dj = base + (float)(64 * j);
@@ -272,7 +316,7 @@ struct Model<SMCX_PULSE> {
   }
   template <int S>
   __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
-    const float base = (float)(tile + lane) - c.nf;
+    const float base = (float)(int)(tile + lane) - c.nf;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
       const float dj = base + (float)(64 * j);
@@ -307,19 +351,19 @@ struct Model<SMCX_GBSINE> {
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
       const GbTile t = gb_tile(c, u);
-      gb_fwd_j<S>(t, c.A, r);
+      gb_fwd_j<S>(t, t.F0, c.A, r);
     }
   }
   template <int S>
   __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
                                  const float (&r)[S]) {
     const double u = (double)(tile + lane);
-    const float uf = (float)(tile + lane);
+    const float uf = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
       const GbTile t = gb_tile(c, u);
       float as = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-      gb_adj_j<S>(t, r, as, c0, c1, c2);
+      gb_adj_j<S>(t, t.F0, r, as, c0, c1, c2);
       // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
       const float b1 = __builtin_fmaf(uf, c0, 64.f * c1);
       const float b2 = __builtin_fmaf(uf * uf, c0, __builtin_fmaf(128.f * uf, c1, 4096.f * c2));
@@ -338,26 +382,12 @@ struct Model<SMCX_GBSINE> {
   template <int S>
   __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
     const GbTile t = gb_tile(c, (double)(tile + lane));
-    float z[S];
-#pragma unroll
-    for (int j = 0; j < S; ++j) z[j] = 0.f;
-    gb_fwd_j<S>(t, -c.A, z);  // z = 0 + A sin  (fma(-(-A), s, 0))
-#pragma unroll
-    for (int j = 0; j < S; ++j) h[j] = z[j];
+    gb_val_j<S>(t, t.F0, c.A, h);
   }
   template <int S>
   __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
     const GbTile t = gb_tile(c, (double)(tile + lane));
-    gb_sub2_j<S>(t, c.A, r1, r2);
-  }
-  template <int S, int J = 0>
-  __device__ static void gb_sub2_j(const GbTile& t, float A, float (&r1)[S], float (&r2)[S]) {
-    if constexpr (J < S) {
-      const float s = __builtin_amdgcn_sinf(rev_of(gb_y<J>(t)));
-      r1[J] = __builtin_fmaf(-A, s, r1[J]);
-      r2[J] = __builtin_fmaf(-A, s, r2[J]);
-      gb_sub2_j<S, J + 1>(t, A, r1, r2);
-    }
+    gb_sub2_j<S>(t, t.F0, c.A, r1, r2);
   }
   // sums: S_sin = sum r sin, C0 = sum r cos, C1 = sum r cos s, C2 = sum r cos s^2.
   __device__ static void scale(const double* th, const double* sums, double bs, const PopArgs& a,
@@ -379,6 +409,96 @@ __host__ __device__ inline size_t const_bytes(int model) {
 __device__ __forceinline__ size_t lds_wave_bytes(int model, int32_t k_max, bool grad) {
   const size_t per = const_bytes(model) + (grad ? (size_t)n_params(model) * 8 : 0);
   return ((size_t)(k_max + 1) * per + 15) & ~(size_t)15;
+}
+
+// ---------------------------------------------------------------- work items
+struct Item {
+  int i;       // particle
+  int c;       // chunk
+  int64_t m0;  // first row
+  int K;       // components
+};
+
+// Map a wave's item index to (particle, chunk). In sorted mode the ordering
+// pass has already validated the particles and settled K = 0 ones. In
+// particle order the wave validates its own particle: its rows must lie in
+// [0, M] and K in [0, k_max] (and a death index in [-1, K)); an invalid
+// particle gets NaN outputs and raises the device flag, a particle without
+// components gets the precomputed K = 0 value (unless `with_k0`).
+// Returns false when the wave has nothing more to do.
+__device__ __forceinline__ bool decode_item(const PopArgs& a, int64_t item, int lane, int P,
+                                            bool with_k0, Item& it) {
+  if (a.order) {
+    const int64_t n_items = (int64_t)(*a.n_active) * a.nch;
+    if (item >= n_items) return false;
+    const int64_t rank = item / a.nch;
+    it.c = (int)(item - rank * a.nch);
+    it.i = a.order[rank];
+    it.m0 = a.offsets[it.i];
+    it.K = (int)(a.offsets[it.i + 1] - it.m0);
+    return true;
+  }
+  if (item >= a.N * (int64_t)a.nch) return false;
+  const int64_t i = item / a.nch;
+  it.c = (int)(item - i * a.nch);
+  it.i = (int)i;
+  if (item == 0 && lane == 0 && (a.offsets[0] != 0 || a.offsets[a.N] != a.M))
+    atomicOr(a.flag, a.offsets[0] != 0 ? kFlagOffsets : kFlagMMax);
+  const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+  const bool rows_ok = o0 >= 0 && o1 >= o0 && o1 <= a.M;
+  int bad = rows_ok ? 0 : kFlagOffsets;
+  if (rows_ok && o1 - o0 > a.k_max) bad |= kFlagKMax;
+  if (a.death_idx) {
+    const int32_t j = a.death_idx[i];
+    if (j < -1 || (int64_t)j >= o1 - o0) bad |= kFlagDeath;
+  }
+  if (bad) {
+    if (it.c == 0) {
+      const double nan = __builtin_nan("");
+      if (lane == 0) {
+        atomicOr(a.flag, bad);
+        if (a.logl) a.logl[i] = nan;
+        if (a.dlogl_birth) a.dlogl_birth[i] = nan;
+        if (a.dlogl_death) a.dlogl_death[i] = nan;
+      }
+      if (a.grad && rows_ok)
+        for (int64_t m = o0 + lane; m < o1; m += 64)
+          for (int p = 0; p < P; ++p) a.grad[m * P + p] = nan;
+    }
+    return false;
+  }
+  it.m0 = o0;
+  it.K = (int)(o1 - o0);
+  if (it.K == 0 && !with_k0) {
+    if (it.c == 0 && lane == 0 && a.logl) a.logl[i] = (a.beta ? a.beta[i] : 1.0) * a.k0;
+    return false;
+  }
+  return true;
+}
+
+// Whether the combine pass has work for particle i (natural order): valid
+// rows and at least one component (or any valid particle when `with_k0`).
+__device__ __forceinline__ bool combine_item(const PopArgs& a, int64_t rank, bool with_k0,
+                                             Item& it) {
+  if (a.order) {
+    if (rank >= *a.n_active) return false;
+    it.i = a.order[rank];
+  } else {
+    if (rank >= a.N) return false;
+    it.i = (int)rank;
+  }
+  const int64_t o0 = a.offsets[it.i], o1 = a.offsets[it.i + 1];
+  if (!a.order) {
+    if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) return false;
+    if (a.death_idx) {
+      const int32_t j = a.death_idx[it.i];
+      if (j < -1 || (int64_t)j >= o1 - o0) return false;
+    }
+  }
+  it.m0 = o0;
+  it.K = (int)(o1 - o0);
+  it.c = 0;
+  return with_k0 || it.K > 0;
 }
 
 // ---------------------------------------------------------------- prep
@@ -452,8 +572,18 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a) {
 // ---------------------------------------------------------------- population kernel
 // GRAD = false: logL only (also the data-assimilation segment pass).
 // GRAD = true : fused forward + adjoint.
+// Occupancy target per tile size: the register file holds 512 VGPRs per lane
+// per SIMD, so 8 waves per SIMD leave 64 VGPRs per wave; the residual tile
+// alone needs S of them.
 template <int MODEL, int S, bool GRAD>
-__global__ __launch_bounds__(256) void pop_kernel(PopArgs a) {
+constexpr int pop_waves_per_simd() {
+  if (S <= 16) return 8;
+  if (S == 32) return (MODEL == SMCX_GBSINE && GRAD) ? 7 : 8;
+  return (MODEL == SMCX_GBSINE && GRAD) ? 4 : 5;
+}
+
+template <int MODEL, int S, bool GRAD>
+__global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void pop_kernel(PopArgs a) {
   using M = Model<MODEL>;
   using C = typename M::C;
   constexpr int P = M::P;
@@ -462,13 +592,12 @@ __global__ __launch_bounds__(256) void pop_kernel(PopArgs a) {
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wpb = blockDim.x >> 6;
   const int64_t item = (int64_t)blockIdx.x * wpb + wid;
-  const int64_t n_items = (int64_t)(*a.n_active) * a.nch;
-  if (item >= n_items) return;
-  const int64_t rank = item / a.nch;
-  const int c = (int)(item - rank * a.nch);
-  const int i = a.order[rank];
-  const int64_t m0 = a.offsets[i];
-  const int K = (int)(a.offsets[i + 1] - m0);
+  Item it;
+  if (!decode_item(a, item, lane, P, false, it)) return;
+  const int c = it.c;
+  const int i = it.i;
+  const int64_t m0 = it.m0;
+  const int K = it.K;
 
   unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
   C* cst = reinterpret_cast<C*>(base);
@@ -485,16 +614,18 @@ __global__ __launch_bounds__(256) void pop_kernel(PopArgs a) {
   double ss = 0.0;
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float r[S];
+    // d32 is zero-padded by a full 4096-sample tile past T: no load guard
+    const float* dp = a.d32 + tile + lane;
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int64_t s = tile + 64 * j + lane;
-      r[j] = s < ce ? a.d32[s] : 0.f;
-    }
+    for (int j = 0; j < S; ++j) r[j] = dp[64 * j];
     M::template forward<S>(cst, K, tile, lane, r);
+    if (tile + 64 * S > ce) {  // ragged tile: samples past the chunk contribute nothing
+      const int nv = (int)(ce - tile) - lane;  // lane's samples j with 64 j < nv are inside
+#pragma unroll
+      for (int j = 0; j < S; ++j) r[j] = 64 * j < nv ? r[j] : 0.f;
+    }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-      const int64_t s = tile + 64 * j + lane;
-      r[j] = s < ce ? r[j] : 0.f;
       const double rd = (double)r[j];
       ss = fma(rd, rd, ss);
     }
@@ -532,10 +663,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + wid;
-  if (rank >= *a.n_active) return;
-  const int i = a.order[rank];
-  const int64_t m0 = a.offsets[i];
-  const int K = (int)(a.offsets[i + 1] - m0);
+  Item it;
+  if (!combine_item(a, rank, false, it)) return;
+  const int i = it.i;
+  const int64_t m0 = it.m0;
+  const int K = it.K;
   const double b = a.beta ? a.beta[i] : 1.0;
   if (lane == 0 && a.logl) {
     double ss = 0.0;
@@ -563,7 +695,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
 // in index order, the templates of the death candidate j and of the birth
 // candidate, and four FP64 inner products per lane.
 template <int MODEL, int S>
-__global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
+__global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a) {
   using M = Model<MODEL>;
   using C = typename M::C;
   constexpr int P = M::P;
@@ -572,15 +704,18 @@ __global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wpb = blockDim.x >> 6;
   const int64_t item = (int64_t)blockIdx.x * wpb + wid;
-  const int64_t n_items = (int64_t)(*a.n_active) * a.nch;
-  if (item >= n_items) return;
-  const int64_t rank = item / a.nch;
-  const int c = (int)(item - rank * a.nch);
-  const int i = a.order[rank];
-  const int64_t m0 = a.offsets[i];
-  const int K = (int)(a.offsets[i + 1] - m0);
+  Item it;
+  if (!decode_item(a, item, lane, P, true, it)) return;
+  const int c = it.c;
+  const int i = it.i;
+  const int64_t m0 = it.m0;
+  const int K = it.K;
   const int j_death = a.death_idx ? a.death_idx[i] : -1;
   const bool birth = a.theta_birth != nullptr;
+  if (!birth && j_death < 0) {  // nothing to evaluate: no birth, no death
+    if (c == 0 && lane == 0) a.dlogl_death[i] = 0.0;
+    return;
+  }
 
   C* cst = reinterpret_cast<C*>(lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, false));
   for (int k = lane; k < K; k += 64) cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
@@ -592,10 +727,10 @@ __global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
   double xb = 0.0, yb = 0.0, xd = 0.0, yd = 0.0;
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float rf[S], rn[S], hj[S];
+    const float* dp = a.d32 + tile + lane;
 #pragma unroll
     for (int jj = 0; jj < S; ++jj) {
-      const int64_t s = tile + 64 * jj + lane;
-      rf[jj] = s < ce ? a.d32[s] : 0.f;
+      rf[jj] = dp[64 * jj];
       rn[jj] = rf[jj];
       hj[jj] = 0.f;
     }
@@ -619,10 +754,10 @@ __global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
 #pragma unroll
       for (int jj = 0; jj < S; ++jj) hn[jj] = 0.f;
     }
+    const int nv = (int)min(ce - tile, (int64_t)(64 * S)) - lane;
 #pragma unroll
     for (int jj = 0; jj < S; ++jj) {
-      const int64_t s = tile + 64 * jj + lane;
-      const bool ok = s < ce;
+      const bool ok = 64 * jj < nv;
       const double r1 = ok ? (double)rf[jj] : 0.0;
       const double r2 = ok ? (double)rn[jj] : 0.0;
       const double h1 = ok ? (double)hn[jj] : 0.0;
@@ -653,8 +788,10 @@ __global__ __launch_bounds__(256) void delta_kernel(PopArgs a) {
 
 __global__ __launch_bounds__(256) void delta_finalize_kernel(PopArgs a) {
   const int64_t rank = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rank >= *a.n_active) return;
-  const int i = a.order[rank];
+  Item it;
+  if (!combine_item(a, rank, true, it)) return;
+  const int i = it.i;
+  if (!a.theta_birth && (!a.death_idx || a.death_idx[i] < 0)) return;  // settled by the main pass
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c = 0; c < a.nch; ++c) {
     const double* src = a.part + ((size_t)c * a.N + i) * 4;
@@ -796,7 +933,6 @@ hipError_t launch_delta_model(const Tiling& t, const PopArgs& a, hipStream_t st)
   switch (t.S) {
     case 8: hipLaunchKernelGGL((delta_kernel<MODEL, 8>), grid, block, lds, st, a); break;
     case 16: hipLaunchKernelGGL((delta_kernel<MODEL, 16>), grid, block, lds, st, a); break;
-    case 32: hipLaunchKernelGGL((delta_kernel<MODEL, 32>), grid, block, lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libsmcx.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "smcx.h")
 
 SMCX_OK, SMCX_EINVAL, SMCX_ENOMEM, SMCX_EDEVICE, SMCX_ECAPTURE = 0, -1, -2, -3, -4
+KIND_LOGL, KIND_GRAD, KIND_DELTA = 0, 1, 2
 PULSE, GBSINE = 0, 1
 N_PARAMS = {PULSE: 3, GBSINE: 4}
 
@@ -60,6 +61,15 @@ def load_library():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.smcx_set_tiling.argtypes = [P, I32, I32, I64, I32]
+    lib.smcx_set_tiling.restype = ctypes.c_int
+    lib.smcx_get_tiling.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I64),
+                                    ctypes.POINTER(I32)]
+    lib.smcx_get_tiling.restype = ctypes.c_int
+    lib.smcx_profile_begin.argtypes = [P, I32]
+    lib.smcx_profile_begin.restype = ctypes.c_int
+    lib.smcx_profile_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.smcx_profile_end.restype = ctypes.c_int
     lib.smcx_last_error.argtypes = []
     lib.smcx_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -135,6 +145,26 @@ class Problem:
 
     def device_status(self, stream=None) -> None:
         _check(load_library().smcx_device_status(self.handle, _stream(stream)))
+
+    def set_tiling(self, kind: int, S: int, chunk_len: int, sorted_: int = 0) -> None:
+        _check(load_library().smcx_set_tiling(self.handle, int(kind), int(S), int(chunk_len),
+                                              int(sorted_)))
+
+    def get_tiling(self, kind: int):
+        """(S, chunk_len, sorted) of one call kind."""
+        S, cl, so = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load_library().smcx_get_tiling(self.handle, int(kind), ctypes.byref(S),
+                                              ctypes.byref(cl), ctypes.byref(so)))
+        return S.value, cl.value, so.value
+
+    def profile_begin(self, max_launches: int = 4096) -> None:
+        _check(load_library().smcx_profile_begin(self.handle, int(max_launches)))
+
+    def profile_end(self):
+        """(total kernel milliseconds, number of bracketed calls) since profile_begin."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(load_library().smcx_profile_end(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
 
 def _pop(prob: Problem, offsets, theta, beta):

@@ -368,3 +368,58 @@ def test_full_size_reweight_sampled(lib, orc):
     e = np.exp(lw_ref - m)
     assert sc.cpu().numpy()[0] == pytest.approx(e.sum() ** 2 / (e * e).sum(), rel=1e-10)
     assert np.allclose(wn.cpu().numpy(), e / e.sum(), rtol=1e-10, atol=0)
+
+
+# ---------------------------------------------------------------- tilings
+@pytest.mark.parametrize("cfg,ov", [("pulse_mutate", dict(N=150, T=5000)),
+                                    ("gb_grad", dict(N=60, T=9000, k_hi=12, rj=True))],
+                         ids=["pulse", "gb"])
+def test_every_tiling_is_parity_green_and_order_free(lib, orc, cfg, ov):
+    w = wl.make_config(cfg, **ov)
+    say("tilings", cfg, ov)
+    s = Setup(lib, w)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    rb, rd = orc.delta_logl_birth_death(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta,
+                                        w.beta, tb, di)
+    sb = pm.delta_scale(w.model, w, list(tb), w.beta, w.sigma, rb)
+    rows = [w.theta[w.offsets[i] + di[i]] if di[i] >= 0 else None for i in range(w.N)]
+    sd = pm.delta_scale(w.model, w, rows, w.beta, w.sigma, rd)
+    tested = 0
+    for kind, Ss in ((lib.KIND_GRAD, (8, 16, 32, 64)), (lib.KIND_LOGL, (8, 16, 32, 64)),
+                     (lib.KIND_DELTA, (8, 16))):
+        for S in Ss:
+            tile = 64 * S
+            for chunk in (tile, 3 * tile, ((w.T + tile - 1) // tile) * tile):
+                outs = []
+                for so in (0, 1):
+                    try:
+                        s.prob.set_tiling(kind, S, chunk, so)
+                    except lib.SmcxError:
+                        continue  # more chunks than the workspace holds
+                    say("  kind", kind, "S", S, "chunk", chunk, "sorted", so)
+                    if kind == lib.KIND_GRAD:
+                        l, g = run_grad(lib, s)
+                        pm.assert_logl(l, ref_l)
+                        pm.assert_grad(w.model, w.offsets, w.theta, g, ref_g, w.T, w.dt)
+                        outs.append((l, g))
+                    elif kind == lib.KIND_LOGL:
+                        l = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+                        torch.cuda.synchronize()
+                        l = l.cpu().numpy()
+                        pm.assert_logl(l, ref_l)
+                        outs.append((l,))
+                    else:
+                        db, dd = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta,
+                                                            pm.to_dev(tb), pm.to_dev(di))
+                        torch.cuda.synchronize()
+                        db, dd = db.cpu().numpy(), dd.cpu().numpy()
+                        assert np.all(np.abs(db - rb) <= 1e-6 * sb)
+                        assert np.all(np.abs(dd - rd) <= 1e-6 * sd)
+                        outs.append((db, dd))
+                    s.prob.device_status()
+                    tested += 1
+                if len(outs) == 2:
+                    for x, y in zip(*outs):
+                        assert np.array_equal(x, y), "sorted and index order must agree bitwise"
+    assert tested >= 20
