@@ -78,6 +78,10 @@ def main():
     logl = torch.empty(w.N, dtype=torch.float64, device=dev)
     grad = torch.empty_like(th)
 
+    tuned = prob.autotune(smcx.KIND_GRAD, off, th, beta, reps=5)
+    log(f"[bench] autotuned tiling S={tuned[0]} chunk={tuned[1]} sorted={tuned[2]} "
+        f"({tuned[3]:.4f} ms/call)")
+
     def step():
         smcx.logl_grad_batch(prob, off, th, beta, logl=logl, grad=grad)
 
@@ -187,7 +191,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "T": w.T, "N": w.N, "M": w.M,
                    "K": f"U{{0..{w.k_max}}}", "beta": "U[0,1]" if w.name == "pulse_batch" else "1",
-                   "precision": "FP32 synthesis/residual, FP64 phase and accumulation"},
+                   "precision": "FP32 synthesis/residual, FP64 phase and accumulation",
+                   "tiling": {"S": tuned[0], "chunk_len": tuned[1], "sorted": tuned[2]}},
         "plain_gpu": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "accuracy": accuracy,

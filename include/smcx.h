@@ -221,6 +221,21 @@ int smcx_set_tiling(smcx_problem* prob, int32_t kind, int32_t S, int64_t chunk_l
 int smcx_get_tiling(smcx_problem* prob, int32_t kind, int32_t* S, int64_t* chunk_len,
                     int32_t* sorted);
 
+/* Autotuner: for call kind `kind`, time every supported tiling (S, chunk
+ * length, ordering) on the given population with HIP events (one warm-up
+ * and `reps` timed calls each), apply the fastest to the handle and report
+ * it. If `cache_path` is not NULL it names a plain-text cache: a matching
+ * entry for (device architecture, model, T, kind, k_max) is applied without
+ * timing, and a new result is appended. The population arguments are those
+ * of the call kind (for SMCX_KIND_DELTA the population's own rows serve as
+ * birth candidates). This is a set-up call: it allocates temporary device
+ * buffers, synchronises `hip_stream`, and returns SMCX_ECAPTURE during
+ * stream capture. Needs N >= 1 and M >= 1. */
+int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* offsets, int64_t M,
+                  const double* theta, const double* beta, int32_t reps, const char* cache_path,
+                  void* hip_stream, int32_t* out_S, int64_t* out_chunk_len, int32_t* out_sorted,
+                  double* out_ms);
+
 /* Measurement hooks. Between smcx_profile_begin and smcx_profile_end every
  * compute call on the handle brackets its batched kernel launches (the
  * population kernel and, for split sample ranges, its combine pass; not the

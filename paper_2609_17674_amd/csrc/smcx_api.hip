@@ -11,6 +11,7 @@
 
 #include "../../include/smcx.h"
 #include "smcx_internal.h"
+#include "smcx_problem.h"
 
 using smcx::Tiling;
 
@@ -28,6 +29,22 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace smcx {
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+}  // namespace smcx
+
+namespace {
+
 int hip_fail(hipError_t e, const char* what) {
   return fail(SMCX_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
@@ -40,7 +57,6 @@ bool capturing(hipStream_t st) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-enum Kind { kFwd = 0, kGrad = 1, kDelta = 2, kNumKinds = 3 };
 
 // Default tiling per (model, kind, T). It depends only on the model and the
 // length of the sample axis, never on N, so a particle's arithmetic (and
@@ -75,32 +91,6 @@ Tiling with_range(Tiling t, int64_t len) {
 
 }  // namespace
 
-struct smcx_problem {
-  int model = 0;
-  int P = 0;
-  int64_t T = 0;
-  double t_start = 0, dt = 0, sigma = 0, inv_sigma2 = 0;
-  int32_t k_max = 0;
-  int64_t n_max = 0, m_max = 0;
-  int device = 0;
-  float* d32 = nullptr;
-  double* d64 = nullptr;
-  std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
-  Tiling tiling[kNumKinds];
-  int max_nch = 0;       // capacity of part (chunks per particle)
-  int max_nch_grad = 0;  // capacity of part_g
-  int32_t* order = nullptr;
-  int32_t* n_active = nullptr;
-  int* flag = nullptr;
-  double* part = nullptr;   // [max_nch][n_max][4]
-  double* part_g = nullptr; // [nch_grad][m_max][P]
-  double* rbuf = nullptr;   // plain form residual [T]
-  double* bpart = nullptr;  // plain form block partials
-  // measurement hooks
-  bool prof_on = false;
-  int prof_n = 0;
-  std::vector<hipEvent_t> prof_ev;  // [2 * capacity]
-};
 
 namespace {
 

@@ -1,0 +1,45 @@
+// Definition of the problem handle, shared by the ABI and autotuner units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "smcx_internal.h"
+
+using smcx::Tiling;
+
+enum Kind { kFwd = 0, kGrad = 1, kDelta = 2, kNumKinds = 3 };
+
+struct smcx_problem {
+  int model = 0;
+  int P = 0;
+  int64_t T = 0;
+  double t_start = 0, dt = 0, sigma = 0, inv_sigma2 = 0;
+  int32_t k_max = 0;
+  int64_t n_max = 0, m_max = 0;
+  int device = 0;
+  float* d32 = nullptr;
+  double* d64 = nullptr;
+  std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
+  Tiling tiling[kNumKinds];
+  int max_nch = 0;       // capacity of part (chunks per particle)
+  int max_nch_grad = 0;  // capacity of part_g
+  int32_t* order = nullptr;
+  int32_t* n_active = nullptr;
+  int* flag = nullptr;
+  double* part = nullptr;   // [max_nch][n_max][4]
+  double* part_g = nullptr; // [nch_grad][m_max][P]
+  double* rbuf = nullptr;   // plain form residual [T]
+  double* bpart = nullptr;  // plain form block partials
+  // measurement hooks
+  bool prof_on = false;
+  int prof_n = 0;
+  std::vector<hipEvent_t> prof_ev;  // [2 * capacity]
+};
+
+namespace smcx {
+// Set the thread's last-error message and return `code`.
+int set_error(int code, const char* fmt, ...);
+}  // namespace smcx

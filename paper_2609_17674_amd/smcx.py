@@ -66,6 +66,10 @@ def load_library():
     lib.smcx_get_tiling.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I64),
                                     ctypes.POINTER(I32)]
     lib.smcx_get_tiling.restype = ctypes.c_int
+    lib.smcx_autotune.argtypes = [P, I32, I64, P, I64, P, P, I32, ctypes.c_char_p, P,
+                                  ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32),
+                                  ctypes.POINTER(D)]
+    lib.smcx_autotune.restype = ctypes.c_int
     lib.smcx_profile_begin.argtypes = [P, I32]
     lib.smcx_profile_begin.restype = ctypes.c_int
     lib.smcx_profile_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -156,6 +160,20 @@ class Problem:
         _check(load_library().smcx_get_tiling(self.handle, int(kind), ctypes.byref(S),
                                               ctypes.byref(cl), ctypes.byref(so)))
         return S.value, cl.value, so.value
+
+    def autotune(self, kind: int, offsets, theta, beta=None, reps: int = 5, cache_path=None,
+                 stream=None):
+        """Time every tiling of call kind `kind` on this population and keep the fastest.
+
+        Returns (S, chunk_len, sorted, ms per call)."""
+        offsets, N, theta, beta = _pop(self, offsets, theta, beta)
+        S, cl, so, ms = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        _check(load_library().smcx_autotune(self.handle, int(kind), N, _ptr(offsets), theta.shape[0],
+                                            _ptr(theta), _ptr(beta), int(reps), cp,
+                                            _stream(stream), ctypes.byref(S), ctypes.byref(cl),
+                                            ctypes.byref(so), ctypes.byref(ms)))
+        return S.value, cl.value, so.value, ms.value
 
     def profile_begin(self, max_launches: int = 4096) -> None:
         _check(load_library().smcx_profile_begin(self.handle, int(max_launches)))

@@ -423,3 +423,24 @@ def test_every_tiling_is_parity_green_and_order_free(lib, orc, cfg, ov):
                     for x, y in zip(*outs):
                         assert np.array_equal(x, y), "sorted and index order must agree bitwise"
     assert tested >= 20
+
+
+def test_autotuner_picks_a_valid_tiling_and_uses_its_cache(lib, orc, tmp_path):
+    w = wl.make_config("pulse_mutate", N=256, T=4096)
+    say("autotune")
+    s = Setup(lib, w)
+    cache = str(tmp_path / "tiling.txt")
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    for kind in (lib.KIND_GRAD, lib.KIND_LOGL, lib.KIND_DELTA):
+        S, chunk, so, ms = s.prob.autotune(kind, s.off, s.th, s.beta, reps=2, cache_path=cache)
+        assert (S, chunk, so) == s.prob.get_tiling(kind) and ms > 0
+    l, g = run_grad(lib, s)
+    pm.assert_logl(l, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, g, ref_g, w.T, w.dt)
+    lines = open(cache).read().strip().split("\n")
+    assert len(lines) == 3 and all(x.startswith("gfx950 0 4096") for x in lines)
+    # a second handle picks the cached choice without timing
+    s2 = Setup(lib, w)
+    got = s2.prob.autotune(lib.KIND_GRAD, s.off, s.th, s.beta, reps=2, cache_path=cache)
+    assert got[:3] == s.prob.get_tiling(lib.KIND_GRAD)
+    assert len(open(cache).read().strip().split("\n")) == 3
