@@ -199,6 +199,66 @@ int smcx_plain_logl_grad(smcx_problem* prob, int64_t N, const int64_t* offsets_h
                          const double* theta, const double* beta, double* logl, double* grad,
                          void* hip_stream);
 
+/* One leapfrog step of Hamiltonian dynamics (Sec. "No-U-Turn-Sampler":
+ * Hamilton's equations integrated with the symplectic leapfrog scheme) for
+ * every active particle, with an identity mass matrix and the tempered log
+ * target beta * logL (a uniform prior adds nothing inside its box):
+ *   p_half = p + (e/2) g,   q' = q + e p_half,   p' = p_half + (e/2) g'
+ * where e = eps * dir[i], g = beta grad logL(q) is supplied by the caller
+ * (for example from logl_grad_batch or the previous step) and g' is
+ * computed at q' by the fused forward + adjoint pass, whose epilogue applies
+ * the closing half kick.
+ *   dir        [N] int8 +1/-1 (integration direction) or NULL for +1
+ *   active     [N] uint8, or NULL for all; an inactive particle's q, p, g
+ *              are copied to the outputs and its logl_out is not written
+ *   q_in, p_in, g_in     [M][P] FP64 state at the start
+ *   q_out, p_out, g_out  [M][P] FP64 state after the step (must not overlap
+ *              the inputs); logl_out [N] tempered logL at q'
+ * Other arguments as logl_grad_batch. Capture-safe: two kernel launches
+ * (three with the ordering pass), no allocation, no host synchronisation. */
+int smcx_leapfrog(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                  const double* beta, double eps, const int8_t* dir, const uint8_t* active,
+                  const double* q_in, const double* p_in, const double* g_in, double* q_out,
+                  double* p_out, double* g_out, double* logl_out, void* hip_stream);
+
+/* Reserve the device workspace of smcx_nuts_transition for trees of depth
+ * up to max_depth (1..10): about (16 + 2 max_depth) m_max P doubles plus
+ * small per-particle arrays. A set-up call: allocates, may synchronise. */
+int smcx_nuts_reserve(smcx_problem* prob, int32_t max_depth);
+
+/* One No-U-Turn transition (Sec. "No-U-Turn-Sampler") for every particle,
+ * all trajectories built in lockstep on the device (multinomial NUTS,
+ * generalised U-turn criterion on every balanced sub-block and on the whole
+ * trajectory, divergence when the energy rises by more than 1000 or a
+ * position leaves the prior box, tree depth <= max_depth, identity metric).
+ * Each doubling of depth j runs 2^j batched leapfrog steps (smcx_leapfrog's
+ * arithmetic) each followed by a controller pass, and is captured once into
+ * a hipGraph and replayed when use_graph != 0 (the graph is rebuilt when any
+ * pointer or size argument changes). The host synchronises once per
+ * doubling to learn whether any trajectory is still growing.
+ *   beta, eps          tempering and leapfrog step size (eps > 0)
+ *   max_depth          at most the depth reserved with smcx_nuts_reserve
+ *   prior_lo, prior_hi [P] box of the uniform prior, or both NULL
+ *   momentum           [M][P] standard-normal draws (initial momenta)
+ *   dirs               [N][max_depth] int8 +1/-1 doubling directions
+ *   u_leaf             [N][2^max_depth - 1] uniforms in [0,1); leaf n of the
+ *                      doubling at depth j uses column 2^j - 1 + n
+ *   u_tree             [N][max_depth] uniforms for merging subtrees
+ *   q, logl, grad      in: state, tempered logL and gradient at q (for
+ *                      example from logl_grad_batch); out: the new state
+ *   depth_out, steps_out, status_out  [N] int32 or NULL: completed
+ *                      doublings, leapfrog steps, and the reason the
+ *                      trajectory stopped (0 no components, 1 U-turn,
+ *                      2 divergence, 3 maximum depth, -1 invalid rows)
+ * Returns SMCX_ECAPTURE if called during stream capture. */
+int smcx_nuts_transition(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                         const double* beta, double eps, int32_t max_depth,
+                         const double* prior_lo, const double* prior_hi, const double* momentum,
+                         const int8_t* dirs, const double* u_leaf, const double* u_tree,
+                         double* q, double* logl, double* grad, int32_t* depth_out,
+                         int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                         void* hip_stream);
+
 /* Tiling of the sample axis, per call kind: SMCX_KIND_LOGL (logl_batch and
  * the segment pass of reweight_extend), SMCX_KIND_GRAD (logl_grad_batch),
  * SMCX_KIND_DELTA (delta_logl_birth_death). A wave owns one (particle,

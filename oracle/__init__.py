@@ -71,6 +71,8 @@ def _load():
         lib.oracle_delta_logl_birth_death.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, P, P]
         lib.oracle_reweight_extend.argtypes = [I, P, D, D, D, I64, I64, I64, P, P, D, P, P, P, P, P]
         lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
+        lib.oracle_nuts_transition.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P, P, P, P,
+                                               P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -174,3 +176,20 @@ def leapfrog(model, d, t_start, dt, sigma, offsets, q, p, beta, eps, active=None
                                    _p(q), _p(p), _p(beta), eps, _p(act), _p(qo), _p(po), _p(lo),
                                    _p(go)), "leapfrog")
     return qo, po, lo, go
+
+
+def nuts_transition(model, d, t_start, dt, sigma, offsets, beta, eps, max_depth, q, logl, grad,
+                    momentum, dirs, u_leaf, u_tree, prior_lo=None, prior_hi=None):
+    """One NUTS transition per particle; returns (q, logl, grad, depth, steps, status)."""
+    d, offsets, beta = _f64(d), _i64(offsets), _f64(beta)
+    q, logl, grad = (np.array(x, dtype=np.float64, order="C", copy=True) for x in (q, logl, grad))
+    momentum, u_leaf, u_tree = _f64(momentum), _f64(u_leaf), _f64(u_tree)
+    dirs = np.ascontiguousarray(dirs, dtype=np.int8)
+    lo, hi = _f64(prior_lo), _f64(prior_hi)
+    N = offsets.shape[0] - 1
+    depth, steps, status = (np.zeros(N, dtype=np.int32) for _ in range(3))
+    _check(_load().oracle_nuts_transition(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                                          _p(beta), eps, int(max_depth), _p(lo), _p(hi), _p(momentum),
+                                          _p(dirs), _p(u_leaf), _p(u_tree), _p(q), _p(logl), _p(grad),
+                                          _p(depth), _p(steps), _p(status)), "nuts_transition")
+    return q, logl, grad, depth, steps, status

@@ -156,6 +156,27 @@ int oracle_logl(int model, const double* d, int64_t T, double t_start, double dt
   return OR_OK;
 }
 
+/* Tempered log-likelihood and gradient of one particle (K components th). */
+static void particle_logl_grad(int model, const double* d, int64_t T, double t_start, double dt,
+                               double sigma, int64_t K, const double* th, double b, double* logl,
+                               double* g) {
+  int P = oracle_n_params(model);
+  double ss = 0.0;
+  for (int64_t k = 0; k < K * P; ++k) g[k] = 0.0;
+  for (int64_t s = 0; s < T; ++s) {
+    double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+    ss += r * r;
+    double t = t_start + (double)s * dt;
+    for (int64_t k = 0; k < K; ++k) {
+      double dh[4];
+      template_partials(model, th + k * P, t, dh);
+      for (int p = 0; p < P; ++p) g[k * P + p] += r * dh[p];
+    }
+  }
+  for (int64_t k = 0; k < K * P; ++k) g[k] = b * (g[k] / (sigma * sigma));
+  *logl = b * (-0.5 * ss / (sigma * sigma));
+}
+
 /* Tempered log-likelihood and its gradient with respect to every component
  * parameter: grad[m][p] = beta * (1/sigma^2) sum_s r_s dh_m(t_s)/dtheta_p.
  * The gradient is what the NUTS kernel of Sec. "No-U-Turn-Sampler" needs
@@ -368,6 +389,175 @@ int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, doubl
     if (!on) continue;
     for (int64_t m = offsets[i] * P; m < offsets[i + 1] * P; ++m)
       p_out[m] = p_out[m] + 0.5 * eps * grad_out[m];
+  }
+  return OR_OK;
+}
+
+/* One No-U-Turn transition per particle (Sec. "No-U-Turn-Sampler"; the
+ * stopping rule of Hoffman & Gelman, in its multinomial form). Reading used
+ * here, written out step by step:
+ *  - potential U = -beta logL inside the uniform prior box, +inf outside;
+ *    H = U + |p|^2 / 2 (identity metric); the momentum is an input draw;
+ *  - the trajectory grows by doublings j = 0, 1, ..., max_depth - 1 in
+ *    direction dirs[j]; doubling j adds 2^j leapfrog steps (oracle_leapfrog's
+ *    arithmetic) continuing from the trajectory end on that side;
+ *  - leaf n of doubling j replaces the subtree's proposal with probability
+ *    exp(-H_n) / (sum of exp(-H) over the subtree's leaves so far), decided
+ *    by u_leaf[2^j - 1 + n] < that probability;
+ *  - a leaf with H_n - H_0 > 1000 (or outside the box) is a divergence;
+ *  - every block of 2^m consecutive leaves of the subtree (m = 1..j, aligned
+ *    to the subtree start) is tested when it completes: with rho the sum of
+ *    the block's momenta and p_a, p_b its first and last momenta, it has
+ *    turned if rho.p_a <= 0 or rho.p_b <= 0;
+ *  - a divergence or turn inside the subtree discards the subtree and ends
+ *    the transition; otherwise the subtree's proposal replaces the
+ *    trajectory's with probability min(1, W_sub / W_traj) (u_tree[j]), the
+ *    weights and momentum sums are merged, and the whole trajectory is
+ *    tested the same way (end momenta p_left, p_right);
+ *  - the transition ends after max_depth doublings at the latest.
+ * Outputs: the proposal's position, tempered logL and gradient; depth = the
+ * number of completed doublings; steps = leapfrog steps taken; status 0 (no
+ * components), 1 (U-turn), 2 (divergence), 3 (maximum depth). */
+static double dot(const double* a, const double* b, int64_t n) {
+  double s = 0.0;
+  for (int64_t x = 0; x < n; ++x) s += a[x] * b[x];
+  return s;
+}
+static double logaddexp(double a, double b) {
+  double m = a > b ? a : b;
+  if (m == -INFINITY) return -INFINITY;
+  return m + log(exp(a - m) + exp(b - m));
+}
+static int inside_box(const double* q, int64_t n, int P, const double* lo, const double* hi) {
+  if (!lo) return 1;
+  for (int64_t x = 0; x < n; ++x)
+    if (!(q[x] >= lo[x % P] && q[x] <= hi[x % P])) return 0;
+  return 1;
+}
+
+#include <stdlib.h>
+#include <string.h>
+
+int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start, double dt,
+                           double sigma, int64_t N, const int64_t* offsets, const double* beta,
+                           double eps, int max_depth, const double* prior_lo,
+                           const double* prior_hi, const double* momentum, const int8_t* dirs,
+                           const double* u_leaf, const double* u_tree, double* q, double* logl,
+                           double* grad, int32_t* depth_out, int32_t* steps_out,
+                           int32_t* status_out) {
+  if (check_population(model, N, offsets, q) != OR_OK || max_depth < 1 || max_depth > 16)
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+  int64_t nleaf = ((int64_t)1 << max_depth) - 1;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    int64_t n = K * P;
+    double* qi = q + offsets[i] * P;
+    double* gi = grad + offsets[i] * P;
+    double b = beta ? beta[i] : 1.0;
+    int depth = 0, steps = 0, status = 0;
+    if (n == 0) {
+      depth_out[i] = 0; steps_out[i] = 0; status_out[i] = 0;
+      continue;
+    }
+    /* 16 + 2*max_depth state vectors of n doubles */
+    double* buf = (double*)calloc((size_t)(16 + 2 * max_depth) * n, sizeof(double));
+    double *qL = buf, *pL = buf + n, *gL = buf + 2 * n, *qR = buf + 3 * n, *pR = buf + 4 * n,
+           *gR = buf + 5 * n, *qF = buf + 6 * n, *pF = buf + 7 * n, *gF = buf + 8 * n,
+           *qP = buf + 9 * n, *gP = buf + 10 * n, *qS = buf + 11 * n, *gS = buf + 12 * n,
+           *rhoT = buf + 13 * n, *rhoS = buf + 14 * n, *tmp = buf + 15 * n;
+    double* ckP = buf + 16 * n;                 /* [max_depth][n] */
+    double* ckR = buf + (16 + max_depth) * n;  /* [max_depth][n] */
+    const double* p0 = momentum + offsets[i] * P;
+    double l0 = logl[i];
+    double H0 = -l0 + 0.5 * dot(p0, p0, n);
+    for (int64_t x = 0; x < n; ++x) {
+      qL[x] = qR[x] = qP[x] = qi[x];
+      pL[x] = pR[x] = rhoT[x] = p0[x];
+      gL[x] = gR[x] = gP[x] = gi[x];
+    }
+    double lL = l0, lR = l0, lP = l0, lS = l0, lF = l0;
+    double lw_tree = -H0;
+    if (!inside_box(qi, n, P, prior_lo, prior_hi) || !isfinite(H0)) {
+      status = 2;
+    } else {
+      status = 3;
+      for (int j = 0; j < max_depth; ++j) {
+        int v = dirs[i * max_depth + j];
+        double e = eps * (double)v;
+        memcpy(qF, v > 0 ? qR : qL, n * sizeof(double));
+        memcpy(pF, v > 0 ? pR : pL, n * sizeof(double));
+        memcpy(gF, v > 0 ? gR : gL, n * sizeof(double));
+        lF = v > 0 ? lR : lL;
+        double lw_sub = -INFINITY;
+        for (int64_t x = 0; x < n; ++x) rhoS[x] = 0.0;
+        int stop = 0;
+        for (int64_t leaf = 0; leaf < ((int64_t)1 << j); ++leaf) {
+          /* leapfrog step from the frontier */
+          for (int64_t x = 0; x < n; ++x) {
+            pF[x] = pF[x] + 0.5 * e * gF[x];
+            qF[x] = qF[x] + e * pF[x];
+          }
+          particle_logl_grad(model, d, T, t_start, dt, sigma, K, qF, b, &lF, gF);
+          for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * gF[x];
+          steps += 1;
+          double H = inside_box(qF, n, P, prior_lo, prior_hi) ? -lF + 0.5 * dot(pF, pF, n)
+                                                              : INFINITY;
+          if (!(H - H0 <= 1000.0)) { status = 2; stop = 1; break; }
+          double lws = logaddexp(lw_sub, -H);
+          if (u_leaf[i * nleaf + ((int64_t)1 << j) - 1 + leaf] < exp(-H - lws)) {
+            memcpy(qS, qF, n * sizeof(double));
+            memcpy(gS, gF, n * sizeof(double));
+            lS = lF;
+          }
+          lw_sub = lws;
+          for (int64_t x = 0; x < n; ++x) tmp[x] = rhoS[x];
+          for (int64_t x = 0; x < n; ++x) rhoS[x] += pF[x];
+          for (int m = 1; m <= j; ++m) {
+            if (leaf % ((int64_t)1 << m) != 0) break;
+            memcpy(ckP + (m - 1) * n, pF, n * sizeof(double));
+            memcpy(ckR + (m - 1) * n, tmp, n * sizeof(double));
+          }
+          int turn = 0;
+          for (int m = 1; m <= j && !turn; ++m) {
+            if ((leaf + 1) % ((int64_t)1 << m) != 0) break;
+            double dl = 0.0, dr = 0.0;
+            for (int64_t x = 0; x < n; ++x) {
+              double rb = rhoS[x] - ckR[(m - 1) * n + x];
+              dl += rb * ckP[(m - 1) * n + x];
+              dr += rb * pF[x];
+            }
+            turn = dl <= 0.0 || dr <= 0.0;
+          }
+          if (turn) { status = 1; stop = 1; break; }
+        }
+        if (stop) break;
+        if (u_tree[i * max_depth + j] < exp(lw_sub - lw_tree)) {
+          memcpy(qP, qS, n * sizeof(double));
+          memcpy(gP, gS, n * sizeof(double));
+          lP = lS;
+        }
+        lw_tree = logaddexp(lw_tree, lw_sub);
+        for (int64_t x = 0; x < n; ++x) rhoT[x] += rhoS[x];
+        if (v > 0) {
+          memcpy(qR, qF, n * sizeof(double)); memcpy(pR, pF, n * sizeof(double));
+          memcpy(gR, gF, n * sizeof(double)); lR = lF;
+        } else {
+          memcpy(qL, qF, n * sizeof(double)); memcpy(pL, pF, n * sizeof(double));
+          memcpy(gL, gF, n * sizeof(double)); lL = lF;
+        }
+        depth = j + 1;
+        if (dot(rhoT, pL, n) <= 0.0 || dot(rhoT, pR, n) <= 0.0) { status = 1; break; }
+      }
+    }
+    memcpy(qi, qP, n * sizeof(double));
+    memcpy(gi, gP, n * sizeof(double));
+    logl[i] = lP;
+    depth_out[i] = depth;
+    steps_out[i] = steps;
+    status_out[i] = status;
+    free(buf);
   }
   return OR_OK;
 }

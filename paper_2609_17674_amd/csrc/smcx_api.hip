@@ -97,6 +97,15 @@ namespace {
 void free_problem(smcx_problem* p) {
   if (!p) return;
   for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
+  for (hipGraphExec_t g : p->nuts_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (p->nuts_capture) (void)hipStreamDestroy(p->nuts_capture);
+  (void)hipFree(p->nuts_vec);
+  (void)hipFree(p->nuts_state);
+  (void)hipFree(p->nuts_logl);
+  (void)hipFree(p->nuts_active);
+  (void)hipFree(p->nuts_dir);
+  (void)hipFree(p->nuts_count);
   (void)hipFree(p->d32);
   (void)hipFree(p->d64);
   (void)hipFree(p->order);
@@ -479,6 +488,222 @@ int smcx_plain_logl_grad(smcx_problem* p, int64_t N, const int64_t* offsets_host
                                                p->rbuf, p->bpart, logl, grad + m0 * p->P, st);
     if (e != hipSuccess) return hip_fail(e, "plain launch");
   }
+  return SMCX_OK;
+}
+
+int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M, const double* beta,
+                  double eps, const int8_t* dir, const uint8_t* active, const double* q_in,
+                  const double* p_in, const double* g_in, double* q_out, double* p_out,
+                  double* g_out, double* logl_out, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, q_in);
+  if (rc) return rc;
+  if (!std::isfinite(eps)) return fail(SMCX_EINVAL, "eps must be finite");
+  if (N > 0 && !logl_out) return fail(SMCX_EINVAL, "logl_out is NULL");
+  if (M > 0 && (!p_in || !g_in || !q_out || !p_out || !g_out))
+    return fail(SMCX_EINVAL, "a state array is NULL");
+  const size_t bytes = (size_t)M * p->P * sizeof(double);
+  const double* ins[3] = {q_in, p_in, g_in};
+  const double* outs[3] = {q_out, p_out, g_out};
+  for (const double* x : ins)
+    for (const double* y : outs)
+      if (M > 0 && (const char*)x < (const char*)y + bytes && (const char*)y < (const char*)x + bytes)
+        return fail(SMCX_EINVAL, "input and output state arrays overlap");
+  if (N == 0) return SMCX_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_drift(p->model, N, offsets, eps, dir, active, q_in, p_in, g_in, q_out,
+                                    p_out, g_out, st);
+  if (e != hipSuccess) return hip_fail(e, "drift launch");
+  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const Tiling& t = p->tiling[kGrad];
+  if (t.sorted) {
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.logl = logl_out;
+    pa.grad = g_out;
+    e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+  }
+  smcx::PopArgs a = base_args(p, N, offsets, M, q_out, beta, t, 0, p->T, k0);
+  a.logl = logl_out;
+  a.grad = g_out;
+  a.active = active;
+  a.p_half = p_out;
+  a.p_out = p_out;
+  a.eps = eps;
+  a.dir = dir;
+  {
+    ProfScope ps(p, st);
+    e = smcx::launch_fused(p->model, t, a, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "leapfrog gradient launch");
+  return SMCX_OK;
+}
+
+int smcx_nuts_reserve(smcx_problem* p, int32_t max_depth) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (max_depth < 1 || max_depth > smcx::kNutsMaxDepth)
+    return fail(SMCX_EINVAL, "max_depth = %d outside [1, %d]", max_depth, smcx::kNutsMaxDepth);
+  if (p->nuts_depth >= max_depth) return SMCX_OK;
+  if (p->nuts_vec) {  // grow: release the smaller workspace first
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->nuts_vec);
+    p->nuts_vec = nullptr;
+    (void)hipFree(p->nuts_count);
+    p->nuts_count = nullptr;
+  }
+  const size_t stride = (size_t)std::max<int64_t>(p->m_max, 1) * p->P;
+  const size_t nN = (size_t)std::max<int64_t>(p->n_max, 1);
+  hipError_t e = hipMalloc(&p->nuts_vec, stride * smcx::kNutsSlots(max_depth) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&p->nuts_count, (max_depth + 1) * sizeof(int));
+  if (e == hipSuccess && !p->nuts_state) e = hipMalloc(&p->nuts_state, nN * sizeof(smcx::NutsState));
+  if (e == hipSuccess && !p->nuts_logl) e = hipMalloc(&p->nuts_logl, nN * sizeof(double));
+  if (e == hipSuccess && !p->nuts_active) e = hipMalloc(&p->nuts_active, nN);
+  if (e == hipSuccess && !p->nuts_dir) e = hipMalloc(&p->nuts_dir, nN);
+  if (e == hipSuccess && !p->nuts_capture) e = hipStreamCreateWithFlags(&p->nuts_capture, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(SMCX_ENOMEM, "NUTS workspace allocation failed: %s", hipGetErrorString(e));
+  p->nuts_depth = max_depth;
+  for (hipGraphExec_t g : p->nuts_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  p->nuts_graph.assign(max_depth, nullptr);
+  p->nuts_graph_key.assign(max_depth, 0);
+  return SMCX_OK;
+}
+
+namespace {
+uint64_t mix_key(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+}  // namespace
+
+int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                         const double* beta, double eps, int32_t max_depth,
+                         const double* prior_lo, const double* prior_hi, const double* momentum,
+                         const int8_t* dirs, const double* u_leaf, const double* u_tree,
+                         double* q, double* logl, double* grad, int32_t* depth_out,
+                         int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                         void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, q);
+  if (rc) return rc;
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SMCX_EINVAL, "eps must be finite and > 0");
+  if (max_depth < 1 || max_depth > p->nuts_depth)
+    return fail(SMCX_EINVAL, "max_depth = %d exceeds the reserved NUTS depth %d (smcx_nuts_reserve)",
+                max_depth, p->nuts_depth);
+  if ((prior_lo == nullptr) != (prior_hi == nullptr))
+    return fail(SMCX_EINVAL, "prior_lo and prior_hi must both be given or both be NULL");
+  if (N > 0 && (!logl || !dirs || !u_leaf || !u_tree)) return fail(SMCX_EINVAL, "an input array is NULL");
+  if (M > 0 && (!momentum || !grad)) return fail(SMCX_EINVAL, "momentum or grad is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (capturing(st)) return fail(SMCX_ECAPTURE, "smcx_nuts_transition called during stream capture");
+  if (N == 0) return SMCX_OK;
+
+  smcx::NutsArgs na;
+  std::memset(&na, 0, sizeof(na));
+  na.P = p->P;
+  na.D = max_depth;
+  na.N = N;
+  na.M = M;
+  na.offsets = offsets;
+  na.eps = eps;
+  na.prior_lo = prior_lo;
+  na.prior_hi = prior_hi;
+  na.momentum = momentum;
+  na.dirs = dirs;
+  na.u_leaf = u_leaf;
+  na.u_tree = u_tree;
+  na.q = q;
+  na.logl = logl;
+  na.grad = grad;
+  na.depth_out = depth_out;
+  na.steps_out = steps_out;
+  na.status_out = status_out;
+  na.vec = p->nuts_vec;
+  na.stride = std::max<int64_t>(p->m_max, 1) * p->P;
+  na.state = (smcx::NutsState*)p->nuts_state;
+  na.logl_front = p->nuts_logl;
+  na.active = p->nuts_active;
+  na.dir = p->nuts_dir;
+  na.count = p->nuts_count;
+  double* qF = p->nuts_vec + 6 * na.stride;
+  double* pF = p->nuts_vec + 7 * na.stride;
+  double* gF = p->nuts_vec + 8 * na.stride;
+  double* pH = p->nuts_vec + 9 * na.stride;
+
+  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const Tiling& t = p->tiling[kGrad];
+  hipError_t e = hipSuccess;
+  if (t.sorted) {  // one ordering pass serves every leapfrog step of the transition
+    smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.logl = p->nuts_logl;
+    e = smcx::launch_prep(pa, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+  }
+  smcx::PopArgs a = base_args(p, N, offsets, M, qF, beta, t, 0, p->T, k0);
+  a.logl = p->nuts_logl;
+  a.grad = gF;
+  a.active = p->nuts_active;
+  a.p_half = pH;
+  a.p_out = pF;
+  a.eps = eps;
+  a.dir = p->nuts_dir;
+
+  auto doubling = [&](int j, hipStream_t s) -> hipError_t {
+    for (int n = 0; n < (1 << j); ++n) {
+      hipError_t err = smcx::launch_fused(p->model, t, a, s);
+      if (err == hipSuccess) err = smcx::launch_nuts_leaf(na, j, n, s);
+      if (err != hipSuccess) return err;
+    }
+    return smcx::launch_nuts_merge(na, j, s);
+  };
+
+  uint64_t key = 0;
+  for (uint64_t v : {(uint64_t)N, (uint64_t)M, (uint64_t)(uintptr_t)offsets, (uint64_t)(uintptr_t)beta,
+                     (uint64_t)(uintptr_t)prior_lo, (uint64_t)(uintptr_t)prior_hi,
+                     (uint64_t)(uintptr_t)momentum, (uint64_t)(uintptr_t)dirs,
+                     (uint64_t)(uintptr_t)u_leaf, (uint64_t)(uintptr_t)u_tree,
+                     (uint64_t)(uintptr_t)q, (uint64_t)(uintptr_t)logl, (uint64_t)(uintptr_t)grad,
+                     (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth})
+    key = mix_key(key, v);
+  uint64_t eb;
+  std::memcpy(&eb, &eps, sizeof(eb));
+  key = mix_key(key, eb);
+
+  e = smcx::launch_nuts_init(na, st);
+  if (e != hipSuccess) return hip_fail(e, "NUTS init launch");
+  for (int j = 0; j < max_depth; ++j) {
+    if (use_graph) {
+      if (!p->nuts_graph[j] || p->nuts_graph_key[j] != key) {
+        if (p->nuts_graph[j]) (void)hipGraphExecDestroy(p->nuts_graph[j]);
+        p->nuts_graph[j] = nullptr;
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(p->nuts_capture, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t e2 = doubling(j, p->nuts_capture);
+          e = hipStreamEndCapture(p->nuts_capture, &g);
+          if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->nuts_graph[j], g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "NUTS graph capture");
+        p->nuts_graph_key[j] = key;
+      }
+      e = hipGraphLaunch(p->nuts_graph[j], st);
+    } else {
+      e = doubling(j, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "NUTS doubling");
+    if (j + 1 < max_depth) {  // stop as soon as no trajectory is still extending
+      int alive = 0;
+      e = hipMemcpyAsync(&alive, p->nuts_count + (j + 1), sizeof(int), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(e, "NUTS active count");
+      if (alive == 0) break;
+    }
+  }
+  e = smcx::launch_nuts_finalize(na, st);
+  if (e != hipSuccess) return hip_fail(e, "NUTS finalize launch");
   return SMCX_OK;
 }
 

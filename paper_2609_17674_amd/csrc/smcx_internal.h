@@ -60,6 +60,14 @@ struct PopArgs {
   double* grad;            // [M][P] or nullptr
   double* part;            // [nch][N][n_part] chunk partials when nch > 1
   double* part_g;          // [nch][m_max][P] chunk gradient partials when nch > 1
+  // leapfrog mode of the fused pass (p_half != nullptr): theta holds the
+  // drifted positions q'; after the gradient g' the momenta are kicked,
+  // p_out = p_half + (eps_i / 2) g', with eps_i = eps * dir[i]
+  const uint8_t* active;   // [N] or nullptr: particles with active[i] == 0 are skipped
+  const double* p_half;    // [M][P] half-step momenta
+  double* p_out;           // [M][P] full-step momenta (may be p_half itself)
+  double eps;
+  const int8_t* dir;       // [N] +-1 or nullptr (+1)
   // birth / death
   const double* theta_birth;  // [N][P] or nullptr
   const int32_t* death_idx;   // [N] or nullptr
@@ -91,6 +99,53 @@ struct PrepArgs {
   int include_k0;      // 1: K = 0 particles stay in the work list (birth pass)
 };
 
+// Per-particle scalars of a NUTS transition.
+struct NutsState {
+  double H0;         // energy at the start point
+  double lw_tree;    // log of the summed weights exp(-H) of the trajectory
+  double lw_sub;     // same for the subtree being built
+  double logl_prop;  // tempered logL at the trajectory proposal
+  double logl_sub;   // tempered logL at the subtree proposal
+  int depth;         // completed doublings
+  int steps;         // leapfrog steps taken
+  int status;        // 0 no components, 1 U-turn, 2 divergence, 3 maximum depth, 4 running
+  int pad;
+};
+
+struct NutsArgs {
+  int P;
+  int D;                   // maximum tree depth
+  int64_t N, M;
+  const int64_t* offsets;
+  double eps;
+  const double* prior_lo;  // [P] or nullptr
+  const double* prior_hi;  // [P]
+  const double* momentum;  // [M][P] standard normal draws
+  const int8_t* dirs;      // [N][D]
+  const double* u_leaf;    // [N][2^D - 1]
+  const double* u_tree;    // [N][D]
+  double* q;               // [M][P] in/out
+  double* logl;            // [N] in/out (tempered)
+  double* grad;            // [M][P] in/out (tempered)
+  int32_t* depth_out;
+  int32_t* steps_out;
+  int32_t* status_out;
+  double* vec;             // state vectors, slot k at vec + k * stride
+  int64_t stride;
+  NutsState* state;        // [N]
+  double* logl_front;      // [N]
+  uint8_t* active;         // [N]
+  int8_t* dir;             // [N]
+  int* count;              // [D + 1]
+};
+constexpr int kNutsMaxDepth = 10;
+constexpr int kNutsSlots(int D) { return 16 + 2 * D; }
+
+hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st);
+hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st);
+hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st);
+hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st);
+
 // Host launchers (defined in smcx_kernels.hip / smcx_plain.hip).
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
@@ -99,6 +154,10 @@ hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
                                   const double* logw_prev, double* logw, double* w_norm,
                                   double* scalars, double* scratch, hipStream_t st);
+hipError_t launch_drift(int model, int64_t N, const int64_t* offsets, double eps, const int8_t* dir,
+                        const uint8_t* active, const double* q_in, const double* p_in,
+                        const double* g_in, double* q_out, double* p_out, double* g_out,
+                        hipStream_t st);
 hipError_t launch_template_sum(int model, int64_t K, const double* theta, int64_t T,
                                double t_start, double dt, double* out, hipStream_t st);
 hipError_t launch_plain_particle(int model, const double* d64, int64_t T, double t_start,

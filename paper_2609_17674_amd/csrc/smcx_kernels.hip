@@ -598,6 +598,7 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
   const int i = it.i;
   const int64_t m0 = it.m0;
   const int K = it.K;
+  if (a.active && !a.active[i]) return;
 
   unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
   C* cst = reinterpret_cast<C*>(base);
@@ -639,10 +640,14 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
     if constexpr (GRAD) {
       wave_sync();
       const double bs = b * a.inv_sigma2;
+      const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
       for (int k = lane; k < K; k += 64) {
         double g[P];
         M::scale(a.theta + (m0 + k) * P, acc + k * P, bs, a, g);
         for (int p = 0; p < P; ++p) a.grad[(m0 + k) * P + p] = g[p];
+        if (a.p_half)
+          for (int p = 0; p < P; ++p)
+            a.p_out[(m0 + k) * P + p] = fma(he, g[p], a.p_half[(m0 + k) * P + p]);
       }
     }
   } else {
@@ -668,6 +673,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
   const int i = it.i;
   const int64_t m0 = it.m0;
   const int K = it.K;
+  if (a.active && !a.active[i]) return;
   const double b = a.beta ? a.beta[i] : 1.0;
   if (lane == 0 && a.logl) {
     double ss = 0.0;
@@ -686,6 +692,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
       double g[P];
       M::scale(a.theta + (m0 + k) * P, sums, bs, a, g);
       for (int p = 0; p < P; ++p) a.grad[(m0 + k) * P + p] = g[p];
+      if (a.p_half) {
+        const double he = 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0);
+        for (int p = 0; p < P; ++p)
+          a.p_out[(m0 + k) * P + p] = fma(he, g[p], a.p_half[(m0 + k) * P + p]);
+      }
     }
   }
 }
@@ -871,6 +882,35 @@ __global__ __launch_bounds__(1024) void reweight_kernel(int64_t N, double delta_
   }
 }
 
+// ---------------------------------------------------------------- leapfrog drift
+// First half of a leapfrog step, one wave per particle over its K*P values:
+//   p_half = p + (eps_i/2) g,  q' = q + eps_i p_half;
+// inactive particles copy (q, p, g) to the outputs unchanged.
+__global__ __launch_bounds__(256) void drift_kernel(int P, int64_t N, const int64_t* offsets,
+                                                    double eps, const int8_t* dir,
+                                                    const uint8_t* active, const double* q_in,
+                                                    const double* p_in, const double* g_in,
+                                                    double* q_out, double* p_out, double* g_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= N) return;
+  const int64_t o0 = offsets[i], o1 = offsets[i + 1];
+  if (o0 < 0 || o1 < o0) return;  // invalid particles are reported by the gradient pass
+  const bool on = !active || active[i];
+  const double e = eps * (dir ? (double)dir[i] : 1.0);
+  for (int64_t x = o0 * P + lane; x < o1 * P; x += 64) {
+    if (on) {
+      const double ph = fma(0.5 * e, g_in[x], p_in[x]);
+      p_out[x] = ph;
+      q_out[x] = fma(e, ph, q_in[x]);
+    } else {
+      q_out[x] = q_in[x];
+      p_out[x] = p_in[x];
+      g_out[x] = g_in[x];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- synthesis
 __global__ __launch_bounds__(256) void template_sum_kernel(int model, int64_t K,
                                                            const double* theta, int64_t T,
@@ -975,6 +1015,16 @@ hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* lo
                                   double* scalars, double* /*scratch*/, hipStream_t st) {
   hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(1024), 0, st, N, delta_beta, logl_ext,
                      logw_prev, logw, w_norm, scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_drift(int model, int64_t N, const int64_t* offsets, double eps, const int8_t* dir,
+                        const uint8_t* active, const double* q_in, const double* p_in,
+                        const double* g_in, double* q_out, double* p_out, double* g_out,
+                        hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(drift_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, n_params(model),
+                     N, offsets, eps, dir, active, q_in, p_in, g_in, q_out, p_out, g_out);
   return hipGetLastError();
 }
 

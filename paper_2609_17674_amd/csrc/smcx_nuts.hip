@@ -1,0 +1,301 @@
+// Batched No-U-Turn transition kernels (Sec. "No-U-Turn-Sampler").
+//
+// Every particle builds its own trajectory by repeated doubling; since a
+// doubling at depth j always has 2^j leapfrog steps, all particles that are
+// still extending sit at the same (depth, leaf) position and advance in
+// lockstep, one batched gradient evaluation per leaf. A particle that stops
+// (U-turn, divergence, maximum depth) simply drops out of the active mask,
+// so trajectory lengths are ragged. The variant is multinomial NUTS:
+//  * within a subtree, leaf n replaces the subtree proposal with probability
+//    w_n / (sum of subtree weights so far), w = exp(-H);
+//  * a completed subtree replaces the trajectory proposal with probability
+//    min(1, W_subtree / W_trajectory);
+//  * the generalised U-turn test on a segment with momentum sum rho and end
+//    momenta p_a, p_b stops when rho.p_a <= 0 or rho.p_b <= 0 (identity
+//    metric); it is applied to every balanced block of the subtree as the
+//    block completes, and to the whole trajectory after each doubling;
+//  * a leaf whose energy exceeds the initial one by more than 1000, or that
+//    leaves the prior box, is a divergence and stops the trajectory;
+//  * a subtree that turns or diverges is discarded.
+// Random numbers are inputs: one direction per doubling, one uniform per
+// leaf and one per doubling.
+//
+// One wave handles one particle; lanes run over its K*P coordinates.
+#include "smcx_internal.h"
+
+#include <math.h>
+
+namespace smcx {
+namespace {
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ int wany(int v) {
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double logaddexp(double a, double b) {
+  const double m = fmax(a, b);
+  if (m == -INFINITY) return -INFINITY;
+  return m + log(exp(a - m) + exp(b - m));
+}
+
+struct View {
+  int lane;
+  int64_t i, x0, x1;  // particle and its coordinate range [x0, x1)
+  int K;
+  bool ok;
+};
+
+__device__ __forceinline__ View view_of(const NutsArgs& a) {
+  View v;
+  v.lane = threadIdx.x & 63;
+  v.i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  v.ok = v.i < a.N;
+  if (!v.ok) return v;
+  const int64_t o0 = a.offsets[v.i], o1 = a.offsets[v.i + 1];
+  v.ok = o0 >= 0 && o1 >= o0 && o1 <= a.M;
+  v.x0 = o0 * a.P;
+  v.x1 = o1 * a.P;
+  v.K = (int)(o1 - o0);
+  return v;
+}
+
+__device__ __forceinline__ double* slot(const NutsArgs& a, int k) { return a.vec + (size_t)k * a.stride; }
+
+enum Slot { qL = 0, pL, gL, qR, pR, gR, qF, pF, gF, pH, qP, gP, qS, gS, rhoT, rhoS, kFirstCk };
+
+__device__ __forceinline__ bool in_box(const NutsArgs& a, int64_t x, double q) {
+  if (!a.prior_lo) return true;
+  const int p = (int)(x % a.P);
+  return q >= a.prior_lo[p] && q <= a.prior_hi[p];
+}
+
+// Drift of the frontier: pH = pF + (e/2) gF, qF += e pH.
+__device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e) {
+  double *q = slot(a, qF), *p = slot(a, pF), *g = slot(a, gF), *h = slot(a, pH);
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    const double ph = fma(0.5 * e, g[x], p[x]);
+    h[x] = ph;
+    q[x] = fma(e, ph, q[x]);
+  }
+}
+
+__global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
+  if (blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
+  const View v = view_of(a);
+  if (!v.ok) {
+    if (v.i < a.N && v.lane == 0) {
+      a.active[v.i] = 0;
+      a.state[v.i].status = -1;
+    }
+    return;
+  }
+  NutsState& s = a.state[v.i];
+  double pp = 0.0;
+  int out = 0;
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    const double q = a.q[x], p = a.momentum[x], g = a.grad[x];
+    pp = fma(p, p, pp);
+    out |= !in_box(a, x, q);
+    slot(a, qL)[x] = q; slot(a, pL)[x] = p; slot(a, gL)[x] = g;
+    slot(a, qR)[x] = q; slot(a, pR)[x] = p; slot(a, gR)[x] = g;
+    slot(a, qF)[x] = q; slot(a, pF)[x] = p; slot(a, gF)[x] = g;
+    slot(a, qP)[x] = q; slot(a, gP)[x] = g;
+    slot(a, rhoT)[x] = p;
+    slot(a, rhoS)[x] = 0.0;
+  }
+  pp = wsum(pp);
+  out = wany(out);
+  const double H0 = -a.logl[v.i] + 0.5 * pp;
+  const bool go = v.K > 0 && !out && (H0 == H0) && fabs(H0) < INFINITY;
+  const int8_t d = go ? a.dirs[v.i * a.D] : (int8_t)1;
+  if (v.lane == 0) {
+    s.H0 = H0;
+    s.lw_tree = -H0;
+    s.lw_sub = -INFINITY;
+    s.logl_prop = a.logl[v.i];
+    s.logl_sub = a.logl[v.i];
+    s.depth = 0;
+    s.steps = 0;
+    s.status = v.K == 0 ? 0 : (go ? 4 : 2);
+    a.active[v.i] = go ? 1 : 0;
+    a.dir[v.i] = d;
+  }
+  if (go) drift(a, v, a.eps * (double)d);
+}
+
+// Leaf n of the doubling at depth j (the frontier has just been moved by one
+// leapfrog step: qF, pF, gF and the frontier logL are current).
+__global__ __launch_bounds__(256) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
+  const View v = view_of(a);
+  if (!v.ok || !a.active[v.i]) return;
+  NutsState& s = a.state[v.i];
+  const double* q = slot(a, qF);
+  const double* p = slot(a, pF);
+  double pp = 0.0;
+  int out = 0;
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    pp = fma(p[x], p[x], pp);
+    out |= !in_box(a, x, q[x]);
+  }
+  pp = wsum(pp);
+  out = wany(out);
+  const double lf = a.logl_front[v.i];
+  const double H = out ? INFINITY : -lf + 0.5 * pp;
+  if (!(H - s.H0 <= 1000.0)) {  // divergence (also NaN)
+    if (v.lane == 0) {
+      s.steps += 1;
+      s.status = 2;
+      a.active[v.i] = 0;
+    }
+    return;
+  }
+  // multinomial choice inside the subtree
+  const double lw = -H;
+  const double lws = logaddexp(s.lw_sub, lw);
+  const double u = a.u_leaf[v.i * ((1ll << a.D) - 1) + ((1ll << j) - 1) + n];
+  const bool take = u < exp(lw - lws);
+  // momentum sum and checkpoints at block starts
+  double* rs = slot(a, rhoS);
+  const double* g = slot(a, gF);
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    if (take) {
+      slot(a, qS)[x] = q[x];
+      slot(a, gS)[x] = g[x];
+    }
+    const double before = rs[x];
+    rs[x] = before + p[x];
+    for (int m = 1; m <= j; ++m) {
+      if ((n & ((1 << m) - 1)) != 0) break;  // n starts blocks of 2^1 .. 2^m leaves
+      slot(a, kFirstCk + (m - 1))[x] = p[x];
+      slot(a, kFirstCk + a.D + (m - 1))[x] = before;
+    }
+  }
+  // U-turn test of every block of 2^m leaves that ends at leaf n
+  bool turn = false;
+  for (int m = 1; m <= j && !turn; ++m) {
+    if (((n + 1) & ((1 << m) - 1)) != 0) break;
+    const double* ckp = slot(a, kFirstCk + (m - 1));
+    const double* ckr = slot(a, kFirstCk + a.D + (m - 1));
+    double dl = 0.0, dr = 0.0;
+    for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+      const double rb = rs[x] - ckr[x];
+      dl = fma(rb, ckp[x], dl);
+      dr = fma(rb, p[x], dr);
+    }
+    dl = wsum(dl);
+    dr = wsum(dr);
+    turn = dl <= 0.0 || dr <= 0.0;
+  }
+  if (v.lane == 0) {
+    if (take) s.logl_sub = lf;
+    s.lw_sub = lws;
+    s.steps += 1;
+    if (turn) {
+      s.status = 1;
+      a.active[v.i] = 0;
+    }
+  }
+  if (!turn && n < (1 << j) - 1) drift(a, v, a.eps * (double)a.dir[v.i]);
+}
+
+// End of the doubling at depth j: merge the (valid) subtree into the trajectory.
+__global__ __launch_bounds__(256) void nuts_merge_kernel(NutsArgs a, int j) {
+  const View v = view_of(a);
+  if (!v.ok || !a.active[v.i]) return;
+  NutsState& s = a.state[v.i];
+  const bool take = a.u_tree[v.i * a.D + j] < exp(s.lw_sub - s.lw_tree);
+  const int8_t d = a.dir[v.i];
+  const int e0 = d > 0 ? qR : qL;
+  double dl = 0.0, dr = 0.0;
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    if (take) {
+      slot(a, qP)[x] = slot(a, qS)[x];
+      slot(a, gP)[x] = slot(a, gS)[x];
+    }
+    const double rt = slot(a, rhoT)[x] + slot(a, rhoS)[x];
+    slot(a, rhoT)[x] = rt;
+    slot(a, e0)[x] = slot(a, qF)[x];
+    slot(a, e0 + 1)[x] = slot(a, pF)[x];
+    slot(a, e0 + 2)[x] = slot(a, gF)[x];
+    dl = fma(rt, slot(a, pL)[x], dl);
+    dr = fma(rt, slot(a, pR)[x], dr);
+  }
+  dl = wsum(dl);
+  dr = wsum(dr);
+  const bool turn = dl <= 0.0 || dr <= 0.0;
+  const int depth = j + 1;
+  const bool more = !turn && depth < a.D;
+  const int8_t dn = more ? a.dirs[v.i * a.D + depth] : d;
+  if (v.lane == 0) {
+    if (take) s.logl_prop = s.logl_sub;
+    s.lw_tree = logaddexp(s.lw_tree, s.lw_sub);
+    s.depth = depth;
+    if (!more) {
+      s.status = turn ? 1 : 3;
+      a.active[v.i] = 0;
+    } else {
+      s.lw_sub = -INFINITY;
+      a.dir[v.i] = dn;
+      atomicAdd(&a.count[depth], 1);
+    }
+  }
+  if (!more) return;
+  const int e1 = dn > 0 ? qR : qL;
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    slot(a, qF)[x] = slot(a, e1)[x];
+    slot(a, pF)[x] = slot(a, e1 + 1)[x];
+    slot(a, gF)[x] = slot(a, e1 + 2)[x];
+    slot(a, rhoS)[x] = 0.0;
+  }
+  drift(a, v, a.eps * (double)dn);
+}
+
+__global__ __launch_bounds__(256) void nuts_finalize_kernel(NutsArgs a) {
+  const View v = view_of(a);
+  if (!v.ok) {
+    if (v.i < a.N && v.lane == 0) {
+      if (a.status_out) a.status_out[v.i] = -1;
+      if (a.depth_out) a.depth_out[v.i] = 0;
+      if (a.steps_out) a.steps_out[v.i] = 0;
+    }
+    return;
+  }
+  const NutsState& s = a.state[v.i];
+  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+    a.q[x] = slot(a, qP)[x];
+    a.grad[x] = slot(a, gP)[x];
+  }
+  if (v.lane == 0) {
+    a.logl[v.i] = s.logl_prop;
+    if (a.depth_out) a.depth_out[v.i] = s.depth;
+    if (a.steps_out) a.steps_out[v.i] = s.steps;
+    if (a.status_out) a.status_out[v.i] = s.status;
+  }
+}
+
+dim3 grid_of(int64_t N) { return dim3((unsigned)((N + 3) / 4)); }
+
+}  // namespace
+
+hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(nuts_init_kernel, grid_of(a.N), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st) {
+  hipLaunchKernelGGL(nuts_leaf_kernel, grid_of(a.N), dim3(256), 0, st, a, j, n);
+  return hipGetLastError();
+}
+hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st) {
+  hipLaunchKernelGGL(nuts_merge_kernel, grid_of(a.N), dim3(256), 0, st, a, j);
+  return hipGetLastError();
+}
+hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(nuts_finalize_kernel, grid_of(a.N), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace smcx

@@ -33,6 +33,17 @@ struct smcx_problem {
   double* part_g = nullptr; // [nch_grad][m_max][P]
   double* rbuf = nullptr;   // plain form residual [T]
   double* bpart = nullptr;  // plain form block partials
+  // NUTS workspace (smcx_nuts_reserve)
+  int nuts_depth = 0;
+  double* nuts_vec = nullptr;      // [nuts_slots][m_max * P] per-row state vectors
+  void* nuts_state = nullptr;      // [n_max] per-particle scalars
+  double* nuts_logl = nullptr;     // [n_max] tempered logL at the frontier
+  uint8_t* nuts_active = nullptr;  // [n_max]
+  int8_t* nuts_dir = nullptr;      // [n_max] direction of the current doubling
+  int* nuts_count = nullptr;       // [nuts_depth + 1] particles still extending
+  hipStream_t nuts_capture = nullptr;
+  std::vector<hipGraphExec_t> nuts_graph;  // one per doubling depth
+  std::vector<uint64_t> nuts_graph_key;
   // measurement hooks
   bool prof_on = false;
   int prof_n = 0;

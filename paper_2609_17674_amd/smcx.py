@@ -56,6 +56,10 @@ def load_library():
         "reweight_extend": [P, I64, I64, I64, P, I64, P, D, P, P, P, P, P, P],
         "smcx_template_sum": [I, I64, P, I64, D, D, P, P],
         "smcx_plain_logl_grad": [P, I64, P, I64, P, P, P, P, P],
+        "smcx_leapfrog": [P, I64, P, I64, P, D, P, P, P, P, P, P, P, P, P, P],
+        "smcx_nuts_reserve": [P, I32],
+        "smcx_nuts_transition": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, P, P, P, P,
+                                 I32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -287,6 +291,58 @@ def plain_logl_grad(prob: Problem, offsets_host, theta, beta=None, logl=None, gr
                                                theta.shape[0], _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
                                                _stream(stream)))
     return logl, grad
+
+
+def leapfrog(prob: Problem, offsets, beta, eps: float, q, p, g, dir=None, active=None, out=None,
+             stream=None):
+    """One leapfrog step; returns (q', p', g', logl') (smcx_leapfrog)."""
+    offsets, N, q, beta = _pop(prob, offsets, q, beta)
+    p = _dev(p, torch.float64, "p", tuple(q.shape))
+    g = _dev(g, torch.float64, "g", tuple(q.shape))
+    if dir is not None:
+        dir = _dev(dir, torch.int8, "dir", (N,))
+    if active is not None:
+        active = _dev(active, torch.uint8, "active", (N,))
+    if out is None:
+        out = (torch.empty_like(q), torch.empty_like(q), torch.empty_like(q),
+               torch.empty(N, dtype=torch.float64, device=q.device))
+    qo, po, go, lo = out
+    _check(load_library().smcx_leapfrog(prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta),
+                                        float(eps), _ptr(dir), _ptr(active), _ptr(q), _ptr(p),
+                                        _ptr(g), _ptr(qo), _ptr(po), _ptr(go), _ptr(lo),
+                                        _stream(stream)))
+    return qo, po, go, lo
+
+
+def nuts_reserve(prob: Problem, max_depth: int) -> None:
+    _check(load_library().smcx_nuts_reserve(prob.handle, int(max_depth)))
+
+
+def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q, logl, grad,
+                    momentum, dirs, u_leaf, u_tree, prior_lo=None, prior_hi=None, use_graph=True,
+                    stream=None):
+    """One batched NUTS transition, in place on (q, logl, grad).
+
+    Returns (depth, steps, status) int32 tensors [N]."""
+    offsets, N, q, beta = _pop(prob, offsets, q, beta)
+    logl = _dev(logl, torch.float64, "logl", (N,))
+    grad = _dev(grad, torch.float64, "grad", tuple(q.shape))
+    momentum = _dev(momentum, torch.float64, "momentum", tuple(q.shape))
+    dirs = _dev(dirs, torch.int8, "dirs", (N, max_depth))
+    u_leaf = _dev(u_leaf, torch.float64, "u_leaf", (N, (1 << max_depth) - 1))
+    u_tree = _dev(u_tree, torch.float64, "u_tree", (N, max_depth))
+    if prior_lo is not None:
+        prior_lo = _dev(prior_lo, torch.float64, "prior_lo", (prob.P,))
+        prior_hi = _dev(prior_hi, torch.float64, "prior_hi", (prob.P,))
+    depth = torch.empty(N, dtype=torch.int32, device=q.device)
+    steps = torch.empty_like(depth)
+    status = torch.empty_like(depth)
+    _check(load_library().smcx_nuts_transition(
+        prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta), float(eps), int(max_depth),
+        _ptr(prior_lo), _ptr(prior_hi), _ptr(momentum), _ptr(dirs), _ptr(u_leaf), _ptr(u_tree),
+        _ptr(q), _ptr(logl), _ptr(grad), _ptr(depth), _ptr(steps), _ptr(status),
+        1 if use_graph else 0, _stream(stream)))
+    return depth, steps, status
 
 
 class LogLGrad(torch.autograd.Function):

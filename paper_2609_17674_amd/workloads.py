@@ -206,3 +206,15 @@ def subsample(w: Workload, idx: np.ndarray) -> Workload:
     return Workload(name=w.name + "_sub", model=w.model, T=w.T, t_start=w.t_start, dt=w.dt,
                     sigma=w.sigma, inj=w.inj, noise=w.noise, offsets=off, theta=theta,
                     beta=w.beta[idx], k_max=w.k_max, extra=extra)
+
+
+def nuts_draws(N: int, M: int, P: int, max_depth: int, seed: int):
+    """Random inputs of one NUTS transition: momenta [M,P] ~ N(0,1), doubling
+    directions [N,max_depth] in {-1,+1}, leaf uniforms [N, 2^max_depth - 1],
+    subtree-merge uniforms [N, max_depth]."""
+    rng = np.random.default_rng(seed)
+    momentum = rng.standard_normal((M, P))
+    dirs = np.where(rng.random((N, max_depth)) < 0.5, -1, 1).astype(np.int8)
+    u_leaf = rng.random((N, (1 << max_depth) - 1))
+    u_tree = rng.random((N, max_depth))
+    return momentum, dirs, u_leaf, u_tree
