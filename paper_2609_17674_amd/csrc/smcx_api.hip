@@ -511,8 +511,8 @@ int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
         return fail(SMCX_EINVAL, "input and output state arrays overlap");
   if (N == 0) return SMCX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
-  hipError_t e = smcx::launch_drift(p->model, N, offsets, eps, dir, active, q_in, p_in, g_in, q_out,
-                                    p_out, g_out, st);
+  hipError_t e = smcx::launch_drift(p->model, N, M, offsets, eps, dir, active, q_in, p_in, g_in,
+                                    q_out, p_out, g_out, st);
   if (e != hipSuccess) return hip_fail(e, "drift launch");
   const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
   const Tiling& t = p->tiling[kGrad];

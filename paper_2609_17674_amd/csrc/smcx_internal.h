@@ -154,10 +154,10 @@ hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
                                   const double* logw_prev, double* logw, double* w_norm,
                                   double* scalars, double* scratch, hipStream_t st);
-hipError_t launch_drift(int model, int64_t N, const int64_t* offsets, double eps, const int8_t* dir,
-                        const uint8_t* active, const double* q_in, const double* p_in,
-                        const double* g_in, double* q_out, double* p_out, double* g_out,
-                        hipStream_t st);
+hipError_t launch_drift(int model, int64_t N, int64_t M, const int64_t* offsets, double eps,
+                        const int8_t* dir, const uint8_t* active, const double* q_in,
+                        const double* p_in, const double* g_in, double* q_out, double* p_out,
+                        double* g_out, hipStream_t st);
 hipError_t launch_template_sum(int model, int64_t K, const double* theta, int64_t T,
                                double t_start, double dt, double* out, hipStream_t st);
 hipError_t launch_plain_particle(int model, const double* d64, int64_t T, double t_start,

@@ -886,8 +886,9 @@ __global__ __launch_bounds__(1024) void reweight_kernel(int64_t N, double delta_
 // First half of a leapfrog step, one wave per particle over its K*P values:
 //   p_half = p + (eps_i/2) g,  q' = q + eps_i p_half;
 // inactive particles copy (q, p, g) to the outputs unchanged.
-__global__ __launch_bounds__(256) void drift_kernel(int P, int64_t N, const int64_t* offsets,
-                                                    double eps, const int8_t* dir,
+__global__ __launch_bounds__(256) void drift_kernel(int P, int64_t N, int64_t M,
+                                                    const int64_t* offsets, double eps,
+                                                    const int8_t* dir,
                                                     const uint8_t* active, const double* q_in,
                                                     const double* p_in, const double* g_in,
                                                     double* q_out, double* p_out, double* g_out) {
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(256) void drift_kernel(int P, int64_t N, const int6
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= N) return;
   const int64_t o0 = offsets[i], o1 = offsets[i + 1];
-  if (o0 < 0 || o1 < o0) return;  // invalid particles are reported by the gradient pass
+  if (o0 < 0 || o1 < o0 || o1 > M) return;  // invalid particles are reported by the gradient pass
   const bool on = !active || active[i];
   const double e = eps * (dir ? (double)dir[i] : 1.0);
   for (int64_t x = o0 * P + lane; x < o1 * P; x += 64) {
@@ -1018,13 +1019,13 @@ hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* lo
   return hipGetLastError();
 }
 
-hipError_t launch_drift(int model, int64_t N, const int64_t* offsets, double eps, const int8_t* dir,
-                        const uint8_t* active, const double* q_in, const double* p_in,
-                        const double* g_in, double* q_out, double* p_out, double* g_out,
-                        hipStream_t st) {
+hipError_t launch_drift(int model, int64_t N, int64_t M, const int64_t* offsets, double eps,
+                        const int8_t* dir, const uint8_t* active, const double* q_in,
+                        const double* p_in, const double* g_in, double* q_out, double* p_out,
+                        double* g_out, hipStream_t st) {
   if (N == 0) return hipSuccess;
   hipLaunchKernelGGL(drift_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, n_params(model),
-                     N, offsets, eps, dir, active, q_in, p_in, g_in, q_out, p_out, g_out);
+                     N, M, offsets, eps, dir, active, q_in, p_in, g_in, q_out, p_out, g_out);
   return hipGetLastError();
 }
 

@@ -129,7 +129,10 @@ def test_nuts_graph_replays_equal_eager(lib, orc):
             assert np.array_equal(x, y)
     depth, steps, status = results[0][3:]
     assert np.all((status >= 0) & (status <= 3))
-    assert np.all(steps >= 1) and np.all(steps <= (1 << D) - 1)
+    has = w.K > 0
+    assert np.all(status[~has] == 0) and np.all(steps[~has] == 0)
+    assert np.all(steps[has] >= 1) and np.all(steps[has] <= (1 << D) - 1)
+    assert np.all(steps[has] >= (1 << depth[has]) - 1)
 
 
 def test_nuts_matches_oracle_statistically(lib, orc):
