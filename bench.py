@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
-"""Throughput of the batched fused log-likelihood + gradient on one MI355X.
+"""Throughput of the batched population likelihood paths on one MI355X.
 
-A step is one logl_grad_batch call over the whole population of the
-workload (template synthesis, residual, FP64 inner products, adjoint
-gradient and ragged batching in one pass): the unit of work is one particle
-log-likelihood + gradient evaluation. The same population is then run
-through the plain one-particle-per-launch FP64 form on the same GPU, and
-through the FP64 CPU oracle on a bounded sample on the host cores; the
+Default workload (pulse_batch): a step is one logl_grad_batch call over the
+whole population (template synthesis, residual, FP64 inner products,
+adjoint gradient and ragged batching in one fused pass); the unit of work is
+one particle log-likelihood + gradient evaluation. The same population is
+then run through the plain one-particle-per-launch FP64 form on the same GPU,
+and through the FP64 CPU oracle on a bounded sample on the host cores; the
 oracle's results on that sample also give the reported error of the GPU
-path. Inputs are seeded synthetic workloads resident in device memory
-before the timed region starts.
+path. Inputs are seeded synthetic workloads resident in device memory before
+the timed region starts.
+
+Other workloads (--workload):
+  gb_grad       the same metric on the chirping-sinusoid population
+  gb_extend     data-assimilation reweighting: segment logL of every particle
+                on the new samples plus weights, ESS and evidence increment
+  pulse_mutate  one NUTS transition of every particle (hipGraph-replayed
+                leapfrog sweeps) plus the birth/death log-likelihood changes
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
-[--workload pulse_batch|gb_grad] [--gpus 1].
+[--workload ...] [--gpus 1].
 """
 import argparse
 import json
@@ -29,18 +36,260 @@ METRIC = "particle logL+grad evals/sec (ragged K) vs plain GPU form at ≤1e-6 r
 # (128 FP32 FMA lanes per CU per clock), FP64 vector 78.6 TFLOP/s.
 PEAK_FP32_TFLOPS = 157.3
 
-# Issue cost of one component-sample of the fused forward + adjoint pass in
-# FP32-FMA-equivalent VALU slots (FP32 op = 1, FP64 op = 2, transcendental =
-# 4; the weights are the published FP32:FP64 ratio and the measured
-# exp/sin/cos issue rate on gfx950). Pulse: forward add, fma, mul, exp2,
-# fma; adjoint add, fma, mul, exp2, mul, add, mul, add, fma. Sinusoid:
-# forward 2 FP64 fma, cvt, mul, sin, fma; adjoint 2 FP64 fma, cvt, mul,
-# sin, cos, fma, mul, add, fma, fma.
-SLOTS_PER_COMPONENT_SAMPLE = {0: 8 + 12, 1: 11 + 19}
+# Issue cost of one component-sample in FP32-FMA-equivalent VALU slots
+# (FP32 op = 1, FP64 op = 2, transcendental = 4, from the published
+# FP32:FP64 ratio and the measured exp/sin/cos issue rate on gfx950).
+#   pulse forward: add, fma, mul, exp2, fma                        4 + 4
+#   pulse adjoint: add, fma, mul, exp2, mul, add, mul, add, fma    8 + 4
+#   sinusoid forward: int add, cvt, fma, mul, sin, fma             5 + 4
+#   sinusoid adjoint: int add, cvt, fma, mul, sin, cos,
+#                     fma, mul, add, fma, fma                      9 + 8
+SLOTS = {(0, "grad"): 20, (1, "grad"): 26, (0, "fwd"): 8, (1, "fwd"): 9}
+
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
+# known size. Valid only for the kernel source they were taken on (its hash).
+PMC_TRAFFIC = {("pulse_batch", "64,4096,1"): {"bytes": 1.3140e7, "kernels_sha1": "4ff13c53e0d8a42b"}}
+
+
+def kernels_sha1():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2609_17674_amd", "csrc", "smcx_kernels.hip")
+    return hashlib.sha1(open(path, "rb").read()).hexdigest()[:16]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def roofline(model, kind, comp_samples, kern_ms, kernel):
+    slots = SLOTS[(model, kind)] * comp_samples
+    achieved = 2.0 * slots / (kern_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": kernel, "kernel_ms": round(kern_ms, 5),
+            "work": f"{comp_samples:.4e} component-samples x {SLOTS[(model, kind)]} "
+                    f"FP32-FMA-equivalent slots"}
+
+
+def timed(fn, prob, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    prob.device_status()
+    prob.profile_begin(max(steps, 1) * 300)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, kern_n = prob.profile_end()
+    return (t1 - t0) * 1e3 / steps, kern_ms / max(kern_n, 1), kern_n
+
+
+def cpu_sample(w, per_eval_fn, budget_s, rng):
+    import numpy as np
+    from paper_2609_17674_amd import workloads as wl
+    probe = wl.subsample(w, np.sort(rng.choice(w.N, size=min(32, w.N), replace=False)))
+    t0 = time.perf_counter()
+    per_eval_fn(probe)
+    per = (time.perf_counter() - t0) / probe.N
+    n = int(min(w.N, max(64, budget_s / max(per, 1e-9))))
+    idx = np.sort(rng.choice(w.N, size=n, replace=False))
+    return idx, wl.subsample(w, idx)
+
+
+def setup(w, dev, smcx, torch):
+    inj = torch.tensor(w.inj, device=dev)
+    d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, inj, w.T, w.t_start, w.dt)
+    prob = smcx.Problem(w.model, d, w.t_start, w.dt, w.sigma, w.k_max, w.N, w.M)
+    return d, prob, torch.tensor(w.offsets, device=dev), torch.tensor(w.theta, device=dev)
+
+
+def bench_grad(args, w, dev, smcx, np, torch):
+    d, prob, off, th = setup(w, dev, smcx, torch)
+    beta = torch.tensor(w.beta, device=dev)
+    logl = torch.empty(w.N, dtype=torch.float64, device=dev)
+    grad = torch.empty_like(th)
+    if args.tiling:
+        S, chunk, so = (int(x) for x in args.tiling.split(","))
+        prob.set_tiling(smcx.KIND_GRAD, S, chunk, so)
+        tuned = (S, chunk, so, float("nan"))
+    else:
+        tuned = prob.autotune(smcx.KIND_GRAD, off, th, beta, reps=5)
+    log(f"[bench] tiling S={tuned[0]} chunk={tuned[1]} sorted={tuned[2]} "
+        f"({tuned[3]:.4f} ms/call when tuned)")
+
+    def step():
+        smcx.logl_grad_batch(prob, off, th, beta, logl=logl, grad=grad)
+
+    ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
+    value = w.N / (ms * 1e-3)
+    log(f"[bench] {ms:.4f} ms/step, kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
+    rl = roofline(w.model, "grad", float(w.M) * w.T, kern_ms, "pop_kernel (fused forward+adjoint)")
+    pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
+    if pmc and pmc["kernels_sha1"] == kernels_sha1():
+        rl["traffic"] = pmc["bytes"]
+    out_l, out_g = logl.cpu().numpy(), grad.cpu().numpy()
+
+    plain = None
+    if not args.no_plain:
+        pl, pg = torch.empty_like(logl), torch.empty_like(grad)
+        sub = min(64, w.N)
+        msub = int(w.offsets[sub])
+        smcx.plain_logl_grad(prob, w.offsets[:sub + 1], th[:msub], beta[:sub], logl=pl[:sub],
+                             grad=pg[:msub])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smcx.plain_logl_grad(prob, w.offsets, th, beta, logl=pl, grad=pg)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        plain = {"value": w.N / (plain_ms * 1e-3), "unit": "evals/s", "ms_per_step": plain_ms,
+                 "form": "one particle per forward+adjoint launch pair, FP64"}
+        plain_l, plain_g = pl.cpu().numpy(), pg.cpu().numpy()
+        log(f"[bench] plain form {plain_ms:.1f} ms/step")
+
+    cpu = accuracy = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import parity as pm
+        oracle.build(force=False)
+        d_host = d.cpu().numpy()
+        rng = np.random.default_rng(2024)
+        idx, sub = cpu_sample(w, lambda s: oracle.logl_grad(w.model, d_host, w.t_start, w.dt,
+                                                            w.sigma, s.offsets, s.theta, s.beta),
+                              args.cpu_seconds, rng)
+        t0 = time.perf_counter()
+        ref_l, ref_g = oracle.logl_grad(w.model, d_host, w.t_start, w.dt, w.sigma, sub.offsets,
+                                        sub.theta, sub.beta)
+        cpu_s = time.perf_counter() - t0
+        n = len(idx)
+        cpu = {"value": n / cpu_s, "unit": "evals/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"{n} of {w.N} particles of the same workload (seeded), all {w.T} "
+                         f"samples, {cpu_s:.1f} s"}
+        log(f"[bench] cpu oracle {n} particles in {cpu_s:.1f} s")
+        rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
+        el = pm.logl_errors(out_l[idx], ref_l)
+        rel, cos = pm.grad_errors(w.model, sub.offsets, sub.theta, out_g[rows], ref_g, w.T, w.dt)
+        accuracy = {"checked_particles": n, "logl_max_rel_err": float(el.max()),
+                    "grad_max_rel_err": float(rel.max()) if len(rel) else 0.0,
+                    "grad_min_cos": float(cos.min()) if len(cos) else 1.0}
+        if plain is not None:
+            pel = pm.logl_errors(plain_l[idx], ref_l)
+            prel, _ = pm.grad_errors(w.model, sub.offsets, sub.theta, plain_g[rows], ref_g, w.T,
+                                     w.dt)
+            plain["logl_max_rel_err"] = float(pel.max())
+            plain["grad_max_rel_err"] = float(prel.max()) if len(prel) else 0.0
+    return dict(metric=METRIC, value=value, unit="evals/s", ms_per_step=ms,
+                config={"workload": w.name, "T": w.T, "N": w.N, "M": w.M,
+                        "K": f"U{{0..{w.k_max}}}",
+                        "beta": "U[0,1]" if w.name == "pulse_batch" else "1",
+                        "tiling": {"S": tuned[0], "chunk_len": tuned[1], "sorted": tuned[2]}},
+                plain_gpu=plain, speedup_vs_plain=(value / plain["value"]) if plain else None,
+                accuracy=accuracy, roofline=rl, cpu_baseline=cpu)
+
+
+def bench_extend(args, w, dev, smcx, np, torch):
+    T1, T2 = w.extra["T1"], w.extra["T2"]
+    d, prob, off, th = setup(w, dev, smcx, torch)
+    tuned = prob.autotune(smcx.KIND_LOGL, off, th, None, reps=2)
+    outs = tuple(torch.empty(n, dtype=torch.float64, device=dev) for n in (w.N, w.N, w.N, 3))
+
+    def step():
+        smcx.reweight_extend(prob, T1, T2, off, th, 1.0, out=outs)
+
+    ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
+    value = w.N / (ms * 1e-3)
+    log(f"[bench] reweight {ms:.3f} ms/step, segment kernel {kern_ms:.3f} ms")
+    rl = roofline(w.model, "fwd", float(w.M) * (T2 - T1), kern_ms, "pop_kernel (segment forward)")
+    cpu = accuracy = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import parity as pm
+        oracle.build(force=False)
+        d_host = d.cpu().numpy()
+        rng = np.random.default_rng(2025)
+        idx, sub = cpu_sample(w, lambda s: oracle.reweight_extend(w.model, d_host, w.t_start, w.dt,
+                                                                  w.sigma, T1, T2, s.offsets,
+                                                                  s.theta, 1.0),
+                              args.cpu_seconds, rng)
+        t0 = time.perf_counter()
+        ref = oracle.reweight_extend(w.model, d_host, w.t_start, w.dt, w.sigma, T1, T2, sub.offsets,
+                                     sub.theta, 1.0)[0]
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": len(idx) / cpu_s, "unit": "evals/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"{len(idx)} of {w.N} particles, samples [{T1}, {T2}), {cpu_s:.1f} s"}
+        el = pm.logl_errors(outs[0].cpu().numpy()[idx], ref)
+        accuracy = {"checked_particles": len(idx), "logl_ext_max_rel_err": float(el.max())}
+    sc = outs[3].cpu().numpy()
+    return dict(metric="particle segment-logL evals/sec for data-assimilation reweighting",
+                value=value, unit="evals/s", ms_per_step=ms,
+                config={"workload": w.name, "T1": T1, "T2": T2, "N": w.N, "M": w.M,
+                        "K": f"U{{0..{w.k_max}}}",
+                        "tiling": {"S": tuned[0], "chunk_len": tuned[1], "sorted": tuned[2]},
+                        "ESS_at_delta_beta_1": float(sc[0])},
+                accuracy=accuracy, roofline=rl, cpu_baseline=cpu)
+
+
+def bench_mutate(args, w, dev, smcx, np, torch):
+    from paper_2609_17674_amd import workloads as wl
+    d, prob, off, th0 = setup(w, dev, smcx, torch)
+    beta = torch.tensor(w.beta, device=dev)
+    D, eps = int(w.extra["max_depth"]), float(w.extra["eps"])
+    prob.autotune(smcx.KIND_GRAD, off, th0, beta, reps=3)
+    prob.autotune(smcx.KIND_DELTA, off, th0, beta, reps=3)
+    smcx.nuts_reserve(prob, D)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, w.P, D, seed=4242)
+    mom, dirs, ul, ut = (torch.tensor(x, device=dev) for x in (mom, dirs, ul, ut))
+    lo = torch.tensor(wl.PULSE_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.PULSE_PRIOR[:, 1].copy(), device=dev)
+    tb = torch.tensor(w.extra["theta_birth"], device=dev)
+    di = torch.tensor(w.extra["death_idx"], device=dev)
+    l0, g0 = smcx.logl_grad_batch(prob, off, th0, beta)
+    q, l, g = th0.clone(), l0.clone(), g0.clone()
+    state = {}
+
+    def step():
+        q.copy_(th0)
+        l.copy_(l0)
+        g.copy_(g0)
+        state["out"] = smcx.nuts_transition(prob, off, beta, eps, D, q, l, g, mom, dirs, ul, ut,
+                                            lo, hi)
+        state["delta"] = smcx.delta_logl_birth_death(prob, off, q, beta, tb, di)
+
+    ms, kern_ms, kern_n = timed(step, prob, args.steps, args.warmup)
+    depth, steps, status = (x.cpu().numpy() for x in state["out"])
+    total_steps = int(steps.sum())
+    value = total_steps / (ms * 1e-3)
+    log(f"[bench] NUTS+RJ {ms:.3f} ms/step, {total_steps} leapfrog grads, {value:.3e} grads/s")
+    return dict(metric="leapfrog gradient evals/sec inside batched NUTS (ragged trajectories)",
+                value=value, unit="evals/s", ms_per_step=ms,
+                config={"workload": w.name, "T": w.T, "N": w.N, "M": w.M, "max_depth": D,
+                        "eps": eps, "beta": 0.5,
+                        "depth_histogram": np.bincount(depth, minlength=D + 1).tolist(),
+                        "status_counts": np.bincount(status, minlength=4).tolist(),
+                        "leapfrog_steps": total_steps,
+                        "delta_pass_ms": kern_ms})
+
+
+def copy_probe(args, torch):
+    """Device-to-device copy of a known size, for calibrating HBM byte counters."""
+    n = 1 << 26  # 64 Mi float32 = 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(max(args.steps, 1)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": 4 * n,
+                      "copy_probe_bytes_written_per_launch": 4 * n, "launches": args.steps}),
+          flush=True)
 
 
 def main():
@@ -48,7 +297,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pulse_batch", choices=["pulse_batch", "gb_grad"])
+    ap.add_argument("--workload", default="pulse_batch",
+                    choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "copy_probe"])
+    ap.add_argument("--tiling", default="", help="S,chunk_len,sorted: fixed tiling, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -67,138 +318,35 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "copy_probe":
+        copy_probe(args, torch)
+        return
     w = wl.make_config(args.workload)
     log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    inj = torch.tensor(w.inj, device=dev)
-    d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, inj, w.T, w.t_start, w.dt)
-    prob = smcx.Problem(w.model, d, w.t_start, w.dt, w.sigma, w.k_max, w.N, w.M)
-    off = torch.tensor(w.offsets, device=dev)
-    th = torch.tensor(w.theta, device=dev)
-    beta = torch.tensor(w.beta, device=dev)
-    logl = torch.empty(w.N, dtype=torch.float64, device=dev)
-    grad = torch.empty_like(th)
-
-    tuned = prob.autotune(smcx.KIND_GRAD, off, th, beta, reps=5)
-    log(f"[bench] autotuned tiling S={tuned[0]} chunk={tuned[1]} sorted={tuned[2]} "
-        f"({tuned[3]:.4f} ms/call)")
-
-    def step():
-        smcx.logl_grad_batch(prob, off, th, beta, logl=logl, grad=grad)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    prob.device_status()
-    log(f"[bench] warmup done ({args.warmup} steps)")
-
-    prob.profile_begin(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern_ms, kern_n = prob.profile_end()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = w.N / (ms_per_step * 1e-3)
-    kern_avg_ms = kern_ms / max(kern_n, 1)
-    log(f"[bench] {ms_per_step:.4f} ms/step, kernel {kern_avg_ms:.4f} ms, {value:.4e} evals/s")
-
-    comp_samples = float(w.M) * w.T
-    slots = SLOTS_PER_COMPONENT_SAMPLE[w.model] * comp_samples
-    achieved = 2.0 * slots / (kern_avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "pop_kernel (fused forward+adjoint)",
-                "kernel_ms": round(kern_avg_ms, 5),
-                "work": f"{comp_samples:.4e} component-samples x "
-                        f"{SLOTS_PER_COMPONENT_SAMPLE[w.model]} FP32-FMA-equivalent slots"}
-
-    out_l = logl.cpu().numpy()
-    out_g = grad.cpu().numpy()
-
-    plain = None
-    if not args.no_plain:
-        pl = torch.empty_like(logl)
-        pg = torch.empty_like(grad)
-        sub = min(64, w.N)
-        msub = int(w.offsets[sub])
-        smcx.plain_logl_grad(prob, w.offsets[:sub + 1], th[:msub], beta[:sub],
-                             logl=pl[:sub], grad=pg[:msub])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        smcx.plain_logl_grad(prob, w.offsets, th, beta, logl=pl, grad=pg)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        plain_ms = (t1 - t0) * 1e3
-        plain = {"value": w.N / (plain_ms * 1e-3), "unit": "evals/s", "ms_per_step": plain_ms,
-                 "form": "one particle per forward+adjoint launch pair, FP64"}
-        plain_l, plain_g = pl.cpu().numpy(), pg.cpu().numpy()
-        log(f"[bench] plain form {plain_ms:.1f} ms/step")
-
-    cpu = None
-    accuracy = None
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        d_host = d.cpu().numpy()
-        rng = np.random.default_rng(2024)
-        probe = wl.subsample(w, np.sort(rng.choice(w.N, size=min(32, w.N), replace=False)))
-        t0 = time.perf_counter()
-        oracle.logl_grad(w.model, d_host, w.t_start, w.dt, w.sigma, probe.offsets, probe.theta,
-                         probe.beta)
-        per = (time.perf_counter() - t0) / probe.N
-        n = int(min(w.N, max(64, args.cpu_seconds / max(per, 1e-9))))
-        idx = np.sort(rng.choice(w.N, size=n, replace=False))
-        sub = wl.subsample(w, idx)
-        t0 = time.perf_counter()
-        ref_l, ref_g = oracle.logl_grad(w.model, d_host, w.t_start, w.dt, w.sigma, sub.offsets,
-                                        sub.theta, sub.beta)
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": n / cpu_s, "unit": "evals/s", "cores": oracle.get_threads(),
-               "kind": "oracle",
-               "sample": f"{n} of {w.N} particles of the same workload (seeded), all {w.T} "
-                         f"samples, {cpu_s:.1f} s"}
-        log(f"[bench] cpu oracle {n} particles in {cpu_s:.1f} s")
-
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        import parity as pm
-        rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
-        el = pm.logl_errors(out_l[idx], ref_l)
-        rel, cos = pm.grad_errors(w.model, sub.offsets, sub.theta, out_g[rows], ref_g, w.T, w.dt)
-        accuracy = {"checked_particles": n, "logl_max_rel_err": float(el.max()),
-                    "grad_max_rel_err": float(rel.max()) if len(rel) else 0.0,
-                    "grad_min_cos": float(cos.min()) if len(cos) else 1.0}
-        if plain is not None:
-            pel = pm.logl_errors(plain_l[idx], ref_l)
-            prel, _ = pm.grad_errors(w.model, sub.offsets, sub.theta, plain_g[rows], ref_g, w.T,
-                                     w.dt)
-            plain["logl_max_rel_err"] = float(pel.max())
-            plain["grad_max_rel_err"] = float(prel.max()) if len(prel) else 0.0
-
+    if args.workload in ("pulse_batch", "gb_grad"):
+        res = bench_grad(args, w, dev, smcx, np, torch)
+    elif args.workload == "gb_extend":
+        res = bench_extend(args, w, dev, smcx, np, torch)
+    else:
+        res = bench_mutate(args, w, dev, smcx, np, torch)
     line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "evals/s",
+        "metric": res["metric"],
+        "value": res["value"],
+        "unit": res["unit"],
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "T": w.T, "N": w.N, "M": w.M,
-                   "K": f"U{{0..{w.k_max}}}", "beta": "U[0,1]" if w.name == "pulse_batch" else "1",
-                   "precision": "FP32 synthesis/residual, FP64 phase and accumulation",
-                   "tiling": {"S": tuned[0], "chunk_len": tuned[1], "sorted": tuned[2]}},
-        "plain_gpu": plain,
-        "speedup_vs_plain": (value / plain["value"]) if plain else None,
-        "accuracy": accuracy,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "config": res["config"],
     }
+    for key in ("plain_gpu", "speedup_vs_plain", "accuracy", "roofline", "cpu_baseline"):
+        if key in res:
+            line[key] = res[key]
     print(json.dumps(line), flush=True)
 
 
