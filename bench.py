@@ -40,11 +40,11 @@ PEAK_FP32_TFLOPS = 157.3
 # (FP32 op = 1, FP64 op = 2, transcendental = 4, from the published
 # FP32:FP64 ratio and the measured exp/sin/cos issue rate on gfx950).
 #   pulse forward: add, fma, mul, exp2, fma                        4 + 4
-#   pulse adjoint: add, fma, mul, exp2, mul, add, mul, add, fma    8 + 4
+#   pulse adjoint: add, fma, mul, exp2, mul, add, fma, fma         7 + 4
 #   sinusoid forward: int add, cvt, fma, mul, sin, fma             5 + 4
 #   sinusoid adjoint: int add, cvt, fma, mul, sin, cos,
 #                     fma, mul, add, fma, fma                      9 + 8
-SLOTS = {(0, "grad"): 20, (1, "grad"): 26, (0, "fwd"): 8, (1, "fwd"): 9}
+SLOTS = {(0, "grad"): 19, (1, "grad"): 26, (0, "fwd"): 8, (1, "fwd"): 9}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -71,6 +71,21 @@ def roofline(model, kind, comp_samples, kern_ms, kernel):
             "kernel": kernel, "kernel_ms": round(kern_ms, 5),
             "work": f"{comp_samples:.4e} component-samples x {SLOTS[(model, kind)]} "
                     f"FP32-FMA-equivalent slots"}
+
+
+def component_samples(w, s_lo, s_hi):
+    """Component-samples the method needs on samples [s_lo, s_hi). Sinusoids
+    cover every sample; pulses are truncated where |t - t0| >= sqrt(128 ln 2) w
+    (template below 2^-64 of its peak), so only samples inside that support
+    count."""
+    import numpy as np
+    if w.model != 0:
+        return float(w.M) * (s_hi - s_lo)
+    c = (w.theta[:, 1] - w.t_start) / w.dt
+    hw = np.sqrt(128.0 * np.log(2.0)) * np.abs(w.theta[:, 2]) / w.dt
+    lo = np.maximum(np.ceil(c - hw), s_lo)
+    hi = np.minimum(np.floor(c + hw), s_hi - 1)
+    return float(np.maximum(hi - lo + 1.0, 0.0).sum())
 
 
 def timed(fn, prob, steps, warmup):
@@ -129,7 +144,8 @@ def bench_grad(args, w, dev, smcx, np, torch):
     ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
     value = w.N / (ms * 1e-3)
     log(f"[bench] {ms:.4f} ms/step, kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
-    rl = roofline(w.model, "grad", float(w.M) * w.T, kern_ms, "pop_kernel (fused forward+adjoint)")
+    rl = roofline(w.model, "grad", component_samples(w, 0, w.T), kern_ms,
+                  "pop_kernel (fused forward+adjoint)")
     pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
     if pmc and pmc["kernels_sha1"] == kernels_sha1():
         rl["traffic"] = pmc["bytes"]
@@ -206,7 +222,8 @@ def bench_extend(args, w, dev, smcx, np, torch):
     ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
     value = w.N / (ms * 1e-3)
     log(f"[bench] reweight {ms:.3f} ms/step, segment kernel {kern_ms:.3f} ms")
-    rl = roofline(w.model, "fwd", float(w.M) * (T2 - T1), kern_ms, "pop_kernel (segment forward)")
+    rl = roofline(w.model, "fwd", component_samples(w, T1, T2), kern_ms,
+                  "pop_kernel (segment forward)")
     cpu = accuracy = None
     if not args.no_cpu_baseline:
         import oracle

@@ -42,7 +42,14 @@
  * Precision. Template synthesis and residual arithmetic run in FP32; the
  * Galactic-binary phase is formed and reduced modulo one cycle in FP64; the
  * per-particle inner products are accumulated in FP64 and all outputs are
- * FP64.
+ * FP64. In logl_batch, logl_grad_batch, reweight_extend and the leapfrog and
+ * NUTS calls, a pulse is truncated to |t - t0| < sqrt(128 ln 2) |w| (about
+ * 9.42 |w|), outside which its template is below 2^-64 of its peak. Blocks of
+ * 64 samples that meet the support are evaluated whole. The truncation is far
+ * under the FP32 resolution of the residual; only a component lying entirely
+ * outside the sample range notices it, whose negligible gradient may then come
+ * out as exactly zero. delta_logl_birth_death and smcx_plain_logl_grad
+ * evaluate pulses on every sample.
  *
  * Errors. Every call returns SMCX_OK or a negative code and never throws
  * across the ABI; smcx_last_error() gives a message for the calling thread.

@@ -110,6 +110,7 @@ void free_problem(smcx_problem* p) {
   (void)hipFree(p->d64);
   (void)hipFree(p->order);
   (void)hipFree(p->n_active);
+  (void)hipFree(p->prep_hist);
   (void)hipFree(p->flag);
   (void)hipFree(p->part);
   (void)hipFree(p->part_g);
@@ -192,6 +193,7 @@ smcx::PrepArgs prep_args(smcx_problem* p, int64_t N, const int64_t* offsets, int
   a.P = p->P;
   a.order = p->order;
   a.n_active = p->n_active;
+  a.block_hist = p->prep_hist;
   a.flag = p->flag;
   a.tempered = tempered;
   return a;
@@ -266,6 +268,8 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
       {(void**)&p->d64, T * sizeof(double)},
       {(void**)&p->order, (size_t)std::max<int64_t>(n_max, 1) * sizeof(int32_t)},
       {(void**)&p->n_active, sizeof(int32_t)},
+      {(void**)&p->prep_hist,
+       (size_t)smcx::prep_slices(std::max<int64_t>(n_max, 1)) * (k_max + 1) * sizeof(int32_t)},
       {(void**)&p->flag, sizeof(int)},
       {(void**)&p->part, part_elems * sizeof(double)},
       {(void**)&p->part_g, partg_elems * sizeof(double)},

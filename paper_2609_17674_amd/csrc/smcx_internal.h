@@ -94,6 +94,7 @@ struct PrepArgs {
   const int32_t* death_idx;  // validated against [-1, K_i) when dlogl_death is set
   int32_t* order;
   int32_t* n_active;
+  int32_t* block_hist; // [prep_slices(N)][k_max + 1] workspace of the ordering pass
   int* flag;
   int tempered;        // 1: K=0 value times beta_i, 0: untempered
   int include_k0;      // 1: K = 0 particles stay in the work list (birth pass)
@@ -148,6 +149,8 @@ hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st);
 
 // Host launchers (defined in smcx_kernels.hip / smcx_plain.hip).
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+// Number of particle slices of the ordering pass (its histogram workspace rows).
+int64_t prep_slices(int64_t N);
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);

@@ -12,14 +12,17 @@
 //    and a fraction f, so x = (s - n) - f is formed exactly up to one FP32
 //    rounding of x itself; the exponent uses one pre-scaled coefficient so
 //    the Gaussian is a single hardware exp2.
+//    Pulses are truncated where |t - t0| >= sqrt(128 ln 2) w: there the
+//    template is below 2^-64 of its peak, far under the FP32 resolution of the
+//    residual and the FP64 resolution of the sums it feeds. Each component
+//    carries the sample range of its support, and the tile loops skip groups
+//    of 64-sample blocks outside it with wave-uniform branches.
 //  * Sinusoids: the phase in cycles is a quadratic in the sample index. Per
-//    component and lane it is re-expanded around the lane's first sample,
-//    the constant term is reduced modulo one cycle in FP64, and the
-//    per-sample phase is evaluated in FP64 on top of the magic constant
-//    1.5 * 2^20, whose unit in the last place is 2^-32 cycles: the low 32 bits
-//    of the FP64 result are then the phase modulo one cycle as a signed
-//    fixed-point number, which is converted to FP32 revolutions for the
-//    hardware sin/cos (they take revolutions).
+//    component, lane and tile its value and its per-64-sample step are
+//    reduced modulo one cycle in FP64 and carried as 32-bit fixed point
+//    (units of 2^-32 cycles, so wrap-around is the modulo); per sample the
+//    phase is one integer add plus a small FP32 chirp correction, converted
+//    to FP32 revolutions for the hardware sin/cos (they take revolutions).
 //  * Sums of r^2 and the birth/death inner products are accumulated per lane
 //    in FP64 (products of FP32 values are exact in FP64); gradient sums are
 //    FP32 per lane per tile, reduced across the wave in FP32 and accumulated
@@ -30,11 +33,18 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace smcx {
 namespace {
 
 // sqrt(log2(e) / 2): exp(-x^2 / (2 w^2)) = exp2(-(a x)^2) with a = this / w.
 constexpr double kSqrtHalfLog2e = 0.84932180028801904272150283410289;
+// Pulse truncation radius in units of z = a x: z^2 = 64 gives exp2(-z^2) = 2^-64,
+// i.e. |t - t0| = sqrt(128 ln 2) w.
+constexpr double kPulseCutZ = 8.0;
+// Bound on sample indices of a pulse support (the data length is at most 2^22).
+constexpr double kSampleBound = 16777216.0;
 // 1.5 * 2^20: doubles in [2^20, 2^21) have a unit in the last place of 2^-32.
 constexpr double kPhaseMagic = 1572864.0;
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -91,6 +101,12 @@ __device__ __forceinline__ double lane63_d(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo);
+}
+
 // ---------------------------------------------------------------- models
 // Gaussian pulse h = A exp(-(t - t0)^2 / (2 w^2)).
 struct PulseC {
@@ -98,8 +114,10 @@ struct PulseC {
   float a;   // sqrt(log2 e / 2) / (w / dt)
   float fa;  // (fractional part of the centre) * a
   float A;
+  int lo, hi;  // first and last sample of the truncation support
+  int pad0, pad1;
 };
-static_assert(sizeof(PulseC) == 16, "pulse constants are one float4");
+static_assert(sizeof(PulseC) == 32, "pulse constants are 32 bytes");
 
 __device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, double dt) {
   const double A = th[0], t0 = th[1], w = th[2];
@@ -113,7 +131,40 @@ __device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, d
   r.a = (float)a;
   r.fa = (float)(f * a);
   r.A = (float)A;
+  // Support |s - c| <= 8 / |a|. Non-finite parameters keep the whole range so
+  // that a NaN reaches the particle's outputs.
+  double lo = -kSampleBound, hi = kSampleBound;
+  const double aa = fabs(a);
+  if (isfinite(A) && isfinite(c) && isfinite(aa) && aa > 0.0) {
+    const double hw = kPulseCutZ / aa;
+    lo = fmin(fmax(ceil(c - hw), -kSampleBound), kSampleBound);
+    hi = fmin(fmax(floor(c + hw), -kSampleBound), kSampleBound);
+  }
+  r.lo = (int)lo;
+  r.hi = (int)hi;
+  r.pad0 = r.pad1 = 0;
   return r;
+}
+
+// Blocks of 64 samples are skipped in groups of kPulseGroup.
+constexpr int kPulseGroup = 2;
+
+// Bit g set when block group g of the tile starting at sample `tile` meets the
+// support (wave-uniform). 32-bit masks where they suffice: they test in one
+// scalar instruction.
+template <int S>
+using GroupMask = typename std::conditional<(S / kPulseGroup > 32), unsigned long long,
+                                            unsigned int>::type;
+
+template <int S>
+__device__ __forceinline__ GroupMask<S> pulse_groups(const PulseC& c, int tile) {
+  static_assert(S / kPulseGroup <= 64, "one bit per block group");
+  // arithmetic shift: floor division by 64
+  const int jlo = __builtin_amdgcn_readfirstlane(max((c.lo - tile) >> 6, 0));
+  const int jhi = __builtin_amdgcn_readfirstlane(min(((c.hi - tile) >> 6) + 1, S));
+  if (jlo >= jhi) return 0;
+  const int glo = jlo / kPulseGroup, n = (jhi - 1) / kPulseGroup - glo + 1;
+  return (GroupMask<S>)((n >= 64 ? ~0ull : ((1ull << n) - 1ull)) << glo);
 }
 
 // Chirping sinusoid h = A sin(2 pi (a0 + a1 s + a2 s^2)) in sample index s.
@@ -181,40 +232,63 @@ __device__ __forceinline__ float gb_rev(const GbTile& t, unsigned int F) {
 }
 
 // ---------------------------------------------------------------- tile bodies
-// Pulse forward, two samples per step so that each exp has independent work
-// behind it before its result is consumed.
+// Pulse forward over the tile's block groups that meet the support; within a
+// group the blocks are independent, so each exp has other work behind it.
+template <int S, int J>
+__device__ __forceinline__ void pulse_fwd_one(const PulseC& c, float base, float (&r)[S]) {
+  const float d = base + (float)(64 * J);
+  const float z = __builtin_fmaf(d, c.a, -c.fa);
+  r[J] = __builtin_fmaf(-c.A, __builtin_amdgcn_exp2f(-(z * z)), r[J]);
+}
+
+template <int S, int J, int G>
+__device__ __forceinline__ void pulse_fwd_group(const PulseC& c, float base, float (&r)[S]) {
+  if constexpr (G > 0 && J < S) {
+    pulse_fwd_one<S, J>(c, base, r);
+    pulse_fwd_group<S, J + 1, G - 1>(c, base, r);
+  }
+}
+
 template <int S, int J = 0>
-__device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S]) {
-  if constexpr (J + 1 < S) {
-    const float d0 = base + (float)(64 * J);
-    const float d1 = base + (float)(64 * (J + 1));
-    const float z0 = __builtin_fmaf(d0, c.a, -c.fa);
-    const float z1 = __builtin_fmaf(d1, c.a, -c.fa);
-    const float e0 = __builtin_amdgcn_exp2f(-(z0 * z0));
-    const float e1 = __builtin_amdgcn_exp2f(-(z1 * z1));
-    r[J] = __builtin_fmaf(-c.A, e0, r[J]);
-    r[J + 1] = __builtin_fmaf(-c.A, e1, r[J + 1]);
-    pulse_fwd_j<S, J + 2>(c, base, r);
-  } else if constexpr (J < S) {
-    const float d0 = base + (float)(64 * J);
-    const float z0 = __builtin_fmaf(d0, c.a, -c.fa);
-    r[J] = __builtin_fmaf(-c.A, __builtin_amdgcn_exp2f(-(z0 * z0)), r[J]);
+__device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S],
+                                            GroupMask<S> groups) {
+  if constexpr (J < S) {
+    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u))
+      pulse_fwd_group<S, J, kPulseGroup>(c, base, r);
+    pulse_fwd_j<S, J + kPulseGroup>(c, base, r, groups);
+  }
+}
+
+template <int J>
+__device__ __forceinline__ void pulse_adj_one(const PulseC& c, float base, float rj, float& s0,
+                                              float& s1, float& s2) {
+  const float dj = base + (float)(64 * J);
+  const float z = __builtin_fmaf(dj, c.a, -c.fa);
+  const float nzz = -(z * z);  // the exp argument doubles as the width weight
+  const float e = __builtin_amdgcn_exp2f(nzz);
+  const float re = rj * e;
+  s0 += re;
+  s1 = __builtin_fmaf(re, z, s1);
+  s2 = __builtin_fmaf(re, nzz, s2);
+}
+
+template <int S, int J, int G>
+__device__ __forceinline__ void pulse_adj_group(const PulseC& c, float base, const float (&r)[S],
+                                                float& s0, float& s1, float& s2) {
+  if constexpr (G > 0 && J < S) {
+    pulse_adj_one<J>(c, base, r[J], s0, s1, s2);
+    pulse_adj_group<S, J + 1, G - 1>(c, base, r, s0, s1, s2);
   }
 }
 
 template <int S, int J = 0>
 __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const float (&r)[S],
-                                            float& s0, float& s1, float& s2) {
+                                            float& s0, float& s1, float& s2,
+                                            GroupMask<S> groups) {
   if constexpr (J < S) {
-    const float dj = base + (float)(64 * J);
-    const float z = __builtin_fmaf(dj, c.a, -c.fa);
-    const float e = __builtin_amdgcn_exp2f(-(z * z));
-    const float re = r[J] * e;
-    s0 += re;
-    const float rz = re * z;
-    s1 += rz;
-    s2 = __builtin_fmaf(rz, z, s2);
-    pulse_adj_j<S, J + 1>(c, base, r, s0, s1, s2);
+    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u))
+      pulse_adj_group<S, J, kPulseGroup>(c, base, r, s0, s1, s2);
+    pulse_adj_j<S, J + kPulseGroup>(c, base, r, s0, s1, s2, groups);
   }
 }
 
@@ -282,7 +356,9 @@ struct Model<SMCX_PULSE> {
     const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
-      pulse_fwd_j<S>(c, sf0 - c.nf, r);
+      const GroupMask<S> groups = pulse_groups<S>(c, (int)tile);
+      if (groups == 0) continue;
+      pulse_fwd_j<S>(c, sf0 - c.nf, r, groups);
     }
   }
   template <int S>
@@ -291,8 +367,10 @@ struct Model<SMCX_PULSE> {
     const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
+      const GroupMask<S> groups = pulse_groups<S>(c, (int)tile);
+      if (groups == 0) continue;  // the component adds nothing on this tile
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-      pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2);
+      pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2, groups);
       s0 = wave_sum_f(s0);
       s1 = wave_sum_f(s1);
       s2 = wave_sum_f(s2);
@@ -327,14 +405,14 @@ struct Model<SMCX_PULSE> {
     }
   }
   // g = beta/sigma^2 * sum_s r_s dh/dtheta from the accumulated sums
-  // S0 = sum r e, S1 = sum r e z, S2 = sum r e z^2 with z = a x (x in samples).
+  // S0 = sum r e, S1 = sum r e z, S2 = -sum r e z^2 with z = a x (x in samples).
   __device__ static void scale(const double* th, const double* sums, double bs, const PopArgs& a,
                                double* g) {
     const double A = th[0], w = th[2];
     const double af = (double)pulse_make(th, a.t_start, a.dt).a;
     g[0] = bs * sums[0];
     g[1] = bs * (A * a.dt / (af * w * w)) * sums[1];
-    g[2] = bs * (A * a.dt * a.dt / (af * af * w * w * w)) * sums[2];
+    g[2] = -bs * (A * a.dt * a.dt / (af * af * w * w * w)) * sums[2];
   }
 };
 
@@ -502,32 +580,31 @@ __device__ __forceinline__ bool combine_item(const PopArgs& a, int64_t rank, boo
 }
 
 // ---------------------------------------------------------------- prep
-__global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a) {
-  extern __shared__ int sh[];
-  int* hist = sh;                  // [k_max + 1]
-  int* start = sh + (a.k_max + 1); // [k_max + 1]
-  __shared__ int bad_global;
-  for (int k = threadIdx.x; k <= a.k_max; k += blockDim.x) hist[k] = 0;
-  if (threadIdx.x == 0) {
-    int bad = 0;
-    if (a.N > 0 && (a.offsets[0] != 0 || a.offsets[a.N] != a.M)) bad = 1;
-    bad_global = bad;
-    if (bad) atomicOr(a.flag, a.offsets[0] != 0 ? kFlagOffsets : kFlagMMax);
-  }
-  __syncthreads();
-  const double nan = __builtin_nan("");
-  for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x) {
-    const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
-    const int64_t K = o1 - o0;
-    int bits = 0;
-    if (bad_global) bits |= kFlagOffsets;
-    if (K < 0) bits |= kFlagOffsets;
-    if (K > a.k_max) bits |= kFlagKMax;
-    if (a.dlogl_death && a.death_idx) {
-      const int32_t j = a.death_idx[i];
-      if (j < -1 || (int64_t)j >= K) bits |= kFlagDeath;
-    }
-    if (bits) {
+// Ordering pass: validates every particle, settles the ones without work (K = 0
+// outside the birth pass, invalid ones) and lists the rest longest-K first
+// (a counting sort). Two launches over slices of kPrepSlice particles: the
+// count pass writes one K histogram per slice, the scatter pass combines them
+// into list positions and places its slice's particles. Each thread loads all
+// of its particles of a slice before it uses any, so a pass pays about one
+// memory latency. Particles of equal K are listed in no particular order
+// (results do not depend on it).
+constexpr int kPrepBlock = 256;
+constexpr int kPrepUnroll = 8;
+constexpr int kPrepSlice = kPrepBlock * kPrepUnroll;
+
+// Work-list key of particle i: K, or -1 when it needs no pass. With `settle`,
+// also writes the outputs of invalid and K = 0 particles.
+__device__ __forceinline__ int prep_key(const PrepArgs& a, int64_t i, int64_t o0, int64_t o1,
+                                        int32_t dj, double beta_i, int bad_global, bool settle) {
+  const int64_t K = o1 - o0;
+  int bits = 0;
+  if (bad_global) bits |= kFlagOffsets;
+  if (K < 0) bits |= kFlagOffsets;
+  if (K > a.k_max) bits |= kFlagKMax;
+  if (a.dlogl_death && a.death_idx && (dj < -1 || (int64_t)dj >= K)) bits |= kFlagDeath;
+  if (bits) {
+    if (settle) {
+      const double nan = __builtin_nan("");
       if (!bad_global) atomicOr(a.flag, bits);
       if (a.logl) a.logl[i] = nan;
       if (a.dlogl_birth) a.dlogl_birth[i] = nan;
@@ -536,37 +613,138 @@ __global__ __launch_bounds__(1024) void prep_kernel(PrepArgs a) {
         for (int64_t m = o0 < 0 ? 0 : o0; m < o1 && m < a.M; ++m)
           for (int p = 0; p < a.P; ++p) a.grad[m * a.P + p] = nan;
       }
-      continue;
     }
-    if (K == 0 && !a.include_k0) {
-      const double b = (a.tempered && a.beta) ? a.beta[i] : 1.0;
-      if (a.logl) a.logl[i] = b * a.k0_value;
-      continue;
-    }
-    atomicAdd(&hist[K], 1);
+    return -1;
   }
-  __syncthreads();
+  if (K == 0 && !a.include_k0) {
+    if (settle && a.logl) a.logl[i] = beta_i * a.k0_value;
+    return -1;
+  }
+  return (int)K;
+}
+
+// Runs fn(i, key) for every particle of this block's slice. The loads are
+// unconditional, on a clamped index, so that they are all in flight together.
+template <bool SETTLE, bool DEATH, typename F>
+__device__ __forceinline__ void prep_slice(const PrepArgs& a, int bad_global, F fn) {
+  const int64_t base = (int64_t)blockIdx.x * kPrepSlice + threadIdx.x;
+  int64_t o0[kPrepUnroll], o1[kPrepUnroll];
+  int32_t dj[kPrepUnroll];
+  double bt[kPrepUnroll];
+#pragma unroll
+  for (int u = 0; u < kPrepUnroll; ++u) {
+    int64_t i = base + (int64_t)u * kPrepBlock;
+    i = i < a.N ? i : a.N - 1;
+    o0[u] = a.offsets[i];
+    o1[u] = a.offsets[i + 1];
+    dj[u] = DEATH ? a.death_idx[i] : 0;
+    bt[u] = 1.0;
+  }
+  // the K = 0 outputs are tempered: fetch beta with the rest
+  if (SETTLE && a.tempered && a.beta && a.logl) {
+#pragma unroll
+    for (int u = 0; u < kPrepUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * kPrepBlock;
+      bt[u] = a.beta[i < a.N ? i : a.N - 1];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kPrepUnroll; ++u) {
+    const int64_t i = base + (int64_t)u * kPrepBlock;
+    if (i < a.N) fn(i, prep_key(a, i, o0[u], o1[u], dj[u], bt[u], bad_global, SETTLE));
+  }
+}
+
+template <bool SETTLE, typename F>
+__device__ __forceinline__ void prep_slice(const PrepArgs& a, int bad_global, F fn) {
+  if (a.dlogl_death && a.death_idx)
+    prep_slice<SETTLE, true>(a, bad_global, fn);
+  else
+    prep_slice<SETTLE, false>(a, bad_global, fn);
+}
+
+// Whether offsets[0] != 0 or offsets[N] != M (every particle is then invalid).
+__device__ __forceinline__ int prep_bad_global(const PrepArgs& a, bool raise) {
+  __shared__ int bad_global;
   if (threadIdx.x == 0) {
-    int pos = 0;
-    for (int k = a.k_max; k >= 0; --k) {
-      start[k] = pos;
-      pos += hist[k];
-      hist[k] = 0;
-    }
-    *a.n_active = pos;
+    int bad = 0;
+    if (a.N > 0 && (a.offsets[0] != 0 || a.offsets[a.N] != a.M)) bad = 1;
+    bad_global = bad;
+    if (bad && raise) atomicOr(a.flag, a.offsets[0] != 0 ? kFlagOffsets : kFlagMMax);
   }
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x) {
-    const int64_t K = a.offsets[i + 1] - a.offsets[i];
-    if (bad_global || K < 0 || K > a.k_max) continue;
-    if (a.dlogl_death && a.death_idx) {
-      const int32_t j = a.death_idx[i];
-      if (j < -1 || (int64_t)j >= K) continue;
+  return bad_global;
+}
+
+__global__ __launch_bounds__(kPrepBlock) void prep_count_kernel(PrepArgs a) {
+  extern __shared__ int hist[];  // [k_max + 1]
+  const int nk = a.k_max + 1;
+  for (int k = threadIdx.x; k < nk; k += kPrepBlock) hist[k] = 0;
+  const int bg = prep_bad_global(a, blockIdx.x == 0);
+  prep_slice<true>(a, bg, [&](int64_t, int key) {
+    if (key >= 0) atomicAdd(&hist[key], 1);
+  });
+  __syncthreads();
+  for (int k = threadIdx.x; k < nk; k += kPrepBlock) a.block_hist[(size_t)blockIdx.x * nk + k] = hist[k];
+}
+
+__global__ __launch_bounds__(kPrepBlock) void prep_scatter_kernel(PrepArgs a) {
+  extern __shared__ int sh[];
+  const int nk = a.k_max + 1;  // at most 4 * kPrepBlock
+  int* tot = sh;               // [nk] particles with K = k, all slices
+  int* pos = sh + nk;          // [nk] particles with K = k in earlier slices, then list positions
+  __shared__ int scan[kPrepBlock];
+  const int tid = threadIdx.x;
+  for (int k = tid; k < nk; k += kPrepBlock) tot[k] = pos[k] = 0;
+  const int bg = prep_bad_global(a, false);
+  // combine the slice histograms (loads batched four at a time)
+  const int nh = (int)gridDim.x * nk;
+  for (int base = 0; base < nh; base += 4 * kPrepBlock) {
+    int c[4], idx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      idx[q] = base + q * kPrepBlock + tid;
+      c[q] = a.block_hist[idx[q] < nh ? idx[q] : nh - 1];
     }
-    if (K == 0 && !a.include_k0) continue;
-    const int slot = start[K] + atomicAdd(&hist[K], 1);
-    a.order[slot] = (int32_t)i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (idx[q] < nh && c[q]) {
+        const int b = idx[q] / nk, k = idx[q] - b * nk;
+        atomicAdd(&tot[k], c[q]);
+        if (b < (int)blockIdx.x) atomicAdd(&pos[k], c[q]);
+      }
+    }
   }
+  __syncthreads();
+  // exclusive prefix of tot over K in descending order: 4 entries per thread,
+  // then a Hillis-Steele scan over the thread sums
+  int loc[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 4 * tid + q;  // j-th K in descending order
+    loc[q] = j < nk ? tot[a.k_max - j] : 0;
+    sum += loc[q];
+  }
+  scan[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kPrepBlock; off <<= 1) {
+    const int v = tid >= off ? scan[tid - off] : 0;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  int run = scan[tid] - sum;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 4 * tid + q;
+    if (j < nk) pos[a.k_max - j] += run;
+    run += loc[q];
+  }
+  if (blockIdx.x == 0 && tid == kPrepBlock - 1) *a.n_active = scan[kPrepBlock - 1];
+  __syncthreads();
+  prep_slice<false>(a, bg, [&](int64_t i, int key) {
+    if (key >= 0) a.order[atomicAdd(&pos[key], 1)] = (int32_t)i;
+  });
 }
 
 // ---------------------------------------------------------------- population kernel
@@ -594,10 +772,11 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
   const int64_t item = (int64_t)blockIdx.x * wpb + wid;
   Item it;
   if (!decode_item(a, item, lane, P, false, it)) return;
-  const int c = it.c;
-  const int i = it.i;
-  const int64_t m0 = it.m0;
-  const int K = it.K;
+  // one wave per item: make the item's fields scalar
+  const int c = __builtin_amdgcn_readfirstlane(it.c);
+  const int i = __builtin_amdgcn_readfirstlane(it.i);
+  const int64_t m0 = uniform_i64(it.m0);
+  const int K = __builtin_amdgcn_readfirstlane(it.K);
   if (a.active && !a.active[i]) return;
 
   unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
@@ -991,10 +1170,18 @@ size_t pop_lds_bytes_per_wave(int model, int32_t k_max, bool grad) {
 }
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
-  const size_t lds = 2 * (size_t)(a.k_max + 1) * sizeof(int);
-  hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(1024), lds, st, a);
+  if (a.k_max + 1 > 4 * kPrepBlock) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)prep_slices(a.N));
+  hipLaunchKernelGGL(prep_count_kernel, grid, dim3(kPrepBlock), (size_t)(a.k_max + 1) * sizeof(int),
+                     st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prep_scatter_kernel, grid, dim3(kPrepBlock),
+                     2 * (size_t)(a.k_max + 1) * sizeof(int), st, a);
   return hipGetLastError();
 }
+
+int64_t prep_slices(int64_t N) { return N > 0 ? (N + kPrepSlice - 1) / kPrepSlice : 1; }
 
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
   return model == SMCX_PULSE ? launch_pop_model<SMCX_PULSE, false>(t, a, st)

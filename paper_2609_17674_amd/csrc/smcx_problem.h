@@ -28,6 +28,7 @@ struct smcx_problem {
   int max_nch_grad = 0;  // capacity of part_g
   int32_t* order = nullptr;
   int32_t* n_active = nullptr;
+  int32_t* prep_hist = nullptr;  // [prep_slices(n_max)][k_max + 1]
   int* flag = nullptr;
   double* part = nullptr;   // [max_nch][n_max][4]
   double* part_g = nullptr; // [nch_grad][m_max][P]

@@ -113,6 +113,72 @@ def test_k0_and_empty(lib, orc):
     assert l0.numel() == 0 and g0.numel() == 0
 
 
+def test_pulse_truncation_support(lib, orc):
+    """Pulses are truncated where |t - t0| >= sqrt(128 ln 2) w (template below
+    2^-64 of its peak). Components straddling the data edges, narrower than one
+    64-sample block, just outside the data and far outside it, under several
+    tilings: every particle with some support inside the data is at parity, and
+    one whose components all lie outside gets a negligible gradient, as the
+    oracle does."""
+    T = 9000
+    w = wl.make_config("pulse_small", N=1, T=T)
+    cut = np.sqrt(128.0 * np.log(2.0))
+    rng = np.random.default_rng(77)
+
+    def component(kind):
+        wd = rng.uniform(0.002, 0.05)
+        if kind == 0:    # straddles an edge
+            t0 = rng.choice([0.0, 1.0]) + rng.uniform(-0.9, 0.9) * cut * wd
+        elif kind == 1:  # narrower than one block
+            wd = rng.uniform(0.0005, 0.001)
+            t0 = rng.uniform(0.0, 1.0)
+        elif kind == 2:  # support ends just outside the data
+            t0 = 1.0 + 1.01 * cut * wd if rng.random() < 0.5 else -1.01 * cut * wd
+        else:            # far outside
+            t0 = rng.choice([-0.7, 1.6])
+        return [rng.uniform(2.0, 6.0), t0, wd]
+
+    thetas, counts, outside = [], [], []
+    for i in range(48):
+        k = int(rng.integers(1, 7))
+        if i % 12 == 0:  # every component outside the data
+            kinds = [int(rng.integers(2, 4)) for _ in range(k)]
+        else:            # at least one component with support inside
+            kinds = [int(rng.integers(0, 2))] + [int(rng.integers(0, 4)) for _ in range(k - 1)]
+        thetas += [component(kd) for kd in kinds]
+        counts.append(k)
+        outside.append(all(kd >= 2 for kd in kinds))
+    w.offsets = wl.counts_to_offsets(np.array(counts, dtype=np.int64))
+    w.theta = np.array(thetas)
+    w.beta = rng.uniform(0.2, 1.0, len(counts))
+    outside = np.array(outside)
+    assert outside.sum() >= 4 and (~outside).sum() >= 30
+    say("pulse_truncation", "N", w.N, "M", w.M, "outside", int(outside.sum()))
+    s = Setup(lib, w, k_max=8)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    inside = np.nonzero(~outside)[0]
+    rows_in = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in inside])
+    rows_out = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1])
+                               for i in np.nonzero(outside)[0]])
+    sub_off = wl.counts_to_offsets(np.diff(w.offsets)[inside])
+    for S, chunk, so in [(8, 4096, 1), (16, 4096, 0), (32, 8192, 1), (64, 4096, 1), (64, 12288, 0)]:
+        say("pulse_truncation tiling", S, chunk, so)
+        s.prob.set_tiling(lib.KIND_GRAD, S, chunk, so)
+        s.prob.set_tiling(lib.KIND_LOGL, S, chunk, so)
+        logl, grad = run_grad(lib, s)
+        l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+        torch.cuda.synchronize()
+        pm.assert_logl(logl, ref_l)
+        pm.assert_logl(l2.cpu().numpy(), ref_l)
+        pm.assert_grad(w.model, sub_off, w.theta[rows_in], grad[rows_in], ref_g[rows_in], w.T, w.dt)
+        # components outside the data: the exact gradient is negligible, and
+        # the kernel's is zero or made of the sub-2^-64 values of a block
+        # that straddles the data edge
+        scale = pm.natural_scale(w.model, w.theta[rows_out], w.T, w.dt)
+        assert np.all(np.abs(ref_g[rows_out] * scale) < 1e-12)
+        assert np.all(np.abs(grad[rows_out] * scale) < 1e-12)
+
+
 def test_batch_independence_and_determinism(lib, orc):
     """A particle's result is bitwise the same in any batch, order and run."""
     w = wl.make_config("pulse_batch", N=400, T=4096)
@@ -162,6 +228,45 @@ def test_device_flag_for_k_above_kmax(lib, orc):
     ref = orc.logl(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
     pm.assert_logl(ln[~big], ref[~big])
     s.prob.device_status()  # cleared
+
+
+def test_ordering_pass_across_slices(lib, orc):
+    """The ordering pass works on slices of 2048 particles: a population of
+    several slices with a ragged last one, K = 0 particles, particles above
+    k_max and bad death indices in every slice gives the same bits in sorted
+    and index order, the oracle's values for valid particles and NaN for the
+    invalid ones."""
+    w = wl.make_config("pulse_small", N=5000, T=300, k_lo=0, k_hi=7, rj=True)
+    say("ordering_slices", "N", w.N)
+    s = Setup(lib, w, k_max=6)
+    big = w.K > 6
+    assert big[:2048].any() and big[2048:4096].any() and big[4096:].any()
+    ref = orc.logl(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    di = w.extra["death_idx"].copy()
+    di[::997] = 50  # out of range wherever K <= 50
+    bad_death = (di < -1) | (di >= w.K)
+    outs = []
+    for so in (1, 0):
+        s.prob.set_tiling(lib.KIND_GRAD, 16, 1024, so)
+        s.prob.set_tiling(lib.KIND_LOGL, 16, 1024, so)
+        s.prob.set_tiling(lib.KIND_DELTA, 8, 512, so)
+        logl, grad = lib.logl_grad_batch(s.prob, s.off, s.th, s.beta)
+        l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+        db, dd = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta,
+                                            pm.to_dev(w.extra["theta_birth"]), pm.to_dev(di))
+        torch.cuda.synchronize()
+        with pytest.raises(lib.SmcxError):
+            s.prob.device_status()
+        outs.append([x.cpu().numpy() for x in (logl, grad, l2, db, dd)])
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y, equal_nan=True)
+    logl, grad, l2, db, dd = outs[0]
+    assert np.all(np.isnan(logl[big])) and np.all(np.isnan(l2[big]))
+    pm.assert_logl(logl[~big], ref[~big])
+    pm.assert_logl(l2[~big], ref[~big])
+    bad = big | bad_death
+    assert np.all(np.isnan(db[bad])) and np.all(np.isnan(dd[bad]))
+    assert np.all(np.isfinite(db[~bad]))
 
 
 def test_host_argument_errors(lib):
