@@ -70,6 +70,10 @@ def _load():
         lib.oracle_logl_grad.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P]
         lib.oracle_delta_logl_birth_death.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, P, P]
         lib.oracle_reweight_extend.argtypes = [I, P, D, D, D, I64, I64, I64, P, P, D, P, P, P, P, P]
+        lib.oracle_next_beta.argtypes = [I64, P, P, D, D, P, P, P]
+        lib.oracle_resample_systematic.argtypes = [I, I64, P, P, P, D, I64, P, P, P]
+        lib.oracle_rj_apply.argtypes = [I, I64, P, P, P, P, P, P, P, P, ctypes.c_int32,
+                                        ctypes.c_int32, D, I64, P, P, P]
         lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
         lib.oracle_nuts_transition.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P, P, P, P,
                                                P, P, P, P, P, P]
@@ -193,3 +197,51 @@ def nuts_transition(model, d, t_start, dt, sigma, offsets, beta, eps, max_depth,
                                           _p(dirs), _p(u_leaf), _p(u_tree), _p(q), _p(logl), _p(grad),
                                           _p(depth), _p(steps), _p(status)), "nuts_transition")
     return q, logl, grad, depth, steps, status
+
+
+def next_beta(logl, beta_prev, alpha, logw_prev=None):
+    """ESS-bisection choice of the next inverse temperature; returns
+    (logw, w_norm, scalars = [beta, ESS, logZ increment, ESS evaluations])."""
+    logl, logw_prev = _f64(logl), _f64(logw_prev)
+    N = logl.shape[0]
+    logw, w, scal = np.empty(N), np.empty(N), np.empty(4)
+    _check(_load().oracle_next_beta(N, _p(logl), _p(logw_prev), beta_prev, alpha, _p(logw), _p(w),
+                                    _p(scal)), "next_beta")
+    return logw, w, scal
+
+
+def resample_systematic(model, offsets, theta, w_norm, u, m_cap=None):
+    """Systematic resampling; returns (ancestors, offsets_out, theta_out)."""
+    offsets, theta, w_norm = _i64(offsets), _f64(theta), _f64(w_norm)
+    N = offsets.shape[0] - 1
+    P = n_params(model)
+    if m_cap is None:
+        m_cap = int(np.diff(offsets).max(initial=0)) * N
+    anc = np.empty(N, dtype=np.int32)
+    off = np.empty(N + 1, dtype=np.int64)
+    th = np.empty((max(m_cap, 1), P))
+    _check(_load().oracle_resample_systematic(model, N, _p(offsets), _p(theta), _p(w_norm), u, m_cap,
+                                              _p(anc), _p(off), _p(th)), "resample_systematic")
+    return anc, off, th[:off[-1]].copy()
+
+
+def rj_apply(model, offsets, theta, move, theta_birth, death_idx, dlogl_birth, dlogl_death, log_u,
+             k_lo, k_hi, log_pd_over_pb=0.0, m_cap=None):
+    """Accept/reject birth and death moves; returns (accepted, offsets_out, theta_out)."""
+    offsets, theta = _i64(offsets), _f64(theta)
+    theta_birth, dlogl_birth, dlogl_death, log_u = (_f64(x) for x in (theta_birth, dlogl_birth,
+                                                                       dlogl_death, log_u))
+    move = np.ascontiguousarray(move, dtype=np.int8)
+    death_idx = None if death_idx is None else np.ascontiguousarray(death_idx, dtype=np.int32)
+    N = offsets.shape[0] - 1
+    P = n_params(model)
+    if m_cap is None:
+        m_cap = int(offsets[-1]) + N
+    acc = np.empty(N, dtype=np.int8)
+    off = np.empty(N + 1, dtype=np.int64)
+    th = np.empty((max(m_cap, 1), P))
+    _check(_load().oracle_rj_apply(model, N, _p(offsets), _p(theta), _p(move), _p(theta_birth),
+                                   _p(death_idx), _p(dlogl_birth), _p(dlogl_death), _p(log_u),
+                                   int(k_lo), int(k_hi), float(log_pd_over_pb), m_cap, _p(off),
+                                   _p(th), _p(acc)), "rj_apply")
+    return acc, off, th[:off[-1]].copy()

@@ -561,3 +561,204 @@ int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------ SMC steps
+ * The steps of one SMC iteration around the likelihood (Sec. "Sequential
+ * Monte Carlo" and Sec. "Algorithm and implementation"): choice of the next
+ * inverse temperature, reweighting, resampling, and the accept/reject of the
+ * birth and death moves of the mutation kernel (eq. kernel_mixture,
+ * eq. rj_acceptance). */
+
+/* ESS of w_i = exp(logw_prev_i + db * logl_i) (eq. ess), by a max-shifted sum.
+ * Also returns the shift m and s1 = sum_i exp(log w_i - m). */
+static double ess_at(int64_t N, const double* logl, const double* logw_prev, double db,
+                     double* m_out, double* s1_out) {
+  double m = -INFINITY;
+  for (int64_t i = 0; i < N; ++i) {
+    double lw = (logw_prev ? logw_prev[i] : 0.0) + db * logl[i];
+    if (lw > m) m = lw;
+  }
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    double lw = (logw_prev ? logw_prev[i] : 0.0) + db * logl[i];
+    double e = exp(lw - m);
+    s1 += e;
+    s2 += e * e;
+  }
+  if (m_out) *m_out = m;
+  if (s1_out) *s1_out = s1;
+  return s1 * s1 / s2;
+}
+
+/* Next inverse temperature of the prior bridge (eq. prior_bridge) by the ESS
+ * condition (eq. ess_target), for the incremental weights of
+ * eq. incremental_weight: log w_i = logw_prev_i + (beta - beta_prev) logl_i with
+ * untempered log-likelihoods logl (logw_prev NULL: uniform previous weights).
+ *   beta = 1 if ESS(1) >= alpha N; otherwise bisection on [beta_prev, 1]: the
+ *   bracket is halved (at most 60 times, and no further once its midpoint is
+ *   no longer strictly inside), keeping its lower end where ESS >= alpha N;
+ *   the result is the lower end, or the upper end if the lower end never
+ *   moved (ESS(beta_prev) < alpha N, possible only with uneven logw_prev).
+ * Outputs log w_i, normalised weights w_norm_i, and
+ * scalars = {beta, ESS(beta), log Z_t/Z_{t-1}, number of ESS evaluations in
+ * the bisection}, the evidence increment being log sum exp(log w) minus
+ * log sum exp(logw_prev) (log N for uniform previous weights). */
+int oracle_next_beta(int64_t N, const double* logl, const double* logw_prev, double beta_prev,
+                     double alpha, double* logw, double* w_norm, double* scalars) {
+  if (N < 1 || !logl || !logw || !w_norm || !scalars || !(beta_prev >= 0.0 && beta_prev <= 1.0) ||
+      !(alpha > 0.0 && alpha <= 1.0))
+    return OR_EINVAL;
+  const double target = alpha * (double)N;
+  double beta = 1.0;
+  int evals = 0;
+  if (!(ess_at(N, logl, logw_prev, 1.0 - beta_prev, NULL, NULL) >= target)) {
+    double lo = beta_prev, hi = 1.0;
+    int moved = 0;
+    for (int it = 0; it < 60; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      double e = ess_at(N, logl, logw_prev, mid - beta_prev, NULL, NULL);
+      ++evals;
+      if (e >= target) {
+        lo = mid;
+        moved = 1;
+      } else {
+        hi = mid;
+      }
+    }
+    beta = moved ? lo : hi;
+  }
+  const double db = beta - beta_prev;
+  double m, s1;
+  const double ess = ess_at(N, logl, logw_prev, db, &m, &s1);
+  for (int64_t i = 0; i < N; ++i) {
+    logw[i] = (logw_prev ? logw_prev[i] : 0.0) + db * logl[i];
+    w_norm[i] = exp(logw[i] - m) / s1;
+  }
+  double lse_prev;
+  if (logw_prev) {
+    double mp = -INFINITY, sp = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+      if (logw_prev[i] > mp) mp = logw_prev[i];
+    for (int64_t i = 0; i < N; ++i) sp += exp(logw_prev[i] - mp);
+    lse_prev = mp + log(sp);
+  } else {
+    lse_prev = log((double)N);
+  }
+  scalars[0] = beta;
+  scalars[1] = ess;
+  scalars[2] = m + log(s1) - lse_prev;
+  scalars[3] = (double)evals;
+  return OR_OK;
+}
+
+/* Systematic resampling (the scheme is a reading: the paper resamples by the
+ * normalised weights without naming one). With weights carried as integers
+ * c_i = round(w_norm_i * 2^40) (0 for non-positive or NaN weights), inclusive
+ * prefix sums C_i and their total C, offspring j = 0..N-1 takes position
+ * U_j = floor(((j + u) * C) / N) (in double precision, evaluated in that
+ * order; capped at C - 1) and the ancestor a_j = min{i : C_i > U_j}.
+ * The new population is the ancestors' rows in CSR form: offsets_out[N+1],
+ * theta_out[offsets_out[N]][P], which must not exceed m_cap rows. */
+int oracle_resample_systematic(int model, int64_t N, const int64_t* offsets, const double* theta,
+                               const double* w_norm, double u, int64_t m_cap, int32_t* ancestors,
+                               int64_t* offsets_out, double* theta_out) {
+  if (check_population(model, N, offsets, theta) != OR_OK || N < 1 || !w_norm || !ancestors ||
+      !offsets_out || !(u >= 0.0 && u < 1.0))
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+  int64_t* C = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  if (!C) return OR_EINVAL;
+  int64_t run = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    double w = w_norm[i];
+    int64_t c = 0;
+    if (w > 0.0) c = (int64_t)rint((w < 1.0 ? w : 1.0) * 1099511627776.0);
+    run += c;
+    C[i] = run;
+  }
+  const int64_t total = run;
+  if (total <= 0) {
+    free(C);
+    return OR_EINVAL;
+  }
+  int64_t a = 0; /* U_j does not decrease with j, so the scan resumes where it stopped */
+  for (int64_t j = 0; j < N; ++j) {
+    int64_t U = (int64_t)floor(((double)j + u) * (double)total / (double)N);
+    if (U >= total) U = total - 1;
+    while (C[a] <= U) ++a; /* the first index whose prefix exceeds U */
+    ancestors[j] = (int32_t)a;
+  }
+  free(C);
+  offsets_out[0] = 0;
+  for (int64_t j = 0; j < N; ++j) {
+    int64_t a = ancestors[j];
+    offsets_out[j + 1] = offsets_out[j] + (offsets[a + 1] - offsets[a]);
+  }
+  if (offsets_out[N] > m_cap) return OR_EINVAL;
+  for (int64_t j = 0; j < N; ++j) {
+    int64_t a = ancestors[j];
+    for (int64_t x = 0; x < (offsets[a + 1] - offsets[a]) * P; ++x)
+      theta_out[offsets_out[j] * P + x] = theta[offsets[a] * P + x];
+  }
+  return OR_OK;
+}
+
+/* Accept/reject of the transdimensional moves of the mutation kernel
+ * (Sec. "Reversible Jump Markov Chain Monte Carlo", eq. rj_acceptance) and
+ * the new population. move[i]: 0 keeps particle i, 1 proposes the birth of
+ * theta_birth[i] (drawn from the single-component prior), 2 proposes the
+ * death of its component death_idx[i]. Reading of the acceptance ratio:
+ * components are exchangeable, so a birth is taken to insert the new
+ * component at a uniformly chosen one of the k+1 positions (appending it is
+ * the same state up to order, which the likelihood and prior ignore) and a
+ * death removes a uniformly chosen one of the k+1 (resp. k) components; the
+ * 1/(k+1) position and selection probabilities then cancel, the prior
+ * density of the new component cancels its proposal density, the Jacobian is
+ * one, and with a uniform prior on k over [k_lo, k_hi]:
+ *   birth: log alpha = dlogl_birth + log(p_death / p_birth)  if k + 1 <= k_hi
+ *   death: log alpha = dlogl_death - log(p_death / p_birth)  if k - 1 >= k_lo
+ * (-inf outside the k range), with the tempered log-likelihood changes of
+ * delta_logl_birth_death. The move is accepted when log_u[i] < log alpha.
+ * An accepted birth appends theta_birth[i] as the particle's last row; an
+ * accepted death removes row death_idx[i]; other rows keep their order.
+ * accepted[i] = 1 for an accepted move, else 0. The new population must not
+ * exceed m_cap rows. */
+int oracle_rj_apply(int model, int64_t N, const int64_t* offsets, const double* theta,
+                    const int8_t* move, const double* theta_birth, const int32_t* death_idx,
+                    const double* dlogl_birth, const double* dlogl_death, const double* log_u,
+                    int32_t k_lo, int32_t k_hi, double log_pd_over_pb, int64_t m_cap,
+                    int64_t* offsets_out, double* theta_out, int8_t* accepted) {
+  if (check_population(model, N, offsets, theta) != OR_OK || !move || !log_u || !offsets_out ||
+      !accepted || k_lo < 0 || k_hi < k_lo)
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+  offsets_out[0] = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    int acc = 0;
+    if (move[i] == 1 && theta_birth && dlogl_birth && K + 1 <= k_hi)
+      acc = log_u[i] < dlogl_birth[i] + log_pd_over_pb;
+    else if (move[i] == 2 && death_idx && dlogl_death && K - 1 >= k_lo && death_idx[i] >= 0 &&
+             death_idx[i] < K)
+      acc = log_u[i] < dlogl_death[i] - log_pd_over_pb;
+    accepted[i] = (int8_t)acc;
+    offsets_out[i + 1] = offsets_out[i] + K + (acc ? (move[i] == 1 ? 1 : -1) : 0);
+  }
+  if (offsets_out[N] > m_cap) return OR_EINVAL;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    int64_t skip = (accepted[i] && move[i] == 2) ? death_idx[i] : -1;
+    int64_t o = offsets_out[i];
+    for (int64_t k = 0; k < K; ++k) {
+      if (k == skip) continue;
+      for (int p = 0; p < P; ++p) theta_out[o * P + p] = theta[(offsets[i] + k) * P + p];
+      ++o;
+    }
+    if (accepted[i] && move[i] == 1) {
+      for (int p = 0; p < P; ++p) theta_out[o * P + p] = theta_birth[i * P + p];
+      ++o;
+    }
+  }
+  return OR_OK;
+}

@@ -1,0 +1,204 @@
+"""Pins of the oracle's SMC steps: the ESS-bisection temperature, systematic
+resampling and the birth/death accept/reject.
+
+Each is checked against something other than the oracle: closed-form roots of
+ESS(beta) = alpha N for a two-point population, scipy's log-sum-exp,
+textbook properties of systematic resampling (offspring counts are floor or
+ceil of N W_i, ancestors never decrease, the counts are unbiased) and the
+stationary distribution of the number of components under known targets.
+"""
+import numpy as np
+import pytest
+from scipy.special import logsumexp
+
+from paper_2609_17674_amd import workloads as wl
+
+PULSE = wl.PULSE
+
+
+def ess(logl, db, logw_prev=None):
+    lw = db * logl + (0.0 if logw_prev is None else logw_prev)
+    return float(np.exp(2 * logsumexp(lw) - logsumexp(2 * lw)))
+
+
+# ------------------------------------------------------------------ next beta
+def test_next_beta_equal_logl_goes_to_one(orc):
+    logl = np.full(500, -123.25)
+    logw, w, sc = orc.next_beta(logl, 0.3, 0.9)
+    assert sc[0] == 1.0 and sc[3] == 0
+    assert abs(sc[1] - 500) < 1e-9
+    # log Z increment of identical weights exp(0.7 * c)
+    assert abs(sc[2] - 0.7 * -123.25) < 1e-12
+    assert np.allclose(w, 1.0 / 500, rtol=1e-14)
+
+
+@pytest.mark.parametrize("N0,N1,L,alpha,beta_prev", [(300, 700, 50.0, 0.9, 0.0),
+                                                     (50, 950, 2000.0, 0.5, 0.25),
+                                                     (900, 100, 7.0, 0.95, 0.6)])
+def test_next_beta_two_point_closed_form(orc, N0, N1, L, alpha, beta_prev):
+    """ESS((N0 + N1 x)^2 / (N0 + N1 x^2)) = alpha N with x = exp(-db L) is a
+    quadratic in x."""
+    N = N0 + N1
+    logl = np.concatenate([np.zeros(N0), np.full(N1, -L)])
+    a = N1 * (N1 - alpha * N)
+    b = 2.0 * N0 * N1
+    c = N0 * (N0 - alpha * N)
+    roots = np.roots([a, b, c])
+    x = [r.real for r in roots if abs(r.imag) < 1e-12 and 0 < r.real < 1]
+    assert len(x) == 1
+    db = -np.log(x[0]) / L
+    expect = min(1.0, beta_prev + db)
+    _, _, sc = orc.next_beta(logl, beta_prev, alpha)
+    assert abs(sc[0] - expect) <= 1e-12 * max(expect, 1e-3), (sc[0], expect)
+    if expect < 1.0:
+        assert alpha * N <= sc[1] <= alpha * N + 1e-6 * N
+
+
+def test_next_beta_random_population_brackets_the_root(orc):
+    rng = np.random.default_rng(4)
+    logl = -0.5 * rng.chisquare(4096, size=4000)  # like logL of a 4096-sample residual
+    for beta_prev, alpha in ((0.0, 0.9), (0.013, 0.9), (0.5, 0.7)):
+        logw, w, sc = orc.next_beta(logl, beta_prev, alpha)
+        beta = sc[0]
+        assert beta_prev < beta <= 1.0
+        N = len(logl)
+        e = ess(logl, beta - beta_prev)
+        assert abs(e - sc[1]) <= 1e-9 * N
+        if beta < 1.0:
+            # the lower end of the bracket keeps ESS >= alpha N; just above, it is below
+            assert sc[1] >= alpha * N
+            assert e >= alpha * N - 1e-9 * N
+            assert ess(logl, beta - beta_prev + 1e-9 * (1 - beta_prev)) < alpha * N
+        # weights and evidence against scipy
+        lw = (beta - beta_prev) * logl
+        assert np.allclose(logw, lw, rtol=0, atol=1e-12 * np.abs(lw).max())
+        assert np.allclose(w, np.exp(lw - logsumexp(lw)), rtol=1e-12, atol=1e-300)
+        assert abs(sc[2] - (logsumexp(lw) - np.log(N))) < 1e-9
+        assert abs(w.sum() - 1.0) < 1e-12
+
+
+def test_next_beta_with_previous_weights(orc):
+    rng = np.random.default_rng(5)
+    logl = -rng.exponential(30.0, size=1000)
+    lwp = rng.normal(0.0, 0.3, size=1000)
+    logw, w, sc = orc.next_beta(logl, 0.2, 0.5, logw_prev=lwp)
+    lw = lwp + (sc[0] - 0.2) * logl
+    assert np.allclose(logw, lw, rtol=0, atol=1e-12)
+    assert abs(sc[2] - (logsumexp(lw) - logsumexp(lwp))) < 1e-10
+    assert abs(sc[1] - ess(logl, sc[0] - 0.2, lwp)) < 1e-8
+    # at beta_prev = 1 nothing moves
+    _, w1, sc1 = orc.next_beta(logl, 1.0, 0.9)
+    assert sc1[0] == 1.0 and abs(sc1[1] - 1000) < 1e-9 and sc1[2] == 0.0
+
+
+# ------------------------------------------------------------------ resampling
+def _population(N, seed, k_hi=5):
+    w = wl.make_config("pulse_small", N=N, T=64, k_lo=0, k_hi=k_hi, seed=seed)
+    return w.offsets, w.theta
+
+
+def test_systematic_counts_are_floor_or_ceil_and_ancestors_sorted(orc):
+    rng = np.random.default_rng(6)
+    N = 3000
+    off, th = _population(N, 7)
+    for trial in range(5):
+        W = rng.dirichlet(np.full(N, 0.3))
+        u = rng.random()
+        anc, off2, th2 = orc.resample_systematic(PULSE, off, th, W, u)
+        assert np.all(np.diff(anc) >= 0)
+        n = np.bincount(anc, minlength=N)
+        NW = N * W
+        assert n.sum() == N
+        assert np.all((n == np.floor(NW)) | (n == np.ceil(NW)) | (np.abs(NW - np.round(NW)) < 1e-6))
+        # the new CSR rows are the ancestors' rows
+        K = np.diff(off)
+        assert np.array_equal(np.diff(off2), K[anc])
+        for j in rng.choice(N, 50, replace=False):
+            a = anc[j]
+            assert np.array_equal(th2[off2[j]:off2[j + 1]], th[off[a]:off[a + 1]])
+
+
+def test_systematic_special_weights(orc):
+    N = 257
+    off, th = _population(N, 8)
+    for u in (0.37, 0.0):  # u = 0 puts every position exactly on a prefix sum
+        anc, _, _ = orc.resample_systematic(PULSE, off, th, np.full(N, 1.0 / N), u)
+        assert np.array_equal(anc, np.arange(N))
+    W = np.zeros(N)
+    W[123] = 1.0
+    anc, off2, _ = orc.resample_systematic(PULSE, off, th, W, 0.99)
+    assert np.all(anc == 123)
+    with pytest.raises(ValueError):
+        orc.resample_systematic(PULSE, off, th, np.zeros(N), 0.5)
+    K = np.diff(off)
+    with pytest.raises(ValueError):  # not enough rows for the offspring
+        orc.resample_systematic(PULSE, off, th, W, 0.5, m_cap=int(K[123]) * N - 1)
+
+
+def test_systematic_is_unbiased(orc):
+    """E[n_i] = N W_i over the uniform u."""
+    rng = np.random.default_rng(9)
+    N = 40
+    off, th = _population(N, 10)
+    W = rng.dirichlet(np.ones(N))
+    us = (np.arange(4000) + 0.5) / 4000  # a fine uniform grid of u
+    counts = np.zeros(N)
+    for u in us:
+        anc, _, _ = orc.resample_systematic(PULSE, off, th, W, u)
+        counts += np.bincount(anc, minlength=N)
+    assert np.allclose(counts / len(us), N * W, atol=2e-3)
+
+
+# ------------------------------------------------------------------ birth/death
+def _rj_chain(orc, c, p_birth, k_lo, k_hi, steps, N, seed):
+    """Births and deaths only, with log-likelihood change +c per component
+    (the target is p(k) proportional to exp(c k) on [k_lo, k_hi])."""
+    rng = np.random.default_rng(seed)
+    K = np.full(N, k_lo, dtype=np.int64)
+    off = wl.counts_to_offsets(K)
+    th = wl.draw_components(PULSE, int(off[-1]), rng)
+    lr = np.log((1.0 - p_birth) / p_birth)
+    for _ in range(steps):
+        K = np.diff(off)
+        move = np.where(rng.random(N) < p_birth, 1, 2).astype(np.int8)
+        tb = wl.draw_components(PULSE, N, rng)
+        di = np.where(K > 0, (rng.random(N) * np.maximum(K, 1)).astype(np.int32), -1)
+        acc, off, th = orc.rj_apply(PULSE, off, th, move, tb, di, np.full(N, c), np.full(N, -c),
+                                    np.log(rng.random(N)), k_lo, k_hi, lr)
+    return np.diff(off)
+
+
+@pytest.mark.parametrize("c,p_birth", [(0.0, 0.5), (0.4, 0.5), (-0.3, 0.3)])
+def test_rj_stationary_distribution_of_k(orc, c, p_birth):
+    k_lo, k_hi = 1, 6
+    K = _rj_chain(orc, c, p_birth, k_lo, k_hi, steps=150, N=6000, seed=11)
+    ks = np.arange(k_lo, k_hi + 1)
+    target = np.exp(c * ks)
+    target /= target.sum()
+    hist = np.bincount(K, minlength=k_hi + 1)[k_lo:] / len(K)
+    assert K.min() >= k_lo and K.max() <= k_hi
+    assert np.abs(hist - target).max() < 0.02, (hist, target)
+
+
+def test_rj_apply_bookkeeping(orc):
+    rng = np.random.default_rng(12)
+    N = 200
+    w = wl.make_config("pulse_small", N=N, T=64, k_lo=0, k_hi=6, seed=13)
+    off, th = w.offsets, w.theta
+    K = np.diff(off)
+    move = rng.integers(0, 3, size=N).astype(np.int8)
+    tb = wl.draw_components(PULSE, N, rng)
+    di = np.where(K > 0, (rng.random(N) * np.maximum(K, 1)).astype(np.int32), -1)
+    db = np.where(rng.random(N) < 0.5, np.inf, -np.inf)
+    db[::17] = np.nan
+    dd = -db
+    acc, off2, th2 = orc.rj_apply(PULSE, off, th, move, tb, di, db, dd, np.zeros(N), 1, 6)
+    for i in range(N):
+        rows = th[off[i]:off[i + 1]]
+        new = th2[off2[i]:off2[i + 1]]
+        if move[i] == 1 and K[i] + 1 <= 6 and db[i] == np.inf:
+            assert acc[i] == 1 and np.array_equal(new, np.vstack([rows, tb[i:i + 1]]))
+        elif move[i] == 2 and K[i] - 1 >= 1 and dd[i] == np.inf:
+            assert acc[i] == 1 and np.array_equal(new, np.delete(rows, di[i], axis=0))
+        else:
+            assert acc[i] == 0 and np.array_equal(new, rows)
