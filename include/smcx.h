@@ -251,20 +251,22 @@ int smcx_nuts_reserve(smcx_problem* prob, int32_t max_depth);
  *   u_leaf             [N][2^max_depth - 1] uniforms in [0,1); leaf n of the
  *                      doubling at depth j uses column 2^j - 1 + n
  *   u_tree             [N][max_depth] uniforms for merging subtrees
+ *   mask               [N] uint8 or NULL: a particle with mask[i] == 0 is
+ *                      left as it is (status 0), for mixtures of moves
  *   q, logl, grad      in: state, tempered logL and gradient at q (for
  *                      example from logl_grad_batch); out: the new state
  *   depth_out, steps_out, status_out  [N] int32 or NULL: completed
  *                      doublings, leapfrog steps, and the reason the
- *                      trajectory stopped (0 no components, 1 U-turn,
+ *                      trajectory stopped (0 no components or masked, 1 U-turn,
  *                      2 divergence, 3 maximum depth, -1 invalid rows)
  * Returns SMCX_ECAPTURE if called during stream capture. */
 int smcx_nuts_transition(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                          const double* beta, double eps, int32_t max_depth,
                          const double* prior_lo, const double* prior_hi, const double* momentum,
                          const int8_t* dirs, const double* u_leaf, const double* u_tree,
-                         double* q, double* logl, double* grad, int32_t* depth_out,
-                         int32_t* steps_out, int32_t* status_out, int32_t use_graph,
-                         void* hip_stream);
+                         const uint8_t* mask, double* q, double* logl, double* grad,
+                         int32_t* depth_out, int32_t* steps_out, int32_t* status_out,
+                         int32_t use_graph, void* hip_stream);
 
 /* Tiling of the sample axis, per call kind: SMCX_KIND_LOGL (logl_batch and
  * the segment pass of reweight_extend), SMCX_KIND_GRAD (logl_grad_batch),
@@ -302,6 +304,82 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
                   const double* theta, const double* beta, int32_t reps, const char* cache_path,
                   void* hip_stream, int32_t* out_S, int64_t* out_chunk_len, int32_t* out_sorted,
                   double* out_ms);
+
+/* ---- SMC steps around the likelihood (Sec. "Sequential Monte Carlo",
+ * Sec. "Algorithm and implementation") ---------------------------------- */
+
+/* Next inverse temperature of the prior bridge (eq. prior_bridge), chosen by
+ * the ESS condition of eq. ess_target, with the incremental weights of
+ * eq. incremental_weight, log w_i = logw_prev_i + (beta - beta_prev) logl_i,
+ * and the ESS of eq. ess.
+ *   logl       [N] UNTEMPERED log-likelihoods (logl_batch with beta = NULL)
+ *   logw_prev  [N] log weights carried over, or NULL for uniform ones
+ *   beta_prev  current inverse temperature in [0, 1]; alpha in (0, 1]
+ * beta = 1 when ESS(1) >= alpha N; otherwise the bracket [beta_prev, 1] is
+ * halved (at most 60 times, and no further once its midpoint is no longer
+ * strictly inside), keeping the lower end where ESS >= alpha N, and beta is
+ * that lower end (its upper end if the lower end never moved, which only
+ * uneven logw_prev can cause).
+ * Outputs (device): beta_out [N] every entry set to beta (ready for the
+ * tempered calls; may be NULL), logw [N], w_norm [N] normalised weights,
+ * scalars [4] = {beta, ESS(beta), log Z_t/Z_{t-1}, ESS evaluations of the
+ * bisection}; the evidence increment is log sum exp(log w) - log sum
+ * exp(logw_prev) (log N for uniform previous weights). N in [1, n_max].
+ * One single-block launch; no allocation, no host synchronisation. */
+int smcx_next_beta(smcx_problem* prob, int64_t N, const double* logl, const double* logw_prev,
+                   double beta_prev, double alpha, double* beta_out, double* logw,
+                   double* w_norm, double* scalars, void* hip_stream);
+
+/* Systematic resampling of the population by its normalised weights (the
+ * paper leaves the scheme open; systematic resampling is the reading taken).
+ * Weights become integers c_i = round(w_norm_i 2^40) (0 unless w_norm_i > 0),
+ * with exact int64 prefix sums C_i and total C; offspring j takes position
+ * U_j = floor(((j + u) C) / N) in double precision (evaluated in that order,
+ * capped at C - 1) and ancestor a_j = min{i : C_i > U_j}. The same inputs
+ * therefore give the same ancestors on any implementation.
+ *   offsets, M, theta   the population (validated on the device as for
+ *                       logl_batch; an invalid particle contributes no rows)
+ *   w_norm [N], u in [0, 1)
+ *   ancestors [N] int32, offsets_out [N+1] int64, theta_out [m_cap][P]
+ * The new population is the ancestors' rows in CSR form. If it needs more
+ * than m_cap rows the device flag is raised (smcx_device_status) and rows
+ * past m_cap are not written; m_cap = N k_max always suffices. Weights
+ * without a positive entry raise the flag and keep every particle. The
+ * outputs must not overlap the inputs. N in [1, n_max]. */
+int smcx_resample_systematic(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                             const double* theta, const double* w_norm, double u, int64_t m_cap,
+                             int32_t* ancestors, int64_t* offsets_out, double* theta_out,
+                             void* hip_stream);
+
+/* Accept/reject of the birth and death moves of the mutation kernel
+ * (eq. kernel_mixture; Sec. "Reversible Jump Markov Chain Monte Carlo",
+ * eq. rj_acceptance) and the rebuilt population.
+ *   move [N] int8: 0 keep, 1 birth of theta_birth[i] (drawn from the
+ *       single-component prior), 2 death of component death_idx[i]
+ *   dlogl_birth, dlogl_death [N]: the tempered changes from
+ *       delta_logl_birth_death for the same proposals
+ *   log_u [N]: logs of uniforms; k_lo <= k_hi <= k_max: the uniform prior
+ *       range of K; log_pd_over_pb = log(p_death / p_birth)
+ * Reading of the ratio: components are exchangeable, so a birth is taken to
+ * insert at one of the k+1 positions uniformly (equal to appending, up to an
+ * order the target ignores) and a death to remove a uniformly chosen
+ * component; the 1/(k+1) factors cancel, the prior density of the new
+ * component cancels its proposal density and the Jacobian is one, leaving
+ *   birth: log alpha = dlogl_birth + log_pd_over_pb   (K + 1 <= k_hi)
+ *   death: log alpha = dlogl_death - log_pd_over_pb   (K - 1 >= k_lo,
+ *                                                       0 <= death_idx < K)
+ * and -inf otherwise; a move is accepted when log_u < log alpha (a NaN
+ * change is rejected). An accepted birth appends its row last, an accepted
+ * death removes its row, the other rows keep their order.
+ * Outputs: offsets_out [N+1], theta_out [m_cap][P] (capacity handled as in
+ * smcx_resample_systematic; m_cap = M + N always suffices), accepted [N]
+ * int8. The outputs must not overlap the inputs. */
+int smcx_rj_apply(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                  const double* theta, const int8_t* move, const double* theta_birth,
+                  const int32_t* death_idx, const double* dlogl_birth, const double* dlogl_death,
+                  const double* log_u, int32_t k_lo, int32_t k_hi, double log_pd_over_pb,
+                  int64_t m_cap, int64_t* offsets_out, double* theta_out, int8_t* accepted,
+                  void* hip_stream);
 
 /* Measurement hooks. Between smcx_profile_begin and smcx_profile_end every
  * compute call on the handle brackets its batched kernel launches (the

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -111,6 +112,12 @@ void free_problem(smcx_problem* p) {
   (void)hipFree(p->order);
   (void)hipFree(p->n_active);
   (void)hipFree(p->prep_hist);
+  (void)hipFree(p->smc.cum);
+  (void)hipFree(p->smc.src_row);
+  (void)hipFree(p->smc.src_len);
+  (void)hipFree(p->smc.skip);
+  (void)hipFree(p->smc.append);
+  (void)hipFree(p->smc.count);
   (void)hipFree(p->flag);
   (void)hipFree(p->part);
   (void)hipFree(p->part_g);
@@ -263,6 +270,7 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
                                  ? (size_t)p->max_nch_grad * (size_t)std::max<int64_t>(m_max, 1) * p->P
                                  : 1;
   const int nb = (int)((T + 255) / 256);
+  const size_t n1 = (size_t)std::max<int64_t>(n_max, 1);
   struct { void** ptr; size_t bytes; } allocs[] = {
       {(void**)&p->d32, T_pad * sizeof(float)},
       {(void**)&p->d64, T * sizeof(double)},
@@ -270,6 +278,12 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
       {(void**)&p->n_active, sizeof(int32_t)},
       {(void**)&p->prep_hist,
        (size_t)smcx::prep_slices(std::max<int64_t>(n_max, 1)) * (k_max + 1) * sizeof(int32_t)},
+      {(void**)&p->smc.cum, n1 * sizeof(int64_t)},
+      {(void**)&p->smc.src_row, n1 * sizeof(int64_t)},
+      {(void**)&p->smc.src_len, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.skip, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.append, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.count, n1 * sizeof(int64_t)},
       {(void**)&p->flag, sizeof(int)},
       {(void**)&p->part, part_elems * sizeof(double)},
       {(void**)&p->part_g, partg_elems * sizeof(double)},
@@ -318,9 +332,11 @@ int smcx_device_status(smcx_problem* p, void* hip_stream) {
   std::string msg = "device-side argument errors:";
   if (flag & smcx::kFlagOffsets) msg += " offsets not a valid CSR prefix sum;";
   if (flag & smcx::kFlagKMax) msg += " a particle has K > k_max;";
-  if (flag & smcx::kFlagMMax) msg += " offsets[N] > m_max;";
+  if (flag & smcx::kFlagMMax) msg += " offsets[N] differs from M;";
   if (flag & smcx::kFlagDeath) msg += " death index outside [-1, K);";
   if (flag & smcx::kFlagPhase) msg += " sinusoid frequency too high for the sample spacing;";
+  if (flag & smcx::kFlagCapacity) msg += " rebuilt population exceeds the output rows (m_cap);";
+  if (flag & smcx::kFlagWeights) msg += " resampling weights have no positive entry;";
   return fail(SMCX_EDEVICE, "%s", msg.c_str());
 }
 
@@ -585,9 +601,9 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
                          const double* beta, double eps, int32_t max_depth,
                          const double* prior_lo, const double* prior_hi, const double* momentum,
                          const int8_t* dirs, const double* u_leaf, const double* u_tree,
-                         double* q, double* logl, double* grad, int32_t* depth_out,
-                         int32_t* steps_out, int32_t* status_out, int32_t use_graph,
-                         void* hip_stream) {
+                         const uint8_t* mask, double* q, double* logl, double* grad,
+                         int32_t* depth_out, int32_t* steps_out, int32_t* status_out,
+                         int32_t use_graph, void* hip_stream) {
   g_last_error.clear();
   int rc = check_pop(p, N, offsets, M, q);
   if (rc) return rc;
@@ -617,6 +633,7 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   na.dirs = dirs;
   na.u_leaf = u_leaf;
   na.u_tree = u_tree;
+  na.mask = mask;
   na.q = q;
   na.logl = logl;
   na.grad = grad;
@@ -773,6 +790,70 @@ int smcx_profile_end(smcx_problem* p, double* total_ms, int64_t* launches) {
   if (total_ms) *total_ms = tot;
   if (launches) *launches = p->prof_n;
   p->prof_n = 0;
+  return SMCX_OK;
+}
+
+int smcx_next_beta(smcx_problem* p, int64_t N, const double* logl, const double* logw_prev,
+                   double beta_prev, double alpha, double* beta_out, double* logw,
+                   double* w_norm, double* scalars, void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (N < 1 || N > p->n_max)
+    return fail(SMCX_EINVAL, "N = %lld outside [1, n_max = %lld]", (long long)N,
+                (long long)p->n_max);
+  if (!logl || !logw || !w_norm || !scalars)
+    return fail(SMCX_EINVAL, "logl, logw, w_norm and scalars are required");
+  if (!(beta_prev >= 0.0 && beta_prev <= 1.0))
+    return fail(SMCX_EINVAL, "beta_prev = %g outside [0, 1]", beta_prev);
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SMCX_EINVAL, "alpha = %g outside (0, 1]", alpha);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_next_beta(N, logl, logw_prev, beta_prev, alpha, beta_out, logw,
+                                        w_norm, scalars, st);
+  if (e != hipSuccess) return hip_fail(e, "next_beta launch");
+  return SMCX_OK;
+}
+
+int smcx_resample_systematic(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                             const double* theta, const double* w_norm, double u, int64_t m_cap,
+                             int32_t* ancestors, int64_t* offsets_out, double* theta_out,
+                             void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N < 1) return fail(SMCX_EINVAL, "N must be positive");
+  if (N > INT32_MAX) return fail(SMCX_EINVAL, "N too large for int32 ancestors");
+  if (!w_norm || !ancestors || !offsets_out) return fail(SMCX_EINVAL, "null output or weights");
+  if (m_cap < 0 || (m_cap > 0 && !theta_out)) return fail(SMCX_EINVAL, "bad m_cap / theta_out");
+  if (!(u >= 0.0 && u < 1.0)) return fail(SMCX_EINVAL, "u = %g outside [0, 1)", u);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_resample(p->smc, p->model, p->k_max, N, offsets, M, theta, w_norm, u,
+                                       m_cap, ancestors, offsets_out, theta_out, p->flag, st);
+  if (e != hipSuccess) return hip_fail(e, "resample launch");
+  return SMCX_OK;
+}
+
+int smcx_rj_apply(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                  const double* theta, const int8_t* move, const double* theta_birth,
+                  const int32_t* death_idx, const double* dlogl_birth, const double* dlogl_death,
+                  const double* log_u, int32_t k_lo, int32_t k_hi, double log_pd_over_pb,
+                  int64_t m_cap, int64_t* offsets_out, double* theta_out, int8_t* accepted,
+                  void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N == 0) return SMCX_OK;
+  if (!move || !log_u || !offsets_out || !accepted)
+    return fail(SMCX_EINVAL, "move, log_u, offsets_out and accepted are required");
+  if (m_cap < 0 || (m_cap > 0 && !theta_out)) return fail(SMCX_EINVAL, "bad m_cap / theta_out");
+  if (k_lo < 0 || k_hi < k_lo || k_hi > p->k_max)
+    return fail(SMCX_EINVAL, "k range [%d, %d] not inside [0, k_max = %d]", k_lo, k_hi, p->k_max);
+  if (!(log_pd_over_pb == log_pd_over_pb)) return fail(SMCX_EINVAL, "log_pd_over_pb is NaN");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_rj_apply(p->smc, p->model, p->k_max, N, offsets, M, theta, move,
+                                       theta_birth, death_idx, dlogl_birth, dlogl_death, log_u,
+                                       k_lo, k_hi, log_pd_over_pb, m_cap, offsets_out, theta_out,
+                                       accepted, p->flag, st);
+  if (e != hipSuccess) return hip_fail(e, "rj_apply launch");
   return SMCX_OK;
 }
 

@@ -19,6 +19,18 @@ enum : int {
   kFlagMMax = 4,      // offsets[N] != M (rows of theta passed by the caller)
   kFlagDeath = 8,     // death index outside [-1, K_i)
   kFlagPhase = 16,    // GB phase increment too large for the per-tile reduction
+  kFlagCapacity = 32, // a rebuilt population needs more rows than the output holds
+  kFlagWeights = 64,  // resampling weights without a positive entry
+};
+
+// Per-particle workspace of the SMC steps (resampling, birth/death rebuild).
+struct SmcWork {
+  int64_t* cum;      // [n_max] integer weight prefix sums
+  int64_t* src_row;  // [n_max] first source row of each output particle
+  int32_t* src_len;  // [n_max] source rows
+  int32_t* skip;     // [n_max] source row left out (-1 none)
+  int32_t* append;   // [n_max] 1: a row of theta_add follows
+  int64_t* count;    // [n_max] rows of each output particle
 };
 
 // Number of parameters per component.
@@ -125,6 +137,7 @@ struct NutsArgs {
   const int8_t* dirs;      // [N][D]
   const double* u_leaf;    // [N][2^D - 1]
   const double* u_tree;    // [N][D]
+  const uint8_t* mask;     // [N] or nullptr: particles with mask[i] == 0 stay put
   double* q;               // [M][P] in/out
   double* logl;            // [N] in/out (tempered)
   double* grad;            // [M][P] in/out (tempered)
@@ -151,6 +164,22 @@ hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 // Number of particle slices of the ordering pass (its histogram workspace rows).
 int64_t prep_slices(int64_t N);
+
+// SMC steps (smcx_smc.hip).
+hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,
+                            double beta_prev, double alpha, double* beta_out, double* logw,
+                            double* w_norm, double* scalars, hipStream_t st);
+hipError_t launch_resample(const SmcWork& w, int model, int32_t k_max, int64_t N,
+                           const int64_t* offsets, int64_t M, const double* theta,
+                           const double* w_norm, double u, int64_t m_cap, int32_t* ancestors,
+                           int64_t* offsets_out, double* theta_out, int* flag, hipStream_t st);
+hipError_t launch_rj_apply(const SmcWork& w, int model, int32_t k_max, int64_t N,
+                           const int64_t* offsets, int64_t M, const double* theta,
+                           const int8_t* move, const double* theta_birth, const int32_t* death_idx,
+                           const double* dlogl_birth, const double* dlogl_death,
+                           const double* log_u, int32_t k_lo, int32_t k_hi, double log_pd_over_pb,
+                           int64_t m_cap, int64_t* offsets_out, double* theta_out,
+                           int8_t* accepted, int* flag, hipStream_t st);
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);

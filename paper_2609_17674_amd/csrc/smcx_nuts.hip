@@ -110,7 +110,8 @@ __global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
   pp = wsum(pp);
   out = wany(out);
   const double H0 = -a.logl[v.i] + 0.5 * pp;
-  const bool go = v.K > 0 && !out && (H0 == H0) && fabs(H0) < INFINITY;
+  const bool still = v.K == 0 || (a.mask && !a.mask[v.i]);  // no move: kept as it is
+  const bool go = !still && !out && (H0 == H0) && fabs(H0) < INFINITY;
   const int8_t d = go ? a.dirs[v.i * a.D] : (int8_t)1;
   if (v.lane == 0) {
     s.H0 = H0;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
     s.logl_sub = a.logl[v.i];
     s.depth = 0;
     s.steps = 0;
-    s.status = v.K == 0 ? 0 : (go ? 4 : 2);
+    s.status = still ? 0 : (go ? 4 : 2);
     a.active[v.i] = go ? 1 : 0;
     a.dir[v.i] = d;
   }

@@ -29,6 +29,7 @@ struct smcx_problem {
   int32_t* order = nullptr;
   int32_t* n_active = nullptr;
   int32_t* prep_hist = nullptr;  // [prep_slices(n_max)][k_max + 1]
+  smcx::SmcWork smc{};            // SMC-step workspace, [n_max] each
   int* flag = nullptr;
   double* part = nullptr;   // [max_nch][n_max][4]
   double* part_g = nullptr; // [nch_grad][m_max][P]

@@ -1,0 +1,404 @@
+// SMC steps around the likelihood (Sec. "Sequential Monte Carlo",
+// Sec. "Algorithm and implementation"): the ESS-bisection choice of the next
+// inverse temperature with its weights and evidence increment, systematic
+// resampling, the accept/reject of birth and death moves (eq. rj_acceptance),
+// and the CSR rebuild the last two share.
+//
+// Population-wide reductions run in one block with a fixed combination order
+// (butterfly within a wave, then waves in order), so results do not depend on
+// timing. Resampling works on integer weights so that its prefix sums, and
+// therefore the ancestors, are exact.
+#include "smcx_internal.h"
+
+#include <math.h>
+
+namespace smcx {
+namespace {
+
+constexpr int kBlock = 1024;  // single-block kernels
+constexpr int kBlockWaves = kBlock / 64;
+constexpr double kWeightUnit = 1099511627776.0;  // 2^40: integer weight units
+
+// Sum of a and b over the block, the same bits in every thread.
+__device__ void block_sum2(double& a, double& b, double* sh) {
+  for (int o = 32; o >= 1; o >>= 1) {  // butterfly: each step is commutative, so all lanes agree
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = a;
+    sh[kBlockWaves + w] = b;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < kBlockWaves; ++i) {
+    a += sh[i];
+    b += sh[kBlockWaves + i];
+  }
+}
+
+__device__ double block_max(double a, double* sh) {
+  for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = a;
+  __syncthreads();
+  a = -INFINITY;
+  for (int i = 0; i < kBlockWaves; ++i) a = fmax(a, sh[i]);
+  return a;
+}
+
+struct NextBetaArgs {
+  int64_t N;
+  const double* logl;
+  const double* logw_prev;
+  double beta_prev, alpha;
+  double* beta_out;
+  double* logw;
+  double* w_norm;
+  double* scalars;
+};
+
+__device__ __forceinline__ double log_weight(const NextBetaArgs& a, int64_t i, double db) {
+  return (a.logw_prev ? a.logw_prev[i] : 0.0) + db * a.logl[i];
+}
+
+// ESS of the weights at increment db (eq. ess), with the shift and sum.
+__device__ double ess_at(const NextBetaArgs& a, double db, double* sh, double* m_out,
+                         double* s1_out) {
+  double m = -INFINITY;
+  for (int64_t i = threadIdx.x; i < a.N; i += kBlock) m = fmax(m, log_weight(a, i, db));
+  m = block_max(m, sh);
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < a.N; i += kBlock) {
+    const double e = exp(log_weight(a, i, db) - m);
+    s1 += e;
+    s2 += e * e;
+  }
+  block_sum2(s1, s2, sh);
+  if (m_out) *m_out = m;
+  if (s1_out) *s1_out = s1;
+  return s1 * s1 / s2;
+}
+
+// One block: bisection on [beta_prev, 1] for ESS = alpha N (eq. ess_target),
+// then the weights of eq. incremental_weight and the evidence increment.
+__global__ __launch_bounds__(kBlock) void next_beta_kernel(NextBetaArgs a) {
+  __shared__ double sh[2 * kBlockWaves];
+  const double target = a.alpha * (double)a.N;
+  double beta = 1.0;
+  int evals = 0;
+  if (!(ess_at(a, 1.0 - a.beta_prev, sh, nullptr, nullptr) >= target)) {
+    double lo = a.beta_prev, hi = 1.0;
+    bool moved = false;
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      const double e = ess_at(a, mid - a.beta_prev, sh, nullptr, nullptr);
+      ++evals;
+      if (e >= target) {
+        lo = mid;
+        moved = true;
+      } else {
+        hi = mid;
+      }
+    }
+    beta = moved ? lo : hi;
+  }
+  const double db = beta - a.beta_prev;
+  double m, s1;
+  const double ess = ess_at(a, db, sh, &m, &s1);
+  for (int64_t i = threadIdx.x; i < a.N; i += kBlock) {
+    const double lw = log_weight(a, i, db);
+    a.logw[i] = lw;
+    a.w_norm[i] = exp(lw - m) / s1;
+    if (a.beta_out) a.beta_out[i] = beta;
+  }
+  double lse_prev = log((double)a.N);
+  if (a.logw_prev) {
+    double mp = -INFINITY;
+    for (int64_t i = threadIdx.x; i < a.N; i += kBlock) mp = fmax(mp, a.logw_prev[i]);
+    mp = block_max(mp, sh);
+    double sp = 0.0, unused = 0.0;
+    for (int64_t i = threadIdx.x; i < a.N; i += kBlock) sp += exp(a.logw_prev[i] - mp);
+    block_sum2(sp, unused, sh);
+    lse_prev = mp + log(sp);
+  }
+  if (threadIdx.x == 0) {
+    a.scalars[0] = beta;
+    a.scalars[1] = ess;
+    a.scalars[2] = m + log(s1) - lse_prev;
+    a.scalars[3] = (double)evals;
+  }
+}
+
+// ---------------------------------------------------------------- CSR rebuild
+// Output particle j takes rows src_row[j] .. src_row[j] + src_len[j] - 1 of
+// theta, without row skip[j] (local index, -1 = none), followed by row j of
+// theta_add when append[j] != 0.
+struct RebuildArgs {
+  int64_t N, M;
+  int P;
+  int32_t k_max;
+  const int64_t* offsets;  // source population
+  const double* theta;
+  int64_t* src_row;   // [N] workspace
+  int32_t* src_len;   // [N]
+  int32_t* skip;      // [N]
+  int32_t* append;    // [N]
+  int64_t* count;     // [N] rows of output particle j
+  const double* theta_add;  // [N][P] rows appended (births)
+  int64_t* offsets_out;     // [N + 1]
+  double* theta_out;        // [m_cap][P]
+  int64_t m_cap;
+  int* flag;
+};
+
+// Rows of source particle i, validated against [0, M] and k_max (an invalid
+// particle contributes no rows and raises the flag).
+__device__ __forceinline__ bool source_rows(const RebuildArgs& a, int64_t i, int64_t& row,
+                                            int32_t& len) {
+  const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+  if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) {
+    atomicOr(a.flag, (o1 - o0 > a.k_max && o0 >= 0 && o1 <= a.M) ? kFlagKMax : kFlagOffsets);
+    row = 0;
+    len = 0;
+    return false;
+  }
+  row = o0;
+  len = (int32_t)(o1 - o0);
+  return true;
+}
+
+// Exclusive prefix sum of count[0..N) into offsets_out[0..N] (one block).
+__global__ __launch_bounds__(kBlock) void csr_scan_kernel(RebuildArgs a) {
+  __shared__ int64_t part[kBlock];
+  const int64_t per = (a.N + kBlock - 1) / kBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per;
+  const int64_t b1 = b0 + per < a.N ? b0 + per : a.N;
+  int64_t s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += a.count[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int64_t i = b0; i < b1; ++i) {
+    a.offsets_out[i] = run;
+    run += a.count[i];
+  }
+  if (threadIdx.x == kBlock - 1) {
+    a.offsets_out[a.N] = part[kBlock - 1];
+    if (part[kBlock - 1] > a.m_cap) atomicOr(a.flag, kFlagCapacity);
+  }
+}
+
+// One wave per output particle copies its rows; rows at or past m_cap are
+// not written (the capacity flag is raised by the scan).
+__global__ __launch_bounds__(256) void csr_gather_kernel(RebuildArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= a.N) return;
+  const int64_t start = a.offsets_out[j];
+  const int64_t row = a.src_row[j];
+  const int32_t len = a.src_len[j], skip = a.skip[j];
+  const int P = a.P;
+  for (int64_t x = lane; x < (int64_t)len * P; x += 64) {
+    const int32_t k = (int32_t)(x / P);
+    const int p = (int)(x - (int64_t)k * P);
+    if (k == skip) continue;
+    const int64_t out = start + k - (skip >= 0 && k > skip ? 1 : 0);
+    if (out < a.m_cap) a.theta_out[out * P + p] = a.theta[(row + k) * P + p];
+  }
+  if (a.append[j] && lane < P) {
+    const int64_t out = start + len - (skip >= 0 ? 1 : 0);
+    if (out < a.m_cap) a.theta_out[out * P + lane] = a.theta_add[j * P + lane];
+  }
+}
+
+// ---------------------------------------------------------------- resampling
+struct ResampleArgs {
+  RebuildArgs r;
+  const double* w_norm;
+  double u;
+  int64_t* cum;       // [N] inclusive prefix sums of the integer weights
+  int32_t* ancestors; // [N]
+};
+
+// Integer weights c_i = round(w_i 2^40) (0 unless w_i > 0) and their inclusive
+// prefix sums, exact in int64 (one block).
+__global__ __launch_bounds__(kBlock) void resample_prefix_kernel(ResampleArgs a) {
+  __shared__ int64_t part[kBlock];
+  const int64_t N = a.r.N;
+  const int64_t per = (N + kBlock - 1) / kBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per;
+  const int64_t b1 = b0 + per < N ? b0 + per : N;
+  int64_t s = 0;
+  for (int64_t i = b0; i < b1; ++i) {
+    const double w = a.w_norm[i];
+    const int64_t c = w > 0.0 ? (int64_t)rint((w < 1.0 ? w : 1.0) * kWeightUnit) : 0;
+    a.cum[i] = c;
+    s += c;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int64_t i = b0; i < b1; ++i) {
+    run += a.cum[i];
+    a.cum[i] = run;
+  }
+  if (threadIdx.x == 0 && part[kBlock - 1] <= 0) atomicOr(a.r.flag, kFlagWeights);
+}
+
+// Offspring j: position U_j = floor(((j + u) C) / N), ancestor = first i with
+// cum[i] > U_j (binary search); then its rows for the rebuild.
+__global__ __launch_bounds__(256) void resample_ancestor_kernel(ResampleArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t N = a.r.N;
+  if (j >= N) return;
+  const int64_t total = a.cum[N - 1];
+  int64_t anc = j;  // no positive weight: every particle keeps itself (flagged)
+  if (total > 0) {
+    int64_t U = (int64_t)floor(((double)j + a.u) * (double)total / (double)N);
+    if (U >= total) U = total - 1;
+    int64_t lo = 0, hi = N - 1;  // cum[hi] = total > U
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (a.cum[mid] > U) hi = mid;
+      else lo = mid + 1;
+    }
+    anc = lo;
+  }
+  a.ancestors[j] = (int32_t)anc;
+  int64_t row;
+  int32_t len;
+  source_rows(a.r, anc, row, len);
+  a.r.src_row[j] = row;
+  a.r.src_len[j] = len;
+  a.r.skip[j] = -1;
+  a.r.append[j] = 0;
+  a.r.count[j] = len;
+}
+
+// ---------------------------------------------------------------- birth/death
+struct RjArgs {
+  RebuildArgs r;
+  const int8_t* move;
+  const int32_t* death_idx;
+  const double* dlogl_birth;
+  const double* dlogl_death;
+  const double* log_u;
+  int32_t k_lo, k_hi;
+  double log_pd_over_pb;
+  int8_t* accepted;
+};
+
+// Accept/reject per particle: log alpha = dlogl_birth + log(p_death/p_birth)
+// for a birth with K + 1 <= k_hi, dlogl_death - log(p_death/p_birth) for a
+// death of a valid index with K - 1 >= k_lo (the reading of eq. rj_acceptance
+// for exchangeable components, a birth proposal equal to the prior and a
+// uniform prior on K); accepted when log_u < log alpha.
+__global__ __launch_bounds__(256) void rj_decide_kernel(RjArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.r.N) return;
+  int64_t row;
+  int32_t K;
+  const bool ok = source_rows(a.r, i, row, K);
+  const int mv = a.move[i];
+  bool acc = false;
+  int32_t skip = -1;
+  if (ok && mv == 1 && a.r.theta_add && a.dlogl_birth && K + 1 <= a.k_hi) {
+    acc = a.log_u[i] < a.dlogl_birth[i] + a.log_pd_over_pb;
+  } else if (ok && mv == 2 && a.death_idx && a.dlogl_death && K - 1 >= a.k_lo) {
+    const int32_t j = a.death_idx[i];
+    if (j >= 0 && j < K) {
+      acc = a.log_u[i] < a.dlogl_death[i] - a.log_pd_over_pb;
+      if (acc) skip = j;
+    }
+  }
+  a.accepted[i] = acc ? 1 : 0;
+  a.r.src_row[i] = row;
+  a.r.src_len[i] = K;
+  a.r.skip[i] = skip;
+  a.r.append[i] = (acc && mv == 1) ? 1 : 0;
+  a.r.count[i] = K + (acc ? (mv == 1 ? 1 : -1) : 0);
+}
+
+hipError_t launch_rebuild(const RebuildArgs& r, hipStream_t st) {
+  hipLaunchKernelGGL(csr_scan_kernel, dim3(1), dim3(kBlock), 0, st, r);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(csr_gather_kernel, dim3((unsigned)((r.N + 3) / 4)), dim3(256), 0, st, r);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,
+                            double beta_prev, double alpha, double* beta_out, double* logw,
+                            double* w_norm, double* scalars, hipStream_t st) {
+  NextBetaArgs a{N, logl, logw_prev, beta_prev, alpha, beta_out, logw, w_norm, scalars};
+  hipLaunchKernelGGL(next_beta_kernel, dim3(1), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample(const SmcWork& w, int model, int32_t k_max, int64_t N,
+                           const int64_t* offsets, int64_t M, const double* theta,
+                           const double* w_norm, double u, int64_t m_cap, int32_t* ancestors,
+                           int64_t* offsets_out, double* theta_out, int* flag, hipStream_t st) {
+  ResampleArgs a;
+  a.r = RebuildArgs{N, M, n_params(model), k_max, offsets, theta, w.src_row, w.src_len, w.skip,
+                    w.append, w.count, nullptr, offsets_out, theta_out, m_cap, flag};
+  a.w_norm = w_norm;
+  a.u = u;
+  a.cum = w.cum;
+  a.ancestors = ancestors;
+  hipLaunchKernelGGL(resample_prefix_kernel, dim3(1), dim3(kBlock), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(resample_ancestor_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                     a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_rebuild(a.r, st);
+}
+
+hipError_t launch_rj_apply(const SmcWork& w, int model, int32_t k_max, int64_t N,
+                           const int64_t* offsets, int64_t M, const double* theta,
+                           const int8_t* move, const double* theta_birth, const int32_t* death_idx,
+                           const double* dlogl_birth, const double* dlogl_death,
+                           const double* log_u, int32_t k_lo, int32_t k_hi, double log_pd_over_pb,
+                           int64_t m_cap, int64_t* offsets_out, double* theta_out,
+                           int8_t* accepted, int* flag, hipStream_t st) {
+  RjArgs a;
+  a.r = RebuildArgs{N, M, n_params(model), k_max, offsets, theta, w.src_row, w.src_len, w.skip,
+                    w.append, w.count, theta_birth, offsets_out, theta_out, m_cap, flag};
+  a.move = move;
+  a.death_idx = death_idx;
+  a.dlogl_birth = dlogl_birth;
+  a.dlogl_death = dlogl_death;
+  a.log_u = log_u;
+  a.k_lo = k_lo;
+  a.k_hi = k_hi;
+  a.log_pd_over_pb = log_pd_over_pb;
+  a.accepted = accepted;
+  hipLaunchKernelGGL(rj_decide_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_rebuild(a.r, st);
+}
+
+}  // namespace smcx

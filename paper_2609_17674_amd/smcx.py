@@ -59,7 +59,10 @@ def load_library():
         "smcx_leapfrog": [P, I64, P, I64, P, D, P, P, P, P, P, P, P, P, P, P],
         "smcx_nuts_reserve": [P, I32],
         "smcx_nuts_transition": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, P, P, P, P,
-                                 I32, P],
+                                 P, I32, P],
+        "smcx_next_beta": [P, I64, P, P, D, D, P, P, P, P, P],
+        "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
+        "smcx_rj_apply": [P, I64, P, I64, P, P, P, P, P, P, P, I32, I32, D, I64, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -320,8 +323,9 @@ def nuts_reserve(prob: Problem, max_depth: int) -> None:
 
 def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q, logl, grad,
                     momentum, dirs, u_leaf, u_tree, prior_lo=None, prior_hi=None, use_graph=True,
-                    stream=None):
-    """One batched NUTS transition, in place on (q, logl, grad).
+                    mask=None, stream=None):
+    """One batched NUTS transition, in place on (q, logl, grad); particles with
+    mask[i] == 0 (uint8 [N], optional) are left as they are.
 
     Returns (depth, steps, status) int32 tensors [N]."""
     offsets, N, q, beta = _pop(prob, offsets, q, beta)
@@ -334,15 +338,83 @@ def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q,
     if prior_lo is not None:
         prior_lo = _dev(prior_lo, torch.float64, "prior_lo", (prob.P,))
         prior_hi = _dev(prior_hi, torch.float64, "prior_hi", (prob.P,))
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
     depth = torch.empty(N, dtype=torch.int32, device=q.device)
     steps = torch.empty_like(depth)
     status = torch.empty_like(depth)
     _check(load_library().smcx_nuts_transition(
         prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta), float(eps), int(max_depth),
         _ptr(prior_lo), _ptr(prior_hi), _ptr(momentum), _ptr(dirs), _ptr(u_leaf), _ptr(u_tree),
-        _ptr(q), _ptr(logl), _ptr(grad), _ptr(depth), _ptr(steps), _ptr(status),
+        _ptr(mask), _ptr(q), _ptr(logl), _ptr(grad), _ptr(depth), _ptr(steps), _ptr(status),
         1 if use_graph else 0, _stream(stream)))
     return depth, steps, status
+
+
+def next_beta(prob: Problem, logl, beta_prev: float, alpha: float, logw_prev=None, beta_out=None,
+              stream=None):
+    """ESS-bisection choice of the next inverse temperature from UNTEMPERED
+    log-likelihoods. Returns (beta_out [N], logw [N], w_norm [N],
+    scalars [4] = beta, ESS, log Z increment, ESS evaluations), all on the device."""
+    logl = _dev(logl, torch.float64, "logl")
+    N = logl.numel()
+    if logw_prev is not None:
+        logw_prev = _dev(logw_prev, torch.float64, "logw_prev", (N,))
+    if beta_out is None:
+        beta_out = torch.empty(N, dtype=torch.float64, device=logl.device)
+    beta_out = _dev(beta_out, torch.float64, "beta_out", (N,))
+    logw = torch.empty_like(logl)
+    w = torch.empty_like(logl)
+    scal = torch.empty(4, dtype=torch.float64, device=logl.device)
+    _check(load_library().smcx_next_beta(prob.handle, N, _ptr(logl), _ptr(logw_prev),
+                                         float(beta_prev), float(alpha), _ptr(beta_out),
+                                         _ptr(logw), _ptr(w), _ptr(scal), _stream(stream)))
+    return beta_out, logw, w, scal
+
+
+def resample_systematic(prob: Problem, offsets, theta, w_norm, u: float, m_cap: int = None,
+                        stream=None):
+    """Systematic resampling. Returns (ancestors int32 [N], offsets_out int64 [N+1],
+    theta_out [m_cap, P]); the new population has offsets_out[N] rows."""
+    offsets, N, theta, _ = _pop(prob, offsets, theta, None)
+    w_norm = _dev(w_norm, torch.float64, "w_norm", (N,))
+    if m_cap is None:
+        m_cap = N * prob.k_max
+    anc = torch.empty(N, dtype=torch.int32, device=theta.device)
+    off = torch.empty(N + 1, dtype=torch.int64, device=theta.device)
+    th = torch.empty((max(int(m_cap), 1), prob.P), dtype=torch.float64, device=theta.device)
+    _check(load_library().smcx_resample_systematic(prob.handle, N, _ptr(offsets), theta.shape[0],
+                                                   _ptr(theta), _ptr(w_norm), float(u),
+                                                   int(m_cap), _ptr(anc), _ptr(off), _ptr(th),
+                                                   _stream(stream)))
+    return anc, off, th
+
+
+def rj_apply(prob: Problem, offsets, theta, move, theta_birth, death_idx, dlogl_birth, dlogl_death,
+             log_u, k_lo: int, k_hi: int, log_pd_over_pb: float = 0.0, m_cap: int = None,
+             stream=None):
+    """Accept/reject birth and death moves. Returns (accepted int8 [N],
+    offsets_out int64 [N+1], theta_out [m_cap, P])."""
+    offsets, N, theta, _ = _pop(prob, offsets, theta, None)
+    move = _dev(move, torch.int8, "move", (N,))
+    log_u = _dev(log_u, torch.float64, "log_u", (N,))
+    if theta_birth is not None:
+        theta_birth = _dev(theta_birth, torch.float64, "theta_birth", (N, prob.P))
+        dlogl_birth = _dev(dlogl_birth, torch.float64, "dlogl_birth", (N,))
+    if death_idx is not None:
+        death_idx = _dev(death_idx, torch.int32, "death_idx", (N,))
+        dlogl_death = _dev(dlogl_death, torch.float64, "dlogl_death", (N,))
+    if m_cap is None:
+        m_cap = theta.shape[0] + N
+    acc = torch.empty(N, dtype=torch.int8, device=theta.device)
+    off = torch.empty(N + 1, dtype=torch.int64, device=theta.device)
+    th = torch.empty((max(int(m_cap), 1), prob.P), dtype=torch.float64, device=theta.device)
+    _check(load_library().smcx_rj_apply(prob.handle, N, _ptr(offsets), theta.shape[0], _ptr(theta),
+                                        _ptr(move), _ptr(theta_birth), _ptr(death_idx),
+                                        _ptr(dlogl_birth), _ptr(dlogl_death), _ptr(log_u),
+                                        int(k_lo), int(k_hi), float(log_pd_over_pb), int(m_cap),
+                                        _ptr(off), _ptr(th), _ptr(acc), _stream(stream)))
+    return acc, off, th
 
 
 class LogLGrad(torch.autograd.Function):

@@ -54,6 +54,13 @@ def test_null_handle_rejected_before_launch(smcx):
     rc = lib.smcx_device_status(None, None)
     assert rc == smcx.SMCX_EINVAL
     assert lib.smcx_problem_destroy(None) == smcx.SMCX_OK
+    rc = lib.smcx_next_beta(None, 4, None, None, 0.0, 0.9, None, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_resample_systematic(None, 4, None, 0, None, None, 0.5, 0, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_rj_apply(None, 4, None, 0, None, None, None, None, None, None, None, 1, 5, 0.0, 0,
+                           None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
 
 
 def test_create_argument_checks(smcx):

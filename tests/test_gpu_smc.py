@@ -1,0 +1,182 @@
+"""SMC steps on the GPU against the oracle, through the C ABI: the
+ESS-bisection temperature, systematic resampling, birth/death accept/reject
+with the population rebuild, and the masked NUTS transition."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import parity as pm
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+PULSE = wl.PULSE
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(lib, w, n_max=None, m_max=None, k_max=None):
+    d = pm.data_of(w)
+    return lib.Problem(w.model, pm.to_dev(d), w.t_start, w.dt, w.sigma, k_max or w.k_max,
+                       n_max or w.N, m_max or max(w.M, 1)), d
+
+
+@pytest.mark.parametrize("N", [1, 777, 65536])
+def test_next_beta_matches_oracle(lib, orc, N):
+    say("next_beta", N)
+    w = wl.make_config("pulse_small", N=1, T=64)
+    prob, _ = _problem(lib, w, n_max=N)
+    rng = np.random.default_rng(N)
+    logl = -0.5 * rng.chisquare(4096, size=N)
+    for beta_prev, alpha, prev in ((0.0, 0.9, False), (0.02, 0.9, False), (0.3, 0.5, True),
+                                   (1.0, 0.9, False)):
+        lwp = rng.normal(0.0, 0.2, size=N) if prev else None
+        bo, logw, wn, sc = lib.next_beta(prob, pm.to_dev(logl), beta_prev, alpha,
+                                         logw_prev=None if lwp is None else pm.to_dev(lwp))
+        torch.cuda.synchronize()
+        bo, logw, wn, sc = (x.cpu().numpy() for x in (bo, logw, wn, sc))
+        rlogw, rw, rsc = orc.next_beta(logl, beta_prev, alpha, logw_prev=lwp)
+        db = abs(sc[0] - rsc[0])
+        assert db <= 1e-9 * max(rsc[0] - beta_prev, 1e-12), (sc[0], rsc[0])
+        assert np.all(bo == sc[0])
+        assert abs(sc[1] - rsc[1]) <= 1e-9 * N + db * N * 1e3
+        tol_lw = db * np.abs(logl).max() + 1e-12 * np.abs(rlogw).max() + 1e-300
+        assert np.all(np.abs(logw - rlogw) <= tol_lw)
+        assert np.all(np.abs(wn - rw) <= rw * 2 * tol_lw + 1e-15)
+        assert abs(sc[2] - rsc[2]) <= tol_lw + 1e-12
+        if N > 1 and sc[0] < 1.0:
+            assert sc[1] >= alpha * N
+
+
+def test_next_beta_two_point_closed_form_on_gpu(lib):
+    N0, N1, L, alpha = 300, 700, 50.0, 0.9
+    w = wl.make_config("pulse_small", N=1, T=64)
+    prob, _ = _problem(lib, w, n_max=N0 + N1)
+    logl = np.concatenate([np.zeros(N0), np.full(N1, -L)])
+    roots = np.roots([N1 * (N1 - alpha * (N0 + N1)), 2.0 * N0 * N1, N0 * (N0 - alpha * (N0 + N1))])
+    x = [r.real for r in roots if abs(r.imag) < 1e-12 and 0 < r.real < 1][0]
+    _, _, _, sc = lib.next_beta(prob, pm.to_dev(logl), 0.0, alpha)
+    torch.cuda.synchronize()
+    assert abs(sc[0].item() + np.log(x) / L) <= 1e-12 * (-np.log(x) / L)
+
+
+def _weights(rng, N, kind):
+    if kind == "dirichlet":
+        return rng.dirichlet(np.full(N, 0.3))
+    if kind == "uniform":
+        return np.full(N, 1.0 / N)
+    W = np.zeros(N)
+    W[rng.integers(N)] = 1.0
+    return W
+
+
+@pytest.mark.parametrize("kind,u", [("dirichlet", 0.4183), ("dirichlet", 0.0), ("uniform", 0.0),
+                                    ("uniform", 0.999), ("one", 0.5)])
+def test_resample_is_bit_exact(lib, orc, kind, u):
+    w = wl.make_config("pulse_small", N=5000, T=64, k_lo=0, k_hi=9, seed=21)
+    say("resample", kind, u)
+    prob, _ = _problem(lib, w)
+    rng = np.random.default_rng(22)
+    W = _weights(rng, w.N, kind)
+    ranc, roff, rth = orc.resample_systematic(PULSE, w.offsets, w.theta, W, u,
+                                              m_cap=w.N * w.k_max)
+    anc, off, th = lib.resample_systematic(prob, pm.to_dev(w.offsets), pm.to_dev(w.theta),
+                                           pm.to_dev(W), u)
+    torch.cuda.synchronize()
+    prob.device_status()
+    anc, off, th = anc.cpu().numpy(), off.cpu().numpy(), th.cpu().numpy()
+    assert np.array_equal(anc, ranc)
+    assert np.array_equal(off, roff)
+    assert np.array_equal(th[:off[-1]], rth)
+
+
+def test_resample_capacity_and_zero_weights(lib, orc):
+    w = wl.make_config("pulse_small", N=3000, T=64, k_lo=1, k_hi=6, seed=23)
+    say("resample_capacity")
+    prob, _ = _problem(lib, w)
+    rng = np.random.default_rng(24)
+    W = rng.dirichlet(np.ones(w.N))
+    ranc, roff, rth = orc.resample_systematic(PULSE, w.offsets, w.theta, W, 0.25,
+                                              m_cap=w.N * w.k_max)
+    cap = int(roff[-1]) - 7
+    anc, off, th = lib.resample_systematic(prob, pm.to_dev(w.offsets), pm.to_dev(w.theta),
+                                           pm.to_dev(W), 0.25, m_cap=cap)
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError, match="m_cap"):
+        prob.device_status()
+    assert np.array_equal(off.cpu().numpy(), roff)  # offsets are complete
+    assert np.array_equal(th.cpu().numpy()[:cap], rth[:cap])  # rows up to the capacity
+    anc, off, _ = lib.resample_systematic(prob, pm.to_dev(w.offsets), pm.to_dev(w.theta),
+                                          pm.to_dev(np.zeros(w.N)), 0.25)
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError, match="positive"):
+        prob.device_status()
+    assert np.array_equal(anc.cpu().numpy(), np.arange(w.N))
+
+
+def test_rj_apply_is_bit_exact(lib, orc):
+    w = wl.make_config("pulse_mutate", N=6000, T=1024, k_lo=0, k_hi=8, rj=True, seed=25)
+    say("rj_apply")
+    prob, d = _problem(lib, w, k_max=10)
+    rng = np.random.default_rng(26)
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(w.beta)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    # the changes come from the GPU path; both sides take the same decisions from them
+    db, dd = lib.delta_logl_birth_death(prob, off, th, be, pm.to_dev(tb), pm.to_dev(di))
+    torch.cuda.synchronize()
+    db, dd = db.cpu().numpy(), dd.cpu().numpy()
+    move = rng.integers(0, 3, size=w.N).astype(np.int8)
+    log_u = np.log(rng.random(w.N))
+    log_u[::11] = np.log(0.5)
+    for k_lo, k_hi, lr in ((1, 8, 0.0), (0, 10, 0.3)):
+        racc, roff, rth = orc.rj_apply(PULSE, w.offsets, w.theta, move, tb, di, db, dd, log_u,
+                                       k_lo, k_hi, lr)
+        acc, off2, th2 = lib.rj_apply(prob, off, th, pm.to_dev(move), pm.to_dev(tb),
+                                      pm.to_dev(di), pm.to_dev(db), pm.to_dev(dd),
+                                      pm.to_dev(log_u), k_lo, k_hi, lr)
+        torch.cuda.synchronize()
+        prob.device_status()
+        acc, off2, th2 = acc.cpu().numpy(), off2.cpu().numpy(), th2.cpu().numpy()
+        assert np.array_equal(acc, racc)
+        assert np.array_equal(off2, roff)
+        assert np.array_equal(th2[:off2[-1]], rth)
+        assert 0 < acc.sum() < w.N
+
+
+def test_nuts_mask_leaves_masked_particles_alone(lib, orc):
+    w = wl.make_config("pulse_mutate", N=400, T=2048, seed=27)
+    say("nuts_mask")
+    prob, d = _problem(lib, w)
+    D = 5
+    lib.nuts_reserve(prob, D)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, w.P, D, 28)
+    dev = [pm.to_dev(x) for x in (mom, dirs, ul, ut)]
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(w.beta)
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    lo = pm.to_dev(wl.PULSE_PRIOR[:, 0].copy())
+    hi = pm.to_dev(wl.PULSE_PRIOR[:, 1].copy())
+    mask = (np.random.default_rng(29).random(w.N) < 0.6).astype(np.uint8)
+    outs = []
+    for m in (None, pm.to_dev(mask)):
+        q, l, g = th.clone(), l0.clone(), g0.clone()
+        depth, steps, status = lib.nuts_transition(prob, off, be, 2e-4, D, q, l, g, *dev, lo, hi,
+                                                   mask=m)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (q, l, g, depth, steps, status)])
+    (q0, l0n, g0n, d0, s0, st0), (q1, l1, g1, d1, s1, st1) = outs
+    on = mask.astype(bool)
+    rows_on = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in np.nonzero(on)[0]])
+    rows_off = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1])
+                               for i in np.nonzero(~on)[0]])
+    # unmasked particles: the same bits as without a mask
+    assert np.array_equal(q1[rows_on], q0[rows_on]) and np.array_equal(g1[rows_on], g0n[rows_on])
+    assert np.array_equal(l1[on], l0n[on]) and np.array_equal(st1[on], st0[on])
+    # masked particles: untouched, status 0, no steps
+    assert np.array_equal(q1[rows_off], w.theta[rows_off])
+    assert np.array_equal(g1[rows_off], g0.cpu().numpy()[rows_off])
+    assert np.array_equal(l1[~on], l0.cpu().numpy()[~on])
+    assert np.all(st1[~on] == 0) and np.all(s1[~on] == 0)
