@@ -1,0 +1,144 @@
+"""Prior-start SMC driver over the C ABI (Sec. "Algorithm and implementation").
+
+One run draws N particles from the prior (K uniform on [k_lo, k_hi], each
+component uniform in the prior box) at beta = 0 and repeats until beta = 1:
+
+1. choose the next beta by the ESS condition (eq. ess_target) and reweight
+   (eq. incremental_weight), accumulating the evidence: ``smcx_next_beta``;
+2. resample systematically by the normalised weights: ``smcx_resample_systematic``;
+3. mutate every particle ``n_mutations`` times with the mixture kernel of
+   eq. kernel_mixture: with probability p_nuts a NUTS transition of the
+   tempered target (``smcx_nuts_transition`` with a mask), otherwise a birth
+   (a component drawn from the prior) or the death of a uniformly chosen
+   component, scored by ``delta_logl_birth_death`` and accepted or rejected
+   by ``smcx_rj_apply``.
+
+All arithmetic runs in the library's kernels. This module draws the random
+inputs on the device (a seeded torch generator) and sequences the calls; it
+synchronises with the host a few times per iteration (to read beta and the
+new row count).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import torch
+
+from . import smcx
+
+
+@dataclass
+class SMCConfig:
+    N: int
+    k_lo: int = 1
+    k_hi: int = 10
+    alpha: float = 0.9                 # ESS fraction kept per iteration
+    p_nuts: float = 0.6                # mixture weights of eq. kernel_mixture
+    p_birth: float = 0.2
+    p_death: float = 0.2
+    n_mutations: int = 4               # mixture-kernel steps per SMC iteration
+    max_depth: int = 6                 # NUTS tree depth
+    eps: Callable[[float], float] = field(default=lambda beta: 3e-4 / math.sqrt(max(beta, 1e-4)))
+    max_iters: int = 200
+    seed: int = 0
+
+
+@dataclass
+class SMCResult:
+    offsets: torch.Tensor              # final population (CSR), on the device
+    theta: torch.Tensor
+    betas: list
+    ess: list
+    log_evidence: float                # sum of the log Z increments
+    k_hist: list                       # per iteration: counts of K = 0..k_hi after mutation
+    rj_accept: list                    # per iteration: accepted fraction of birth/death moves
+    nuts_steps: list                   # per iteration: leapfrog steps of the NUTS moves
+
+    @property
+    def iterations(self) -> int:
+        return len(self.betas)
+
+
+def run_prior_start(prob: smcx.Problem, prior_lo: torch.Tensor, prior_hi: torch.Tensor,
+                    cfg: SMCConfig, on_iteration: Optional[Callable[[int, dict], None]] = None
+                    ) -> SMCResult:
+    """Run the prior-start SMC of the paper's Sec. "Algorithm and implementation"
+    on the problem's data. The handle needs n_max >= N, k_max >= k_hi and
+    m_max >= N k_hi; prior_lo, prior_hi are the [P] box of the uniform prior
+    (on the device)."""
+    if not (cfg.N <= prob.n_max and cfg.k_hi <= prob.k_max and cfg.N * cfg.k_hi <= prob.m_max):
+        raise ValueError("the problem handle is too small for this SMC configuration")
+    if abs(cfg.p_nuts + cfg.p_birth + cfg.p_death - 1.0) > 1e-12:
+        raise ValueError("mixture weights must sum to 1")
+    dev = prior_lo.device
+    P, N, D = prob.P, cfg.N, cfg.max_depth
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(cfg.seed)
+    smcx.nuts_reserve(prob, D)
+    lo, hi = prior_lo.to(torch.float64).contiguous(), prior_hi.to(torch.float64).contiguous()
+    f64 = dict(dtype=torch.float64, device=dev)
+
+    def prior_rows(n: int) -> torch.Tensor:
+        return (lo + torch.rand((n, P), generator=gen, **f64) * (hi - lo)).contiguous()
+
+    K = torch.randint(cfg.k_lo, cfg.k_hi + 1, (N,), generator=gen, device=dev)
+    off = torch.zeros(N + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(K, 0)
+    M = int(off[-1])
+    th = prior_rows(M)
+    log_ratio = math.log(cfg.p_death / cfg.p_birth)
+    beta = 0.0
+    res = SMCResult(off, th, [], [], 0.0, [], [], [])
+    for it in range(cfg.max_iters):
+        logl = smcx.logl_batch(prob, off, th)  # untempered
+        beta_arr, _, w_norm, sc = smcx.next_beta(prob, logl, beta, cfg.alpha)
+        beta, ess, dlogz = (float(x) for x in sc[:3].cpu())
+        res.betas.append(beta)
+        res.ess.append(ess)
+        res.log_evidence += dlogz
+        u = float(torch.rand(1, generator=gen, **f64))
+        _, off, th_all = smcx.resample_systematic(prob, off, th, w_norm, min(u, 1.0 - 2**-53),
+                                                  m_cap=N * cfg.k_hi)
+        M = int(off[-1])
+        th = th_all[:M]
+        acc_rj = tried_rj = steps = 0
+        eps = float(cfg.eps(beta))
+        for _ in range(cfg.n_mutations):
+            r = torch.rand(N, generator=gen, **f64)
+            nuts = r < cfg.p_nuts
+            move = torch.where(nuts, 0, torch.where(r < cfg.p_nuts + cfg.p_birth, 1, 2)).to(torch.int8)
+            if M > 0:
+                l, g = smcx.logl_grad_batch(prob, off, th, beta_arr)
+                mom = torch.randn((M, P), generator=gen, **f64)
+                dirs = (torch.randint(0, 2, (N, D), generator=gen, device=dev) * 2 - 1).to(torch.int8)
+                ul = torch.rand((N, (1 << D) - 1), generator=gen, **f64)
+                ut = torch.rand((N, D), generator=gen, **f64)
+                _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
+                                                ul, ut, lo, hi, mask=nuts.to(torch.uint8))
+                steps += int(st.sum())
+            Kc = off[1:] - off[:-1]
+            tb = prior_rows(N)
+            di = torch.floor(torch.rand(N, generator=gen, **f64) * Kc).to(torch.int32)
+            di = torch.where(Kc > 0, di, torch.full_like(di, -1))
+            db, dd = smcx.delta_logl_birth_death(prob, off, th, beta_arr, tb, di)
+            log_u = torch.log(torch.rand(N, generator=gen, **f64))
+            acc, off, th_all = smcx.rj_apply(prob, off, th, move, tb, di, db, dd, log_u, cfg.k_lo,
+                                             cfg.k_hi, log_ratio, m_cap=M + N)
+            M = int(off[-1])
+            th = th_all[:M]
+            acc_rj += int(acc.sum())
+            tried_rj += int((~nuts).sum())
+        Kc = (off[1:] - off[:-1]).cpu()
+        res.k_hist.append(torch.bincount(Kc, minlength=cfg.k_hi + 1).tolist())
+        res.rj_accept.append(acc_rj / max(tried_rj, 1))
+        res.nuts_steps.append(steps)
+        if on_iteration:
+            on_iteration(it, dict(beta=beta, ess=ess, k_hist=res.k_hist[-1],
+                                  rj_accept=res.rj_accept[-1], nuts_steps=steps))
+        if beta >= 1.0:
+            break
+    prob.device_status()
+    res.offsets, res.theta = off, th
+    return res
