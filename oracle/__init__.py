@@ -77,6 +77,13 @@ def _load():
         lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
         lib.oracle_nuts_transition.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P, P, P, P,
                                                P, P, P, P, P, P]
+        lib.oracle_logl_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P]
+        lib.oracle_logl_grad_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P, P]
+        lib.oracle_delta_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, I64, P, P]
+        lib.oracle_leapfrog_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, I64, P, P,
+                                              P, P]
+        lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
+                                                     P, P, P, I64, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -245,3 +252,65 @@ def rj_apply(model, offsets, theta, move, theta_birth, death_idx, dlogl_birth, d
                                    int(k_lo), int(k_hi), float(log_pd_over_pb), m_cap, _p(off),
                                    _p(th), _p(acc)), "rj_apply")
     return acc, off, th[:off[-1]].copy()
+
+
+# ---- posterior-start bridge: samples s < split untempered, s >= split tempered by beta
+def logl_split(model, d, t_start, dt, sigma, offsets, theta, beta, split):
+    d, offsets, theta, beta = _f64(d), _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    out = np.empty(N)
+    _check(_load().oracle_logl_split(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                                     _p(theta), _p(beta), int(split), _p(out)), "logl_split")
+    return out
+
+
+def logl_grad_split(model, d, t_start, dt, sigma, offsets, theta, beta, split):
+    d, offsets, theta, beta = _f64(d), _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    out = np.empty(N)
+    grad = np.empty((int(offsets[-1]), n_params(model)))
+    _check(_load().oracle_logl_grad_split(model, _p(d), d.shape[0], t_start, dt, sigma, N,
+                                          _p(offsets), _p(theta), _p(beta), int(split), _p(out),
+                                          _p(grad)), "logl_grad_split")
+    return out, grad
+
+
+def delta_split(model, d, t_start, dt, sigma, offsets, theta, beta, theta_birth, death_idx, split):
+    d, offsets, theta, beta, theta_birth = _f64(d), _i64(offsets), _f64(theta), _f64(beta), \
+        _f64(theta_birth)
+    death_idx = None if death_idx is None else np.ascontiguousarray(death_idx, dtype=np.int32)
+    N = offsets.shape[0] - 1
+    db, dd = np.zeros(N), np.zeros(N)
+    _check(_load().oracle_delta_split(model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets),
+                                      _p(theta), _p(beta), _p(theta_birth), _p(death_idx),
+                                      int(split), _p(db), _p(dd)), "delta_split")
+    return db, dd
+
+
+def leapfrog_split(model, d, t_start, dt, sigma, offsets, q, p, beta, eps, split, active=None):
+    d, offsets, q, p, beta = _f64(d), _i64(offsets), _f64(q), _f64(p), _f64(beta)
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    N = offsets.shape[0] - 1
+    qo, po, lo, go = np.empty_like(q), np.empty_like(p), np.empty(N), np.empty_like(q)
+    _check(_load().oracle_leapfrog_split(model, _p(d), d.shape[0], t_start, dt, sigma, N,
+                                         _p(offsets), _p(q), _p(p), _p(beta), eps, _p(act),
+                                         int(split), _p(qo), _p(po), _p(lo), _p(go)),
+           "leapfrog_split")
+    return qo, po, lo, go
+
+
+def nuts_transition_split(model, d, t_start, dt, sigma, offsets, beta, eps, max_depth, q, logl,
+                          grad, momentum, dirs, u_leaf, u_tree, split, prior_lo=None,
+                          prior_hi=None):
+    d, offsets, beta = _f64(d), _i64(offsets), _f64(beta)
+    q, logl, grad = (np.array(x, dtype=np.float64, order="C", copy=True) for x in (q, logl, grad))
+    momentum, u_leaf, u_tree = _f64(momentum), _f64(u_leaf), _f64(u_tree)
+    dirs = np.ascontiguousarray(dirs, dtype=np.int8)
+    lo, hi = _f64(prior_lo), _f64(prior_hi)
+    N = offsets.shape[0] - 1
+    depth, steps, status = (np.zeros(N, dtype=np.int32) for _ in range(3))
+    _check(_load().oracle_nuts_transition_split(
+        model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets), _p(beta), eps,
+        int(max_depth), _p(lo), _p(hi), _p(momentum), _p(dirs), _p(u_leaf), _p(u_tree), int(split),
+        _p(q), _p(logl), _p(grad), _p(depth), _p(steps), _p(status)), "nuts_transition_split")
+    return q, logl, grad, depth, steps, status

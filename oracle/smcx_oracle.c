@@ -213,6 +213,133 @@ int oracle_logl_grad(int model, const double* d, int64_t T, double t_start, doub
   return OR_OK;
 }
 
+/* ---- posterior-start bridge (eq. reuse_bridge) ----
+ * For white noise the likelihood factorises over samples, so the bridge
+ * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta between the posterior on the
+ * first `split` samples (d1) and the posterior on all T samples (d2) has the
+ * log-likelihood part
+ *   logL_split = -(1/(2 sigma^2)) [ sum_{s<split} r_s^2 + beta sum_{s>=split} r_s^2 ]
+ * i.e. samples before the split enter untempered and the later ones tempered
+ * by beta. split = 0 is the prior bridge (eq. prior_bridge), split = T the
+ * untempered posterior. The functions below are the tempered ones above
+ * with that per-sample weight. */
+static double sample_weight(int64_t s, int64_t split, double b) { return s < split ? 1.0 : b; }
+
+int oracle_logl_split(int model, const double* d, int64_t T, double t_start, double dt,
+                      double sigma, int64_t N, const int64_t* offsets, const double* theta,
+                      const double* beta, int64_t split, double* logl) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d) ||
+      (N > 0 && !logl) || split < 0)
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double b = beta ? beta[i] : 1.0;
+    double ss = 0.0;
+    for (int64_t s = 0; s < T; ++s) {
+      double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+      ss += sample_weight(s, split, b) * (r * r);
+    }
+    logl[i] = -0.5 * ss / (sigma * sigma);
+  }
+  return OR_OK;
+}
+
+static void particle_logl_grad_split(int model, const double* d, int64_t T, double t_start,
+                                     double dt, double sigma, int64_t K, const double* th,
+                                     double b, int64_t split, double* logl, double* g) {
+  int P = oracle_n_params(model);
+  double ss = 0.0;
+  for (int64_t k = 0; k < K * P; ++k) g[k] = 0.0;
+  for (int64_t s = 0; s < T; ++s) {
+    double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+    double ws = sample_weight(s, split, b);
+    ss += ws * (r * r);
+    double t = t_start + (double)s * dt;
+    for (int64_t k = 0; k < K; ++k) {
+      double dh[4];
+      template_partials(model, th + k * P, t, dh);
+      for (int p = 0; p < P; ++p) g[k * P + p] += ws * (r * dh[p]);
+    }
+  }
+  for (int64_t k = 0; k < K * P; ++k) g[k] = g[k] / (sigma * sigma);
+  *logl = -0.5 * ss / (sigma * sigma);
+}
+
+int oracle_logl_grad_split(int model, const double* d, int64_t T, double t_start, double dt,
+                           double sigma, int64_t N, const int64_t* offsets, const double* theta,
+                           const double* beta, int64_t split, double* logl, double* grad) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d) ||
+      split < 0)
+    return OR_EINVAL;
+  if (N > 0 && offsets[N] > 0 && !grad) return OR_EINVAL;
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double l;
+    particle_logl_grad_split(model, d, T, t_start, dt, sigma, K, th, beta ? beta[i] : 1.0, split,
+                             &l, grad ? grad + offsets[i] * P : NULL);
+    if (logl) logl[i] = l;
+  }
+  return OR_OK;
+}
+
+/* Birth/death changes of logL_split: the inner products of
+ * oracle_delta_logl_birth_death with the per-sample weight. */
+int oracle_delta_split(int model, const double* d, int64_t T, double t_start, double dt,
+                       double sigma, int64_t N, const int64_t* offsets, const double* theta,
+                       const double* beta, const double* theta_birth, const int32_t* death_idx,
+                       int64_t split, double* d_birth, double* d_death) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || (T > 0 && !d) ||
+      split < 0)
+    return OR_EINVAL;
+  if (N > 0 && ((theta_birth && !d_birth) || (death_idx && !d_death))) return OR_EINVAL;
+  for (int64_t i = 0; death_idx && i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    if (death_idx[i] < -1 || death_idx[i] >= K) return OR_EINVAL;
+  }
+  int P = oracle_n_params(model);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double b = beta ? beta[i] : 1.0;
+    if (theta_birth) {
+      const double* tb = theta_birth + i * P;
+      double x = 0.0, y = 0.0;
+      for (int64_t s = 0; s < T; ++s) {
+        double r = residual_at(model, d, t_start, dt, s, K, th, P, -1);
+        double h = template_value(model, tb, t_start + (double)s * dt);
+        double ws = sample_weight(s, split, b);
+        x += ws * (r * h);
+        y += ws * (h * h);
+      }
+      d_birth[i] = (x - 0.5 * y) / (sigma * sigma);
+    }
+    if (death_idx) {
+      int64_t j = death_idx[i];
+      if (j < 0) {
+        d_death[i] = 0.0;
+      } else {
+        double x = 0.0, y = 0.0;
+        for (int64_t s = 0; s < T; ++s) {
+          double r = residual_at(model, d, t_start, dt, s, K, th, P, j);
+          double h = template_value(model, th + j * P, t_start + (double)s * dt);
+          double ws = sample_weight(s, split, b);
+          x += ws * (r * h);
+          y += ws * (h * h);
+        }
+        d_death[i] = -((x - 0.5 * y) / (sigma * sigma));
+      }
+    }
+  }
+  return OR_OK;
+}
+
 /* Change of tempered log-likelihood for the nested birth/death moves of
  * Sec. "Reversible Jump MCMC" (k' = k +- 1, unit Jacobian):
  *   birth of theta_new appended at index K:
@@ -355,17 +482,29 @@ int oracle_reweight_extend(int model, const double* d, double t_start, double dt
  *   p'     = p_half + (eps/2) grad(beta logL)(q')
  * Particles with active[i] == 0 (active may be NULL = all active) are copied
  * unchanged. Outputs q', p' and the tempered logL and gradient at q'. */
-int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, double dt,
-                    double sigma, int64_t N, const int64_t* offsets, const double* q,
-                    const double* p, const double* beta, double eps, const uint8_t* active,
-                    double* q_out, double* p_out, double* logl_out, double* grad_out) {
+/* Population gradient of the tempered target: the prior bridge when
+ * split == 0, the posterior-start bridge otherwise. */
+static int target_logl_grad(int model, const double* d, int64_t T, double t_start, double dt,
+                            double sigma, int64_t N, const int64_t* offsets, const double* q,
+                            const double* beta, int64_t split, double* logl, double* grad) {
+  if (split == 0)
+    return oracle_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q, beta, logl, grad);
+  return oracle_logl_grad_split(model, d, T, t_start, dt, sigma, N, offsets, q, beta, split, logl,
+                                grad);
+}
+
+static int leapfrog_impl(int model, const double* d, int64_t T, double t_start, double dt,
+                         double sigma, int64_t N, const int64_t* offsets, const double* q,
+                         const double* p, const double* beta, double eps, const uint8_t* active,
+                         int64_t split, double* q_out, double* p_out, double* logl_out,
+                         double* grad_out) {
   if (check_population(model, N, offsets, q) != OR_OK || T < 0 || (T > 0 && !d)) return OR_EINVAL;
   int64_t M = N > 0 ? offsets[N] : 0;
   if (M > 0 && (!p || !q_out || !p_out || !grad_out)) return OR_EINVAL;
   if (N > 0 && !logl_out) return OR_EINVAL;
   int P = oracle_n_params(model);
   /* gradient at the start point, into grad_out as scratch */
-  int rc = oracle_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q, beta, logl_out,
+  int rc = target_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q, beta, split, logl_out,
                             grad_out);
   if (rc != OR_OK) return rc;
   for (int64_t i = 0; i < N; ++i) {
@@ -381,7 +520,7 @@ int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, doubl
       }
     }
   }
-  rc = oracle_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q_out, beta, logl_out,
+  rc = target_logl_grad(model, d, T, t_start, dt, sigma, N, offsets, q_out, beta, split, logl_out,
                         grad_out);
   if (rc != OR_OK) return rc;
   for (int64_t i = 0; i < N; ++i) {
@@ -391,6 +530,25 @@ int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, doubl
       p_out[m] = p_out[m] + 0.5 * eps * grad_out[m];
   }
   return OR_OK;
+}
+
+int oracle_leapfrog(int model, const double* d, int64_t T, double t_start, double dt,
+                    double sigma, int64_t N, const int64_t* offsets, const double* q,
+                    const double* p, const double* beta, double eps, const uint8_t* active,
+                    double* q_out, double* p_out, double* logl_out, double* grad_out) {
+  return leapfrog_impl(model, d, T, t_start, dt, sigma, N, offsets, q, p, beta, eps, active, 0,
+                       q_out, p_out, logl_out, grad_out);
+}
+
+/* The leapfrog step for the posterior-start bridge target (split > 0). */
+int oracle_leapfrog_split(int model, const double* d, int64_t T, double t_start, double dt,
+                          double sigma, int64_t N, const int64_t* offsets, const double* q,
+                          const double* p, const double* beta, double eps, const uint8_t* active,
+                          int64_t split, double* q_out, double* p_out, double* logl_out,
+                          double* grad_out) {
+  if (split < 0) return OR_EINVAL;
+  return leapfrog_impl(model, d, T, t_start, dt, sigma, N, offsets, q, p, beta, eps, active, split,
+                       q_out, p_out, logl_out, grad_out);
 }
 
 /* One No-U-Turn transition per particle (Sec. "No-U-Turn-Sampler"; the
@@ -438,13 +596,12 @@ static int inside_box(const double* q, int64_t n, int P, const double* lo, const
 #include <stdlib.h>
 #include <string.h>
 
-int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start, double dt,
-                           double sigma, int64_t N, const int64_t* offsets, const double* beta,
-                           double eps, int max_depth, const double* prior_lo,
-                           const double* prior_hi, const double* momentum, const int8_t* dirs,
-                           const double* u_leaf, const double* u_tree, double* q, double* logl,
-                           double* grad, int32_t* depth_out, int32_t* steps_out,
-                           int32_t* status_out) {
+static int nuts_impl(int model, const double* d, int64_t T, double t_start, double dt,
+                     double sigma, int64_t N, const int64_t* offsets, const double* beta,
+                     double eps, int max_depth, const double* prior_lo, const double* prior_hi,
+                     const double* momentum, const int8_t* dirs, const double* u_leaf,
+                     const double* u_tree, int64_t split, double* q, double* logl, double* grad,
+                     int32_t* depth_out, int32_t* steps_out, int32_t* status_out) {
   if (check_population(model, N, offsets, q) != OR_OK || max_depth < 1 || max_depth > 16)
     return OR_EINVAL;
   int P = oracle_n_params(model);
@@ -499,7 +656,10 @@ int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start
             pF[x] = pF[x] + 0.5 * e * gF[x];
             qF[x] = qF[x] + e * pF[x];
           }
-          particle_logl_grad(model, d, T, t_start, dt, sigma, K, qF, b, &lF, gF);
+          if (split == 0)
+            particle_logl_grad(model, d, T, t_start, dt, sigma, K, qF, b, &lF, gF);
+          else
+            particle_logl_grad_split(model, d, T, t_start, dt, sigma, K, qF, b, split, &lF, gF);
           for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * gF[x];
           steps += 1;
           double H = inside_box(qF, n, P, prior_lo, prior_hi) ? -lF + 0.5 * dot(pF, pF, n)
@@ -560,6 +720,33 @@ int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start
     free(buf);
   }
   return OR_OK;
+}
+
+int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start, double dt,
+                           double sigma, int64_t N, const int64_t* offsets, const double* beta,
+                           double eps, int max_depth, const double* prior_lo,
+                           const double* prior_hi, const double* momentum, const int8_t* dirs,
+                           const double* u_leaf, const double* u_tree, double* q, double* logl,
+                           double* grad, int32_t* depth_out, int32_t* steps_out,
+                           int32_t* status_out) {
+  return nuts_impl(model, d, T, t_start, dt, sigma, N, offsets, beta, eps, max_depth, prior_lo,
+                   prior_hi, momentum, dirs, u_leaf, u_tree, 0, q, logl, grad, depth_out, steps_out,
+                   status_out);
+}
+
+/* The NUTS transition for the posterior-start bridge target (split > 0). */
+int oracle_nuts_transition_split(int model, const double* d, int64_t T, double t_start, double dt,
+                                 double sigma, int64_t N, const int64_t* offsets,
+                                 const double* beta, double eps, int max_depth,
+                                 const double* prior_lo, const double* prior_hi,
+                                 const double* momentum, const int8_t* dirs, const double* u_leaf,
+                                 const double* u_tree, int64_t split, double* q, double* logl,
+                                 double* grad, int32_t* depth_out, int32_t* steps_out,
+                                 int32_t* status_out) {
+  if (split < 0) return OR_EINVAL;
+  return nuts_impl(model, d, T, t_start, dt, sigma, N, offsets, beta, eps, max_depth, prior_lo,
+                   prior_hi, momentum, dirs, u_leaf, u_tree, split, q, logl, grad, depth_out,
+                   steps_out, status_out);
 }
 
 /* ------------------------------------------------------------------ SMC steps

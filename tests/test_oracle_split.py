@@ -1,0 +1,154 @@
+"""Pins of the oracle's posterior-start bridge target (eq. reuse_bridge): with
+white noise its log-likelihood part is logL over samples [0, split) plus beta
+times logL over [split, T).
+
+Pinned by 40-digit brute force of that definition (value, gradient by
+differentiating the brute force, birth/death by differences), by its limits
+(split = T is the untempered likelihood whatever beta is; split = 0 is the
+tempered prior bridge) and by the exact birth-then-death invariant.
+"""
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_2609_17674_amd import workloads as wl
+
+PULSE, GB = wl.PULSE, wl.GBSINE
+
+
+def mp_seg(model, d, t_start, dt, sigma, comps, lo, hi):
+    ss = mp.mpf(0)
+    for s in range(lo, hi):
+        t = mp.mpf(t_start) + s * mp.mpf(dt)
+        h = mp.mpf(0)
+        for c in comps:
+            c = [x if isinstance(x, mp.mpf) else mp.mpf(float(x)) for x in c]
+            if model == PULSE:
+                A, t0, w = c
+                h += A * mp.exp(-(t - t0) ** 2 / (2 * w * w))
+            else:
+                A, f0, fd, p0 = c
+                h += A * mp.sin(2 * mp.pi * f0 * t + mp.pi * fd * t * t + p0)
+        r = mp.mpf(float(d[s])) - h
+        ss += r * r
+    return -ss / (2 * mp.mpf(sigma) ** 2)
+
+
+def mp_split(model, d, t_start, dt, sigma, comps, beta, split):
+    return (mp_seg(model, d, t_start, dt, sigma, comps, 0, split)
+            + mp.mpf(beta) * mp_seg(model, d, t_start, dt, sigma, comps, split, len(d)))
+
+
+def problem(orc, model, seed, T):
+    rng = np.random.default_rng(seed)
+    dt = 1.0 / (T - 1) if model == PULSE else 15.0
+    inj = wl.draw_components(model, 2, rng)
+    K = np.array([0, 1, 3, 2])
+    off = wl.counts_to_offsets(K)
+    theta = wl.draw_components(model, int(off[-1]), rng)
+    d = 0.5 * rng.standard_normal(T) + orc.template_sum(model, inj, T, 0.0, dt)
+    return rng, dt, d, K, off, theta
+
+
+@pytest.mark.parametrize("model", [PULSE, GB])
+def test_split_target_brute_force(orc, model):
+    mp.mp.dps = 40
+    T, split = 96, 41
+    rng, dt, d, K, off, theta = problem(orc, model, 50 + model, T)
+    beta = np.array([0.3, 1.0, 0.55, 0.0])
+    sigma = 0.8
+    l1 = orc.logl_split(model, d, 0.0, dt, sigma, off, theta, beta, split)
+    l2, g = orc.logl_grad_split(model, d, 0.0, dt, sigma, off, theta, beta, split)
+    assert np.array_equal(l1, l2)
+    P = theta.shape[1]
+    for i in range(len(K)):
+        comps = [theta[m] for m in range(off[i], off[i + 1])]
+        ref = mp_split(model, d, 0.0, dt, sigma, comps, beta[i], split)
+        assert abs(l1[i] - float(ref)) <= 1e-12 * abs(float(ref)), (i, l1[i], float(ref))
+        for k in range(K[i]):
+            for p in range(P):
+                def f(v, k=k, p=p):
+                    cs = [[mp.mpf(float(x)) for x in c] for c in comps]
+                    cs[k][p] = v
+                    return mp_split(model, d, 0.0, dt, sigma, cs, beta[i], split)
+                gref = float(mp.diff(f, mp.mpf(float(comps[k][p]))))
+                got = g[off[i] + k, p]
+                # 40-digit differentiation cannot resolve gradients below ~1e-30
+                assert abs(got - gref) <= 1e-10 * abs(gref) + 1e-20, (i, k, p, got, gref)
+    tb = wl.draw_components(model, len(K), rng)
+    death = np.array([-1, 0, 2, 1], dtype=np.int32)
+    db, dd = orc.delta_split(model, d, 0.0, dt, sigma, off, theta, beta, tb, death, split)
+    for i in range(len(K)):
+        comps = [theta[m] for m in range(off[i], off[i + 1])]
+        base = mp_split(model, d, 0.0, dt, sigma, comps, beta[i], split)
+        ref_b = float(mp_split(model, d, 0.0, dt, sigma, comps + [tb[i]], beta[i], split) - base)
+        assert abs(db[i] - ref_b) <= 1e-11 * (abs(ref_b) + 1e-3 * abs(float(base)))
+        if death[i] >= 0:
+            kept = [c for j, c in enumerate(comps) if j != death[i]]
+            ref_d = float(mp_split(model, d, 0.0, dt, sigma, kept, beta[i], split) - base)
+            assert abs(dd[i] - ref_d) <= 1e-11 * (abs(ref_d) + 1e-3 * abs(float(base)))
+        else:
+            assert dd[i] == 0.0
+
+
+def test_split_limits(orc):
+    """split = T: the untempered likelihood for any beta; split = 0: the
+    tempered prior bridge."""
+    w = wl.make_config("pulse_small", N=40, T=500, rj=True, seed=52)
+    d = w.noise + orc.template_sum(PULSE, w.inj, w.T, w.t_start, w.dt)
+    beta = np.random.default_rng(53).random(w.N)
+    args = (PULSE, d, w.t_start, w.dt, w.sigma, w.offsets, w.theta)
+    l1, g1 = orc.logl_grad(*args, np.ones(w.N))
+    lT, gT = orc.logl_grad_split(*args, beta, w.T)
+    assert np.allclose(lT, l1, rtol=1e-14, atol=0) and np.allclose(gT, g1, rtol=1e-13, atol=1e-12)
+    lb, gb = orc.logl_grad(*args, beta)
+    l0, g0 = orc.logl_grad_split(*args, beta, 0)
+    assert np.allclose(l0, lb, rtol=1e-14, atol=0) and np.allclose(g0, gb, rtol=1e-13, atol=1e-12)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    rb, rd = orc.delta_logl_birth_death(*args, beta, tb, di)
+    sb, sd = orc.delta_split(*args, beta, tb, di, 0)
+    assert np.allclose(sb, rb, rtol=1e-12, atol=1e-9) and np.allclose(sd, rd, rtol=1e-12, atol=1e-9)
+
+
+def test_split_birth_then_death_is_exactly_zero(orc):
+    w = wl.make_config("pulse_small", N=30, T=400, rj=True, seed=54)
+    d = w.noise + orc.template_sum(PULSE, w.inj, w.T, w.t_start, w.dt)
+    tb = w.extra["theta_birth"]
+    db, _ = orc.delta_split(PULSE, d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta, tb,
+                            None, 150)
+    rows = []
+    for i in range(w.N):
+        rows.append(w.theta[w.offsets[i]:w.offsets[i + 1]])
+        rows.append(tb[i:i + 1])
+    off2 = wl.counts_to_offsets(w.K + 1)
+    _, dd = orc.delta_split(PULSE, d, w.t_start, w.dt, w.sigma, off2, np.vstack(rows), w.beta,
+                            None, w.K.astype(np.int32), 150)
+    assert np.all(db + dd == 0.0)
+
+
+def test_split_nuts_depth_one_is_metropolis_on_the_split_energy(orc):
+    w = wl.make_config("pulse_small", N=30, T=400, k_lo=1, k_hi=3, n_inj=2, seed=55)
+    d = w.noise + orc.template_sum(PULSE, w.inj, w.T, w.t_start, w.dt)
+    beta = np.full(w.N, 0.4)
+    split = 170
+    l0, g0 = orc.logl_grad_split(PULSE, d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta, split)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, 3, 1, seed=56)
+    eps = 1e-4
+    q, l, g, depth, steps, status = orc.nuts_transition_split(
+        PULSE, d, w.t_start, w.dt, w.sigma, w.offsets, beta, eps, 1, w.theta, l0, g0, mom, dirs,
+        ul, ut, split)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        sub = np.array([0, b - a])
+        qi, pi, li, _ = orc.leapfrog_split(PULSE, d, w.t_start, w.dt, w.sigma, sub, w.theta[a:b],
+                                           mom[a:b], beta[i:i + 1], eps * dirs[i, 0], split)
+        H0 = -l0[i] + 0.5 * np.sum(mom[a:b] ** 2)
+        H1 = -li[0] + 0.5 * np.sum(pi ** 2)
+        assert steps[i] == 1
+        if not H1 - H0 <= 1000:
+            assert status[i] == 2 and np.array_equal(q[a:b], w.theta[a:b])
+            continue
+        accept = ut[i, 0] < np.exp(H0 - H1)
+        ref = qi if accept else w.theta[a:b]
+        assert np.allclose(q[a:b], ref, rtol=0, atol=1e-14)
+        assert np.array_equal(l[i], li[0]) if accept else l[i] == l0[i]
