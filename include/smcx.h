@@ -305,6 +305,26 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
                   void* hip_stream, int32_t* out_S, int64_t* out_chunk_len, int32_t* out_sorted,
                   double* out_ms);
 
+/* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
+ * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first
+ * `split` samples d1 to the posterior on all T samples d2 has the
+ * log-likelihood part
+ *   logL_split = -(1/(2 sigma^2)) [ sum_{s<split} r_s^2 + beta sum_{s>=split} r_s^2 ]
+ * After smcx_set_bridge_split(prob, split) every tempered call on the handle
+ * (logl_batch, logl_grad_batch, delta_logl_birth_death, smcx_leapfrog,
+ * smcx_nuts_transition) evaluates this target with beta_i from its beta
+ * argument: samples before the split enter untempered, later ones weighted
+ * by beta_i (gradients and birth/death changes likewise). split = 0, the
+ * default, is the prior bridge of eq. prior_bridge (beta times logL);
+ * split = T the untempered posterior. reweight_extend is not affected (its
+ * segment log-likelihood is untempered), and smcx_plain_logl_grad refuses
+ * to run while a split is set. The incremental weights of this bridge are
+ * (beta - beta_prev) times the untempered log-likelihood of samples
+ * [split, T), which reweight_extend(prob, split, T, ...) computes.
+ * 0 <= split <= T. */
+int smcx_set_bridge_split(smcx_problem* prob, int64_t split);
+int smcx_get_bridge_split(smcx_problem* prob, int64_t* split);
+
 /* ---- SMC steps around the likelihood (Sec. "Sequential Monte Carlo",
  * Sec. "Algorithm and implementation") ---------------------------------- */
 

@@ -186,6 +186,14 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
   return a;
 }
 
+// logL of a particle without components, split at the posterior-start bridge
+// sample (0 without one): the part from the split on, tempered by beta, and
+// the untempered part before it (FP64 prefix sums of d^2).
+double k0_tempered(const smcx_problem* p) {
+  return -0.5 * (p->prefix[p->T] - p->prefix[p->split]) * p->inv_sigma2;
+}
+double k0_untempered(const smcx_problem* p) { return -0.5 * p->prefix[p->split] * p->inv_sigma2; }
+
 smcx::PrepArgs prep_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
                          const double* beta, double k0, int tempered) {
   smcx::PrepArgs a;
@@ -348,16 +356,19 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   if (N > 0 && !logl) return fail(SMCX_EINVAL, "logl is NULL");
   if (N == 0) return SMCX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
-  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const double k0 = k0_tempered(p);
   const Tiling& t = p->tiling[kFwd];
   hipError_t e = hipSuccess;
   if (t.sorted) {
     smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.k0_lo = k0_untempered(p);
     pa.logl = logl;
     e = smcx::launch_prep(pa, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
   }
   smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, k0);
+  a.split = p->split;
+  a.k0_lo = k0_untempered(p);
   a.logl = logl;
   {
     ProfScope ps(p, st);
@@ -376,17 +387,20 @@ int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   if (M > 0 && !grad) return fail(SMCX_EINVAL, "grad is NULL");
   if (N == 0) return SMCX_OK;
   hipStream_t st = (hipStream_t)hip_stream;
-  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const double k0 = k0_tempered(p);
   const Tiling& t = p->tiling[kGrad];
   hipError_t e = hipSuccess;
   if (t.sorted) {
     smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.k0_lo = k0_untempered(p);
     pa.logl = logl;
     pa.grad = grad;
     e = smcx::launch_prep(pa, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
   }
   smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, k0);
+  a.split = p->split;
+  a.k0_lo = k0_untempered(p);
   a.logl = logl;
   a.grad = grad;
   {
@@ -421,6 +435,8 @@ int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, i
     if (e != hipSuccess) return hip_fail(e, "prep launch");
   }
   smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, t, 0, p->T, 0.0);
+  a.split = p->split;
+  a.k0_lo = k0_untempered(p);
   a.theta_birth = theta_birth;
   a.death_idx = death_idx;
   a.dlogl_birth = dlogl_birth;
@@ -488,6 +504,8 @@ int smcx_plain_logl_grad(smcx_problem* p, int64_t N, const int64_t* offsets_host
                          const double* theta, const double* beta, double* logl, double* grad,
                          void* hip_stream) {
   g_last_error.clear();
+  if (p && p->split != 0)
+    return fail(SMCX_EINVAL, "the plain form evaluates the prior bridge only (bridge split is set)");
   int rc = check_pop(p, N, offsets_host, M, theta);
   if (rc) return rc;
   if (N > 0 && !logl) return fail(SMCX_EINVAL, "logl is NULL");
@@ -534,16 +552,19 @@ int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   hipError_t e = smcx::launch_drift(p->model, N, M, offsets, eps, dir, active, q_in, p_in, g_in,
                                     q_out, p_out, g_out, st);
   if (e != hipSuccess) return hip_fail(e, "drift launch");
-  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const double k0 = k0_tempered(p);
   const Tiling& t = p->tiling[kGrad];
   if (t.sorted) {
     smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.k0_lo = k0_untempered(p);
     pa.logl = logl_out;
     pa.grad = g_out;
     e = smcx::launch_prep(pa, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
   }
   smcx::PopArgs a = base_args(p, N, offsets, M, q_out, beta, t, 0, p->T, k0);
+  a.split = p->split;
+  a.k0_lo = k0_untempered(p);
   a.logl = logl_out;
   a.grad = g_out;
   a.active = active;
@@ -652,16 +673,19 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   double* gF = p->nuts_vec + 8 * na.stride;
   double* pH = p->nuts_vec + 9 * na.stride;
 
-  const double k0 = -0.5 * p->prefix[p->T] * p->inv_sigma2;
+  const double k0 = k0_tempered(p);
   const Tiling& t = p->tiling[kGrad];
   hipError_t e = hipSuccess;
   if (t.sorted) {  // one ordering pass serves every leapfrog step of the transition
     smcx::PrepArgs pa = prep_args(p, N, offsets, M, beta, k0, 1);
+    pa.k0_lo = k0_untempered(p);
     pa.logl = p->nuts_logl;
     e = smcx::launch_prep(pa, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
   }
   smcx::PopArgs a = base_args(p, N, offsets, M, qF, beta, t, 0, p->T, k0);
+  a.split = p->split;
+  a.k0_lo = k0_untempered(p);
   a.logl = p->nuts_logl;
   a.grad = gF;
   a.active = p->nuts_active;
@@ -685,7 +709,8 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
                      (uint64_t)(uintptr_t)momentum, (uint64_t)(uintptr_t)dirs,
                      (uint64_t)(uintptr_t)u_leaf, (uint64_t)(uintptr_t)u_tree,
                      (uint64_t)(uintptr_t)q, (uint64_t)(uintptr_t)logl, (uint64_t)(uintptr_t)grad,
-                     (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth})
+                     (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth,
+                     (uint64_t)p->split})
     key = mix_key(key, v);
   uint64_t eb;
   std::memcpy(&eb, &eps, sizeof(eb));
@@ -725,6 +750,22 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   }
   e = smcx::launch_nuts_finalize(na, st);
   if (e != hipSuccess) return hip_fail(e, "NUTS finalize launch");
+  return SMCX_OK;
+}
+
+int smcx_set_bridge_split(smcx_problem* p, int64_t split) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (split < 0 || split > p->T)
+    return fail(SMCX_EINVAL, "split = %lld outside [0, T = %lld]", (long long)split, (long long)p->T);
+  p->split = split;
+  return SMCX_OK;
+}
+
+int smcx_get_bridge_split(smcx_problem* p, int64_t* split) {
+  g_last_error.clear();
+  if (!p || !split) return fail(SMCX_EINVAL, "problem handle or output is NULL");
+  *split = p->split;
   return SMCX_OK;
 }
 

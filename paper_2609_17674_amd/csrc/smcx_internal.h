@@ -62,7 +62,10 @@ struct PopArgs {
   int64_t M;               // rows of theta (offsets[N] must equal it)
   int32_t k_max;
   int64_t m_max;
-  double k0;               // untempered logL of a particle without components
+  double k0;               // logL of a particle without components (tempered part)
+  double k0_lo;            // its untempered part: samples before the split (0 without one)
+  int64_t split;           // posterior-start bridge: samples s < split are untempered
+                           // (weight 1), later ones weighted by beta; 0 (or <= s_lo) = off
   const int32_t* order;    // [N] particles sorted by K descending, or nullptr: particle order
   const int32_t* n_active; // device scalar: number of entries of order (sorted mode)
   int nch;
@@ -96,7 +99,8 @@ struct PrepArgs {
   int32_t k_max;
   int64_t m_max;
   int64_t M;           // rows of theta: offsets[N] must equal it
-  double k0_value;     // untempered logL of a particle with no components
+  double k0_value;     // untempered logL of a particle with no components (tempered part)
+  double k0_lo;        // part of it before the bridge split, added untempered (0: no split)
   double* logl;        // written for K = 0 (tempered) and invalid (NaN) particles
   double* logl2;       // optional second output set to the K=0 value (nullptr)
   int P;

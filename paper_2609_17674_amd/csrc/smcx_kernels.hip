@@ -548,7 +548,7 @@ __device__ __forceinline__ bool decode_item(const PopArgs& a, int64_t item, int 
   it.m0 = o0;
   it.K = (int)(o1 - o0);
   if (it.K == 0 && !with_k0) {
-    if (it.c == 0 && lane == 0 && a.logl) a.logl[i] = (a.beta ? a.beta[i] : 1.0) * a.k0;
+    if (it.c == 0 && lane == 0 && a.logl) a.logl[i] = a.k0_lo + (a.beta ? a.beta[i] : 1.0) * a.k0;
     return false;
   }
   return true;
@@ -617,7 +617,7 @@ __device__ __forceinline__ int prep_key(const PrepArgs& a, int64_t i, int64_t o0
     return -1;
   }
   if (K == 0 && !a.include_k0) {
-    if (settle && a.logl) a.logl[i] = beta_i * a.k0_value;
+    if (settle && a.logl) a.logl[i] = a.k0_lo + beta_i * a.k0_value;
     return -1;
   }
   return (int)K;
@@ -791,7 +791,9 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
 
   const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
   const int64_t ce = min(cs + a.chunk_len, a.s_hi);
-  double ss = 0.0;
+  const bool split = a.split > a.s_lo;  // posterior-start bridge target
+  const double b = a.beta ? a.beta[i] : 1.0;
+  double ss = 0.0, ss_lo = 0.0;  // tempered and (with a split) untempered sums of r^2
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float r[S];
     // d32 is zero-padded by a full 4096-sample tile past T: no load guard
@@ -804,21 +806,36 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
 #pragma unroll
       for (int j = 0; j < S; ++j) r[j] = 64 * j < nv ? r[j] : 0.f;
     }
+    if (!split) {
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const double rd = (double)r[j];
-      ss = fma(rd, rd, ss);
+      for (int j = 0; j < S; ++j) {
+        const double rd = (double)r[j];
+        ss = fma(rd, rd, ss);
+      }
+    } else {
+      // samples before the split count untempered; later ones carry beta,
+      // which the adjoint then sees through the residual
+      const float bf = (float)b;
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const double rd = (double)r[j];
+        const bool lo = tile + 64 * j + lane < a.split;
+        ss_lo = lo ? fma(rd, rd, ss_lo) : ss_lo;
+        ss = lo ? ss : fma(rd, rd, ss);
+        if constexpr (GRAD) r[j] = lo ? r[j] : r[j] * bf;
+      }
     }
     if constexpr (GRAD) M::template adjoint<S>(cst, acc, K, tile, lane, r);
   }
   ss = lane63_d(wave_sum_d(ss));
+  if (split) ss = lane63_d(wave_sum_d(ss_lo)) + b * ss;
+  const double outer = split ? 1.0 : b;  // tempering still to apply
 
   if (a.nch == 1) {
-    const double b = a.beta ? a.beta[i] : 1.0;
-    if (lane == 0 && a.logl) a.logl[i] = b * (-0.5 * ss * a.inv_sigma2);
+    if (lane == 0 && a.logl) a.logl[i] = outer * (-0.5 * ss * a.inv_sigma2);
     if constexpr (GRAD) {
       wave_sync();
-      const double bs = b * a.inv_sigma2;
+      const double bs = outer * a.inv_sigma2;
       const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
       for (int k = lane; k < K; k += 64) {
         double g[P];
@@ -853,14 +870,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
   const int64_t m0 = it.m0;
   const int K = it.K;
   if (a.active && !a.active[i]) return;
-  const double b = a.beta ? a.beta[i] : 1.0;
+  // with a split the chunk partials already carry the per-sample tempering
+  const double outer = a.split > a.s_lo ? 1.0 : (a.beta ? a.beta[i] : 1.0);
   if (lane == 0 && a.logl) {
     double ss = 0.0;
     for (int c = 0; c < a.nch; ++c) ss += a.part[(size_t)c * a.N + i];
-    a.logl[i] = b * (-0.5 * ss * a.inv_sigma2);
+    a.logl[i] = outer * (-0.5 * ss * a.inv_sigma2);
   }
   if constexpr (GRAD) {
-    const double bs = b * a.inv_sigma2;
+    const double bs = outer * a.inv_sigma2;
     for (int k = lane; k < K; k += 64) {
       double sums[P];
       for (int p = 0; p < P; ++p) sums[p] = 0.0;
@@ -914,6 +932,8 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
 
   const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
   const int64_t ce = min(cs + a.chunk_len, a.s_hi);
+  const bool split = a.split > a.s_lo;  // posterior-start bridge target
+  const double bw = a.beta ? a.beta[i] : 1.0;
   double xb = 0.0, yb = 0.0, xd = 0.0, yd = 0.0;
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float rf[S], rn[S], hj[S];
@@ -945,17 +965,33 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
       for (int jj = 0; jj < S; ++jj) hn[jj] = 0.f;
     }
     const int nv = (int)min(ce - tile, (int64_t)(64 * S)) - lane;
+    if (!split) {
 #pragma unroll
-    for (int jj = 0; jj < S; ++jj) {
-      const bool ok = 64 * jj < nv;
-      const double r1 = ok ? (double)rf[jj] : 0.0;
-      const double r2 = ok ? (double)rn[jj] : 0.0;
-      const double h1 = ok ? (double)hn[jj] : 0.0;
-      const double h2 = ok ? (double)hj[jj] : 0.0;
-      xb = fma(r1, h1, xb);
-      yb = fma(h1, h1, yb);
-      xd = fma(r2, h2, xd);
-      yd = fma(h2, h2, yd);
+      for (int jj = 0; jj < S; ++jj) {
+        const bool ok = 64 * jj < nv;
+        const double r1 = ok ? (double)rf[jj] : 0.0;
+        const double r2 = ok ? (double)rn[jj] : 0.0;
+        const double h1 = ok ? (double)hn[jj] : 0.0;
+        const double h2 = ok ? (double)hj[jj] : 0.0;
+        xb = fma(r1, h1, xb);
+        yb = fma(h1, h1, yb);
+        xd = fma(r2, h2, xd);
+        yd = fma(h2, h2, yd);
+      }
+    } else {  // per-sample weight: 1 before the split, beta after (products of floats are exact)
+#pragma unroll
+      for (int jj = 0; jj < S; ++jj) {
+        const bool ok = 64 * jj < nv;
+        const double r1 = ok ? (double)rf[jj] : 0.0;
+        const double r2 = ok ? (double)rn[jj] : 0.0;
+        const double h1 = ok ? (double)hn[jj] : 0.0;
+        const double h2 = ok ? (double)hj[jj] : 0.0;
+        const double ws = tile + 64 * jj + lane < a.split ? 1.0 : bw;
+        xb = fma(ws, r1 * h1, xb);
+        yb = fma(ws, h1 * h1, yb);
+        xd = fma(ws, r2 * h2, xd);
+        yd = fma(ws, h2 * h2, yd);
+      }
     }
   }
   xb = lane63_d(wave_sum_d(xb));
@@ -964,7 +1000,7 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
   yd = lane63_d(wave_sum_d(yd));
   if (lane != 0) return;
   if (a.nch == 1) {
-    const double b = a.beta ? a.beta[i] : 1.0;
+    const double b = split ? 1.0 : bw;  // tempering still to apply
     if (birth) a.dlogl_birth[i] = b * (xb - 0.5 * yb) * a.inv_sigma2;
     if (a.death_idx) a.dlogl_death[i] = j_death < 0 ? 0.0 : -(b * (xd - 0.5 * yd) * a.inv_sigma2);
   } else {
@@ -987,7 +1023,7 @@ __global__ __launch_bounds__(256) void delta_finalize_kernel(PopArgs a) {
     const double* src = a.part + ((size_t)c * a.N + i) * 4;
     for (int q = 0; q < 4; ++q) s[q] += src[q];
   }
-  const double b = a.beta ? a.beta[i] : 1.0;
+  const double b = a.split > a.s_lo ? 1.0 : (a.beta ? a.beta[i] : 1.0);
   if (a.theta_birth) a.dlogl_birth[i] = b * (s[0] - 0.5 * s[1]) * a.inv_sigma2;
   if (a.death_idx) {
     const int j = a.death_idx[i];

@@ -24,6 +24,7 @@ struct smcx_problem {
   double* d64 = nullptr;
   std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
   Tiling tiling[kNumKinds];
+  int64_t split = 0;  // posterior-start bridge split (smcx_set_bridge_split); 0 = prior bridge
   int max_nch = 0;       // capacity of part (chunks per particle)
   int max_nch_grad = 0;  // capacity of part_g
   int32_t* order = nullptr;

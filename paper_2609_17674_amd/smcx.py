@@ -77,6 +77,10 @@ def load_library():
                                   ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I32),
                                   ctypes.POINTER(D)]
     lib.smcx_autotune.restype = ctypes.c_int
+    lib.smcx_set_bridge_split.argtypes = [P, I64]
+    lib.smcx_set_bridge_split.restype = ctypes.c_int
+    lib.smcx_get_bridge_split.argtypes = [P, ctypes.POINTER(I64)]
+    lib.smcx_get_bridge_split.restype = ctypes.c_int
     lib.smcx_profile_begin.argtypes = [P, I32]
     lib.smcx_profile_begin.restype = ctypes.c_int
     lib.smcx_profile_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -181,6 +185,16 @@ class Problem:
                                             _stream(stream), ctypes.byref(S), ctypes.byref(cl),
                                             ctypes.byref(so), ctypes.byref(ms)))
         return S.value, cl.value, so.value, ms.value
+
+    def set_bridge_split(self, split: int) -> None:
+        """Samples before `split` enter every tempered call untempered (the
+        posterior-start bridge); 0 restores the prior bridge."""
+        _check(load_library().smcx_set_bridge_split(self.handle, int(split)))
+
+    def get_bridge_split(self) -> int:
+        v = ctypes.c_int64()
+        _check(load_library().smcx_get_bridge_split(self.handle, ctypes.byref(v)))
+        return int(v.value)
 
     def profile_begin(self, max_launches: int = 4096) -> None:
         _check(load_library().smcx_profile_begin(self.handle, int(max_launches)))
