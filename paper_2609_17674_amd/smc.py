@@ -1,6 +1,6 @@
-"""Prior-start SMC driver over the C ABI (Sec. "Algorithm and implementation").
+"""SMC driver over the C ABI (Sec. "Algorithm and implementation").
 
-One run draws N particles from the prior (K uniform on [k_lo, k_hi], each
+A prior-start run draws N particles from the prior (K uniform on [k_lo, k_hi], each
 component uniform in the prior box) at beta = 0 and repeats until beta = 1:
 
 1. choose the next beta by the ESS condition (eq. ess_target) and reweight
@@ -12,6 +12,12 @@ component uniform in the prior box) at beta = 0 and repeats until beta = 1:
    (a component drawn from the prior) or the death of a uniformly chosen
    component, scored by ``delta_logl_birth_death`` and accepted or rejected
    by ``smcx_rj_apply``.
+
+The posterior-start mode (``run_posterior_start``) starts instead from a
+population sampled on the first `split` samples of the data and follows the
+bridge of eq. reuse_bridge: the problem's bridge split makes every tempered
+call evaluate logL[0, split) + beta logL[split, T), and the incremental
+weights use the untempered log-likelihood of the new samples only.
 
 All arithmetic runs in the library's kernels. This module draws the random
 inputs on the device (a seeded torch generator) and sequences the calls; it
@@ -40,6 +46,8 @@ class SMCConfig:
     p_death: float = 0.2
     n_mutations: int = 4               # mixture-kernel steps per SMC iteration
     max_depth: int = 6                 # NUTS tree depth
+    # NUTS step size as a function of beta (identity metric in raw coordinates);
+    # the default suits the prior bridge, whose target widens as beta falls
     eps: Callable[[float], float] = field(default=lambda beta: 3e-4 / math.sqrt(max(beta, 1e-4)))
     max_iters: int = 200
     seed: int = 0
@@ -68,39 +76,83 @@ def run_prior_start(prob: smcx.Problem, prior_lo: torch.Tensor, prior_hi: torch.
     on the problem's data. The handle needs n_max >= N, k_max >= k_hi and
     m_max >= N k_hi; prior_lo, prior_hi are the [P] box of the uniform prior
     (on the device)."""
+    _check(prob, cfg)
+    gen = _generator(prior_lo.device, cfg.seed)
+    N = cfg.N
+    K = torch.randint(cfg.k_lo, cfg.k_hi + 1, (N,), generator=gen, device=prior_lo.device)
+    off = torch.zeros(N + 1, dtype=torch.int64, device=prior_lo.device)
+    off[1:] = torch.cumsum(K, 0)
+    th = _prior_rows(prob, prior_lo, prior_hi, int(off[-1]), gen)
+    prob.set_bridge_split(0)
+    return _run(prob, off, th, prior_lo, prior_hi, cfg, gen,
+                lambda o, t: smcx.logl_batch(prob, o, t), on_iteration)
+
+
+def run_posterior_start(prob: smcx.Problem, split: int, offsets: torch.Tensor,
+                        theta: torch.Tensor, prior_lo: torch.Tensor, prior_hi: torch.Tensor,
+                        cfg: SMCConfig, on_iteration: Optional[Callable[[int, dict], None]] = None
+                        ) -> SMCResult:
+    """Run the posterior-start SMC (eq. reuse_bridge): `offsets`, `theta` are
+    a population sampled from the posterior on the first `split` samples of
+    the problem's data (on the same time grid), for example the result of
+    run_prior_start on a problem built from them. The bridge split is set on
+    the handle for the run and cleared afterwards."""
+    _check(prob, cfg)
+    if not 0 < split < prob.T:
+        raise ValueError("split must lie inside the data")
+    if offsets.numel() - 1 != cfg.N:
+        raise ValueError("the starting population must have cfg.N particles")
+    gen = _generator(prior_lo.device, cfg.seed)
+    prob.set_bridge_split(split)
+    try:
+        return _run(prob, offsets, theta.contiguous(), prior_lo, prior_hi, cfg, gen,
+                    lambda o, t: smcx.reweight_extend(prob, split, prob.T, o, t, 0.0)[0],
+                    on_iteration)
+    finally:
+        prob.set_bridge_split(0)
+
+
+def _check(prob: smcx.Problem, cfg: SMCConfig) -> None:
     if not (cfg.N <= prob.n_max and cfg.k_hi <= prob.k_max and cfg.N * cfg.k_hi <= prob.m_max):
         raise ValueError("the problem handle is too small for this SMC configuration")
     if abs(cfg.p_nuts + cfg.p_birth + cfg.p_death - 1.0) > 1e-12:
         raise ValueError("mixture weights must sum to 1")
+
+
+def _generator(dev, seed: int) -> torch.Generator:
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    return gen
+
+
+def _prior_rows(prob, lo, hi, n: int, gen) -> torch.Tensor:
+    lo, hi = lo.to(torch.float64), hi.to(torch.float64)
+    u = torch.rand((n, prob.P), generator=gen, dtype=torch.float64, device=lo.device)
+    return (lo + u * (hi - lo)).contiguous()
+
+
+def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration) -> SMCResult:
+    """The SMC iterations from beta = 0; weight_logl(offsets, theta) gives the
+    untempered log-likelihood whose (beta - beta_prev) multiple is the log
+    incremental weight."""
     dev = prior_lo.device
     P, N, D = prob.P, cfg.N, cfg.max_depth
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(cfg.seed)
     smcx.nuts_reserve(prob, D)
     lo, hi = prior_lo.to(torch.float64).contiguous(), prior_hi.to(torch.float64).contiguous()
     f64 = dict(dtype=torch.float64, device=dev)
-
-    def prior_rows(n: int) -> torch.Tensor:
-        return (lo + torch.rand((n, P), generator=gen, **f64) * (hi - lo)).contiguous()
-
-    K = torch.randint(cfg.k_lo, cfg.k_hi + 1, (N,), generator=gen, device=dev)
-    off = torch.zeros(N + 1, dtype=torch.int64, device=dev)
-    off[1:] = torch.cumsum(K, 0)
     M = int(off[-1])
-    th = prior_rows(M)
     log_ratio = math.log(cfg.p_death / cfg.p_birth)
     beta = 0.0
     res = SMCResult(off, th, [], [], 0.0, [], [], [])
     for it in range(cfg.max_iters):
-        logl = smcx.logl_batch(prob, off, th)  # untempered
+        logl = weight_logl(off, th)
         beta_arr, _, w_norm, sc = smcx.next_beta(prob, logl, beta, cfg.alpha)
         beta, ess, dlogz = (float(x) for x in sc[:3].cpu())
         res.betas.append(beta)
         res.ess.append(ess)
         res.log_evidence += dlogz
         u = float(torch.rand(1, generator=gen, **f64))
-        _, off, th_all = smcx.resample_systematic(prob, off, th, w_norm, min(u, 1.0 - 2**-53),
-                                                  m_cap=N * cfg.k_hi)
+        _, off, th_all = smcx.resample_systematic(prob, off, th, w_norm, u, m_cap=N * cfg.k_hi)
         M = int(off[-1])
         th = th_all[:M]
         acc_rj = tried_rj = steps = 0
@@ -119,7 +171,7 @@ def run_prior_start(prob: smcx.Problem, prior_lo: torch.Tensor, prior_hi: torch.
                                                 ul, ut, lo, hi, mask=nuts.to(torch.uint8))
                 steps += int(st.sum())
             Kc = off[1:] - off[:-1]
-            tb = prior_rows(N)
+            tb = _prior_rows(prob, lo, hi, N, gen)
             di = torch.floor(torch.rand(N, generator=gen, **f64) * Kc).to(torch.int32)
             di = torch.where(Kc > 0, di, torch.full_like(di, -1))
             db, dd = smcx.delta_logl_birth_death(prob, off, th, beta_arr, tb, di)

@@ -50,3 +50,49 @@ def test_prior_start_smc_recovers_the_number_of_pulses(lib, orc):
     # every particle's rows stay inside the prior box
     th = res.theta.cpu().numpy()
     assert np.all(th >= wl.PULSE_PRIOR[:, 0]) and np.all(th <= wl.PULSE_PRIOR[:, 1])
+
+
+def test_posterior_start_reuses_the_shorter_run(lib, orc):
+    """Sec. "Algorithm and implementation", posterior-start mode: a population
+    sampled on the first half of the data is carried to the full data by the
+    bridge of eq. reuse_bridge. It must end with the full data's component
+    count and take fewer SMC iterations than a prior-start run on the full
+    data (the trend the paper reports for its pulse example)."""
+    T, split = 1000, 500
+    dt = 1.0 / (T - 1)
+    inj = np.array([[5.0, 0.2, 0.02], [4.0, 0.36, 0.03], [5.5, 0.75, 0.015]])
+    rng = np.random.default_rng(33)
+    d = rng.standard_normal(T) + orc.template_sum(wl.PULSE, inj, T, 0.0, dt)
+    N, k_hi = 2048, 6
+    dev = "cuda"
+    lo = torch.tensor(wl.PULSE_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.PULSE_PRIOR[:, 1].copy(), device=dev)
+
+    def report(tag):
+        def f(it, info):
+            print(f"[smc {tag}] it={it} beta={info['beta']:.4g} k={info['k_hist']} "
+                  f"rj={info['rj_accept']:.3f}", flush=True)
+        return f
+
+    print("[case] posterior_start", flush=True)
+    p1 = lib.Problem(wl.PULSE, torch.tensor(d[:split], device=dev), 0.0, dt, 1.0, k_hi, N, N * k_hi)
+    cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=150, seed=7)
+    first = smc.run_prior_start(p1, lo, hi, cfg, on_iteration=report("d1"))
+    # components beyond the first half cost nothing there, so K itself stays
+    # broad; the components inside the observed window must number two
+    th1, off1 = first.theta.cpu().numpy(), first.offsets.cpu().numpy()
+    seen = np.array([int(np.sum(th1[off1[i]:off1[i + 1], 1] < 0.45)) for i in range(N)])
+    assert int(np.argmax(np.bincount(seen))) == 2, np.bincount(seen)
+    p2 = lib.Problem(wl.PULSE, torch.tensor(d, device=dev), 0.0, dt, 1.0, k_hi, N, N * k_hi)
+    cfg2 = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=150, seed=8, eps=lambda beta: 3e-4)
+    post = smc.run_posterior_start(p2, split, first.offsets, first.theta, lo, hi, cfg2,
+                                   on_iteration=report("post"))
+    assert p2.get_bridge_split() == 0
+    assert post.betas[-1] == 1.0
+    k2 = np.array(post.k_hist[-1], dtype=float) / N
+    assert int(np.argmax(k2)) == 3, k2
+    prior = smc.run_prior_start(p2, lo, hi, smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=150,
+                                                          seed=9), on_iteration=report("prior"))
+    print(f"[smc] iterations: posterior-start {post.iterations}, prior-start {prior.iterations}",
+          flush=True)
+    assert post.iterations < prior.iterations
