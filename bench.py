@@ -17,6 +17,8 @@ Other workloads (--workload):
                 on the new samples plus weights, ESS and evidence increment
   pulse_mutate  one NUTS transition of every particle (hipGraph-replayed
                 leapfrog sweeps) plus the birth/death log-likelihood changes
+  smc_pulses    whole SMC runs (prior-start, timed per run; then one
+                posterior-start run) on a 10-pulse problem at N = 6000
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -50,7 +52,7 @@ SLOTS = {(0, "grad"): 19, (1, "grad"): 26, (0, "fwd"): 8, (1, "fwd"): 9}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("pulse_batch", "64,4096,1"): {"bytes": 1.3140e7, "kernels_sha1": "4ff13c53e0d8a42b"}}
+PMC_TRAFFIC = {("pulse_batch", "64,4096,1"): {"bytes": 1.3173e+07, "kernels_sha1": "577d588560b3e3af"}}
 
 
 def kernels_sha1():
@@ -296,6 +298,63 @@ def bench_mutate(args, w, dev, smcx, np, torch):
                         "delta_pass_ms": kern_ms})
 
 
+def bench_smc(args, w, dev, smcx, np, torch):
+    """Whole SMC runs on the pulse problem at the paper's pulse settings
+    (Sec. "Sequence of gaussian pulses": N = 6000, K in [1, 10], alpha = 0.9,
+    p_NUTS / p_birth / p_death = 0.6 / 0.2 / 0.2): a timed prior-start run on
+    all samples, then a posterior-start run from a population sampled on the
+    first half (that preparatory run is not timed)."""
+    from paper_2609_17674_amd import smc
+    from paper_2609_17674_amd import workloads as wl
+    d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, torch.tensor(w.inj, device=dev),
+                                                               w.T, w.t_start, w.dt)
+    N, k_hi = w.N, w.k_max
+    lo = torch.tensor(wl.PULSE_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.PULSE_PRIOR[:, 1].copy(), device=dev)
+    prob = smcx.Problem(w.model, d, w.t_start, w.dt, w.sigma, k_hi, N, N * k_hi)
+    for kind in (smcx.KIND_GRAD, smcx.KIND_LOGL):
+        prob.set_tiling(kind, 32, 4096, 1)
+    prob.set_tiling(smcx.KIND_DELTA, 16, 4096, 1)
+    runs = []
+    for r in range(args.warmup + args.steps):
+        cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=100 + r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = smc.run_prior_start(prob, lo, hi, cfg)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        log(f"[bench] prior-start run {r}: {res.iterations} iterations, {t:.2f} s, "
+            f"K histogram {res.k_hist[-1]}")
+        if r >= args.warmup:
+            runs.append((t, res))
+    ms = 1e3 * sum(t for t, _ in runs) / len(runs)
+    iters = [res.iterations for _, res in runs]
+    grads = sum(sum(res.nuts_steps) for _, res in runs)
+    half = w.T // 2
+    p1 = smcx.Problem(w.model, d[:half].contiguous(), w.t_start, w.dt, w.sigma, k_hi, N, N * k_hi)
+    first = smc.run_prior_start(p1, lo, hi, smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300,
+                                                           seed=7))
+    cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=8, eps=lambda beta: 3e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    post = smc.run_posterior_start(prob, half, first.offsets, first.theta, lo, hi, cfg)
+    torch.cuda.synchronize()
+    t_post = time.perf_counter() - t0
+    log(f"[bench] posterior-start: {post.iterations} iterations, {t_post:.2f} s")
+    value = N * sum(iters) / (sum(t for t, _ in runs))
+    return dict(metric="particle-iterations/sec of whole prior-start SMC runs (pulse problem)",
+                value=value, unit="particle-iterations/s", ms_per_step=ms,
+                config={"workload": "smc_pulses", "T": w.T, "N": N, "n_injected": len(w.inj),
+                        "K_range": [1, k_hi], "alpha": 0.9, "p_moves": [0.6, 0.2, 0.2],
+                        "n_mutations": 4, "nuts_max_depth": 6,
+                        "prior_start": {"iterations": iters, "seconds": [round(t, 3) for t, _ in runs],
+                                        "final_K_hist": runs[-1][1].k_hist[-1],
+                                        "leapfrog_grads_per_s": grads / sum(t for t, _ in runs)},
+                        "posterior_start": {"split": half, "iterations": post.iterations,
+                                            "seconds": round(t_post, 3),
+                                            "final_K_hist": post.k_hist[-1]}})
+
+
 def copy_probe(args, torch):
     """Device-to-device copy of a known size, for calibrating HBM byte counters."""
     n = 1 << 26  # 64 Mi float32 = 256 MiB
@@ -315,7 +374,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
-                    choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "copy_probe"])
+                    choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
+                             "copy_probe"])
     ap.add_argument("--tiling", default="", help="S,chunk_len,sorted: fixed tiling, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -323,8 +383,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (N=1); multi-GPU runs are not part of "
-              "it", file=sys.stderr)
+        print("bench.py: measures one GPU only (N=1); runs on several GPUs are not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -338,12 +398,17 @@ def main():
     if args.workload == "copy_probe":
         copy_probe(args, torch)
         return
-    w = wl.make_config(args.workload)
+    if args.workload == "smc_pulses":
+        w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
+    else:
+        w = wl.make_config(args.workload)
     log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
     if args.workload in ("pulse_batch", "gb_grad"):
         res = bench_grad(args, w, dev, smcx, np, torch)
     elif args.workload == "gb_extend":
         res = bench_extend(args, w, dev, smcx, np, torch)
+    elif args.workload == "smc_pulses":
+        res = bench_smc(args, w, dev, smcx, np, torch)
     else:
         res = bench_mutate(args, w, dev, smcx, np, torch)
     line = {
