@@ -84,6 +84,7 @@ def _load():
                                               P, P]
         lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
                                                      P, P, P, I64, P, P, P, P, P, P]
+        lib.oracle_fisher.argtypes = [I, I64, D, D, D, I64, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -314,3 +315,28 @@ def nuts_transition_split(model, d, t_start, dt, sigma, offsets, beta, eps, max_
         int(max_depth), _p(lo), _p(hi), _p(momentum), _p(dirs), _p(u_leaf), _p(u_tree), int(split),
         _p(q), _p(logl), _p(grad), _p(depth), _p(steps), _p(status)), "nuts_transition_split")
     return q, logl, grad, depth, steps, status
+
+
+def fisher_offsets(model, offsets):
+    """Start of each particle's (K P)^2 block in the packed metric array."""
+    P = n_params(model)
+    n = np.diff(_i64(offsets)) * P
+    out = np.zeros(len(n) + 1, dtype=np.int64)
+    np.cumsum(n * n, out=out[1:])
+    return out
+
+
+def fisher(model, T, t_start, dt, sigma, offsets, theta, beta=None):
+    """Gauss-Newton metric of every particle; returns a list of (K P) x (K P) arrays."""
+    offsets, theta, beta = _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    P = n_params(model)
+    fo = fisher_offsets(model, offsets)
+    F = np.empty(max(int(fo[-1]), 1))
+    _check(_load().oracle_fisher(model, int(T), t_start, dt, sigma, N, _p(offsets), _p(theta),
+                                 _p(beta), _p(fo), _p(F)), "fisher")
+    out = []
+    for i in range(N):
+        n = int(offsets[i + 1] - offsets[i]) * P
+        out.append(F[fo[i]:fo[i] + n * n].reshape(n, n).copy())
+    return out

@@ -949,3 +949,47 @@ int oracle_rj_apply(int model, int64_t N, const int64_t* offsets, const double* 
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------ metric
+ * Gauss-Newton (Fisher) approximation of the Hessian of the tempered
+ * negative log-likelihood, for the NUTS mass matrix (Sec. "No-U-Turn-Sampler"
+ * takes the Hessian of the negative log posterior as the metric; a uniform
+ * prior adds nothing inside its box). With J_s the vector of template
+ * partials dh_k(t_s)/dtheta_{k,p} of one particle (entry k P + p):
+ *   F = (beta / sigma^2) sum_s J_s J_s^T
+ * which is the Hessian of -beta logL without the term in r_s d2h/dtheta2
+ * (exact when the residual vanishes). Output: the (K P) x (K P) matrix of
+ * particle i, row-major, at F + f_offsets[i], where the caller's
+ * f_offsets[i+1] - f_offsets[i] must equal (K_i P)^2. */
+int oracle_fisher(int model, int64_t T, double t_start, double dt, double sigma, int64_t N,
+                  const int64_t* offsets, const double* theta, const double* beta,
+                  const int64_t* f_offsets, double* F) {
+  if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || !f_offsets)
+    return OR_EINVAL;
+  int P = oracle_n_params(model);
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t n = (offsets[i + 1] - offsets[i]) * P;
+    if (f_offsets[i + 1] - f_offsets[i] != n * n) return OR_EINVAL;
+  }
+  if (N > 0 && f_offsets[N] > 0 && !F) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i];
+    int64_t n = K * P;
+    const double* th = theta ? theta + offsets[i] * P : NULL;
+    double* Fi = F ? F + f_offsets[i] : NULL;
+    double b = beta ? beta[i] : 1.0;
+    if (n == 0) continue;
+    double* J = (double*)malloc((size_t)n * sizeof(double));
+    for (int64_t x = 0; x < n * n; ++x) Fi[x] = 0.0;
+    for (int64_t s = 0; s < T; ++s) {
+      double t = t_start + (double)s * dt;
+      for (int64_t k = 0; k < K; ++k) template_partials(model, th + k * P, t, J + k * P);
+      for (int64_t a = 0; a < n; ++a)
+        for (int64_t c = 0; c < n; ++c) Fi[a * n + c] += J[a] * J[c];
+    }
+    for (int64_t x = 0; x < n * n; ++x) Fi[x] = b * (Fi[x] / (sigma * sigma));
+    free(J);
+  }
+  return OR_OK;
+}
