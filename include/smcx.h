@@ -305,6 +305,26 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
                   void* hip_stream, int32_t* out_S, int64_t* out_chunk_len, int32_t* out_sorted,
                   double* out_ms);
 
+/* Gauss-Newton mass matrix for NUTS (Sec. "No-U-Turn-Sampler" takes the
+ * Hessian of the negative log posterior as the metric): per particle
+ *   F_i = (beta_i / sigma^2) sum_s J_s J_s^T,
+ * J_s = the template partials dh_k(t_s)/dtheta_{k,p} (entry k P + p), i.e.
+ * the Hessian of -beta logL without its residual term (exact where the
+ * residual vanishes), as a dense (K_i P) x (K_i P) FP64 row-major matrix at
+ * F + f_offsets[i]. f_offsets [N+1] (device, int64) are the caller's block
+ * starts: f_offsets[i+1] - f_offsets[i] must equal (K_i P)^2 (else the
+ * particle is skipped and the device flag raised); f_size is the length of F.
+ * Computed on the matrix cores: J is formed in FP32 in natural units
+ * (s = (1, w, w) for pulses, (1, 1/T_obs, 1/T_obs^2, 1) for sinusoids),
+ * rounded to FP16, and J^T J accumulated in FP32 (flushed to FP64 every 4096
+ * samples). The relative error of an entry is then bounded by about 1e-3 of
+ * sqrt(F_aa F_cc), ample for a preconditioner. Requires k_max P <= 128 and no
+ * bridge split. beta may be NULL (1). Every sample is evaluated (no pulse
+ * truncation). */
+int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                             const double* theta, const double* beta, const int64_t* f_offsets,
+                             int64_t f_size, double* F, void* hip_stream);
+
 /* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
  * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first
  * `split` samples d1 to the posterior on all T samples d2 has the

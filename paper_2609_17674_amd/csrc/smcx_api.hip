@@ -898,4 +898,25 @@ int smcx_rj_apply(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   return SMCX_OK;
 }
 
+int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                             const double* theta, const double* beta, const int64_t* f_offsets,
+                             int64_t f_size, double* F, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N == 0) return SMCX_OK;
+  if (!f_offsets) return fail(SMCX_EINVAL, "f_offsets is NULL");
+  if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
+  if ((int64_t)p->k_max * p->P > 128)
+    return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
+  if (p->split != 0)
+    return fail(SMCX_EINVAL, "the metric is defined for the prior bridge only (bridge split is set)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
+                                     p->k_max, offsets, theta, beta, f_offsets, f_size, F,
+                                     p->flag, st);
+  if (e != hipSuccess) return hip_fail(e, "metric launch");
+  return SMCX_OK;
+}
+
 }  // extern "C"

@@ -169,6 +169,12 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 // Number of particle slices of the ordering pass (its histogram workspace rows).
 int64_t prep_slices(int64_t N);
 
+// Gauss-Newton metric on the matrix cores (smcx_metric.hip); k_max * P <= 128.
+hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
+                         double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
+                         const double* theta, const double* beta, const int64_t* f_offsets,
+                         int64_t f_size, double* F, int* flag, hipStream_t st);
+
 // SMC steps (smcx_smc.hip).
 hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,
                             double beta_prev, double alpha, double* beta_out, double* logw,

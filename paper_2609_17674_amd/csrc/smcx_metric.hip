@@ -1,0 +1,230 @@
+// Gauss-Newton (Fisher) metric of every particle on the matrix cores.
+//
+// F_i = (beta_i / sigma^2) sum_s J_s J_s^T with J_s the template partials
+// dh_k(t_s)/dtheta_{k,p} of particle i (coordinate k P + p): the Hessian of the
+// tempered negative log-likelihood without its residual term, the mass matrix
+// the NUTS section of the paper asks for (the Hessian of the negative log
+// posterior; a uniform prior adds nothing inside its box).
+//
+// One wave owns one particle and walks the samples in steps of 8. Per step
+// each lane forms J at 4 samples for its coordinate in each block of 32
+// coordinates, in natural units (J~ = J * s with s = (1, w, w) for pulses and
+// (1, 1/T_obs, 1/T_obs^2, 1) for sinusoids, so every entry is of order one),
+// rounds them to FP16 and feeds them as both operands of
+// v_mfma_f32_32x32x8_f16: with A[i][k] held by lane i + 32 (k/4), element
+// k%4, and B[k][j] by lane j + 32 (k/4), a lane's own values are its row of
+// A and column of B, and D = J~_block_i^T J~_block_j. The FP32 accumulators
+// are flushed into the FP64 output every 4096 samples, each entry owned by one
+// lane (read-add-write, no atomics), so the result is deterministic; entries
+// below the diagonal are written as copies of those above it.
+// Error: FP16 rounding of J~ (2^-11 relative) bounds |dF~_ac| by about
+// 2^-10 sqrt(F~_aa F~_cc), plus FP32 accumulation over 512 steps.
+#include "smcx_internal.h"
+
+#include <math.h>
+
+namespace smcx {
+namespace {
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+constexpr double kTwoPiM = 6.283185307179586476925286766559;
+constexpr double kPiM = 3.141592653589793238462643383279;
+constexpr double kHalfLog2eRoot = 0.84932180028801904272150283410289;  // sqrt(log2(e) / 2)
+constexpr int kFlushSamples = 4096;
+
+struct MetricArgs {
+  int P;
+  int64_t N, M, T;
+  double t_start, dt, inv_sigma2, t_obs;
+  int32_t k_max;
+  const int64_t* offsets;
+  const double* theta;
+  const double* beta;
+  const int64_t* f_offsets;
+  int64_t f_size;  // entries of F: every block must fit
+  double* F;
+  int* flag;
+};
+
+// Per-lane description of one coordinate (component k, parameter p).
+template <int MODEL>
+struct Coord;
+
+// pulse: x = (s - nf) - f in samples, z = x a - fa, J~ = e * {1, A u, A u^2}, u = (t - t0)/w
+template <>
+struct Coord<SMCX_PULSE> {
+  float nf, a, fa, A;
+  int p;  // -1: padding lane
+};
+
+// sinusoid: phase in cycles c0 + c1 s + c2 s^2 (FP64)
+template <>
+struct Coord<SMCX_GBSINE> {
+  double c0, c1, c2;
+  float A;
+  int p;
+};
+
+template <int MODEL>
+__device__ Coord<MODEL> make_coord(const MetricArgs& a, const double* th, int c, int n,
+                                   double* scale) {
+  Coord<MODEL> q{};
+  q.p = -1;
+  *scale = 1.0;
+  if (c >= n) return q;
+  q.p = c % a.P;
+  const double* r = th + (int64_t)(c / a.P) * a.P;
+  if constexpr (MODEL == SMCX_PULSE) {
+    const double A = r[0], t0 = r[1], w = r[2];
+    const double cc = (t0 - a.t_start) / a.dt;
+    double nn = floor(cc);
+    nn = fmin(fmax(nn, -4194304.0), 4194304.0);
+    const double al = kHalfLog2eRoot * a.dt / w;
+    q.nf = (float)nn;
+    q.a = (float)al;
+    q.fa = (float)((cc - nn) * al);
+    q.A = (float)A;
+    *scale = q.p == 0 ? 1.0 : w;
+  } else {
+    const double A = r[0], f0 = r[1], fd = r[2], phi0 = r[3];
+    const double ts = a.t_start, dt = a.dt;
+    q.c0 = f0 * ts + 0.5 * fd * ts * ts + phi0 / kTwoPiM;
+    q.c1 = (f0 + fd * ts) * dt;
+    q.c2 = 0.5 * fd * dt * dt;
+    q.A = (float)A;
+    *scale = q.p == 1 ? 1.0 / a.t_obs : (q.p == 2 ? 1.0 / (a.t_obs * a.t_obs) : 1.0);
+  }
+  return q;
+}
+
+// J~ of one coordinate at sample s (0 past the data or for padding lanes).
+template <int MODEL>
+__device__ __forceinline__ float jvalue(const MetricArgs& a, const Coord<MODEL>& q, int64_t s) {
+  if (q.p < 0 || s >= a.T) return 0.f;
+  if constexpr (MODEL == SMCX_PULSE) {
+    const float z = __builtin_fmaf((float)(int)s - q.nf, q.a, -q.fa);
+    const float e = __builtin_amdgcn_exp2f(-(z * z));
+    const float u = z * (float)(1.0 / kHalfLog2eRoot);  // (t - t0) / w
+    const float f = q.p == 0 ? 1.f : (q.p == 1 ? q.A * u : q.A * u * u);
+    return e * f;
+  } else {
+    const double sd = (double)s;
+    const double ph = fma(fma(q.c2, sd, q.c1), sd, q.c0);
+    const float rev = (float)(ph - rint(ph));  // revolutions in [-0.5, 0.5]
+    if (q.p == 0) return __builtin_amdgcn_sinf(rev);
+    const float c = q.A * __builtin_amdgcn_cosf(rev);
+    if (q.p == 3) return c;
+    const float tr = (float)((a.t_start + sd * a.dt) / a.t_obs);  // t / T_obs
+    return q.p == 1 ? (float)kTwoPiM * tr * c : (float)kPiM * tr * tr * c;
+  }
+}
+
+template <int MODEL, int NB>
+__global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  extern __shared__ double scl[];  // [4 waves][32 NB] inverse natural scales of the coordinates
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wid;
+  if (i >= a.N) return;
+  const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+  if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  const int n = (int)(o1 - o0) * a.P;
+  const int64_t fo = a.f_offsets[i];
+  if (a.f_offsets[i + 1] - fo != (int64_t)n * n || n > 32 * NB || fo < 0 ||
+      fo + (int64_t)n * n > a.f_size) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  if (n == 0) return;
+  const double* th = a.theta + o0 * a.P;
+  Coord<MODEL> q[NB];
+  double* my = scl + wid * 32 * NB;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double sc;
+    q[b] = make_coord<MODEL>(a, th, 32 * b + (lane & 31), n, &sc);
+    if (lane < 32) my[32 * b + lane] = 1.0 / sc;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double bs = (a.beta ? a.beta[i] : 1.0) * a.inv_sigma2;
+  const int half = lane >> 5;  // which group of 4 samples of a step this lane feeds
+  for (int64_t w0 = 0; w0 < a.T; w0 += kFlushSamples) {
+    float16v acc[NP];
+#pragma unroll
+    for (int x = 0; x < NP; ++x) acc[x] = float16v{};
+    const int64_t w1 = min(w0 + (int64_t)kFlushSamples, a.T);
+#pragma unroll 1
+    for (int64_t s0 = w0; s0 < w1; s0 += 8) {
+      half4 j[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) j[b][e] = (_Float16)jvalue<MODEL>(a, q[b], s0 + 4 * half + e);
+      int x = 0;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int bj = bi; bj < NB; ++bj, ++x)
+          acc[x] = __builtin_amdgcn_mfma_f32_32x32x8f16(j[bi], j[bj], acc[x], 0, 0, 0);
+    }
+    // flush: lane holds D[r_i][c_j] with c_j = lane % 32, r_i = 8 (r/4) + 4 half + r % 4
+    int x = 0;
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+      for (int bj = bi; bj < NB; ++bj, ++x) {
+        const int c = 32 * bj + (lane & 31);
+        if (c >= n) continue;
+        const double sc = bs * my[c];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int rr = 32 * bi + 8 * (r >> 2) + 4 * half + (r & 3);
+          // inside a diagonal block only the upper triangle is taken and
+          // mirrored, so the result is exactly symmetric
+          if (rr >= n || (bi == bj && rr > c)) continue;
+          const double v = (double)acc[x][r] * sc * my[rr];
+          double* e1 = a.F + fo + (int64_t)rr * n + c;
+          *e1 = w0 == 0 ? v : *e1 + v;
+          if (rr != c) {
+            double* e2 = a.F + fo + (int64_t)c * n + rr;
+            *e2 = w0 == 0 ? v : *e2 + v;
+          }
+        }
+      }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
+                         double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
+                         const double* theta, const double* beta, const int64_t* f_offsets,
+                         int64_t f_size, double* F, int* flag, hipStream_t st) {
+  MetricArgs a{P, N, M, T, t_start, dt, inv_sigma2, (double)T * dt, k_max, offsets, theta,
+               beta, f_offsets, f_size, F, flag};
+  const int nmax = k_max * P;
+  const dim3 grid((unsigned)((N + 3) / 4)), block(256);
+  const int nb = nmax <= 32 ? 1 : (nmax <= 64 ? 2 : 4);
+  if (nmax > 128) return hipErrorInvalidValue;
+  const size_t lds = 4 * 32 * (size_t)nb * sizeof(double);
+  if (model == SMCX_PULSE) {
+    if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 1>), grid, block, lds, st, a);
+    else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 2>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 4>), grid, block, lds, st, a);
+  } else {
+    if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 1>), grid, block, lds, st, a);
+    else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 2>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 4>), grid, block, lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace smcx

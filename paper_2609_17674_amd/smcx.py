@@ -61,6 +61,7 @@ def load_library():
         "smcx_nuts_transition": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, P, P, P, P,
                                  P, I32, P],
         "smcx_next_beta": [P, I64, P, P, D, D, P, P, P, P, P],
+        "smcx_gauss_newton_metric": [P, I64, P, I64, P, P, P, I64, P, P],
         "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
         "smcx_rj_apply": [P, I64, P, I64, P, P, P, P, P, P, P, I32, I32, D, I64, P, P, P, P],
     }
@@ -363,6 +364,33 @@ def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q,
         _ptr(mask), _ptr(q), _ptr(logl), _ptr(grad), _ptr(depth), _ptr(steps), _ptr(status),
         1 if use_graph else 0, _stream(stream)))
     return depth, steps, status
+
+
+def metric_offsets(prob: Problem, offsets) -> torch.Tensor:
+    """Start of each particle's (K P)^2 block in the packed metric array (device)."""
+    offsets = _dev(offsets, torch.int64, "offsets")
+    n = (offsets[1:] - offsets[:-1]) * prob.P
+    out = torch.zeros_like(offsets)
+    out[1:] = torch.cumsum(n * n, 0)
+    return out
+
+
+def gauss_newton_metric(prob: Problem, offsets, theta, beta=None, f_offsets=None, out=None,
+                        stream=None):
+    """Gauss-Newton metric of every particle. Returns (f_offsets, F) with particle
+    i's (K P) x (K P) matrix at F[f_offsets[i]:f_offsets[i+1]] (row-major)."""
+    offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
+    if f_offsets is None:
+        f_offsets = metric_offsets(prob, offsets)
+    f_offsets = _dev(f_offsets, torch.int64, "f_offsets", (N + 1,))
+    size = int(f_offsets[-1]) if N > 0 else 0
+    if out is None:
+        out = torch.empty(max(size, 1), dtype=torch.float64, device=theta.device)
+    out = _dev(out, torch.float64, "F")
+    _check(load_library().smcx_gauss_newton_metric(prob.handle, N, _ptr(offsets), theta.shape[0],
+                                                   _ptr(theta), _ptr(beta), _ptr(f_offsets),
+                                                   out.numel(), _ptr(out), _stream(stream)))
+    return f_offsets, out
 
 
 def next_beta(prob: Problem, logl, beta_prev: float, alpha: float, logw_prev=None, beta_out=None,

@@ -1,0 +1,98 @@
+"""The Gauss-Newton metric on the matrix cores against the oracle, through the C ABI.
+
+Tolerance, from the arithmetic: J is rounded to FP16 in natural units
+(relative error at most 2^-11 per entry), so |dF~_ac| <= sum |J~_a||J~_c| 2^-10
+<= 2^-10 sqrt(F~_aa F~_cc) by Cauchy-Schwarz; FP32 accumulation over at most
+512 steps of 8 samples adds about 512 * 2^-24 of the same bound. The bound is
+invariant under the diagonal change of units, so it is checked in raw units.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import parity as pm
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+PULSE, GB = wl.PULSE, wl.GBSINE
+TOL = 2.0 ** -10 + 512 * 2.0 ** -24 + 1e-5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    ("pulse_nb1", "pulse_batch", dict(N=70, T=4096, k_hi=8)),
+    ("pulse_nb2", "pulse_batch", dict(N=60, T=4096, k_hi=20)),
+    ("pulse_nb4_two_windows", "pulse_batch", dict(N=24, T=9000, k_lo=20, k_hi=42)),
+    ("gb_nb1", "gb_grad", dict(N=30, T=5000, k_hi=8)),
+    ("gb_nb4", "gb_grad", dict(N=20, T=3000, k_lo=20, k_hi=30)),
+]
+
+
+@pytest.mark.parametrize("name,cfg,ov", CASES, ids=[c[0] for c in CASES])
+def test_metric_matches_oracle(lib, orc, name, cfg, ov):
+    w = wl.make_config(cfg, **ov)
+    if name == "gb_nb1":
+        w.t_start = 3.9e6
+    beta = np.random.default_rng(80).random(w.N)
+    say(name, "N", w.N, "T", w.T, "k_max", w.k_max)
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       w.M)
+    fo, F = lib.gauss_newton_metric(prob, pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(beta))
+    torch.cuda.synchronize()
+    prob.device_status()
+    fo, F = fo.cpu().numpy(), F.cpu().numpy()
+    ref = orc.fisher(w.model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta)
+    P = w.P
+    worst = 0.0
+    for i in range(w.N):
+        n = int(w.offsets[i + 1] - w.offsets[i]) * P
+        assert fo[i + 1] - fo[i] == n * n
+        if n == 0:
+            continue
+        got = F[fo[i]:fo[i + 1]].reshape(n, n)
+        r = ref[i]
+        d = np.sqrt(np.diag(r))
+        bound = TOL * np.outer(d, d) + 1e-300
+        err = np.abs(got - r) / bound
+        worst = max(worst, float(err.max()))
+        assert np.all(err <= 1.0), (i, float(err.max()))
+        assert np.array_equal(got, got.T)
+    print(f"[metric] {name}: worst error / bound = {worst:.3f}", flush=True)
+
+
+def test_metric_checks_its_output_blocks(lib, orc):
+    w = wl.make_config("pulse_batch", N=30, T=1024, k_hi=6, seed=81)
+    say("metric_blocks")
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       w.M)
+    off, th = pm.to_dev(w.offsets), pm.to_dev(w.theta)
+    fo = lib.metric_offsets(prob, off)
+    size = int(fo[-1])
+    # an array one block short: the last particle's block does not fit and is skipped
+    last = int(np.nonzero(w.K)[0][-1])
+    short = int(fo[last])
+    guard = torch.full((size + 64,), 7.0, dtype=torch.float64, device="cuda")
+    _, F = lib.gauss_newton_metric(prob, off, th, f_offsets=fo, out=guard[:short])
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError):
+        prob.device_status()
+    assert torch.all(guard[short:] == 7.0)
+    # offsets that disagree with (K P)^2
+    bad = fo.clone()
+    bad[1:] += 1
+    lib.gauss_newton_metric(prob, off, th, f_offsets=bad, out=torch.empty(size + w.N + 1,
+                                                                            dtype=torch.float64,
+                                                                            device="cuda"))
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError):
+        prob.device_status()
+    # the split is refused
+    prob.set_bridge_split(100)
+    with pytest.raises(lib.SmcxError, match="prior bridge"):
+        lib.gauss_newton_metric(prob, off, th)
