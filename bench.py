@@ -19,6 +19,7 @@ Other workloads (--workload):
                 leapfrog sweeps) plus the birth/death log-likelihood changes
   smc_pulses    whole SMC runs (prior-start, timed per run; then one
                 posterior-start run) on a 10-pulse problem at N = 6000
+  metric        Gauss-Newton metric of the headline population (matrix cores)
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -355,6 +356,54 @@ def bench_smc(args, w, dev, smcx, np, torch):
                                             "final_K_hist": post.k_hist[-1]}})
 
 
+def bench_metric(args, w, dev, smcx, np, torch):
+    """Gauss-Newton metric of every particle of the headline population on the
+    matrix cores: one smcx_gauss_newton_metric call per step."""
+    d, prob, off, th = setup(w, dev, smcx, torch)
+    beta = torch.tensor(w.beta, device=dev)
+    fo = smcx.metric_offsets(prob, off)
+    F = torch.empty(int(fo[-1]), dtype=torch.float64, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def step():
+        smcx.gauss_newton_metric(prob, off, th, beta, f_offsets=fo, out=F)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(args.steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    prob.device_status()
+    K = np.diff(w.offsets)
+    n = K * w.P
+    nb = 1 if w.k_max * w.P <= 32 else (2 if w.k_max * w.P <= 64 else 4)
+    useful = float(np.sum(n.astype(np.float64) ** 2) * w.T * 2)        # sum_i n_i^2 T (FMA = 2)
+    issued = float(np.count_nonzero(K) * (w.T / 8) * nb * (nb + 1) / 2 * 2 * 32 * 32 * 8)
+    jvals = float(np.count_nonzero(K) * 32 * nb * w.T)                  # J~ entries formed
+    tf = issued / (ms * 1e-3) / 1e12
+    value = w.N / (ms * 1e-3)
+    # the J entries are synthesised on the vector units, 13 FP32-FMA-equivalent
+    # slots each (sub, fma, mul, exp2 = 4, two fma, mul, f16 convert, select),
+    # which is what bounds the kernel; the matrix cores carry the contraction
+    slots_tf = 2.0 * 13 * jvals / (ms * 1e-3) / 1e12
+    log(f"[bench] metric {ms:.4f} ms/step, {value:.4e} particles/s, MFMA {tf:.1f} TFLOP/s issued")
+    return dict(metric="particle Gauss-Newton metrics/sec (FP16 matrix cores, FP64 output)",
+                value=value, unit="particles/s", ms_per_step=ms,
+                config={"workload": "metric_pulse_batch", "T": w.T, "N": w.N, "M": w.M,
+                        "K": f"U{{0..{w.k_max}}}", "coordinate_blocks": nb},
+                roofline={"bound": "alu", "achieved": round(slots_tf, 3), "peak": PEAK_FP32_TFLOPS,
+                          "unit": "TFLOP/s", "frac": round(slots_tf / PEAK_FP32_TFLOPS, 4),
+                          "traffic": None, "kernel": "metric_kernel", "kernel_ms": round(ms, 5),
+                          "work": f"{jvals:.4e} J entries x 13 FP32-FMA-equivalent slots",
+                          "mfma_issued_tflops": round(tf, 2), "mfma_peak_fp16_tflops": 2500.0,
+                          "mfma_frac": round(tf / 2500.0, 4),
+                          "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 2)})
+
+
 def copy_probe(args, torch):
     """Device-to-device copy of a known size, for calibrating HBM byte counters."""
     n = 1 << 26  # 64 Mi float32 = 256 MiB
@@ -375,7 +424,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "copy_probe"])
+                             "metric", "copy_probe"])
     ap.add_argument("--tiling", default="", help="S,chunk_len,sorted: fixed tiling, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -400,6 +449,8 @@ def main():
         return
     if args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
+    elif args.workload == "metric":
+        w = wl.make_config("pulse_batch")
     else:
         w = wl.make_config(args.workload)
     log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
@@ -409,6 +460,8 @@ def main():
         res = bench_extend(args, w, dev, smcx, np, torch)
     elif args.workload == "smc_pulses":
         res = bench_smc(args, w, dev, smcx, np, torch)
+    elif args.workload == "metric":
+        res = bench_metric(args, w, dev, smcx, np, torch)
     else:
         res = bench_mutate(args, w, dev, smcx, np, torch)
     line = {

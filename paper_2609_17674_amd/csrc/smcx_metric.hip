@@ -14,8 +14,9 @@
 // v_mfma_f32_32x32x8_f16: with A[i][k] held by lane i + 32 (k/4), element
 // k%4, and B[k][j] by lane j + 32 (k/4), a lane's own values are its row of
 // A and column of B, and D = J~_block_i^T J~_block_j. The FP32 accumulators
-// are flushed into the FP64 output every 4096 samples, each entry owned by one
-// lane (read-add-write, no atomics), so the result is deterministic; entries
+// are flushed into the FP64 output after each window of 4096 samples (one
+// launch per window), each entry owned by one lane (read-add-write, no
+// atomics), so the result is deterministic; entries
 // below the diagonal are written as copies of those above it.
 // Error: FP16 rounding of J~ (2^-11 relative) bounds |dF~_ac| by about
 // 2^-10 sqrt(F~_aa F~_cc), plus FP32 accumulation over 512 steps.
@@ -46,35 +47,39 @@ struct MetricArgs {
   int64_t f_size;  // entries of F: every block must fit
   double* F;
   int* flag;
+  int64_t w0, w1;  // sample window of this launch; the first window writes F, later ones add
 };
 
-// Per-lane description of one coordinate (component k, parameter p).
+// Per-lane description of one coordinate (component k, parameter p), set up
+// so that J~ needs no branch on p; padding lanes get zero coefficients.
 template <int MODEL>
 struct Coord;
 
-// pulse: x = (s - nf) - f in samples, z = x a - fa, J~ = e * {1, A u, A u^2}, u = (t - t0)/w
+// pulse: x = s - nf (exact), z = x a - fa, J~ = e (c0 + c1 z + c2 z^2) with
+// e = 2^(-z^2): (c0, c1, c2) = (1, 0, 0), (0, A k, 0), (0, 0, A k^2) for
+// p = 0, 1, 2, k = 1 / sqrt(log2(e)/2) so that k z = (t - t0)/w
 template <>
 struct Coord<SMCX_PULSE> {
-  float nf, a, fa, A;
-  int p;  // -1: padding lane
+  float nf, a, fa, c0, c1, c2;
 };
 
-// sinusoid: phase in cycles c0 + c1 s + c2 s^2 (FP64)
+// sinusoid: phase in cycles ph0 + ph1 s + ph2 s^2 (FP64);
+// J~ = sin(2 pi (phase + shift)) (k0 + k1 tr + k2 tr^2), tr = t / T_obs
+// = tr0 + s dtr: shift 0 and (1, 0, 0) for A'; a quarter cycle (the cosine)
+// and (0, 2 pi A', 0), (0, 0, pi A'), (A', 0, 0) for f0, fdot, phi0
 template <>
 struct Coord<SMCX_GBSINE> {
-  double c0, c1, c2;
-  float A;
-  int p;
+  double ph0, ph1, ph2;
+  float shift, k0, k1, k2, tr0, dtr;
 };
 
 template <int MODEL>
 __device__ Coord<MODEL> make_coord(const MetricArgs& a, const double* th, int c, int n,
                                    double* scale) {
   Coord<MODEL> q{};
-  q.p = -1;
   *scale = 1.0;
-  if (c >= n) return q;
-  q.p = c % a.P;
+  if (c >= n) return q;  // all coefficients zero
+  const int p = c % a.P;
   const double* r = th + (int64_t)(c / a.P) * a.P;
   if constexpr (MODEL == SMCX_PULSE) {
     const double A = r[0], t0 = r[1], w = r[2];
@@ -82,42 +87,44 @@ __device__ Coord<MODEL> make_coord(const MetricArgs& a, const double* th, int c,
     double nn = floor(cc);
     nn = fmin(fmax(nn, -4194304.0), 4194304.0);
     const double al = kHalfLog2eRoot * a.dt / w;
+    const double k = 1.0 / kHalfLog2eRoot;
     q.nf = (float)nn;
     q.a = (float)al;
     q.fa = (float)((cc - nn) * al);
-    q.A = (float)A;
-    *scale = q.p == 0 ? 1.0 : w;
+    q.c0 = p == 0 ? 1.f : 0.f;
+    q.c1 = p == 1 ? (float)(A * k) : 0.f;
+    q.c2 = p == 2 ? (float)(A * k * k) : 0.f;
+    *scale = p == 0 ? 1.0 : w;
   } else {
     const double A = r[0], f0 = r[1], fd = r[2], phi0 = r[3];
     const double ts = a.t_start, dt = a.dt;
-    q.c0 = f0 * ts + 0.5 * fd * ts * ts + phi0 / kTwoPiM;
-    q.c1 = (f0 + fd * ts) * dt;
-    q.c2 = 0.5 * fd * dt * dt;
-    q.A = (float)A;
-    *scale = q.p == 1 ? 1.0 / a.t_obs : (q.p == 2 ? 1.0 / (a.t_obs * a.t_obs) : 1.0);
+    q.ph0 = f0 * ts + 0.5 * fd * ts * ts + phi0 / kTwoPiM;
+    q.ph1 = (f0 + fd * ts) * dt;
+    q.ph2 = 0.5 * fd * dt * dt;
+    q.shift = p == 0 ? 0.f : 0.25f;
+    q.k0 = p == 0 ? 1.f : (p == 3 ? (float)A : 0.f);
+    q.k1 = p == 1 ? (float)(kTwoPiM * A) : 0.f;
+    q.k2 = p == 2 ? (float)(kPiM * A) : 0.f;
+    q.tr0 = (float)(ts / a.t_obs);
+    q.dtr = (float)(dt / a.t_obs);
+    *scale = p == 1 ? 1.0 / a.t_obs : (p == 2 ? 1.0 / (a.t_obs * a.t_obs) : 1.0);
   }
   return q;
 }
 
-// J~ of one coordinate at sample s (0 past the data or for padding lanes).
+// J~ of one coordinate at sample s.
 template <int MODEL>
-__device__ __forceinline__ float jvalue(const MetricArgs& a, const Coord<MODEL>& q, int64_t s) {
-  if (q.p < 0 || s >= a.T) return 0.f;
+__device__ __forceinline__ float jvalue(const Coord<MODEL>& q, int s) {
   if constexpr (MODEL == SMCX_PULSE) {
-    const float z = __builtin_fmaf((float)(int)s - q.nf, q.a, -q.fa);
+    const float z = __builtin_fmaf((float)s - q.nf, q.a, -q.fa);
     const float e = __builtin_amdgcn_exp2f(-(z * z));
-    const float u = z * (float)(1.0 / kHalfLog2eRoot);  // (t - t0) / w
-    const float f = q.p == 0 ? 1.f : (q.p == 1 ? q.A * u : q.A * u * u);
-    return e * f;
+    return e * __builtin_fmaf(__builtin_fmaf(q.c2, z, q.c1), z, q.c0);
   } else {
     const double sd = (double)s;
-    const double ph = fma(fma(q.c2, sd, q.c1), sd, q.c0);
-    const float rev = (float)(ph - rint(ph));  // revolutions in [-0.5, 0.5]
-    if (q.p == 0) return __builtin_amdgcn_sinf(rev);
-    const float c = q.A * __builtin_amdgcn_cosf(rev);
-    if (q.p == 3) return c;
-    const float tr = (float)((a.t_start + sd * a.dt) / a.t_obs);  // t / T_obs
-    return q.p == 1 ? (float)kTwoPiM * tr * c : (float)kPiM * tr * tr * c;
+    const double ph = fma(fma(q.ph2, sd, q.ph1), sd, q.ph0);
+    const float rev = (float)(ph - rint(ph)) + q.shift;  // revolutions in [-0.5, 0.75]
+    const float tr = __builtin_fmaf((float)s, q.dtr, q.tr0);
+    return __builtin_amdgcn_sinf(rev) * __builtin_fmaf(__builtin_fmaf(q.k2, tr, q.k1), tr, q.k0);
   }
 }
 
@@ -156,50 +163,52 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const double bs = (a.beta ? a.beta[i] : 1.0) * a.inv_sigma2;
   const int half = lane >> 5;  // which group of 4 samples of a step this lane feeds
-  for (int64_t w0 = 0; w0 < a.T; w0 += kFlushSamples) {
-    float16v acc[NP];
+  float16v acc[NP];
 #pragma unroll
-    for (int x = 0; x < NP; ++x) acc[x] = float16v{};
-    const int64_t w1 = min(w0 + (int64_t)kFlushSamples, a.T);
+  for (int x = 0; x < NP; ++x) acc[x] = float16v{};
+  const int w1 = (int)a.w1;  // sample indices fit in 32 bits (T <= 2^22)
 #pragma unroll 1
-    for (int64_t s0 = w0; s0 < w1; s0 += 8) {
-      half4 j[NB];
+  for (int s0 = (int)a.w0 + 4 * half; s0 < w1 + 4 * half; s0 += 8) {
+    half4 j[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) j[b][e] = (_Float16)jvalue<MODEL>(a, q[b], s0 + 4 * half + e);
-      int x = 0;
-#pragma unroll
-      for (int bi = 0; bi < NB; ++bi)
-#pragma unroll
-        for (int bj = bi; bj < NB; ++bj, ++x)
-          acc[x] = __builtin_amdgcn_mfma_f32_32x32x8f16(j[bi], j[bj], acc[x], 0, 0, 0);
-    }
-    // flush: lane holds D[r_i][c_j] with c_j = lane % 32, r_i = 8 (r/4) + 4 half + r % 4
+      for (int e = 0; e < 4; ++e) {
+        const float v = jvalue<MODEL>(q[b], s0 + e);
+        j[b][e] = (_Float16)(s0 + e < w1 ? v : 0.f);
+      }
     int x = 0;
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-      for (int bj = bi; bj < NB; ++bj, ++x) {
-        const int c = 32 * bj + (lane & 31);
-        if (c >= n) continue;
-        const double sc = bs * my[c];
+      for (int bj = bi; bj < NB; ++bj, ++x)
+        acc[x] = __builtin_amdgcn_mfma_f32_32x32x8f16(j[bi], j[bj], acc[x], 0, 0, 0);
+  }
+  // flush: lane holds D[r_i][c_j] with c_j = lane % 32, r_i = 8 (r/4) + 4 half + r % 4
+  const bool first = a.w0 == 0;
+  int x = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int rr = 32 * bi + 8 * (r >> 2) + 4 * half + (r & 3);
-          // inside a diagonal block only the upper triangle is taken and
-          // mirrored, so the result is exactly symmetric
-          if (rr >= n || (bi == bj && rr > c)) continue;
-          const double v = (double)acc[x][r] * sc * my[rr];
-          double* e1 = a.F + fo + (int64_t)rr * n + c;
-          *e1 = w0 == 0 ? v : *e1 + v;
-          if (rr != c) {
-            double* e2 = a.F + fo + (int64_t)c * n + rr;
-            *e2 = w0 == 0 ? v : *e2 + v;
-          }
+  for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+    for (int bj = bi; bj < NB; ++bj, ++x) {
+      const int c = 32 * bj + (lane & 31);
+      if (c >= n) continue;
+      const double sc = bs * my[c];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rr = 32 * bi + 8 * (r >> 2) + 4 * half + (r & 3);
+        // inside a diagonal block only the upper triangle is taken and
+        // mirrored, so the result is exactly symmetric
+        if (rr >= n || (bi == bj && rr > c)) continue;
+        const double v = (double)acc[x][r] * sc * my[rr];
+        double* e1 = a.F + fo + (int64_t)rr * n + c;
+        *e1 = first ? v : *e1 + v;
+        if (rr != c) {
+          double* e2 = a.F + fo + (int64_t)c * n + rr;
+          *e2 = first ? v : *e2 + v;
         }
       }
-  }
+    }
 }
 
 }  // namespace
@@ -209,20 +218,27 @@ hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, doub
                          const double* theta, const double* beta, const int64_t* f_offsets,
                          int64_t f_size, double* F, int* flag, hipStream_t st) {
   MetricArgs a{P, N, M, T, t_start, dt, inv_sigma2, (double)T * dt, k_max, offsets, theta,
-               beta, f_offsets, f_size, F, flag};
+               beta, f_offsets, f_size, F, flag, 0, 0};
   const int nmax = k_max * P;
   const dim3 grid((unsigned)((N + 3) / 4)), block(256);
   const int nb = nmax <= 32 ? 1 : (nmax <= 64 ? 2 : 4);
   if (nmax > 128) return hipErrorInvalidValue;
   const size_t lds = 4 * 32 * (size_t)nb * sizeof(double);
-  if (model == SMCX_PULSE) {
-    if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 1>), grid, block, lds, st, a);
-    else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 2>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 4>), grid, block, lds, st, a);
-  } else {
-    if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 1>), grid, block, lds, st, a);
-    else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 2>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 4>), grid, block, lds, st, a);
+  // one launch per window of samples: later windows add to what earlier ones wrote
+  for (int64_t w0 = 0; w0 < T; w0 += kFlushSamples) {
+    a.w0 = w0;
+    a.w1 = w0 + kFlushSamples < T ? w0 + kFlushSamples : T;
+    if (model == SMCX_PULSE) {
+      if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 1>), grid, block, lds, st, a);
+      else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 2>), grid, block, lds, st, a);
+      else hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 4>), grid, block, lds, st, a);
+    } else {
+      if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 1>), grid, block, lds, st, a);
+      else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 2>), grid, block, lds, st, a);
+      else hipLaunchKernelGGL((metric_kernel<SMCX_GBSINE, 4>), grid, block, lds, st, a);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
