@@ -216,7 +216,12 @@ def bench_grad(args, w, dev, smcx, np, torch):
 def bench_extend(args, w, dev, smcx, np, torch):
     T1, T2 = w.extra["T1"], w.extra["T2"]
     d, prob, off, th = setup(w, dev, smcx, torch)
-    tuned = prob.autotune(smcx.KIND_LOGL, off, th, None, reps=2)
+    if args.tiling:
+        S, chunk, so = (int(x) for x in args.tiling.split(","))
+        prob.set_tiling(smcx.KIND_LOGL, S, chunk, so)
+        tuned = (S, chunk, so, float("nan"))
+    else:
+        tuned = prob.autotune(smcx.KIND_LOGL, off, th, None, reps=2)
     outs = tuple(torch.empty(n, dtype=torch.float64, device=dev) for n in (w.N, w.N, w.N, 3))
 
     def step():
@@ -263,8 +268,12 @@ def bench_mutate(args, w, dev, smcx, np, torch):
     d, prob, off, th0 = setup(w, dev, smcx, torch)
     beta = torch.tensor(w.beta, device=dev)
     D, eps = int(w.extra["max_depth"]), float(w.extra["eps"])
-    prob.autotune(smcx.KIND_GRAD, off, th0, beta, reps=3)
-    prob.autotune(smcx.KIND_DELTA, off, th0, beta, reps=3)
+    if args.tiling:
+        S, chunk, so = (int(x) for x in args.tiling.split(","))
+        prob.set_tiling(smcx.KIND_GRAD, S, chunk, so)
+    else:
+        prob.autotune(smcx.KIND_GRAD, off, th0, beta, reps=3)
+        prob.autotune(smcx.KIND_DELTA, off, th0, beta, reps=3)
     smcx.nuts_reserve(prob, D)
     mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, w.P, D, seed=4242)
     mom, dirs, ul, ut = (torch.tensor(x, device=dev) for x in (mom, dirs, ul, ut))
@@ -425,7 +434,8 @@ def main():
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
                              "metric", "copy_probe"])
-    ap.add_argument("--tiling", default="", help="S,chunk_len,sorted: fixed tiling, no autotuning")
+    ap.add_argument("--tiling", default="",
+                    help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
