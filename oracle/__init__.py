@@ -19,6 +19,13 @@ Parity status of each function (what pins it is listed in the tests under
   likelihood and by textbook ESS / log-sum-exp special cases.
 * ``leapfrog``: pinned by time reversibility and by the O(eps^2) energy
   error of the symplectic integrator.
+* ``fisher``: pinned by the Hessian at zero residual, Gaussian moment and
+  bin-centred sinusoid closed forms, symmetry, semi-definiteness, beta scaling.
+* ``metric_factor``: pinned by numpy's Cholesky and inverse, W M W^T = I and
+  the refusal of indefinite matrices.
+* ``nuts_transition_metric``: pinned by the identity factor (equal to the
+  plain transition) and by the unit harmonic oscillator that a leapfrog step
+  in whitened coordinates follows near a noise-free fit.
 """
 from __future__ import annotations
 
@@ -85,6 +92,9 @@ def _load():
         lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
                                                      P, P, P, I64, P, P, P, P, P, P]
         lib.oracle_fisher.argtypes = [I, I64, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_nuts_transition_metric.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P,
+                                                      P, P, P, P, I64, P, P, P, P, P, P, P, P]
+        lib.oracle_metric_factor.argtypes = [I, I64, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -340,3 +350,46 @@ def fisher(model, T, t_start, dt, sigma, offsets, theta, beta=None):
         n = int(offsets[i + 1] - offsets[i]) * P
         out.append(F[fo[i]:fo[i] + n * n].reshape(n, n).copy())
     return out
+
+
+def pack_blocks(blocks):
+    """Concatenate square blocks row-major; returns (offsets, packed array)."""
+    fo = np.zeros(len(blocks) + 1, dtype=np.int64)
+    np.cumsum([b.size for b in blocks], out=fo[1:])
+    packed = np.concatenate([np.ravel(b) for b in blocks]) if fo[-1] else np.zeros(0)
+    return fo, np.ascontiguousarray(packed, dtype=np.float64)
+
+
+def metric_factor(model, offsets, blocks, ridge):
+    """W = L^{-1} of M = F + diag(ridge) per particle (blocks: list of (K P)^2
+    arrays); returns (list of W blocks, status array)."""
+    offsets = _i64(offsets)
+    N = offsets.shape[0] - 1
+    fo, F = pack_blocks(blocks)
+    W = np.empty(max(F.size, 1))
+    status = np.zeros(N, dtype=np.int32)
+    ridge = _f64(np.broadcast_to(np.asarray(ridge, dtype=np.float64), (n_params(model),)))
+    _check(_load().oracle_metric_factor(model, N, _p(offsets), _p(fo), _p(F), _p(ridge), _p(W),
+                                        _p(status)), "metric_factor")
+    return [W[fo[i]:fo[i + 1]].reshape(blocks[i].shape).copy() for i in range(N)], status
+
+
+def nuts_transition_metric(model, d, t_start, dt, sigma, offsets, beta, eps, max_depth, q, logl,
+                           grad, momentum, dirs, u_leaf, u_tree, w_blocks, split=0, prior_lo=None,
+                           prior_hi=None):
+    """NUTS transition with the mass matrix (W^T W)^{-1}; momentum is the whitened draw."""
+    d, offsets, beta = _f64(d), _i64(offsets), _f64(beta)
+    q, logl, grad = (np.array(x, dtype=np.float64, order="C", copy=True) for x in (q, logl, grad))
+    momentum, u_leaf, u_tree = _f64(momentum), _f64(u_leaf), _f64(u_tree)
+    dirs = np.ascontiguousarray(dirs, dtype=np.int8)
+    lo, hi = _f64(prior_lo), _f64(prior_hi)
+    N = offsets.shape[0] - 1
+    wo, W = pack_blocks(w_blocks)
+    W = W if W.size else np.zeros(1)
+    depth, steps, status = (np.zeros(N, dtype=np.int32) for _ in range(3))
+    _check(_load().oracle_nuts_transition_metric(
+        model, _p(d), d.shape[0], t_start, dt, sigma, N, _p(offsets), _p(beta), eps,
+        int(max_depth), _p(lo), _p(hi), _p(momentum), _p(dirs), _p(u_leaf), _p(u_tree), int(split),
+        _p(wo), _p(W), _p(q), _p(logl), _p(grad), _p(depth), _p(steps), _p(status)),
+        "nuts_transition_metric")
+    return q, logl, grad, depth, steps, status

@@ -581,6 +581,14 @@ static double dot(const double* a, const double* b, int64_t n) {
   for (int64_t x = 0; x < n; ++x) s += a[x] * b[x];
   return s;
 }
+/* y = W v (trans == 0) or W^T v (trans == 1) for an n x n row-major W */
+static void matvec(const double* W, int64_t n, int trans, const double* v, double* y) {
+  for (int64_t a = 0; a < n; ++a) {
+    double s = 0.0;
+    for (int64_t c = 0; c < n; ++c) s += (trans ? W[c * n + a] : W[a * n + c]) * v[c];
+    y[a] = s;
+  }
+}
 static double logaddexp(double a, double b) {
   double m = a > b ? a : b;
   if (m == -INFINITY) return -INFINITY;
@@ -600,11 +608,19 @@ static int nuts_impl(int model, const double* d, int64_t T, double t_start, doub
                      double sigma, int64_t N, const int64_t* offsets, const double* beta,
                      double eps, int max_depth, const double* prior_lo, const double* prior_hi,
                      const double* momentum, const int8_t* dirs, const double* u_leaf,
-                     const double* u_tree, int64_t split, double* q, double* logl, double* grad,
-                     int32_t* depth_out, int32_t* steps_out, int32_t* status_out) {
+                     const double* u_tree, int64_t split, const int64_t* w_off, const double* W,
+                     double* q, double* logl, double* grad, int32_t* depth_out,
+                     int32_t* steps_out, int32_t* status_out) {
   if (check_population(model, N, offsets, q) != OR_OK || max_depth < 1 || max_depth > 16)
     return OR_EINVAL;
   int P = oracle_n_params(model);
+  if (W) {
+    if (!w_off) return OR_EINVAL;
+    for (int64_t i = 0; i < N; ++i) {
+      int64_t n = (offsets[i + 1] - offsets[i]) * P;
+      if (w_off[i + 1] - w_off[i] != n * n || w_off[i] < 0) return OR_EINVAL;
+    }
+  }
   int64_t nleaf = ((int64_t)1 << max_depth) - 1;
 #pragma omp parallel for schedule(dynamic)
   for (int64_t i = 0; i < N; ++i) {
@@ -626,6 +642,8 @@ static int nuts_impl(int model, const double* d, int64_t T, double t_start, doub
            *rhoT = buf + 13 * n, *rhoS = buf + 14 * n, *tmp = buf + 15 * n;
     double* ckP = buf + 16 * n;                 /* [max_depth][n] */
     double* ckR = buf + (16 + max_depth) * n;  /* [max_depth][n] */
+    const double* Wi = W ? W + w_off[i] : NULL;
+    double* wv = W ? (double*)malloc((size_t)n * sizeof(double)) : NULL;
     const double* p0 = momentum + offsets[i] * P;
     double l0 = logl[i];
     double H0 = -l0 + 0.5 * dot(p0, p0, n);
@@ -651,16 +669,25 @@ static int nuts_impl(int model, const double* d, int64_t T, double t_start, doub
         for (int64_t x = 0; x < n; ++x) rhoS[x] = 0.0;
         int stop = 0;
         for (int64_t leaf = 0; leaf < ((int64_t)1 << j); ++leaf) {
-          /* leapfrog step from the frontier */
-          for (int64_t x = 0; x < n; ++x) {
-            pF[x] = pF[x] + 0.5 * e * gF[x];
-            qF[x] = qF[x] + e * pF[x];
+          /* leapfrog step from the frontier; with a metric the momentum is
+           * the whitened one: kicks by W grad, drift by W^T p */
+          if (!Wi) {
+            for (int64_t x = 0; x < n; ++x) {
+              pF[x] = pF[x] + 0.5 * e * gF[x];
+              qF[x] = qF[x] + e * pF[x];
+            }
+          } else {
+            matvec(Wi, n, 0, gF, wv);
+            for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * wv[x];
+            matvec(Wi, n, 1, pF, wv);
+            for (int64_t x = 0; x < n; ++x) qF[x] = qF[x] + e * wv[x];
           }
           if (split == 0)
             particle_logl_grad(model, d, T, t_start, dt, sigma, K, qF, b, &lF, gF);
           else
             particle_logl_grad_split(model, d, T, t_start, dt, sigma, K, qF, b, split, &lF, gF);
-          for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * gF[x];
+          if (Wi) matvec(Wi, n, 0, gF, wv);
+          for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * (Wi ? wv[x] : gF[x]);
           steps += 1;
           double H = inside_box(qF, n, P, prior_lo, prior_hi) ? -lF + 0.5 * dot(pF, pF, n)
                                                               : INFINITY;
@@ -718,6 +745,7 @@ static int nuts_impl(int model, const double* d, int64_t T, double t_start, doub
     steps_out[i] = steps;
     status_out[i] = status;
     free(buf);
+    free(wv);
   }
   return OR_OK;
 }
@@ -730,8 +758,8 @@ int oracle_nuts_transition(int model, const double* d, int64_t T, double t_start
                            double* grad, int32_t* depth_out, int32_t* steps_out,
                            int32_t* status_out) {
   return nuts_impl(model, d, T, t_start, dt, sigma, N, offsets, beta, eps, max_depth, prior_lo,
-                   prior_hi, momentum, dirs, u_leaf, u_tree, 0, q, logl, grad, depth_out, steps_out,
-                   status_out);
+                   prior_hi, momentum, dirs, u_leaf, u_tree, 0, NULL, NULL, q, logl, grad, depth_out,
+                   steps_out, status_out);
 }
 
 /* The NUTS transition for the posterior-start bridge target (split > 0). */
@@ -745,8 +773,33 @@ int oracle_nuts_transition_split(int model, const double* d, int64_t T, double t
                                  int32_t* status_out) {
   if (split < 0) return OR_EINVAL;
   return nuts_impl(model, d, T, t_start, dt, sigma, N, offsets, beta, eps, max_depth, prior_lo,
-                   prior_hi, momentum, dirs, u_leaf, u_tree, split, q, logl, grad, depth_out,
-                   steps_out, status_out);
+                   prior_hi, momentum, dirs, u_leaf, u_tree, split, NULL, NULL, q, logl, grad,
+                   depth_out, steps_out, status_out);
+}
+
+/* The NUTS transition with a mass matrix M given through a factor W with
+ * M^{-1} = W^T W (one n x n row-major block per particle at W + w_off[i],
+ * n = K P; for example W = L^{-1} with M = L L^T, as oracle_metric_factor
+ * gives). The momentum input is the whitened momentum r = W p_M, so the
+ * draw stays N(0, I) and the kinetic energy |r|^2 / 2 equals
+ * p_M^T M^{-1} p_M / 2. Hamilton's equations in (q, r) read
+ *   dq/dt = W^T r,   dr/dt = W grad(beta logL),
+ * so a leapfrog step kicks by (eps/2) W g and drifts by eps W^T r, and the
+ * U-turn test rho.r is the metric's generalised criterion. split > 0 selects
+ * the posterior-start bridge target as in oracle_nuts_transition_split. */
+int oracle_nuts_transition_metric(int model, const double* d, int64_t T, double t_start,
+                                  double dt, double sigma, int64_t N, const int64_t* offsets,
+                                  const double* beta, double eps, int max_depth,
+                                  const double* prior_lo, const double* prior_hi,
+                                  const double* momentum, const int8_t* dirs,
+                                  const double* u_leaf, const double* u_tree, int64_t split,
+                                  const int64_t* w_off, const double* W, double* q, double* logl,
+                                  double* grad, int32_t* depth_out, int32_t* steps_out,
+                                  int32_t* status_out) {
+  if (split < 0 || !W) return OR_EINVAL;
+  return nuts_impl(model, d, T, t_start, dt, sigma, N, offsets, beta, eps, max_depth, prior_lo,
+                   prior_hi, momentum, dirs, u_leaf, u_tree, split, w_off, W, q, logl, grad,
+                   depth_out, steps_out, status_out);
 }
 
 /* ------------------------------------------------------------------ SMC steps
@@ -990,6 +1043,62 @@ int oracle_fisher(int model, int64_t T, double t_start, double dt, double sigma,
     }
     for (int64_t x = 0; x < n * n; ++x) Fi[x] = b * (Fi[x] / (sigma * sigma));
     free(J);
+  }
+  return OR_OK;
+}
+
+/* Factor of the NUTS mass matrix from the metric: M = F + diag(ridge) with
+ * ridge[p] added to the diagonal entry of parameter p of every component (a
+ * floor where F is singular, e.g. the prior's precision), factored as
+ * M = L L^T (Cholesky, row by row) and inverted by forward substitution:
+ * W = L^{-1}, lower triangular, so M^{-1} = W^T W. Only the lower triangle of
+ * each F block is read. Blocks share f_offsets' layout; W may not alias F.
+ * status[i] = 0, or 1 when M is not numerically positive definite (a pivot
+ * <= 0 or NaN), in which case particle i's W block is all NaN. */
+int oracle_metric_factor(int model, int64_t N, const int64_t* offsets, const int64_t* f_offsets,
+                         const double* F, const double* ridge, double* W, int32_t* status) {
+  if (N < 0 || (N > 0 && (!offsets || !f_offsets || !ridge || !status))) return OR_EINVAL;
+  int P = oracle_n_params(model);
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t n = (offsets[i + 1] - offsets[i]) * P;
+    if (n < 0 || f_offsets[i + 1] - f_offsets[i] != n * n) return OR_EINVAL;
+  }
+  if (N > 0 && f_offsets[N] > 0 && (!F || !W)) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t n = (offsets[i + 1] - offsets[i]) * P;
+    status[i] = 0;
+    if (n == 0) continue;
+    const double* Fi = F + f_offsets[i];
+    double* Wi = W + f_offsets[i];
+    double* L = (double*)calloc((size_t)(n * n), sizeof(double));
+    int ok = 1;
+    for (int64_t r = 0; r < n && ok; ++r) {
+      for (int64_t c = 0; c <= r; ++c) {
+        double v = Fi[r * n + c] + (r == c ? ridge[r % P] : 0.0);
+        for (int64_t k = 0; k < c; ++k) v -= L[r * n + k] * L[c * n + k];
+        if (r == c) {
+          if (!(v > 0.0)) { ok = 0; break; }
+          L[r * n + r] = sqrt(v);
+        } else {
+          L[r * n + c] = v / L[c * n + c];
+        }
+      }
+    }
+    if (!ok) {
+      status[i] = 1;
+      for (int64_t x = 0; x < n * n; ++x) Wi[x] = NAN;
+    } else {
+      /* column c of W solves L w = e_c */
+      for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < n; ++r) {
+          if (r < c) { Wi[r * n + c] = 0.0; continue; }
+          double v = r == c ? 1.0 : 0.0;
+          for (int64_t k = c; k < r; ++k) v -= L[r * n + k] * Wi[k * n + c];
+          Wi[r * n + c] = v / L[r * n + r];
+        }
+    }
+    free(L);
   }
   return OR_OK;
 }
