@@ -92,6 +92,7 @@ def _load():
         lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
                                                      P, P, P, I64, P, P, P, P, P, P]
         lib.oracle_fisher.argtypes = [I, I64, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_fisher_split.argtypes = [I, I64, D, D, D, I64, P, P, P, I64, P, P]
         lib.oracle_nuts_transition_metric.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P,
                                                       P, P, P, P, I64, P, P, P, P, P, P, P, P]
         lib.oracle_metric_factor.argtypes = [I, I64, P, P, P, P, P, P]
@@ -336,15 +337,21 @@ def fisher_offsets(model, offsets):
     return out
 
 
-def fisher(model, T, t_start, dt, sigma, offsets, theta, beta=None):
-    """Gauss-Newton metric of every particle; returns a list of (K P) x (K P) arrays."""
+def fisher(model, T, t_start, dt, sigma, offsets, theta, beta=None, split=None):
+    """Gauss-Newton metric of every particle; returns a list of (K P) x (K P) arrays.
+    With split given, the metric of the posterior-start bridge target."""
     offsets, theta, beta = _i64(offsets), _f64(theta), _f64(beta)
     N = offsets.shape[0] - 1
     P = n_params(model)
     fo = fisher_offsets(model, offsets)
     F = np.empty(max(int(fo[-1]), 1))
-    _check(_load().oracle_fisher(model, int(T), t_start, dt, sigma, N, _p(offsets), _p(theta),
-                                 _p(beta), _p(fo), _p(F)), "fisher")
+    if split is None:
+        _check(_load().oracle_fisher(model, int(T), t_start, dt, sigma, N, _p(offsets), _p(theta),
+                                     _p(beta), _p(fo), _p(F)), "fisher")
+    else:
+        _check(_load().oracle_fisher_split(model, int(T), t_start, dt, sigma, N, _p(offsets),
+                                           _p(theta), _p(beta), int(split), _p(fo), _p(F)),
+               "fisher_split")
     out = []
     for i in range(N):
         n = int(offsets[i + 1] - offsets[i]) * P

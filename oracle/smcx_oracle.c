@@ -1014,9 +1014,29 @@ int oracle_rj_apply(int model, int64_t N, const int64_t* offsets, const double* 
  * (exact when the residual vanishes). Output: the (K P) x (K P) matrix of
  * particle i, row-major, at F + f_offsets[i], where the caller's
  * f_offsets[i+1] - f_offsets[i] must equal (K_i P)^2. */
+static int fisher_impl(int model, int64_t T, double t_start, double dt, double sigma, int64_t N,
+                       const int64_t* offsets, const double* theta, const double* beta,
+                       int64_t split, const int64_t* f_offsets, double* F);
+
 int oracle_fisher(int model, int64_t T, double t_start, double dt, double sigma, int64_t N,
                   const int64_t* offsets, const double* theta, const double* beta,
                   const int64_t* f_offsets, double* F) {
+  return fisher_impl(model, T, t_start, dt, sigma, N, offsets, theta, beta, 0, f_offsets, F);
+}
+
+/* The metric of the posterior-start bridge target (eq. reuse_bridge):
+ * samples before `split` enter with weight 1, later ones with beta_i,
+ *   F = (1 / sigma^2) sum_s w_s J_s J_s^T,  w_s = 1 (s < split) or beta_i. */
+int oracle_fisher_split(int model, int64_t T, double t_start, double dt, double sigma, int64_t N,
+                        const int64_t* offsets, const double* theta, const double* beta,
+                        int64_t split, const int64_t* f_offsets, double* F) {
+  if (split < 0) return OR_EINVAL;
+  return fisher_impl(model, T, t_start, dt, sigma, N, offsets, theta, beta, split, f_offsets, F);
+}
+
+static int fisher_impl(int model, int64_t T, double t_start, double dt, double sigma, int64_t N,
+                       const int64_t* offsets, const double* theta, const double* beta,
+                       int64_t split, const int64_t* f_offsets, double* F) {
   if (check_population(model, N, offsets, theta) != OR_OK || T < 0 || !f_offsets)
     return OR_EINVAL;
   int P = oracle_n_params(model);
@@ -1037,11 +1057,14 @@ int oracle_fisher(int model, int64_t T, double t_start, double dt, double sigma,
     for (int64_t x = 0; x < n * n; ++x) Fi[x] = 0.0;
     for (int64_t s = 0; s < T; ++s) {
       double t = t_start + (double)s * dt;
+      double ws = split == 0 ? 1.0 : sample_weight(s, split, b);
       for (int64_t k = 0; k < K; ++k) template_partials(model, th + k * P, t, J + k * P);
       for (int64_t a = 0; a < n; ++a)
-        for (int64_t c = 0; c < n; ++c) Fi[a * n + c] += J[a] * J[c];
+        for (int64_t c = 0; c < n; ++c) Fi[a * n + c] += ws * (J[a] * J[c]);
     }
-    for (int64_t x = 0; x < n * n; ++x) Fi[x] = b * (Fi[x] / (sigma * sigma));
+    /* without a split the tempering is one factor outside the sum */
+    double outer = split == 0 ? b : 1.0;
+    for (int64_t x = 0; x < n * n; ++x) Fi[x] = outer * (Fi[x] / (sigma * sigma));
     free(J);
   }
   return OR_OK;

@@ -91,3 +91,30 @@ def test_fisher_symmetric_psd_and_beta_linear(orc):
         s = np.sqrt(np.diag(a))
         assert np.linalg.eigvalsh(a / np.outer(s, s)).min() > -1e-9
         assert np.allclose(b, beta[i] * a, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("model", [PULSE, GB])
+def test_fisher_split_is_the_sum_of_its_segments(orc, model):
+    """The bridge target's metric (samples before the split untempered, later
+    ones weighted by beta) equals the metric of the first segment plus beta
+    times that of the second, each computed on its own time grid."""
+    w = wl.make_config("pulse_small" if model == PULSE else "gb_grad", N=5, T=900, k_lo=1,
+                       k_hi=4, seed=74)
+    beta = np.linspace(0.15, 0.9, w.N)
+    ones = np.ones(w.N)
+    for split in (1, 333, 899):
+        got = orc.fisher(model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta, split=split)
+        a = orc.fisher(model, split, w.t_start, w.dt, w.sigma, w.offsets, w.theta, ones)
+        b = orc.fisher(model, w.T - split, w.t_start + split * w.dt, w.dt, w.sigma, w.offsets,
+                       w.theta, ones)
+        for i in range(w.N):
+            ref = a[i] + beta[i] * b[i]
+            s = np.sqrt(np.outer(np.diag(ref), np.diag(ref)))
+            assert np.all(np.abs(got[i] - ref) <= 1e-12 * s), (split, i)
+    # split = T is the untempered metric and split = 0 the tempered one, exactly
+    full = orc.fisher(model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta, split=w.T)
+    unt = orc.fisher(model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, ones)
+    zero = orc.fisher(model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta, split=0)
+    tem = orc.fisher(model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta)
+    for x, y in zip(full + zero, unt + tem):
+        assert np.array_equal(x, y)
