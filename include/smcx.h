@@ -237,7 +237,8 @@ int smcx_nuts_reserve(smcx_problem* prob, int32_t max_depth);
  * all trajectories built in lockstep on the device (multinomial NUTS,
  * generalised U-turn criterion on every balanced sub-block and on the whole
  * trajectory, divergence when the energy rises by more than 1000 or a
- * position leaves the prior box, tree depth <= max_depth, identity metric).
+ * position leaves the prior box, tree depth <= max_depth, identity metric;
+ * smcx_nuts_transition_metric below takes a dense mass matrix).
  * Each doubling of depth j runs 2^j batched leapfrog steps (smcx_leapfrog's
  * arithmetic) each followed by a controller pass, and is captured once into
  * a hipGraph and replayed when use_graph != 0 (the graph is rebuilt when any
@@ -267,6 +268,30 @@ int smcx_nuts_transition(smcx_problem* prob, int64_t N, const int64_t* offsets, 
                          const uint8_t* mask, double* q, double* logl, double* grad,
                          int32_t* depth_out, int32_t* steps_out, int32_t* status_out,
                          int32_t use_graph, void* hip_stream);
+
+/* smcx_nuts_transition with the mass matrix M_i = (W_i^T W_i)^{-1} of each
+ * particle (Sec. "No-U-Turn-Sampler": momentum ~ N(0, M), kinetic energy
+ * r^T M^{-1} r / 2, M the Hessian of the negative log posterior), given by
+ * a factor W_i such as the one smcx_metric_factor returns: a dense
+ * (K_i P)^2 row-major block at W + w_offsets[i] (device, int64 [N+1]; w_size
+ * entries in W). The transition runs in whitened momentum: `momentum` holds
+ * the standard-normal draws z = W p_M, each leapfrog step kicks by
+ * (eps/2) W grad and drifts by eps W^T z, and the energy and the U-turn test
+ * use |z|^2 and rho.z (the metric's generalised criterion). eps is then in
+ * the metric's units (order one when M is the posterior's Hessian). Needs
+ * k_max P <= 128. A particle whose block does not match (K_i P)^2 or lies
+ * outside W keeps its state, reports status -1 and raises a device flag.
+ * Other arguments and behaviour as smcx_nuts_transition; with W_i = I the
+ * result equals it bitwise. */
+int smcx_nuts_transition_metric(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                                const double* beta, double eps, int32_t max_depth,
+                                const double* prior_lo, const double* prior_hi,
+                                const double* momentum, const int8_t* dirs, const double* u_leaf,
+                                const double* u_tree, const uint8_t* mask,
+                                const int64_t* w_offsets, int64_t w_size, const double* W,
+                                double* q, double* logl, double* grad, int32_t* depth_out,
+                                int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                                void* hip_stream);
 
 /* Tiling of the sample axis, per call kind: SMCX_KIND_LOGL (logl_batch and
  * the segment pass of reweight_extend), SMCX_KIND_GRAD (logl_grad_batch),
@@ -318,12 +343,33 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
  * (s = (1, w, w) for pulses, (1, 1/T_obs, 1/T_obs^2, 1) for sinusoids),
  * rounded to FP16, and J^T J accumulated in FP32 (flushed to FP64 every 4096
  * samples). The relative error of an entry is then bounded by about 1e-3 of
- * sqrt(F_aa F_cc), ample for a preconditioner. Requires k_max P <= 128 and no
- * bridge split. beta may be NULL (1). Every sample is evaluated (no pulse
+ * sqrt(F_aa F_cc), ample for a preconditioner. Requires k_max P <= 128.
+ * With a bridge split set (smcx_set_bridge_split) it is the metric of the
+ * bridge target: samples before the split enter with weight 1, later ones
+ * with beta_i. beta may be NULL (1). Every sample is evaluated (no pulse
  * truncation). */
 int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                              const double* theta, const double* beta, const int64_t* f_offsets,
                              int64_t f_size, double* F, void* hip_stream);
+
+/* Factor of the NUTS mass matrix built from the metric (Sec. "No-U-Turn-
+ * Sampler": mass matrix = Hessian of the negative log posterior). Per
+ * particle M_i = F_i + diag(ridge), ridge[p] (host array, P values >= 0)
+ * added to the diagonal entry of parameter p of every component -- a floor
+ * where F is singular, e.g. the uniform prior's precision 12 / width^2 --
+ * factored as M_i = L L^T (Cholesky, FP64) and inverted: W_i = L^{-1}, lower
+ * triangular, written as a dense (K_i P)^2 row-major block at W + f_offsets[i]
+ * with zeros above the diagonal, so that M_i^{-1} = W_i^T W_i. Only the lower
+ * triangle of each F block is read; W may equal F (in place). A block that
+ * is not numerically positive definite (a pivot <= 0 or NaN) is written as
+ * NaN and raises a device flag; offsets that disagree with (K_i P)^2 or
+ * blocks beyond f_size skip the particle and raise a flag. One workgroup per
+ * particle keeps its triangle in LDS: needs k_max P <= 128 and
+ * (k_max P)(k_max P + 1)/2 doubles of LDS per workgroup (SMCX_EINVAL
+ * otherwise). Capture-safe: one launch, no allocation. */
+int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                       const int64_t* f_offsets, int64_t f_size, const double* F,
+                       const double* ridge, double* W, void* hip_stream);
 
 /* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
  * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first
@@ -341,6 +387,7 @@ int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offse
  * to run while a split is set. The incremental weights of this bridge are
  * (beta - beta_prev) times the untempered log-likelihood of samples
  * [split, T), which reweight_extend(prob, split, T, ...) computes.
+ * smcx_gauss_newton_metric follows the split as well.
  * 0 <= split <= T. */
 int smcx_set_bridge_split(smcx_problem* prob, int64_t split);
 int smcx_get_bridge_split(smcx_problem* prob, int64_t* split);

@@ -252,6 +252,8 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
   p->m_max = m_max;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
+  e = hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipDeviceGetAttribute"); }
 
   p->max_nch = cap_chunks(T);
   p->max_nch_grad = cap_chunks_grad(T);
@@ -338,13 +340,14 @@ int smcx_device_status(smcx_problem* p, void* hip_stream) {
   if (e != hipSuccess) return hip_fail(e, "device flag read");
   if (flag == 0) return SMCX_OK;
   std::string msg = "device-side argument errors:";
-  if (flag & smcx::kFlagOffsets) msg += " offsets not a valid CSR prefix sum;";
+  if (flag & smcx::kFlagOffsets) msg += " offsets (or metric block offsets) not a valid prefix sum;";
   if (flag & smcx::kFlagKMax) msg += " a particle has K > k_max;";
   if (flag & smcx::kFlagMMax) msg += " offsets[N] differs from M;";
   if (flag & smcx::kFlagDeath) msg += " death index outside [-1, K);";
   if (flag & smcx::kFlagPhase) msg += " sinusoid frequency too high for the sample spacing;";
   if (flag & smcx::kFlagCapacity) msg += " rebuilt population exceeds the output rows (m_cap);";
   if (flag & smcx::kFlagWeights) msg += " resampling weights have no positive entry;";
+  if (flag & smcx::kFlagNotPD) msg += " a metric block is not positive definite (its factor is NaN);";
   return fail(SMCX_EDEVICE, "%s", msg.c_str());
 }
 
@@ -618,16 +621,23 @@ uint64_t mix_key(uint64_t h, uint64_t v) {
 }
 }  // namespace
 
-int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                         const double* beta, double eps, int32_t max_depth,
-                         const double* prior_lo, const double* prior_hi, const double* momentum,
-                         const int8_t* dirs, const double* u_leaf, const double* u_tree,
-                         const uint8_t* mask, double* q, double* logl, double* grad,
-                         int32_t* depth_out, int32_t* steps_out, int32_t* status_out,
-                         int32_t use_graph, void* hip_stream) {
-  g_last_error.clear();
+namespace {
+int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                    const double* beta, double eps, int32_t max_depth, const double* prior_lo,
+                    const double* prior_hi, const double* momentum, const int8_t* dirs,
+                    const double* u_leaf, const double* u_tree, const uint8_t* mask,
+                    const int64_t* w_offsets, int64_t w_size, const double* W, double* q,
+                    double* logl, double* grad, int32_t* depth_out, int32_t* steps_out,
+                    int32_t* status_out, int32_t use_graph, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, q);
   if (rc) return rc;
+  if (W) {
+    if (!w_offsets) return fail(SMCX_EINVAL, "w_offsets is NULL");
+    if (w_size < 0) return fail(SMCX_EINVAL, "w_size must be >= 0");
+    if ((int64_t)p->k_max * p->P > smcx::kNutsMetricMax)
+      return fail(SMCX_EINVAL, "a NUTS metric needs k_max * P <= %d (here %d)", smcx::kNutsMetricMax,
+                  p->k_max * p->P);
+  }
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(SMCX_EINVAL, "eps must be finite and > 0");
   if (max_depth < 1 || max_depth > p->nuts_depth)
     return fail(SMCX_EINVAL, "max_depth = %d exceeds the reserved NUTS depth %d (smcx_nuts_reserve)",
@@ -668,6 +678,10 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   na.active = p->nuts_active;
   na.dir = p->nuts_dir;
   na.count = p->nuts_count;
+  na.wmat = W;
+  na.w_off = W ? w_offsets : nullptr;
+  na.w_size = w_size;
+  na.flag = p->flag;
   double* qF = p->nuts_vec + 6 * na.stride;
   double* pF = p->nuts_vec + 7 * na.stride;
   double* gF = p->nuts_vec + 8 * na.stride;
@@ -689,8 +703,10 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   a.logl = p->nuts_logl;
   a.grad = gF;
   a.active = p->nuts_active;
-  a.p_half = pH;
-  a.p_out = pF;
+  // with a metric the closing kick needs W times the whole gradient: the
+  // leaf kernel applies it instead of the gradient pass's epilogue
+  a.p_half = W ? nullptr : pH;
+  a.p_out = W ? nullptr : pF;
   a.eps = eps;
   a.dir = p->nuts_dir;
 
@@ -710,7 +726,8 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
                      (uint64_t)(uintptr_t)u_leaf, (uint64_t)(uintptr_t)u_tree,
                      (uint64_t)(uintptr_t)q, (uint64_t)(uintptr_t)logl, (uint64_t)(uintptr_t)grad,
                      (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth,
-                     (uint64_t)p->split})
+                     (uint64_t)p->split, (uint64_t)(uintptr_t)W, (uint64_t)(uintptr_t)w_offsets,
+                     (uint64_t)w_size})
     key = mix_key(key, v);
   uint64_t eb;
   std::memcpy(&eb, &eps, sizeof(eb));
@@ -751,6 +768,37 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
   e = smcx::launch_nuts_finalize(na, st);
   if (e != hipSuccess) return hip_fail(e, "NUTS finalize launch");
   return SMCX_OK;
+}
+}  // namespace
+
+int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                         const double* beta, double eps, int32_t max_depth,
+                         const double* prior_lo, const double* prior_hi, const double* momentum,
+                         const int8_t* dirs, const double* u_leaf, const double* u_tree,
+                         const uint8_t* mask, double* q, double* logl, double* grad,
+                         int32_t* depth_out, int32_t* steps_out, int32_t* status_out,
+                         int32_t use_graph, void* hip_stream) {
+  g_last_error.clear();
+  return nuts_transition(p, N, offsets, M, beta, eps, max_depth, prior_lo, prior_hi, momentum, dirs,
+                         u_leaf, u_tree, mask, nullptr, 0, nullptr, q, logl, grad, depth_out,
+                         steps_out, status_out, use_graph, hip_stream);
+}
+
+int smcx_nuts_transition_metric(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                                const double* beta, double eps, int32_t max_depth,
+                                const double* prior_lo, const double* prior_hi,
+                                const double* momentum, const int8_t* dirs, const double* u_leaf,
+                                const double* u_tree, const uint8_t* mask,
+                                const int64_t* w_offsets, int64_t w_size, const double* W,
+                                double* q, double* logl, double* grad, int32_t* depth_out,
+                                int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                                void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (!W && N > 0) return fail(SMCX_EINVAL, "W is NULL");
+  return nuts_transition(p, N, offsets, M, beta, eps, max_depth, prior_lo, prior_hi, momentum, dirs,
+                         u_leaf, u_tree, mask, w_offsets, w_size, W, q, logl, grad, depth_out,
+                         steps_out, status_out, use_graph, hip_stream);
 }
 
 int smcx_set_bridge_split(smcx_problem* p, int64_t split) {
@@ -909,13 +957,37 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
   if ((int64_t)p->k_max * p->P > 128)
     return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
-  if (p->split != 0)
-    return fail(SMCX_EINVAL, "the metric is defined for the prior bridge only (bridge split is set)");
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
                                      p->k_max, offsets, theta, beta, f_offsets, f_size, F,
-                                     p->flag, st);
+                                     p->split, p->flag, st);
   if (e != hipSuccess) return hip_fail(e, "metric launch");
+  return SMCX_OK;
+}
+
+int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                       const int64_t* f_offsets, int64_t f_size, const double* F,
+                       const double* ridge, double* W, void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, F ? F : W);  // theta is not read: only the sizes matter
+  if (rc) return rc;
+  if (N == 0) return SMCX_OK;
+  if (!f_offsets) return fail(SMCX_EINVAL, "f_offsets is NULL");
+  if (f_size < 0 || (f_size > 0 && (!F || !W))) return fail(SMCX_EINVAL, "bad f_size / F / W");
+  if (!ridge) return fail(SMCX_EINVAL, "ridge is NULL");
+  for (int q = 0; q < p->P; ++q)
+    if (!(ridge[q] >= 0.0) || !std::isfinite(ridge[q]))
+      return fail(SMCX_EINVAL, "ridge[%d] must be finite and >= 0", q);
+  const int nmax = p->k_max * p->P;
+  if (nmax > smcx::kNutsMetricMax)
+    return fail(SMCX_EINVAL, "the metric factor supports k_max * P <= %d", smcx::kNutsMetricMax);
+  if ((int64_t)smcx::factor_lds_bytes(nmax) > (int64_t)p->lds_max)
+    return fail(SMCX_EINVAL, "k_max * P = %d needs %zu bytes of LDS per workgroup; the device has %d",
+                nmax, smcx::factor_lds_bytes(nmax), p->lds_max);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e = smcx::launch_metric_factor(p->P, N, M, p->k_max, offsets, f_offsets, f_size, F,
+                                            ridge, W, p->flag, st);
+  if (e != hipSuccess) return hip_fail(e, "metric factor launch");
   return SMCX_OK;
 }
 

@@ -21,6 +21,7 @@ enum : int {
   kFlagPhase = 16,    // GB phase increment too large for the per-tile reduction
   kFlagCapacity = 32, // a rebuilt population needs more rows than the output holds
   kFlagWeights = 64,  // resampling weights without a positive entry
+  kFlagNotPD = 128,   // a metric block is not positive definite (its factor is NaN)
 };
 
 // Per-particle workspace of the SMC steps (resampling, birth/death rebuild).
@@ -155,7 +156,15 @@ struct NutsArgs {
   uint8_t* active;         // [N]
   int8_t* dir;             // [N]
   int* count;              // [D + 1]
+  // mass matrix (W^T W)^{-1}: per-particle n x n row-major blocks W at
+  // wmat + w_off[i] (n = K P <= kNutsMetricMax), or wmat == nullptr for the
+  // identity; the momentum is then the whitened one
+  const double* wmat;
+  const int64_t* w_off;    // [N + 1]
+  int64_t w_size;          // entries of wmat
+  int* flag;
 };
+constexpr int kNutsMetricMax = 128;  // coordinates per particle with a metric (two per lane)
 constexpr int kNutsMaxDepth = 10;
 constexpr int kNutsSlots(int D) { return 16 + 2 * D; }
 
@@ -173,7 +182,14 @@ int64_t prep_slices(int64_t N);
 hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
-                         int64_t f_size, double* F, int* flag, hipStream_t st);
+                         int64_t f_size, double* F, int64_t split, int* flag, hipStream_t st);
+// Factor W = L^{-1} of F + diag(ridge) per particle (smcx_metric.hip); ridge is
+// a host array of P values; LDS bytes of one workgroup for k_max * P = nmax.
+hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
+                                const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
+                                const double* F, const double* ridge, double* W, int* flag,
+                                hipStream_t st);
+size_t factor_lds_bytes(int nmax);
 
 // SMC steps (smcx_smc.hip).
 hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,

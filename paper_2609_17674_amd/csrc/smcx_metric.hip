@@ -48,6 +48,7 @@ struct MetricArgs {
   double* F;
   int* flag;
   int64_t w0, w1;  // sample window of this launch; the first window writes F, later ones add
+  int tempered;    // 1: the window's samples carry beta_i (0: before a bridge split)
 };
 
 // Per-lane description of one coordinate (component k, parameter p), set up
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const double bs = (a.beta ? a.beta[i] : 1.0) * a.inv_sigma2;
+  const double bs = (a.tempered && a.beta ? a.beta[i] : 1.0) * a.inv_sigma2;
   const int half = lane >> 5;  // which group of 4 samples of a step this lane feeds
   float16v acc[NP];
 #pragma unroll
@@ -211,23 +212,146 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- factor
+// W = L^{-1} of M = F + diag(ridge) (M = L L^T), the NUTS mass matrix's
+// factor with M^{-1} = W^T W. One workgroup of one wave per particle keeps
+// the lower triangle of its block packed in LDS (row r at r (r + 1) / 2):
+// right-looking Cholesky, one column per step (the subtractions into each
+// entry come in column order, as in the row-by-row textbook form), then the
+// in-place inversion of the triangle from the last column to the first with
+// W_rj = -(sum_{j<k<=r} W_rk L_kj) / L_jj, W_jj = 1 / L_jj. Lanes own rows;
+// barriers separate the steps. A pivot that is not > 0 (or NaN) stops the
+// factorisation: the block is filled with NaN and a flag is raised.
+struct FactorArgs {
+  int P;
+  int64_t N, M;
+  int32_t k_max;
+  const int64_t* offsets;
+  const int64_t* f_offsets;
+  int64_t f_size;
+  const double* F;
+  double* W;
+  double ridge[4];
+  int* flag;
+};
+
+__device__ __forceinline__ int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+__global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
+  extern __shared__ double L[];
+  const int lane = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  if (i >= a.N) return;
+  const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+  if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  const int n = (int)(o1 - o0) * a.P;
+  const int64_t fo = a.f_offsets[i];
+  if (a.f_offsets[i + 1] - fo != (int64_t)n * n || fo < 0 || fo + (int64_t)n * n > a.f_size) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  if (n == 0) return;
+  const double* Fi = a.F + fo;
+  double* Wi = a.W + fo;
+  for (int r = 0; r < n; ++r)
+    for (int c = lane; c <= r; c += 64)
+      L[tri(r, c)] = Fi[(int64_t)r * n + c] + (r == c ? a.ridge[c % a.P] : 0.0);
+  __syncthreads();
+  bool ok = true;
+  for (int j = 0; j < n; ++j) {
+    const double d = L[tri(j, j)];
+    if (!(d > 0.0)) {  // the same value in every lane: a uniform exit
+      ok = false;
+      break;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    for (int r = j + 1 + lane; r < n; r += 64) L[tri(r, j)] = L[tri(r, j)] / ljj;
+    if (lane == 0) L[tri(j, j)] = ljj;
+    __syncthreads();
+    for (int r = j + 1 + lane; r < n; r += 64) {
+      const double lrj = L[tri(r, j)];
+      for (int c = j + 1; c <= r; ++c) L[tri(r, c)] = fma(-lrj, L[tri(c, j)], L[tri(r, c)]);
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    if (lane == 0) atomicOr(a.flag, kFlagNotPD);
+    for (int64_t e = lane; e < (int64_t)n * n; e += 64) Wi[e] = __builtin_nan("");
+    return;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const double ljj = L[tri(j, j)];
+    double acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = j + 1 + lane + 64 * t;
+      double s = 0.0;
+      if (r < n)
+        for (int k = j + 1; k <= r; ++k) s = fma(L[tri(r, k)], L[tri(k, j)], s);
+      acc[t] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = j + 1 + lane + 64 * t;
+      if (r < n) L[tri(r, j)] = -acc[t] / ljj;
+    }
+    if (lane == 0) L[tri(j, j)] = 1.0 / ljj;
+    __syncthreads();
+  }
+  for (int64_t e = lane; e < (int64_t)n * n; e += 64) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    Wi[e] = c <= r ? L[tri(r, c)] : 0.0;
+  }
+}
+
 }  // namespace
+
+size_t factor_lds_bytes(int nmax) { return (size_t)nmax * (nmax + 1) / 2 * sizeof(double); }
+
+hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
+                                const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
+                                const double* F, const double* ridge, double* W, int* flag,
+                                hipStream_t st) {
+  FactorArgs a{};
+  a.P = P;
+  a.N = N;
+  a.M = M;
+  a.k_max = k_max;
+  a.offsets = offsets;
+  a.f_offsets = f_offsets;
+  a.f_size = f_size;
+  a.F = F;
+  a.W = W;
+  for (int p = 0; p < P && p < 4; ++p) a.ridge[p] = ridge[p];
+  a.flag = flag;
+  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)N), dim3(64), factor_lds_bytes(k_max * P), st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
-                         int64_t f_size, double* F, int* flag, hipStream_t st) {
+                         int64_t f_size, double* F, int64_t split, int* flag, hipStream_t st) {
   MetricArgs a{P, N, M, T, t_start, dt, inv_sigma2, (double)T * dt, k_max, offsets, theta,
-               beta, f_offsets, f_size, F, flag, 0, 0};
+               beta, f_offsets, f_size, F, flag, 0, 0, 1};
   const int nmax = k_max * P;
   const dim3 grid((unsigned)((N + 3) / 4)), block(256);
   const int nb = nmax <= 32 ? 1 : (nmax <= 64 ? 2 : 4);
   if (nmax > 128) return hipErrorInvalidValue;
   const size_t lds = 4 * 32 * (size_t)nb * sizeof(double);
-  // one launch per window of samples: later windows add to what earlier ones wrote
-  for (int64_t w0 = 0; w0 < T; w0 += kFlushSamples) {
+  // one launch per window of samples: later windows add to what earlier ones
+  // wrote; with a bridge split the windows stop at the split, and only those
+  // after it are tempered
+  for (int64_t w0 = 0; w0 < T; w0 = a.w1) {
+    const int64_t end = split > 0 && w0 < split ? split : T;  // windows never straddle the split
     a.w0 = w0;
-    a.w1 = w0 + kFlushSamples < T ? w0 + kFlushSamples : T;
+    a.w1 = w0 + kFlushSamples < end ? w0 + kFlushSamples : end;
+    a.tempered = split == 0 || w0 >= split ? 1 : 0;
     if (model == SMCX_PULSE) {
       if (nb == 1) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 1>), grid, block, lds, st, a);
       else if (nb == 2) hipLaunchKernelGGL((metric_kernel<SMCX_PULSE, 2>), grid, block, lds, st, a);

@@ -11,16 +11,25 @@
 //  * a completed subtree replaces the trajectory proposal with probability
 //    min(1, W_subtree / W_trajectory);
 //  * the generalised U-turn test on a segment with momentum sum rho and end
-//    momenta p_a, p_b stops when rho.p_a <= 0 or rho.p_b <= 0 (identity
-//    metric); it is applied to every balanced block of the subtree as the
-//    block completes, and to the whole trajectory after each doubling;
+//    momenta p_a, p_b stops when rho.p_a <= 0 or rho.p_b <= 0; it is applied
+//    to every balanced block of the subtree as the block completes, and to
+//    the whole trajectory after each doubling;
 //  * a leaf whose energy exceeds the initial one by more than 1000, or that
 //    leaves the prior box, is a divergence and stops the trajectory;
 //  * a subtree that turns or diverges is discarded.
 // Random numbers are inputs: one direction per doubling, one uniform per
 // leaf and one per doubling.
 //
-// One wave handles one particle; lanes run over its K*P coordinates.
+// With a mass matrix M = (W^T W)^{-1} (the section's Hessian metric, W the
+// inverse Cholesky factor of the Gauss-Newton metric) the state carries the
+// whitened momentum r = W p_M, drawn N(0, I): kicks add (e/2) W g, drifts add
+// e W^T r, and the energy and U-turn test keep the identity form in r. The
+// closing kick of a leapfrog step then needs the whole gradient of the
+// particle, so it moves from the gradient pass's epilogue into the leaf
+// kernel.
+//
+// One workgroup of one wave handles one particle; lanes run over its K*P
+// coordinates (at most two each when a metric is used).
 #include "smcx_internal.h"
 
 #include <math.h>
@@ -73,17 +82,76 @@ __device__ __forceinline__ bool in_box(const NutsArgs& a, int64_t x, double q) {
   return q >= a.prior_lo[p] && q <= a.prior_hi[p];
 }
 
-// Drift of the frontier: pH = pF + (e/2) gF, qF += e pH.
-__device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e) {
-  double *q = slot(a, qF), *p = slot(a, pF), *g = slot(a, gF), *h = slot(a, pH);
-  for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
-    const double ph = fma(0.5 * e, g[x], p[x]);
-    h[x] = ph;
-    q[x] = fma(e, ph, q[x]);
+// ---- products with the metric factor (one wave per workgroup, n <= 128)
+// sh[c] = src[x0 + c], visible to the whole wave on return
+__device__ __forceinline__ void stage(double* sh, const double* src, const View& v) {
+  const int n = (int)(v.x1 - v.x0);
+  for (int c = v.lane; c < n; c += 64) sh[c] = src[v.x0 + c];
+  __syncthreads();
+}
+// y[t] = (W sh)_c for c = lane + 64 t (TRANS: (W^T sh)_c), c < n; the sum
+// runs over c' in index order with fused multiply-adds
+template <bool TRANS>
+__device__ __forceinline__ void wmul(const double* W, int n, const double* sh, int lane,
+                                     double y[2]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = lane + 64 * t;
+    double s = 0.0;
+    if (c < n)
+      for (int k = 0; k < n; ++k) s = fma(TRANS ? W[(int64_t)k * n + c] : W[(int64_t)c * n + k], sh[k], s);
+    y[t] = s;
   }
 }
+__device__ __forceinline__ const double* wblock(const NutsArgs& a, const View& v) {
+  return a.wmat + a.w_off[v.i];
+}
 
-__global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
+// Drift of the frontier: pH = pF + (e/2) gF, qF += e pH; with a metric
+// pH = pF + (e/2) W gF, qF += e W^T pH (wg: W gF when the caller has it).
+__device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e, double* sh,
+                                      const double* wg_in = nullptr) {
+  double *q = slot(a, qF), *p = slot(a, pF), *g = slot(a, gF), *h = slot(a, pH);
+  if (!a.wmat) {
+    for (int64_t x = v.x0 + v.lane; x < v.x1; x += 64) {
+      const double ph = fma(0.5 * e, g[x], p[x]);
+      h[x] = ph;
+      q[x] = fma(e, ph, q[x]);
+    }
+    return;
+  }
+  const int n = (int)(v.x1 - v.x0);
+  const double* W = wblock(a, v);
+  double wg[2], y[2];
+  if (wg_in) {
+    wg[0] = wg_in[0];
+    wg[1] = wg_in[1];
+  } else {
+    stage(sh, g, v);
+    wmul<false>(W, n, sh, v.lane, wg);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = v.lane + 64 * t;
+    if (c < n) {
+      const double ph = fma(0.5 * e, wg[t], p[v.x0 + c]);
+      h[v.x0 + c] = ph;
+      sh[c] = ph;
+    }
+  }
+  __syncthreads();
+  wmul<true>(W, n, sh, v.lane, y);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = v.lane + 64 * t;
+    if (c < n) q[v.x0 + c] = fma(e, y[t], q[v.x0 + c]);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
+  __shared__ double sh[kNutsMetricMax];
   if (blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
   const View v = view_of(a);
   if (!v.ok) {
@@ -110,7 +178,15 @@ __global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
   pp = wsum(pp);
   out = wany(out);
   const double H0 = -a.logl[v.i] + 0.5 * pp;
-  const bool still = v.K == 0 || (a.mask && !a.mask[v.i]);  // no move: kept as it is
+  // a metric block that does not match (K P)^2 or lies outside the array:
+  // the particle is kept as it is, with status -1 and the offsets flag
+  bool bad_w = false;
+  if (a.wmat && v.K > 0) {
+    const int64_t n = v.x1 - v.x0, w0 = a.w_off[v.i], w1 = a.w_off[v.i + 1];
+    bad_w = n > kNutsMetricMax || w1 - w0 != n * n || w0 < 0 || w1 > a.w_size;
+    if (bad_w && v.lane == 0) atomicOr(a.flag, kFlagOffsets);
+  }
+  const bool still = v.K == 0 || (a.mask && !a.mask[v.i]) || bad_w;  // no move: kept as it is
   const bool go = !still && !out && (H0 == H0) && fabs(H0) < INFINITY;
   const int8_t d = go ? a.dirs[v.i * a.D] : (int8_t)1;
   if (v.lane == 0) {
@@ -121,19 +197,35 @@ __global__ __launch_bounds__(256) void nuts_init_kernel(NutsArgs a) {
     s.logl_sub = a.logl[v.i];
     s.depth = 0;
     s.steps = 0;
-    s.status = still ? 0 : (go ? 4 : 2);
+    s.status = bad_w ? -1 : (still ? 0 : (go ? 4 : 2));
     a.active[v.i] = go ? 1 : 0;
     a.dir[v.i] = d;
   }
-  if (go) drift(a, v, a.eps * (double)d);
+  if (go) drift(a, v, a.eps * (double)d, sh);
 }
 
 // Leaf n of the doubling at depth j (the frontier has just been moved by one
 // leapfrog step: qF, pF, gF and the frontier logL are current).
-__global__ __launch_bounds__(256) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
+__global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
+  __shared__ double sh[kNutsMetricMax];
   const View v = view_of(a);
   if (!v.ok || !a.active[v.i]) return;
   NutsState& s = a.state[v.i];
+  const double e = a.eps * (double)a.dir[v.i];
+  double wg[2];
+  if (a.wmat) {  // closing half-kick of the step: pF = pH + (e/2) W gF
+    const int nc = (int)(v.x1 - v.x0);
+    stage(sh, slot(a, gF), v);
+    wmul<false>(wblock(a, v), nc, sh, v.lane, wg);
+    __syncthreads();
+    const double* h = slot(a, pH);
+    double* pf = slot(a, pF);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int c = v.lane + 64 * t;
+      if (c < nc) pf[v.x0 + c] = fma(0.5 * e, wg[t], h[v.x0 + c]);
+    }
+  }
   const double* q = slot(a, qF);
   const double* p = slot(a, pF);
   double pp = 0.0;
@@ -200,11 +292,12 @@ __global__ __launch_bounds__(256) void nuts_leaf_kernel(NutsArgs a, int j, int n
       a.active[v.i] = 0;
     }
   }
-  if (!turn && n < (1 << j) - 1) drift(a, v, a.eps * (double)a.dir[v.i]);
+  if (!turn && n < (1 << j) - 1) drift(a, v, e, sh, wg);
 }
 
 // End of the doubling at depth j: merge the (valid) subtree into the trajectory.
-__global__ __launch_bounds__(256) void nuts_merge_kernel(NutsArgs a, int j) {
+__global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
+  __shared__ double sh[kNutsMetricMax];
   const View v = view_of(a);
   if (!v.ok || !a.active[v.i]) return;
   NutsState& s = a.state[v.i];
@@ -252,10 +345,10 @@ __global__ __launch_bounds__(256) void nuts_merge_kernel(NutsArgs a, int j) {
     slot(a, gF)[x] = slot(a, e1 + 2)[x];
     slot(a, rhoS)[x] = 0.0;
   }
-  drift(a, v, a.eps * (double)dn);
+  drift(a, v, a.eps * (double)dn, sh);
 }
 
-__global__ __launch_bounds__(256) void nuts_finalize_kernel(NutsArgs a) {
+__global__ __launch_bounds__(64) void nuts_finalize_kernel(NutsArgs a) {
   const View v = view_of(a);
   if (!v.ok) {
     if (v.i < a.N && v.lane == 0) {
@@ -278,24 +371,24 @@ __global__ __launch_bounds__(256) void nuts_finalize_kernel(NutsArgs a) {
   }
 }
 
-dim3 grid_of(int64_t N) { return dim3((unsigned)((N + 3) / 4)); }
+dim3 grid_of(int64_t N) { return dim3((unsigned)N); }  // one wave-sized workgroup per particle
 
 }  // namespace
 
 hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_init_kernel, grid_of(a.N), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(nuts_init_kernel, grid_of(a.N), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_leaf_kernel, grid_of(a.N), dim3(256), 0, st, a, j, n);
+  hipLaunchKernelGGL(nuts_leaf_kernel, grid_of(a.N), dim3(64), 0, st, a, j, n);
   return hipGetLastError();
 }
 hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_merge_kernel, grid_of(a.N), dim3(256), 0, st, a, j);
+  hipLaunchKernelGGL(nuts_merge_kernel, grid_of(a.N), dim3(64), 0, st, a, j);
   return hipGetLastError();
 }
 hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_finalize_kernel, grid_of(a.N), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(nuts_finalize_kernel, grid_of(a.N), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 

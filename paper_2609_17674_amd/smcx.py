@@ -62,6 +62,9 @@ def load_library():
                                  P, I32, P],
         "smcx_next_beta": [P, I64, P, P, D, D, P, P, P, P, P],
         "smcx_gauss_newton_metric": [P, I64, P, I64, P, P, P, I64, P, P],
+        "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, P, P],
+        "smcx_nuts_transition_metric": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, I64, P,
+                                        P, P, P, P, P, P, I32, P],
         "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
         "smcx_rj_apply": [P, I64, P, I64, P, P, P, P, P, P, P, I32, I32, D, I64, P, P, P, P],
     }
@@ -338,9 +341,11 @@ def nuts_reserve(prob: Problem, max_depth: int) -> None:
 
 def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q, logl, grad,
                     momentum, dirs, u_leaf, u_tree, prior_lo=None, prior_hi=None, use_graph=True,
-                    mask=None, stream=None):
+                    mask=None, metric=None, stream=None):
     """One batched NUTS transition, in place on (q, logl, grad); particles with
-    mask[i] == 0 (uint8 [N], optional) are left as they are.
+    mask[i] == 0 (uint8 [N], optional) are left as they are. metric = (w_offsets,
+    W), for example from metric_factor, selects the mass matrix (W^T W)^{-1}
+    (smcx_nuts_transition_metric); momentum is then the whitened draw.
 
     Returns (depth, steps, status) int32 tensors [N]."""
     offsets, N, q, beta = _pop(prob, offsets, q, beta)
@@ -358,6 +363,16 @@ def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q,
     depth = torch.empty(N, dtype=torch.int32, device=q.device)
     steps = torch.empty_like(depth)
     status = torch.empty_like(depth)
+    if metric is not None:
+        w_off = _dev(metric[0], torch.int64, "w_offsets", (N + 1,))
+        W = _dev(metric[1], torch.float64, "W")
+        _check(load_library().smcx_nuts_transition_metric(
+            prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta), float(eps), int(max_depth),
+            _ptr(prior_lo), _ptr(prior_hi), _ptr(momentum), _ptr(dirs), _ptr(u_leaf),
+            _ptr(u_tree), _ptr(mask), _ptr(w_off), W.numel(), _ptr(W), _ptr(q), _ptr(logl),
+            _ptr(grad), _ptr(depth), _ptr(steps), _ptr(status), 1 if use_graph else 0,
+            _stream(stream)))
+        return depth, steps, status
     _check(load_library().smcx_nuts_transition(
         prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta), float(eps), int(max_depth),
         _ptr(prior_lo), _ptr(prior_hi), _ptr(momentum), _ptr(dirs), _ptr(u_leaf), _ptr(u_tree),
@@ -480,3 +495,27 @@ class LogLGrad(torch.autograd.Function):
         counts = offsets[1:] - offsets[:-1]
         rows = torch.repeat_interleave(g_logl.contiguous(), counts, output_size=grad.shape[0])
         return grad * rows.unsqueeze(1), None, None, None
+
+
+def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None, stream=None):
+    """Factor W = L^{-1} of F + diag(ridge) for every particle (smcx_metric_factor):
+    ridge is a sequence of P values >= 0; out may be F itself (in place).
+    Returns W with the blocks of f_offsets (zeros above each diagonal)."""
+    offsets = _dev(offsets, torch.int64, "offsets")
+    N = offsets.numel() - 1
+    f_offsets = _dev(f_offsets, torch.int64, "f_offsets", (N + 1,))
+    F = _dev(F, torch.float64, "F")
+    if out is None:
+        out = torch.empty_like(F)
+    out = _dev(out, torch.float64, "W")
+    r = [float(x) for x in ridge]
+    if len(r) != prob.P:
+        raise ValueError(f"ridge needs {prob.P} values")
+    rarr = (ctypes.c_double * prob.P)(*r)
+    if M is None:
+        M = int(offsets[-1]) if N > 0 else 0
+    _check(load_library().smcx_metric_factor(prob.handle, N, _ptr(offsets), int(M), _ptr(f_offsets),
+                                             min(F.numel(), out.numel()), _ptr(F),
+                                             ctypes.cast(rarr, ctypes.c_void_p), _ptr(out),
+                                             _stream(stream)))
+    return out

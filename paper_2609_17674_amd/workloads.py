@@ -218,3 +218,42 @@ def nuts_draws(N: int, M: int, P: int, max_depth: int, seed: int):
     u_leaf = rng.random((N, (1 << max_depth) - 1))
     u_tree = rng.random((N, max_depth))
     return momentum, dirs, u_leaf, u_tree
+
+
+def spd_blocks(sizes, seed: int, spread: float = 4.0):
+    """Random symmetric positive-definite matrices, one per size n: C = A A^T / n
+    + I/2 (A standard normal) with rows and columns scaled by 10^U[-spread,
+    spread], so that the diagonal spans many orders of magnitude as a raw-unit
+    metric does."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        n = int(n)
+        a = rng.standard_normal((n, n))
+        c = a @ a.T / max(n, 1) + 0.5 * np.eye(n)
+        s = 10.0 ** rng.uniform(-spread, spread, n)
+        out.append(c * np.outer(s, s))
+    return out
+
+
+def whitening_draws(K, scales, seed: int, mix: float = 0.3):
+    """Random mass-matrix factors W = (I + R) diag(s) per particle: R strictly
+    lower triangular with N(0, mix^2 / n) entries and s the per-parameter
+    scales repeated over the particle's K components, so that the drift W^T r
+    of a standard-normal r moves coordinate c by about s_c."""
+    rng = np.random.default_rng(seed)
+    scales = np.asarray(scales, dtype=np.float64)
+    out = []
+    for k in K:
+        n = int(k) * scales.size
+        r = np.tril(rng.standard_normal((n, n)), -1) * (mix / np.sqrt(max(n, 1)))
+        out.append((np.eye(n) + r) * np.tile(scales, int(k))[None, :])
+    return out
+
+
+def pack_blocks(blocks):
+    """Concatenate square blocks row-major; returns (block offsets, packed array)."""
+    fo = np.zeros(len(blocks) + 1, dtype=np.int64)
+    np.cumsum([b.size for b in blocks], out=fo[1:])
+    packed = np.concatenate([np.ravel(b) for b in blocks]) if fo[-1] else np.zeros(0)
+    return fo, np.ascontiguousarray(packed, dtype=np.float64)

@@ -61,6 +61,12 @@ def test_null_handle_rejected_before_launch(smcx):
     rc = lib.smcx_rj_apply(None, 4, None, 0, None, None, None, None, None, None, None, 1, 5, 0.0, 0,
                            None, None, None, None)
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_metric_factor(None, 4, None, 0, None, 0, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_nuts_transition_metric(None, 4, None, 0, None, 0.1, 2, None, None, None, None,
+                                         None, None, None, None, 0, None, None, None, None, None,
+                                         None, None, 0, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
 
 
 def test_create_argument_checks(smcx):

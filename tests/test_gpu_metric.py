@@ -92,7 +92,30 @@ def test_metric_checks_its_output_blocks(lib, orc):
     torch.cuda.synchronize()
     with pytest.raises(lib.SmcxError):
         prob.device_status()
-    # the split is refused
-    prob.set_bridge_split(100)
-    with pytest.raises(lib.SmcxError, match="prior bridge"):
-        lib.gauss_newton_metric(prob, off, th)
+
+
+@pytest.mark.parametrize("model,cfg,T,split", [(PULSE, "pulse_batch", 9000, 5000),
+                                               (PULSE, "pulse_batch", 3000, 3000),
+                                               (GB, "gb_grad", 5000, 1234)],
+                         ids=["pulse_mid", "pulse_at_T", "gb"])
+def test_metric_of_the_bridge_target(lib, orc, model, cfg, T, split):
+    """With a bridge split the metric weights samples before it by 1 and later
+    ones by beta (the windows stop at the split)."""
+    w = wl.make_config(cfg, N=40, T=T, k_hi=8, seed=82)
+    beta = np.random.default_rng(83).random(w.N)
+    say("metric_split", model, T, split)
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       w.M)
+    prob.set_bridge_split(split)
+    fo, F = lib.gauss_newton_metric(prob, pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(beta))
+    torch.cuda.synchronize()
+    prob.device_status()
+    fo, F = fo.cpu().numpy(), F.cpu().numpy()
+    ref = orc.fisher(w.model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta, split=split)
+    for i in range(w.N):
+        n = int(w.offsets[i + 1] - w.offsets[i]) * w.P
+        if n == 0:
+            continue
+        got = F[fo[i]:fo[i + 1]].reshape(n, n)
+        d = np.sqrt(np.diag(ref[i]))
+        assert np.all(np.abs(got - ref[i]) <= TOL * np.outer(d, d) + 1e-300), i
