@@ -17,8 +17,10 @@ Other workloads (--workload):
                 on the new samples plus weights, ESS and evidence increment
   pulse_mutate  one NUTS transition of every particle (hipGraph-replayed
                 leapfrog sweeps) plus the birth/death log-likelihood changes
-  smc_pulses    whole SMC runs (prior-start, timed per run; then one
-                posterior-start run) on a 10-pulse problem at N = 6000
+  smc_pulses    whole SMC runs with NUTS on the Gauss-Newton mass matrix
+                (prior-start, timed per run; then one posterior-start run, and
+                one identity-metric run for comparison) on a 10-pulse problem
+                at N = 6000
   metric        Gauss-Newton metric of the headline population (matrix cores)
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
@@ -311,9 +313,11 @@ def bench_mutate(args, w, dev, smcx, np, torch):
 def bench_smc(args, w, dev, smcx, np, torch):
     """Whole SMC runs on the pulse problem at the paper's pulse settings
     (Sec. "Sequence of gaussian pulses": N = 6000, K in [1, 10], alpha = 0.9,
-    p_NUTS / p_birth / p_death = 0.6 / 0.2 / 0.2): a timed prior-start run on
-    all samples, then a posterior-start run from a population sampled on the
-    first half (that preparatory run is not timed)."""
+    p_NUTS / p_birth / p_death = 0.6 / 0.2 / 0.2) with NUTS on the Gauss-Newton
+    mass matrix (Sec. "No-U-Turn-Sampler"): timed prior-start runs on all
+    samples, then a posterior-start run from a population sampled on the first
+    half (that preparatory run is not timed). One prior-start run with the
+    identity mass matrix is reported beside them."""
     from paper_2609_17674_amd import smc
     from paper_2609_17674_amd import workloads as wl
     d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, torch.tensor(w.inj, device=dev),
@@ -325,31 +329,36 @@ def bench_smc(args, w, dev, smcx, np, torch):
     for kind in (smcx.KIND_GRAD, smcx.KIND_LOGL):
         prob.set_tiling(kind, 32, 4096, 1)
     prob.set_tiling(smcx.KIND_DELTA, 16, 4096, 1)
-    runs = []
-    for r in range(args.warmup + args.steps):
-        cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=100 + r)
+
+    def timed(fn):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = smc.run_prior_start(prob, lo, hi, cfg)
+        res = fn()
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
+        return res, time.perf_counter() - t0
+
+    runs = []
+    for r in range(args.warmup + args.steps):
+        cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=100 + r, metric=True)
+        res, t = timed(lambda: smc.run_prior_start(prob, lo, hi, cfg))
         log(f"[bench] prior-start run {r}: {res.iterations} iterations, {t:.2f} s, "
-            f"K histogram {res.k_hist[-1]}")
+            f"K histogram {res.k_hist[-1]}, log Z {res.log_evidence:.2f}")
         if r >= args.warmup:
             runs.append((t, res))
     ms = 1e3 * sum(t for t, _ in runs) / len(runs)
     iters = [res.iterations for _, res in runs]
     grads = sum(sum(res.nuts_steps) for _, res in runs)
+    ident, t_ident = timed(lambda: smc.run_prior_start(
+        prob, lo, hi, smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=100)))
+    log(f"[bench] identity-metric prior-start: {ident.iterations} iterations, {t_ident:.2f} s, "
+        f"K histogram {ident.k_hist[-1]}, log Z {ident.log_evidence:.2f}")
     half = w.T // 2
     p1 = smcx.Problem(w.model, d[:half].contiguous(), w.t_start, w.dt, w.sigma, k_hi, N, N * k_hi)
     first = smc.run_prior_start(p1, lo, hi, smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300,
-                                                           seed=7))
-    cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=8, eps=lambda beta: 3e-4)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    post = smc.run_posterior_start(prob, half, first.offsets, first.theta, lo, hi, cfg)
-    torch.cuda.synchronize()
-    t_post = time.perf_counter() - t0
+                                                           seed=7, metric=True))
+    cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=300, seed=8, metric=True)
+    post, t_post = timed(lambda: smc.run_posterior_start(prob, half, first.offsets, first.theta,
+                                                         lo, hi, cfg))
     log(f"[bench] posterior-start: {post.iterations} iterations, {t_post:.2f} s")
     value = N * sum(iters) / (sum(t for t, _ in runs))
     return dict(metric="particle-iterations/sec of whole prior-start SMC runs (pulse problem)",
@@ -357,9 +366,15 @@ def bench_smc(args, w, dev, smcx, np, torch):
                 config={"workload": "smc_pulses", "T": w.T, "N": N, "n_injected": len(w.inj),
                         "K_range": [1, k_hi], "alpha": 0.9, "p_moves": [0.6, 0.2, 0.2],
                         "n_mutations": 4, "nuts_max_depth": 6,
+                        "nuts_mass_matrix": "Gauss-Newton metric + prior precision, eps 0.3 whitened",
                         "prior_start": {"iterations": iters, "seconds": [round(t, 3) for t, _ in runs],
                                         "final_K_hist": runs[-1][1].k_hist[-1],
+                                        "log_evidence": [round(r.log_evidence, 2) for _, r in runs],
                                         "leapfrog_grads_per_s": grads / sum(t for t, _ in runs)},
+                        "prior_start_identity_metric": {
+                            "iterations": ident.iterations, "seconds": round(t_ident, 3),
+                            "final_K_hist": ident.k_hist[-1],
+                            "log_evidence": round(ident.log_evidence, 2)},
                         "posterior_start": {"split": half, "iterations": post.iterations,
                                             "seconds": round(t_post, 3),
                                             "final_K_hist": post.k_hist[-1]}})

@@ -13,6 +13,15 @@ component uniform in the prior box) at beta = 0 and repeats until beta = 1:
    component, scored by ``delta_logl_birth_death`` and accepted or rejected
    by ``smcx_rj_apply``.
 
+With ``metric=True`` the NUTS moves use the mass matrix of Sec.
+"No-U-Turn-Sampler" (the Hessian of the negative log posterior): before each
+mutation step the Gauss-Newton metric of the tempered target is computed at
+every particle's current position (``smcx_gauss_newton_metric``), the prior's
+precision 12 / width^2 is added to its diagonal as a floor
+(``smcx_metric_factor``), and the transition runs in the whitened momentum
+(``smcx_nuts_transition_metric``) with the step ``eps_metric``, which is
+then in units of the target's own scale.
+
 The posterior-start mode (``run_posterior_start``) starts instead from a
 population sampled on the first `split` samples of the data and follows the
 bridge of eq. reuse_bridge: the problem's bridge split makes every tempered
@@ -28,7 +37,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import Callable, Optional
+from typing import Callable, Optional, Sequence
 
 import torch
 
@@ -51,6 +60,9 @@ class SMCConfig:
     eps: Callable[[float], float] = field(default=lambda beta: 3e-4 / math.sqrt(max(beta, 1e-4)))
     max_iters: int = 200
     seed: int = 0
+    metric: bool = False               # NUTS with the Gauss-Newton mass matrix
+    eps_metric: float = 0.3            # its step size (whitened units)
+    ridge: Optional[Sequence[float]] = None  # diagonal floor per parameter; None: 12 / width^2
 
 
 @dataclass
@@ -117,6 +129,8 @@ def _check(prob: smcx.Problem, cfg: SMCConfig) -> None:
         raise ValueError("the problem handle is too small for this SMC configuration")
     if abs(cfg.p_nuts + cfg.p_birth + cfg.p_death - 1.0) > 1e-12:
         raise ValueError("mixture weights must sum to 1")
+    if cfg.metric and cfg.k_hi * prob.P > 128:
+        raise ValueError("the NUTS metric needs k_hi * P <= 128")
 
 
 def _generator(dev, seed: int) -> torch.Generator:
@@ -142,6 +156,10 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
     f64 = dict(dtype=torch.float64, device=dev)
     M = int(off[-1])
     log_ratio = math.log(cfg.p_death / cfg.p_birth)
+    if cfg.metric:
+        ridge = (list(cfg.ridge) if cfg.ridge is not None
+                 else (12.0 / (hi - lo) ** 2).cpu().tolist())
+        fbuf = torch.empty(1, **f64)
     beta = 0.0
     res = SMCResult(off, th, [], [], 0.0, [], [], [])
     for it in range(cfg.max_iters):
@@ -156,7 +174,7 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
         M = int(off[-1])
         th = th_all[:M]
         acc_rj = tried_rj = steps = 0
-        eps = float(cfg.eps(beta))
+        eps = cfg.eps_metric if cfg.metric else float(cfg.eps(beta))
         for _ in range(cfg.n_mutations):
             r = torch.rand(N, generator=gen, **f64)
             nuts = r < cfg.p_nuts
@@ -167,8 +185,18 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                 dirs = (torch.randint(0, 2, (N, D), generator=gen, device=dev) * 2 - 1).to(torch.int8)
                 ul = torch.rand((N, (1 << D) - 1), generator=gen, **f64)
                 ut = torch.rand((N, D), generator=gen, **f64)
+                metric = None
+                if cfg.metric:
+                    fo = smcx.metric_offsets(prob, off)
+                    size = max(int(fo[-1]), 1)
+                    if fbuf.numel() < size:
+                        fbuf = torch.empty(size + size // 4, **f64)
+                    _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
+                                                    out=fbuf[:size])
+                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
-                                                ul, ut, lo, hi, mask=nuts.to(torch.uint8))
+                                                ul, ut, lo, hi, mask=nuts.to(torch.uint8),
+                                                metric=metric)
                 steps += int(st.sum())
             Kc = off[1:] - off[:-1]
             tb = _prior_rows(prob, lo, hi, N, gen)
