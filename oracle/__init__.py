@@ -38,6 +38,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smcx_oracle.c")
+_SRC_GB = os.path.join(_HERE, "gblisa_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PULSE = 0
@@ -46,10 +47,11 @@ GBSINE = 1
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_GB))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, _SRC_GB, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -96,6 +98,18 @@ def _load():
         lib.oracle_nuts_transition_metric.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P,
                                                       P, P, P, P, I64, P, P, P, P, P, P, P, P]
         lib.oracle_metric_factor.argtypes = [I, I64, P, P, P, P, P, P]
+        lib.oracle_gblisa_tensors.argtypes = [D, P, P]
+        lib.oracle_gblisa_tensors.restype = None
+        lib.oracle_gblisa_positions.argtypes = [D, P]
+        lib.oracle_gblisa_positions.restype = None
+        lib.oracle_gblisa_response.argtypes = [D, D, D, D, P, P]
+        lib.oracle_gblisa_response.restype = None
+        lib.oracle_gblisa_strain.argtypes = [P, D, P]
+        lib.oracle_gblisa_strain.restype = None
+        lib.oracle_gblisa_spectrum.argtypes = [I64, P, D, I, I64, I64, P]
+        lib.oracle_gblisa_spectrum_dft.argtypes = [I64, P, D, I64, I64, I64, P]
+        lib.oracle_gblisa_logl_grad.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P]
+        lib.oracle_gblisa_delta.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -400,3 +414,87 @@ def nuts_transition_metric(model, d, t_start, dt, sigma, offsets, beta, eps, max
         _p(wo), _p(W), _p(q), _p(logl), _p(grad), _p(depth), _p(steps), _p(status)),
         "nuts_transition_metric")
     return q, logl, grad, depth, steps, status
+
+
+# ---------------------------------------------------------------- LISA GB model
+GB_P = 8
+GB_NS = 64  # envelope samples of the fast/slow template
+
+
+def gblisa_tensors(t):
+    """Detector tensors (3x3) of the A and E channels at time t."""
+    DA, DE = np.empty(9), np.empty(9)
+    _load().oracle_gblisa_tensors(float(t), _p(DA), _p(DE))
+    return DA.reshape(3, 3), DE.reshape(3, 3)
+
+
+def gblisa_positions(t):
+    x = np.empty(9)
+    _load().oracle_gblisa_positions(float(t), _p(x))
+    return x.reshape(3, 3)
+
+
+def gblisa_response(t, beta, lam, psi):
+    """(F+, Fx) of the A and E channels: two arrays of 2."""
+    Fp, Fx = np.empty(2), np.empty(2)
+    _load().oracle_gblisa_response(float(t), float(beta), float(lam), float(psi), _p(Fp), _p(Fx))
+    return Fp, Fx
+
+
+def gblisa_strain(theta, t):
+    """Time-domain strain (A, E) of one source at time t."""
+    th, h = _f64(theta), np.empty(2)
+    _load().oracle_gblisa_strain(_p(th), float(t), _p(h))
+    return h
+
+
+def gblisa_spectrum(theta, T_obs, k0, B, Ns=GB_NS):
+    """Band spectrum [2, B] (complex) of K sources, fast/slow decomposition."""
+    th = _f64(theta).reshape(-1, GB_P)
+    out = np.empty((2, B, 2))
+    _check(_load().oracle_gblisa_spectrum(th.shape[0], _p(th), float(T_obs), int(Ns), int(k0), int(B),
+                                          _p(out)), "gblisa_spectrum")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def gblisa_spectrum_dft(theta, T_obs, Nt, k0, B):
+    """Band spectrum [2, B] from the plain DFT of the strain sampled at Nt points."""
+    th = _f64(theta).reshape(-1, GB_P)
+    out = np.empty((2, B, 2))
+    _check(_load().oracle_gblisa_spectrum_dft(th.shape[0], _p(th), float(T_obs), int(Nt), int(k0),
+                                              int(B), _p(out)), "gblisa_spectrum_dft")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def _fd_data(d):
+    d = np.asarray(d)
+    if np.iscomplexobj(d):
+        d = np.stack([d.real, d.imag], axis=-1)
+    return np.ascontiguousarray(d, dtype=np.float64)
+
+
+def gblisa_logl_grad(d, k0, T_obs, S, offsets, theta, beta=None, grad=True, Ns=GB_NS):
+    """Tempered logL [N] (and gradient [M, 8]) of every particle; d is [2, B] complex."""
+    d = _fd_data(d)
+    B = d.shape[1]
+    offsets, theta, beta = _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    logl = np.empty(N)
+    g = np.zeros((max(int(offsets[-1]), 0), GB_P)) if grad else None
+    _check(_load().oracle_gblisa_logl_grad(_p(d), int(k0), B, float(T_obs), float(S), int(Ns), N,
+                                           _p(offsets), _p(theta), _p(beta), _p(logl), _p(g)),
+           "gblisa_logl_grad")
+    return (logl, g) if grad else logl
+
+
+def gblisa_delta(d, k0, T_obs, S, offsets, theta, beta, theta_birth, death_idx, Ns=GB_NS):
+    d = _fd_data(d)
+    B = d.shape[1]
+    offsets, theta, beta, tb = _i64(offsets), _f64(theta), _f64(beta), _f64(theta_birth)
+    di = np.ascontiguousarray(death_idx, dtype=np.int32)
+    N = offsets.shape[0] - 1
+    db, dd = np.empty(N), np.empty(N)
+    _check(_load().oracle_gblisa_delta(_p(d), int(k0), B, float(T_obs), float(S), int(Ns), N,
+                                       _p(offsets), _p(theta), _p(beta), _p(tb), _p(di), _p(db),
+                                       _p(dd)), "gblisa_delta")
+    return db, dd

@@ -39,8 +39,9 @@ import numpy as np
 
 PULSE = 0
 GBSINE = 1
+GBLISA = 2
 
-N_PARAMS = {PULSE: 3, GBSINE: 4}
+N_PARAMS = {PULSE: 3, GBSINE: 4, GBLISA: 8}
 
 # Uniform prior boxes, one row per parameter: (low, high).
 PULSE_PRIOR = np.array([[2.0, 6.0],      # amplitude A
@@ -51,6 +52,26 @@ GB_PRIOR = np.array([[-22.0, -21.0],     # log10 A (before the 1e21 rescale)
                      [1e-18, 1e-16],     # fdot [Hz/s]
                      [0.0, 2.0 * np.pi]])   # phi0 [rad]
 GB_RESCALE_LOG10 = 21.0
+
+# LISA Galactic binaries in the frequency domain (Sec. "LISA Galactic
+# binaries"): theta = (f0, fdot, log10 A, latitude, longitude, psi, iota,
+# phi0), one year of data, channels A and E over a band of bins
+# [GBLISA_K0, GBLISA_K0 + GBLISA_B) with a constant PSD. The PSD puts the
+# injections' optimal SNR in 10..40 for log10 A in [-21.6, -21.0].
+GBLISA_PRIOR = np.array([[0.9997e-3, 1.0007e-3],   # f0 [Hz]
+                         [1e-18, 1e-16],           # fdot [Hz/s]
+                         [-22.0, -20.5],           # log10 A
+                         [-0.5 * np.pi, 0.5 * np.pi],  # ecliptic latitude
+                         [0.0, 2.0 * np.pi],       # ecliptic longitude
+                         [0.0, np.pi],             # polarisation psi
+                         [0.0, np.pi],             # inclination iota
+                         [0.0, 2.0 * np.pi]])      # initial phase phi0
+GBLISA_T_OBS = 31557600.0
+GBLISA_PSD = 3.4e4
+GBLISA_K0 = 31500
+GBLISA_B = 128
+GBLISA_INJ_LOG10A = (-21.6, -21.0)
+GBLISA_INJ_F0 = (0.9998e-3, 1.0006e-3)
 
 CONFIG_NAMES = ("pulse_small", "pulse_batch", "gb_grad", "pulse_mutate", "gb_extend")
 CONFIG_SEEDS = (101, 102, 103, 104, 105)
@@ -257,3 +278,74 @@ def pack_blocks(blocks):
     np.cumsum([b.size for b in blocks], out=fo[1:])
     packed = np.concatenate([np.ravel(b) for b in blocks]) if fo[-1] else np.zeros(0)
     return fo, np.ascontiguousarray(packed, dtype=np.float64)
+
+
+@dataclass
+class GBLisaWorkload:
+    """A seeded LISA Galactic-binary problem: injections, frequency-domain
+    noise of the two channels over the band (zero for the noise-free case
+    of the paper), and a population drawn from the prior."""
+
+    T_obs: float
+    k0: int
+    B: int
+    S: float
+    inj: np.ndarray            # [n_inj, 8]
+    noise: np.ndarray          # [2, B] complex
+    offsets: np.ndarray
+    theta: np.ndarray          # [M, 8]
+    beta: np.ndarray
+    k_max: int
+    extra: dict = field(default_factory=dict)
+
+    model = GBLISA
+    P = 8
+
+    @property
+    def N(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def M(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def K(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+
+def draw_gblisa(n: int, rng: np.random.Generator) -> np.ndarray:
+    lo, hi = GBLISA_PRIOR[:, 0], GBLISA_PRIOR[:, 1]
+    return lo + rng.random((n, 8)) * (hi - lo)
+
+
+def make_gblisa(N: int = 40000, k_lo: int = 1, k_hi: int = 10, n_inj: int = 10,
+                beta: str = "one", noise: bool = False, seed: int = 106) -> GBLisaWorkload:
+    """Injections with f0 on an equally spaced grid over GBLISA_INJ_F0 and the
+    other parameters uniform (log10 A in GBLISA_INJ_LOG10A); white noise of
+    PSD S in each channel when ``noise`` (each bin's real and imaginary parts
+    N(0, S T_obs / 4)); a population of N particles with K ~ U{k_lo..k_hi}
+    drawn from the prior box."""
+    s_inj, s_noise, s_part, s_beta, s_rj, _ = np.random.SeedSequence(seed).spawn(6)
+    r_inj = np.random.default_rng(s_inj)
+    inj = draw_gblisa(n_inj, r_inj)
+    inj[:, 0] = np.linspace(GBLISA_INJ_F0[0], GBLISA_INJ_F0[1], n_inj) if n_inj > 1 else \
+        GBLISA_INJ_F0[0]
+    inj[:, 2] = r_inj.uniform(GBLISA_INJ_LOG10A[0], GBLISA_INJ_LOG10A[1], n_inj)
+    sd = np.sqrt(GBLISA_PSD * GBLISA_T_OBS / 4.0)
+    r_noise = np.random.default_rng(s_noise)
+    nz = (sd * (r_noise.standard_normal((2, GBLISA_B)) + 1j * r_noise.standard_normal((2, GBLISA_B)))
+          if noise else np.zeros((2, GBLISA_B), dtype=complex))
+    r_part = np.random.default_rng(s_part)
+    K = draw_counts(N, k_lo, k_hi, r_part)
+    offsets = counts_to_offsets(K)
+    theta = draw_gblisa(int(offsets[-1]), r_part)
+    r_beta = np.random.default_rng(s_beta)
+    b = {"one": np.ones(N), "half": np.full(N, 0.5), "uniform": r_beta.random(N)}[beta]
+    r_rj = np.random.default_rng(s_rj)
+    extra = {"seed": seed, "theta_birth": draw_gblisa(N, r_rj)}
+    u = r_rj.random(N)
+    extra["death_idx"] = np.where(K > 0, np.minimum(np.floor(u * np.maximum(K, 1)), K - 1),
+                                  -1).astype(np.int32)
+    return GBLisaWorkload(T_obs=GBLISA_T_OBS, k0=GBLISA_K0, B=GBLISA_B, S=GBLISA_PSD, inj=inj,
+                          noise=nz, offsets=offsets, theta=theta, beta=b, k_max=k_hi, extra=extra)

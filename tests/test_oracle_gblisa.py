@@ -1,0 +1,196 @@
+"""Pins of the oracle's LISA Galactic-binary model (Sec. "LISA Galactic
+binaries": eight parameters, channels A and E, frequency-domain likelihood of
+eq. gw_likelihood with a constant PSD).
+
+* Orbits: arm lengths L to first order in the eccentricity, the guiding centre
+  on the 1 AU circle, the constellation plane inclined by 60 degrees.
+* Response: averaged over the sky and the polarisation angle, any traceless
+  detector tensor D gives <(D:e+)^2> = <(D:ex)^2> = (2/5) D:D (exact for a
+  quadrature of the right degree); the A and E tensors have D:D = 9/16 and are
+  orthogonal, to first order in the eccentricity; T = sum of the Michelson
+  tensors vanishes exactly.
+* Spectrum: for a source on a bin centre with fdot = 0 the envelope is
+  periodic over the year, and the fast/slow template equals the plain DFT of
+  the sampled strain (to rounding); off the bin centre it differs by the
+  decomposition's aliasing, which falls as the envelope sampling grows.
+* Likelihood: zero residual at the injections, the K = 0 energy, beta scaling,
+  the birth/death changes against differences of logL and the exact
+  birth-then-death zero, and the gradient against Richardson differences.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_17674_amd import workloads as wl
+
+YEAR = 31557600.0
+AU = 1.495978707e11
+ARM = 2.5e9
+
+
+def test_orbits(orc):
+    for t in np.linspace(0, YEAR, 13):
+        x = orc.gblisa_positions(t)
+        a = 2 * np.pi * t / YEAR
+        c = x.mean(axis=0)
+        assert np.allclose(c, AU * np.array([np.cos(a), np.sin(a), 0.0]), rtol=0, atol=1e-6 * AU * 1e-3)
+        e = ARM / (2 * np.sqrt(3) * AU)
+        for i in range(3):
+            L = np.linalg.norm(x[(i + 1) % 3] - x[i])
+            assert abs(L - ARM) <= 2 * e * ARM
+        nrm = np.cross(x[1] - x[0], x[2] - x[0])
+        tilt = np.degrees(np.arccos(abs(nrm[2]) / np.linalg.norm(nrm)))
+        assert abs(tilt - 60.0) < 1.0
+
+
+def _sky_quadrature(n=12):
+    z, wz = np.polynomial.legendre.leggauss(n)         # z = sin(latitude)
+    lam = 2 * np.pi * np.arange(2 * n) / (2 * n)
+    psi = np.pi * np.arange(2 * n) / (2 * n)
+    return z, wz, lam, psi
+
+
+@pytest.mark.parametrize("t", [0.0, 0.3 * YEAR, 0.77 * YEAR])
+def test_sky_averaged_response(orc, t):
+    DA, DE = orc.gblisa_tensors(t)
+    assert abs(np.trace(DA)) < 1e-14 and abs(np.trace(DE)) < 1e-14
+    assert np.allclose(DA, DA.T, atol=1e-15) and np.allclose(DE, DE.T, atol=1e-15)
+    z, wz, lam, psi = _sky_quadrature()
+    acc = np.zeros((2, 2, 2))  # [pol][c][c']
+    for zi, wi in zip(z, wz):
+        b = np.arcsin(zi)
+        for l in lam:
+            for p in psi:
+                Fp, Fx = orc.gblisa_response(t, b, l, p)
+                w = wi / 2 / len(lam) / len(psi)
+                acc[0] += w * np.outer(Fp, Fp)
+                acc[1] += w * np.outer(Fx, Fx)
+    DD = np.array([[np.sum(DA * DA), np.sum(DA * DE)], [np.sum(DE * DA), np.sum(DE * DE)]])
+    for pol in range(2):
+        assert np.allclose(acc[pol], 0.4 * DD, rtol=0, atol=1e-12)
+    e = ARM / (2 * np.sqrt(3) * AU)
+    assert abs(DD[0, 0] - 9 / 16) < 10 * e and abs(DD[1, 1] - 9 / 16) < 10 * e
+    assert abs(DD[0, 1]) < 10 * e
+
+
+def test_michelson_tensors_sum_to_zero(orc):
+    # T = (X + Y + Z) / sqrt(3) vanishes: A and E span the response, and
+    # A (x) A + E (x) E is invariant under relabelling of the spacecraft
+    for t in (0.1 * YEAR, 0.6 * YEAR):
+        DA, DE = orc.gblisa_tensors(t)
+        x = orc.gblisa_positions(t)
+        M = []
+        for k in range(3):
+            u = (x[(k + 1) % 3] - x[k]) / np.linalg.norm(x[(k + 1) % 3] - x[k])
+            v = (x[(k + 2) % 3] - x[k]) / np.linalg.norm(x[(k + 2) % 3] - x[k])
+            M.append(0.5 * (np.outer(u, u) - np.outer(v, v)))
+        assert np.allclose(M[0] + M[1] + M[2], 0, atol=1e-15)
+        G = np.einsum("ij,kl->ijkl", DA, DA) + np.einsum("ij,kl->ijkl", DE, DE)
+        Gs = sum(np.einsum("ij,kl->ijkl", m, m) for m in M)
+        assert np.allclose(G, Gs, rtol=0, atol=1e-14)
+
+
+def _source(rng, f0, fdot=None):
+    lo, hi = wl.GBLISA_PRIOR[:, 0], wl.GBLISA_PRIOR[:, 1]
+    th = lo + rng.random(8) * (hi - lo)
+    th[0] = f0
+    if fdot is not None:
+        th[1] = fdot
+    return th
+
+
+def test_fast_slow_equals_the_dft_on_bin_centres(orc):
+    rng = np.random.default_rng(300)
+    T = YEAR
+    for q in (31552, 31563, 31577):
+        th = _source(rng, q / T, fdot=0.0)
+        k0, B = q - 60, 128
+        fs = orc.gblisa_spectrum(th, T, k0, B)
+        ex = orc.gblisa_spectrum_dft(th, T, 2 ** 17, k0, B)
+        assert np.linalg.norm(fs - ex) <= 1e-9 * np.linalg.norm(ex)
+    # the same with twice the envelope samples
+    th = _source(rng, 31560 / T, fdot=0.0)
+    fs = orc.gblisa_spectrum(th, T, 31500, 128, Ns=128)
+    ex = orc.gblisa_spectrum_dft(th, T, 2 ** 17, 31500, 128)
+    assert np.linalg.norm(fs - ex) <= 1e-9 * np.linalg.norm(ex)
+
+
+def test_fast_slow_aliasing_falls_with_the_envelope_sampling(orc):
+    rng = np.random.default_rng(301)
+    T = YEAR
+    for f0 in (0.99985e-3, 1.00031e-3):
+        th = _source(rng, f0)
+        ex = orc.gblisa_spectrum_dft(th, T, 2 ** 17, 31480, 160)
+        errs = [np.linalg.norm(orc.gblisa_spectrum(th, T, 31480, 160, Ns=n) - ex) / np.linalg.norm(ex)
+                for n in (64, 128, 256)]
+        assert errs[0] < 0.3 and errs[1] < errs[0] and errs[2] < errs[1], errs
+
+
+def test_likelihood_invariants(orc):
+    rng = np.random.default_rng(302)
+    T, S, k0, B = YEAR, wl.GBLISA_PSD, wl.GBLISA_K0, wl.GBLISA_B
+    inj = np.array([_source(rng, f) for f in (0.9999e-3, 1.0002e-3, 1.0004e-3)])
+    inj[:, 2] = -21.2
+    d = orc.gblisa_spectrum(inj, T, k0, B)
+    off = np.array([0, 3, 3, 5])
+    th = np.concatenate([inj, inj[:2] + 1e-9 * np.array([1, 0, 0, 0, 0, 0, 0, 0])])
+    beta = np.array([0.7, 0.3, 1.0])
+    l = orc.gblisa_logl_grad(d, k0, T, S, off, th, beta, grad=False)
+    e = np.sum(np.abs(d) ** 2)
+    # zero residual at the injections (the sources are subtracted in another
+    # order than they were summed, so up to rounding of the spectrum)
+    assert abs(l[0]) <= 1e-25 * 4 / (T * S) * e
+    assert np.isclose(l[1], -0.3 * 0.5 * 4 / (T * S) * e, rtol=1e-13, atol=0)
+    l1 = orc.gblisa_logl_grad(d, k0, T, S, off, th, np.ones(3), grad=False)
+    assert np.allclose(l, beta * l1, rtol=1e-15, atol=0)
+    # birth then death of the appended component is exactly zero; both
+    # changes equal differences of logL
+    tb = np.array([_source(rng, 1.0001e-3) for _ in range(3)])
+    di = np.array([1, -1, 0], dtype=np.int32)
+    db, dd = orc.gblisa_delta(d, k0, T, S, off, th, beta, tb, di)
+    for i in range(3):
+        a, b_ = off[i], off[i + 1]
+        cur = orc.gblisa_logl_grad(d, k0, T, S, [0, b_ - a], th[a:b_], beta[i:i + 1], grad=False)[0]
+        plus = orc.gblisa_logl_grad(d, k0, T, S, [0, b_ - a + 1], np.vstack([th[a:b_], tb[i]]),
+                                    beta[i:i + 1], grad=False)[0]
+        assert np.isclose(db[i], plus - cur, rtol=1e-9, atol=1e-9 * abs(cur))
+        if di[i] >= 0:
+            rest = np.delete(th[a:b_], di[i], axis=0)
+            minus = orc.gblisa_logl_grad(d, k0, T, S, [0, b_ - a - 1], rest, beta[i:i + 1],
+                                         grad=False)[0]
+            assert np.isclose(dd[i], minus - cur, rtol=1e-9, atol=1e-9 * abs(cur))
+        else:
+            assert dd[i] == 0.0
+        # death of the newborn (last) component undoes the birth
+        grown = np.vstack([th[a:b_], tb[i]])
+        _, back = orc.gblisa_delta(d, k0, T, S, [0, b_ - a + 1], grown, beta[i:i + 1],
+                                   tb[i:i + 1], np.array([b_ - a], dtype=np.int32))
+        assert np.isclose(db[i] + back[0], 0.0, rtol=0, atol=1e-9 * abs(db[i]) + 1e-12)
+
+
+NAT = np.array([1 / YEAR, 1 / YEAR ** 2, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+
+
+def test_gradient_against_richardson_differences(orc):
+    rng = np.random.default_rng(303)
+    T, S, k0, B = YEAR, wl.GBLISA_PSD, wl.GBLISA_K0, wl.GBLISA_B
+    inj = np.array([_source(rng, f) for f in (0.99991e-3, 1.00023e-3)])
+    d = orc.gblisa_spectrum(inj, T, k0, B)
+    th = inj.copy()
+    th[:, 0] += np.array([0.21, -0.17]) / T        # within the same carrier bins
+    th[:, 2:] += rng.normal(0, 0.05, (2, 6))
+    off = np.array([0, 2])
+    beta = np.array([0.8])
+    l, g = orc.gblisa_logl_grad(d, k0, T, S, off, th, beta)
+    gn = g.reshape(-1) * np.tile(NAT, 2)
+    num = np.zeros(16)
+    for j in range(16):
+        h = 1e-4 * np.tile(NAT, 2)[j]
+
+        def f(x):
+            t2 = th.copy().reshape(-1)
+            t2[j] += x
+            return orc.gblisa_logl_grad(d, k0, T, S, off, t2.reshape(2, 8), beta, grad=False)[0]
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        num[j] = (4 * d2 - d1) / 3 * np.tile(NAT, 2)[j]
+    assert np.linalg.norm(gn - num) <= 1e-6 * np.linalg.norm(num), (gn, num)
