@@ -26,6 +26,21 @@
  *               (single-channel time-domain stand-in for the Galactic
  *               binaries of Sec. "LISA Galactic binaries"; A' is the
  *               amplitude after rescaling the data by 1e21).
+ *   SMCX_GBLISA (P=8, theta = f0 [Hz], fdot [Hz/s], log10 A, ecliptic
+ *               latitude, ecliptic longitude, psi, iota, phi0 [rad]): the
+ *               Galactic binaries of Sec. "LISA Galactic binaries" in the
+ *               frequency domain (smcx_problem_create_fd): channels A and E
+ *               of the constellation in its long-wavelength limit, and
+ *                 logL = -(1/2) (4 / (T_obs S)) sum_c sum_k |d_c[k] - h_c[k]|^2
+ *               over the bins of a band (eq. gw_likelihood with a constant
+ *               PSD S). Templates by the fast/slow decomposition: the
+ *               heterodyned envelope at 64 points over the record, its
+ *               64-point DFT filling bins floor(f0 T_obs) - 32 .. + 31.
+ *               Amplitudes in units of 1e-21 strain (A = 10^(log10 A + 21)).
+ *               Supported: logl_batch, logl_grad_batch, delta_logl_birth_death,
+ *               smcx_leapfrog, smcx_nuts_transition(_metric) and the SMC
+ *               steps; not the time-domain calls (reweight_extend, the
+ *               plain form, tiling, the bridge split, the metric).
  *
  * Layout. The population is CSR: offsets[N+1] (int64, offsets[0] = 0,
  * non-decreasing, K_i = offsets[i+1]-offsets[i]), theta[M][P] (FP64,
@@ -81,7 +96,7 @@ enum {
   SMCX_ECAPTURE = -4  /* call not allowed while the stream is being captured */
 };
 
-enum { SMCX_PULSE = 0, SMCX_GBSINE = 1 };
+enum { SMCX_PULSE = 0, SMCX_GBSINE = 1, SMCX_GBLISA = 2 };
 
 /* Create a problem handle for one data vector.
  *   model      SMCX_PULSE or SMCX_GBSINE
@@ -100,6 +115,29 @@ enum { SMCX_PULSE = 0, SMCX_GBSINE = 1 };
 int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_start, double dt,
                         double sigma, int32_t k_max, int64_t n_max, int64_t m_max,
                         void* hip_stream, smcx_problem** out);
+
+/* Create a frequency-domain problem (model SMCX_GBLISA).
+ *   d_dev      [2][B][2] FP64 device data: the A and E spectra (re, im) of
+ *              bins k0 .. k0 + B - 1, in the convention
+ *              d[k] = dt sum_n d(t_n) exp(-2 pi i k n / N_t); copied during
+ *              the call
+ *   k0, B      first bin and number of bins, 1 <= B <= 256
+ *   T_obs      record length [s] (bin spacing 1 / T_obs); envelope samples
+ *              sit at j T_obs / 64 from the start of the record
+ *   psd        constant one-sided PSD S of both channels (> 0)
+ *   k_max, n_max, m_max, hip_stream, out   as smcx_problem_create
+ * Source windows that reach outside the band are cut at its edges. The
+ * handle's calls run in FP64 throughout. Allocates and synchronises. */
+int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B, double T_obs,
+                           double psd, int32_t k_max, int64_t n_max, int64_t m_max,
+                           void* hip_stream, smcx_problem** out);
+
+/* Band spectrum of K sources of the frequency-domain model (for building
+ * data): out [2][B][2] FP64 (device), theta [K][8] (device), as the
+ * templates of a handle with the same T_obs, k0, B. A set-up call: it
+ * allocates a small table, launches one wave and synchronises. */
+int smcx_template_spectrum(int model, int64_t K, const double* theta, double T_obs, int64_t k0,
+                           int64_t B, double* out, void* hip_stream);
 
 /* Free the handle and its workspace (after synchronising its last stream).
  * NULL is accepted. */

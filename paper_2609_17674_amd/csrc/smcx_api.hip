@@ -109,6 +109,8 @@ void free_problem(smcx_problem* p) {
   (void)hipFree(p->nuts_count);
   (void)hipFree(p->d32);
   (void)hipFree(p->d64);
+  (void)hipFree(p->fd_data);
+  (void)hipFree(p->fd_table);
   (void)hipFree(p->order);
   (void)hipFree(p->n_active);
   (void)hipFree(p->prep_hist);
@@ -183,7 +185,67 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
   a.part = p->part;
   a.part_g = p->part_g;
   a.flag = p->flag;
+  if (p->fd) {
+    a.fd_data = p->fd_data;
+    a.fd_table = p->fd_table;
+    a.fd_k0 = p->fd_k0;
+    a.fd_B = p->fd_B;
+    a.fd_T_obs = p->fd_T_obs;
+    a.fd_scale = p->fd_T_obs / 64.0;
+  }
   return a;
+}
+
+// Coarse-grid constants of the frequency-domain model for observation time
+// T_obs: per envelope sample t_j = j T_obs / 64 the symmetric detector tensors
+// of the A and E channels, cos and sin of the orbital phase, t_j; then the 64
+// roots exp(-2 pi i k / 64). The constellation follows the first-order
+// circular-orbit solution (guiding centre on the 1 AU circle, arms of length L
+// in a plane inclined by 60 degrees to the ecliptic); the Michelson tensor
+// with vertex k is (u u - v v) / 2 for the unit vectors towards spacecraft
+// k+1 and k+2, A = (M_2 - M_0) / sqrt(2), E = (M_0 - 2 M_1 + M_2) / sqrt(6).
+void fd_table_host(double T_obs, std::vector<double>& tab) {
+  const double kPi = 3.14159265358979323846, R = 1.495978707e11, L = 2.5e9, year = 31557600.0;
+  const double ecc = L / (2.0 * std::sqrt(3.0) * R);
+  tab.assign(smcx::kFdTableSize, 0.0);
+  for (int j = 0; j < 64; ++j) {
+    const double t = j * T_obs / 64.0, a = 2.0 * kPi * t / year;
+    double x[3][3];
+    for (int k = 0; k < 3; ++k) {
+      const double b = 2.0 * kPi * k / 3.0;
+      x[k][0] = R * std::cos(a) + 0.5 * ecc * R * (std::cos(2.0 * a - b) - 3.0 * std::cos(b));
+      x[k][1] = R * std::sin(a) + 0.5 * ecc * R * (std::sin(2.0 * a - b) - 3.0 * std::sin(b));
+      x[k][2] = -std::sqrt(3.0) * ecc * R * std::cos(a - b);
+    }
+    double M[3][3][3];
+    for (int k = 0; k < 3; ++k) {
+      double u[3], v[3], nu = 0.0, nv = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        u[c] = x[(k + 1) % 3][c] - x[k][c];
+        v[c] = x[(k + 2) % 3][c] - x[k][c];
+        nu += u[c] * u[c];
+        nv += v[c] * v[c];
+      }
+      nu = std::sqrt(nu);
+      nv = std::sqrt(nv);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[k][r][c] = 0.5 * (u[r] * u[c] / (nu * nu) - v[r] * v[c] / (nv * nv));
+    }
+    static const int ri[6] = {0, 1, 2, 0, 0, 1}, ci[6] = {0, 1, 2, 1, 2, 2};
+    double* row = tab.data() + j * smcx::kFdTableStride;
+    for (int e = 0; e < 6; ++e) {
+      const int r = ri[e], c = ci[e];
+      row[e] = (M[2][r][c] - M[0][r][c]) / std::sqrt(2.0);
+      row[6 + e] = (M[0][r][c] - 2.0 * M[1][r][c] + M[2][r][c]) / std::sqrt(6.0);
+    }
+    row[12] = std::cos(a);
+    row[13] = std::sin(a);
+    row[14] = t;
+  }
+  for (int k = 0; k < 64; ++k) {
+    tab[smcx::kFdRootsOffset + 2 * k] = std::cos(2.0 * kPi * k / 64.0);
+    tab[smcx::kFdRootsOffset + 2 * k + 1] = -std::sin(2.0 * kPi * k / 64.0);
+  }
 }
 
 // logL of a particle without components, split at the posterior-start bridge
@@ -315,6 +377,129 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "upload of d"); }
   *out = p;
+  return SMCX_OK;
+}
+
+int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B, double T_obs,
+                           double psd, int32_t k_max, int64_t n_max, int64_t m_max,
+                           void* hip_stream, smcx_problem** out) {
+  g_last_error.clear();
+  if (!out) return fail(SMCX_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (model != SMCX_GBLISA) return fail(SMCX_EINVAL, "model %d has no frequency-domain form", model);
+  if (!d_dev) return fail(SMCX_EINVAL, "d_dev is NULL");
+  if (B < 1 || B > 256) return fail(SMCX_EINVAL, "B = %lld outside [1, 256]", (long long)B);
+  if (k0 < 0) return fail(SMCX_EINVAL, "k0 must be >= 0");
+  if (!(T_obs > 0.0) || !std::isfinite(T_obs)) return fail(SMCX_EINVAL, "T_obs must be finite and > 0");
+  if (!(psd > 0.0) || !std::isfinite(psd)) return fail(SMCX_EINVAL, "psd must be finite and > 0");
+  if (k_max < 1 || k_max > 512) return fail(SMCX_EINVAL, "k_max = %d outside [1, 512]", k_max);
+  if (n_max < 0 || n_max > (int64_t(1) << 30)) return fail(SMCX_EINVAL, "n_max = %lld out of range", (long long)n_max);
+  if (m_max < 0 || m_max > (int64_t(1) << 34)) return fail(SMCX_EINVAL, "m_max = %lld out of range", (long long)m_max);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (capturing(st)) return fail(SMCX_ECAPTURE, "smcx_problem_create_fd called during stream capture");
+
+  smcx_problem* p = new smcx_problem();
+  p->model = model;
+  p->P = smcx::n_params(model);
+  p->T = 1;  // no time axis: one "sample" carries the band's energy
+  p->t_start = 0.0;
+  p->dt = 1.0;
+  p->sigma = 1.0;
+  p->inv_sigma2 = 4.0 / (T_obs * psd);  // the inner product's 4 df / S
+  p->k_max = k_max;
+  p->n_max = n_max;
+  p->m_max = m_max;
+  p->fd = true;
+  p->fd_k0 = k0;
+  p->fd_B = B;
+  p->fd_T_obs = T_obs;
+  p->fd_S = psd;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
+  e = hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipDeviceGetAttribute"); }
+  for (int k = 0; k < kNumKinds; ++k) p->tiling[k] = Tiling{16, 1024, 1, 1};
+  p->max_nch = p->max_nch_grad = 1;
+  const int64_t Bp = B <= 128 ? 128 : 256;
+  std::vector<double> h(4 * B), hp(4 * Bp, 0.0), tab;
+  e = hipMemcpyAsync(h.data(), d_dev, 4 * B * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "copy of d"); }
+  double energy = 0.0;
+  for (int c = 0; c < 2; ++c)
+    for (int64_t b = 0; b < B; ++b)
+      for (int x = 0; x < 2; ++x) {
+        const double v = h[(c * B + b) * 2 + x];
+        hp[(c * Bp + b) * 2 + x] = v;
+        energy += v * v;
+      }
+  p->prefix = {0.0, energy};
+  fd_table_host(T_obs, tab);
+  const size_t n1 = (size_t)std::max<int64_t>(n_max, 1);
+  struct { void** ptr; size_t bytes; } allocs[] = {
+      {(void**)&p->fd_data, 4 * Bp * sizeof(double)},
+      {(void**)&p->fd_table, tab.size() * sizeof(double)},
+      {(void**)&p->order, n1 * sizeof(int32_t)},
+      {(void**)&p->n_active, sizeof(int32_t)},
+      {(void**)&p->prep_hist, (size_t)smcx::prep_slices((int64_t)n1) * (k_max + 1) * sizeof(int32_t)},
+      {(void**)&p->smc.cum, n1 * sizeof(int64_t)},
+      {(void**)&p->smc.src_row, n1 * sizeof(int64_t)},
+      {(void**)&p->smc.src_len, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.skip, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.append, n1 * sizeof(int32_t)},
+      {(void**)&p->smc.count, n1 * sizeof(int64_t)},
+      {(void**)&p->flag, sizeof(int)},
+      {(void**)&p->part, n1 * 4 * sizeof(double)},
+      {(void**)&p->part_g, sizeof(double)},
+  };
+  for (auto& al : allocs) {
+    e = hipMalloc(al.ptr, al.bytes);
+    if (e != hipSuccess) {
+      free_problem(p);
+      return fail(SMCX_ENOMEM, "hipMalloc of %zu bytes failed: %s", al.bytes, hipGetErrorString(e));
+    }
+  }
+  const int zero = 0;
+  e = hipMemcpyAsync(p->fd_data, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->fd_table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->flag, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->n_active, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) { free_problem(p); return hip_fail(e, "upload of d"); }
+  *out = p;
+  return SMCX_OK;
+}
+
+int smcx_template_spectrum(int model, int64_t K, const double* theta, double T_obs, int64_t k0,
+                           int64_t B, double* out, void* hip_stream) {
+  g_last_error.clear();
+  if (model != SMCX_GBLISA) return fail(SMCX_EINVAL, "model %d has no frequency-domain form", model);
+  if (K < 0) return fail(SMCX_EINVAL, "negative K");
+  if (K > 0 && !theta) return fail(SMCX_EINVAL, "theta is NULL");
+  if (B < 1 || B > 256) return fail(SMCX_EINVAL, "B = %lld outside [1, 256]", (long long)B);
+  if (!out) return fail(SMCX_EINVAL, "out is NULL");
+  if (!(T_obs > 0.0) || !std::isfinite(T_obs)) return fail(SMCX_EINVAL, "T_obs must be finite and > 0");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (capturing(st)) return fail(SMCX_ECAPTURE, "smcx_template_spectrum called during stream capture");
+  std::vector<double> tab;
+  fd_table_host(T_obs, tab);
+  double* dtab = nullptr;
+  hipError_t e = hipMalloc(&dtab, tab.size() * sizeof(double));
+  if (e != hipSuccess) return fail(SMCX_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+  e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  smcx::PopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.theta = theta;
+  a.fd_table = dtab;
+  a.fd_k0 = k0;
+  a.fd_B = B;
+  a.fd_T_obs = T_obs;
+  a.fd_scale = T_obs / 64.0;
+  if (e == hipSuccess) e = smcx::launch_fd_spectrum(a, K, out, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dtab);
+  if (e != hipSuccess) return hip_fail(e, "template spectrum");
   return SMCX_OK;
 }
 
@@ -457,6 +642,9 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
                     double* logl_ext, double* logw, double* w_norm, double* scalars,
                     void* hip_stream) {
   g_last_error.clear();
+  if (p && p->fd)
+    return fail(SMCX_EINVAL, "reweight_extend needs a time-domain problem; for the frequency-domain "
+                             "model evaluate logl_batch on both problems");
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
   if (T1 < 0 || T2 <= T1 || T2 > p->T)
@@ -509,6 +697,7 @@ int smcx_plain_logl_grad(smcx_problem* p, int64_t N, const int64_t* offsets_host
   g_last_error.clear();
   if (p && p->split != 0)
     return fail(SMCX_EINVAL, "the plain form evaluates the prior bridge only (bridge split is set)");
+  if (p && p->fd) return fail(SMCX_EINVAL, "the plain form is defined for time-domain problems only");
   int rc = check_pop(p, N, offsets_host, M, theta);
   if (rc) return rc;
   if (N > 0 && !logl) return fail(SMCX_EINVAL, "logl is NULL");
@@ -804,6 +993,7 @@ int smcx_nuts_transition_metric(smcx_problem* p, int64_t N, const int64_t* offse
 int smcx_set_bridge_split(smcx_problem* p, int64_t split) {
   g_last_error.clear();
   if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (p->fd && split != 0) return fail(SMCX_EINVAL, "frequency-domain problems have no bridge split");
   if (split < 0 || split > p->T)
     return fail(SMCX_EINVAL, "split = %lld outside [0, T = %lld]", (long long)split, (long long)p->T);
   p->split = split;
@@ -820,6 +1010,7 @@ int smcx_get_bridge_split(smcx_problem* p, int64_t* split) {
 int smcx_set_tiling(smcx_problem* p, int32_t kind, int32_t S, int64_t chunk_len, int32_t sorted) {
   g_last_error.clear();
   if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (p->fd) return fail(SMCX_EINVAL, "frequency-domain problems have no sample tiling");
   if (kind < 0 || kind >= kNumKinds) return fail(SMCX_EINVAL, "unknown call kind %d", kind);
   const bool s_ok = kind == kDelta ? (S == 8 || S == 16) : (S == 8 || S == 16 || S == 32 || S == 64);
   if (!s_ok) return fail(SMCX_EINVAL, "S = %d not supported for this call kind", S);
@@ -952,6 +1143,7 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   g_last_error.clear();
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
+  if (p->fd) return fail(SMCX_EINVAL, "the metric is implemented for the time-domain models");
   if (N == 0) return SMCX_OK;
   if (!f_offsets) return fail(SMCX_EINVAL, "f_offsets is NULL");
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");

@@ -1,0 +1,476 @@
+// LISA Galactic binaries in the frequency domain (Sec. "LISA Galactic
+// binaries"): eight parameters per source (f0, fdot, log10 A, ecliptic
+// latitude and longitude, psi, iota, phi0), the A and E channels in the
+// long-wavelength limit of the constellation, and the likelihood of
+// eq. gw_likelihood with a constant PSD over a band of bins [k0, k0 + B):
+//   logL = -(1/2) (4 / (T_obs S)) sum_c sum_k |d_c[k] - h_c[k]|^2.
+//
+// Templates use the fast/slow decomposition the paper's waveforms come from:
+// the heterodyned envelope z_c(t) = a_c(t) e^{i(Phi(tau) - 2 pi q t / T_obs)} / 2
+// (carrier bin q = floor(f0 T_obs), tau the retarded time at the guiding
+// centre) is sampled at t_j = j T_obs / 64 and its 64-point DFT fills bins
+// q - 32 .. q + 31:  h_c[q + m] = (T_obs / 64) sum_j z_c(t_j) e^{-2 pi i m j / 64}.
+//
+// Mapping: one wave per particle; lane j owns envelope sample j and band
+// bins j + 64 r. A source's 64 samples go through one FFT across the wave
+// (radix 2, six butterfly stages over lane pairs lane ^ h, FP64), then each
+// lane fetches the window value of its own bins from the lane holding it.
+// The residual stays in registers; the adjoint contracts the inverse FFT of
+// each source's residual window with the analytic envelope derivatives, so
+// d logL / d theta = beta (4 / (T_obs S)) (T_obs / 64) Re sum_j conj(w_j) dz_j.
+// Everything is FP64: a source concentrates its signal in a few bins, where
+// an FP32 template would not hold the likelihood to 1e-6.
+#include "smcx_internal.h"
+
+#include <math.h>
+
+namespace smcx {
+namespace {
+
+constexpr int kNs = 64;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kLn10 = 2.302585092994045684017991454684;
+constexpr double kAuLight = 1.495978707e11 / 299792458.0;  // R / c [s]
+
+// Per-lane constants of the coarse time grid: symmetric detector tensors
+// of A and E (xx, yy, zz, xy, xz, yz), cos and sin of the orbital phase,
+// t_j; then the 64 roots exp(-2 pi i k / 64).
+struct LaneGeom {
+  double dA[6], dE[6], ca, sa, t;
+};
+
+__device__ __forceinline__ LaneGeom load_geom(const double* tab, int lane) {
+  LaneGeom g;
+  const double* r = tab + lane * kFdTableStride;
+#pragma unroll
+  for (int x = 0; x < 6; ++x) {
+    g.dA[x] = r[x];
+    g.dE[x] = r[6 + x];
+  }
+  g.ca = r[12];
+  g.sa = r[13];
+  g.t = r[14];
+  return g;
+}
+
+struct V3 {
+  double x, y, z;
+};
+__device__ __forceinline__ double dot3(const V3& a, const V3& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 mul_sym(const double* d, const V3& v) {
+  return {d[0] * v.x + d[3] * v.y + d[4] * v.z, d[3] * v.x + d[1] * v.y + d[5] * v.z,
+          d[4] * v.x + d[5] * v.y + d[2] * v.z};
+}
+
+// Source constants, the same in every lane.
+struct Src {
+  double f0, fd, A, cb, sb, cl, sl, c2p, s2p, ci, si, cyc0;
+  V3 n, u, v;
+  int64_t q;
+};
+
+__device__ __forceinline__ Src make_src(const double* th, double T_obs) {
+  Src s;
+  s.f0 = th[0];
+  s.fd = th[1];
+  s.A = exp10(th[2] + 21.0);
+  sincos(th[3], &s.sb, &s.cb);
+  sincos(th[4], &s.sl, &s.cl);
+  sincos(2.0 * th[5], &s.s2p, &s.c2p);
+  sincos(th[6], &s.si, &s.ci);
+  s.cyc0 = th[7] / kTwoPi;
+  s.n = {s.cb * s.cl, s.cb * s.sl, s.sb};
+  s.u = {s.sb * s.cl, s.sb * s.sl, -s.cb};
+  s.v = {-s.sl, s.cl, 0.0};
+  s.q = (int64_t)floor(s.f0 * T_obs);
+  return s;
+}
+
+// Envelope of one source at this lane's sample, both channels (no (-1)^j).
+struct Env {
+  double zr[2], zi[2];  // z_c
+  double ar[2], ai[2];  // complex amplitude a_c
+  double Fp[2], Fx[2];
+  double cph, sph, tau, doppler;  // doppler = cos(a - l) (R/c)
+};
+
+__device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lane) {
+  Env e;
+  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double* D = c == 0 ? g.dA : g.dE;
+    const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
+    const double P = dot3(s.u, Du) - dot3(s.v, Dv), X = 2.0 * dot3(s.u, Dv);
+    e.Fp[c] = s.c2p * P + s.s2p * X;
+    e.Fx[c] = -s.s2p * P + s.c2p * X;
+    e.ar[c] = e.Fp[c] * Ap;
+    e.ai[c] = -e.Fx[c] * Ax;
+  }
+  e.doppler = kAuLight * (g.ca * s.cl + g.sa * s.sl);
+  e.tau = g.t + s.cb * e.doppler;
+  // phase in cycles, reduced before the product with 2 pi
+  double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
+               (double)(s.q & (kNs - 1)) * (double)lane / (double)kNs + s.cyc0;
+  cyc -= rint(cyc);
+  sincospi(2.0 * cyc, &e.sph, &e.cph);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    e.zr[c] = 0.5 * (e.ar[c] * e.cph - e.ai[c] * e.sph);
+    e.zi[c] = 0.5 * (e.ar[c] * e.sph + e.ai[c] * e.cph);
+  }
+  return e;
+}
+
+__device__ __forceinline__ int bitrev6(int x) { return (int)(__builtin_bitreverse32((unsigned)x) >> 26); }
+
+// Forward DFT over the wave, decimation in frequency: natural order in,
+// lane L ends with X[bitrev6(L)]. roots[k] = exp(-2 pi i k / 64).
+__device__ __forceinline__ void fft_dif(double re[2], double im[2], const double* roots, int lane) {
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+    const bool up = lane & h;
+    const int k = (lane & (h - 1)) * (32 / h);
+    const double wr = roots[2 * k], wi = roots[2 * k + 1];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double ore = __shfl_xor(re[c], h), oim = __shfl_xor(im[c], h);
+      if (up) {
+        const double dr = ore - re[c], di = oim - im[c];
+        re[c] = dr * wr - di * wi;
+        im[c] = dr * wi + di * wr;
+      } else {
+        re[c] += ore;
+        im[c] += oim;
+      }
+    }
+  }
+}
+
+// Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT over the wave, decimation
+// in time: lane L holds input index bitrev6(L), output in natural order.
+__device__ __forceinline__ void ifft_dit(double re[2], double im[2], const double* roots, int lane) {
+#pragma unroll
+  for (int h = 1; h <= 32; h <<= 1) {
+    const bool up = lane & h;
+    const int k = (lane & (h - 1)) * (32 / h);
+    const double wr = roots[2 * k], wi = -roots[2 * k + 1];  // conjugate root
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double ore = __shfl_xor(re[c], h), oim = __shfl_xor(im[c], h);
+      // lower: x + w o; upper: o - w x
+      const double br = up ? re[c] : ore, bi = up ? im[c] : oim;
+      const double tr = wr * br - wi * bi, ti = wr * bi + wi * br;
+      re[c] = up ? ore - tr : re[c] + tr;
+      im[c] = up ? oim - ti : im[c] + ti;
+    }
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// The source's window spectrum (times T_obs / 64), bit-reversed across the
+// wave: lane L holds bin q - 32 + bitrev6(L).
+__device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* roots,
+                                                double scale, int lane, double re[2], double im[2]) {
+  const Env e = envelope(s, g, lane);
+  const double sg = (lane & 1) ? -scale : scale;  // (-1)^j centres the window on q
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    re[c] = sg * e.zr[c];
+    im[c] = sg * e.zi[c];
+  }
+  fft_dif(re, im, roots, lane);
+}
+
+// Value of the window spectrum at band bin b (0 outside the window), read
+// from the lane that holds it. All lanes must call this together.
+__device__ __forceinline__ void window_at(const double re[2], const double im[2], int64_t b_abs,
+                                          int64_t q, double out_re[2], double out_im[2]) {
+  const int64_t m = b_abs - (q - kNs / 2);
+  const bool in = m >= 0 && m < kNs;
+  const int src = bitrev6((int)(m & (kNs - 1)));
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double vr = __shfl(re[c], src), vi = __shfl(im[c], src);
+    out_re[c] = in ? vr : 0.0;
+    out_im[c] = in ? vi : 0.0;
+  }
+}
+
+template <int NR>
+struct Resid {
+  double re[2][NR], im[2][NR];
+};
+
+template <int NR>
+__device__ __forceinline__ void load_resid(const PopArgs& a, int lane, Resid<NR>& R) {
+  const int Bp = kNs * NR;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int b = lane + kNs * r;
+      R.re[c][r] = a.fd_data[(c * Bp + b) * 2];
+      R.im[c][r] = a.fd_data[(c * Bp + b) * 2 + 1];
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void subtract_source(const PopArgs& a, const Src& s, const LaneGeom& g,
+                                                int lane, Resid<NR>& R, double sign) {
+  double re[2], im[2];
+  window_spectrum(s, g, a.fd_table + kFdRootsOffset, a.fd_scale, lane, re, im);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int64_t b = lane + kNs * r;
+    double vr[2], vi[2];
+    window_at(re, im, a.fd_k0 + b, s.q, vr, vi);
+    const bool live = b < a.fd_B;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      R.re[c][r] -= live ? sign * vr[c] : 0.0;
+      R.im[c][r] -= live ? sign * vi[c] : 0.0;
+    }
+  }
+}
+
+// Re<R, h> and |h|^2 over the band for one source (both channels).
+template <int NR>
+__device__ __forceinline__ void overlap(const PopArgs& a, const Src& s, const LaneGeom& g, int lane,
+                                        const Resid<NR>& R, double* rh, double* hh) {
+  double re[2], im[2];
+  window_spectrum(s, g, a.fd_table + kFdRootsOffset, a.fd_scale, lane, re, im);
+  double x = 0.0, y = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int64_t b = lane + kNs * r;
+    double vr[2], vi[2];
+    window_at(re, im, a.fd_k0 + b, s.q, vr, vi);
+    if (b < a.fd_B)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        x = fma(R.re[c][r], vr[c], fma(R.im[c][r], vi[c], x));
+        y = fma(vr[c], vr[c], fma(vi[c], vi[c], y));
+      }
+  }
+  *rh = wave_sum(x);
+  *hh = wave_sum(y);
+}
+
+struct FdItem {
+  int64_t i, m0;
+  int K;
+};
+
+// Work item of this wave (sorted mode: the ordering pass listed the valid
+// particles with K > 0, or all valid ones for birth/death).
+__device__ __forceinline__ bool fd_item(const PopArgs& a, int64_t rank, FdItem& it) {
+  if (a.order) {
+    if (rank >= *a.n_active) return false;
+    it.i = a.order[rank];
+  } else {
+    if (rank >= a.N) return false;
+    it.i = rank;
+  }
+  const int64_t o0 = a.offsets[it.i], o1 = a.offsets[it.i + 1];
+  if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) return false;
+  it.m0 = o0;
+  it.K = (int)(o1 - o0);
+  return true;
+}
+
+// MODE 0: logL; 1: logL and gradient (with the leapfrog kick when p_half
+// is set); 2: birth / death changes.
+template <int MODE, int NR>
+__global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  FdItem it;
+  if (!fd_item(a, rank, it)) return;
+  const int64_t i = it.i;
+  if (a.active && !a.active[i]) return;
+  const double b = a.beta ? a.beta[i] : 1.0;
+  const double bc = b * a.inv_sigma2;  // beta * 4 / (T_obs S)
+  const LaneGeom g = load_geom(a.fd_table, lane);
+  Resid<NR> R;
+  load_resid<NR>(a, lane, R);
+  for (int k = 0; k < it.K; ++k) {
+    const Src s = make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+    subtract_source<NR>(a, s, g, lane, R, 1.0);
+  }
+  if constexpr (MODE == 2) {
+    if (a.theta_birth && a.dlogl_birth) {
+      const Src s = make_src(a.theta_birth + i * 8, a.fd_T_obs);
+      double rh, hh;
+      overlap<NR>(a, s, g, lane, R, &rh, &hh);
+      if (lane == 0) a.dlogl_birth[i] = bc * (rh - 0.5 * hh);
+    }
+    if (a.death_idx && a.dlogl_death) {
+      const int j = a.death_idx[i];
+      if (j >= 0 && j < it.K) {
+        const Src s = make_src(a.theta + (it.m0 + j) * 8, a.fd_T_obs);
+        double rh, hh;
+        overlap<NR>(a, s, g, lane, R, &rh, &hh);
+        if (lane == 0) a.dlogl_death[i] = -(bc * (rh + 0.5 * hh));
+      } else if (lane == 0) {
+        a.dlogl_death[i] = j == -1 ? 0.0 : __builtin_nan("");
+        if (j != -1) atomicOr(a.flag, kFlagDeath);
+      }
+    }
+    return;
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ss = fma(R.re[c][r], R.re[c][r], fma(R.im[c][r], R.im[c][r], ss));
+  ss = wave_sum(ss);
+  if (lane == 0 && a.logl) a.logl[i] = b * (-0.5 * a.inv_sigma2 * ss);
+  if constexpr (MODE == 1) {
+    const double* roots = a.fd_table + kFdRootsOffset;
+    const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
+    const int lr = bitrev6(lane);
+    for (int k = 0; k < it.K; ++k) {
+      const Src s = make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+      // residual window of the source, bit-reversed for the inverse FFT
+      const int64_t bw = s.q - kNs / 2 + lr - a.fd_k0;  // band index this lane gathers
+      const bool in = bw >= 0 && bw < a.fd_B;
+      const int src = (int)(bw & (kNs - 1));
+      const int reg = in ? (int)(bw >> 6) : 0;
+      double wr[2], wi[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double vr = 0.0, vi = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double xr = __shfl(R.re[c][r], src), xi = __shfl(R.im[c][r], src);
+          vr = reg == r ? xr : vr;
+          vi = reg == r ? xi : vi;
+        }
+        wr[c] = in ? vr : 0.0;
+        wi[c] = in ? vi : 0.0;
+      }
+      ifft_dit(wr, wi, roots, lane);
+      // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
+      // of the window (indexed from q - 32)
+      if (lane & 1) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          wr[c] = -wr[c];
+          wi[c] = -wi[c];
+        }
+      }
+      // Re(conj(w) dz) per parameter; dz = (da e^{i ph}) / 2 + i dphi z
+      const Env e = envelope(s, g, lane);
+      const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+      const double fi = s.f0 + s.fd * e.tau;
+      double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
+                        kTwoPi * fi * (-s.sb * e.doppler),
+                        kTwoPi * fi * (s.cb * kAuLight * (g.sa * s.cl - g.ca * s.sl)), 0.0, 0.0,
+                        1.0};
+      double gp[8];
+#pragma unroll
+      for (int p = 0; p < 8; ++p) gp[p] = 0.0;
+      const V3 ul = {s.sb * s.v.x, s.sb * s.v.y, 0.0};
+      const V3 vl = {-s.cl, -s.sl, 0.0};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double* D = c == 0 ? g.dA : g.dE;
+        const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
+        const double dPb = 2.0 * dot3(s.n, Du), dXb = 2.0 * dot3(s.n, Dv);
+        const double dPl = 2.0 * (dot3(ul, Du) - dot3(vl, Dv));
+        const double dXl = 2.0 * (dot3(ul, Dv) + dot3(vl, Du));
+        double da_r[8], da_i[8];
+        da_r[0] = da_i[0] = da_r[1] = da_i[1] = da_r[7] = da_i[7] = 0.0;
+        da_r[2] = kLn10 * e.ar[c];
+        da_i[2] = kLn10 * e.ai[c];
+        da_r[3] = (s.c2p * dPb + s.s2p * dXb) * Ap;
+        da_i[3] = -(-s.s2p * dPb + s.c2p * dXb) * Ax;
+        da_r[4] = (s.c2p * dPl + s.s2p * dXl) * Ap;
+        da_i[4] = -(-s.s2p * dPl + s.c2p * dXl) * Ax;
+        da_r[5] = 2.0 * e.Fx[c] * Ap;
+        da_i[5] = 2.0 * e.Fp[c] * Ax;
+        da_r[6] = e.Fp[c] * (-2.0 * s.A * s.ci * s.si);
+        da_i[6] = -e.Fx[c] * (2.0 * s.A * s.si);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          const double dzr = 0.5 * (da_r[p] * e.cph - da_i[p] * e.sph) - dphi[p] * e.zi[c];
+          const double dzi = 0.5 * (da_r[p] * e.sph + da_i[p] * e.cph) + dphi[p] * e.zr[c];
+          gp[p] = fma(wr[c], dzr, fma(wi[c], dzi, gp[p]));
+        }
+      }
+      const double gs = bc * a.fd_scale;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) gp[p] = wave_sum(gp[p]) * gs;
+      if (lane < 8) {
+        double gv = gp[0];
+#pragma unroll
+        for (int p = 1; p < 8; ++p) gv = lane == p ? gp[p] : gv;
+        const int64_t x = (it.m0 + k) * 8 + lane;
+        if (a.grad) a.grad[x] = gv;
+        if (a.p_half) a.p_out[x] = fma(he, gv, a.p_half[x]);
+      }
+    }
+  }
+}
+
+// The band spectrum of K sources (out [2][B][2]): one wave.
+__global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, double* out) {
+  const int lane = threadIdx.x;
+  const LaneGeom g = load_geom(a.fd_table, lane);
+  Resid<4> R;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R.re[c][r] = R.im[c][r] = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const Src s = make_src(a.theta + k * 8, a.fd_T_obs);
+    subtract_source<4>(a, s, g, lane, R, -1.0);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t b = lane + kNs * r;
+      if (b < a.fd_B) {
+        out[(c * a.fd_B + b) * 2] = R.re[c][r];
+        out[(c * a.fd_B + b) * 2 + 1] = R.im[c][r];
+      }
+    }
+}
+
+template <int MODE>
+hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
+  if (a.N == 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.N + 3) / 4)), block(256);
+  if (a.fd_B <= 2 * kNs)
+    hipLaunchKernelGGL((fd_kernel<MODE, 2>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((fd_kernel<MODE, 4>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
+  if (a.fd_B < 1 || a.fd_B > 4 * kNs) return hipErrorInvalidValue;
+  switch (mode) {
+    case 0: return launch_fd_mode<0>(a, st);
+    case 1: return launch_fd_mode<1>(a, st);
+    case 2: return launch_fd_mode<2>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st) {
+  if (a.fd_B < 1 || a.fd_B > 4 * kNs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fd_spectrum_kernel, dim3(1), dim3(64), 0, st, a, K, out);
+  return hipGetLastError();
+}
+
+}  // namespace smcx

@@ -35,7 +35,9 @@ struct SmcWork {
 };
 
 // Number of parameters per component.
-__host__ __device__ constexpr int n_params(int model) { return model == SMCX_PULSE ? 3 : 4; }
+__host__ __device__ constexpr int n_params(int model) {
+  return model == SMCX_PULSE ? 3 : (model == SMCX_GBSINE ? 4 : 8);
+}
 
 // ---------------------------------------------------------------------------
 // Tiling of the sample axis. A wave owns one work item = (particle, chunk);
@@ -90,7 +92,19 @@ struct PopArgs {
   double* dlogl_birth;
   double* dlogl_death;
   int* flag;
+  // frequency-domain (LISA Galactic-binary) problems
+  const double* fd_data;   // [2][Bp][2] band spectrum of A and E (re, im), Bp = 128 or 256
+  const double* fd_table;  // per-lane coarse-grid constants and the 64 roots of unity
+  int64_t fd_k0;           // first bin of the band
+  int64_t fd_B;            // bins in the band
+  double fd_T_obs;         // observation time [s]
+  double fd_scale;         // T_obs / 64
 };
+// Layout of fd_table: [64][kFdTableStride] (tensors of A, E; cos, sin of
+// the orbital phase; t_j), then [64][2] roots exp(-2 pi i k / 64).
+constexpr int kFdTableStride = 16;
+constexpr int kFdRootsOffset = 64 * kFdTableStride;
+constexpr int kFdTableSize = kFdRootsOffset + 128;
 
 // Sort particles by K (descending) and settle K = 0 / invalid particles.
 struct PrepArgs {
@@ -207,6 +221,10 @@ hipError_t launch_rj_apply(const SmcWork& w, int model, int32_t k_max, int64_t N
                            int64_t m_cap, int64_t* offsets_out, double* theta_out,
                            int8_t* accepted, int* flag, hipStream_t st);
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
+// Frequency-domain model (smcx_gblisa.hip): mode 0 logL, 1 logL + gradient
+// (leapfrog kick when p_half is set), 2 birth / death changes.
+hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st);
+hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,

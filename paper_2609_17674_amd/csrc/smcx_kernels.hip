@@ -1220,16 +1220,19 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
 int64_t prep_slices(int64_t N) { return N > 0 ? (N + kPrepSlice - 1) / kPrepSlice : 1; }
 
 hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  if (model == SMCX_GBLISA) return launch_fd(0, a, st);
   return model == SMCX_PULSE ? launch_pop_model<SMCX_PULSE, false>(t, a, st)
                              : launch_pop_model<SMCX_GBSINE, false>(t, a, st);
 }
 
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  if (model == SMCX_GBLISA) return launch_fd(1, a, st);
   return model == SMCX_PULSE ? launch_pop_model<SMCX_PULSE, true>(t, a, st)
                              : launch_pop_model<SMCX_GBSINE, true>(t, a, st);
 }
 
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st) {
+  if (model == SMCX_GBLISA) return launch_fd(2, a, st);
   return model == SMCX_PULSE ? launch_delta_model<SMCX_PULSE>(t, a, st)
                              : launch_delta_model<SMCX_GBSINE>(t, a, st);
 }

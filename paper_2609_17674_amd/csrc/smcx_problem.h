@@ -26,6 +26,12 @@ struct smcx_problem {
   std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2
   Tiling tiling[kNumKinds];
   int64_t split = 0;  // posterior-start bridge split (smcx_set_bridge_split); 0 = prior bridge
+  // frequency-domain problems (smcx_problem_create_fd)
+  bool fd = false;
+  int64_t fd_k0 = 0, fd_B = 0;
+  double fd_T_obs = 0, fd_S = 0;
+  double* fd_data = nullptr;   // [2][Bp][2], Bp = 128 or 256, zero past B
+  double* fd_table = nullptr;  // kFdTableSize doubles
   int max_nch = 0;       // capacity of part (chunks per particle)
   int max_nch_grad = 0;  // capacity of part_g
   int32_t* order = nullptr;

@@ -92,6 +92,7 @@ extern "C" int smcx_autotune(smcx_problem* p, int32_t kind, int64_t N, const int
                              const char* cache_path, void* hip_stream, int32_t* out_S,
                              int64_t* out_chunk, int32_t* out_sorted, double* out_ms) {
   if (!p) return smcx::set_error(SMCX_EINVAL, "problem handle is NULL");
+  if (p->fd) return smcx::set_error(SMCX_EINVAL, "frequency-domain problems have no sample tiling");
   if (kind < 0 || kind >= kNumKinds) return smcx::set_error(SMCX_EINVAL, "unknown call kind %d", kind);
   if (reps < 1 || reps > 1000) return smcx::set_error(SMCX_EINVAL, "reps out of range");
   if (N < 1 || N > p->n_max || M < 1 || M > p->m_max || !offsets || !theta)

@@ -23,8 +23,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "smcx.h")
 
 SMCX_OK, SMCX_EINVAL, SMCX_ENOMEM, SMCX_EDEVICE, SMCX_ECAPTURE = 0, -1, -2, -3, -4
 KIND_LOGL, KIND_GRAD, KIND_DELTA = 0, 1, 2
-PULSE, GBSINE = 0, 1
-N_PARAMS = {PULSE: 3, GBSINE: 4}
+PULSE, GBSINE, GBLISA = 0, 1, 2
+N_PARAMS = {PULSE: 3, GBSINE: 4, GBLISA: 8}
 
 
 class SmcxError(RuntimeError):
@@ -48,6 +48,8 @@ def load_library():
     PP = ctypes.POINTER(ctypes.c_void_p)
     sig = {
         "smcx_problem_create": [I, P, I64, D, D, D, I32, I64, I64, P, PP],
+        "smcx_problem_create_fd": [I, P, I64, I64, D, D, I32, I64, I64, P, PP],
+        "smcx_template_spectrum": [I, I64, P, D, I64, I64, P, P],
         "smcx_problem_destroy": [P],
         "smcx_device_status": [P, P],
         "logl_batch": [P, I64, P, I64, P, P, P, P],
@@ -150,6 +152,31 @@ class Problem:
                                        self.k_max, self.n_max, self.m_max, _stream(stream),
                                        ctypes.byref(h)))
         self.handle = h
+
+    @classmethod
+    def frequency_domain(cls, model: int, d, k0: int, T_obs: float, psd: float, k_max: int,
+                         n_max: int, m_max: int, stream=None) -> "Problem":
+        """Frequency-domain problem (smcx_problem_create_fd): d is the band
+        spectrum of channels A and E, a complex [2, B] tensor (or float64
+        [2, B, 2]) on the device, for bins k0 .. k0 + B - 1 of a record of
+        length T_obs with constant one-sided PSD psd."""
+        lib = load_library()
+        if torch.is_complex(d):
+            d = torch.view_as_real(d.to(torch.complex128).contiguous())
+        d = _dev(d, torch.float64, "d")
+        if d.dim() != 3 or d.shape[0] != 2 or d.shape[2] != 2:
+            raise ValueError("d must be [2, B] complex or [2, B, 2] float64")
+        self = cls.__new__(cls)
+        self.model, self.P = int(model), N_PARAMS[int(model)]
+        self.T, self.t_start, self.dt, self.sigma = 1, 0.0, 1.0, 1.0
+        self.k0, self.B, self.T_obs, self.psd = int(k0), int(d.shape[1]), float(T_obs), float(psd)
+        self.k_max, self.n_max, self.m_max = int(k_max), int(n_max), int(m_max)
+        h = ctypes.c_void_p()
+        _check(lib.smcx_problem_create_fd(self.model, _ptr(d), self.k0, self.B, self.T_obs, self.psd,
+                                          self.k_max, self.n_max, self.m_max, _stream(stream),
+                                          ctypes.byref(h)))
+        self.handle = h
+        return self
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -519,3 +546,14 @@ def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None,
                                              ctypes.cast(rarr, ctypes.c_void_p), _ptr(out),
                                              _stream(stream)))
     return out
+
+
+def template_spectrum(model: int, theta, T_obs: float, k0: int, B: int, stream=None) -> torch.Tensor:
+    """Band spectrum [2, B] (complex128, device) of the sources theta [K, 8]
+    (smcx_template_spectrum; a set-up call that synchronises)."""
+    theta = _dev(theta, torch.float64, "theta")
+    out = torch.empty((2, int(B), 2), dtype=torch.float64, device=theta.device)
+    _check(load_library().smcx_template_spectrum(int(model), theta.shape[0] if theta.dim() == 2 else 0,
+                                                 _ptr(theta), float(T_obs), int(k0), int(B),
+                                                 _ptr(out), _stream(stream)))
+    return torch.view_as_complex(out)

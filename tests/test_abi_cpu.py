@@ -61,6 +61,14 @@ def test_null_handle_rejected_before_launch(smcx):
     rc = lib.smcx_rj_apply(None, 4, None, 0, None, None, None, None, None, None, None, 1, 5, 0.0, 0,
                            None, None, None, None)
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    out = ctypes.c_void_p()
+    rc = lib.smcx_problem_create_fd(2, None, 31500, 128, 3e7, 1.0, 4, 4, 16, None, ctypes.byref(out))
+    assert rc == smcx.SMCX_EINVAL and "d_dev" in smcx.last_error()
+    rc = lib.smcx_problem_create_fd(1, ctypes.c_void_p(0x1000), 0, 128, 3e7, 1.0, 4, 4, 16, None,
+                                    ctypes.byref(out))
+    assert rc == smcx.SMCX_EINVAL and "frequency-domain" in smcx.last_error()
+    rc = lib.smcx_template_spectrum(2, 1, None, 3e7, 0, 128, None, None)
+    assert rc == smcx.SMCX_EINVAL
     rc = lib.smcx_metric_factor(None, 4, None, 0, None, 0, None, None, None, None)
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
     rc = lib.smcx_nuts_transition_metric(None, 4, None, 0, None, 0.1, 2, None, None, None, None,

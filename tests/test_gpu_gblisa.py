@@ -1,0 +1,164 @@
+"""The LISA Galactic-binary model (frequency domain) on the GPU against the
+oracle, through the C ABI.
+
+Tolerance, from the arithmetic: both sides evaluate the same definitions in
+FP64 (the GPU with a radix-2 FFT, the oracle with a direct 64-point sum and
+libm), so templates agree to a few hundred ulp of the largest bin. The
+residual in a bin is at least about the noise there, at most about 20 times
+smaller than the template, so logL agrees to well under 1e-10 relative and
+the gradient (natural coordinates: f0 T_obs, fdot T_obs^2, the rest as they
+are) to 1e-8 of its norm. The bounds used are 1e-9 and 1e-7.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+GBLISA = wl.GBLISA
+NAT = np.array([wl.GBLISA_T_OBS, wl.GBLISA_T_OBS ** 2, 1, 1, 1, 1, 1, 1], dtype=float)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def _data(orc, w):
+    return w.noise + orc.gblisa_spectrum(w.inj, w.T_obs, w.k0, w.B)
+
+
+def _problem(lib, w, d):
+    return lib.Problem.frequency_domain(GBLISA, dev(d), w.k0, w.T_obs, w.S, w.k_max, w.N,
+                                        max(w.M, 1))
+
+
+def test_template_spectrum_matches_oracle(lib, orc):
+    say("gblisa_spectrum")
+    w = wl.make_gblisa(N=4, n_inj=10, seed=400)
+    # include sources whose windows leave the band on either side
+    th = np.vstack([w.inj, w.inj[:2]])
+    th[-2, 0] = (w.k0 + 5) / w.T_obs
+    th[-1, 0] = (w.k0 + w.B - 3) / w.T_obs
+    for B in (w.B, 77, 200):
+        got = lib.template_spectrum(GBLISA, dev(th), w.T_obs, w.k0, B).cpu().numpy()
+        ref = orc.gblisa_spectrum(th, w.T_obs, w.k0, B)
+        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), B
+
+
+@pytest.mark.parametrize("noise,beta", [(True, "uniform"), (False, "one")], ids=["noise", "noisefree"])
+def test_logl_and_gradient_match_oracle(lib, orc, noise, beta):
+    w = wl.make_gblisa(N=300, k_lo=0, k_hi=10, n_inj=6, beta=beta, noise=noise, seed=401)
+    say("gblisa_logl_grad", noise, beta, "N", w.N, "M", w.M)
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l_only = lib.logl_batch(prob, off, th, be)
+    l, g = lib.logl_grad_batch(prob, off, th, be)
+    torch.cuda.synchronize()
+    prob.device_status()
+    l_only, l, g = l_only.cpu().numpy(), l.cpu().numpy(), g.cpu().numpy()
+    rl, rg = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    assert np.array_equal(l, l_only)
+    assert np.all(np.abs(l - rl) <= 1e-9 * np.abs(rl) + 1e-300)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        if a == b:
+            continue
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg[a:b] / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn) + 1e-300, i
+
+
+def test_birth_death_match_oracle(lib, orc):
+    w = wl.make_gblisa(N=200, k_lo=0, k_hi=8, n_inj=5, beta="uniform", noise=True, seed=402)
+    say("gblisa_delta")
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(prob, dev(w.offsets), dev(w.theta), dev(w.beta), dev(tb),
+                                        dev(di))
+    torch.cuda.synchronize()
+    prob.device_status()
+    rb, rd = orc.gblisa_delta(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta, tb, di)
+    db, dd = db.cpu().numpy(), dd.cpu().numpy()
+    # condition-scaled: 1e-9 of |<r, h>| + |h|^2 / 2, which bounds both terms
+    l0 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta, grad=False)
+    scale = np.abs(rb) + np.abs(rd) + 1e-6 * np.abs(l0) + 1.0
+    assert np.all(np.abs(db - rb) <= 1e-9 * scale)
+    assert np.all(np.abs(dd - rd) <= 1e-9 * scale)
+    assert np.all(dd[di == -1] == 0.0)
+
+
+def test_invalid_particles_and_refusals(lib, orc):
+    w = wl.make_gblisa(N=6, k_lo=1, k_hi=3, n_inj=2, seed=403)
+    say("gblisa_invalid")
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    off = w.offsets.copy()
+    off[3] = off[2] - 1  # non-monotone
+    l = lib.logl_batch(prob, dev(off), dev(w.theta), dev(w.beta))
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError):
+        prob.device_status()
+    assert np.isnan(l.cpu().numpy()[2])
+    with pytest.raises(lib.SmcxError, match="time-domain"):
+        lib.reweight_extend(prob, 0, 1, dev(w.offsets), dev(w.theta), 0.1)
+    with pytest.raises(lib.SmcxError, match="tiling"):
+        prob.set_tiling(lib.KIND_GRAD, 16, 1024, 1)
+    with pytest.raises(lib.SmcxError, match="split"):
+        prob.set_bridge_split(1)
+
+
+def test_nuts_depth_one_on_the_frequency_domain_model(lib, orc):
+    """One NUTS leaf on the GB model: a leapfrog step with the oracle's
+    gradients, with a diagonal mass matrix (W = diag of per-parameter
+    scales), then the acceptance on exp(H0 - H1)."""
+    w = wl.make_gblisa(N=64, k_lo=1, k_hi=4, n_inj=4, beta="half", noise=True, seed=404)
+    say("gblisa_nuts_depth1")
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    lib.nuts_reserve(prob, 1)
+    scales = np.array([0.05 / w.T_obs, 1e-19, 0.02, 0.02, 0.02, 0.02, 0.02, 0.05])
+    Wb = [np.diag(np.tile(scales, int(k))) for k in w.K]
+    wo, Wp = wl.pack_blocks(Wb)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, 8, 1, seed=405)
+    ul[:] = 0.0
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    q, l, g = th.clone(), l0.clone(), g0.clone()
+    eps = 0.4
+    _, steps, status = lib.nuts_transition(prob, off, be, eps, 1, q, l, g, dev(mom), dev(dirs),
+                                           dev(ul), dev(ut), metric=(dev(wo), dev(Wp)))
+    torch.cuda.synchronize()
+    prob.device_status()
+    q, status = q.cpu().numpy(), status.cpu().numpy()
+    rl0, rg0 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        Wi = Wb[i]
+        e = eps * dirs[i, 0]
+        r0 = mom[a:b].reshape(-1)
+        rh = r0 + 0.5 * e * Wi @ rg0[a:b].reshape(-1)
+        q1 = w.theta[a:b].reshape(-1) + e * Wi.T @ rh
+        l1, g1 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, [0, b - a], q1.reshape(-1, 8),
+                                      w.beta[i:i + 1])
+        r1 = rh + 0.5 * e * Wi @ g1.reshape(-1)
+        H0 = -rl0[i] + 0.5 * r0 @ r0
+        H1 = -l1[0] + 0.5 * r1 @ r1
+        if not H1 - H0 <= 1000:
+            assert status[i] == 2
+            continue
+        accept = ut[i, 0] < np.exp(H0 - H1)
+        ref = q1 if accept else w.theta[a:b].reshape(-1)
+        # the kicks differ by the gradient bound (1e-7 of the natural norm),
+        # far below 1e-6 of a step's scale
+        tol = 1e-12 * np.abs(ref) + 1e-6 * np.tile(scales, b - a)
+        assert np.all(np.abs(q[a:b].reshape(-1) - ref) <= tol), i
