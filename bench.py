@@ -428,6 +428,99 @@ def bench_metric(args, w, dev, smcx, np, torch):
                           "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 2)})
 
 
+# FP64 operations per lane of the wave per source in one logL + gradient
+# evaluation of the frequency-domain model: envelope synthesis 175 (two
+# detector-tensor products per channel, retarded time, phase, sincospi),
+# forward FFT 60, placement 8, inverse FFT 60, envelope again 175, the eight
+# derivatives and their products with the inverse FFT 390, reductions 48.
+GBLISA_FLOPS_PER_LANE = 920
+PEAK_FP64_TFLOPS = 78.6
+
+
+def bench_gblisa(args, dev, smcx, np, torch):
+    """LISA Galactic binaries in the frequency domain at the paper's settings
+    (Sec. "LISA Galactic binaries": one year, ten sources with f0 on a grid in
+    [0.9998, 1.0006] mHz, noise-free A and E data, N = 40000 particles, K in
+    [1, 10]); one logl_grad_batch call per step, beta ~ U[0, 1]."""
+    from paper_2609_17674_amd import workloads as wl
+    w = wl.make_gblisa(N=40000, k_lo=1, k_hi=10, n_inj=10, beta="uniform", noise=False)
+    log(f"[bench] workload gb_lisa: N={w.N} M={w.M} B={w.B} bins")
+    inj = torch.tensor(w.inj, device=dev)
+    d = smcx.template_spectrum(wl.GBLISA, inj, w.T_obs, w.k0, w.B)
+    prob = smcx.Problem.frequency_domain(wl.GBLISA, d, w.k0, w.T_obs, w.S, w.k_max, w.N, w.M)
+    off, th = torch.tensor(w.offsets, device=dev), torch.tensor(w.theta, device=dev)
+    beta = torch.tensor(w.beta, device=dev)
+    logl = torch.empty(w.N, dtype=torch.float64, device=dev)
+    grad = torch.empty_like(th)
+
+    def step():
+        smcx.logl_grad_batch(prob, off, th, beta, logl=logl, grad=grad)
+
+    ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
+    value = w.N / (ms * 1e-3)
+    log(f"[bench] {ms:.4f} ms/step, kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
+    flops = float(w.M) * 64 * GBLISA_FLOPS_PER_LANE
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    rl = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+          "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+          "kernel": "fd_kernel (fused forward+adjoint, FP64)", "kernel_ms": round(kern_ms, 5),
+          "work": f"{w.M} sources x 64 lanes x {GBLISA_FLOPS_PER_LANE} FP64 flops"}
+    cpu = accuracy = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        d_host = d.cpu().numpy()
+        rng = np.random.default_rng(2025)
+
+        def orc_eval(s):
+            return oracle.gblisa_logl_grad(d_host, w.k0, w.T_obs, w.S, s.offsets, s.theta, s.beta)
+
+        probe = np.sort(rng.choice(w.N, size=32, replace=False))
+        sub = _gb_subset(w, probe)
+        t0 = time.perf_counter()
+        orc_eval(sub)
+        per = (time.perf_counter() - t0) / len(probe)
+        n = int(min(w.N, max(64, args.cpu_seconds / max(per, 1e-9))))
+        idx = np.sort(rng.choice(w.N, size=n, replace=False))
+        sub = _gb_subset(w, idx)
+        t0 = time.perf_counter()
+        ref_l, ref_g = orc_eval(sub)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": n / cpu_s, "unit": "evals/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"{n} of {w.N} particles of the same workload (seeded), all {w.B} bins, "
+                         f"{cpu_s:.1f} s"}
+        log(f"[bench] cpu oracle {n} particles in {cpu_s:.1f} s")
+        out_l, out_g = logl.cpu().numpy(), grad.cpu().numpy()
+        rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
+        el = np.abs(out_l[idx] - ref_l) / np.abs(ref_l)
+        nat = np.array([w.T_obs, w.T_obs ** 2, 1, 1, 1, 1, 1, 1])
+        gr = []
+        for j, i in enumerate(idx):
+            a, b = sub.offsets[j], sub.offsets[j + 1]
+            gg, rr = out_g[rows[a:b]] / nat, ref_g[a:b] / nat
+            gr.append(np.linalg.norm(gg - rr) / max(np.linalg.norm(rr), 1e-300))
+        accuracy = {"checked_particles": n, "logl_max_rel_err": float(el.max()),
+                    "grad_max_rel_err": float(max(gr))}
+    return dict(metric="particle logL+grad evals/sec, LISA Galactic binaries (frequency domain, "
+                       "A+E, FP64)",
+                value=value, unit="evals/s", ms_per_step=ms,
+                config={"workload": "gb_lisa", "T_obs_s": w.T_obs, "bins": w.B, "N": w.N,
+                        "M": w.M, "K": f"U{{1..{w.k_max}}}", "beta": "U[0,1]",
+                        "n_injected": len(w.inj), "data": "noise-free"},
+                accuracy=accuracy, roofline=rl, cpu_baseline=cpu, dtype="f64")
+
+
+def _gb_subset(w, idx):
+    import numpy as np
+    from types import SimpleNamespace
+    K = w.K[idx]
+    off = np.zeros(len(idx) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(K)
+    rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
+    return SimpleNamespace(offsets=off, theta=w.theta[rows], beta=w.beta[idx])
+
+
 def copy_probe(args, torch):
     """Device-to-device copy of a known size, for calibrating HBM byte counters."""
     n = 1 << 26  # 64 Mi float32 = 256 MiB
@@ -448,7 +541,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "metric", "copy_probe"])
+                             "metric", "gb_lisa", "copy_probe"])
     ap.add_argument("--tiling", default="",
                     help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -472,14 +565,20 @@ def main():
     if args.workload == "copy_probe":
         copy_probe(args, torch)
         return
-    if args.workload == "smc_pulses":
+    if args.workload == "gb_lisa":
+        res = bench_gblisa(args, dev, smcx, np, torch)
+        w = None
+    elif args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
     elif args.workload == "metric":
         w = wl.make_config("pulse_batch")
     else:
         w = wl.make_config(args.workload)
-    log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    if args.workload in ("pulse_batch", "gb_grad"):
+    if w is not None:
+        log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
+    if args.workload == "gb_lisa":
+        pass
+    elif args.workload in ("pulse_batch", "gb_grad"):
         res = bench_grad(args, w, dev, smcx, np, torch)
     elif args.workload == "gb_extend":
         res = bench_extend(args, w, dev, smcx, np, torch)
@@ -500,7 +599,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": res.get("dtype", "f32+f64"),
         "data": "synthetic",
         "config": res["config"],
     }
