@@ -110,6 +110,7 @@ def _load():
         lib.oracle_gblisa_spectrum_dft.argtypes = [I64, P, D, I64, I64, I64, P]
         lib.oracle_gblisa_logl_grad.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P]
         lib.oracle_gblisa_delta.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P, P, P]
+        lib.oracle_gblisa_fisher.argtypes = [I64, I64, D, D, I, I64, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -498,3 +499,17 @@ def gblisa_delta(d, k0, T_obs, S, offsets, theta, beta, theta_birth, death_idx, 
                                        _p(offsets), _p(theta), _p(beta), _p(tb), _p(di), _p(db),
                                        _p(dd)), "gblisa_delta")
     return db, dd
+
+
+def gblisa_fisher(k0, B, T_obs, S, offsets, theta, beta=None, Ns=GB_NS):
+    """Per-source Gauss-Newton metric blocks; returns a list of (8K) x (8K) arrays."""
+    offsets, theta, beta = _i64(offsets), _f64(theta), _f64(beta)
+    N = offsets.shape[0] - 1
+    n = np.diff(offsets) * GB_P
+    fo = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(n * n, out=fo[1:])
+    F = np.empty(max(int(fo[-1]), 1))
+    _check(_load().oracle_gblisa_fisher(int(k0), int(B), float(T_obs), float(S), int(Ns), N,
+                                        _p(offsets), _p(theta), _p(beta), _p(fo), _p(F)),
+           "gblisa_fisher")
+    return [F[fo[i]:fo[i + 1]].reshape(n[i], n[i]).copy() for i in range(N)]

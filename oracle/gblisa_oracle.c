@@ -445,3 +445,48 @@ int oracle_gblisa_delta(const double* d, int64_t k0, int64_t B, double T_obs, do
   }
   return OR_OK;
 }
+
+/* Gauss-Newton metric of the frequency-domain model, per source: for every
+ * particle the (8K) x (8K) matrix whose diagonal 8 x 8 block k is
+ *   F_k = beta (4 df / S) Re sum_c sum_k conj(dh_c[k] / dtheta_a) dh_c[k] / dtheta_b
+ * over the band (the Hessian of -beta logL in that source's parameters
+ * without its residual term), and whose blocks between different sources
+ * are zero. Blocks at F + f_offsets[i], row-major; f_offsets[i+1] -
+ * f_offsets[i] must be (8 K_i)^2. */
+int oracle_gblisa_fisher(int64_t k0, int64_t B, double T_obs, double S, int Ns, int64_t N,
+                         const int64_t* offsets, const double* theta, const double* beta,
+                         const int64_t* f_offsets, double* F) {
+  if (check_population_ok(N, offsets, theta) != OR_OK || B < 0 || !(T_obs > 0) || !(S > 0) ||
+      (N > 0 && !f_offsets))
+    return OR_EINVAL;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t n = (offsets[i + 1] - offsets[i]) * GB_P;
+    if (f_offsets[i + 1] - f_offsets[i] != n * n) return OR_EINVAL;
+  }
+  if (N > 0 && f_offsets[N] > 0 && !F) return OR_EINVAL;
+  double cnorm = 4.0 / (T_obs * S);
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t K = offsets[i + 1] - offsets[i], n = K * GB_P;
+    double b = beta ? beta[i] : 1.0;
+    double* Fi = F ? F + f_offsets[i] : NULL;
+    if (n == 0) continue;
+    for (int64_t x = 0; x < n * n; ++x) Fi[x] = 0.0;
+    double* dh = malloc((size_t)(GB_P * 4 * B + 1) * sizeof(double));
+    double* junk = malloc((size_t)(4 * B + 1) * sizeof(double));
+    for (int64_t k = 0; k < K; ++k) {
+      memset(dh, 0, (size_t)(GB_P * 4 * B) * sizeof(double));
+      memset(junk, 0, (size_t)(4 * B) * sizeof(double));
+      add_source(theta + (offsets[i] + k) * GB_P, T_obs, Ns, k0, B, 1.0, junk, dh);
+      for (int pa = 0; pa < GB_P; ++pa)
+        for (int pb = 0; pb < GB_P; ++pb) {
+          double s = 0.0;
+          for (int64_t x = 0; x < 4 * B; ++x) s += dh[pa * 4 * B + x] * dh[pb * 4 * B + x];
+          Fi[(k * GB_P + pa) * n + k * GB_P + pb] = b * cnorm * s;
+        }
+    }
+    free(dh);
+    free(junk);
+  }
+  return OR_OK;
+}

@@ -194,3 +194,40 @@ def test_gradient_against_richardson_differences(orc):
         d2 = (f(h / 2) - f(-h / 2)) / h
         num[j] = (4 * d2 - d1) / 3 * np.tile(NAT, 2)[j]
     assert np.linalg.norm(gn - num) <= 1e-6 * np.linalg.norm(num), (gn, num)
+
+
+def test_metric_blocks(orc):
+    """The per-source metric equals the Hessian of -beta logL at zero residual
+    (one source, noise-free data at the injection; Richardson differences of
+    the pinned gradient), is symmetric and positive semi-definite, and for
+    several sources keeps each source's own block with zeros between them."""
+    rng = np.random.default_rng(304)
+    T, S, k0, B = YEAR, wl.GBLISA_PSD, wl.GBLISA_K0, wl.GBLISA_B
+    inj = _source(rng, 1.00021e-3)
+    inj[2] = -21.1
+    d = orc.gblisa_spectrum(inj, T, k0, B)
+    beta = np.array([0.6])
+    (F,) = orc.gblisa_fisher(k0, B, T, S, [0, 1], inj[None], beta)
+    s = NAT  # natural step of each parameter
+    H = np.zeros((8, 8))
+    for j in range(8):
+        h = 1e-4 * s[j]
+
+        def g(x):
+            t2 = inj.copy()
+            t2[j] += x
+            return orc.gblisa_logl_grad(d, k0, T, S, [0, 1], t2[None], beta)[1].reshape(-1)
+        d1 = (g(h) - g(-h)) / (2 * h)
+        d2 = (g(h / 2) - g(-h / 2)) / h
+        H[:, j] = (4 * d2 - d1) / 3
+    Fs, Hs = F * np.outer(s, s), -H * np.outer(s, s)
+    assert np.allclose(Fs, Hs, rtol=0, atol=1e-6 * np.abs(Fs).max())
+    assert np.array_equal(F, F.T)
+    dn = np.sqrt(np.diag(F))
+    assert np.linalg.eigvalsh(F / np.outer(dn, dn)).min() > -1e-9
+    # two sources: own blocks, zero coupling
+    other = _source(rng, 0.99991e-3)
+    (F2,) = orc.gblisa_fisher(k0, B, T, S, [0, 2], np.vstack([inj, other]), beta)
+    (Fo,) = orc.gblisa_fisher(k0, B, T, S, [0, 1], other[None], beta)
+    assert np.array_equal(F2[:8, :8], F) and np.array_equal(F2[8:, 8:], Fo)
+    assert np.all(F2[:8, 8:] == 0) and np.all(F2[8:, :8] == 0)
