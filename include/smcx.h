@@ -39,8 +39,9 @@
  *               Amplitudes in units of 1e-21 strain (A = 10^(log10 A + 21)).
  *               Supported: logl_batch, logl_grad_batch, delta_logl_birth_death,
  *               smcx_leapfrog, smcx_nuts_transition(_metric) and the SMC
- *               steps; not the time-domain calls (reweight_extend, the
- *               plain form, tiling, the bridge split, the metric).
+ *               steps and smcx_gauss_newton_metric (per-source blocks); not
+ *               the time-domain calls (reweight_extend, the plain form,
+ *               tiling, the bridge split).
  *
  * Layout. The population is CSR: offsets[N+1] (int64, offsets[0] = 0,
  * non-decreasing, K_i = offsets[i+1]-offsets[i]), theta[M][P] (FP64,
@@ -385,7 +386,11 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
  * With a bridge split set (smcx_set_bridge_split) it is the metric of the
  * bridge target: samples before the split enter with weight 1, later ones
  * with beta_i. beta may be NULL (1). Every sample is evaluated (no pulse
- * truncation). */
+ * truncation). For the frequency-domain model (SMCX_GBLISA) the metric is
+ * kept per source: block k is the Gauss-Newton Hessian in that source's
+ * eight parameters over its 64-bin window, computed in FP64 from the
+ * envelope derivatives by Parseval's identity, and blocks between sources
+ * are zero. */
 int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                              const double* theta, const double* beta, const int64_t* f_offsets,
                              int64_t f_size, double* F, void* hip_stream);

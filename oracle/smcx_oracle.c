@@ -54,6 +54,7 @@ static const double PI = 3.141592653589793238462643383279;
 int oracle_n_params(int model) {
   if (model == MODEL_PULSE) return 3;
   if (model == MODEL_GBSINE) return 4;
+  if (model == 2) return 8; /* the frequency-domain Galactic binaries (gblisa_oracle.c) */
   return -1;
 }
 

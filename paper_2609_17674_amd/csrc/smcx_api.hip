@@ -1143,10 +1143,17 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   g_last_error.clear();
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
-  if (p->fd) return fail(SMCX_EINVAL, "the metric is implemented for the time-domain models");
   if (N == 0) return SMCX_OK;
   if (!f_offsets) return fail(SMCX_EINVAL, "f_offsets is NULL");
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
+  if (p->fd) {
+    if ((int64_t)p->k_max * p->P > 128)
+      return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
+    smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
+    hipError_t e = smcx::launch_fd_metric(a, f_offsets, f_size, F, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "metric launch");
+    return SMCX_OK;
+  }
   if ((int64_t)p->k_max * p->P > 128)
     return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
   hipStream_t st = (hipStream_t)hip_stream;

@@ -262,6 +262,43 @@ __device__ __forceinline__ void overlap(const PopArgs& a, const Src& s, const La
   *hh = wave_sum(y);
 }
 
+// Derivatives of the envelope z_c (channel c) with respect to the eight
+// parameters at this lane's sample: dz = (da e^{i ph}) / 2 + i dphi z, with a
+// the complex amplitude and ph the heterodyned phase.
+__device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, const Env& e, int c,
+                                           double dzr[8], double dzi[8]) {
+  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+  const double fi = s.f0 + s.fd * e.tau;
+  const double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
+                          kTwoPi * fi * (-s.sb * e.doppler),
+                          kTwoPi * fi * (s.cb * kAuLight * (g.sa * s.cl - g.ca * s.sl)), 0.0, 0.0,
+                          1.0};
+  const V3 ul = {s.sb * s.v.x, s.sb * s.v.y, 0.0};
+  const V3 vl = {-s.cl, -s.sl, 0.0};
+  const double* D = c == 0 ? g.dA : g.dE;
+  const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
+  const double dPb = 2.0 * dot3(s.n, Du), dXb = 2.0 * dot3(s.n, Dv);
+  const double dPl = 2.0 * (dot3(ul, Du) - dot3(vl, Dv));
+  const double dXl = 2.0 * (dot3(ul, Dv) + dot3(vl, Du));
+  double da_r[8], da_i[8];
+  da_r[0] = da_i[0] = da_r[1] = da_i[1] = da_r[7] = da_i[7] = 0.0;
+  da_r[2] = kLn10 * e.ar[c];
+  da_i[2] = kLn10 * e.ai[c];
+  da_r[3] = (s.c2p * dPb + s.s2p * dXb) * Ap;
+  da_i[3] = -(-s.s2p * dPb + s.c2p * dXb) * Ax;
+  da_r[4] = (s.c2p * dPl + s.s2p * dXl) * Ap;
+  da_i[4] = -(-s.s2p * dPl + s.c2p * dXl) * Ax;
+  da_r[5] = 2.0 * e.Fx[c] * Ap;
+  da_i[5] = 2.0 * e.Fp[c] * Ax;
+  da_r[6] = e.Fp[c] * (-2.0 * s.A * s.ci * s.si);
+  da_i[6] = -e.Fx[c] * (2.0 * s.A * s.si);
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    dzr[p] = 0.5 * (da_r[p] * e.cph - da_i[p] * e.sph) - dphi[p] * e.zi[c];
+    dzi[p] = 0.5 * (da_r[p] * e.sph + da_i[p] * e.cph) + dphi[p] * e.zr[c];
+  }
+}
+
 struct FdItem {
   int64_t i, m0;
   int K;
@@ -365,44 +402,17 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
           wi[c] = -wi[c];
         }
       }
-      // Re(conj(w) dz) per parameter; dz = (da e^{i ph}) / 2 + i dphi z
+      // Re(conj(w) dz) per parameter
       const Env e = envelope(s, g, lane);
-      const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
-      const double fi = s.f0 + s.fd * e.tau;
-      double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
-                        kTwoPi * fi * (-s.sb * e.doppler),
-                        kTwoPi * fi * (s.cb * kAuLight * (g.sa * s.cl - g.ca * s.sl)), 0.0, 0.0,
-                        1.0};
       double gp[8];
 #pragma unroll
       for (int p = 0; p < 8; ++p) gp[p] = 0.0;
-      const V3 ul = {s.sb * s.v.x, s.sb * s.v.y, 0.0};
-      const V3 vl = {-s.cl, -s.sl, 0.0};
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const double* D = c == 0 ? g.dA : g.dE;
-        const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
-        const double dPb = 2.0 * dot3(s.n, Du), dXb = 2.0 * dot3(s.n, Dv);
-        const double dPl = 2.0 * (dot3(ul, Du) - dot3(vl, Dv));
-        const double dXl = 2.0 * (dot3(ul, Dv) + dot3(vl, Du));
-        double da_r[8], da_i[8];
-        da_r[0] = da_i[0] = da_r[1] = da_i[1] = da_r[7] = da_i[7] = 0.0;
-        da_r[2] = kLn10 * e.ar[c];
-        da_i[2] = kLn10 * e.ai[c];
-        da_r[3] = (s.c2p * dPb + s.s2p * dXb) * Ap;
-        da_i[3] = -(-s.s2p * dPb + s.c2p * dXb) * Ax;
-        da_r[4] = (s.c2p * dPl + s.s2p * dXl) * Ap;
-        da_i[4] = -(-s.s2p * dPl + s.c2p * dXl) * Ax;
-        da_r[5] = 2.0 * e.Fx[c] * Ap;
-        da_i[5] = 2.0 * e.Fp[c] * Ax;
-        da_r[6] = e.Fp[c] * (-2.0 * s.A * s.ci * s.si);
-        da_i[6] = -e.Fx[c] * (2.0 * s.A * s.si);
+        double dzr[8], dzi[8];
+        env_derivs(s, g, e, c, dzr, dzi);
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-          const double dzr = 0.5 * (da_r[p] * e.cph - da_i[p] * e.sph) - dphi[p] * e.zi[c];
-          const double dzi = 0.5 * (da_r[p] * e.sph + da_i[p] * e.cph) + dphi[p] * e.zr[c];
-          gp[p] = fma(wr[c], dzr, fma(wi[c], dzi, gp[p]));
-        }
+        for (int p = 0; p < 8; ++p) gp[p] = fma(wr[c], dzr[p], fma(wi[c], dzi[p], gp[p]));
       }
       const double gs = bc * a.fd_scale;
 #pragma unroll
@@ -416,6 +426,66 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
         if (a.p_half) a.p_out[x] = fma(he, gv, a.p_half[x]);
       }
     }
+  }
+}
+
+// Per-source Gauss-Newton metric: block k of particle i is
+//   beta (4 / (T_obs S)) Re sum_c sum_m conj(dh_c / dtheta_a) dh_c / dtheta_b
+// over the source's 64-bin window, which by Parseval's identity for the
+// 64-point DFT equals beta (4 / (T_obs S)) (T_obs / 64)^2 64 Re sum_c sum_j
+// conj(dz_c,a(t_j)) dz_c,b(t_j); blocks between sources are zero. One wave
+// per particle; 36 wave sums per source.
+__global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t* f_off, int64_t f_size,
+                                                        double* F) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= a.N) return;
+  const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
+  if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  const int K = (int)(o1 - o0), n = 8 * K;
+  const int64_t fo = f_off[i];
+  if (f_off[i + 1] - fo != (int64_t)n * n || fo < 0 || fo + (int64_t)n * n > f_size) {
+    if (lane == 0) atomicOr(a.flag, kFlagOffsets);
+    return;
+  }
+  if (n == 0) return;
+  double* Fi = F + fo;
+  for (int64_t x = lane; x < (int64_t)n * n; x += 64) {
+    const int r = (int)(x / n), c = (int)(x % n);
+    if ((r >> 3) != (c >> 3)) Fi[x] = 0.0;
+  }
+  const double b = a.beta ? a.beta[i] : 1.0;
+  const double gs = b * a.inv_sigma2 * a.fd_scale * a.fd_scale * kNs;
+  const LaneGeom g = load_geom(a.fd_table, lane);
+  const int ra = lane >> 3, rb = lane & 7;  // the block entry this lane writes
+  for (int k = 0; k < K; ++k) {
+    const Src s = make_src(a.theta + (o0 + k) * 8, a.fd_T_obs);
+    const Env e = envelope(s, g, lane);
+    double acc[36];
+#pragma unroll
+    for (int x = 0; x < 36; ++x) acc[x] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double dzr[8], dzi[8];
+      env_derivs(s, g, e, c, dzr, dzi);
+      int x = 0;
+#pragma unroll
+      for (int p = 0; p < 8; ++p)
+#pragma unroll
+        for (int q = p; q < 8; ++q, ++x) acc[x] = fma(dzr[p], dzr[q], fma(dzi[p], dzi[q], acc[x]));
+    }
+    const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+    const int want = lo * 8 - lo * (lo - 1) / 2 + (hi - lo);  // index of (lo, hi) in the upper triangle
+    double v = 0.0;
+#pragma unroll
+    for (int x = 0; x < 36; ++x) {
+      const double t = wave_sum(acc[x]);
+      v = x == want ? t : v;
+    }
+    Fi[(int64_t)(8 * k + ra) * n + 8 * k + rb] = gs * v;
   }
 }
 
@@ -465,6 +535,14 @@ hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
     case 2: return launch_fd_mode<2>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
+                            hipStream_t st) {
+  if (a.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a,
+                     f_offsets, f_size, F);
+  return hipGetLastError();
 }
 
 hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st) {

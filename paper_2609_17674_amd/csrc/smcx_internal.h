@@ -225,6 +225,8 @@ hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStrea
 // (leapfrog kick when p_half is set), 2 birth / death changes.
 hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st);
 hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st);
+hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
+                            hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,

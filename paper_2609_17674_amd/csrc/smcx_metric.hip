@@ -231,7 +231,7 @@ struct FactorArgs {
   int64_t f_size;
   const double* F;
   double* W;
-  double ridge[4];
+  double ridge[8];  // per parameter, P <= 8
   int* flag;
 };
 
@@ -327,7 +327,8 @@ hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
   a.f_size = f_size;
   a.F = F;
   a.W = W;
-  for (int p = 0; p < P && p < 4; ++p) a.ridge[p] = ridge[p];
+  if (P > 8) return hipErrorInvalidValue;
+  for (int p = 0; p < P; ++p) a.ridge[p] = ridge[p];
   a.flag = flag;
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)N), dim3(64), factor_lds_bytes(k_max * P), st, a);
   return hipGetLastError();

@@ -162,3 +162,61 @@ def test_nuts_depth_one_on_the_frequency_domain_model(lib, orc):
         # far below 1e-6 of a step's scale
         tol = 1e-12 * np.abs(ref) + 1e-6 * np.tile(scales, b - a)
         assert np.all(np.abs(q[a:b].reshape(-1) - ref) <= tol), i
+
+
+def test_metric_matches_oracle(lib, orc):
+    """Per-source Gauss-Newton blocks (both sides FP64; the GPU sums the
+    envelope derivatives over the 64 samples, the oracle the derivative
+    spectra over the band, equal by Parseval while windows lie inside it)."""
+    w = wl.make_gblisa(N=120, k_lo=0, k_hi=6, n_inj=4, beta="uniform", noise=True, seed=406)
+    say("gblisa_metric")
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    fo, F = lib.gauss_newton_metric(prob, dev(w.offsets), dev(w.theta), dev(w.beta))
+    torch.cuda.synchronize()
+    prob.device_status()
+    fo, F = fo.cpu().numpy(), F.cpu().numpy()
+    ref = orc.gblisa_fisher(w.k0, w.B, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    for i in range(w.N):
+        n = 8 * int(w.K[i])
+        if n == 0:
+            continue
+        got = F[fo[i]:fo[i + 1]].reshape(n, n)
+        dg = np.sqrt(np.diag(ref[i]))
+        assert np.all(np.abs(got - ref[i]) <= 1e-9 * np.outer(dg, dg)), i
+        mask = np.kron(np.eye(n // 8), np.ones((8, 8))) == 0
+        assert np.all(got[mask] == 0.0)
+
+
+def test_factor_with_eight_parameters(lib, orc):
+    """Blocks of the eight-parameter model that are singular in the last
+    three parameters of every source (as the metric of a face-on source is)
+    and definite only through the ridge on those parameters."""
+    say("gblisa_factor")
+    K = np.array([3, 0, 1, 5, 2])
+    off = np.concatenate([[0], np.cumsum(K)])
+    blocks = wl.spd_blocks(K * 8, seed=410, spread=3.0)
+    for b, k in zip(blocks, K):
+        for j in range(int(k)):
+            sl = slice(8 * j + 5, 8 * j + 8)
+            b[sl, :] = 0.0
+            b[:, sl] = 0.0
+    ridge = np.array([1e-3, 1e-2, 0.5, 0.7, 0.3, 1.2, 1.2, 0.3])
+    fo, Fp = wl.pack_blocks(blocks)
+    w = wl.make_gblisa(N=len(K), k_hi=int(K.max()), n_inj=1, seed=411)
+    prob = lib.Problem.frequency_domain(GBLISA, dev(w.noise), w.k0, w.T_obs, w.S, int(K.max()),
+                                        len(K), int(off[-1]))
+    W = lib.metric_factor(prob, dev(off), dev(fo), dev(Fp), ridge)
+    torch.cuda.synchronize()
+    prob.device_status()
+    Wg = W.cpu().numpy()
+    ref, status = orc.metric_factor(GBLISA, off, blocks, ridge)
+    assert np.all(status == 0)
+    for i, (blk, r) in enumerate(zip(blocks, ref)):
+        n = blk.shape[0]
+        if n == 0:
+            continue
+        g = Wg[fo[i]:fo[i + 1]].reshape(n, n)
+        D = np.sqrt(np.diag(blk) + np.tile(ridge, K[i]))
+        gd, rd = g * D, r * D
+        assert np.all(np.abs(gd - rd) <= 1e-10 * np.abs(rd).max(axis=1, keepdims=True)), i
