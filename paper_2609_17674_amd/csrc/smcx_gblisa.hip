@@ -69,6 +69,30 @@ struct Src {
   int64_t q;
 };
 
+// Source constants kept per wave between the forward and the adjoint pass
+// (the first kFdCacheK sources of a particle; later ones are recomputed).
+constexpr int kFdCacheK = 16;
+constexpr int kSrcWords = 22;
+
+__device__ __forceinline__ void src_store(double* c, const Src& s) {
+  const double v[kSrcWords] = {s.f0, s.fd, s.A, s.cb, s.sb, s.cl, s.sl, s.c2p, s.s2p, s.ci, s.si,
+                               s.cyc0, s.n.x, s.n.y, s.n.z, s.u.x, s.u.y, s.u.z, s.v.x, s.v.y,
+                               s.v.z, (double)s.q};
+#pragma unroll
+  for (int x = 0; x < kSrcWords; ++x) c[x] = v[x];
+}
+
+__device__ __forceinline__ Src src_load(const double* c) {
+  Src s;
+  s.f0 = c[0]; s.fd = c[1]; s.A = c[2]; s.cb = c[3]; s.sb = c[4]; s.cl = c[5]; s.sl = c[6];
+  s.c2p = c[7]; s.s2p = c[8]; s.ci = c[9]; s.si = c[10]; s.cyc0 = c[11];
+  s.n = {c[12], c[13], c[14]};
+  s.u = {c[15], c[16], c[17]};
+  s.v = {c[18], c[19], c[20]};
+  s.q = (int64_t)c[21];
+  return s;
+}
+
 __device__ __forceinline__ Src make_src(const double* th, double T_obs) {
   Src s;
   s.f0 = th[0];
@@ -333,12 +357,20 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
   if (a.active && !a.active[i]) return;
   const double b = a.beta ? a.beta[i] : 1.0;
   const double bc = b * a.inv_sigma2;  // beta * 4 / (T_obs S)
+  __shared__ double cache[4][kFdCacheK][kSrcWords];
+  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   const LaneGeom g = load_geom(a.fd_table, lane);
   Resid<NR> R;
   load_resid<NR>(a, lane, R);
   for (int k = 0; k < it.K; ++k) {
     const Src s = make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+    if (MODE == 1 && k < kFdCacheK && lane == 0) src_store(mine[k], s);
     subtract_source<NR>(a, s, g, lane, R, 1.0);
+  }
+  if constexpr (MODE == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if constexpr (MODE == 2) {
     if (a.theta_birth && a.dlogl_birth) {
@@ -373,7 +405,7 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bitrev6(lane);
     for (int k = 0; k < it.K; ++k) {
-      const Src s = make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+      const Src s = k < kFdCacheK ? src_load(mine[k]) : make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
       // residual window of the source, bit-reversed for the inverse FFT
       const int64_t bw = s.q - kNs / 2 + lr - a.fd_k0;  // band index this lane gathers
       const bool in = bw >= 0 && bw < a.fd_B;
