@@ -22,6 +22,9 @@ Other workloads (--workload):
                 one identity-metric run for comparison) on a 10-pulse problem
                 at N = 6000
   metric        Gauss-Newton metric of the headline population (matrix cores)
+  gb_lisa       LISA Galactic binaries in the frequency domain (A+E, FP64),
+                N = 40000, one logL+grad call per step
+  smc_gblisa    whole prior-start SMC runs on ten Galactic binaries, N = 40000
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -511,6 +514,50 @@ def bench_gblisa(args, dev, smcx, np, torch):
                 accuracy=accuracy, roofline=rl, cpu_baseline=cpu, dtype="f64")
 
 
+def bench_smc_gblisa(args, dev, smcx, np, torch):
+    """Whole prior-start SMC runs on the Galactic-binary problem at the paper's
+    settings (Sec. "LISA Galactic binaries": one year, ten noise-free
+    binaries, N = 40000 particles, K in [1, 10], alpha = 0.9, moves 0.6 / 0.2
+    / 0.2) with NUTS on the per-source Gauss-Newton mass matrix."""
+    from paper_2609_17674_amd import smc
+    from paper_2609_17674_amd import workloads as wl
+    N, k_hi = 40000, 10
+    w = wl.make_gblisa(N=16, k_lo=1, k_hi=k_hi, n_inj=10, noise=False)
+    inj = torch.tensor(w.inj, device=dev)
+    d = smcx.template_spectrum(wl.GBLISA, inj, w.T_obs, w.k0, w.B)
+    prob = smcx.Problem.frequency_domain(wl.GBLISA, d, w.k0, w.T_obs, w.S, k_hi, N, N * k_hi)
+    lo = torch.tensor(wl.GBLISA_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.GBLISA_PRIOR[:, 1].copy(), device=dev)
+    runs = []
+    for r in range(args.warmup + args.steps):
+        cfg = smc.SMCConfig(N=N, k_lo=1, k_hi=k_hi, max_iters=400, seed=300 + r, metric=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = smc.run_prior_start(prob, lo, hi, cfg)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        log(f"[bench] GB prior-start run {r}: {res.iterations} iterations, {t:.2f} s, "
+            f"K histogram {res.k_hist[-1]}, log Z {res.log_evidence:.1f}")
+        if r >= args.warmup:
+            runs.append((t, res))
+    iters = [res.iterations for _, res in runs]
+    total = sum(t for t, _ in runs)
+    grads = sum(sum(res.nuts_steps) for _, res in runs)
+    return dict(metric="particle-iterations/sec of whole prior-start SMC runs (LISA Galactic "
+                       "binaries, frequency domain)",
+                value=N * sum(iters) / total, unit="particle-iterations/s",
+                ms_per_step=1e3 * total / len(runs), dtype="f64",
+                config={"workload": "smc_gblisa", "T_obs_s": w.T_obs, "bins": w.B, "N": N,
+                        "n_injected": 10, "K_range": [1, k_hi], "alpha": 0.9,
+                        "p_moves": [0.6, 0.2, 0.2], "n_mutations": 4, "nuts_max_depth": 6,
+                        "nuts_mass_matrix": "per-source Gauss-Newton metric + prior precision, "
+                                            "eps 0.3 whitened",
+                        "iterations": iters, "seconds": [round(t, 3) for t, _ in runs],
+                        "final_K_hist": runs[-1][1].k_hist[-1],
+                        "log_evidence": [round(r.log_evidence, 2) for _, r in runs],
+                        "leapfrog_grads_per_s": grads / total})
+
+
 def _gb_subset(w, idx):
     import numpy as np
     from types import SimpleNamespace
@@ -541,7 +588,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "metric", "gb_lisa", "copy_probe"])
+                             "metric", "gb_lisa", "smc_gblisa", "copy_probe"])
     ap.add_argument("--tiling", default="",
                     help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -568,6 +615,9 @@ def main():
     if args.workload == "gb_lisa":
         res = bench_gblisa(args, dev, smcx, np, torch)
         w = None
+    elif args.workload == "smc_gblisa":
+        res = bench_smc_gblisa(args, dev, smcx, np, torch)
+        w = None
     elif args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
     elif args.workload == "metric":
@@ -576,7 +626,7 @@ def main():
         w = wl.make_config(args.workload)
     if w is not None:
         log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    if args.workload == "gb_lisa":
+    if args.workload in ("gb_lisa", "smc_gblisa"):
         pass
     elif args.workload in ("pulse_batch", "gb_grad"):
         res = bench_grad(args, w, dev, smcx, np, torch)

@@ -220,3 +220,25 @@ def test_factor_with_eight_parameters(lib, orc):
         D = np.sqrt(np.diag(blk) + np.tile(ridge, K[i]))
         gd, rd = g * D, r * D
         assert np.all(np.abs(gd - rd) <= 1e-10 * np.abs(rd).max(axis=1, keepdims=True)), i
+
+
+def test_full_size_population_on_sampled_particles(lib, orc):
+    """The benchmark's configuration (N = 40000, K ~ U{1..10}, ten noise-free
+    binaries, one year) in one launch; particles sampled for the oracle."""
+    w = wl.make_gblisa(N=40000, k_lo=1, k_hi=10, n_inj=10, beta="uniform", noise=False)
+    say("gblisa_full_size", "M", w.M)
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    l, g = lib.logl_grad_batch(prob, dev(w.offsets), dev(w.theta), dev(w.beta))
+    torch.cuda.synchronize()
+    prob.device_status()
+    l, g = l.cpu().numpy(), g.cpu().numpy()
+    rng = np.random.default_rng(407)
+    idx = np.sort(rng.choice(w.N, size=400, replace=False))
+    for i in idx:
+        a, b = w.offsets[i], w.offsets[i + 1]
+        rl, rg = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, [0, b - a], w.theta[a:b],
+                                      w.beta[i:i + 1])
+        assert abs(l[i] - rl[0]) <= 1e-9 * abs(rl[0]), i
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn), i
