@@ -433,6 +433,22 @@ int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, in
  * smcx_gauss_newton_metric follows the split as well.
  * 0 <= split <= T. */
 int smcx_set_bridge_split(smcx_problem* prob, int64_t split);
+
+/* Posterior-start bridge between two frequency-domain records (eq.
+ * reuse_bridge for the Galactic-binary model, whose bins all change when
+ * the record grows): after smcx_set_bridge_partner(prob, partner) every
+ * tempered call on prob (logl_batch, logl_grad_batch, delta_logl_birth_death,
+ * smcx_leapfrog, smcx_nuts_transition(_metric), smcx_gauss_newton_metric)
+ * evaluates
+ *   (1 - beta_i) logL_partner + beta_i logL_prob
+ * (and the matching gradients, changes and metric), where partner holds the
+ * shorter record d1 and prob the longer one d2; beta = NULL gives logL_prob.
+ * The incremental weights of this bridge are (beta - beta_prev) times
+ * logL_prob - logL_partner (two untempered logl_batch calls, one per handle).
+ * Both handles must be frequency-domain handles of the same model; the
+ * partner must outlive the setting and have no partner itself; NULL clears.
+ * The partner's data are read, its workspace is not used. */
+int smcx_set_bridge_partner(smcx_problem* prob, smcx_problem* partner);
 int smcx_get_bridge_split(smcx_problem* prob, int64_t* split);
 
 /* ---- SMC steps around the likelihood (Sec. "Sequential Monte Carlo",

@@ -192,6 +192,16 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
     a.fd_B = p->fd_B;
     a.fd_T_obs = p->fd_T_obs;
     a.fd_scale = p->fd_T_obs / 64.0;
+    if (p->partner) {
+      const smcx_problem* q = p->partner;
+      a.fd_bridge = 1;
+      a.fd2_data = q->fd_data;
+      a.fd2_table = q->fd_table;
+      a.fd2_k0 = q->fd_k0;
+      a.fd2_B = q->fd_B;
+      a.fd2_T_obs = q->fd_T_obs;
+      a.fd2_cnorm = q->inv_sigma2;
+    }
   }
   return a;
 }
@@ -251,10 +261,17 @@ void fd_table_host(double T_obs, std::vector<double>& tab) {
 // logL of a particle without components, split at the posterior-start bridge
 // sample (0 without one): the part from the split on, tempered by beta, and
 // the untempered part before it (FP64 prefix sums of d^2).
+// Under a bridge between two frequency-domain records the K = 0 value is
+// (1 - beta) E_partner + beta E_own = E_partner + beta (E_own - E_partner).
+double k0_fd(const smcx_problem* p) { return -0.5 * p->prefix[1] * p->inv_sigma2; }
 double k0_tempered(const smcx_problem* p) {
+  if (p->fd && p->partner) return k0_fd(p) - k0_fd(p->partner);
   return -0.5 * (p->prefix[p->T] - p->prefix[p->split]) * p->inv_sigma2;
 }
-double k0_untempered(const smcx_problem* p) { return -0.5 * p->prefix[p->split] * p->inv_sigma2; }
+double k0_untempered(const smcx_problem* p) {
+  if (p->fd && p->partner) return k0_fd(p->partner);
+  return -0.5 * p->prefix[p->split] * p->inv_sigma2;
+}
 
 smcx::PrepArgs prep_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
                          const double* beta, double k0, int tempered) {
@@ -916,7 +933,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
                      (uint64_t)(uintptr_t)q, (uint64_t)(uintptr_t)logl, (uint64_t)(uintptr_t)grad,
                      (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth,
                      (uint64_t)p->split, (uint64_t)(uintptr_t)W, (uint64_t)(uintptr_t)w_offsets,
-                     (uint64_t)w_size})
+                     (uint64_t)w_size, (uint64_t)(uintptr_t)p->partner})
     key = mix_key(key, v);
   uint64_t eb;
   std::memcpy(&eb, &eps, sizeof(eb));
@@ -997,6 +1014,20 @@ int smcx_set_bridge_split(smcx_problem* p, int64_t split) {
   if (split < 0 || split > p->T)
     return fail(SMCX_EINVAL, "split = %lld outside [0, T = %lld]", (long long)split, (long long)p->T);
   p->split = split;
+  return SMCX_OK;
+}
+
+int smcx_set_bridge_partner(smcx_problem* p, smcx_problem* partner) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (partner) {
+    if (!p->fd || !partner->fd)
+      return fail(SMCX_EINVAL, "a bridge partner joins two frequency-domain handles");
+    if (partner == p) return fail(SMCX_EINVAL, "a handle cannot be its own bridge partner");
+    if (partner->model != p->model) return fail(SMCX_EINVAL, "the partner has another model");
+    if (partner->partner) return fail(SMCX_EINVAL, "the partner has a bridge partner itself");
+  }
+  p->partner = partner;
   return SMCX_OK;
 }
 

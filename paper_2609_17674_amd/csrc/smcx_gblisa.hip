@@ -226,35 +226,51 @@ __device__ __forceinline__ void window_at(const double re[2], const double im[2]
   }
 }
 
+// One data set of the likelihood: the handle's own, or under a bridge
+// (eq. reuse_bridge between two records) also its partner's.
+struct FdSide {
+  const double* data;
+  const double* table;
+  int64_t k0, B;
+  double T_obs, scale, cnorm;
+};
+
+__device__ __forceinline__ FdSide own_side(const PopArgs& a) {
+  return {a.fd_data, a.fd_table, a.fd_k0, a.fd_B, a.fd_T_obs, a.fd_scale, a.inv_sigma2};
+}
+__device__ __forceinline__ FdSide partner_side(const PopArgs& a) {
+  return {a.fd2_data, a.fd2_table, a.fd2_k0, a.fd2_B, a.fd2_T_obs, a.fd2_T_obs / 64.0, a.fd2_cnorm};
+}
+
 template <int NR>
 struct Resid {
   double re[2][NR], im[2][NR];
 };
 
 template <int NR>
-__device__ __forceinline__ void load_resid(const PopArgs& a, int lane, Resid<NR>& R) {
+__device__ __forceinline__ void load_resid(const FdSide& sd, int lane, Resid<NR>& R) {
   const int Bp = kNs * NR;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int b = lane + kNs * r;
-      R.re[c][r] = a.fd_data[(c * Bp + b) * 2];
-      R.im[c][r] = a.fd_data[(c * Bp + b) * 2 + 1];
+      R.re[c][r] = sd.data[(c * Bp + b) * 2];
+      R.im[c][r] = sd.data[(c * Bp + b) * 2 + 1];
     }
 }
 
 template <int NR>
-__device__ __forceinline__ void subtract_source(const PopArgs& a, const Src& s, const LaneGeom& g,
+__device__ __forceinline__ void subtract_source(const FdSide& sd, const Src& s, const LaneGeom& g,
                                                 int lane, Resid<NR>& R, double sign) {
   double re[2], im[2];
-  window_spectrum(s, g, a.fd_table + kFdRootsOffset, a.fd_scale, lane, re, im);
+  window_spectrum(s, g, sd.table + kFdRootsOffset, sd.scale, lane, re, im);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int64_t b = lane + kNs * r;
     double vr[2], vi[2];
-    window_at(re, im, a.fd_k0 + b, s.q, vr, vi);
-    const bool live = b < a.fd_B;
+    window_at(re, im, sd.k0 + b, s.q, vr, vi);
+    const bool live = b < sd.B;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       R.re[c][r] -= live ? sign * vr[c] : 0.0;
@@ -265,17 +281,17 @@ __device__ __forceinline__ void subtract_source(const PopArgs& a, const Src& s, 
 
 // Re<R, h> and |h|^2 over the band for one source (both channels).
 template <int NR>
-__device__ __forceinline__ void overlap(const PopArgs& a, const Src& s, const LaneGeom& g, int lane,
+__device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const LaneGeom& g, int lane,
                                         const Resid<NR>& R, double* rh, double* hh) {
   double re[2], im[2];
-  window_spectrum(s, g, a.fd_table + kFdRootsOffset, a.fd_scale, lane, re, im);
+  window_spectrum(s, g, sd.table + kFdRootsOffset, sd.scale, lane, re, im);
   double x = 0.0, y = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int64_t b = lane + kNs * r;
     double vr[2], vi[2];
-    window_at(re, im, a.fd_k0 + b, s.q, vr, vi);
-    if (b < a.fd_B)
+    window_at(re, im, sd.k0 + b, s.q, vr, vi);
+    if (b < sd.B)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         x = fma(R.re[c][r], vr[c], fma(R.im[c][r], vi[c], x));
@@ -345,27 +361,22 @@ __device__ __forceinline__ bool fd_item(const PopArgs& a, int64_t rank, FdItem& 
   return true;
 }
 
-// MODE 0: logL; 1: logL and gradient (with the leapfrog kick when p_half
-// is set); 2: birth / death changes.
+// One particle on one data set, weighted by w; the first side writes the
+// outputs, a second one adds to them, and the leapfrog kick (p_half set)
+// follows the last side's gradient.
 template <int MODE, int NR>
-__global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  FdItem it;
-  if (!fd_item(a, rank, it)) return;
+__device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, const FdItem& it,
+                                            int lane, double w, bool first, bool last,
+                                            double (*mine)[kSrcWords]) {
   const int64_t i = it.i;
-  if (a.active && !a.active[i]) return;
-  const double b = a.beta ? a.beta[i] : 1.0;
-  const double bc = b * a.inv_sigma2;  // beta * 4 / (T_obs S)
-  __shared__ double cache[4][kFdCacheK][kSrcWords];
-  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
-  const LaneGeom g = load_geom(a.fd_table, lane);
+  const double wc = w * sd.cnorm;  // weight * 4 / (T_obs S)
+  const LaneGeom g = load_geom(sd.table, lane);
   Resid<NR> R;
-  load_resid<NR>(a, lane, R);
+  load_resid<NR>(sd, lane, R);
   for (int k = 0; k < it.K; ++k) {
-    const Src s = make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+    const Src s = make_src(a.theta + (it.m0 + k) * 8, sd.T_obs);
     if (MODE == 1 && k < kFdCacheK && lane == 0) src_store(mine[k], s);
-    subtract_source<NR>(a, s, g, lane, R, 1.0);
+    subtract_source<NR>(sd, s, g, lane, R, 1.0);
   }
   if constexpr (MODE == 1) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -374,19 +385,21 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
   }
   if constexpr (MODE == 2) {
     if (a.theta_birth && a.dlogl_birth) {
-      const Src s = make_src(a.theta_birth + i * 8, a.fd_T_obs);
+      const Src s = make_src(a.theta_birth + i * 8, sd.T_obs);
       double rh, hh;
-      overlap<NR>(a, s, g, lane, R, &rh, &hh);
-      if (lane == 0) a.dlogl_birth[i] = bc * (rh - 0.5 * hh);
+      overlap<NR>(sd, s, g, lane, R, &rh, &hh);
+      const double v = wc * (rh - 0.5 * hh);
+      if (lane == 0) a.dlogl_birth[i] = first ? v : a.dlogl_birth[i] + v;
     }
     if (a.death_idx && a.dlogl_death) {
       const int j = a.death_idx[i];
       if (j >= 0 && j < it.K) {
-        const Src s = make_src(a.theta + (it.m0 + j) * 8, a.fd_T_obs);
+        const Src s = make_src(a.theta + (it.m0 + j) * 8, sd.T_obs);
         double rh, hh;
-        overlap<NR>(a, s, g, lane, R, &rh, &hh);
-        if (lane == 0) a.dlogl_death[i] = -(bc * (rh + 0.5 * hh));
-      } else if (lane == 0) {
+        overlap<NR>(sd, s, g, lane, R, &rh, &hh);
+        const double v = -(wc * (rh + 0.5 * hh));
+        if (lane == 0) a.dlogl_death[i] = first ? v : a.dlogl_death[i] + v;
+      } else if (lane == 0 && first) {
         a.dlogl_death[i] = j == -1 ? 0.0 : __builtin_nan("");
         if (j != -1) atomicOr(a.flag, kFlagDeath);
       }
@@ -399,16 +412,19 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) ss = fma(R.re[c][r], R.re[c][r], fma(R.im[c][r], R.im[c][r], ss));
   ss = wave_sum(ss);
-  if (lane == 0 && a.logl) a.logl[i] = b * (-0.5 * a.inv_sigma2 * ss);
+  if (lane == 0 && a.logl) {
+    const double v = -0.5 * wc * ss;
+    a.logl[i] = first ? v : a.logl[i] + v;
+  }
   if constexpr (MODE == 1) {
-    const double* roots = a.fd_table + kFdRootsOffset;
+    const double* roots = sd.table + kFdRootsOffset;
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bitrev6(lane);
     for (int k = 0; k < it.K; ++k) {
-      const Src s = k < kFdCacheK ? src_load(mine[k]) : make_src(a.theta + (it.m0 + k) * 8, a.fd_T_obs);
+      const Src s = k < kFdCacheK ? src_load(mine[k]) : make_src(a.theta + (it.m0 + k) * 8, sd.T_obs);
       // residual window of the source, bit-reversed for the inverse FFT
-      const int64_t bw = s.q - kNs / 2 + lr - a.fd_k0;  // band index this lane gathers
-      const bool in = bw >= 0 && bw < a.fd_B;
+      const int64_t bw = s.q - kNs / 2 + lr - sd.k0;  // band index this lane gathers
+      const bool in = bw >= 0 && bw < sd.B;
       const int src = (int)(bw & (kNs - 1));
       const int reg = in ? (int)(bw >> 6) : 0;
       double wr[2], wi[2];
@@ -446,7 +462,7 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
 #pragma unroll
         for (int p = 0; p < 8; ++p) gp[p] = fma(wr[c], dzr[p], fma(wi[c], dzi[p], gp[p]));
       }
-      const double gs = bc * a.fd_scale;
+      const double gs = wc * sd.scale;
 #pragma unroll
       for (int p = 0; p < 8; ++p) gp[p] = wave_sum(gp[p]) * gs;
       if (lane < 8) {
@@ -454,10 +470,33 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
 #pragma unroll
         for (int p = 1; p < 8; ++p) gv = lane == p ? gp[p] : gv;
         const int64_t x = (it.m0 + k) * 8 + lane;
+        if (!first && a.grad) gv += a.grad[x];
         if (a.grad) a.grad[x] = gv;
-        if (a.p_half) a.p_out[x] = fma(he, gv, a.p_half[x]);
+        if (last && a.p_half) a.p_out[x] = fma(he, gv, a.p_half[x]);
       }
     }
+  }
+}
+
+// MODE 0: logL; 1: logL and gradient (with the leapfrog kick when p_half
+// is set); 2: birth / death changes. Under a bridge (fd_bridge) the target
+// is (1 - beta) logL_partner + beta logL_own, so each particle runs on both
+// data sets.
+template <int MODE, int NR>
+__global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  FdItem it;
+  if (!fd_item(a, rank, it)) return;
+  if (a.active && !a.active[it.i]) return;
+  const double b = a.beta ? a.beta[it.i] : 1.0;
+  __shared__ double cache[4][kFdCacheK][kSrcWords];
+  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
+  if (a.fd_bridge) {
+    fd_particle<MODE, NR>(a, partner_side(a), it, lane, 1.0 - b, true, false, mine);
+    fd_particle<MODE, NR>(a, own_side(a), it, lane, b, false, true, mine);
+  } else {
+    fd_particle<MODE, NR>(a, own_side(a), it, lane, b, true, true, mine);
   }
 }
 
@@ -490,11 +529,14 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
     if ((r >> 3) != (c >> 3)) Fi[x] = 0.0;
   }
   const double b = a.beta ? a.beta[i] : 1.0;
-  const double gs = b * a.inv_sigma2 * a.fd_scale * a.fd_scale * kNs;
-  const LaneGeom g = load_geom(a.fd_table, lane);
   const int ra = lane >> 3, rb = lane & 7;  // the block entry this lane writes
+  for (int side = a.fd_bridge ? 0 : 1; side < 2; ++side) {
+  const FdSide sd = side == 0 ? partner_side(a) : own_side(a);
+  const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs;
+  const bool first = side == 0 || !a.fd_bridge;
+  const LaneGeom g = load_geom(sd.table, lane);
   for (int k = 0; k < K; ++k) {
-    const Src s = make_src(a.theta + (o0 + k) * 8, a.fd_T_obs);
+    const Src s = make_src(a.theta + (o0 + k) * 8, sd.T_obs);
     const Env e = envelope(s, g, lane);
     double acc[36];
 #pragma unroll
@@ -517,7 +559,9 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
       const double t = wave_sum(acc[x]);
       v = x == want ? t : v;
     }
-    Fi[(int64_t)(8 * k + ra) * n + 8 * k + rb] = gs * v;
+    double* dst = Fi + (int64_t)(8 * k + ra) * n + 8 * k + rb;
+    *dst = first ? gs * v : *dst + gs * v;
+  }
   }
 }
 
@@ -532,7 +576,7 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
     for (int r = 0; r < 4; ++r) R.re[c][r] = R.im[c][r] = 0.0;
   for (int64_t k = 0; k < K; ++k) {
     const Src s = make_src(a.theta + k * 8, a.fd_T_obs);
-    subtract_source<4>(a, s, g, lane, R, -1.0);
+    subtract_source<4>(own_side(a), s, g, lane, R, -1.0);
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c)

@@ -99,6 +99,12 @@ struct PopArgs {
   int64_t fd_B;            // bins in the band
   double fd_T_obs;         // observation time [s]
   double fd_scale;         // T_obs / 64
+  // bridge between two records (eq. reuse_bridge): the partner handle's data
+  int fd_bridge;           // 1: target (1 - beta) logL_partner + beta logL_own
+  const double* fd2_data;
+  const double* fd2_table;
+  int64_t fd2_k0, fd2_B;
+  double fd2_T_obs, fd2_cnorm;
 };
 // Layout of fd_table: [64][kFdTableStride] (tensors of A, E; cos, sin of
 // the orbital phase; t_j), then [64][2] roots exp(-2 pi i k / 64).

@@ -32,6 +32,7 @@ struct smcx_problem {
   double fd_T_obs = 0, fd_S = 0;
   double* fd_data = nullptr;   // [2][Bp][2], Bp = 128 or 256, zero past B
   double* fd_table = nullptr;  // kFdTableSize doubles
+  smcx_problem* partner = nullptr;  // bridge partner (smcx_set_bridge_partner), or none
   int max_nch = 0;       // capacity of part (chunks per particle)
   int max_nch_grad = 0;  // capacity of part_g
   int32_t* order = nullptr;

@@ -26,7 +26,10 @@ The posterior-start mode (``run_posterior_start``) starts instead from a
 population sampled on the first `split` samples of the data and follows the
 bridge of eq. reuse_bridge: the problem's bridge split makes every tempered
 call evaluate logL[0, split) + beta logL[split, T), and the incremental
-weights use the untempered log-likelihood of the new samples only.
+weights use the untempered log-likelihood of the new samples only. For the
+frequency-domain Galactic binaries, whose bins all change when the record
+grows, ``run_bridge_start`` bridges two handles instead:
+(1 - beta) logL_short + beta logL_long.
 
 All arithmetic runs in the library's kernels. This module draws the random
 inputs on the device (a seeded torch generator) and sequences the calls; it
@@ -122,6 +125,28 @@ def run_posterior_start(prob: smcx.Problem, split: int, offsets: torch.Tensor,
                     on_iteration)
     finally:
         prob.set_bridge_split(0)
+
+
+def run_bridge_start(prob: smcx.Problem, partner: smcx.Problem, offsets: torch.Tensor,
+                     theta: torch.Tensor, prior_lo: torch.Tensor, prior_hi: torch.Tensor,
+                     cfg: SMCConfig, on_iteration: Optional[Callable[[int, dict], None]] = None
+                     ) -> SMCResult:
+    """Posterior-start across two frequency-domain records (eq. reuse_bridge):
+    `offsets`, `theta` sample the posterior on the shorter record held by
+    `partner`; the run follows (1 - beta) logL_partner + beta logL_prob from
+    beta = 0 to 1, with incremental weights from logL_prob - logL_partner. The
+    handles' bridge is set for the run and cleared afterwards."""
+    _check(prob, cfg)
+    if offsets.numel() - 1 != cfg.N:
+        raise ValueError("the starting population must have cfg.N particles")
+    gen = _generator(prior_lo.device, cfg.seed)
+    prob.set_bridge_partner(partner)
+    try:
+        return _run(prob, offsets, theta.contiguous(), prior_lo, prior_hi, cfg, gen,
+                    lambda o, t: smcx.logl_batch(prob, o, t) - smcx.logl_batch(partner, o, t),
+                    on_iteration)
+    finally:
+        prob.set_bridge_partner(None)
 
 
 def _check(prob: smcx.Problem, cfg: SMCConfig) -> None:

@@ -87,6 +87,8 @@ def load_library():
     lib.smcx_set_bridge_split.restype = ctypes.c_int
     lib.smcx_get_bridge_split.argtypes = [P, ctypes.POINTER(I64)]
     lib.smcx_get_bridge_split.restype = ctypes.c_int
+    lib.smcx_set_bridge_partner.argtypes = [P, P]
+    lib.smcx_set_bridge_partner.restype = ctypes.c_int
     lib.smcx_profile_begin.argtypes = [P, I32]
     lib.smcx_profile_begin.restype = ctypes.c_int
     lib.smcx_profile_end.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -221,6 +223,14 @@ class Problem:
         """Samples before `split` enter every tempered call untempered (the
         posterior-start bridge); 0 restores the prior bridge."""
         _check(load_library().smcx_set_bridge_split(self.handle, int(split)))
+
+    def set_bridge_partner(self, partner: Optional["Problem"]) -> None:
+        """Bridge between two frequency-domain records (smcx_set_bridge_partner):
+        tempered calls on this handle evaluate (1 - beta) logL_partner + beta
+        logL_self. None clears it."""
+        _check(load_library().smcx_set_bridge_partner(self.handle,
+                                                       partner.handle if partner else None))
+        self._partner = partner
 
     def get_bridge_split(self) -> int:
         v = ctypes.c_int64()

@@ -349,3 +349,13 @@ def make_gblisa(N: int = 40000, k_lo: int = 1, k_hi: int = 10, n_inj: int = 10,
                                   -1).astype(np.int32)
     return GBLisaWorkload(T_obs=GBLISA_T_OBS, k0=GBLISA_K0, B=GBLISA_B, S=GBLISA_PSD, inj=inj,
                           noise=nz, offsets=offsets, theta=theta, beta=b, k_max=k_hi, extra=extra)
+
+
+def gblisa_band(T_obs: float, B: int = GBLISA_B):
+    """First bin of a band of B bins that holds the windows (carrier bin +-32)
+    of every f0 of the prior box for a record of length T_obs."""
+    lo = int(np.floor(GBLISA_PRIOR[0, 0] * T_obs)) - 32
+    hi = int(np.floor(GBLISA_PRIOR[0, 1] * T_obs)) + 32
+    if hi - lo > B:
+        raise ValueError("the band is too narrow for this record length")
+    return lo - (B - (hi - lo)) // 2

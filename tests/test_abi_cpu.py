@@ -67,6 +67,8 @@ def test_null_handle_rejected_before_launch(smcx):
     rc = lib.smcx_problem_create_fd(1, ctypes.c_void_p(0x1000), 0, 128, 3e7, 1.0, 4, 4, 16, None,
                                     ctypes.byref(out))
     assert rc == smcx.SMCX_EINVAL and "frequency-domain" in smcx.last_error()
+    rc = lib.smcx_set_bridge_partner(None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
     rc = lib.smcx_template_spectrum(2, 1, None, 3e7, 0, 128, None, None)
     assert rc == smcx.SMCX_EINVAL
     rc = lib.smcx_metric_factor(None, 4, None, 0, None, 0, None, None, None, None)

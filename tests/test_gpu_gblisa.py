@@ -242,3 +242,64 @@ def test_full_size_population_on_sampled_particles(lib, orc):
         assert abs(l[i] - rl[0]) <= 1e-9 * abs(rl[0]), i
         gn, rn = (g[a:b] / NAT).reshape(-1), (rg / NAT).reshape(-1)
         assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn), i
+
+
+def test_bridge_between_two_records(lib, orc):
+    """Eq. reuse_bridge between a six-month and a twelve-month record: every
+    tempered call evaluates (1 - beta) logL_6 + beta logL_12 (gradient,
+    birth/death and metric alike); clearing the partner restores the
+    twelve-month handle bit for bit."""
+    w = wl.make_gblisa(N=150, k_lo=0, k_hi=6, n_inj=4, beta="uniform", noise=False, seed=420)
+    say("gblisa_bridge")
+    T2, T1 = w.T_obs, w.T_obs / 2
+    k1 = wl.gblisa_band(T1)
+    d2 = orc.gblisa_spectrum(w.inj, T2, w.k0, w.B)
+    d1 = orc.gblisa_spectrum(w.inj, T1, k1, w.B)
+    p2 = _problem(lib, w, d2)
+    p1 = lib.Problem.frequency_domain(GBLISA, dev(d1), k1, T1, w.S, w.k_max, w.N, max(w.M, 1))
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    plain_l, plain_g = lib.logl_grad_batch(p2, off, th, be)
+    p2.set_bridge_partner(p1)
+    l, g = lib.logl_grad_batch(p2, off, th, be)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(p2, off, th, be, dev(tb), dev(di))
+    fo, F = lib.gauss_newton_metric(p2, off, th, be)
+    torch.cuda.synchronize()
+    p2.device_status()
+    l, g, db, dd = (x.cpu().numpy() for x in (l, g, db, dd))
+    fo, F = fo.cpu().numpy(), F.cpu().numpy()
+    b = w.beta
+    r1l, r1g = orc.gblisa_logl_grad(d1, k1, T1, w.S, w.offsets, w.theta, np.ones(w.N))
+    r2l, r2g = orc.gblisa_logl_grad(d2, w.k0, T2, w.S, w.offsets, w.theta, np.ones(w.N))
+    rl = (1 - b) * r1l + b * r2l
+    assert np.all(np.abs(l - rl) <= 1e-9 * (np.abs(r1l) + np.abs(r2l)))
+    rows = np.repeat(np.arange(w.N), w.K)
+    rg = (1 - b[rows])[:, None] * r1g + b[rows][:, None] * r2g
+    for i in range(w.N):
+        a, c = w.offsets[i], w.offsets[i + 1]
+        if a == c:
+            continue
+        scale = np.linalg.norm((np.abs(r1g[a:c]) + np.abs(r2g[a:c])) / NAT)
+        assert np.linalg.norm((g[a:c] - rg[a:c]) / NAT) <= 1e-7 * scale, i
+    b1, dd1 = orc.gblisa_delta(d1, k1, T1, w.S, w.offsets, w.theta, np.ones(w.N), tb, di)
+    b2, dd2 = orc.gblisa_delta(d2, w.k0, T2, w.S, w.offsets, w.theta, np.ones(w.N), tb, di)
+    sc = np.abs(b1) + np.abs(b2) + np.abs(dd1) + np.abs(dd2) + 1.0
+    assert np.all(np.abs(db - ((1 - b) * b1 + b * b2)) <= 1e-9 * sc)
+    assert np.all(np.abs(dd - ((1 - b) * dd1 + b * dd2)) <= 1e-9 * sc)
+    F1 = orc.gblisa_fisher(k1, w.B, T1, w.S, w.offsets, w.theta, np.ones(w.N))
+    F2 = orc.gblisa_fisher(w.k0, w.B, T2, w.S, w.offsets, w.theta, np.ones(w.N))
+    for i in range(w.N):
+        n = 8 * int(w.K[i])
+        if n == 0:
+            continue
+        ref = (1 - b[i]) * F1[i] + b[i] * F2[i]
+        dg = np.sqrt(np.diag(F1[i]) + np.diag(F2[i]))
+        got = F[fo[i]:fo[i + 1]].reshape(n, n)
+        assert np.all(np.abs(got - ref) <= 1e-9 * np.outer(dg, dg)), i
+    # clearing restores the handle
+    p2.set_bridge_partner(None)
+    l3, g3 = lib.logl_grad_batch(p2, off, th, be)
+    torch.cuda.synchronize()
+    assert torch.equal(l3, plain_l) and torch.equal(g3, plain_g)
+    with pytest.raises(lib.SmcxError, match="own"):
+        p2.set_bridge_partner(p2)
