@@ -25,6 +25,8 @@ Other workloads (--workload):
   gb_lisa       LISA Galactic binaries in the frequency domain (A+E, FP64),
                 N = 40000, one logL+grad call per step
   smc_gblisa    whole prior-start SMC runs on ten Galactic binaries, N = 40000
+  gb_durations  the Galactic-binary study over record lengths (3..12 months):
+                prior-start and bridged posterior-start runs at each length
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -558,6 +560,59 @@ def bench_smc_gblisa(args, dev, smcx, np, torch):
                         "leapfrog_grads_per_s": grads / total})
 
 
+def bench_gb_durations(args, dev, smcx, np, torch):
+    """The paper's Galactic-binary study over record lengths (Sec. "LISA
+    Galactic binaries": from three months to a year in steps of one month,
+    N = 40000, ten noise-free binaries): at each length a prior-start run, and
+    a posterior-start run bridged (eq. reuse_bridge) from the previous
+    length's final population. Reports SMC iterations and seconds of both."""
+    from paper_2609_17674_amd import smc
+    from paper_2609_17674_amd import workloads as wl
+    N, k_hi = args.gb_n, 10
+    w = wl.make_gblisa(N=16, k_lo=1, k_hi=k_hi, n_inj=10, noise=False)
+    inj = torch.tensor(w.inj, device=dev)
+    lo = torch.tensor(wl.GBLISA_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.GBLISA_PRIOR[:, 1].copy(), device=dev)
+    rows, prev, total_t, total_pi = [], None, 0.0, 0
+    for m in range(3, 13):
+        T = w.T_obs * m / 12.0
+        k0 = wl.gblisa_band(T)
+        d = smcx.template_spectrum(wl.GBLISA, inj, T, k0, w.B)
+        prob = smcx.Problem.frequency_domain(wl.GBLISA, d, k0, T, w.S, k_hi, N, N * k_hi)
+        cfg = dict(N=N, k_lo=1, k_hi=k_hi, max_iters=400, metric=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = smc.run_prior_start(prob, lo, hi, smc.SMCConfig(seed=400 + m, **cfg))
+        torch.cuda.synchronize()
+        t_pr = time.perf_counter() - t0
+        row = {"months": m, "prior_start": {"iterations": pr.iterations, "seconds": round(t_pr, 3),
+                                            "K_mode": int(np.argmax(pr.k_hist[-1]))}}
+        total_t += t_pr
+        total_pi += N * pr.iterations
+        if prev is not None:
+            pprob, pres = prev
+            t0 = time.perf_counter()
+            po = smc.run_bridge_start(prob, pprob, pres.offsets, pres.theta, lo, hi,
+                                      smc.SMCConfig(seed=500 + m, **cfg))
+            torch.cuda.synchronize()
+            t_po = time.perf_counter() - t0
+            row["posterior_start"] = {"iterations": po.iterations, "seconds": round(t_po, 3),
+                                      "K_mode": int(np.argmax(po.k_hist[-1]))}
+            total_t += t_po
+            total_pi += N * po.iterations
+            prev = (prob, po)
+        else:
+            prev = (prob, pr)
+        log(f"[bench] {m} months: {row}")
+        rows.append(row)
+    return dict(metric="particle-iterations/sec of the Galactic-binary duration study "
+                       "(prior-start and posterior-start SMC, 3..12 months)",
+                value=total_pi / total_t, unit="particle-iterations/s",
+                ms_per_step=1e3 * total_t, dtype="f64",
+                config={"workload": "gb_durations", "N": N, "n_injected": 10,
+                        "K_range": [1, k_hi], "bins": w.B, "runs": rows})
+
+
 def _gb_subset(w, idx):
     import numpy as np
     from types import SimpleNamespace
@@ -588,7 +643,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "metric", "gb_lisa", "smc_gblisa", "copy_probe"])
+                             "metric", "gb_lisa", "smc_gblisa", "gb_durations", "copy_probe"])
+    ap.add_argument("--gb-n", type=int, default=40000, help="particles of the gb_durations study")
     ap.add_argument("--tiling", default="",
                     help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -618,6 +674,9 @@ def main():
     elif args.workload == "smc_gblisa":
         res = bench_smc_gblisa(args, dev, smcx, np, torch)
         w = None
+    elif args.workload == "gb_durations":
+        res = bench_gb_durations(args, dev, smcx, np, torch)
+        w = None
     elif args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
     elif args.workload == "metric":
@@ -626,7 +685,7 @@ def main():
         w = wl.make_config(args.workload)
     if w is not None:
         log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    if args.workload in ("gb_lisa", "smc_gblisa"):
+    if args.workload in ("gb_lisa", "smc_gblisa", "gb_durations"):
         pass
     elif args.workload in ("pulse_batch", "gb_grad"):
         res = bench_grad(args, w, dev, smcx, np, torch)
