@@ -409,10 +409,14 @@ int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offse
  * blocks beyond f_size skip the particle and raise a flag. One workgroup per
  * particle keeps its triangle in LDS: needs k_max P <= 128 and
  * (k_max P)(k_max P + 1)/2 doubles of LDS per workgroup (SMCX_EINVAL
- * otherwise). Capture-safe: one launch, no allocation. */
+ * otherwise). block = 0 factors the whole matrix; block = b (dividing P)
+ * factors its block-diagonal part in b x b blocks and writes zeros between
+ * them -- exact when F is block-diagonal, as the frequency-domain model's
+ * per-source metric is with b = 8 -- using b (b + 1)/2 doubles of LDS.
+ * Capture-safe: one launch, no allocation. */
 int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                        const int64_t* f_offsets, int64_t f_size, const double* F,
-                       const double* ridge, double* W, void* hip_stream);
+                       const double* ridge, int32_t block, double* W, void* hip_stream);
 
 /* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
  * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first

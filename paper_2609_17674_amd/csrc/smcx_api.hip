@@ -1197,7 +1197,7 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
 
 int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
                        const int64_t* f_offsets, int64_t f_size, const double* F,
-                       const double* ridge, double* W, void* hip_stream) {
+                       const double* ridge, int32_t block, double* W, void* hip_stream) {
   g_last_error.clear();
   int rc = check_pop(p, N, offsets, M, F ? F : W);  // theta is not read: only the sizes matter
   if (rc) return rc;
@@ -1211,12 +1211,14 @@ int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64
   const int nmax = p->k_max * p->P;
   if (nmax > smcx::kNutsMetricMax)
     return fail(SMCX_EINVAL, "the metric factor supports k_max * P <= %d", smcx::kNutsMetricMax);
-  if ((int64_t)smcx::factor_lds_bytes(nmax) > (int64_t)p->lds_max)
+  if (block < 0 || (block > 0 && p->P % block != 0))
+    return fail(SMCX_EINVAL, "block = %d must be 0 or divide P = %d", block, p->P);
+  if ((int64_t)smcx::factor_lds_bytes(block > 0 ? block : nmax) > (int64_t)p->lds_max)
     return fail(SMCX_EINVAL, "k_max * P = %d needs %zu bytes of LDS per workgroup; the device has %d",
                 nmax, smcx::factor_lds_bytes(nmax), p->lds_max);
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_metric_factor(p->P, N, M, p->k_max, offsets, f_offsets, f_size, F,
-                                            ridge, W, p->flag, st);
+                                            ridge, block, W, p->flag, st);
   if (e != hipSuccess) return hip_fail(e, "metric factor launch");
   return SMCX_OK;
 }

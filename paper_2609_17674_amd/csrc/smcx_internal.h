@@ -207,8 +207,8 @@ hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, doub
 // a host array of P values; LDS bytes of one workgroup for k_max * P = nmax.
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
                                 const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
-                                const double* F, const double* ridge, double* W, int* flag,
-                                hipStream_t st);
+                                const double* F, const double* ridge, int block, double* W,
+                                int* flag, hipStream_t st);
 size_t factor_lds_bytes(int nmax);
 
 // SMC steps (smcx_smc.hip).

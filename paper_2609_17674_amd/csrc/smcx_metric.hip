@@ -232,10 +232,65 @@ struct FactorArgs {
   const double* F;
   double* W;
   double ridge[8];  // per parameter, P <= 8
+  int block;        // 0: the whole block; b: its block-diagonal part in b x b blocks
   int* flag;
 };
 
 __device__ __forceinline__ int tri(int r, int c) { return r * (r + 1) / 2 + c; }
+
+// Factor of the diagonal block [o, o + m) of particle block Fi (n x n), its
+// W written into Wi at the same place; L is the LDS triangle (m (m+1)/2
+// doubles). Returns false (in every lane) if a pivot is not > 0.
+__device__ bool factor_block(const FactorArgs& a, const double* Fi, double* Wi, int n, int o, int m,
+                             double* L, int lane) {
+  for (int r = 0; r < m; ++r)
+    for (int c = lane; c <= r; c += 64)
+      L[tri(r, c)] = Fi[(int64_t)(o + r) * n + o + c] + (r == c ? a.ridge[(o + c) % a.P] : 0.0);
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    const double d = L[tri(j, j)];
+    if (!(d > 0.0)) {  // the same value in every lane: a uniform exit
+      __syncthreads();
+      return false;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    for (int r = j + 1 + lane; r < m; r += 64) L[tri(r, j)] = L[tri(r, j)] / ljj;
+    if (lane == 0) L[tri(j, j)] = ljj;
+    __syncthreads();
+    for (int r = j + 1 + lane; r < m; r += 64) {
+      const double lrj = L[tri(r, j)];
+      for (int c = j + 1; c <= r; ++c) L[tri(r, c)] = fma(-lrj, L[tri(c, j)], L[tri(r, c)]);
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const double ljj = L[tri(j, j)];
+    double acc[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = j + 1 + lane + 64 * t;
+      double s = 0.0;
+      if (r < m)
+        for (int k = j + 1; k <= r; ++k) s = fma(L[tri(r, k)], L[tri(k, j)], s);
+      acc[t] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int r = j + 1 + lane + 64 * t;
+      if (r < m) L[tri(r, j)] = -acc[t] / ljj;
+    }
+    if (lane == 0) L[tri(j, j)] = 1.0 / ljj;
+    __syncthreads();
+  }
+  for (int e = lane; e < m * m; e += 64) {
+    const int r = e / m, c = e % m;
+    Wi[(int64_t)(o + r) * n + o + c] = c <= r ? L[tri(r, c)] : 0.0;
+  }
+  __syncthreads();  // L is reused by the next block
+  return true;
+}
 
 __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
   extern __shared__ double L[];
@@ -256,56 +311,22 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
   if (n == 0) return;
   const double* Fi = a.F + fo;
   double* Wi = a.W + fo;
-  for (int r = 0; r < n; ++r)
-    for (int c = lane; c <= r; c += 64)
-      L[tri(r, c)] = Fi[(int64_t)r * n + c] + (r == c ? a.ridge[c % a.P] : 0.0);
-  __syncthreads();
   bool ok = true;
-  for (int j = 0; j < n; ++j) {
-    const double d = L[tri(j, j)];
-    if (!(d > 0.0)) {  // the same value in every lane: a uniform exit
-      ok = false;
-      break;
-    }
-    const double ljj = sqrt(d);
-    __syncthreads();
-    for (int r = j + 1 + lane; r < n; r += 64) L[tri(r, j)] = L[tri(r, j)] / ljj;
-    if (lane == 0) L[tri(j, j)] = ljj;
-    __syncthreads();
-    for (int r = j + 1 + lane; r < n; r += 64) {
-      const double lrj = L[tri(r, j)];
-      for (int c = j + 1; c <= r; ++c) L[tri(r, c)] = fma(-lrj, L[tri(c, j)], L[tri(r, c)]);
-    }
-    __syncthreads();
+  if (a.block == 0) {
+    ok = factor_block(a, Fi, Wi, n, 0, n, L, lane);
+  } else {
+    // block-diagonal part only: the blocks between diagonal blocks are zero
+    // in W (when W is F itself they are overwritten after every read)
+    for (int o = 0; o < n && ok; o += a.block) ok = factor_block(a, Fi, Wi, n, o, a.block, L, lane);
+    if (ok)
+      for (int64_t e = lane; e < (int64_t)n * n; e += 64) {
+        const int r = (int)(e / n), c = (int)(e % n);
+        if (r / a.block != c / a.block) Wi[e] = 0.0;
+      }
   }
   if (!ok) {
     if (lane == 0) atomicOr(a.flag, kFlagNotPD);
     for (int64_t e = lane; e < (int64_t)n * n; e += 64) Wi[e] = __builtin_nan("");
-    return;
-  }
-  for (int j = n - 1; j >= 0; --j) {
-    const double ljj = L[tri(j, j)];
-    double acc[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int r = j + 1 + lane + 64 * t;
-      double s = 0.0;
-      if (r < n)
-        for (int k = j + 1; k <= r; ++k) s = fma(L[tri(r, k)], L[tri(k, j)], s);
-      acc[t] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int r = j + 1 + lane + 64 * t;
-      if (r < n) L[tri(r, j)] = -acc[t] / ljj;
-    }
-    if (lane == 0) L[tri(j, j)] = 1.0 / ljj;
-    __syncthreads();
-  }
-  for (int64_t e = lane; e < (int64_t)n * n; e += 64) {
-    const int r = (int)(e / n), c = (int)(e % n);
-    Wi[e] = c <= r ? L[tri(r, c)] : 0.0;
   }
 }
 
@@ -315,8 +336,8 @@ size_t factor_lds_bytes(int nmax) { return (size_t)nmax * (nmax + 1) / 2 * sizeo
 
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
                                 const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
-                                const double* F, const double* ridge, double* W, int* flag,
-                                hipStream_t st) {
+                                const double* F, const double* ridge, int block, double* W,
+                                int* flag, hipStream_t st) {
   FactorArgs a{};
   a.P = P;
   a.N = N;
@@ -330,7 +351,9 @@ hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
   if (P > 8) return hipErrorInvalidValue;
   for (int p = 0; p < P; ++p) a.ridge[p] = ridge[p];
   a.flag = flag;
-  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)N), dim3(64), factor_lds_bytes(k_max * P), st, a);
+  a.block = block;
+  hipLaunchKernelGGL(factor_kernel, dim3((unsigned)N), dim3(64),
+                     factor_lds_bytes(block > 0 ? block : k_max * P), st, a);
   return hipGetLastError();
 }
 

@@ -218,7 +218,9 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                         fbuf = torch.empty(size + size // 4, **f64)
                     _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
                                                     out=fbuf[:size])
-                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
+                    # the frequency-domain model's metric is block-diagonal per source
+                    blk = prob.P if prob.model == smcx.GBLISA else 0
+                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M, block=blk))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
                                                 ul, ut, lo, hi, mask=nuts.to(torch.uint8),
                                                 metric=metric)

@@ -64,7 +64,7 @@ def load_library():
                                  P, I32, P],
         "smcx_next_beta": [P, I64, P, P, D, D, P, P, P, P, P],
         "smcx_gauss_newton_metric": [P, I64, P, I64, P, P, P, I64, P, P],
-        "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, P, P],
+        "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, I32, P, P],
         "smcx_nuts_transition_metric": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, I64, P,
                                         P, P, P, P, P, P, I32, P],
         "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
@@ -534,9 +534,11 @@ class LogLGrad(torch.autograd.Function):
         return grad * rows.unsqueeze(1), None, None, None
 
 
-def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None, stream=None):
+def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None, block=0,
+                  stream=None):
     """Factor W = L^{-1} of F + diag(ridge) for every particle (smcx_metric_factor):
-    ridge is a sequence of P values >= 0; out may be F itself (in place).
+    ridge is a sequence of P values >= 0; out may be F itself (in place);
+    block = b > 0 factors the block-diagonal part in b x b blocks.
     Returns W with the blocks of f_offsets (zeros above each diagonal)."""
     offsets = _dev(offsets, torch.int64, "offsets")
     N = offsets.numel() - 1
@@ -553,8 +555,8 @@ def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None,
         M = int(offsets[-1]) if N > 0 else 0
     _check(load_library().smcx_metric_factor(prob.handle, N, _ptr(offsets), int(M), _ptr(f_offsets),
                                              min(F.numel(), out.numel()), _ptr(F),
-                                             ctypes.cast(rarr, ctypes.c_void_p), _ptr(out),
-                                             _stream(stream)))
+                                             ctypes.cast(rarr, ctypes.c_void_p), int(block),
+                                             _ptr(out), _stream(stream)))
     return out
 
 

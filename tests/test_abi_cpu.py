@@ -71,7 +71,7 @@ def test_null_handle_rejected_before_launch(smcx):
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
     rc = lib.smcx_template_spectrum(2, 1, None, 3e7, 0, 128, None, None)
     assert rc == smcx.SMCX_EINVAL
-    rc = lib.smcx_metric_factor(None, 4, None, 0, None, 0, None, None, None, None)
+    rc = lib.smcx_metric_factor(None, 4, None, 0, None, 0, None, None, 0, None, None)
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
     rc = lib.smcx_nuts_transition_metric(None, 4, None, 0, None, 0.1, 2, None, None, None, None,
                                          None, None, None, None, 0, None, None, None, None, None,

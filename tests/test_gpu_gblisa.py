@@ -303,3 +303,52 @@ def test_bridge_between_two_records(lib, orc):
     assert torch.equal(l3, plain_l) and torch.equal(g3, plain_g)
     with pytest.raises(lib.SmcxError, match="own"):
         p2.set_bridge_partner(p2)
+
+
+def test_block_diagonal_factor(lib, orc):
+    """block = 8: the factor of the block-diagonal part of each metric block,
+    which equals the oracle's full factor of that part (exact zeros between
+    the blocks); in place, and with coupling entries that it ignores."""
+    say("gblisa_block_factor")
+    K = np.array([4, 1, 0, 10, 6])
+    off = np.concatenate([[0], np.cumsum(K)])
+    rng = np.random.default_rng(412)
+    diag = [wl.spd_blocks([8] * int(k), seed=413 + i, spread=3.0) for i, k in enumerate(K)]
+    bd = []
+    for blocks in diag:
+        n = 8 * len(blocks)
+        m = np.zeros((n, n))
+        for j, b in enumerate(blocks):
+            m[8 * j:8 * j + 8, 8 * j:8 * j + 8] = b
+        bd.append(m)
+    coupled = []
+    for m in bd:  # the same with (ignored) coupling between sources
+        c = m.copy()
+        mask = np.kron(np.eye(len(m) // 8), np.ones((8, 8))) == 0
+        c[mask] = rng.normal(0, 1e-3, mask.sum()) * np.sqrt(np.outer(np.diag(m), np.diag(m)))[mask]
+        coupled.append(0.5 * (c + c.T))
+    ridge = np.array([1e-3, 1e-2, 0.5, 0.7, 0.3, 1.2, 1.2, 0.3])
+    ref, status = orc.metric_factor(GBLISA, off, bd, ridge)
+    assert np.all(status == 0)
+    w = wl.make_gblisa(N=len(K), k_hi=int(K.max()), n_inj=1, seed=414)
+    prob = lib.Problem.frequency_domain(GBLISA, dev(w.noise), w.k0, w.T_obs, w.S, int(K.max()),
+                                        len(K), int(off[-1]))
+    for inp in (bd, coupled):
+        fo, Fp = wl.pack_blocks(inp)
+        F = dev(Fp)
+        W = lib.metric_factor(prob, dev(off), dev(fo), F, ridge, out=F, block=8)
+        torch.cuda.synchronize()
+        prob.device_status()
+        Wg = W.cpu().numpy()
+        for i, r in enumerate(ref):
+            n = r.shape[0]
+            if n == 0:
+                continue
+            g = Wg[fo[i]:fo[i + 1]].reshape(n, n)
+            D = np.sqrt(np.diag(bd[i]) + np.tile(ridge, K[i]))
+            gd, rd = g * D, r * D
+            assert np.all(np.abs(gd - rd) <= 1e-10 * np.abs(rd).max(axis=1, keepdims=True)), i
+            mask = np.kron(np.eye(n // 8), np.ones((8, 8))) == 0
+            assert np.all(g[mask] == 0.0)
+    with pytest.raises(lib.SmcxError, match="block"):
+        lib.metric_factor(prob, dev(off), dev(fo), F, ridge, block=3)
