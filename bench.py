@@ -27,6 +27,7 @@ Other workloads (--workload):
   smc_gblisa    whole prior-start SMC runs on ten Galactic binaries, N = 40000
   gb_durations  the Galactic-binary study over record lengths (3..12 months):
                 prior-start and bridged posterior-start runs at each length
+  pulse_durations  the same study for the pulse record (1/4 .. 1 of it)
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -613,6 +614,64 @@ def bench_gb_durations(args, dev, smcx, np, torch):
                         "K_range": [1, k_hi], "bins": w.B, "runs": rows})
 
 
+def bench_pulse_durations(args, dev, smcx, np, torch):
+    """The paper's pulse study over record lengths (Sec. "Sequence of gaussian
+    pulses": iterations of prior-start and posterior-start SMC as the analysed
+    portion of the record grows): the ten-pulse record of smc_pulses (N = 6000,
+    K in [1, 10]) cut at 1/4, 3/8, .., 1 of its 4096 samples; at each length a
+    prior-start run and a posterior-start run from the previous length's final
+    population through the bridge split at the previous length."""
+    from paper_2609_17674_amd import smc
+    from paper_2609_17674_amd import workloads as wl
+    w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
+    d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, torch.tensor(w.inj, device=dev),
+                                                               w.T, w.t_start, w.dt)
+    N, k_hi = w.N, w.k_max
+    lo = torch.tensor(wl.PULSE_PRIOR[:, 0].copy(), device=dev)
+    hi = torch.tensor(wl.PULSE_PRIOR[:, 1].copy(), device=dev)
+    rows, prev, total_t, total_pi = [], None, 0.0, 0
+    for eighth in range(2, 9):
+        n = w.T * eighth // 8
+        prob = smcx.Problem(w.model, d[:n].contiguous(), w.t_start, w.dt, w.sigma, k_hi, N, N * k_hi)
+        for kind in (smcx.KIND_GRAD, smcx.KIND_LOGL):
+            prob.set_tiling(kind, 32, 4096, 1)
+        prob.set_tiling(smcx.KIND_DELTA, 16, 4096, 1)
+        cfg = dict(N=N, k_lo=1, k_hi=k_hi, max_iters=400, metric=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr = smc.run_prior_start(prob, lo, hi, smc.SMCConfig(seed=600 + eighth, **cfg))
+        torch.cuda.synchronize()
+        t_pr = time.perf_counter() - t0
+        n_in = int(np.sum(w.inj[:, 1] < w.t_start + n * w.dt))
+        row = {"samples": n, "injected_in_record": n_in,
+               "prior_start": {"iterations": pr.iterations, "seconds": round(t_pr, 3),
+                               "K_mode": int(np.argmax(pr.k_hist[-1]))}}
+        total_t += t_pr
+        total_pi += N * pr.iterations
+        if prev is not None:
+            n_prev, pres = prev
+            t0 = time.perf_counter()
+            po = smc.run_posterior_start(prob, n_prev, pres.offsets, pres.theta, lo, hi,
+                                         smc.SMCConfig(seed=700 + eighth, **cfg))
+            torch.cuda.synchronize()
+            t_po = time.perf_counter() - t0
+            row["posterior_start"] = {"iterations": po.iterations, "seconds": round(t_po, 3),
+                                      "K_mode": int(np.argmax(po.k_hist[-1]))}
+            total_t += t_po
+            total_pi += N * po.iterations
+            prev = (n, po)
+        else:
+            prev = (n, pr)
+        log(f"[bench] {n} samples: {row}")
+        rows.append(row)
+    return dict(metric="particle-iterations/sec of the pulse duration study (prior-start and "
+                       "posterior-start SMC)",
+                value=total_pi / total_t, unit="particle-iterations/s",
+                ms_per_step=1e3 * total_t,
+                config={"workload": "pulse_durations", "N": N, "n_injected": len(w.inj),
+                        "K_range": [1, k_hi], "T": w.T, "runs": rows})
+
+
 def _gb_subset(w, idx):
     import numpy as np
     from types import SimpleNamespace
@@ -643,7 +702,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="pulse_batch",
                     choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "metric", "gb_lisa", "smc_gblisa", "gb_durations", "copy_probe"])
+                             "metric", "gb_lisa", "smc_gblisa", "gb_durations", "pulse_durations",
+                             "copy_probe"])
     ap.add_argument("--gb-n", type=int, default=40000, help="particles of the gb_durations study")
     ap.add_argument("--tiling", default="",
                     help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
@@ -677,6 +737,9 @@ def main():
     elif args.workload == "gb_durations":
         res = bench_gb_durations(args, dev, smcx, np, torch)
         w = None
+    elif args.workload == "pulse_durations":
+        res = bench_pulse_durations(args, dev, smcx, np, torch)
+        w = None
     elif args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
     elif args.workload == "metric":
@@ -685,7 +748,7 @@ def main():
         w = wl.make_config(args.workload)
     if w is not None:
         log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    if args.workload in ("gb_lisa", "smc_gblisa", "gb_durations"):
+    if args.workload in ("gb_lisa", "smc_gblisa", "gb_durations", "pulse_durations"):
         pass
     elif args.workload in ("pulse_batch", "gb_grad"):
         res = bench_grad(args, w, dev, smcx, np, torch)
