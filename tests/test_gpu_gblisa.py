@@ -352,3 +352,43 @@ def test_block_diagonal_factor(lib, orc):
             assert np.all(g[mask] == 0.0)
     with pytest.raises(lib.SmcxError, match="block"):
         lib.metric_factor(prob, dev(off), dev(fo), F, ridge, block=3)
+
+
+def test_leapfrog_step_on_the_frequency_domain_model(lib, orc):
+    """smcx_leapfrog on the GB model: drift, the frequency-domain gradient at
+    the new point and the closing kick, against the step built from the
+    oracle's gradients (identity metric: momenta in raw units, small eps)."""
+    w = wl.make_gblisa(N=80, k_lo=0, k_hi=5, n_inj=4, beta="uniform", noise=True, seed=415)
+    say("gblisa_leapfrog")
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    rng = np.random.default_rng(416)
+    scales = np.array([0.05 / w.T_obs, 1e-19, 0.02, 0.02, 0.02, 0.02, 0.02, 0.05])
+    # raw-unit momenta sized so that one drift moves each coordinate by about
+    # half its scale (the identity metric cannot balance the raw gradients,
+    # whose f0 and fdot parts are 1e9 and 1e17 times the others)
+    eps = 1e-17
+    p0 = 0.5 * rng.standard_normal(w.theta.shape) * scales / eps
+    dirs = np.where(rng.random(w.N) < 0.5, -1, 1).astype(np.int8)
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    q1, p1, g1, l1 = lib.leapfrog(prob, off, be, eps, th, dev(p0), g0, dir=dev(dirs))
+    torch.cuda.synchronize()
+    prob.device_status()
+    q1, p1, l1 = q1.cpu().numpy(), p1.cpu().numpy(), l1.cpu().numpy()
+    _, rg0 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    rows = np.repeat(np.arange(w.N), w.K)
+    e = eps * dirs[rows][:, None]
+    ph = p0 + 0.5 * e * rg0
+    rq = w.theta + e * ph
+    rl, rg = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, rq, w.beta)
+    rp = ph + 0.5 * e * rg
+    # the kicks carry the gradient bound (1e-7 of the natural norm) in raw units
+    gb = np.zeros_like(rg0)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        if a < b:
+            gb[a:b] = 1e-7 * np.linalg.norm(rg0[a:b] / NAT) * NAT
+    assert np.all(np.abs(q1 - rq) <= 0.5 * eps * eps * gb + 1e-13 * np.abs(rq))
+    assert np.all(np.abs(p1 - rp) <= eps * 2 * gb + 1e-12 * np.abs(rp))
+    assert np.all(np.abs(l1 - rl) <= 1e-9 * np.abs(rl))
