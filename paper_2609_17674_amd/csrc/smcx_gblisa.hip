@@ -35,22 +35,18 @@ constexpr double kAuLight = 1.495978707e11 / 299792458.0;  // R / c [s]
 // Per-lane constants of the coarse time grid: symmetric detector tensors
 // of A and E (xx, yy, zz, xy, xz, yz), cos and sin of the orbital phase,
 // t_j; then the 64 roots exp(-2 pi i k / 64).
+// The lane's row of the table is read where it is used (L1-resident), which
+// keeps 15 doubles out of the registers of the particle's whole pass.
 struct LaneGeom {
-  double dA[6], dE[6], ca, sa, t;
+  const double* r;
+  __device__ __forceinline__ const double* tensor(int c) const { return r + 6 * c; }
+  __device__ __forceinline__ double ca() const { return r[12]; }
+  __device__ __forceinline__ double sa() const { return r[13]; }
+  __device__ __forceinline__ double t() const { return r[14]; }
 };
 
 __device__ __forceinline__ LaneGeom load_geom(const double* tab, int lane) {
-  LaneGeom g;
-  const double* r = tab + lane * kFdTableStride;
-#pragma unroll
-  for (int x = 0; x < 6; ++x) {
-    g.dA[x] = r[x];
-    g.dE[x] = r[6 + x];
-  }
-  g.ca = r[12];
-  g.sa = r[13];
-  g.t = r[14];
-  return g;
+  return LaneGeom{tab + lane * kFdTableStride};
 }
 
 struct V3 {
@@ -69,8 +65,10 @@ struct Src {
   int64_t q;
 };
 
-// Source constants kept per wave between the forward and the adjoint pass
-// (the first kFdCacheK sources of a particle; later ones are recomputed).
+// Source constants of a particle, kept per wave in LDS: lane k computes
+// those of source c0 + k of a chunk of kFdCacheK sources, and every lane
+// reads them back from there in both passes (a particle with at most
+// kFdCacheK sources fills the chunk once).
 constexpr int kFdCacheK = 16;
 constexpr int kSrcWords = 22;
 
@@ -123,7 +121,7 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
   const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const double* D = c == 0 ? g.dA : g.dE;
+    const double* D = g.tensor(c);
     const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
     const double P = dot3(s.u, Du) - dot3(s.v, Dv), X = 2.0 * dot3(s.u, Dv);
     e.Fp[c] = s.c2p * P + s.s2p * X;
@@ -131,8 +129,8 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
     e.ar[c] = e.Fp[c] * Ap;
     e.ai[c] = -e.Fx[c] * Ax;
   }
-  e.doppler = kAuLight * (g.ca * s.cl + g.sa * s.sl);
-  e.tau = g.t + s.cb * e.doppler;
+  e.doppler = kAuLight * (g.ca() * s.cl + g.sa() * s.sl);
+  e.tau = g.t() + s.cb * e.doppler;
   // phase in cycles, reduced before the product with 2 pi
   double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
                (double)(s.q & (kNs - 1)) * (double)lane / (double)kNs + s.cyc0;
@@ -148,52 +146,105 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
 
 __device__ __forceinline__ int bitrev6(int x) { return (int)(__builtin_bitreverse32((unsigned)x) >> 26); }
 
+// The value of lane (lane ^ H), H a power of two below 64, with no trip
+// through the LDS crossbar: DPP row permutations for H <= 8 (H = 4 and 8 as
+// the half-row mirror i -> i ^ 7 followed by i -> i ^ 3 or the row mirror
+// i -> i ^ 15) and the row-swap instructions for H = 16 and 32.
+template <int H>
+__device__ __forceinline__ int xor_lane_u32(int v, int lane) {
+  if constexpr (H == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+  } else if constexpr (H == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+  } else if constexpr (H == 4) {
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, true);          // quad_perm [3,2,1,0]
+  } else if constexpr (H == 8) {
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, true);         // row_mirror
+  } else if constexpr (H == 16) {
+    // both operands a copy of v: the first ends with rows (0, 0, 2, 2), the
+    // second with rows (1, 1, 3, 3)
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((lane & 16) ? r[0] : r[1]);
+  } else {
+    static_assert(H == 32, "xor distance");
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((lane & 32) ? r[0] : r[1]);
+  }
+}
+
+template <int H>
+__device__ __forceinline__ double xor_lane(double v, int lane) {
+  const int64_t b = __builtin_bit_cast(int64_t, v);
+  const int lo = xor_lane_u32<H>((int)(uint32_t)b, lane), hi = xor_lane_u32<H>((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// One radix-2 stage over lane pairs (L, L ^ H) of the forward transform,
+// decimation in frequency.
+template <int H>
+__device__ __forceinline__ void dif_stage(double re[2], double im[2], const double* roots, int lane) {
+  const bool up = lane & H;
+  const int k = (lane & (H - 1)) * (32 / H);
+  const double wr = roots[2 * k], wi = roots[2 * k + 1];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double ore = xor_lane<H>(re[c], lane), oim = xor_lane<H>(im[c], lane);
+    const double dr = ore - re[c], di = oim - im[c];
+    re[c] = up ? dr * wr - di * wi : re[c] + ore;
+    im[c] = up ? dr * wi + di * wr : im[c] + oim;
+  }
+}
+
 // Forward DFT over the wave, decimation in frequency: natural order in,
 // lane L ends with X[bitrev6(L)]. roots[k] = exp(-2 pi i k / 64).
 __device__ __forceinline__ void fft_dif(double re[2], double im[2], const double* roots, int lane) {
+  dif_stage<32>(re, im, roots, lane);
+  dif_stage<16>(re, im, roots, lane);
+  dif_stage<8>(re, im, roots, lane);
+  dif_stage<4>(re, im, roots, lane);
+  dif_stage<2>(re, im, roots, lane);
+  dif_stage<1>(re, im, roots, lane);
+}
+
+// One stage of the inverse transform, decimation in time, with the
+// conjugate root: lower lane x + w o, upper lane o - w x.
+template <int H>
+__device__ __forceinline__ void dit_stage(double re[2], double im[2], const double* roots, int lane) {
+  const bool up = lane & H;
+  const int k = (lane & (H - 1)) * (32 / H);
+  const double wr = roots[2 * k], wi = -roots[2 * k + 1];
 #pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const bool up = lane & h;
-    const int k = (lane & (h - 1)) * (32 / h);
-    const double wr = roots[2 * k], wi = roots[2 * k + 1];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const double ore = __shfl_xor(re[c], h), oim = __shfl_xor(im[c], h);
-      if (up) {
-        const double dr = ore - re[c], di = oim - im[c];
-        re[c] = dr * wr - di * wi;
-        im[c] = dr * wi + di * wr;
-      } else {
-        re[c] += ore;
-        im[c] += oim;
-      }
-    }
+  for (int c = 0; c < 2; ++c) {
+    const double ore = xor_lane<H>(re[c], lane), oim = xor_lane<H>(im[c], lane);
+    const double br = up ? re[c] : ore, bi = up ? im[c] : oim;
+    const double tr = wr * br - wi * bi, ti = wr * bi + wi * br;
+    re[c] = up ? ore - tr : re[c] + tr;
+    im[c] = up ? oim - ti : im[c] + ti;
   }
 }
 
 // Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT over the wave, decimation
 // in time: lane L holds input index bitrev6(L), output in natural order.
 __device__ __forceinline__ void ifft_dit(double re[2], double im[2], const double* roots, int lane) {
-#pragma unroll
-  for (int h = 1; h <= 32; h <<= 1) {
-    const bool up = lane & h;
-    const int k = (lane & (h - 1)) * (32 / h);
-    const double wr = roots[2 * k], wi = -roots[2 * k + 1];  // conjugate root
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const double ore = __shfl_xor(re[c], h), oim = __shfl_xor(im[c], h);
-      // lower: x + w o; upper: o - w x
-      const double br = up ? re[c] : ore, bi = up ? im[c] : oim;
-      const double tr = wr * br - wi * bi, ti = wr * bi + wi * br;
-      re[c] = up ? ore - tr : re[c] + tr;
-      im[c] = up ? oim - ti : im[c] + ti;
-    }
-  }
+  dit_stage<1>(re, im, roots, lane);
+  dit_stage<2>(re, im, roots, lane);
+  dit_stage<4>(re, im, roots, lane);
+  dit_stage<8>(re, im, roots, lane);
+  dit_stage<16>(re, im, roots, lane);
+  dit_stage<32>(re, im, roots, lane);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Butterfly sum: every lane ends with the same (bitwise) total, since each
+// stage adds the same two values in both lanes of a pair.
+__device__ __forceinline__ double wave_sum(double v, int lane) {
+  v += xor_lane<32>(v, lane);
+  v += xor_lane<16>(v, lane);
+  v += xor_lane<8>(v, lane);
+  v += xor_lane<4>(v, lane);
+  v += xor_lane<2>(v, lane);
+  v += xor_lane<1>(v, lane);
   return v;
 }
 
@@ -298,8 +349,8 @@ __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const La
         y = fma(vr[c], vr[c], fma(vi[c], vi[c], y));
       }
   }
-  *rh = wave_sum(x);
-  *hh = wave_sum(y);
+  *rh = wave_sum(x, lane);
+  *hh = wave_sum(y, lane);
 }
 
 // Derivatives of the envelope z_c (channel c) with respect to the eight
@@ -311,11 +362,11 @@ __device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, cons
   const double fi = s.f0 + s.fd * e.tau;
   const double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
                           kTwoPi * fi * (-s.sb * e.doppler),
-                          kTwoPi * fi * (s.cb * kAuLight * (g.sa * s.cl - g.ca * s.sl)), 0.0, 0.0,
+                          kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)), 0.0, 0.0,
                           1.0};
   const V3 ul = {s.sb * s.v.x, s.sb * s.v.y, 0.0};
   const V3 vl = {-s.cl, -s.sl, 0.0};
-  const double* D = c == 0 ? g.dA : g.dE;
+  const double* D = g.tensor(c);
   const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
   const double dPb = 2.0 * dot3(s.n, Du), dXb = 2.0 * dot3(s.n, Dv);
   const double dPl = 2.0 * (dot3(ul, Du) - dot3(vl, Dv));
@@ -337,6 +388,20 @@ __device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, cons
     dzr[p] = 0.5 * (da_r[p] * e.cph - da_i[p] * e.sph) - dphi[p] * e.zi[c];
     dzi[p] = 0.5 * (da_r[p] * e.sph + da_i[p] * e.cph) + dphi[p] * e.zr[c];
   }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sources c0 .. c0 + kFdCacheK - 1 (those below K) into the wave's cache.
+__device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int K, int c0, double T_obs,
+                                           int lane, double (*mine)[kSrcWords]) {
+  wave_sync();  // earlier reads of the cache are done
+  if (lane < kFdCacheK && c0 + lane < K) src_store(mine[lane], make_src(theta + (m0 + c0 + lane) * 8, T_obs));
+  wave_sync();
 }
 
 struct FdItem {
@@ -374,14 +439,8 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
   Resid<NR> R;
   load_resid<NR>(sd, lane, R);
   for (int k = 0; k < it.K; ++k) {
-    const Src s = make_src(a.theta + (it.m0 + k) * 8, sd.T_obs);
-    if (MODE == 1 && k < kFdCacheK && lane == 0) src_store(mine[k], s);
-    subtract_source<NR>(sd, s, g, lane, R, 1.0);
-  }
-  if constexpr (MODE == 1) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
+    subtract_source<NR>(sd, src_load(mine[k % kFdCacheK]), g, lane, R, 1.0);
   }
   if constexpr (MODE == 2) {
     if (a.theta_birth && a.dlogl_birth) {
@@ -411,7 +470,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int r = 0; r < NR; ++r) ss = fma(R.re[c][r], R.re[c][r], fma(R.im[c][r], R.im[c][r], ss));
-  ss = wave_sum(ss);
+  ss = wave_sum(ss, lane);
   if (lane == 0 && a.logl) {
     const double v = -0.5 * wc * ss;
     a.logl[i] = first ? v : a.logl[i] + v;
@@ -421,7 +480,8 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bitrev6(lane);
     for (int k = 0; k < it.K; ++k) {
-      const Src s = k < kFdCacheK ? src_load(mine[k]) : make_src(a.theta + (it.m0 + k) * 8, sd.T_obs);
+      if (it.K > kFdCacheK && k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
+      const Src s = src_load(mine[k % kFdCacheK]);
       // residual window of the source, bit-reversed for the inverse FFT
       const int64_t bw = s.q - kNs / 2 + lr - sd.k0;  // band index this lane gathers
       const bool in = bw >= 0 && bw < sd.B;
@@ -464,7 +524,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
       }
       const double gs = wc * sd.scale;
 #pragma unroll
-      for (int p = 0; p < 8; ++p) gp[p] = wave_sum(gp[p]) * gs;
+      for (int p = 0; p < 8; ++p) gp[p] = wave_sum(gp[p], lane) * gs;
       if (lane < 8) {
         double gv = gp[0];
 #pragma unroll
@@ -556,7 +616,7 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
     double v = 0.0;
 #pragma unroll
     for (int x = 0; x < 36; ++x) {
-      const double t = wave_sum(acc[x]);
+      const double t = wave_sum(acc[x], lane);
       v = x == want ? t : v;
     }
     double* dst = Fi + (int64_t)(8 * k + ra) * n + 8 * k + rb;
