@@ -390,7 +390,8 @@ int smcx_autotune(smcx_problem* prob, int32_t kind, int64_t N, const int64_t* of
  * kept per source: block k is the Gauss-Newton Hessian in that source's
  * eight parameters over its 64-bin window, computed in FP64 from the
  * envelope derivatives by Parseval's identity, and blocks between sources
- * are zero. */
+ * are zero; there k_max is not limited (the k_max P <= 128 bound above is
+ * the time-domain kernel's). */
 int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                              const double* theta, const double* beta, const int64_t* f_offsets,
                              int64_t f_size, double* F, void* hip_stream);

@@ -252,6 +252,22 @@ void fd_table_host(double T_obs, std::vector<double>& tab) {
     row[13] = std::sin(a);
     row[14] = t;
   }
+  // Stage s (span H = 32 >> s) of the transform: lane l's butterfly has index
+  // l & (H - 1) in its block, root exp(-2 pi i (l & (H - 1)) (32 / H) / 64).
+  // For H <= 8 the forward root carries the sign of the lane's difference
+  // (-1 where bit H of the lane is set); the inverse takes the conjugate.
+  for (int st = 0; st < 6; ++st) {
+    const int H = 32 >> st;
+    for (int l = 0; l < 64; ++l) {
+      const int k = (l & (H - 1)) * (32 / H);
+      const double c = std::cos(2.0 * kPi * k / 64.0), sn = -std::sin(2.0 * kPi * k / 64.0);
+      const double sg = (H <= 8 && (l & H)) ? -1.0 : 1.0;
+      tab[smcx::kFdTwiddleFwd + st * 128 + 2 * l] = sg * c;
+      tab[smcx::kFdTwiddleFwd + st * 128 + 2 * l + 1] = sg * sn;
+      tab[smcx::kFdTwiddleInv + st * 128 + 2 * l] = c;
+      tab[smcx::kFdTwiddleInv + st * 128 + 2 * l + 1] = -sn;
+    }
+  }
   for (int k = 0; k < 64; ++k) {
     tab[smcx::kFdRootsOffset + 2 * k] = std::cos(2.0 * kPi * k / 64.0);
     tab[smcx::kFdRootsOffset + 2 * k + 1] = -std::sin(2.0 * kPi * k / 64.0);
@@ -1178,8 +1194,6 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   if (!f_offsets) return fail(SMCX_EINVAL, "f_offsets is NULL");
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
   if (p->fd) {
-    if ((int64_t)p->k_max * p->P > 128)
-      return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
     hipError_t e = smcx::launch_fd_metric(a, f_offsets, f_size, F, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "metric launch");

@@ -13,8 +13,9 @@
 //
 // Mapping: one wave per particle; lane j owns envelope sample j and band
 // bins j + 64 r. A source's 64 samples go through one FFT across the wave
-// (radix 2, six butterfly stages over lane pairs lane ^ h, FP64), then each
-// lane fetches the window value of its own bins from the lane holding it.
+// (radix 2, six stages over lane pairs lane ^ h, both channels at once,
+// FP64), then each lane fetches the window value of its own bins from the
+// lane holding it.
 // The residual stays in registers; the adjoint contracts the inverse FFT of
 // each source's residual window with the analytic envelope derivatives, so
 // d logL / d theta = beta (4 / (T_obs S)) (T_obs / 64) Re sum_j conj(w_j) dz_j.
@@ -34,7 +35,7 @@ constexpr double kAuLight = 1.495978707e11 / 299792458.0;  // R / c [s]
 
 // Per-lane constants of the coarse time grid: symmetric detector tensors
 // of A and E (xx, yy, zz, xy, xz, yz), cos and sin of the orbital phase,
-// t_j; then the 64 roots exp(-2 pi i k / 64).
+// t_j; then the 64 roots exp(-2 pi i k / 64) and the FFT twiddles.
 // The lane's row of the table is read where it is used (L1-resident), which
 // keeps 15 doubles out of the registers of the particle's whole pass.
 struct LaneGeom {
@@ -144,8 +145,6 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
   return e;
 }
 
-__device__ __forceinline__ int bitrev6(int x) { return (int)(__builtin_bitreverse32((unsigned)x) >> 26); }
-
 // The value of lane (lane ^ H), H a power of two below 64, with no trip
 // through the LDS crossbar: DPP row permutations for H <= 8 (H = 4 and 8 as
 // the half-row mirror i -> i ^ 7 followed by i -> i ^ 3 or the row mirror
@@ -181,59 +180,215 @@ __device__ __forceinline__ double xor_lane(double v, int lane) {
   return __builtin_bit_cast(double, (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// One radix-2 stage over lane pairs (L, L ^ H) of the forward transform,
-// decimation in frequency.
+__device__ __forceinline__ double join_words(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+// Transposed sums: a stage over lane pairs (L, L ^ H) takes two partial sums
+// per lane and leaves one, lanes with bit H clear keeping the first value's
+// pair sum and the others the second's. Each value's total is formed over
+// the same pairs, level by level, as in a butterfly, so it is bitwise the
+// same; a stage costs one exchange per pair of values instead of one per
+// value. At H = 32 and 16 the row swaps do it without selects: after
+// swapping the upper rows of a with the lower rows of b, a + b holds a's pair
+// sum in the lower rows and b's in the upper ones.
 template <int H>
-__device__ __forceinline__ void dif_stage(double re[2], double im[2], const double* roots, int lane) {
-  const bool up = lane & H;
-  const int k = (lane & (H - 1)) * (32 / H);
-  const double wr = roots[2 * k], wi = roots[2 * k + 1];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const double ore = xor_lane<H>(re[c], lane), oim = xor_lane<H>(im[c], lane);
-    const double dr = ore - re[c], di = oim - im[c];
-    re[c] = up ? dr * wr - di * wi : re[c] + ore;
-    im[c] = up ? dr * wi + di * wr : im[c] + oim;
+__device__ __forceinline__ double pair_sum(double a, double b, int lane) {
+  if constexpr (H == 32 || H == 16) {
+    const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+    const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+    if constexpr (H == 32) {
+      const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+      const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+      return join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
+    } else {
+      const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+      const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+      return join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
+    }
+  } else {
+    const bool up = lane & H;
+    const double send = up ? a : b, keep = up ? b : a;
+    return keep + xor_lane<H>(send, lane);
   }
 }
 
-// Forward DFT over the wave, decimation in frequency: natural order in,
-// lane L ends with X[bitrev6(L)]. roots[k] = exp(-2 pi i k / 64).
-__device__ __forceinline__ void fft_dif(double re[2], double im[2], const double* roots, int lane) {
-  dif_stage<32>(re, im, roots, lane);
-  dif_stage<16>(re, im, roots, lane);
-  dif_stage<8>(re, im, roots, lane);
-  dif_stage<4>(re, im, roots, lane);
-  dif_stage<2>(re, im, roots, lane);
-  dif_stage<1>(re, im, roots, lane);
+// Wave totals of eight values: lane L ends with the total of v[L >> 3].
+__device__ __forceinline__ double transposed_sum8(const double v[8], int lane) {
+  double t5[4], t4[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t5[i] = pair_sum<32>(v[i], v[i + 4], lane);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) t4[i] = pair_sum<16>(t5[i], t5[i + 2], lane);
+  double t = pair_sum<8>(t4[0], t4[1], lane);
+  t += xor_lane<4>(t, lane);
+  t += xor_lane<2>(t, lane);
+  t += xor_lane<1>(t, lane);
+  return t;
 }
 
-// One stage of the inverse transform, decimation in time, with the
-// conjugate root: lower lane x + w o, upper lane o - w x.
-template <int H>
-__device__ __forceinline__ void dit_stage(double re[2], double im[2], const double* roots, int lane) {
-  const bool up = lane & H;
-  const int k = (lane & (H - 1)) * (32 / H);
-  const double wr = roots[2 * k], wi = -roots[2 * k + 1];
+// Wave totals of 36 values. Value x is given the lane slot kSlot36[x]; the
+// slots are R5 and R5 + 32 with R5 = R4 and R4 + 16, R4 = {0,1,2,4,5,8,9,10,12},
+// so each stage halves the number of live partial sums (36, 18, 9, 5, 3, 2,
+// 1) and pairs absent from a stage are zero. Lane L ends with the total of
+// the value whose slot is L.
+__constant__ const int kSlot36[36] = {0,  1,  2,  4,  5,  8,  9,  10, 12, 16, 17, 18,
+                                      20, 21, 24, 25, 26, 28, 32, 33, 34, 36, 37, 40,
+                                      41, 42, 44, 48, 49, 50, 52, 53, 56, 57, 58, 60};
+
+__device__ __forceinline__ double transposed_sum36(const double v[36], int lane) {
+  double t5[18], t4[9], t3[5], t2[3], t1[2];
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const double ore = xor_lane<H>(re[c], lane), oim = xor_lane<H>(im[c], lane);
-    const double br = up ? re[c] : ore, bi = up ? im[c] : oim;
-    const double tr = wr * br - wi * bi, ti = wr * bi + wi * br;
-    re[c] = up ? ore - tr : re[c] + tr;
-    im[c] = up ? oim - ti : im[c] + ti;
+  for (int i = 0; i < 18; ++i) t5[i] = pair_sum<32>(v[i], v[i + 18], lane);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) t4[i] = pair_sum<16>(t5[i], t5[i + 9], lane);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) t3[i] = pair_sum<8>(t4[i], i + 5 < 9 ? t4[i + 5] : 0.0, lane);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t2[i] = pair_sum<4>(t3[i], i + 3 < 5 ? t3[i + 3] : 0.0, lane);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) t1[i] = pair_sum<2>(t2[i], i + 2 < 3 ? t2[i + 2] : 0.0, lane);
+  return pair_sum<1>(t1[0], t1[1], lane);
+}
+
+// The 64-point transforms keep two complex values per lane, A and B; at the
+// start A is channel A's and B channel E's sample of the lane. A stage of
+// span H first trades values between lanes L and L ^ H so that a lane with
+// bit H clear holds (its A, the partner's A) and one with bit H set (the
+// partner's B, its B): a butterfly pair of one sub-transform. The lane then
+// forms both outputs of that butterfly, so no lane computes a result it
+// throws away. At H = 32 and 16 the row swaps make the trade, one
+// instruction per register; below, one DPP exchange and selects. After the
+// six forward stages lane 32c + i holds channel c's window bins bitrev5(i)
+// and 32 + bitrev5(i); one more row swap at span 32 leaves lane 32s + i with
+// both channels of bin 32s + bitrev5(i). Each trade is its own inverse, so
+// the inverse transform runs the stages backwards. The twiddles come from
+// the table, one complex number per lane and stage.
+struct Pair {
+  double ar, ai, br, bi;  // A = ar + i ai, B = br + i bi
+};
+
+// the trade at span 32 or 16 of one register pair
+template <int H>
+__device__ __forceinline__ void row_swap(double& a, double& b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+  if constexpr (H == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a = join_words(lo[0], hi[0]);
+    b = join_words(lo[1], hi[1]);
+  } else {
+    static_assert(H == 16, "row swap span");
+    const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    a = join_words(lo[0], hi[0]);
+    b = join_words(lo[1], hi[1]);
   }
 }
 
-// Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT over the wave, decimation
-// in time: lane L holds input index bitrev6(L), output in natural order.
-__device__ __forceinline__ void ifft_dit(double re[2], double im[2], const double* roots, int lane) {
-  dit_stage<1>(re, im, roots, lane);
-  dit_stage<2>(re, im, roots, lane);
-  dit_stage<4>(re, im, roots, lane);
-  dit_stage<8>(re, im, roots, lane);
-  dit_stage<16>(re, im, roots, lane);
-  dit_stage<32>(re, im, roots, lane);
+template <int H>
+__device__ __forceinline__ void trade(Pair& p, int lane) {
+  if constexpr (H >= 16) {
+    row_swap<H>(p.ar, p.br);
+    row_swap<H>(p.ai, p.bi);
+  } else {
+    const bool set = lane & H;
+    const double rr = xor_lane<H>(set ? p.ar : p.br, lane), ri = xor_lane<H>(set ? p.ai : p.bi, lane);
+    p.ar = set ? rr : p.ar;
+    p.ai = set ? ri : p.ai;
+    p.br = set ? p.br : rr;
+    p.bi = set ? p.bi : ri;
+  }
+}
+
+// Forward stage S (span 32 >> S), decimation in frequency: (a, b) ->
+// (a + b, (a - b) w). Below span 16 the lane keeps x (its A, or its B with
+// bit H set) and receives y, so the pair is (x, y) or (y, x); the sign of
+// the difference in the second case is folded into the lane's twiddle.
+template <int S>
+__device__ __forceinline__ void fwd_stage(Pair& p, const double* tw, int lane) {
+  constexpr int H = 32 >> S;
+  const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
+  double xr, xi, yr, yi;
+  if constexpr (H >= 16) {
+    row_swap<H>(p.ar, p.br);
+    row_swap<H>(p.ai, p.bi);
+    xr = p.ar;
+    xi = p.ai;
+    yr = p.br;
+    yi = p.bi;
+  } else {
+    const bool set = lane & H;
+    xr = set ? p.br : p.ar;
+    xi = set ? p.bi : p.ai;
+    yr = xor_lane<H>(set ? p.ar : p.br, lane);
+    yi = xor_lane<H>(set ? p.ai : p.bi, lane);
+  }
+  const double dr = xr - yr, di = xi - yi;
+  p.ar = xr + yr;
+  p.ai = xi + yi;
+  p.br = dr * wr - di * wi;
+  p.bi = dr * wi + di * wr;
+}
+
+// Inverse stage S: (s, d) -> (s + conj(w) d, s - conj(w) d), then the trade.
+template <int S>
+__device__ __forceinline__ void inv_stage(Pair& p, const double* tw, int lane) {
+  constexpr int H = 32 >> S;
+  const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
+  const double tr = p.br * wr - p.bi * wi, ti = p.br * wi + p.bi * wr;
+  const double sr = p.ar, si = p.ai;
+  p.ar = sr + tr;
+  p.ai = si + ti;
+  p.br = sr - tr;
+  p.bi = si - ti;
+  trade<H>(p, lane);
+}
+
+__device__ __forceinline__ int bitrev5(int x) { return (int)(__builtin_bitreverse32((unsigned)x) >> 27); }
+
+// The lane holding window bin m (0 <= m < 64) after the forward transform,
+// and the bin a lane holds: the map is its own inverse.
+__device__ __forceinline__ int bin_lane(int m) { return (m & 32) | bitrev5(m & 31); }
+
+// Forward DFT of both channels over the wave: lane j holds sample j of each
+// channel in (re[c], im[c]); lane bin_lane(m) ends with bin m of each.
+// table: the lane table (forward twiddles at kFdTwiddleFwd).
+__device__ __forceinline__ void fft_fwd(double re[2], double im[2], const double* table, int lane) {
+  const double* tw = table + kFdTwiddleFwd;
+  Pair p{re[0], im[0], re[1], im[1]};
+  fwd_stage<0>(p, tw, lane);
+  fwd_stage<1>(p, tw, lane);
+  fwd_stage<2>(p, tw, lane);
+  fwd_stage<3>(p, tw, lane);
+  fwd_stage<4>(p, tw, lane);
+  fwd_stage<5>(p, tw, lane);
+  row_swap<32>(p.ar, p.br);
+  row_swap<32>(p.ai, p.bi);
+  re[0] = p.ar;
+  im[0] = p.ai;
+  re[1] = p.br;
+  im[1] = p.bi;
+}
+
+// Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT of both channels: lane L
+// holds bin bin_lane(L) of each channel, lane j ends with sample j.
+__device__ __forceinline__ void fft_inv(double re[2], double im[2], const double* table, int lane) {
+  const double* tw = table + kFdTwiddleInv;
+  Pair p{re[0], im[0], re[1], im[1]};
+  row_swap<32>(p.ar, p.br);
+  row_swap<32>(p.ai, p.bi);
+  inv_stage<5>(p, tw, lane);
+  inv_stage<4>(p, tw, lane);
+  inv_stage<3>(p, tw, lane);
+  inv_stage<2>(p, tw, lane);
+  inv_stage<1>(p, tw, lane);
+  inv_stage<0>(p, tw, lane);
+  re[0] = p.ar;
+  im[0] = p.ai;
+  re[1] = p.br;
+  im[1] = p.bi;
 }
 
 // Butterfly sum: every lane ends with the same (bitwise) total, since each
@@ -248,9 +403,9 @@ __device__ __forceinline__ double wave_sum(double v, int lane) {
   return v;
 }
 
-// The source's window spectrum (times T_obs / 64), bit-reversed across the
-// wave: lane L holds bin q - 32 + bitrev6(L).
-__device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* roots,
+// The source's window spectrum (times T_obs / 64) across the wave: lane L
+// holds bin q - 32 + bin_lane(L).
+__device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* table,
                                                 double scale, int lane, double re[2], double im[2]) {
   const Env e = envelope(s, g, lane);
   const double sg = (lane & 1) ? -scale : scale;  // (-1)^j centres the window on q
@@ -259,7 +414,7 @@ __device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g,
     re[c] = sg * e.zr[c];
     im[c] = sg * e.zi[c];
   }
-  fft_dif(re, im, roots, lane);
+  fft_fwd(re, im, table, lane);
 }
 
 // Value of the window spectrum at band bin b (0 outside the window), read
@@ -268,7 +423,7 @@ __device__ __forceinline__ void window_at(const double re[2], const double im[2]
                                           int64_t q, double out_re[2], double out_im[2]) {
   const int64_t m = b_abs - (q - kNs / 2);
   const bool in = m >= 0 && m < kNs;
-  const int src = bitrev6((int)(m & (kNs - 1)));
+  const int src = bin_lane((int)(m & (kNs - 1)));
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const double vr = __shfl(re[c], src), vi = __shfl(im[c], src);
@@ -315,7 +470,7 @@ template <int NR>
 __device__ __forceinline__ void subtract_source(const FdSide& sd, const Src& s, const LaneGeom& g,
                                                 int lane, Resid<NR>& R, double sign) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.table + kFdRootsOffset, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.table, sd.scale, lane, re, im);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int64_t b = lane + kNs * r;
@@ -335,7 +490,7 @@ template <int NR>
 __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const LaneGeom& g, int lane,
                                         const Resid<NR>& R, double* rh, double* hh) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.table + kFdRootsOffset, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.table, sd.scale, lane, re, im);
   double x = 0.0, y = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -476,13 +631,12 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
     a.logl[i] = first ? v : a.logl[i] + v;
   }
   if constexpr (MODE == 1) {
-    const double* roots = sd.table + kFdRootsOffset;
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
-    const int lr = bitrev6(lane);
+    const int lr = bin_lane(lane);
     for (int k = 0; k < it.K; ++k) {
       if (it.K > kFdCacheK && k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
       const Src s = src_load(mine[k % kFdCacheK]);
-      // residual window of the source, bit-reversed for the inverse FFT
+      // residual window of the source in the inverse transform's input order
       const int64_t bw = s.q - kNs / 2 + lr - sd.k0;  // band index this lane gathers
       const bool in = bw >= 0 && bw < sd.B;
       const int src = (int)(bw & (kNs - 1));
@@ -500,7 +654,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
         wr[c] = in ? vr : 0.0;
         wi[c] = in ? vi : 0.0;
       }
-      ifft_dit(wr, wi, roots, lane);
+      fft_inv(wr, wi, sd.table, lane);
       // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
       // of the window (indexed from q - 32)
       if (lane & 1) {
@@ -522,14 +676,10 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
 #pragma unroll
         for (int p = 0; p < 8; ++p) gp[p] = fma(wr[c], dzr[p], fma(wi[c], dzi[p], gp[p]));
       }
-      const double gs = wc * sd.scale;
-#pragma unroll
-      for (int p = 0; p < 8; ++p) gp[p] = wave_sum(gp[p], lane) * gs;
-      if (lane < 8) {
-        double gv = gp[0];
-#pragma unroll
-        for (int p = 1; p < 8; ++p) gv = lane == p ? gp[p] : gv;
-        const int64_t x = (it.m0 + k) * 8 + lane;
+      // lane 8p ends with parameter p's total
+      double gv = transposed_sum8(gp, lane) * (wc * sd.scale);
+      if ((lane & 7) == 0) {
+        const int64_t x = (it.m0 + k) * 8 + (lane >> 3);
         if (!first && a.grad) gv += a.grad[x];
         if (a.grad) a.grad[x] = gv;
         if (last && a.p_half) a.p_out[x] = fma(he, gv, a.p_half[x]);
@@ -590,13 +740,19 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
   }
   const double b = a.beta ? a.beta[i] : 1.0;
   const int ra = lane >> 3, rb = lane & 7;  // the block entry this lane writes
+  const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+  // the lane holding entry (lo, hi) of the upper triangle after the sums
+  const int holder = kSlot36[lo * 8 - lo * (lo - 1) / 2 + (hi - lo)];
+  __shared__ double cache[4][kFdCacheK][kSrcWords];
+  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   for (int side = a.fd_bridge ? 0 : 1; side < 2; ++side) {
   const FdSide sd = side == 0 ? partner_side(a) : own_side(a);
   const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs;
   const bool first = side == 0 || !a.fd_bridge;
   const LaneGeom g = load_geom(sd.table, lane);
   for (int k = 0; k < K; ++k) {
-    const Src s = make_src(a.theta + (o0 + k) * 8, sd.T_obs);
+    if (k % kFdCacheK == 0) fill_cache(a.theta, o0, K, k, sd.T_obs, lane, mine);
+    const Src s = src_load(mine[k % kFdCacheK]);
     const Env e = envelope(s, g, lane);
     double acc[36];
 #pragma unroll
@@ -611,14 +767,7 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
 #pragma unroll
         for (int q = p; q < 8; ++q, ++x) acc[x] = fma(dzr[p], dzr[q], fma(dzi[p], dzi[q], acc[x]));
     }
-    const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-    const int want = lo * 8 - lo * (lo - 1) / 2 + (hi - lo);  // index of (lo, hi) in the upper triangle
-    double v = 0.0;
-#pragma unroll
-    for (int x = 0; x < 36; ++x) {
-      const double t = wave_sum(acc[x], lane);
-      v = x == want ? t : v;
-    }
+    const double v = __shfl(transposed_sum36(acc, lane), holder);
     double* dst = Fi + (int64_t)(8 * k + ra) * n + 8 * k + rb;
     *dst = first ? gs * v : *dst + gs * v;
   }

@@ -107,10 +107,15 @@ struct PopArgs {
   double fd2_T_obs, fd2_cnorm;
 };
 // Layout of fd_table: [64][kFdTableStride] (tensors of A, E; cos, sin of
-// the orbital phase; t_j), then [64][2] roots exp(-2 pi i k / 64).
+// the orbital phase; t_j), then [64][2] roots exp(-2 pi i k / 64), then the
+// per-lane twiddles of the six FFT stages, [6][64][2] for the forward
+// transform and [6][64][2] for the inverse (stage s has span 32 >> s; see
+// the transform in the frequency-domain kernels for the lane layout).
 constexpr int kFdTableStride = 16;
 constexpr int kFdRootsOffset = 64 * kFdTableStride;
-constexpr int kFdTableSize = kFdRootsOffset + 128;
+constexpr int kFdTwiddleFwd = kFdRootsOffset + 128;
+constexpr int kFdTwiddleInv = kFdTwiddleFwd + 6 * 128;
+constexpr int kFdTableSize = kFdTwiddleInv + 6 * 128;
 
 // Sort particles by K (descending) and settle K = 0 / invalid particles.
 struct PrepArgs {

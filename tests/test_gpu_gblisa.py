@@ -97,6 +97,41 @@ def test_birth_death_match_oracle(lib, orc):
     assert np.all(dd[di == -1] == 0.0)
 
 
+def test_particles_with_many_sources(lib, orc):
+    """K up to 40: the kernels keep source constants for 16 sources at a time,
+    so these particles take several fills in the forward pass, again in the
+    adjoint, and in the metric."""
+    w = wl.make_gblisa(N=40, k_lo=14, k_hi=40, n_inj=6, beta="uniform", noise=True, seed=430)
+    say("gblisa_many_sources", "N", w.N, "M", w.M, "K max", int(w.K.max()))
+    assert w.K.max() > 32 and w.K.min() <= 16
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l, g = lib.logl_grad_batch(prob, off, th, be)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(prob, off, th, be, dev(tb), dev(di))
+    fo, F = lib.gauss_newton_metric(prob, off, th, be)
+    torch.cuda.synchronize()
+    prob.device_status()
+    l, g, db, dd = l.cpu().numpy(), g.cpu().numpy(), db.cpu().numpy(), dd.cpu().numpy()
+    fo, F = fo.cpu().numpy(), F.cpu().numpy()
+    rl, rg = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    assert np.all(np.abs(l - rl) <= 1e-9 * np.abs(rl))
+    rb, rd = orc.gblisa_delta(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta, tb, di)
+    scale = np.abs(rb) + np.abs(rd) + 1e-6 * np.abs(rl) + 1.0
+    assert np.all(np.abs(db - rb) <= 1e-9 * scale)
+    assert np.all(np.abs(dd - rd) <= 1e-9 * scale)
+    ref = orc.gblisa_fisher(w.k0, w.B, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg[a:b] / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn), i
+        n = 8 * (b - a)
+        got = F[fo[i]:fo[i + 1]].reshape(n, n)
+        dg = np.sqrt(np.diag(ref[i]))
+        assert np.all(np.abs(got - ref[i]) <= 1e-9 * np.outer(dg, dg)), i
+
+
 def test_invalid_particles_and_refusals(lib, orc):
     w = wl.make_gblisa(N=6, k_lo=1, k_hi=3, n_inj=2, seed=403)
     say("gblisa_invalid")
