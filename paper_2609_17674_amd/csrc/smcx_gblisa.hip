@@ -559,6 +559,49 @@ __device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int 
   wave_sync();
 }
 
+// This lane's share of the gradient of one source, sum_c Re(conj(w_c) dz_c,p)
+// for the eight parameters, without forming dz_c,p = (da_c,p / 2) e^{i ph} +
+// i dphi_p z_c (env_derivs): per channel
+//   Re(conj(w) dz_p) = Re(da_p) ur + Im(da_p) ui + dphi_p (Im w Re z - Re w Im z),
+// ur = (Re w cos ph + Im w sin ph) / 2, ui = (Im w cos ph - Re w sin ph) / 2,
+// and the dphi terms of both channels share one factor G. The two sky
+// derivatives are linear in (dP, dX), which are bilinear in the detector
+// tensor D_c, so with the weights alpha, beta that the polarisation angle and
+// the amplitudes give dP and dX they contract to 2 n.D y1 (latitude) and
+// 2 (ul.D y1 + vl.D y2) (longitude), y1 = alpha u + beta v, y2 = beta u - alpha v.
+__device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
+                                           const double wr[2], const double wi[2], double gp[8]) {
+  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+  const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
+  const V3 v = {-s.sl, s.cl, 0.0};
+  const V3 ul = {-s.sb * s.sl, s.sb * s.cl, 0.0}, vl = {-s.cl, -s.sl, 0.0};
+  double G = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double ur = 0.5 * (wr[c] * e.cph + wi[c] * e.sph), ui = 0.5 * (wi[c] * e.cph - wr[c] * e.sph);
+    G += wi[c] * e.zr[c] - wr[c] * e.zi[c];
+    const double al = kPa * ur + kXa * ui, be = kPb * ur - kXb * ui;
+    const V3 y1 = {al * s.u.x + be * v.x, al * s.u.y + be * v.y, al * s.u.z};
+    const V3 y2 = {be * s.u.x - al * v.x, be * s.u.y - al * v.y, be * s.u.z};
+    const double* D = g.tensor(c);
+    const V3 Dy1 = mul_sym(D, y1), Dy2 = mul_sym(D, y2);
+    t2 += e.ar[c] * ur + e.ai[c] * ui;
+    t3 += dot3(s.n, Dy1);
+    t4 += dot3(ul, Dy1) + dot3(vl, Dy2);
+    t5 += e.Fx[c] * Ap * ur + e.Fp[c] * Ax * ui;
+    t6 += s.ci * e.Fp[c] * ur + e.Fx[c] * ui;
+  }
+  const double fi = s.f0 + s.fd * e.tau;
+  gp[0] = kTwoPi * e.tau * G;
+  gp[1] = 0.5 * kTwoPi * e.tau * e.tau * G;
+  gp[2] = kLn10 * t2;
+  gp[3] = 2.0 * t3 + kTwoPi * fi * (-s.sb * e.doppler) * G;
+  gp[4] = 2.0 * t4 + kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G;
+  gp[5] = 2.0 * t5;
+  gp[6] = -2.0 * s.A * s.si * t6;
+  gp[7] = G;
+}
+
 struct FdItem {
   int64_t i, m0;
   int K;
@@ -667,15 +710,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
       // Re(conj(w) dz) per parameter
       const Env e = envelope(s, g, lane);
       double gp[8];
-#pragma unroll
-      for (int p = 0; p < 8; ++p) gp[p] = 0.0;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        double dzr[8], dzi[8];
-        env_derivs(s, g, e, c, dzr, dzi);
-#pragma unroll
-        for (int p = 0; p < 8; ++p) gp[p] = fma(wr[c], dzr[p], fma(wi[c], dzi[p], gp[p]));
-      }
+      grad_terms(s, g, e, wr, wi, gp);
       // lane 8p ends with parameter p's total
       double gv = transposed_sum8(gp, lane) * (wc * sd.scale);
       if ((lane & 7) == 0) {
