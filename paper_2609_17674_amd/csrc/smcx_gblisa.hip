@@ -62,7 +62,12 @@ __device__ __forceinline__ V3 mul_sym(const double* d, const V3& v) {
 // Source constants, the same in every lane.
 struct Src {
   double f0, fd, A, cb, sb, cl, sl, c2p, s2p, ci, si, cyc0;
-  V3 n, u, v;
+  double Ap, Ax;  // amplitudes of h+ and hx
+  // The polarisation patterns are the quadratic forms P = u.D u - v.D v and
+  // X = 2 u.D v of a detector tensor D; as weights of its six components
+  // (xx, yy, zz, xy, xz, yz): P = sum ep[e] D[e], X = sum ex[e] D[e].
+  double ep[6], ex[6];
+  V3 n, u, v;  // v = (-sin l, cos l, 0)
   int64_t q;
 };
 
@@ -71,24 +76,31 @@ struct Src {
 // reads them back from there in both passes (a particle with at most
 // kFdCacheK sources fills the chunk once).
 constexpr int kFdCacheK = 16;
-constexpr int kSrcWords = 22;
+constexpr int kSrcWords = 34;  // 33 used; rows stay 16-byte aligned
 
 __device__ __forceinline__ void src_store(double* c, const Src& s) {
-  const double v[kSrcWords] = {s.f0, s.fd, s.A, s.cb, s.sb, s.cl, s.sl, s.c2p, s.s2p, s.ci, s.si,
-                               s.cyc0, s.n.x, s.n.y, s.n.z, s.u.x, s.u.y, s.u.z, s.v.x, s.v.y,
-                               s.v.z, (double)s.q};
+  const double v[33] = {s.f0,    s.fd,    s.A,     s.cb,    s.sb,    s.cl,    s.sl,
+                        s.c2p,   s.s2p,   s.ci,    s.si,    s.cyc0,  s.Ap,    s.Ax,
+                        s.ep[0], s.ep[1], s.ep[2], s.ep[3], s.ep[4], s.ep[5], s.ex[0],
+                        s.ex[1], s.ex[2], s.ex[3], s.ex[4], s.ex[5], s.n.x,   s.n.y,
+                        s.n.z,   s.u.x,   s.u.y,   s.u.z,   __builtin_bit_cast(double, s.q)};
 #pragma unroll
-  for (int x = 0; x < kSrcWords; ++x) c[x] = v[x];
+  for (int x = 0; x < 33; ++x) c[x] = v[x];
 }
 
 __device__ __forceinline__ Src src_load(const double* c) {
   Src s;
   s.f0 = c[0]; s.fd = c[1]; s.A = c[2]; s.cb = c[3]; s.sb = c[4]; s.cl = c[5]; s.sl = c[6];
-  s.c2p = c[7]; s.s2p = c[8]; s.ci = c[9]; s.si = c[10]; s.cyc0 = c[11];
-  s.n = {c[12], c[13], c[14]};
-  s.u = {c[15], c[16], c[17]};
-  s.v = {c[18], c[19], c[20]};
-  s.q = (int64_t)c[21];
+  s.c2p = c[7]; s.s2p = c[8]; s.ci = c[9]; s.si = c[10]; s.cyc0 = c[11]; s.Ap = c[12]; s.Ax = c[13];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    s.ep[e] = c[14 + e];
+    s.ex[e] = c[20 + e];
+  }
+  s.n = {c[26], c[27], c[28]};
+  s.u = {c[29], c[30], c[31]};
+  s.v = {-s.sl, s.cl, 0.0};
+  s.q = __builtin_bit_cast(int64_t, c[32]);  // stored as its bit pattern
   return s;
 }
 
@@ -106,6 +118,22 @@ __device__ __forceinline__ Src make_src(const double* th, double T_obs) {
   s.u = {s.sb * s.cl, s.sb * s.sl, -s.cb};
   s.v = {-s.sl, s.cl, 0.0};
   s.q = (int64_t)floor(s.f0 * T_obs);
+  s.Ap = s.A * (1.0 + s.ci * s.ci);
+  s.Ax = -2.0 * s.A * s.ci;
+  const V3& u = s.u;
+  const V3& v = s.v;
+  s.ep[0] = u.x * u.x - v.x * v.x;
+  s.ep[1] = u.y * u.y - v.y * v.y;
+  s.ep[2] = u.z * u.z - v.z * v.z;
+  s.ep[3] = 2.0 * (u.x * u.y - v.x * v.y);
+  s.ep[4] = 2.0 * (u.x * u.z - v.x * v.z);
+  s.ep[5] = 2.0 * (u.y * u.z - v.y * v.z);
+  s.ex[0] = 2.0 * u.x * v.x;
+  s.ex[1] = 2.0 * u.y * v.y;
+  s.ex[2] = 2.0 * u.z * v.z;
+  s.ex[3] = 2.0 * (u.x * v.y + u.y * v.x);
+  s.ex[4] = 2.0 * (u.x * v.z + u.z * v.x);
+  s.ex[5] = 2.0 * (u.y * v.z + u.z * v.y);
   return s;
 }
 
@@ -119,16 +147,19 @@ struct Env {
 
 __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lane) {
   Env e;
-  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const double* D = g.tensor(c);
-    const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
-    const double P = dot3(s.u, Du) - dot3(s.v, Dv), X = 2.0 * dot3(s.u, Dv);
+    double P = 0.0, X = 0.0;
+#pragma unroll
+    for (int x = 0; x < 6; ++x) {
+      P = fma(s.ep[x], D[x], P);
+      X = fma(s.ex[x], D[x], X);
+    }
     e.Fp[c] = s.c2p * P + s.s2p * X;
     e.Fx[c] = -s.s2p * P + s.c2p * X;
-    e.ar[c] = e.Fp[c] * Ap;
-    e.ai[c] = -e.Fx[c] * Ax;
+    e.ar[c] = e.Fp[c] * s.Ap;
+    e.ai[c] = -e.Fx[c] * s.Ax;
   }
   e.doppler = kAuLight * (g.ca() * s.cl + g.sa() * s.sl);
   e.tau = g.t() + s.cb * e.doppler;
@@ -513,7 +544,7 @@ __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const La
 // the complex amplitude and ph the heterodyned phase.
 __device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, const Env& e, int c,
                                            double dzr[8], double dzi[8]) {
-  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+  const double Ap = s.Ap, Ax = s.Ax;
   const double fi = s.f0 + s.fd * e.tau;
   const double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
                           kTwoPi * fi * (-s.sb * e.doppler),
@@ -571,9 +602,9 @@ __device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int 
 // 2 (ul.D y1 + vl.D y2) (longitude), y1 = alpha u + beta v, y2 = beta u - alpha v.
 __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
                                            const double wr[2], const double wi[2], double gp[8]) {
-  const double Ap = s.A * (1.0 + s.ci * s.ci), Ax = -2.0 * s.A * s.ci;
+  const double Ap = s.Ap, Ax = s.Ax;
   const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
-  const V3 v = {-s.sl, s.cl, 0.0};
+  const V3& v = s.v;
   const V3 ul = {-s.sb * s.sl, s.sb * s.cl, 0.0}, vl = {-s.cl, -s.sl, 0.0};
   double G = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0;
 #pragma unroll
@@ -680,20 +711,24 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
       if (it.K > kFdCacheK && k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
       const Src s = src_load(mine[k % kFdCacheK]);
       // residual window of the source in the inverse transform's input order
-      const int64_t bw = s.q - kNs / 2 + lr - sd.k0;  // band index this lane gathers
+      // The window covers 64 consecutive band positions, one per residue
+      // mod 64, so the lane holding a position's residual picks the register
+      // before the exchange: position bp = lane (mod 64) in the window.
+      const int64_t lo = s.q - kNs / 2 - sd.k0;  // band index of window bin 0
+      const int regp = (int)((lo + ((lane - lo) & (kNs - 1))) >> 6);
+      const int64_t bw = lo + lr;  // band index this lane gathers
       const bool in = bw >= 0 && bw < sd.B;
       const int src = (int)(bw & (kNs - 1));
-      const int reg = in ? (int)(bw >> 6) : 0;
       double wr[2], wi[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        double vr = 0.0, vi = 0.0;
+        double pr = R.re[c][0], pi = R.im[c][0];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const double xr = __shfl(R.re[c][r], src), xi = __shfl(R.im[c][r], src);
-          vr = reg == r ? xr : vr;
-          vi = reg == r ? xi : vi;
+        for (int r = 1; r < NR; ++r) {
+          pr = regp == r ? R.re[c][r] : pr;
+          pi = regp == r ? R.im[c][r] : pi;
         }
+        const double vr = __shfl(pr, src), vi = __shfl(pi, src);
         wr[c] = in ? vr : 0.0;
         wi[c] = in ? vi : 0.0;
       }
