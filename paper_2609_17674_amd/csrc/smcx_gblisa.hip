@@ -35,19 +35,36 @@ constexpr double kAuLight = 1.495978707e11 / 299792458.0;  // R / c [s]
 
 // Per-lane constants of the coarse time grid: symmetric detector tensors
 // of A and E (xx, yy, zz, xy, xz, yz), cos and sin of the orbital phase,
-// t_j; then the 64 roots exp(-2 pi i k / 64) and the FFT twiddles.
-// The lane's row of the table is read where it is used (L1-resident), which
-// keeps 15 doubles out of the registers of the particle's whole pass.
+// t_j. Each workgroup stages them in LDS as [field][lane], so that a wave
+// reads one field of all its lanes without bank conflicts; g points at this
+// lane's column. Read where used, they keep 15 doubles out of the registers
+// of the particle's whole pass.
+constexpr int kGeoFields = 15;
 struct LaneGeom {
-  const double* r;
-  __device__ __forceinline__ const double* tensor(int c) const { return r + 6 * c; }
-  __device__ __forceinline__ double ca() const { return r[12]; }
-  __device__ __forceinline__ double sa() const { return r[13]; }
-  __device__ __forceinline__ double t() const { return r[14]; }
+  const double* g;
+  __device__ __forceinline__ double d(int c, int x) const { return g[(6 * c + x) * 64]; }
+  __device__ __forceinline__ double ca() const { return g[12 * 64]; }
+  __device__ __forceinline__ double sa() const { return g[13 * 64]; }
+  __device__ __forceinline__ double t() const { return g[14 * 64]; }
 };
 
-__device__ __forceinline__ LaneGeom load_geom(const double* tab, int lane) {
-  return LaneGeom{tab + lane * kFdTableStride};
+// The lane tables of a workgroup in LDS: the grid of the handle's record and,
+// under a bridge, of its partner's; the FFT twiddles, forward then inverse,
+// [stage][lane][re, im] each.
+struct FdTables {
+  double geo[2][kGeoFields][64];
+  double tw[2 * 6 * 128];
+};
+
+// Every thread of the workgroup calls this before any of them returns.
+__device__ __forceinline__ void stage_tables(FdTables& t, const double* own, const double* partner) {
+  for (int x = threadIdx.x; x < kGeoFields * 64; x += blockDim.x) {
+    const int f = x >> 6, l = x & 63;
+    t.geo[0][f][l] = own[l * kFdTableStride + f];
+    if (partner) t.geo[1][f][l] = partner[l * kFdTableStride + f];
+  }
+  for (int x = threadIdx.x; x < 2 * 6 * 128; x += blockDim.x) t.tw[x] = own[kFdTwiddleFwd + x];
+  __syncthreads();
 }
 
 struct V3 {
@@ -149,12 +166,12 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
   Env e;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const double* D = g.tensor(c);
     double P = 0.0, X = 0.0;
 #pragma unroll
     for (int x = 0; x < 6; ++x) {
-      P = fma(s.ep[x], D[x], P);
-      X = fma(s.ex[x], D[x], X);
+      const double D = g.d(c, x);
+      P = fma(s.ep[x], D, P);
+      X = fma(s.ex[x], D, X);
     }
     e.Fp[c] = s.c2p * P + s.s2p * X;
     e.Fx[c] = -s.s2p * P + s.c2p * X;
@@ -385,9 +402,8 @@ __device__ __forceinline__ int bin_lane(int m) { return (m & 32) | bitrev5(m & 3
 
 // Forward DFT of both channels over the wave: lane j holds sample j of each
 // channel in (re[c], im[c]); lane bin_lane(m) ends with bin m of each.
-// table: the lane table (forward twiddles at kFdTwiddleFwd).
-__device__ __forceinline__ void fft_fwd(double re[2], double im[2], const double* table, int lane) {
-  const double* tw = table + kFdTwiddleFwd;
+// tw: the forward twiddles ([stage][lane][re, im]).
+__device__ __forceinline__ void fft_fwd(double re[2], double im[2], const double* tw, int lane) {
   Pair p{re[0], im[0], re[1], im[1]};
   fwd_stage<0>(p, tw, lane);
   fwd_stage<1>(p, tw, lane);
@@ -405,8 +421,8 @@ __device__ __forceinline__ void fft_fwd(double re[2], double im[2], const double
 
 // Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT of both channels: lane L
 // holds bin bin_lane(L) of each channel, lane j ends with sample j.
-__device__ __forceinline__ void fft_inv(double re[2], double im[2], const double* table, int lane) {
-  const double* tw = table + kFdTwiddleInv;
+// tw: the inverse twiddles.
+__device__ __forceinline__ void fft_inv(double re[2], double im[2], const double* tw, int lane) {
   Pair p{re[0], im[0], re[1], im[1]};
   row_swap<32>(p.ar, p.br);
   row_swap<32>(p.ai, p.bi);
@@ -436,7 +452,7 @@ __device__ __forceinline__ double wave_sum(double v, int lane) {
 
 // The source's window spectrum (times T_obs / 64) across the wave: lane L
 // holds bin q - 32 + bin_lane(L).
-__device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* table,
+__device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* tw,
                                                 double scale, int lane, double re[2], double im[2]) {
   const Env e = envelope(s, g, lane);
   const double sg = (lane & 1) ? -scale : scale;  // (-1)^j centres the window on q
@@ -445,7 +461,7 @@ __device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g,
     re[c] = sg * e.zr[c];
     im[c] = sg * e.zi[c];
   }
-  fft_fwd(re, im, table, lane);
+  fft_fwd(re, im, tw, lane);
 }
 
 // Value of the window spectrum at band bin b (0 outside the window), read
@@ -467,16 +483,19 @@ __device__ __forceinline__ void window_at(const double re[2], const double im[2]
 // (eq. reuse_bridge between two records) also its partner's.
 struct FdSide {
   const double* data;
-  const double* table;
+  const double* tw;  // twiddles in LDS, forward then inverse
+  LaneGeom g;        // this lane's grid constants in LDS
   int64_t k0, B;
   double T_obs, scale, cnorm;
 };
 
-__device__ __forceinline__ FdSide own_side(const PopArgs& a) {
-  return {a.fd_data, a.fd_table, a.fd_k0, a.fd_B, a.fd_T_obs, a.fd_scale, a.inv_sigma2};
+__device__ __forceinline__ FdSide own_side(const PopArgs& a, const FdTables& t, int lane) {
+  return {a.fd_data, t.tw, LaneGeom{&t.geo[0][0][lane]}, a.fd_k0, a.fd_B, a.fd_T_obs, a.fd_scale,
+          a.inv_sigma2};
 }
-__device__ __forceinline__ FdSide partner_side(const PopArgs& a) {
-  return {a.fd2_data, a.fd2_table, a.fd2_k0, a.fd2_B, a.fd2_T_obs, a.fd2_T_obs / 64.0, a.fd2_cnorm};
+__device__ __forceinline__ FdSide partner_side(const PopArgs& a, const FdTables& t, int lane) {
+  return {a.fd2_data, t.tw, LaneGeom{&t.geo[1][0][lane]}, a.fd2_k0, a.fd2_B, a.fd2_T_obs,
+          a.fd2_T_obs / 64.0, a.fd2_cnorm};
 }
 
 template <int NR>
@@ -501,7 +520,7 @@ template <int NR>
 __device__ __forceinline__ void subtract_source(const FdSide& sd, const Src& s, const LaneGeom& g,
                                                 int lane, Resid<NR>& R, double sign) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.table, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.tw, sd.scale, lane, re, im);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int64_t b = lane + kNs * r;
@@ -521,7 +540,7 @@ template <int NR>
 __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const LaneGeom& g, int lane,
                                         const Resid<NR>& R, double* rh, double* hh) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.table, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.tw, sd.scale, lane, re, im);
   double x = 0.0, y = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -552,7 +571,9 @@ __device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, cons
                           1.0};
   const V3 ul = {s.sb * s.v.x, s.sb * s.v.y, 0.0};
   const V3 vl = {-s.cl, -s.sl, 0.0};
-  const double* D = g.tensor(c);
+  double D[6];
+#pragma unroll
+  for (int x = 0; x < 6; ++x) D[x] = g.d(c, x);
   const V3 Du = mul_sym(D, s.u), Dv = mul_sym(D, s.v);
   const double dPb = 2.0 * dot3(s.n, Du), dXb = 2.0 * dot3(s.n, Dv);
   const double dPl = 2.0 * (dot3(ul, Du) - dot3(vl, Dv));
@@ -614,7 +635,9 @@ __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, cons
     const double al = kPa * ur + kXa * ui, be = kPb * ur - kXb * ui;
     const V3 y1 = {al * s.u.x + be * v.x, al * s.u.y + be * v.y, al * s.u.z};
     const V3 y2 = {be * s.u.x - al * v.x, be * s.u.y - al * v.y, be * s.u.z};
-    const double* D = g.tensor(c);
+    double D[6];
+#pragma unroll
+    for (int x = 0; x < 6; ++x) D[x] = g.d(c, x);
     const V3 Dy1 = mul_sym(D, y1), Dy2 = mul_sym(D, y2);
     t2 += e.ar[c] * ur + e.ai[c] * ui;
     t3 += dot3(s.n, Dy1);
@@ -664,7 +687,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
                                             double (*mine)[kSrcWords]) {
   const int64_t i = it.i;
   const double wc = w * sd.cnorm;  // weight * 4 / (T_obs S)
-  const LaneGeom g = load_geom(sd.table, lane);
+  const LaneGeom g = sd.g;
   Resid<NR> R;
   load_resid<NR>(sd, lane, R);
   for (int k = 0; k < it.K; ++k) {
@@ -732,7 +755,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
         wr[c] = in ? vr : 0.0;
         wi[c] = in ? vi : 0.0;
       }
-      fft_inv(wr, wi, sd.table, lane);
+      fft_inv(wr, wi, sd.tw + 6 * 128, lane);
       // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
       // of the window (indexed from q - 32)
       if (lane & 1) {
@@ -767,16 +790,20 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
   const int lane = threadIdx.x & 63;
   const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   FdItem it;
-  if (!fd_item(a, rank, it)) return;
-  if (a.active && !a.active[it.i]) return;
+  const bool work = fd_item(a, rank, it) && !(a.active && !a.active[it.i]);
+  // a workgroup without an active particle (late NUTS leaves) leaves at once
+  if (!__syncthreads_or(work)) return;
+  __shared__ FdTables tabs;
+  stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
+  if (!work) return;
   const double b = a.beta ? a.beta[it.i] : 1.0;
   __shared__ double cache[4][kFdCacheK][kSrcWords];
   double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   if (a.fd_bridge) {
-    fd_particle<MODE, NR>(a, partner_side(a), it, lane, 1.0 - b, true, false, mine);
-    fd_particle<MODE, NR>(a, own_side(a), it, lane, b, false, true, mine);
+    fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, mine);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, mine);
   } else {
-    fd_particle<MODE, NR>(a, own_side(a), it, lane, b, true, true, mine);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, mine);
   }
 }
 
@@ -790,6 +817,8 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
                                                         double* F) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  __shared__ FdTables tabs;
+  stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
   if (i >= a.N) return;
   const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
   if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) {
@@ -816,10 +845,10 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
   __shared__ double cache[4][kFdCacheK][kSrcWords];
   double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   for (int side = a.fd_bridge ? 0 : 1; side < 2; ++side) {
-  const FdSide sd = side == 0 ? partner_side(a) : own_side(a);
+  const FdSide sd = side == 0 ? partner_side(a, tabs, lane) : own_side(a, tabs, lane);
   const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs;
   const bool first = side == 0 || !a.fd_bridge;
-  const LaneGeom g = load_geom(sd.table, lane);
+  const LaneGeom g = sd.g;
   for (int k = 0; k < K; ++k) {
     if (k % kFdCacheK == 0) fill_cache(a.theta, o0, K, k, sd.T_obs, lane, mine);
     const Src s = src_load(mine[k % kFdCacheK]);
@@ -847,7 +876,9 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
 // The band spectrum of K sources (out [2][B][2]): one wave.
 __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, double* out) {
   const int lane = threadIdx.x;
-  const LaneGeom g = load_geom(a.fd_table, lane);
+  __shared__ FdTables tabs;
+  stage_tables(tabs, a.fd_table, nullptr);
+  const FdSide sd = own_side(a, tabs, lane);
   Resid<4> R;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -855,7 +886,7 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
     for (int r = 0; r < 4; ++r) R.re[c][r] = R.im[c][r] = 0.0;
   for (int64_t k = 0; k < K; ++k) {
     const Src s = make_src(a.theta + k * 8, a.fd_T_obs);
-    subtract_source<4>(own_side(a), s, g, lane, R, -1.0);
+    subtract_source<4>(sd, s, sd.g, lane, R, -1.0);
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c)
