@@ -332,6 +332,22 @@ int smcx_nuts_transition_metric(smcx_problem* prob, int64_t N, const int64_t* of
                                 int32_t* steps_out, int32_t* status_out, int32_t use_graph,
                                 void* hip_stream);
 
+/* smcx_nuts_transition_metric with a block-diagonal factor: W [M][P][P] in
+ * the layout of smcx_metric_factor_blocks (the factor of source row m at
+ * W + m P P), so each product with W takes P terms per coordinate instead of
+ * K_i P. The result equals smcx_nuts_transition_metric's with the dense W
+ * that has these blocks on its diagonal and zeros elsewhere. Other arguments
+ * and behaviour as smcx_nuts_transition_metric (k_max P <= 128). */
+int smcx_nuts_transition_metric_blocks(smcx_problem* prob, int64_t N, const int64_t* offsets,
+                                       int64_t M, const double* beta, double eps,
+                                       int32_t max_depth, const double* prior_lo,
+                                       const double* prior_hi, const double* momentum,
+                                       const int8_t* dirs, const double* u_leaf,
+                                       const double* u_tree, const uint8_t* mask, const double* W,
+                                       double* q, double* logl, double* grad, int32_t* depth_out,
+                                       int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                                       void* hip_stream);
+
 /* Tiling of the sample axis, per call kind: SMCX_KIND_LOGL (logl_batch and
  * the segment pass of reweight_extend), SMCX_KIND_GRAD (logl_grad_batch),
  * SMCX_KIND_DELTA (delta_logl_birth_death). A wave owns one (particle,
@@ -418,6 +434,33 @@ int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offse
 int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
                        const int64_t* f_offsets, int64_t f_size, const double* F,
                        const double* ridge, int32_t block, double* W, void* hip_stream);
+
+/* Block-diagonal mass matrices kept per source (Sec. "No-U-Turn-Sampler";
+ * the frequency-domain model's metric is exactly block diagonal, one P x P
+ * block per source). The three calls below use one layout: a device FP64
+ * array [M][P][P], the row-major block of source row m of theta at m P P.
+ * It holds M P^2 doubles where the dense layout holds sum_i (K_i P)^2.
+ *
+ * smcx_gauss_newton_metric_blocks: the diagonal blocks of the metric of
+ * smcx_gauss_newton_metric (same definition, precision and bridge
+ * behaviour), F [M][P][P] written for the source rows of the N particles.
+ * Nothing between blocks is written or needed. Time-domain models compute
+ * the whole metric on the matrix cores and keep its per-component blocks
+ * (k_max P <= 128); the frequency-domain model computes only its blocks
+ * (any k_max). Capture-safe. */
+int smcx_gauss_newton_metric_blocks(smcx_problem* prob, int64_t N, const int64_t* offsets,
+                                    int64_t M, const double* theta, const double* beta, double* F,
+                                    void* hip_stream);
+
+/* smcx_metric_factor for the block layout: for each of the M blocks,
+ * W_m = L_m^{-1} with L_m L_m^T = F_m + diag(ridge) (ridge: host array of P
+ * values >= 0), lower triangular with zeros above the diagonal, so that
+ * M_m^{-1} = W_m^T W_m. Each block is factored as smcx_metric_factor's block
+ * mode factors it. A block with a pivot that is not > 0 (or NaN) is written
+ * as NaN and raises the device flag; the others are unaffected. W may equal
+ * F. One thread per block, no LDS; capture-safe. */
+int smcx_metric_factor_blocks(smcx_problem* prob, int64_t M, const double* F, const double* ridge,
+                              double* W, void* hip_stream);
 
 /* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
  * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first

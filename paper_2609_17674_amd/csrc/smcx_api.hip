@@ -848,13 +848,13 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
                     const double* beta, double eps, int32_t max_depth, const double* prior_lo,
                     const double* prior_hi, const double* momentum, const int8_t* dirs,
                     const double* u_leaf, const double* u_tree, const uint8_t* mask,
-                    const int64_t* w_offsets, int64_t w_size, const double* W, double* q,
-                    double* logl, double* grad, int32_t* depth_out, int32_t* steps_out,
+                    const int64_t* w_offsets, int64_t w_size, const double* W, int w_blocks,
+                    double* q, double* logl, double* grad, int32_t* depth_out, int32_t* steps_out,
                     int32_t* status_out, int32_t use_graph, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, q);
   if (rc) return rc;
   if (W) {
-    if (!w_offsets) return fail(SMCX_EINVAL, "w_offsets is NULL");
+    if (!w_blocks && !w_offsets) return fail(SMCX_EINVAL, "w_offsets is NULL");
     if (w_size < 0) return fail(SMCX_EINVAL, "w_size must be >= 0");
     if ((int64_t)p->k_max * p->P > smcx::kNutsMetricMax)
       return fail(SMCX_EINVAL, "a NUTS metric needs k_max * P <= %d (here %d)", smcx::kNutsMetricMax,
@@ -901,8 +901,9 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   na.dir = p->nuts_dir;
   na.count = p->nuts_count;
   na.wmat = W;
-  na.w_off = W ? w_offsets : nullptr;
+  na.w_off = W && !w_blocks ? w_offsets : nullptr;
   na.w_size = w_size;
+  na.w_blocks = W && w_blocks ? 1 : 0;
   na.flag = p->flag;
   double* qF = p->nuts_vec + 6 * na.stride;
   double* pF = p->nuts_vec + 7 * na.stride;
@@ -949,7 +950,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
                      (uint64_t)(uintptr_t)q, (uint64_t)(uintptr_t)logl, (uint64_t)(uintptr_t)grad,
                      (uint64_t)t.S, (uint64_t)t.chunk_len, (uint64_t)t.sorted, (uint64_t)max_depth,
                      (uint64_t)p->split, (uint64_t)(uintptr_t)W, (uint64_t)(uintptr_t)w_offsets,
-                     (uint64_t)w_size, (uint64_t)(uintptr_t)p->partner})
+                     (uint64_t)w_size, (uint64_t)w_blocks, (uint64_t)(uintptr_t)p->partner})
     key = mix_key(key, v);
   uint64_t eb;
   std::memcpy(&eb, &eps, sizeof(eb));
@@ -1002,7 +1003,7 @@ int smcx_nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int
                          int32_t use_graph, void* hip_stream) {
   g_last_error.clear();
   return nuts_transition(p, N, offsets, M, beta, eps, max_depth, prior_lo, prior_hi, momentum, dirs,
-                         u_leaf, u_tree, mask, nullptr, 0, nullptr, q, logl, grad, depth_out,
+                         u_leaf, u_tree, mask, nullptr, 0, nullptr, 0, q, logl, grad, depth_out,
                          steps_out, status_out, use_graph, hip_stream);
 }
 
@@ -1019,8 +1020,26 @@ int smcx_nuts_transition_metric(smcx_problem* p, int64_t N, const int64_t* offse
   if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
   if (!W && N > 0) return fail(SMCX_EINVAL, "W is NULL");
   return nuts_transition(p, N, offsets, M, beta, eps, max_depth, prior_lo, prior_hi, momentum, dirs,
-                         u_leaf, u_tree, mask, w_offsets, w_size, W, q, logl, grad, depth_out,
+                         u_leaf, u_tree, mask, w_offsets, w_size, W, 0, q, logl, grad, depth_out,
                          steps_out, status_out, use_graph, hip_stream);
+}
+
+int smcx_nuts_transition_metric_blocks(smcx_problem* p, int64_t N, const int64_t* offsets,
+                                       int64_t M, const double* beta, double eps,
+                                       int32_t max_depth, const double* prior_lo,
+                                       const double* prior_hi, const double* momentum,
+                                       const int8_t* dirs, const double* u_leaf,
+                                       const double* u_tree, const uint8_t* mask, const double* W,
+                                       double* q, double* logl, double* grad, int32_t* depth_out,
+                                       int32_t* steps_out, int32_t* status_out, int32_t use_graph,
+                                       void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (!W && M > 0) return fail(SMCX_EINVAL, "W is NULL");
+  return nuts_transition(p, N, offsets, M, beta, eps, max_depth, prior_lo, prior_hi, momentum, dirs,
+                         u_leaf, u_tree, mask, nullptr, M * p->P * p->P, M > 0 ? W : nullptr,
+                         M > 0 ? 1 : 0, q, logl, grad, depth_out, steps_out, status_out, use_graph,
+                         hip_stream);
 }
 
 int smcx_set_bridge_split(smcx_problem* p, int64_t split) {
@@ -1195,7 +1214,7 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
   if (p->fd) {
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
-    hipError_t e = smcx::launch_fd_metric(a, f_offsets, f_size, F, (hipStream_t)hip_stream);
+    hipError_t e = smcx::launch_fd_metric(a, f_offsets, f_size, F, 0, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "metric launch");
     return SMCX_OK;
   }
@@ -1204,8 +1223,48 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
                                      p->k_max, offsets, theta, beta, f_offsets, f_size, F,
-                                     p->split, p->flag, st);
+                                     p->split, 0, p->flag, st);
   if (e != hipSuccess) return hip_fail(e, "metric launch");
+  return SMCX_OK;
+}
+
+int smcx_gauss_newton_metric_blocks(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                                    const double* theta, const double* beta, double* F,
+                                    void* hip_stream) {
+  g_last_error.clear();
+  int rc = check_pop(p, N, offsets, M, theta);
+  if (rc) return rc;
+  if (N == 0) return SMCX_OK;
+  if (M > 0 && !F) return fail(SMCX_EINVAL, "F is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (p->fd) {
+    smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
+    hipError_t e = smcx::launch_fd_metric(a, nullptr, 0, F, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "metric launch");
+    return SMCX_OK;
+  }
+  if ((int64_t)p->k_max * p->P > 128)
+    return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
+  hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
+                                     p->k_max, offsets, theta, beta, nullptr, 0, F, p->split, 1,
+                                     p->flag, st);
+  if (e != hipSuccess) return hip_fail(e, "metric launch");
+  return SMCX_OK;
+}
+
+int smcx_metric_factor_blocks(smcx_problem* p, int64_t M, const double* F, const double* ridge,
+                              double* W, void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (M < 0) return fail(SMCX_EINVAL, "M = %lld must be >= 0", (long long)M);
+  if (M > 0 && (!F || !W)) return fail(SMCX_EINVAL, "F or W is NULL");
+  if (!ridge) return fail(SMCX_EINVAL, "ridge is NULL");
+  for (int q = 0; q < p->P; ++q)
+    if (!(ridge[q] >= 0.0) || !std::isfinite(ridge[q]))
+      return fail(SMCX_EINVAL, "ridge[%d] must be finite and >= 0", q);
+  hipError_t e = smcx::launch_metric_factor_blocks(p->P, M, F, ridge, W, p->flag,
+                                                   (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "metric factor launch");
   return SMCX_OK;
 }
 

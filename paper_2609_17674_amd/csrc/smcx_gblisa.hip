@@ -162,7 +162,9 @@ struct Env {
   double cph, sph, tau, doppler;  // doppler = cos(a - l) (R/c)
 };
 
-__device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lane) {
+// The amplitude part of the envelope: antenna patterns, complex amplitudes,
+// Doppler delay and retarded time (no phase).
+__device__ __forceinline__ Env envelope_amp(const Src& s, const LaneGeom& g) {
   Env e;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -180,6 +182,11 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lan
   }
   e.doppler = kAuLight * (g.ca() * s.cl + g.sa() * s.sl);
   e.tau = g.t() + s.cb * e.doppler;
+  return e;
+}
+
+__device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lane) {
+  Env e = envelope_amp(s, g);
   // phase in cycles, reduced before the product with 2 pi
   double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
                (double)(s.q & (kNs - 1)) * (double)lane / (double)kNs + s.cyc0;
@@ -558,11 +565,13 @@ __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const La
   *hh = wave_sum(y, lane);
 }
 
-// Derivatives of the envelope z_c (channel c) with respect to the eight
-// parameters at this lane's sample: dz = (da e^{i ph}) / 2 + i dphi z, with a
-// the complex amplitude and ph the heterodyned phase.
-__device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, const Env& e, int c,
-                                           double dzr[8], double dzi[8]) {
+// Derivatives of the envelope z_c = a_c e^{i ph} / 2 (channel c) with respect
+// to the eight parameters at this lane's sample: dz_p = (da_p e^{i ph}) / 2 +
+// i dphi_p z = (e^{i ph} / 2) g_p with g_p = da_p + i dphi_p a_c, a the complex
+// amplitude and ph the heterodyned phase. This returns g_p; the phase factor
+// has modulus one and drops out of the metric entries Re(conj(dz_a) dz_b).
+__device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g, const Env& e, int c,
+                                                 double gr[8], double gi[8]) {
   const double Ap = s.Ap, Ax = s.Ax;
   const double fi = s.f0 + s.fd * e.tau;
   const double dphi[8] = {kTwoPi * e.tau, 0.5 * kTwoPi * e.tau * e.tau, 0.0,
@@ -592,8 +601,8 @@ __device__ __forceinline__ void env_derivs(const Src& s, const LaneGeom& g, cons
   da_i[6] = -e.Fx[c] * (2.0 * s.A * s.si);
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
-    dzr[p] = 0.5 * (da_r[p] * e.cph - da_i[p] * e.sph) - dphi[p] * e.zi[c];
-    dzi[p] = 0.5 * (da_r[p] * e.sph + da_i[p] * e.cph) + dphi[p] * e.zr[c];
+    gr[p] = da_r[p] - dphi[p] * e.ai[c];
+    gi[p] = da_i[p] + dphi[p] * e.ar[c];
   }
 }
 
@@ -613,7 +622,7 @@ __device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int 
 
 // This lane's share of the gradient of one source, sum_c Re(conj(w_c) dz_c,p)
 // for the eight parameters, without forming dz_c,p = (da_c,p / 2) e^{i ph} +
-// i dphi_p z_c (env_derivs): per channel
+// i dphi_p z_c (amp_phase_derivs): per channel
 //   Re(conj(w) dz_p) = Re(da_p) ur + Im(da_p) ui + dphi_p (Im w Re z - Re w Im z),
 // ur = (Re w cos ph + Im w sin ph) / 2, ui = (Im w cos ph - Re w sin ph) / 2,
 // and the dphi terms of both channels share one factor G. The two sky
@@ -811,10 +820,13 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
 //   beta (4 / (T_obs S)) Re sum_c sum_m conj(dh_c / dtheta_a) dh_c / dtheta_b
 // over the source's 64-bin window, which by Parseval's identity for the
 // 64-point DFT equals beta (4 / (T_obs S)) (T_obs / 64)^2 64 Re sum_c sum_j
-// conj(dz_c,a(t_j)) dz_c,b(t_j); blocks between sources are zero. One wave
-// per particle; 36 wave sums per source.
+// conj(dz_c,a(t_j)) dz_c,b(t_j) = (1/4) Re sum_c sum_j conj(g_c,a) g_c,b (the
+// phase drops out, see amp_phase_derivs); blocks between sources are zero.
+// One wave per particle; 36 sums per source.
+// blocks: F is [M][8][8], block k of particle i at F + (o0 + k) 64 (nothing
+// between blocks is written); otherwise the dense n x n block at F + f_off[i].
 __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t* f_off, int64_t f_size,
-                                                        double* F) {
+                                                        double* F, int blocks) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   __shared__ FdTables tabs;
@@ -826,17 +838,18 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
     return;
   }
   const int K = (int)(o1 - o0), n = 8 * K;
-  const int64_t fo = f_off[i];
-  if (f_off[i + 1] - fo != (int64_t)n * n || fo < 0 || fo + (int64_t)n * n > f_size) {
+  const int64_t fo = blocks ? o0 * 64 : f_off[i];
+  if (!blocks && (f_off[i + 1] - fo != (int64_t)n * n || fo < 0 || fo + (int64_t)n * n > f_size)) {
     if (lane == 0) atomicOr(a.flag, kFlagOffsets);
     return;
   }
   if (n == 0) return;
   double* Fi = F + fo;
-  for (int64_t x = lane; x < (int64_t)n * n; x += 64) {
-    const int r = (int)(x / n), c = (int)(x % n);
-    if ((r >> 3) != (c >> 3)) Fi[x] = 0.0;
-  }
+  if (!blocks)
+    for (int64_t x = lane; x < (int64_t)n * n; x += 64) {
+      const int r = (int)(x / n), c = (int)(x % n);
+      if ((r >> 3) != (c >> 3)) Fi[x] = 0.0;
+    }
   const double b = a.beta ? a.beta[i] : 1.0;
   const int ra = lane >> 3, rb = lane & 7;  // the block entry this lane writes
   const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
@@ -846,28 +859,28 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
   double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   for (int side = a.fd_bridge ? 0 : 1; side < 2; ++side) {
   const FdSide sd = side == 0 ? partner_side(a, tabs, lane) : own_side(a, tabs, lane);
-  const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs;
+  const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs * 0.25;
   const bool first = side == 0 || !a.fd_bridge;
   const LaneGeom g = sd.g;
   for (int k = 0; k < K; ++k) {
     if (k % kFdCacheK == 0) fill_cache(a.theta, o0, K, k, sd.T_obs, lane, mine);
     const Src s = src_load(mine[k % kFdCacheK]);
-    const Env e = envelope(s, g, lane);
+    const Env e = envelope_amp(s, g);
     double acc[36];
 #pragma unroll
     for (int x = 0; x < 36; ++x) acc[x] = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      double dzr[8], dzi[8];
-      env_derivs(s, g, e, c, dzr, dzi);
+      double gr[8], gi[8];
+      amp_phase_derivs(s, g, e, c, gr, gi);
       int x = 0;
 #pragma unroll
       for (int p = 0; p < 8; ++p)
 #pragma unroll
-        for (int q = p; q < 8; ++q, ++x) acc[x] = fma(dzr[p], dzr[q], fma(dzi[p], dzi[q], acc[x]));
+        for (int q = p; q < 8; ++q, ++x) acc[x] = fma(gr[p], gr[q], fma(gi[p], gi[q], acc[x]));
     }
     const double v = __shfl(transposed_sum36(acc, lane), holder);
-    double* dst = Fi + (int64_t)(8 * k + ra) * n + 8 * k + rb;
+    double* dst = blocks ? Fi + 64 * k + 8 * ra + rb : Fi + (int64_t)(8 * k + ra) * n + 8 * k + rb;
     *dst = first ? gs * v : *dst + gs * v;
   }
   }
@@ -924,10 +937,10 @@ hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
-                            hipStream_t st) {
+                            int blocks, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a,
-                     f_offsets, f_size, F);
+                     f_offsets, f_size, F, blocks);
   return hipGetLastError();
 }
 

@@ -182,11 +182,13 @@ struct NutsArgs {
   int8_t* dir;             // [N]
   int* count;              // [D + 1]
   // mass matrix (W^T W)^{-1}: per-particle n x n row-major blocks W at
-  // wmat + w_off[i] (n = K P <= kNutsMetricMax), or wmat == nullptr for the
-  // identity; the momentum is then the whitened one
+  // wmat + w_off[i] (n = K P <= kNutsMetricMax), or with w_blocks one P x P
+  // block per source row m at wmat + m P P (W block diagonal), or
+  // wmat == nullptr for the identity; the momentum is then the whitened one
   const double* wmat;
   const int64_t* w_off;    // [N + 1]
   int64_t w_size;          // entries of wmat
+  int w_blocks;
   int* flag;
 };
 constexpr int kNutsMetricMax = 128;  // coordinates per particle with a metric (two per lane)
@@ -204,12 +206,18 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
 int64_t prep_slices(int64_t N);
 
 // Gauss-Newton metric on the matrix cores (smcx_metric.hip); k_max * P <= 128.
+// blocks: write only the P x P block of each component, at F + m P P for its
+// source row m (f_offsets unused).
 hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
-                         int64_t f_size, double* F, int64_t split, int* flag, hipStream_t st);
+                         int64_t f_size, double* F, int64_t split, int blocks, int* flag,
+                         hipStream_t st);
 // Factor W = L^{-1} of F + diag(ridge) per particle (smcx_metric.hip); ridge is
 // a host array of P values; LDS bytes of one workgroup for k_max * P = nmax.
+// Factor of M independent P x P blocks ([M][P][P], one thread each).
+hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const double* ridge,
+                                       double* W, int* flag, hipStream_t st);
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
                                 const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
                                 const double* F, const double* ridge, int block, double* W,
@@ -237,7 +245,7 @@ hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStrea
 hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st);
 hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st);
 hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
-                            hipStream_t st);
+                            int blocks, hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,

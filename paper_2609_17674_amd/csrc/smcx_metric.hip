@@ -49,6 +49,7 @@ struct MetricArgs {
   int* flag;
   int64_t w0, w1;  // sample window of this launch; the first window writes F, later ones add
   int tempered;    // 1: the window's samples carry beta_i (0: before a bridge split)
+  int blocks;      // 1: only each component's P x P block, at F + m P P (source row m)
 };
 
 // Per-lane description of one coordinate (component k, parameter p), set up
@@ -143,9 +144,10 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
     return;
   }
   const int n = (int)(o1 - o0) * a.P;
-  const int64_t fo = a.f_offsets[i];
-  if (a.f_offsets[i + 1] - fo != (int64_t)n * n || n > 32 * NB || fo < 0 ||
-      fo + (int64_t)n * n > a.f_size) {
+  const int64_t fo = a.blocks ? o0 * a.P * a.P : a.f_offsets[i];
+  if (n > 32 * NB ||
+      (!a.blocks && (a.f_offsets[i + 1] - fo != (int64_t)n * n || fo < 0 ||
+                     fo + (int64_t)n * n > a.f_size))) {
     if (lane == 0) atomicOr(a.flag, kFlagOffsets);
     return;
   }
@@ -202,6 +204,20 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
         // mirrored, so the result is exactly symmetric
         if (rr >= n || (bi == bj && rr > c)) continue;
         const double v = (double)acc[x][r] * sc * my[rr];
+        if (a.blocks) {
+          // a component's block starts at coordinate P k: entries (rr, c) of
+          // one component only, at F + (o0 + k) P P
+          if (rr / a.P != c / a.P) continue;
+          const int64_t bo = fo + (int64_t)(rr / a.P) * a.P * a.P;
+          const int pr = rr % a.P, pc = c % a.P;
+          double* e1 = a.F + bo + pr * a.P + pc;
+          *e1 = first ? v : *e1 + v;
+          if (pr != pc) {
+            double* e2 = a.F + bo + pc * a.P + pr;
+            *e2 = first ? v : *e2 + v;
+          }
+          continue;
+        }
         double* e1 = a.F + fo + (int64_t)rr * n + c;
         *e1 = first ? v : *e1 + v;
         if (rr != c) {
@@ -330,7 +346,81 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
   }
 }
 
+// One P x P block per thread, W_m = L^{-1} with L L^T = F_m + diag(ridge),
+// in registers: the same steps in the same order as factor_block, so a block
+// comes out bitwise as the workgroup factor's block mode gives it. A pivot
+// that is not > 0 (or NaN) fills the block with NaN and raises the flag.
+struct RidgeP {
+  double r[8];
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void factor_blocks_kernel(const double* F, double* W, int64_t M,
+                                                            RidgeP rg, int* flag) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const double* f = F + m * P * P;
+  double L[P][P];
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) L[r][c] = f[r * P + c] + (r == c ? rg.r[c] : 0.0);
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const double d = L[j][j];
+    ok = ok && d > 0.0;
+    const double ljj = sqrt(d);
+#pragma unroll
+    for (int r = j + 1; r < P; ++r) L[r][j] = L[r][j] / ljj;
+    L[j][j] = ljj;
+#pragma unroll
+    for (int r = j + 1; r < P; ++r) {
+      const double lrj = L[r][j];
+#pragma unroll
+      for (int c = j + 1; c <= r; ++c) L[r][c] = fma(-lrj, L[c][j], L[r][c]);
+    }
+  }
+#pragma unroll
+  for (int j = P - 1; j >= 0; --j) {
+    const double ljj = L[j][j];
+    double acc[P];
+#pragma unroll
+    for (int r = j + 1; r < P; ++r) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = j + 1; k <= r; ++k) s = fma(L[r][k], L[k][j], s);
+      acc[r] = s;
+    }
+#pragma unroll
+    for (int r = j + 1; r < P; ++r) L[r][j] = -acc[r] / ljj;
+    L[j][j] = 1.0 / ljj;
+  }
+  double* w = W + m * P * P;
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int c = 0; c < P; ++c) w[r * P + c] = !ok ? __builtin_nan("") : (c <= r ? L[r][c] : 0.0);
+  if (!ok) atomicOr(flag, kFlagNotPD);
+}
+
 }  // namespace
+
+hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const double* ridge,
+                                       double* W, int* flag, hipStream_t st) {
+  if (M == 0) return hipSuccess;
+  RidgeP rg{};
+  if (P > 8) return hipErrorInvalidValue;
+  for (int p = 0; p < P; ++p) rg.r[p] = ridge[p];
+  const dim3 grid((unsigned)((M + 255) / 256)), block(256);
+  switch (P) {
+    case 3: hipLaunchKernelGGL(factor_blocks_kernel<3>, grid, block, 0, st, F, W, M, rg, flag); break;
+    case 4: hipLaunchKernelGGL(factor_blocks_kernel<4>, grid, block, 0, st, F, W, M, rg, flag); break;
+    case 8: hipLaunchKernelGGL(factor_blocks_kernel<8>, grid, block, 0, st, F, W, M, rg, flag); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 size_t factor_lds_bytes(int nmax) { return (size_t)nmax * (nmax + 1) / 2 * sizeof(double); }
 
@@ -360,9 +450,10 @@ hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
 hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, double t_start,
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
-                         int64_t f_size, double* F, int64_t split, int* flag, hipStream_t st) {
+                         int64_t f_size, double* F, int64_t split, int blocks, int* flag,
+                         hipStream_t st) {
   MetricArgs a{P, N, M, T, t_start, dt, inv_sigma2, (double)T * dt, k_max, offsets, theta,
-               beta, f_offsets, f_size, F, flag, 0, 0, 1};
+               beta, f_offsets, f_size, F, flag, 0, 0, 1, blocks};
   const int nmax = k_max * P;
   const dim3 grid((unsigned)((N + 3) / 4)), block(256);
   const int nb = nmax <= 32 ? 1 : (nmax <= 64 ? 2 : 4);

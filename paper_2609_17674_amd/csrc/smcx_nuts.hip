@@ -90,22 +90,34 @@ __device__ __forceinline__ void stage(double* sh, const double* src, const View&
   __syncthreads();
 }
 // y[t] = (W sh)_c for c = lane + 64 t (TRANS: (W^T sh)_c), c < n; the sum
-// runs over c' in index order with fused multiply-adds
+// runs over c' in index order with fused multiply-adds. bs > 0: W is block
+// diagonal, one bs x bs block per source (bs = P) stored one after another,
+// and the sum runs over the block of c only (the dense form's other terms
+// are products with zero, so both give the same value).
 template <bool TRANS>
-__device__ __forceinline__ void wmul(const double* W, int n, const double* sh, int lane,
+__device__ __forceinline__ void wmul(const double* W, int n, int bs, const double* sh, int lane,
                                      double y[2]) {
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int c = lane + 64 * t;
     double s = 0.0;
-    if (c < n)
-      for (int k = 0; k < n; ++k) s = fma(TRANS ? W[(int64_t)k * n + c] : W[(int64_t)c * n + k], sh[k], s);
+    if (c < n) {
+      if (bs) {
+        const int r = c % bs, b = c - r;  // first coordinate of c's source
+        const double* B = W + (int64_t)b * bs;
+        for (int k = 0; k < bs; ++k) s = fma(TRANS ? B[k * bs + r] : B[r * bs + k], sh[b + k], s);
+      } else {
+        for (int k = 0; k < n; ++k)
+          s = fma(TRANS ? W[(int64_t)k * n + c] : W[(int64_t)c * n + k], sh[k], s);
+      }
+    }
     y[t] = s;
   }
 }
 __device__ __forceinline__ const double* wblock(const NutsArgs& a, const View& v) {
-  return a.wmat + a.w_off[v.i];
+  return a.w_blocks ? a.wmat + v.x0 * a.P : a.wmat + a.w_off[v.i];
 }
+__device__ __forceinline__ int wbs(const NutsArgs& a) { return a.w_blocks ? a.P : 0; }
 
 // Drift of the frontier: pH = pF + (e/2) gF, qF += e pH; with a metric
 // pH = pF + (e/2) W gF, qF += e W^T pH (wg: W gF when the caller has it).
@@ -128,7 +140,7 @@ __device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e
     wg[1] = wg_in[1];
   } else {
     stage(sh, g, v);
-    wmul<false>(W, n, sh, v.lane, wg);
+    wmul<false>(W, n, wbs(a), sh, v.lane, wg);
     __syncthreads();
   }
 #pragma unroll
@@ -141,7 +153,7 @@ __device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e
     }
   }
   __syncthreads();
-  wmul<true>(W, n, sh, v.lane, y);
+  wmul<true>(W, n, wbs(a), sh, v.lane, y);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int c = v.lane + 64 * t;
@@ -182,8 +194,13 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
   // the particle is kept as it is, with status -1 and the offsets flag
   bool bad_w = false;
   if (a.wmat && v.K > 0) {
-    const int64_t n = v.x1 - v.x0, w0 = a.w_off[v.i], w1 = a.w_off[v.i + 1];
-    bad_w = n > kNutsMetricMax || w1 - w0 != n * n || w0 < 0 || w1 > a.w_size;
+    const int64_t n = v.x1 - v.x0;
+    if (a.w_blocks) {
+      bad_w = n > kNutsMetricMax;
+    } else {
+      const int64_t w0 = a.w_off[v.i], w1 = a.w_off[v.i + 1];
+      bad_w = n > kNutsMetricMax || w1 - w0 != n * n || w0 < 0 || w1 > a.w_size;
+    }
     if (bad_w && v.lane == 0) atomicOr(a.flag, kFlagOffsets);
   }
   const bool still = v.K == 0 || (a.mask && !a.mask[v.i]) || bad_w;  // no move: kept as it is
@@ -216,7 +233,7 @@ __global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n)
   if (a.wmat) {  // closing half-kick of the step: pF = pH + (e/2) W gF
     const int nc = (int)(v.x1 - v.x0);
     stage(sh, slot(a, gF), v);
-    wmul<false>(wblock(a, v), nc, sh, v.lane, wg);
+    wmul<false>(wblock(a, v), nc, wbs(a), sh, v.lane, wg);
     __syncthreads();
     const double* h = slot(a, pH);
     double* pf = slot(a, pF);

@@ -20,7 +20,10 @@ every particle's current position (``smcx_gauss_newton_metric``), the prior's
 precision 12 / width^2 is added to its diagonal as a floor
 (``smcx_metric_factor``), and the transition runs in the whitened momentum
 (``smcx_nuts_transition_metric``) with the step ``eps_metric``, which is
-then in units of the target's own scale.
+then in units of the target's own scale. The frequency-domain model's metric
+is block diagonal (one P x P block per source), and its runs keep only those
+blocks (``smcx_gauss_newton_metric_blocks``, ``smcx_metric_factor_blocks``,
+``smcx_nuts_transition_metric_blocks``).
 
 The posterior-start mode (``run_posterior_start``) starts instead from a
 population sampled on the first `split` samples of the data and follows the
@@ -185,6 +188,8 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
         ridge = (list(cfg.ridge) if cfg.ridge is not None
                  else (12.0 / (hi - lo) ** 2).cpu().tolist())
         fbuf = torch.empty(1, **f64)
+        blocks = prob.model == smcx.GBLISA
+        bbuf = torch.empty((N * cfg.k_hi, P, P), **f64) if blocks else None
     beta = 0.0
     res = SMCResult(off, th, [], [], 0.0, [], [], [])
     for it in range(cfg.max_iters):
@@ -210,20 +215,21 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                 dirs = (torch.randint(0, 2, (N, D), generator=gen, device=dev) * 2 - 1).to(torch.int8)
                 ul = torch.rand((N, (1 << D) - 1), generator=gen, **f64)
                 ut = torch.rand((N, D), generator=gen, **f64)
-                metric = None
-                if cfg.metric:
+                metric = wblocks = None
+                if cfg.metric and blocks:
+                    F = smcx.gauss_newton_metric_blocks(prob, off, th, beta_arr, out=bbuf[:M])
+                    wblocks = smcx.metric_factor_blocks(prob, F, ridge, out=F)
+                elif cfg.metric:
                     fo = smcx.metric_offsets(prob, off)
                     size = max(int(fo[-1]), 1)
                     if fbuf.numel() < size:
                         fbuf = torch.empty(size + size // 4, **f64)
                     _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
                                                     out=fbuf[:size])
-                    # the frequency-domain model's metric is block-diagonal per source
-                    blk = prob.P if prob.model == smcx.GBLISA else 0
-                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M, block=blk))
+                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
                                                 ul, ut, lo, hi, mask=nuts.to(torch.uint8),
-                                                metric=metric)
+                                                metric=metric, metric_blocks=wblocks)
                 steps += int(st.sum())
             Kc = off[1:] - off[:-1]
             tb = _prior_rows(prob, lo, hi, N, gen)

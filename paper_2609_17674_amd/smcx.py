@@ -67,6 +67,10 @@ def load_library():
         "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, I32, P, P],
         "smcx_nuts_transition_metric": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, I64, P,
                                         P, P, P, P, P, P, I32, P],
+        "smcx_gauss_newton_metric_blocks": [P, I64, P, I64, P, P, P, P],
+        "smcx_metric_factor_blocks": [P, I64, P, P, P, P],
+        "smcx_nuts_transition_metric_blocks": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, P,
+                                               P, P, P, P, P, I32, P],
         "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
         "smcx_rj_apply": [P, I64, P, I64, P, P, P, P, P, P, P, I32, I32, D, I64, P, P, P, P],
     }
@@ -378,11 +382,13 @@ def nuts_reserve(prob: Problem, max_depth: int) -> None:
 
 def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q, logl, grad,
                     momentum, dirs, u_leaf, u_tree, prior_lo=None, prior_hi=None, use_graph=True,
-                    mask=None, metric=None, stream=None):
+                    mask=None, metric=None, metric_blocks=None, stream=None):
     """One batched NUTS transition, in place on (q, logl, grad); particles with
     mask[i] == 0 (uint8 [N], optional) are left as they are. metric = (w_offsets,
     W), for example from metric_factor, selects the mass matrix (W^T W)^{-1}
     (smcx_nuts_transition_metric); momentum is then the whitened draw.
+    metric_blocks = W [M, P, P] from metric_factor_blocks selects a block-diagonal
+    one (smcx_nuts_transition_metric_blocks).
 
     Returns (depth, steps, status) int32 tensors [N]."""
     offsets, N, q, beta = _pop(prob, offsets, q, beta)
@@ -400,6 +406,14 @@ def nuts_transition(prob: Problem, offsets, beta, eps: float, max_depth: int, q,
     depth = torch.empty(N, dtype=torch.int32, device=q.device)
     steps = torch.empty_like(depth)
     status = torch.empty_like(depth)
+    if metric_blocks is not None:
+        W = _dev(metric_blocks, torch.float64, "W", (q.shape[0], prob.P, prob.P))
+        _check(load_library().smcx_nuts_transition_metric_blocks(
+            prob.handle, N, _ptr(offsets), q.shape[0], _ptr(beta), float(eps), int(max_depth),
+            _ptr(prior_lo), _ptr(prior_hi), _ptr(momentum), _ptr(dirs), _ptr(u_leaf),
+            _ptr(u_tree), _ptr(mask), _ptr(W), _ptr(q), _ptr(logl), _ptr(grad), _ptr(depth),
+            _ptr(steps), _ptr(status), 1 if use_graph else 0, _stream(stream)))
+        return depth, steps, status
     if metric is not None:
         w_off = _dev(metric[0], torch.int64, "w_offsets", (N + 1,))
         W = _dev(metric[1], torch.float64, "W")
@@ -443,6 +457,46 @@ def gauss_newton_metric(prob: Problem, offsets, theta, beta=None, f_offsets=None
                                                    _ptr(theta), _ptr(beta), _ptr(f_offsets),
                                                    out.numel(), _ptr(out), _stream(stream)))
     return f_offsets, out
+
+
+def gauss_newton_metric_blocks(prob: Problem, offsets, theta, beta=None, out=None, stream=None):
+    """The per-source (P x P) diagonal blocks of the Gauss-Newton metric
+    (smcx_gauss_newton_metric_blocks). Returns F [M, P, P], the block of source
+    row m at F[m]."""
+    offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
+    M = theta.shape[0]
+    if out is None:
+        out = torch.empty((max(M, 1), prob.P, prob.P), dtype=torch.float64, device=theta.device)
+    out = _dev(out, torch.float64, "F")
+    if out.numel() < M * prob.P * prob.P:
+        raise ValueError(f"F needs {M} blocks of {prob.P} x {prob.P}")
+    _check(load_library().smcx_gauss_newton_metric_blocks(prob.handle, N, _ptr(offsets), M,
+                                                          _ptr(theta), _ptr(beta), _ptr(out),
+                                                          _stream(stream)))
+    return out
+
+
+def metric_factor_blocks(prob: Problem, F, ridge, out=None, M=None, stream=None):
+    """W_m = L_m^{-1} of F_m + diag(ridge) for every P x P block
+    (smcx_metric_factor_blocks); F [M, P, P], out may be F itself."""
+    F = _dev(F, torch.float64, "F")
+    if M is None:
+        M = F.shape[0]
+    if F.numel() < M * prob.P * prob.P:
+        raise ValueError(f"F holds fewer than {M} blocks of {prob.P} x {prob.P}")
+    if out is None:
+        out = torch.empty_like(F)
+    out = _dev(out, torch.float64, "W")
+    if out.numel() < M * prob.P * prob.P:
+        raise ValueError(f"W holds fewer than {M} blocks of {prob.P} x {prob.P}")
+    r = [float(x) for x in ridge]
+    if len(r) != prob.P:
+        raise ValueError(f"ridge needs {prob.P} values")
+    rarr = (ctypes.c_double * prob.P)(*r)
+    _check(load_library().smcx_metric_factor_blocks(prob.handle, int(M), _ptr(F),
+                                                    ctypes.cast(rarr, ctypes.c_void_p), _ptr(out),
+                                                    _stream(stream)))
+    return out
 
 
 def next_beta(prob: Problem, logl, beta_prev: float, alpha: float, logw_prev=None, beta_out=None,

@@ -77,6 +77,14 @@ def test_null_handle_rejected_before_launch(smcx):
                                          None, None, None, None, 0, None, None, None, None, None,
                                          None, None, 0, None)
     assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_gauss_newton_metric_blocks(None, 4, None, 0, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_metric_factor_blocks(None, 4, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
+    rc = lib.smcx_nuts_transition_metric_blocks(None, 4, None, 0, None, 0.1, 2, None, None, None,
+                                                None, None, None, None, None, None, None, None,
+                                                None, None, None, 0, None)
+    assert rc == smcx.SMCX_EINVAL and "handle" in smcx.last_error()
 
 
 def test_create_argument_checks(smcx):

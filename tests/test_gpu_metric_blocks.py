@@ -1,0 +1,253 @@
+"""Block-diagonal mass matrices on the GPU, through the C ABI: the metric's
+per-source blocks (smcx_gauss_newton_metric_blocks), their factors
+(smcx_metric_factor_blocks) and NUTS with them
+(smcx_nuts_transition_metric_blocks), each against the oracle, and each also
+checked against the dense entry point it stands for.
+
+Tolerances are those of the dense forms: the FP16 matrix-core bound for the
+time-domain metric, 1e-9 of sqrt(F_aa F_bb) for the FP64 frequency-domain
+metric, 1e-10 of a row's largest entry of W D for the factor (D = sqrt(diag)).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import parity as pm
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+PULSE, GB, GBLISA = wl.PULSE, wl.GBSINE, wl.GBLISA
+TOL_TD = 2.0 ** -10 + 512 * 2.0 ** -24 + 1e-5
+NAT = np.array([wl.GBLISA_T_OBS, wl.GBLISA_T_OBS ** 2, 1, 1, 1, 1, 1, 1], dtype=float)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _blocks_of(dense, K, P):
+    """The P x P diagonal blocks of per-particle dense matrices, in source-row order."""
+    out = []
+    for m, k in zip(dense, K):
+        for j in range(int(k)):
+            out.append(m[P * j:P * (j + 1), P * j:P * (j + 1)])
+    return np.array(out).reshape(-1, P, P)
+
+
+def _dense_of(blocks, K, P):
+    out, r = [], 0
+    for k in K:
+        n = int(k) * P
+        d = np.zeros((n, n))
+        for j in range(int(k)):
+            d[P * j:P * (j + 1), P * j:P * (j + 1)] = blocks[r]
+            r += 1
+        out.append(d)
+    return out
+
+
+@pytest.mark.parametrize("model", [PULSE, GB, GBLISA], ids=["P3", "P4", "P8"])
+def test_factor_blocks_matches_oracle(lib, orc, model):
+    P = orc.n_params(model)
+    Mb = 700
+    say("factor_blocks", P, Mb)
+    F = np.array(wl.spd_blocks([P] * Mb, seed=500 + P))
+    ridge = 10.0 ** np.random.default_rng(501).uniform(-3, 0, P)
+    if model == GBLISA:
+        w = wl.make_gblisa(N=4, n_inj=1, seed=502)
+        prob = lib.Problem.frequency_domain(GBLISA, pm.to_dev(np.zeros_like(w.noise)), w.k0,
+                                            w.T_obs, w.S, 1, Mb, Mb)
+    else:
+        prob = lib.Problem(model, torch.zeros(64, dtype=torch.float64, device="cuda"), 0.0, 1.0,
+                           1.0, 1, Mb, Mb)
+    Fd = pm.to_dev(F)
+    W = lib.metric_factor_blocks(prob, Fd, ridge)
+    torch.cuda.synchronize()
+    prob.device_status()
+    Wg = W.cpu().numpy()
+    off = np.arange(Mb + 1)
+    ref, status = orc.metric_factor(model, off, list(F), ridge)
+    assert np.all(status == 0)
+    for m in range(Mb):
+        D = np.sqrt(np.diag(F[m]) + ridge)
+        gd, rd = Wg[m] * D, ref[m] * D
+        bound = 1e-10 * np.abs(rd).max(axis=1, keepdims=True)
+        assert np.all(np.abs(gd - rd) <= bound), m
+        assert np.array_equal(np.triu(Wg[m], 1), np.zeros((P, P)))
+    # the same blocks through the dense entry point's block mode: the same bits
+    fo, Fp = wl.pack_blocks(list(F))
+    Wd = lib.metric_factor(prob, pm.to_dev(off), pm.to_dev(fo), pm.to_dev(Fp), ridge, block=P)
+    torch.cuda.synchronize()
+    assert np.array_equal(Wd.cpu().numpy(), Wg.reshape(-1))
+    # in place
+    W2 = lib.metric_factor_blocks(prob, Fd, ridge, out=Fd)
+    torch.cuda.synchronize()
+    assert W2.data_ptr() == Fd.data_ptr() and np.array_equal(Fd.cpu().numpy(), Wg)
+
+
+def test_factor_blocks_flags_an_indefinite_block(lib, orc):
+    say("factor_blocks_flag")
+    F = np.array([np.diag([2.0, 3.0, 4.0])] * 5)
+    F[3, 1, 1] = -1.0
+    prob = lib.Problem(PULSE, torch.zeros(64, dtype=torch.float64, device="cuda"), 0.0, 1.0, 1.0,
+                       1, 5, 5)
+    W = lib.metric_factor_blocks(prob, pm.to_dev(F), [0.0, 0.0, 0.0])
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError, match="positive definite"):
+        prob.device_status()
+    Wg = W.cpu().numpy()
+    assert np.all(np.isnan(Wg[3]))
+    for m in (0, 1, 2, 4):
+        assert np.allclose(Wg[m], np.diag(1.0 / np.sqrt([2.0, 3.0, 4.0])), rtol=0, atol=1e-15)
+    with pytest.raises(lib.SmcxError, match="ridge"):
+        lib.metric_factor_blocks(prob, pm.to_dev(F), [0.0, -1.0, 0.0])
+
+
+@pytest.mark.parametrize("cfg,ov", [("pulse_batch", dict(N=40, T=4096, k_hi=20)),
+                                    ("gb_grad", dict(N=20, T=3000, k_lo=5, k_hi=12))],
+                         ids=["pulse", "gb"])
+def test_time_domain_metric_blocks(lib, orc, cfg, ov):
+    w = wl.make_config(cfg, **ov)
+    beta = np.random.default_rng(503).random(w.N)
+    say("metric_blocks", cfg, "N", w.N, "M", w.M)
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       w.M)
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(beta)
+    Fb = lib.gauss_newton_metric_blocks(prob, off, th, be)
+    fo, F = lib.gauss_newton_metric(prob, off, th, be)
+    torch.cuda.synchronize()
+    prob.device_status()
+    Fb, fo, F = Fb.cpu().numpy(), fo.cpu().numpy(), F.cpu().numpy()
+    P = w.P
+    dense = [F[fo[i]:fo[i + 1]].reshape(int(w.K[i]) * P, int(w.K[i]) * P) for i in range(w.N)]
+    # the blocks are the dense metric's diagonal blocks, bit for bit
+    assert np.array_equal(Fb[:w.M], _blocks_of(dense, w.K, P))
+    ref = orc.fisher(w.model, w.T, w.t_start, w.dt, w.sigma, w.offsets, w.theta, beta)
+    rb = _blocks_of(ref, w.K, P)
+    for m in range(w.M):
+        d = np.sqrt(np.diag(rb[m]))
+        assert np.all(np.abs(Fb[m] - rb[m]) <= TOL_TD * np.outer(d, d) + 1e-300), m
+        assert np.array_equal(Fb[m], Fb[m].T)
+
+
+def _gb_problem(lib, orc, w):
+    d = w.noise + orc.gblisa_spectrum(w.inj, w.T_obs, w.k0, w.B)
+    prob = lib.Problem.frequency_domain(GBLISA, pm.to_dev(d), w.k0, w.T_obs, w.S, w.k_max, w.N,
+                                        max(w.M, 1))
+    return d, prob
+
+
+def test_frequency_domain_metric_blocks(lib, orc):
+    w = wl.make_gblisa(N=90, k_lo=0, k_hi=24, n_inj=4, beta="uniform", noise=True, seed=504)
+    say("gblisa_metric_blocks", "N", w.N, "M", w.M)
+    d, prob = _gb_problem(lib, orc, w)
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(w.beta)
+    Fb = lib.gauss_newton_metric_blocks(prob, off, th, be)
+    fo, F = lib.gauss_newton_metric(prob, off, th, be)
+    torch.cuda.synchronize()
+    prob.device_status()
+    Fb, fo, F = Fb.cpu().numpy(), fo.cpu().numpy(), F.cpu().numpy()
+    dense = [F[fo[i]:fo[i + 1]].reshape(int(w.K[i]) * 8, int(w.K[i]) * 8) for i in range(w.N)]
+    assert np.array_equal(Fb[:w.M], _blocks_of(dense, w.K, 8))
+    ref = orc.gblisa_fisher(w.k0, w.B, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    rb = _blocks_of(ref, w.K, 8)
+    for m in range(w.M):
+        dg = np.sqrt(np.diag(rb[m]))
+        assert np.all(np.abs(Fb[m] - rb[m]) <= 1e-9 * np.outer(dg, dg)), m
+
+
+def _nuts_pair(lib, prob, w, D, eps, Wblocks, seed, lo=None, hi=None):
+    """NUTS with the block factor and with the same factor laid out densely."""
+    mom, dirs, ul, ut = (pm.to_dev(x) for x in wl.nuts_draws(w.N, w.M, w.P, D, seed))
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(w.beta)
+    wo, Wp = wl.pack_blocks(_dense_of(Wblocks, w.K, w.P))
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    out = []
+    for kw in (dict(metric_blocks=pm.to_dev(Wblocks)), dict(metric=(pm.to_dev(wo), pm.to_dev(Wp)))):
+        q, l, g = th.clone(), l0.clone(), g0.clone()
+        r = lib.nuts_transition(prob, off, be, eps, D, q, l, g, mom, dirs, ul, ut, lo, hi, **kw)
+        torch.cuda.synchronize()
+        prob.device_status()
+        out.append([x.cpu().numpy() for x in (q, l, g) + tuple(r)])
+    return out
+
+
+def test_nuts_blocks_equal_the_dense_layout_pulse(lib, orc):
+    w = wl.make_config("pulse_batch", N=200, T=2048, k_lo=1, k_hi=8, seed=505)
+    say("nuts_blocks_pulse", "N", w.N, "M", w.M)
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       w.M)
+    D = 5
+    lib.nuts_reserve(prob, D)
+    scales = np.array([0.3, 0.004, 0.002])
+    Wb = np.array([(np.eye(3) + np.tril(np.random.default_rng(506 + m).standard_normal((3, 3)), -1)
+                    * 0.2) * scales for m in range(w.M)])
+    lo, hi = pm.to_dev(wl.PULSE_PRIOR[:, 0].copy()), pm.to_dev(wl.PULSE_PRIOR[:, 1].copy())
+    a, b = _nuts_pair(lib, prob, w, D, 0.3, Wb, 507, lo, hi)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert np.any(a[0] != w.theta)
+
+
+def test_nuts_blocks_on_the_frequency_domain_model(lib, orc):
+    """Block factor of the frequency-domain metric: equal to the dense layout,
+    and one leaf against the oracle's leapfrog step."""
+    w = wl.make_gblisa(N=64, k_lo=1, k_hi=6, n_inj=4, beta="half", noise=True, seed=508)
+    say("gblisa_nuts_blocks", "N", w.N, "M", w.M)
+    d, prob = _gb_problem(lib, orc, w)
+    off, th, be = pm.to_dev(w.offsets), pm.to_dev(w.theta), pm.to_dev(w.beta)
+    Fb = lib.gauss_newton_metric_blocks(prob, off, th, be)
+    ridge = list(12.0 / (wl.GBLISA_PRIOR[:, 1] - wl.GBLISA_PRIOR[:, 0]) ** 2)
+    Wd = lib.metric_factor_blocks(prob, Fb, ridge)
+    torch.cuda.synchronize()
+    prob.device_status()
+    Wb = Wd.cpu().numpy()[:w.M]
+    D = 4
+    lib.nuts_reserve(prob, D)
+    a, b = _nuts_pair(lib, prob, w, D, 0.3, Wb, 509)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    # depth one, every leaf taken: the leapfrog point of the oracle's gradients
+    lib.nuts_reserve(prob, 1)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, 8, 1, seed=510)
+    ul[:] = 0.0
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    q, l, g = th.clone(), l0.clone(), g0.clone()
+    eps = 0.3
+    _, _, status = lib.nuts_transition(prob, off, be, eps, 1, q, l, g, pm.to_dev(mom),
+                                       pm.to_dev(dirs), pm.to_dev(ul), pm.to_dev(ut),
+                                       metric_blocks=Wd)
+    torch.cuda.synchronize()
+    prob.device_status()
+    q, status = q.cpu().numpy(), status.cpu().numpy()
+    rl0, rg0 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    dense = _dense_of(Wb, w.K, 8)
+    checked = 0
+    for i in range(w.N):
+        lo_, hi_ = w.offsets[i], w.offsets[i + 1]
+        Wi = dense[i]
+        e = eps * dirs[i, 0]
+        r0 = mom[lo_:hi_].reshape(-1)
+        rh = r0 + 0.5 * e * Wi @ rg0[lo_:hi_].reshape(-1)
+        q1 = w.theta[lo_:hi_].reshape(-1) + e * Wi.T @ rh
+        l1, g1 = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, [0, hi_ - lo_], q1.reshape(-1, 8),
+                                      w.beta[i:i + 1])
+        r1 = rh + 0.5 * e * Wi @ g1.reshape(-1)
+        H0 = -rl0[i] + 0.5 * r0 @ r0
+        H1 = -l1[0] + 0.5 * r1 @ r1
+        if not H1 - H0 <= 1000:
+            assert status[i] == 2
+            continue
+        accept = ut[i, 0] < np.exp(H0 - H1)
+        ref = q1 if accept else w.theta[lo_:hi_].reshape(-1)
+        # the gradient gate (1e-7 of the natural-coordinate norm, here 1e-6)
+        # enters the position through the two kicks and W^T W
+        nat = np.tile(NAT, hi_ - lo_)
+        dg = 1e-6 * np.linalg.norm(rg0[lo_:hi_].reshape(-1) / nat) * nat
+        tol = 1e-12 * np.abs(ref) + 0.5 * e * e * (np.abs(Wi.T) @ (np.abs(Wi) @ dg))
+        assert np.all(np.abs(q[lo_:hi_].reshape(-1) - ref) <= tol), i
+        checked += 1
+    assert checked >= w.N // 2
