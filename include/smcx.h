@@ -509,15 +509,19 @@ int smcx_get_bridge_split(smcx_problem* prob, int64_t* split);
  *   logl       [N] UNTEMPERED log-likelihoods (logl_batch with beta = NULL)
  *   logw_prev  [N] log weights carried over, or NULL for uniform ones
  *   beta_prev  current inverse temperature in [0, 1]; alpha in (0, 1]
- * beta = 1 when ESS(1) >= alpha N; otherwise the bracket [beta_prev, 1] is
- * halved (at most 60 times, and no further once its midpoint is no longer
- * strictly inside), keeping the lower end where ESS >= alpha N, and beta is
- * that lower end (its upper end if the lower end never moved, which only
- * uneven logw_prev can cause).
+ * beta = 1 when ESS(1) >= alpha N; otherwise the root in the bracket
+ * [beta_prev, 1], found by a bracketing search that keeps the lower end where
+ * ESS >= alpha N: regula falsi on log(ESS / alpha N) in its Illinois form,
+ * with the midpoint wherever the secant point is not strictly inside, until
+ * the bracket is 1e-14 of (upper end - beta_prev) or no point lies strictly
+ * inside. beta is that lower end, a tested point, so ESS(beta) >= alpha N;
+ * it is the bisection root of eq. ess_target to that width. If the previous
+ * weights alone have ESS < alpha N the bracket is halved instead (at most 60
+ * times) and beta is its upper end, next to beta_prev.
  * Outputs (device): beta_out [N] every entry set to beta (ready for the
  * tempered calls; may be NULL), logw [N], w_norm [N] normalised weights,
  * scalars [4] = {beta, ESS(beta), log Z_t/Z_{t-1}, ESS evaluations of the
- * bisection}; the evidence increment is log sum exp(log w) - log sum
+ * search}; the evidence increment is log sum exp(log w) - log sum
  * exp(logw_prev) (log N for uniform previous weights). N in [1, n_max].
  * One single-block launch; no allocation, no host synchronisation. */
 int smcx_next_beta(smcx_problem* prob, int64_t N, const double* logl, const double* logw_prev,

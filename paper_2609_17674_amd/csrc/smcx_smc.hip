@@ -1,5 +1,5 @@
 // SMC steps around the likelihood (Sec. "Sequential Monte Carlo",
-// Sec. "Algorithm and implementation"): the ESS-bisection choice of the next
+// Sec. "Algorithm and implementation"): the ESS choice of the next
 // inverse temperature with its weights and evidence increment, systematic
 // resampling, the accept/reject of birth and death moves (eq. rj_acceptance),
 // and the CSR rebuild the last two share.
@@ -84,29 +84,66 @@ __device__ double ess_at(const NextBetaArgs& a, double db, double* sh, double* m
   return s1 * s1 / s2;
 }
 
-// One block: bisection on [beta_prev, 1] for ESS = alpha N (eq. ess_target),
+// One block: the root of ESS = alpha N on [beta_prev, 1] (eq. ess_target),
 // then the weights of eq. incremental_weight and the evidence increment.
 __global__ __launch_bounds__(kBlock) void next_beta_kernel(NextBetaArgs a) {
   __shared__ double sh[2 * kBlockWaves];
   const double target = a.alpha * (double)a.N;
   double beta = 1.0;
   int evals = 0;
-  if (!(ess_at(a, 1.0 - a.beta_prev, sh, nullptr, nullptr) >= target)) {
+  const double e1 = ess_at(a, 1.0 - a.beta_prev, sh, nullptr, nullptr);
+  if (!(e1 >= target)) {
+    // The root of ESS(beta) = target in [beta_prev, 1], kept bracketed:
+    // ESS(lo) >= target > ESS(hi). Each step tries the regula-falsi point of
+    // f = log(ESS / target) (the Illinois variant halves the value kept at an
+    // end that stays twice in a row), or the midpoint where that point is not
+    // strictly inside; about ten evaluations reach the bracket width the
+    // plain bisection reaches in fifty. The result is lo, a tested point, so
+    // ESS(beta) >= target holds as for the bisection.
     double lo = a.beta_prev, hi = 1.0;
-    bool moved = false;
-    for (int it = 0; it < 60; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (!(mid > lo && mid < hi)) break;
-      const double e = ess_at(a, mid - a.beta_prev, sh, nullptr, nullptr);
-      ++evals;
-      if (e >= target) {
-        lo = mid;
-        moved = true;
-      } else {
-        hi = mid;
+    const double f0 = a.logw_prev ? log(ess_at(a, 0.0, sh, nullptr, nullptr) / target)
+                                  : log((double)a.N / target);
+    double flo = f0, fhi = log(e1 / target);
+    if (!(flo >= 0.0)) {
+      // the previous weights alone are below the target: plain bisection
+      // (it ends next to beta_prev)
+      bool moved = false;
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        const double e = ess_at(a, mid - a.beta_prev, sh, nullptr, nullptr);
+        ++evals;
+        if (e >= target) {
+          lo = mid;
+          moved = true;
+        } else {
+          hi = mid;
+        }
       }
+      beta = moved ? lo : hi;
+    } else {
+      int side = 0;
+      for (int it = 0; it < 100; ++it) {
+        double x = fhi == fhi && flo - fhi > 0.0 ? hi - fhi * (hi - lo) / (fhi - flo) : 0.5 * (lo + hi);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        if (!(x > lo && x < hi)) break;
+        const double fx = log(ess_at(a, x - a.beta_prev, sh, nullptr, nullptr) / target);
+        ++evals;
+        if (fx >= 0.0) {
+          lo = x;
+          flo = fx;
+          if (side == 1) fhi *= 0.5;
+          side = 1;
+        } else {
+          hi = x;
+          fhi = fx == fx ? fx : -INFINITY;
+          if (side == -1) flo *= 0.5;
+          side = -1;
+        }
+        if (hi - lo <= 1e-14 * (hi - a.beta_prev)) break;
+      }
+      beta = lo;
     }
-    beta = moved ? lo : hi;
   }
   const double db = beta - a.beta_prev;
   double m, s1;

@@ -501,7 +501,7 @@ def metric_factor_blocks(prob: Problem, F, ridge, out=None, M=None, stream=None)
 
 def next_beta(prob: Problem, logl, beta_prev: float, alpha: float, logw_prev=None, beta_out=None,
               stream=None):
-    """ESS-bisection choice of the next inverse temperature from UNTEMPERED
+    """ESS choice of the next inverse temperature (root of eq. ess_target) from UNTEMPERED
     log-likelihoods. Returns (beta_out [N], logw [N], w_norm [N],
     scalars [4] = beta, ESS, log Z increment, ESS evaluations), all on the device."""
     logl = _dev(logl, torch.float64, "logl")
