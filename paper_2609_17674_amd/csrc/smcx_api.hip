@@ -107,6 +107,7 @@ void free_problem(smcx_problem* p) {
   (void)hipFree(p->nuts_active);
   (void)hipFree(p->nuts_dir);
   (void)hipFree(p->nuts_count);
+  (void)hipFree(p->nuts_list);
   (void)hipFree(p->d32);
   (void)hipFree(p->d64);
   (void)hipFree(p->fd_data);
@@ -826,6 +827,7 @@ int smcx_nuts_reserve(smcx_problem* p, int32_t max_depth) {
   if (e == hipSuccess && !p->nuts_logl) e = hipMalloc(&p->nuts_logl, nN * sizeof(double));
   if (e == hipSuccess && !p->nuts_active) e = hipMalloc(&p->nuts_active, nN);
   if (e == hipSuccess && !p->nuts_dir) e = hipMalloc(&p->nuts_dir, nN);
+  if (e == hipSuccess && !p->nuts_list) e = hipMalloc(&p->nuts_list, 2 * nN * sizeof(int32_t));
   if (e == hipSuccess && !p->nuts_capture) e = hipStreamCreateWithFlags(&p->nuts_capture, hipStreamNonBlocking);
   if (e != hipSuccess) return fail(SMCX_ENOMEM, "NUTS workspace allocation failed: %s", hipGetErrorString(e));
   p->nuts_depth = max_depth;
@@ -876,6 +878,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   std::memset(&na, 0, sizeof(na));
   na.P = p->P;
   na.D = max_depth;
+  na.k_max = p->k_max;
   na.N = N;
   na.M = M;
   na.offsets = offsets;
@@ -900,6 +903,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   na.active = p->nuts_active;
   na.dir = p->nuts_dir;
   na.count = p->nuts_count;
+  na.list_next = p->fd ? p->nuts_list : nullptr;  // filled by init for the first doubling
   na.wmat = W;
   na.w_off = W && !w_blocks ? w_offsets : nullptr;
   na.w_size = w_size;
@@ -933,13 +937,31 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   a.eps = eps;
   a.dir = p->nuts_dir;
 
+  // For the frequency-domain model every launch of doubling j (gradient,
+  // leaf, merge) walks the particles still extending at its start (init or
+  // the previous merge listed them), so its cost shrinks with the active set;
+  // the lists alternate between two buffers. The time-domain models keep the
+  // natural order in the leaf and merge launches and the longest-first order
+  // in the gradient: their short launches pay more for the list's extra
+  // dependent load than they save, and their chunked gradient balances
+  // better longest-first (measured on the pulse NUTS workload).
+  const size_t nlist = (size_t)std::max<int64_t>(p->n_max, 1);
   auto doubling = [&](int j, hipStream_t s) -> hipError_t {
+    smcx::NutsArgs nj = na;
+    smcx::PopArgs aj = a;
+    if (p->fd) {
+      nj.list_next = p->nuts_list + (size_t)((j + 1) & 1) * nlist;
+      nj.list = p->nuts_list + (size_t)(j & 1) * nlist;
+      nj.nlist = p->nuts_count + j;
+      aj.order = nj.list;
+      aj.n_active = nj.nlist;
+    }
     for (int n = 0; n < (1 << j); ++n) {
-      hipError_t err = smcx::launch_fused(p->model, t, a, s);
-      if (err == hipSuccess) err = smcx::launch_nuts_leaf(na, j, n, s);
+      hipError_t err = smcx::launch_fused(p->model, t, aj, s);
+      if (err == hipSuccess) err = smcx::launch_nuts_leaf(nj, j, n, s);
       if (err != hipSuccess) return err;
     }
-    return smcx::launch_nuts_merge(na, j, s);
+    return smcx::launch_nuts_merge(nj, j, s);
   };
 
   uint64_t key = 0;
@@ -956,7 +978,8 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   std::memcpy(&eb, &eps, sizeof(eb));
   key = mix_key(key, eb);
 
-  e = smcx::launch_nuts_init(na, st);
+  if (na.list_next) e = smcx::launch_nuts_zero(na, st);
+  if (e == hipSuccess) e = smcx::launch_nuts_init(na, st);
   if (e != hipSuccess) return hip_fail(e, "NUTS init launch");
   for (int j = 0; j < max_depth; ++j) {
     if (use_graph) {

@@ -72,6 +72,22 @@ __device__ __forceinline__ View view_of(const NutsArgs& a) {
   return v;
 }
 
+// The workgroup's particle in the current doubling's list (leaf and merge),
+// or in natural order when no list is given.
+__device__ __forceinline__ View view_of_list(const NutsArgs& a) {
+  if (!a.list) return view_of(a);
+  View v;
+  v.lane = threadIdx.x & 63;
+  v.ok = (int64_t)blockIdx.x < (int64_t)*a.nlist;
+  if (!v.ok) return v;
+  v.i = a.list[blockIdx.x];
+  const int64_t o0 = a.offsets[v.i], o1 = a.offsets[v.i + 1];
+  v.x0 = o0 * a.P;
+  v.x1 = o1 * a.P;
+  v.K = (int)(o1 - o0);
+  return v;
+}
+
 __device__ __forceinline__ double* slot(const NutsArgs& a, int k) { return a.vec + (size_t)k * a.stride; }
 
 enum Slot { qL = 0, pL, gL, qR, pR, gR, qF, pF, gF, pH, qP, gP, qS, gS, rhoT, rhoS, kFirstCk };
@@ -162,9 +178,15 @@ __device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e
   __syncthreads();
 }
 
+// count[0 .. D] = 0 before an init that lists particles (list_next set).
+__global__ __launch_bounds__(64) void nuts_zero_kernel(NutsArgs a) {
+  if ((int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
+}
+
 __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
   __shared__ double sh[kNutsMetricMax];
-  if (blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
+  // without lists nothing else touches the counts in this launch
+  if (!a.list_next && blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
   const View v = view_of(a);
   if (!v.ok) {
     if (v.i < a.N && v.lane == 0) {
@@ -203,6 +225,10 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
     }
     if (bad_w && v.lane == 0) atomicOr(a.flag, kFlagOffsets);
   }
+  // more components than the likelihood kernels accept: kept, status -1, flag
+  const bool bad_k = v.K > a.k_max;
+  if (bad_k && v.lane == 0) atomicOr(a.flag, kFlagKMax);
+  bad_w = bad_w || bad_k;
   const bool still = v.K == 0 || (a.mask && !a.mask[v.i]) || bad_w;  // no move: kept as it is
   const bool go = !still && !out && (H0 == H0) && fabs(H0) < INFINITY;
   const int8_t d = go ? a.dirs[v.i * a.D] : (int8_t)1;
@@ -217,6 +243,7 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
     s.status = bad_w ? -1 : (still ? 0 : (go ? 4 : 2));
     a.active[v.i] = go ? 1 : 0;
     a.dir[v.i] = d;
+    if (go && a.list_next) a.list_next[atomicAdd(&a.count[0], 1)] = (int32_t)v.i;
   }
   if (go) drift(a, v, a.eps * (double)d, sh);
 }
@@ -225,7 +252,7 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
 // leapfrog step: qF, pF, gF and the frontier logL are current).
 __global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
   __shared__ double sh[kNutsMetricMax];
-  const View v = view_of(a);
+  const View v = view_of_list(a);
   if (!v.ok || !a.active[v.i]) return;
   NutsState& s = a.state[v.i];
   const double e = a.eps * (double)a.dir[v.i];
@@ -315,7 +342,7 @@ __global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n)
 // End of the doubling at depth j: merge the (valid) subtree into the trajectory.
 __global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
   __shared__ double sh[kNutsMetricMax];
-  const View v = view_of(a);
+  const View v = view_of_list(a);
   if (!v.ok || !a.active[v.i]) return;
   NutsState& s = a.state[v.i];
   const bool take = a.u_tree[v.i * a.D + j] < exp(s.lw_sub - s.lw_tree);
@@ -351,7 +378,8 @@ __global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
     } else {
       s.lw_sub = -INFINITY;
       a.dir[v.i] = dn;
-      atomicAdd(&a.count[depth], 1);
+      const int slot = atomicAdd(&a.count[depth], 1);
+      if (a.list_next) a.list_next[slot] = (int32_t)v.i;
     }
   }
   if (!more) return;
@@ -392,6 +420,10 @@ dim3 grid_of(int64_t N) { return dim3((unsigned)N); }  // one wave-sized workgro
 
 }  // namespace
 
+hipError_t launch_nuts_zero(const NutsArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(nuts_zero_kernel, dim3(1), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
 hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(nuts_init_kernel, grid_of(a.N), dim3(64), 0, st, a);
   return hipGetLastError();

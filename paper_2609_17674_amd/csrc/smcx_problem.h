@@ -52,6 +52,7 @@ struct smcx_problem {
   uint8_t* nuts_active = nullptr;  // [n_max]
   int8_t* nuts_dir = nullptr;      // [n_max] direction of the current doubling
   int* nuts_count = nullptr;       // [nuts_depth + 1] particles still extending
+  int32_t* nuts_list = nullptr;    // [2][n_max] active particles of a doubling and of the next
   hipStream_t nuts_capture = nullptr;
   std::vector<hipGraphExec_t> nuts_graph;  // one per doubling depth
   std::vector<uint64_t> nuts_graph_key;
