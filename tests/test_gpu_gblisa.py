@@ -427,3 +427,47 @@ def test_leapfrog_step_on_the_frequency_domain_model(lib, orc):
     assert np.all(np.abs(q1 - rq) <= 0.5 * eps * eps * gb + 1e-13 * np.abs(rq))
     assert np.all(np.abs(p1 - rp) <= eps * 2 * gb + 1e-12 * np.abs(rp))
     assert np.all(np.abs(l1 - rl) <= 1e-9 * np.abs(rl))
+
+
+@pytest.mark.parametrize("model", ["fd", "pulse"])
+def test_nuts_keeps_particles_beyond_k_max(lib, orc, model):
+    """A particle with more components than the handle's k_max is not moved:
+    status -1, its rows unchanged, the device flag raised; the others run
+    (the frequency-domain NUTS walks per-doubling lists of active particles,
+    which must never carry it)."""
+    say("nuts_k_max", model)
+    if model == "fd":
+        w = wl.make_gblisa(N=40, k_lo=1, k_hi=6, n_inj=3, beta="half", noise=True, seed=431)
+        d = _data(orc, w)
+        big = lib.Problem.frequency_domain(GBLISA, dev(d), w.k0, w.T_obs, w.S, int(w.K.max()), w.N,
+                                           w.M)
+        prob = lib.Problem.frequency_domain(GBLISA, dev(d), w.k0, w.T_obs, w.S, 4, w.N, w.M)
+        P = 8
+    else:
+        w = wl.make_config("pulse_mutate", N=40, T=1024, k_lo=1, k_hi=6, seed=432)
+        d = orc.template_sum(w.model, w.inj, w.T, w.t_start, w.dt) + w.noise
+        big = lib.Problem(w.model, dev(d), w.t_start, w.dt, w.sigma, int(w.K.max()), w.N, w.M)
+        prob = lib.Problem(w.model, dev(d), w.t_start, w.dt, w.sigma, 4, w.N, w.M)
+        P = 3
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l0, g0 = lib.logl_grad_batch(big, off, th, be)
+    lib.nuts_reserve(prob, 3)
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, P, 3, seed=433)
+    q, l, g = th.clone(), l0.clone(), g0.clone()
+    eps = 1e-3 if model == "pulse" else 0.3
+    scales = np.ones(P) if model == "pulse" else np.array([0.05 / w.T_obs, 1e-19, 0.02, 0.02, 0.02,
+                                                            0.02, 0.02, 0.05])
+    Wb = dev(np.tile(np.diag(scales), (w.M, 1, 1)))
+    _, steps, status = lib.nuts_transition(prob, off, be, eps, 3, q, l, g, dev(mom), dev(dirs),
+                                           dev(ul), dev(ut), metric_blocks=Wb)
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError, match="k_max"):
+        prob.device_status()
+    q, status, steps = q.cpu().numpy(), status.cpu().numpy(), steps.cpu().numpy()
+    over = w.K > 4
+    assert over.any() and (~over).any()
+    for i in np.nonzero(over)[0]:
+        a, b = w.offsets[i], w.offsets[i + 1]
+        assert status[i] == -1 and steps[i] == 0
+        assert np.array_equal(q[a:b], w.theta[a:b])
+    assert np.all(steps[~over & (w.K > 0)] >= 1)
