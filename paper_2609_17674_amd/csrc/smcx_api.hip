@@ -903,7 +903,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   na.active = p->nuts_active;
   na.dir = p->nuts_dir;
   na.count = p->nuts_count;
-  na.list_next = p->fd ? p->nuts_list : nullptr;  // filled by init for the first doubling
+  na.list_next = nullptr;  // init lists nothing: the first doubling runs in natural order
   na.wmat = W;
   na.w_off = W && !w_blocks ? w_offsets : nullptr;
   na.w_size = w_size;
@@ -937,10 +937,11 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   a.eps = eps;
   a.dir = p->nuts_dir;
 
-  // For the frequency-domain model every launch of doubling j (gradient,
-  // leaf, merge) walks the particles still extending at its start (init or
-  // the previous merge listed them), so its cost shrinks with the active set;
-  // the lists alternate between two buffers. The time-domain models keep the
+  // For the frequency-domain model every launch of doubling j >= 1 (gradient,
+  // leaf, merge) walks the particles still extending at its start, which the
+  // previous merge listed, so its cost shrinks with the active set; the lists
+  // alternate between two buffers. The first doubling, where nearly every
+  // particle is active, runs in natural order. The time-domain models keep the
   // natural order in the leaf and merge launches and the longest-first order
   // in the gradient: their short launches pay more for the list's extra
   // dependent load than they save, and their chunked gradient balances
@@ -951,10 +952,12 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
     smcx::PopArgs aj = a;
     if (p->fd) {
       nj.list_next = p->nuts_list + (size_t)((j + 1) & 1) * nlist;
-      nj.list = p->nuts_list + (size_t)(j & 1) * nlist;
-      nj.nlist = p->nuts_count + j;
-      aj.order = nj.list;
-      aj.n_active = nj.nlist;
+      if (j > 0) {
+        nj.list = p->nuts_list + (size_t)(j & 1) * nlist;
+        nj.nlist = p->nuts_count + j;
+        aj.order = nj.list;
+        aj.n_active = nj.nlist;
+      }
     }
     for (int n = 0; n < (1 << j); ++n) {
       hipError_t err = smcx::launch_fused(p->model, t, aj, s);
@@ -978,8 +981,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   std::memcpy(&eb, &eps, sizeof(eb));
   key = mix_key(key, eb);
 
-  if (na.list_next) e = smcx::launch_nuts_zero(na, st);
-  if (e == hipSuccess) e = smcx::launch_nuts_init(na, st);
+  e = smcx::launch_nuts_init(na, st);
   if (e != hipSuccess) return hip_fail(e, "NUTS init launch");
   for (int j = 0; j < max_depth; ++j) {
     if (use_graph) {

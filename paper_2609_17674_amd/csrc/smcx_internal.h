@@ -192,9 +192,8 @@ struct NutsArgs {
   int w_blocks;
   // The particles still extending at the start of the current doubling,
   // list[0 .. *nlist) in no particular order (or nullptr: natural order),
-  // and the list that init (for the first doubling) or the merge (for the
-  // next one) fills, counting in count[depth]. Particles only leave the set
-  // within a doubling.
+  // and the list the merge fills for the next doubling (or nullptr), counting
+  // in count[depth]. Particles only leave the set within a doubling.
   const int32_t* list;
   const int* nlist;
   int32_t* list_next;
@@ -204,7 +203,6 @@ constexpr int kNutsMetricMax = 128;  // coordinates per particle with a metric (
 constexpr int kNutsMaxDepth = 10;
 constexpr int kNutsSlots(int D) { return 16 + 2 * D; }
 
-hipError_t launch_nuts_zero(const NutsArgs& a, hipStream_t st);
 hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st);
 hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st);
 hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st);

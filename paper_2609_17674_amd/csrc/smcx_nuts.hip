@@ -178,15 +178,9 @@ __device__ __forceinline__ void drift(const NutsArgs& a, const View& v, double e
   __syncthreads();
 }
 
-// count[0 .. D] = 0 before an init that lists particles (list_next set).
-__global__ __launch_bounds__(64) void nuts_zero_kernel(NutsArgs a) {
-  if ((int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
-}
-
 __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
   __shared__ double sh[kNutsMetricMax];
-  // without lists nothing else touches the counts in this launch
-  if (!a.list_next && blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && (int)threadIdx.x <= a.D) a.count[threadIdx.x] = 0;
   const View v = view_of(a);
   if (!v.ok) {
     if (v.i < a.N && v.lane == 0) {
@@ -243,7 +237,6 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
     s.status = bad_w ? -1 : (still ? 0 : (go ? 4 : 2));
     a.active[v.i] = go ? 1 : 0;
     a.dir[v.i] = d;
-    if (go && a.list_next) a.list_next[atomicAdd(&a.count[0], 1)] = (int32_t)v.i;
   }
   if (go) drift(a, v, a.eps * (double)d, sh);
 }
@@ -420,10 +413,6 @@ dim3 grid_of(int64_t N) { return dim3((unsigned)N); }  // one wave-sized workgro
 
 }  // namespace
 
-hipError_t launch_nuts_zero(const NutsArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_zero_kernel, dim3(1), dim3(64), 0, st, a);
-  return hipGetLastError();
-}
 hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(nuts_init_kernel, grid_of(a.N), dim3(64), 0, st, a);
   return hipGetLastError();
