@@ -52,6 +52,47 @@ def test_next_beta_matches_oracle(lib, orc, N):
             assert sc[1] >= alpha * N
 
 
+@pytest.mark.parametrize("case", ["uneven_prev", "heavy_tail", "tiny_step", "one_outlier"])
+def test_next_beta_search_edge_cases(lib, orc, case):
+    """The bracketing search against the oracle's bisection where it is
+    hardest: previous weights whose own ESS is below the target (the search
+    falls back to bisection and stops next to beta_prev), heavy-tailed and
+    strongly separated log-likelihoods (a very skewed ESS curve), and a root
+    a tiny step above beta_prev."""
+    N = 4000
+    say("next_beta_edge", case)
+    w = wl.make_config("pulse_small", N=1, T=64)
+    prob, _ = _problem(lib, w, n_max=N)
+    rng = np.random.default_rng(7)
+    lwp, beta_prev, alpha = None, 0.1, 0.9
+    if case == "uneven_prev":
+        logl = -0.5 * rng.chisquare(4096, size=N)
+        lwp = rng.normal(0.0, 3.0, size=N)
+    elif case == "heavy_tail":
+        logl = -np.abs(rng.standard_cauchy(N)) * 50.0
+    elif case == "tiny_step":
+        logl = -0.5 * rng.chisquare(4096, size=N) * 1e4
+        beta_prev = 0.5
+    else:
+        logl = np.full(N, -1e5)
+        logl[17] = -10.0
+    bo, logw, wn, sc = lib.next_beta(prob, pm.to_dev(logl), beta_prev, alpha,
+                                     logw_prev=None if lwp is None else pm.to_dev(lwp))
+    torch.cuda.synchronize()
+    sc = sc.cpu().numpy()
+    rlogw, rw, rsc = orc.next_beta(logl, beta_prev, alpha, logw_prev=lwp)
+    if case == "uneven_prev":
+        # no point above beta_prev reaches the target: both end next to it
+        assert rsc[1] < alpha * N
+        assert beta_prev < sc[0] <= beta_prev + 1e-12 and abs(sc[0] - rsc[0]) <= 1e-12
+    else:
+        assert abs(sc[0] - rsc[0]) <= 1e-9 * max(rsc[0] - beta_prev, 1e-300), (sc[0], rsc[0])
+        assert sc[1] >= alpha * N
+        assert sc[0] < 1.0
+    print(f"[next_beta] {case}: beta {sc[0]:.17g} (oracle {rsc[0]:.17g}), "
+          f"{int(sc[3])} ESS evaluations", flush=True)
+
+
 def test_next_beta_two_point_closed_form_on_gpu(lib):
     N0, N1, L, alpha = 300, 700, 50.0, 0.9
     w = wl.make_config("pulse_small", N=1, T=64)
