@@ -40,6 +40,34 @@ __device__ void block_sum2(double& a, double& b, double* sh) {
   }
 }
 
+// Exclusive prefix sum over the block of one int64 per thread (thread order),
+// and the block's total, the same in every thread. Integer sums are exact,
+// so the grouping (a scan within each wave, then the waves in order) does not
+// change the result. wsum: kBlockWaves entries of shared memory.
+__device__ int64_t block_scan_excl(int64_t v, int64_t* wsum, int64_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int64_t before = 0, tot = 0;
+  for (int i = 0; i < kBlockWaves; ++i) {
+    const int64_t t = wsum[i];
+    before += i < w ? t : 0;
+    tot += t;
+  }
+  __syncthreads();  // wsum may be reused
+  *total = tot;
+  return before + x - v;
+}
+
+// Loads per batch in the single-block prefix passes: the loads of a batch are
+// in flight together.
+constexpr int kScanBatch = 16;
+
 __device__ double block_max(double a, double* sh) {
   for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
   const int w = threadIdx.x >> 6;
@@ -212,28 +240,33 @@ __device__ __forceinline__ bool source_rows(const RebuildArgs& a, int64_t i, int
 
 // Exclusive prefix sum of count[0..N) into offsets_out[0..N] (one block).
 __global__ __launch_bounds__(kBlock) void csr_scan_kernel(RebuildArgs a) {
-  __shared__ int64_t part[kBlock];
+  __shared__ int64_t wsum[kBlockWaves];
   const int64_t per = (a.N + kBlock - 1) / kBlock;
   const int64_t b0 = (int64_t)threadIdx.x * per;
   const int64_t b1 = b0 + per < a.N ? b0 + per : a.N;
   int64_t s = 0;
-  for (int64_t i = b0; i < b1; ++i) s += a.count[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
+    int64_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) v[u] = i0 + u < b1 ? a.count[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) s += v[u];
   }
-  int64_t run = part[threadIdx.x] - s;
-  for (int64_t i = b0; i < b1; ++i) {
-    a.offsets_out[i] = run;
-    run += a.count[i];
+  int64_t total;
+  int64_t run = block_scan_excl(s, wsum, &total);
+  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
+    int64_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) v[u] = i0 + u < b1 ? a.count[i0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      if (i0 + u < b1) a.offsets_out[i0 + u] = run;
+      run += v[u];
+    }
   }
-  if (threadIdx.x == kBlock - 1) {
-    a.offsets_out[a.N] = part[kBlock - 1];
-    if (part[kBlock - 1] > a.m_cap) atomicOr(a.flag, kFlagCapacity);
+  if (threadIdx.x == 0) {
+    a.offsets_out[a.N] = total;
+    if (total > a.m_cap) atomicOr(a.flag, kFlagCapacity);
   }
 }
 
@@ -271,33 +304,37 @@ struct ResampleArgs {
 
 // Integer weights c_i = round(w_i 2^40) (0 unless w_i > 0) and their inclusive
 // prefix sums, exact in int64 (one block).
+__device__ __forceinline__ int64_t weight_units(double w) {
+  return w > 0.0 ? (int64_t)rint((w < 1.0 ? w : 1.0) * kWeightUnit) : 0;
+}
+
 __global__ __launch_bounds__(kBlock) void resample_prefix_kernel(ResampleArgs a) {
-  __shared__ int64_t part[kBlock];
+  __shared__ int64_t wsum[kBlockWaves];
   const int64_t N = a.r.N;
   const int64_t per = (N + kBlock - 1) / kBlock;
   const int64_t b0 = (int64_t)threadIdx.x * per;
   const int64_t b1 = b0 + per < N ? b0 + per : N;
   int64_t s = 0;
-  for (int64_t i = b0; i < b1; ++i) {
-    const double w = a.w_norm[i];
-    const int64_t c = w > 0.0 ? (int64_t)rint((w < 1.0 ? w : 1.0) * kWeightUnit) : 0;
-    a.cum[i] = c;
-    s += c;
+  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
+    double w[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) w[u] = i0 + u < b1 ? a.w_norm[i0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) s += weight_units(w[u]);
   }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  int64_t total;
+  int64_t run = block_scan_excl(s, wsum, &total);
+  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
+    double w[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) w[u] = i0 + u < b1 ? a.w_norm[i0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      run += weight_units(w[u]);
+      if (i0 + u < b1) a.cum[i0 + u] = run;
+    }
   }
-  int64_t run = part[threadIdx.x] - s;
-  for (int64_t i = b0; i < b1; ++i) {
-    run += a.cum[i];
-    a.cum[i] = run;
-  }
-  if (threadIdx.x == 0 && part[kBlock - 1] <= 0) atomicOr(a.r.flag, kFlagWeights);
+  if (threadIdx.x == 0 && total <= 0) atomicOr(a.r.flag, kFlagWeights);
 }
 
 // Offspring j: position U_j = floor(((j + u) C) / N), ancestor = first i with
