@@ -209,8 +209,8 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
 
 // Coarse-grid constants of the frequency-domain model for observation time
 // T_obs: per envelope sample t_j = j T_obs / 64 the symmetric detector tensors
-// of the A and E channels, cos and sin of the orbital phase, t_j; then the 64
-// roots exp(-2 pi i k / 64). The constellation follows the first-order
+// of the A and E channels, cos and sin of the orbital phase, t_j; then the
+// per-lane FFT twiddles. The constellation follows the first-order
 // circular-orbit solution (guiding centre on the 1 AU circle, arms of length L
 // in a plane inclined by 60 degrees to the ecliptic); the Michelson tensor
 // with vertex k is (u u - v v) / 2 for the unit vectors towards spacecraft
@@ -268,10 +268,6 @@ void fd_table_host(double T_obs, std::vector<double>& tab) {
       tab[smcx::kFdTwiddleInv + st * 128 + 2 * l] = c;
       tab[smcx::kFdTwiddleInv + st * 128 + 2 * l + 1] = -sn;
     }
-  }
-  for (int k = 0; k < 64; ++k) {
-    tab[smcx::kFdRootsOffset + 2 * k] = std::cos(2.0 * kPi * k / 64.0);
-    tab[smcx::kFdRootsOffset + 2 * k + 1] = -std::sin(2.0 * kPi * k / 64.0);
   }
 }
 

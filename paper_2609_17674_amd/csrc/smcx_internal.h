@@ -94,7 +94,7 @@ struct PopArgs {
   int* flag;
   // frequency-domain (LISA Galactic-binary) problems
   const double* fd_data;   // [2][Bp][2] band spectrum of A and E (re, im), Bp = 128 or 256
-  const double* fd_table;  // per-lane coarse-grid constants and the 64 roots of unity
+  const double* fd_table;  // per-lane coarse-grid constants and FFT twiddles
   int64_t fd_k0;           // first bin of the band
   int64_t fd_B;            // bins in the band
   double fd_T_obs;         // observation time [s]
@@ -107,13 +107,12 @@ struct PopArgs {
   double fd2_T_obs, fd2_cnorm;
 };
 // Layout of fd_table: [64][kFdTableStride] (tensors of A, E; cos, sin of
-// the orbital phase; t_j), then [64][2] roots exp(-2 pi i k / 64), then the
-// per-lane twiddles of the six FFT stages, [6][64][2] for the forward
-// transform and [6][64][2] for the inverse (stage s has span 32 >> s; see
-// the transform in the frequency-domain kernels for the lane layout).
+// the orbital phase; t_j), then the per-lane twiddles of the six FFT stages,
+// [6][64][2] for the forward transform and [6][64][2] for the inverse (stage
+// s has span 32 >> s; see the transform in the frequency-domain kernels for
+// the lane layout).
 constexpr int kFdTableStride = 16;
-constexpr int kFdRootsOffset = 64 * kFdTableStride;
-constexpr int kFdTwiddleFwd = kFdRootsOffset + 128;
+constexpr int kFdTwiddleFwd = 64 * kFdTableStride;
 constexpr int kFdTwiddleInv = kFdTwiddleFwd + 6 * 128;
 constexpr int kFdTableSize = kFdTwiddleInv + 6 * 128;
 
