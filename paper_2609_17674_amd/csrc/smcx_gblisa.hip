@@ -639,36 +639,48 @@ __device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int 
 __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
                                            const double wr[2], const double wi[2], double gp[8]) {
   const double Ap = s.Ap, Ax = s.Ax;
-  const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
-  const V3& v = s.v;
-  const V3 ul = {-s.sb * s.sl, s.sb * s.cl, 0.0}, vl = {-s.cl, -s.sl, 0.0};
-  double G = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0;
+  // the terms that need the envelope, for both channels; the envelope's
+  // values are dead after this
+  double ur[2], ui[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const double ur = 0.5 * (wr[c] * e.cph + wi[c] * e.sph), ui = 0.5 * (wi[c] * e.cph - wr[c] * e.sph);
-    G += wi[c] * e.zr[c] - wr[c] * e.zi[c];
-    const double al = kPa * ur + kXa * ui, be = kPb * ur - kXb * ui;
-    const V3 y1 = {al * s.u.x + be * v.x, al * s.u.y + be * v.y, al * s.u.z};
-    const V3 y2 = {be * s.u.x - al * v.x, be * s.u.y - al * v.y, be * s.u.z};
-    double D[6];
-#pragma unroll
-    for (int x = 0; x < 6; ++x) D[x] = g.d(c, x);
-    const V3 Dy1 = mul_sym(D, y1), Dy2 = mul_sym(D, y2);
-    t2 += e.ar[c] * ur + e.ai[c] * ui;
-    t3 += dot3(s.n, Dy1);
-    t4 += dot3(ul, Dy1) + dot3(vl, Dy2);
-    t5 += e.Fx[c] * Ap * ur + e.Fp[c] * Ax * ui;
-    t6 += s.ci * e.Fp[c] * ur + e.Fx[c] * ui;
+    ur[c] = 0.5 * (wr[c] * e.cph + wi[c] * e.sph);
+    ui[c] = 0.5 * (wi[c] * e.cph - wr[c] * e.sph);
   }
+  const double G = (wi[0] * e.zr[0] - wr[0] * e.zi[0]) + (wi[1] * e.zr[1] - wr[1] * e.zi[1]);
+  const double t2 = (e.ar[0] * ur[0] + e.ai[0] * ui[0]) + (e.ar[1] * ur[1] + e.ai[1] * ui[1]);
+  const double t5 = (e.Fx[0] * Ap * ur[0] + e.Fp[0] * Ax * ui[0]) +
+                    (e.Fx[1] * Ap * ur[1] + e.Fp[1] * Ax * ui[1]);
+  const double t6 = (s.ci * e.Fp[0] * ur[0] + e.Fx[0] * ui[0]) +
+                    (s.ci * e.Fp[1] * ur[1] + e.Fx[1] * ui[1]);
   const double fi = s.f0 + s.fd * e.tau;
   gp[0] = kTwoPi * e.tau * G;
   gp[1] = 0.5 * kTwoPi * e.tau * e.tau * G;
   gp[2] = kLn10 * t2;
-  gp[3] = 2.0 * t3 + kTwoPi * fi * (-s.sb * e.doppler) * G;
-  gp[4] = 2.0 * t4 + kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G;
+  gp[3] = kTwoPi * fi * (-s.sb * e.doppler) * G;
+  gp[4] = kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G;
   gp[5] = 2.0 * t5;
   gp[6] = -2.0 * s.A * s.si * t6;
   gp[7] = G;
+  // the sky derivatives, one channel at a time (the barrier keeps the two
+  // channels' temporaries from being live together); v, ul and vl have no z
+  // component
+  const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
+  const double vx = -s.sl, vy = s.cl;
+  const double ulx = -s.sb * s.sl, uly = s.sb * s.cl, vlx = -s.cl, vly = -s.sl;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double al = kPa * ur[c] + kXa * ui[c], be = kPb * ur[c] - kXb * ui[c];
+    const V3 y1 = {al * s.u.x + be * vx, al * s.u.y + be * vy, al * s.u.z};
+    const V3 y2 = {be * s.u.x - al * vx, be * s.u.y - al * vy, be * s.u.z};
+    double D[6];
+#pragma unroll
+    for (int x = 0; x < 6; ++x) D[x] = g.d(c, x);
+    const V3 Dy1 = mul_sym(D, y1), Dy2 = mul_sym(D, y2);
+    gp[3] += 2.0 * dot3(s.n, Dy1);
+    gp[4] += 2.0 * ((ulx * Dy1.x + uly * Dy1.y) + (vlx * Dy2.x + vly * Dy2.y));
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 struct FdItem {
