@@ -111,6 +111,7 @@ void free_problem(smcx_problem* p) {
   (void)hipFree(p->d32);
   (void)hipFree(p->d64);
   (void)hipFree(p->fd_data);
+  (void)hipFree(p->fd_src);
   (void)hipFree(p->fd_table);
   (void)hipFree(p->order);
   (void)hipFree(p->n_active);
@@ -188,6 +189,7 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
   a.flag = p->flag;
   if (p->fd) {
     a.fd_data = p->fd_data;
+    a.fd_src = p->fd_src;
     a.fd_table = p->fd_table;
     a.fd_k0 = p->fd_k0;
     a.fd_B = p->fd_B;
@@ -468,6 +470,7 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
   const size_t n1 = (size_t)std::max<int64_t>(n_max, 1);
   struct { void** ptr; size_t bytes; } allocs[] = {
       {(void**)&p->fd_data, 4 * Bp * sizeof(double)},
+      {(void**)&p->fd_src, (size_t)std::max<int64_t>(m_max, 1) * 34 * sizeof(double)},
       {(void**)&p->fd_table, tab.size() * sizeof(double)},
       {(void**)&p->order, n1 * sizeof(int32_t)},
       {(void**)&p->n_active, sizeof(int32_t)},

@@ -94,12 +94,15 @@ struct Src {
   int64_t q;
 };
 
-// Source constants of a particle, kept per wave in LDS: lane k computes
-// those of source c0 + k of a chunk of kFdCacheK sources, and every lane
-// reads them back from there in both passes (a particle with at most
-// kFdCacheK sources fills the chunk once).
-constexpr int kFdCacheK = 16;
-constexpr int kSrcWords = 34;  // 33 used; rows stay 16-byte aligned
+// Source constants, one row of kSrcWords doubles per row of theta, written
+// by fd_src_kernel before each frequency-domain launch (one thread per
+// source) and read by the kernels at wave-uniform addresses through a
+// restrict-qualified pointer, so they arrive by scalar loads into scalar
+// registers instead of occupying vector registers in every lane. Words 0-32
+// hold the constants with the carrier bin q of the handle's record, word 33
+// the carrier bin under the bridge partner's observation time.
+constexpr int kSrcWords = 34;
+constexpr int kQOwn = 32, kQPartner = 33;
 
 __device__ __forceinline__ void src_store(double* c, const Src& s) {
   const double v[33] = {s.f0,    s.fd,    s.A,     s.cb,    s.sb,    s.cl,    s.sl,
@@ -111,7 +114,7 @@ __device__ __forceinline__ void src_store(double* c, const Src& s) {
   for (int x = 0; x < 33; ++x) c[x] = v[x];
 }
 
-__device__ __forceinline__ Src src_load(const double* c) {
+__device__ __forceinline__ Src src_load(const double* c, int qslot) {
   Src s;
   s.f0 = c[0]; s.fd = c[1]; s.A = c[2]; s.cb = c[3]; s.sb = c[4]; s.cl = c[5]; s.sl = c[6];
   s.c2p = c[7]; s.s2p = c[8]; s.ci = c[9]; s.si = c[10]; s.cyc0 = c[11]; s.Ap = c[12]; s.Ax = c[13];
@@ -123,7 +126,7 @@ __device__ __forceinline__ Src src_load(const double* c) {
   s.n = {c[26], c[27], c[28]};
   s.u = {c[29], c[30], c[31]};
   s.v = {-s.sl, s.cl, 0.0};
-  s.q = __builtin_bit_cast(int64_t, c[32]);  // stored as its bit pattern
+  s.q = __builtin_bit_cast(int64_t, c[qslot]);  // stored as its bit pattern
   return s;
 }
 
@@ -500,15 +503,16 @@ struct FdSide {
   LaneGeom g;        // this lane's grid constants in LDS
   int64_t k0, B;
   double T_obs, scale, cnorm;
+  int qslot;         // word of the source rows with this record's carrier bin
 };
 
 __device__ __forceinline__ FdSide own_side(const PopArgs& a, const FdTables& t, int lane) {
   return {a.fd_data, t.tw, LaneGeom{&t.geo[0][0][lane]}, a.fd_k0, a.fd_B, a.fd_T_obs, a.fd_scale,
-          a.inv_sigma2};
+          a.inv_sigma2, kQOwn};
 }
 __device__ __forceinline__ FdSide partner_side(const PopArgs& a, const FdTables& t, int lane) {
   return {a.fd2_data, t.tw, LaneGeom{&t.geo[1][0][lane]}, a.fd2_k0, a.fd2_B, a.fd2_T_obs,
-          a.fd2_T_obs / 64.0, a.fd2_cnorm};
+          a.fd2_T_obs / 64.0, a.fd2_cnorm, kQPartner};
 }
 
 template <int NR>
@@ -612,19 +616,7 @@ __device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g
   }
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
-// Sources c0 .. c0 + kFdCacheK - 1 (those below K) into the wave's cache.
-__device__ __forceinline__ void fill_cache(const double* theta, int64_t m0, int K, int c0, double T_obs,
-                                           int lane, double (*mine)[kSrcWords]) {
-  wave_sync();  // earlier reads of the cache are done
-  if (lane < kFdCacheK && c0 + lane < K) src_store(mine[lane], make_src(theta + (m0 + c0 + lane) * 8, T_obs));
-  wave_sync();
-}
 
 // This lane's share of the gradient of one source, sum_c Re(conj(w_c) dz_c,p)
 // for the eight parameters, without forming dz_c,p = (da_c,p / 2) e^{i ph} +
@@ -711,15 +703,15 @@ __device__ __forceinline__ bool fd_item(const PopArgs& a, int64_t rank, FdItem& 
 template <int MODE, int NR>
 __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, const FdItem& it,
                                             int lane, double w, bool first, bool last,
-                                            double (*mine)[kSrcWords]) {
+                                            const double* __restrict__ src) {
   const int64_t i = it.i;
   const double wc = w * sd.cnorm;  // weight * 4 / (T_obs S)
   const LaneGeom g = sd.g;
   Resid<NR> R;
   load_resid<NR>(sd, lane, R);
   for (int k = 0; k < it.K; ++k) {
-    if (k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
-    subtract_source<NR>(sd, src_load(mine[k % kFdCacheK]), g, lane, R, 1.0);
+    const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
+    subtract_source<NR>(sd, src_load(src + (int64_t)row * kSrcWords, sd.qslot), g, lane, R, 1.0);
   }
   if constexpr (MODE == 2) {
     if (a.theta_birth && a.dlogl_birth) {
@@ -732,7 +724,8 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
     if (a.death_idx && a.dlogl_death) {
       const int j = a.death_idx[i];
       if (j >= 0 && j < it.K) {
-        const Src s = make_src(a.theta + (it.m0 + j) * 8, sd.T_obs);
+        const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + j));
+        const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
         double rh, hh;
         overlap<NR>(sd, s, g, lane, R, &rh, &hh);
         const double v = -(wc * (rh + 0.5 * hh));
@@ -758,8 +751,8 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bin_lane(lane);
     for (int k = 0; k < it.K; ++k) {
-      if (it.K > kFdCacheK && k % kFdCacheK == 0) fill_cache(a.theta, it.m0, it.K, k, sd.T_obs, lane, mine);
-      const Src s = src_load(mine[k % kFdCacheK]);
+      const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
+      const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
       // residual window of the source in the inverse transform's input order
       // The window covers 64 consecutive band positions, one per residue
       // mod 64, so the lane holding a position's residual picks the register
@@ -813,7 +806,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
 // is (1 - beta) logL_partner + beta logL_own, so each particle runs on both
 // data sets.
 template <int MODE, int NR>
-__global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
+__global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __restrict__ src) {
   const int lane = threadIdx.x & 63;
   const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   FdItem it;
@@ -824,13 +817,11 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
   stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
   if (!work) return;
   const double b = a.beta ? a.beta[it.i] : 1.0;
-  __shared__ double cache[4][kFdCacheK][kSrcWords];
-  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   if (a.fd_bridge) {
-    fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, mine);
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, mine);
+    fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, src);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, src);
   } else {
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, mine);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, src);
   }
 }
 
@@ -843,8 +834,9 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a) {
 // One wave per particle; 36 sums per source.
 // blocks: F is [M][8][8], block k of particle i at F + (o0 + k) 64 (nothing
 // between blocks is written); otherwise the dense n x n block at F + f_off[i].
-__global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t* f_off, int64_t f_size,
-                                                        double* F, int blocks) {
+__global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const double* __restrict__ src,
+                                                        const int64_t* f_off, int64_t f_size, double* F,
+                                                        int blocks) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   __shared__ FdTables tabs;
@@ -873,16 +865,14 @@ __global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const int64_t
   const int lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
   // the lane holding entry (lo, hi) of the upper triangle after the sums
   const int holder = kSlot36[lo * 8 - lo * (lo - 1) / 2 + (hi - lo)];
-  __shared__ double cache[4][kFdCacheK][kSrcWords];
-  double(*mine)[kSrcWords] = cache[(threadIdx.x >> 6) & 3];
   for (int side = a.fd_bridge ? 0 : 1; side < 2; ++side) {
   const FdSide sd = side == 0 ? partner_side(a, tabs, lane) : own_side(a, tabs, lane);
   const double gs = (side == 0 ? 1.0 - b : b) * sd.cnorm * sd.scale * sd.scale * kNs * 0.25;
   const bool first = side == 0 || !a.fd_bridge;
   const LaneGeom g = sd.g;
   for (int k = 0; k < K; ++k) {
-    if (k % kFdCacheK == 0) fill_cache(a.theta, o0, K, k, sd.T_obs, lane, mine);
-    const Src s = src_load(mine[k % kFdCacheK]);
+    const int row = __builtin_amdgcn_readfirstlane((int)(o0 + k));
+    const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
     const Env e = envelope_amp(s, g);
     double acc[36];
 #pragma unroll
@@ -931,14 +921,43 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
     }
 }
 
+// The source rows of the particles the following launch works on (the same
+// work items and activity mask), one wave per particle and one lane per
+// source: constants with the carrier bins of both records (T2 = 0: no
+// partner, word 33 repeats word 32). Its cost follows the active set, as in
+// late NUTS leaves (one thread per particle measured slower there).
+__global__ __launch_bounds__(256) void fd_src_kernel(PopArgs a, double T2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  FdItem it;
+  if (!fd_item(a, rank, it)) return;
+  if (a.active && !a.active[it.i]) return;
+  for (int k = lane; k < it.K; k += 64) {
+    const int64_t m = it.m0 + k;
+    const Src s = make_src(a.theta + m * 8, a.fd_T_obs);
+    double* c = a.fd_src + m * kSrcWords;
+    src_store(c, s);
+    c[kQPartner] = T2 > 0.0 ? __builtin_bit_cast(double, (int64_t)floor(s.f0 * T2)) : c[kQOwn];
+  }
+}
+
+hipError_t launch_fd_src(const PopArgs& a, hipStream_t st) {
+  if (a.N == 0) return hipSuccess;
+  hipLaunchKernelGGL(fd_src_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a,
+                     a.fd_bridge ? a.fd2_T_obs : 0.0);
+  return hipGetLastError();
+}
+
 template <int MODE>
 hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
+  hipError_t e = launch_fd_src(a, st);
+  if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((a.N + 3) / 4)), block(256);
   if (a.fd_B <= 2 * kNs)
-    hipLaunchKernelGGL((fd_kernel<MODE, 2>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((fd_kernel<MODE, 2>), grid, block, 0, st, a, a.fd_src);
   else
-    hipLaunchKernelGGL((fd_kernel<MODE, 4>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((fd_kernel<MODE, 4>), grid, block, 0, st, a, a.fd_src);
   return hipGetLastError();
 }
 
@@ -957,7 +976,13 @@ hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
 hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
                             int blocks, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a,
+  // the metric walks every particle in natural order (no ordering pass ran)
+  PopArgs all = a;
+  all.order = nullptr;
+  all.active = nullptr;
+  hipError_t e = launch_fd_src(all, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a, a.fd_src,
                      f_offsets, f_size, F, blocks);
   return hipGetLastError();
 }

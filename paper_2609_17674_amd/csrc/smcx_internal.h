@@ -94,6 +94,7 @@ struct PopArgs {
   int* flag;
   // frequency-domain (LISA Galactic-binary) problems
   const double* fd_data;   // [2][Bp][2] band spectrum of A and E (re, im), Bp = 128 or 256
+  double* fd_src;           // [M][34] source constants (the handle's workspace)
   const double* fd_table;  // per-lane coarse-grid constants and FFT twiddles
   int64_t fd_k0;           // first bin of the band
   int64_t fd_B;            // bins in the band

@@ -31,6 +31,7 @@ struct smcx_problem {
   int64_t fd_k0 = 0, fd_B = 0;
   double fd_T_obs = 0, fd_S = 0;
   double* fd_data = nullptr;   // [2][Bp][2], Bp = 128 or 256, zero past B
+  double* fd_src = nullptr;    // [m_max][34] source constants, rewritten by every launch
   double* fd_table = nullptr;  // kFdTableSize doubles
   smcx_problem* partner = nullptr;  // bridge partner (smcx_set_bridge_partner), or none
   int max_nch = 0;       // capacity of part (chunks per particle)

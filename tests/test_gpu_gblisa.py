@@ -98,9 +98,9 @@ def test_birth_death_match_oracle(lib, orc):
 
 
 def test_particles_with_many_sources(lib, orc):
-    """K up to 40: the kernels keep source constants for 16 sources at a time,
-    so these particles take several fills in the forward pass, again in the
-    adjoint, and in the metric."""
+    """K up to 40: many sources per particle through the forward pass, the
+    adjoint, birth/death and the metric (one lane per source in the pass that
+    prepares their constants)."""
     w = wl.make_gblisa(N=40, k_lo=14, k_hi=40, n_inj=6, beta="uniform", noise=True, seed=430)
     say("gblisa_many_sources", "N", w.N, "M", w.M, "K max", int(w.K.max()))
     assert w.K.max() > 32 and w.K.min() <= 16
