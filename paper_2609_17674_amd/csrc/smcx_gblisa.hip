@@ -26,9 +26,9 @@
 #include <math.h>
 
 // The library is built without floating-point contraction so that the
-// time-domain kernels round as written. These FP64 kernels are checked
-// against the oracle to a tolerance and rely on no particular rounding of a
-// product followed by a sum, so here a * b + c may fuse into one FMA.
+// time-domain kernels round as written. These FP64 kernels are held to a
+// tolerance and rely on no particular rounding of a product followed by a
+// sum, so here a * b + c may fuse into one FMA.
 #pragma clang fp contract(fast)
 
 namespace smcx {
