@@ -195,6 +195,10 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
     a.fd_B = p->fd_B;
     a.fd_T_obs = p->fd_T_obs;
     a.fd_scale = p->fd_T_obs / 64.0;
+    a.n_cu = p->n_cu;
+    // three workgroups of the gradient kernel fit a compute unit at once; its
+    // grid holds at least this many (six per unit, or one per four particles)
+    a.fd_split = std::min<int64_t>(3 * (int64_t)p->n_cu, (N + 3) / 4);
     if (p->partner) {
       const smcx_problem* q = p->partner;
       a.fd_bridge = 1;
@@ -347,6 +351,8 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
   e = hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipDeviceGetAttribute"); }
 
   p->max_nch = cap_chunks(T);
@@ -449,6 +455,8 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipGetDevice"); }
   e = hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipDeviceGetAttribute"); }
   for (int k = 0; k < kNumKinds; ++k) p->tiling[k] = Tiling{16, 1024, 1, 1};
   p->max_nch = p->max_nch_grad = 1;
@@ -877,6 +885,7 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   std::memset(&na, 0, sizeof(na));
   na.P = p->P;
   na.D = max_depth;
+  na.n_cu = p->n_cu;
   na.k_max = p->k_max;
   na.N = N;
   na.M = M;
@@ -949,6 +958,10 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   auto doubling = [&](int j, hipStream_t s) -> hipError_t {
     smcx::NutsArgs nj = na;
     smcx::PopArgs aj = a;
+    // From the third doubling on few particles are still extending (trees
+    // end after one or two doublings for most): the leaf, merge and
+    // frequency-domain launches step through them on fixed grids.
+    nj.stride_grid = aj.stride_grid = j >= 2 ? 1 : 0;
     if (p->fd) {
       nj.list_next = p->nuts_list + (size_t)((j + 1) & 1) * nlist;
       if (j > 0) {

@@ -680,21 +680,25 @@ struct FdItem {
   int K;
 };
 
-// Work item of this wave (sorted mode: the ordering pass listed the valid
-// particles with K > 0, or all valid ones for birth/death).
-__device__ __forceinline__ bool fd_item(const PopArgs& a, int64_t rank, FdItem& it) {
-  if (a.order) {
-    if (rank >= *a.n_active) return false;
-    it.i = a.order[rank];
-  } else {
-    if (rank >= a.N) return false;
-    it.i = rank;
-  }
+// Listed work items of a launch: the ordering pass's count in sorted mode
+// (valid particles with K > 0, or all valid ones for birth/death), else N.
+__device__ __forceinline__ int64_t fd_count(const PopArgs& a) {
+  return a.order ? (int64_t)*a.n_active : a.N;
+}
+
+// Work item at rank < fd_count(a); false for a particle whose offsets are
+// invalid or exceed k_max.
+__device__ __forceinline__ bool fd_item_at(const PopArgs& a, int64_t rank, FdItem& it) {
+  it.i = a.order ? (int64_t)a.order[rank] : rank;
   const int64_t o0 = a.offsets[it.i], o1 = a.offsets[it.i + 1];
   if (!(o0 >= 0 && o1 >= o0 && o1 <= a.M && o1 - o0 <= a.k_max)) return false;
   it.m0 = o0;
   it.K = (int)(o1 - o0);
   return true;
+}
+
+__device__ __forceinline__ bool fd_active_at(const PopArgs& a, int64_t rank, FdItem& it) {
+  return fd_item_at(a, rank, it) && !(a.active && !a.active[it.i]);
 }
 
 // One particle on one data set, weighted by w; the first side writes the
@@ -703,7 +707,8 @@ __device__ __forceinline__ bool fd_item(const PopArgs& a, int64_t rank, FdItem& 
 template <int MODE, int NR>
 __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, const FdItem& it,
                                             int lane, double w, bool first, bool last,
-                                            const double* __restrict__ src) {
+                                            const double* __restrict__ src, int k_first = 0,
+                                            int k_step = 1) {
   const int64_t i = it.i;
   const double wc = w * sd.cnorm;  // weight * 4 / (T_obs S)
   const LaneGeom g = sd.g;
@@ -743,14 +748,14 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
 #pragma unroll
     for (int r = 0; r < NR; ++r) ss = fma(R.re[c][r], R.re[c][r], fma(R.im[c][r], R.im[c][r], ss));
   ss = wave_sum(ss, lane);
-  if (lane == 0 && a.logl) {
+  if (lane == 0 && k_first == 0 && a.logl) {
     const double v = -0.5 * wc * ss;
     a.logl[i] = first ? v : a.logl[i] + v;
   }
   if constexpr (MODE == 1) {
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bin_lane(lane);
-    for (int k = 0; k < it.K; ++k) {
+    for (int k = k_first; k < it.K; k += k_step) {
       const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
       const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
       // residual window of the source in the inverse transform's input order
@@ -806,22 +811,75 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
 // is (1 - beta) logL_partner + beta logL_own, so each particle runs on both
 // data sets.
 template <int MODE, int NR>
-__global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __restrict__ src) {
-  const int lane = threadIdx.x & 63;
-  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  FdItem it;
-  const bool work = fd_item(a, rank, it) && !(a.active && !a.active[it.i]);
-  // a workgroup without an active particle (late NUTS leaves) leaves at once
-  if (!__syncthreads_or(work)) return;
-  __shared__ FdTables tabs;
-  stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
-  if (!work) return;
+__device__ __forceinline__ void fd_run(const PopArgs& a, const FdTables& tabs, const FdItem& it,
+                                       int lane, const double* __restrict__ src, int k_first,
+                                       int k_step) {
   const double b = a.beta ? a.beta[it.i] : 1.0;
   if (a.fd_bridge) {
-    fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, src);
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, src);
+    fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, src,
+                          k_first, k_step);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, src, k_first,
+                          k_step);
   } else {
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, src);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, src, k_first,
+                          k_step);
+  }
+}
+
+// STRIDED (the leapfrog gradient of late NUTS doublings on the 128-bin band):
+// a grid smaller than the population whose workgroups step through the
+// listed particles. Otherwise one pass, one particle per wave, as in full
+// passes, where the hardware hands the workgroups out in the K-sorted order
+// (measured faster than the loop, whose form also keeps more registers live
+// in the other variants).
+template <int MODE, int NR, bool STRIDED>
+__global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __restrict__ src) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int64_t n = fd_count(a);
+  __shared__ FdTables tabs;
+  FdItem it;
+  if constexpr (!STRIDED) {
+    const int64_t rank = (int64_t)blockIdx.x * waves + wave;
+    const bool work = rank < n && fd_active_at(a, rank, it);
+    // a workgroup without an active particle leaves at once
+    if (!__syncthreads_or(work)) return;
+    stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
+    if (work) fd_run<MODE, NR>(a, tabs, it, lane, src, 0, 1);
+  } else {
+    // Few listed particles (late NUTS leaves): the waves of a workgroup
+    // share one particle. Each builds the whole residual and takes every
+    // waves-th source of the gradient pass, so the results are those of one
+    // wave per particle while the latency of a particle drops to about half
+    // and four times as many SIMDs hold work.
+    const bool split = a.order && a.fd_split > 0 && n <= a.fd_split;
+    const int64_t per = split ? 1 : waves;  // particles of one workgroup pass
+    const int64_t stride = (int64_t)gridDim.x * per;
+    const int k_first = split ? wave : 0, k_step = split ? waves : 1;
+    // this wave's first active item, found before the tables are staged (a
+    // workgroup without one leaves at once); the next is looked for after
+    // each particle
+    int64_t r0 = (int64_t)blockIdx.x * per;
+    bool have = false;
+    for (; r0 < n && !have; r0 += stride) {
+      const int64_t rank = split ? r0 : r0 + wave;
+      have = rank < n && fd_active_at(a, rank, it);
+    }
+    if (!__syncthreads_or(have)) return;
+    stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
+    while (have) {
+      // the lane index, opaque to the compiler in each pass: nothing derived
+      // from it (table addresses, lane geometry) stays live from one
+      // particle to the next, which would cost a wave per SIMD
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      fd_run<MODE, NR>(a, tabs, it, ln, src, k_first, k_step);
+      have = false;
+      for (; r0 < n && !have; r0 += stride) {
+        const int64_t rank = split ? r0 : r0 + wave;
+        have = rank < n && fd_active_at(a, rank, it);
+      }
+    }
   }
 }
 
@@ -922,28 +980,45 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
 }
 
 // The source rows of the particles the following launch works on (the same
-// work items and activity mask), one wave per particle and one lane per
-// source: constants with the carrier bins of both records (T2 = 0: no
-// partner, word 33 repeats word 32). Its cost follows the active set, as in
-// late NUTS leaves (one thread per particle measured slower there).
+// work items and activity mask): constants with the carrier bins of both
+// records (T2 = 0: no partner, word 33 repeats word 32). A group of
+// kSrcGroup lanes per particle, one lane per source, four particles to a
+// wave: a whole wave per particle left most lanes idle at K <= 10, and one
+// thread per particle measured slower in late NUTS leaves, where few
+// particles are active. The cost follows the active set.
+constexpr int kSrcGroup = 16;
 __global__ __launch_bounds__(256) void fd_src_kernel(PopArgs a, double T2) {
-  const int lane = threadIdx.x & 63;
-  const int64_t rank = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  FdItem it;
-  if (!fd_item(a, rank, it)) return;
-  if (a.active && !a.active[it.i]) return;
-  for (int k = lane; k < it.K; k += 64) {
-    const int64_t m = it.m0 + k;
-    const Src s = make_src(a.theta + m * 8, a.fd_T_obs);
-    double* c = a.fd_src + m * kSrcWords;
-    src_store(c, s);
-    c[kQPartner] = T2 > 0.0 ? __builtin_bit_cast(double, (int64_t)floor(s.f0 * T2)) : c[kQOwn];
+  const int sub = threadIdx.x & (kSrcGroup - 1);
+  const int64_t n = fd_count(a);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kSrcGroup);
+  for (int64_t rank = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSrcGroup; rank < n;
+       rank += stride) {
+    FdItem it;
+    if (!fd_active_at(a, rank, it)) continue;
+    for (int k = sub; k < it.K; k += kSrcGroup) {
+      const int64_t m = it.m0 + k;
+      const Src s = make_src(a.theta + m * 8, a.fd_T_obs);
+      double* c = a.fd_src + m * kSrcWords;
+      src_store(c, s);
+      c[kQPartner] = T2 > 0.0 ? __builtin_bit_cast(double, (int64_t)floor(s.f0 * T2)) : c[kQOwn];
+    }
   }
+}
+
+// With a.stride_grid, grids of a fixed size per compute unit whose
+// workgroups step through the listed particles: a grid as large as the
+// population costs a dispatch per workgroup even when few particles are
+// listed (late NUTS doublings). Full passes keep one workgroup per group of
+// particles, which the hardware hands out in the K-sorted order.
+unsigned fd_grid(const PopArgs& a, int64_t per_block, int64_t blocks_per_cu) {
+  const int64_t need = (a.N + per_block - 1) / per_block;
+  const int64_t cap = blocks_per_cu * (a.n_cu > 0 ? a.n_cu : 256);
+  return (unsigned)std::max<int64_t>(1, a.stride_grid ? std::min(need, cap) : need);
 }
 
 hipError_t launch_fd_src(const PopArgs& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
-  hipLaunchKernelGGL(fd_src_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a,
+  hipLaunchKernelGGL(fd_src_kernel, dim3(fd_grid(a, 256 / kSrcGroup, 8)), dim3(256), 0, st, a,
                      a.fd_bridge ? a.fd2_T_obs : 0.0);
   return hipGetLastError();
 }
@@ -953,11 +1028,17 @@ hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   hipError_t e = launch_fd_src(a, st);
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((a.N + 3) / 4)), block(256);
+  const dim3 block(256);
+  if (MODE == 1 && a.stride_grid && a.fd_B <= 2 * kNs) {
+    // three workgroups fit a compute unit at once: two rounds of them
+    hipLaunchKernelGGL((fd_kernel<1, 2, true>), dim3(fd_grid(a, 4, 6)), block, 0, st, a, a.fd_src);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)((a.N + 3) / 4));
   if (a.fd_B <= 2 * kNs)
-    hipLaunchKernelGGL((fd_kernel<MODE, 2>), grid, block, 0, st, a, a.fd_src);
+    hipLaunchKernelGGL((fd_kernel<MODE, 2, false>), grid, block, 0, st, a, a.fd_src);
   else
-    hipLaunchKernelGGL((fd_kernel<MODE, 4>), grid, block, 0, st, a, a.fd_src);
+    hipLaunchKernelGGL((fd_kernel<MODE, 4, false>), grid, block, 0, st, a, a.fd_src);
   return hipGetLastError();
 }
 

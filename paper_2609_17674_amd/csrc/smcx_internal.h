@@ -100,6 +100,13 @@ struct PopArgs {
   int64_t fd_B;            // bins in the band
   double fd_T_obs;         // observation time [s]
   double fd_scale;         // T_obs / 64
+  int64_t fd_split;        // gradient launches over at most this many listed particles
+                           // give each particle a whole workgroup (0: never); at most
+                           // the launch's workgroups
+  int n_cu;                // compute units of the device (grid sizes)
+  int stride_grid;         // 1: launches whose kernels step through the listed particles
+                           // take a fixed grid per compute unit (few listed), 0: a
+                           // workgroup per group of particles
   // bridge between two records (eq. reuse_bridge): the partner handle's data
   int fd_bridge;           // 1: target (1 - beta) logL_partner + beta logL_own
   const double* fd2_data;
@@ -198,6 +205,9 @@ struct NutsArgs {
   const int* nlist;
   int32_t* list_next;
   int* flag;
+  int n_cu;                // compute units of the device (grid sizes)
+  int stride_grid;         // 1: leaf and merge take a fixed grid per compute unit
+                           // (few listed particles), 0: a workgroup per particle
 };
 constexpr int kNutsMetricMax = 128;  // coordinates per particle with a metric (two per lane)
 constexpr int kNutsMaxDepth = 10;

@@ -28,11 +28,13 @@
 // particle, so it moves from the gradient pass's epilogue into the leaf
 // kernel.
 //
-// One workgroup of one wave handles one particle; lanes run over its K*P
+// One workgroup of one wave handles one particle at a time; lanes run over its K*P
 // coordinates (at most two each when a metric is used).
 #include "smcx_internal.h"
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace smcx {
 namespace {
@@ -74,14 +76,16 @@ __device__ __forceinline__ View view_of(const NutsArgs& a) {
 
 // The workgroup's particle in the current doubling's list (leaf and merge),
 // or in natural order when no list is given.
-__device__ __forceinline__ View view_of_list(const NutsArgs& a) {
-  if (!a.list) return view_of(a);
+__device__ __forceinline__ int64_t list_count(const NutsArgs& a) {
+  return a.list ? (int64_t)*a.nlist : a.N;
+}
+// Particle at rank r < list_count(a): the r-th listed one, or particle r.
+__device__ __forceinline__ View view_at(const NutsArgs& a, int64_t r) {
   View v;
   v.lane = threadIdx.x & 63;
-  v.ok = (int64_t)blockIdx.x < (int64_t)*a.nlist;
-  if (!v.ok) return v;
-  v.i = a.list[blockIdx.x];
+  v.i = a.list ? (int64_t)a.list[r] : r;
   const int64_t o0 = a.offsets[v.i], o1 = a.offsets[v.i + 1];
+  v.ok = o0 >= 0 && o1 >= o0 && o1 <= a.M;
   v.x0 = o0 * a.P;
   v.x1 = o1 * a.P;
   v.K = (int)(o1 - o0);
@@ -243,10 +247,9 @@ __global__ __launch_bounds__(64) void nuts_init_kernel(NutsArgs a) {
 
 // Leaf n of the doubling at depth j (the frontier has just been moved by one
 // leapfrog step: qF, pF, gF and the frontier logL are current).
-__global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
-  __shared__ double sh[kNutsMetricMax];
-  const View v = view_of_list(a);
-  if (!v.ok || !a.active[v.i]) return;
+__device__ __forceinline__ void leaf_step(const NutsArgs& a, const View& v, int j, int n,
+                                          double* sh) {
+  if (!a.active[v.i]) return;
   NutsState& s = a.state[v.i];
   const double e = a.eps * (double)a.dir[v.i];
   double wg[2];
@@ -333,10 +336,8 @@ __global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n)
 }
 
 // End of the doubling at depth j: merge the (valid) subtree into the trajectory.
-__global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
-  __shared__ double sh[kNutsMetricMax];
-  const View v = view_of_list(a);
-  if (!v.ok || !a.active[v.i]) return;
+__device__ __forceinline__ void merge_step(const NutsArgs& a, const View& v, int j, double* sh) {
+  if (!a.active[v.i]) return;
   NutsState& s = a.state[v.i];
   const bool take = a.u_tree[v.i * a.D + j] < exp(s.lw_sub - s.lw_tree);
   const int8_t d = a.dir[v.i];
@@ -386,6 +387,30 @@ __global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
   drift(a, v, a.eps * (double)dn, sh);
 }
 
+// The leaf and merge passes step through the listed particles (all of them
+// in natural order), one wave per particle at a time, on the grid that
+// stride_grid() picks: late doublings list few particles, and a grid as
+// large as the population would pay a dispatch per particle there.
+__global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
+  __shared__ double sh[kNutsMetricMax];
+  const int64_t cnt = list_count(a);
+  for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const View v = view_at(a, r);
+    if (v.ok) leaf_step(a, v, j, n, sh);
+    __syncthreads();  // sh is the next particle's
+  }
+}
+
+__global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
+  __shared__ double sh[kNutsMetricMax];
+  const int64_t cnt = list_count(a);
+  for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const View v = view_at(a, r);
+    if (v.ok) merge_step(a, v, j, sh);
+    __syncthreads();  // sh is the next particle's
+  }
+}
+
 __global__ __launch_bounds__(64) void nuts_finalize_kernel(NutsArgs a) {
   const View v = view_of(a);
   if (!v.ok) {
@@ -410,6 +435,13 @@ __global__ __launch_bounds__(64) void nuts_finalize_kernel(NutsArgs a) {
 }
 
 dim3 grid_of(int64_t N) { return dim3((unsigned)N); }  // one wave-sized workgroup per particle
+// With a.stride_grid, 32 wave-sized workgroups per compute unit (its full
+// occupancy), at most N; else one per particle, which the hardware hands out
+// faster than a fixed assignment in a full pass.
+dim3 stride_grid(const NutsArgs& a) {
+  const int64_t cap = 32 * (int64_t)(a.n_cu > 0 ? a.n_cu : 256);
+  return dim3((unsigned)std::max<int64_t>(1, a.stride_grid ? std::min(a.N, cap) : a.N));
+}
 
 }  // namespace
 
@@ -418,11 +450,11 @@ hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_leaf_kernel, grid_of(a.N), dim3(64), 0, st, a, j, n);
+  hipLaunchKernelGGL(nuts_leaf_kernel, stride_grid(a), dim3(64), 0, st, a, j, n);
   return hipGetLastError();
 }
 hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_merge_kernel, grid_of(a.N), dim3(64), 0, st, a, j);
+  hipLaunchKernelGGL(nuts_merge_kernel, stride_grid(a), dim3(64), 0, st, a, j);
   return hipGetLastError();
 }
 hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st) {

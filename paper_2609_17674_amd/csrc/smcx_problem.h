@@ -21,6 +21,7 @@ struct smcx_problem {
   int64_t n_max = 0, m_max = 0;
   int device = 0;
   int lds_max = 0;  // LDS bytes per workgroup of the device
+  int n_cu = 0;     // compute units of the device
   float* d32 = nullptr;
   double* d64 = nullptr;
   std::vector<double> prefix;  // FP64 prefix sums of d^2, prefix[s] = sum_{q<s} d_q^2

@@ -132,6 +132,124 @@ def test_particles_with_many_sources(lib, orc):
         assert np.all(np.abs(got - ref[i]) <= 1e-9 * np.outer(dg, dg)), i
 
 
+@pytest.mark.parametrize("B,k_hi", [(128, 10), (200, 40)], ids=["band128", "band200_K40"])
+def test_few_listed_particles_share_a_workgroup(lib, orc, B, k_hi):
+    """A gradient launch over few listed particles gives each particle a whole
+    workgroup, whose waves take every fourth source: logL, gradient and the
+    leapfrog step equal, bit for bit, those of the same particles as a
+    population of their own (one wave per particle), and match the oracle."""
+    base = wl.make_gblisa(N=24, k_lo=1, k_hi=k_hi, n_inj=6, beta="uniform", noise=False,
+                          seed=431)
+    d = orc.gblisa_spectrum(base.inj, base.T_obs, base.k0, B)
+    n_big = 600
+    idx = np.sort(np.random.default_rng(432).choice(n_big, size=base.N, replace=False))
+    counts = np.zeros(n_big, dtype=np.int64)
+    counts[idx] = base.K
+    off_big = np.concatenate([[0], np.cumsum(counts)])
+    beta_big = np.full(n_big, 0.5)
+    beta_big[idx] = base.beta
+    say("gblisa_split", "B", B, "K max", int(base.K.max()), "listed", base.N, "of", n_big)
+    rng = np.random.default_rng(433)
+    scales = np.array([0.05 / base.T_obs, 1e-19, 0.02, 0.02, 0.02, 0.02, 0.02, 0.05])
+    eps = 1e-17
+    p0 = 0.5 * rng.standard_normal(base.theta.shape) * scales / eps
+    dirs = np.where(rng.random(base.N) < 0.5, -1, 1).astype(np.int8)
+    dirs_big = np.ones(n_big, dtype=np.int8)
+    dirs_big[idx] = dirs
+    out = []
+    for N, off, be, di in ((base.N, base.offsets, base.beta, dirs),
+                           (n_big, off_big, beta_big, dirs_big)):
+        prob = lib.Problem.frequency_domain(GBLISA, dev(d), base.k0, base.T_obs, base.S,
+                                            base.k_max, N, base.M)
+        o, th, b = dev(off), dev(base.theta), dev(be)
+        l, g = lib.logl_grad_batch(prob, o, th, b)
+        q1, p1, g1, l1 = lib.leapfrog(prob, o, b, eps, th, dev(p0), g, dir=dev(di))
+        torch.cuda.synchronize()
+        prob.device_status()
+        out.append([x.cpu().numpy() for x in (l, g, q1, p1, g1, l1)])
+    (l, g, q1, p1, g1, l1), (lb, gb, q1b, p1b, g1b, l1b) = out
+    assert np.array_equal(lb[idx], l) and np.array_equal(l1b[idx], l1)
+    for x, y in ((g, gb), (q1, q1b), (p1, p1b), (g1, g1b)):
+        assert np.array_equal(x, y)
+    rl, rg = orc.gblisa_logl_grad(d, base.k0, base.T_obs, base.S, base.offsets, base.theta,
+                                  base.beta)
+    assert np.all(np.abs(l - rl) <= 1e-9 * np.abs(rl))
+    for i in range(base.N):
+        a, b = base.offsets[i], base.offsets[i + 1]
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg[a:b] / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn), i
+
+
+def _nuts_gb(lib, d, w, N, off, theta, beta, D, eps, draws, W):
+    """One GB NUTS transition (block mass matrix W [M, 8, 8]); numpy results."""
+    mom, dirs, ul, ut = draws
+    prob = lib.Problem.frequency_domain(GBLISA, dev(d), w.k0, w.T_obs, w.S, w.k_max, N,
+                                        theta.shape[0])
+    lib.nuts_reserve(prob, D)
+    o, th, be = dev(off), dev(theta), dev(beta)
+    l, g = lib.logl_grad_batch(prob, o, th, be)
+    q = th.clone()
+    depth, steps, status = lib.nuts_transition(prob, o, be, eps, D, q, l, g, dev(mom), dev(dirs),
+                                               dev(ul), dev(ut), metric_blocks=dev(W))
+    torch.cuda.synchronize()
+    prob.device_status()
+    return [x.cpu().numpy() for x in (q, l, g, depth, steps, status)]
+
+
+def test_nuts_late_doublings_step_through_the_listed_particles(lib, orc):
+    """From the third doubling on, the NUTS gradient, leaf and merge launches
+    take fixed grids whose workgroups step through the listed particles, and
+    few listed particles share workgroups. Per-particle results do not
+    depend on that: a population of 12000 (more particles still extending
+    than one pass of the grid holds) equals, bit for bit, its two halves
+    run alone (one pass each); 24 particles among 576 with K = 0 (a
+    workgroup each) equal the 24 alone."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    D, eps = 3, 0.05
+    scales = np.array([0.05 / wl.GBLISA_T_OBS, 1e-19, 0.02, 0.02, 0.02, 0.02, 0.02, 0.05])
+    w = wl.make_gblisa(N=12000, k_lo=1, k_hi=3, n_inj=6, beta="uniform", noise=True, seed=434)
+    d = _data(orc, w)
+    draws = wl.nuts_draws(w.N, w.M, 8, D, seed=435)
+    W = np.broadcast_to(np.diag(scales), (w.M, 8, 8)).copy()
+    say("gblisa_nuts_strided", "N", w.N, "M", w.M, "CUs", n_cu)
+    full = _nuts_gb(lib, d, w, w.N, w.offsets, w.theta, w.beta, D, eps, draws, W)
+    assert np.sum(full[3] >= D) > 6 * n_cu * 4  # more than one pass at the last doubling
+    h = w.N // 2
+    parts = []
+    for lo, hi in ((0, h), (h, w.N)):
+        a, b = w.offsets[lo], w.offsets[hi]
+        sub = (draws[0][a:b], draws[1][lo:hi], draws[2][lo:hi], draws[3][lo:hi])
+        parts.append(_nuts_gb(lib, d, w, hi - lo, w.offsets[lo:hi + 1] - a, w.theta[a:b],
+                              w.beta[lo:hi], D, eps, sub, W[a:b]))
+    for x, y0, y1 in zip(full, *parts):
+        assert np.array_equal(x, np.concatenate([y0, y1]))
+    # few listed particles among many without sources
+    m = 24
+    few = wl.make_gblisa(N=m, k_lo=1, k_hi=3, n_inj=6, beta="uniform", noise=True, seed=436)
+    fd_ = _data(orc, few)
+    fdraws = wl.nuts_draws(m, few.M, 8, D, seed=437)
+    fW = np.broadcast_to(np.diag(scales), (few.M, 8, 8)).copy()
+    alone = _nuts_gb(lib, fd_, few, m, few.offsets, few.theta, few.beta, D, eps, fdraws, fW)
+    n_big = 600
+    idx = np.sort(np.random.default_rng(438).choice(n_big, size=m, replace=False))
+    counts = np.zeros(n_big, dtype=np.int64)
+    counts[idx] = few.K
+    off_big = np.concatenate([[0], np.cumsum(counts)])
+    beta_big = np.full(n_big, 0.5)
+    beta_big[idx] = few.beta
+    dirs_big = np.ones((n_big, D), dtype=np.int8)
+    dirs_big[idx] = fdraws[1]
+    ul_big = np.full((n_big, (1 << D) - 1), 0.5)
+    ul_big[idx] = fdraws[2]
+    ut_big = np.full((n_big, D), 0.5)
+    ut_big[idx] = fdraws[3]
+    among = _nuts_gb(lib, fd_, few, n_big, off_big, few.theta, beta_big, D, eps,
+                     (fdraws[0], dirs_big, ul_big, ut_big), fW)
+    assert np.array_equal(among[0], alone[0]) and np.array_equal(among[2], alone[2])
+    for k in (1, 3, 4, 5):
+        assert np.array_equal(among[k][idx], alone[k])
+
+
 def test_invalid_particles_and_refusals(lib, orc):
     w = wl.make_gblisa(N=6, k_lo=1, k_hi=3, n_inj=2, seed=403)
     say("gblisa_invalid")
