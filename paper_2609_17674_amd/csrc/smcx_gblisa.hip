@@ -892,7 +892,9 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __rest
 // One wave per particle; 36 sums per source.
 // blocks: F is [M][8][8], block k of particle i at F + (o0 + k) 64 (nothing
 // between blocks is written); otherwise the dense n x n block at F + f_off[i].
-__global__ __launch_bounds__(256) void fd_metric_kernel(PopArgs a, const double* __restrict__ src,
+// Held to 168 VGPRs (it needs 171 unconstrained; the excess goes to SGPR
+// spills into VGPR lanes, no scratch), which gives three waves per SIMD.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void fd_metric_kernel(PopArgs a, const double* __restrict__ src,
                                                         const int64_t* f_off, int64_t f_size, double* F,
                                                         int blocks) {
   const int lane = threadIdx.x & 63;
