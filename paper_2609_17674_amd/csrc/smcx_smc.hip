@@ -40,33 +40,64 @@ __device__ void block_sum2(double& a, double& b, double* sh) {
   }
 }
 
-// Exclusive prefix sum over the block of one int64 per thread (thread order),
-// and the block's total, the same in every thread. Integer sums are exact,
-// so the grouping (a scan within each wave, then the waves in order) does not
-// change the result. wsum: kBlockWaves entries of shared memory.
-__device__ int64_t block_scan_excl(int64_t v, int64_t* wsum, int64_t* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  int64_t before = 0, tot = 0;
-  for (int i = 0; i < kBlockWaves; ++i) {
-    const int64_t t = wsum[i];
-    before += i < w ? t : 0;
-    tot += t;
-  }
-  __syncthreads();  // wsum may be reused
-  *total = tot;
-  return before + x - v;
-}
-
 // Loads per batch in the single-block prefix passes: the loads of a batch are
 // in flight together.
 constexpr int kScanBatch = 16;
+
+// Prefix sums over the block of the int64 values value(i), i < N, for the
+// single-block rebuild passes: wave w takes a contiguous segment of items in
+// chunks of 64, lane l holding item c + l, so every load is coalesced and
+// kScanBatch chunks are in flight together. out(i, before, through) receives
+// the sums of the items before i and through i. Integer sums are exact, so
+// the grouping does not change them. Returns the total (all threads).
+template <class Val, class Out>
+__device__ int64_t block_prefix(int64_t N, Val value, Out out, int64_t* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t seg = ((N + kBlockWaves - 1) / kBlockWaves + 63) / 64 * 64;
+  const int64_t s0 = (int64_t)w * seg, s1 = s0 + seg < N ? s0 + seg : N;
+  constexpr int64_t kSpan = 64 * kScanBatch;
+  int64_t s = 0;
+  for (int64_t c0 = s0; c0 < s1; c0 += kSpan) {
+    int64_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      const int64_t i = c0 + 64 * u + lane;
+      v[u] = i < s1 ? value(i) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) s += v[u];
+  }
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) wsum[w] = s;
+  __syncthreads();
+  int64_t run = 0, total = 0;
+  for (int i = 0; i < kBlockWaves; ++i) {
+    const int64_t x = wsum[i];
+    run += i < w ? x : 0;
+    total += x;
+  }
+  __syncthreads();  // wsum may be reused
+  for (int64_t c0 = s0; c0 < s1; c0 += kSpan) {
+    int64_t v[kScanBatch];
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      const int64_t i = c0 + 64 * u + lane;
+      v[u] = i < s1 ? value(i) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kScanBatch; ++u) {
+      int64_t x = v[u];
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+      }
+      const int64_t i = c0 + 64 * u + lane;
+      if (i < s1) out(i, run + x - v[u], run + x);
+      run += __shfl(x, 63);
+    }
+  }
+  return total;
+}
 
 __device__ double block_max(double a, double* sh) {
   for (int o = 32; o >= 1; o >>= 1) a = fmax(a, __shfl_xor(a, o));
@@ -241,29 +272,9 @@ __device__ __forceinline__ bool source_rows(const RebuildArgs& a, int64_t i, int
 // Exclusive prefix sum of count[0..N) into offsets_out[0..N] (one block).
 __global__ __launch_bounds__(kBlock) void csr_scan_kernel(RebuildArgs a) {
   __shared__ int64_t wsum[kBlockWaves];
-  const int64_t per = (a.N + kBlock - 1) / kBlock;
-  const int64_t b0 = (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < a.N ? b0 + per : a.N;
-  int64_t s = 0;
-  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
-    int64_t v[kScanBatch];
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) v[u] = i0 + u < b1 ? a.count[i0 + u] : 0;
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) s += v[u];
-  }
-  int64_t total;
-  int64_t run = block_scan_excl(s, wsum, &total);
-  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
-    int64_t v[kScanBatch];
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) v[u] = i0 + u < b1 ? a.count[i0 + u] : 0;
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) {
-      if (i0 + u < b1) a.offsets_out[i0 + u] = run;
-      run += v[u];
-    }
-  }
+  const int64_t total = block_prefix(
+      a.N, [&](int64_t i) { return a.count[i]; },
+      [&](int64_t i, int64_t before, int64_t) { a.offsets_out[i] = before; }, wsum);
   if (threadIdx.x == 0) {
     a.offsets_out[a.N] = total;
     if (total > a.m_cap) atomicOr(a.flag, kFlagCapacity);
@@ -310,30 +321,9 @@ __device__ __forceinline__ int64_t weight_units(double w) {
 
 __global__ __launch_bounds__(kBlock) void resample_prefix_kernel(ResampleArgs a) {
   __shared__ int64_t wsum[kBlockWaves];
-  const int64_t N = a.r.N;
-  const int64_t per = (N + kBlock - 1) / kBlock;
-  const int64_t b0 = (int64_t)threadIdx.x * per;
-  const int64_t b1 = b0 + per < N ? b0 + per : N;
-  int64_t s = 0;
-  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
-    double w[kScanBatch];
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) w[u] = i0 + u < b1 ? a.w_norm[i0 + u] : 0.0;
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) s += weight_units(w[u]);
-  }
-  int64_t total;
-  int64_t run = block_scan_excl(s, wsum, &total);
-  for (int64_t i0 = b0; i0 < b1; i0 += kScanBatch) {
-    double w[kScanBatch];
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) w[u] = i0 + u < b1 ? a.w_norm[i0 + u] : 0.0;
-#pragma unroll
-    for (int u = 0; u < kScanBatch; ++u) {
-      run += weight_units(w[u]);
-      if (i0 + u < b1) a.cum[i0 + u] = run;
-    }
-  }
+  const int64_t total = block_prefix(
+      a.r.N, [&](int64_t i) { return weight_units(a.w_norm[i]); },
+      [&](int64_t i, int64_t, int64_t through) { a.cum[i] = through; }, wsum);
   if (threadIdx.x == 0 && total <= 0) atomicOr(a.r.flag, kFlagWeights);
 }
 
