@@ -959,9 +959,12 @@ int nuts_transition(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
     smcx::NutsArgs nj = na;
     smcx::PopArgs aj = a;
     // From the third doubling on few particles are still extending (trees
-    // end after one or two doublings for most): the leaf, merge and
-    // frequency-domain launches step through them on fixed grids.
-    nj.stride_grid = aj.stride_grid = j >= 2 ? 1 : 0;
+    // end after one or two doublings for most): on the frequency-domain
+    // model the leaf, merge and gradient launches step through them on fixed
+    // grids, which removes the floor of grids sized to the population. The
+    // time-domain workloads' populations are smaller, and there the
+    // one-pass kernels (half the registers) measured faster.
+    nj.stride_grid = aj.stride_grid = p->fd && j >= 2 ? 1 : 0;
     if (p->fd) {
       nj.list_next = p->nuts_list + (size_t)((j + 1) & 1) * nlist;
       if (j > 0) {

@@ -387,27 +387,46 @@ __device__ __forceinline__ void merge_step(const NutsArgs& a, const View& v, int
   drift(a, v, a.eps * (double)dn, sh);
 }
 
-// The leaf and merge passes step through the listed particles (all of them
-// in natural order), one wave per particle at a time, on the grid that
-// stride_grid() picks: late doublings list few particles, and a grid as
-// large as the population would pay a dispatch per particle there.
+// Leaf and merge over the listed particles (all of them in natural order),
+// one wave per particle. STRIDED (late doublings, few listed): a grid of a
+// fixed size whose workgroups step through them, as a grid as large as the
+// population would pay a dispatch per particle there. Otherwise one
+// workgroup per particle: a loop around the step keeps about twice the
+// registers live (64 -> 127 VGPRs for the leaf), which halves the occupancy
+// of full passes.
+template <bool STRIDED>
 __global__ __launch_bounds__(64) void nuts_leaf_kernel(NutsArgs a, int j, int n) {
   __shared__ double sh[kNutsMetricMax];
   const int64_t cnt = list_count(a);
-  for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
-    const View v = view_at(a, r);
+  if constexpr (!STRIDED) {
+    if ((int64_t)blockIdx.x >= cnt) return;
+    const View v = view_at(a, blockIdx.x);
     if (v.ok) leaf_step(a, v, j, n, sh);
-    __syncthreads();  // sh is the next particle's
+  } else {
+    for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+      const View v = view_at(a, r);
+      if (v.ok) leaf_step(a, v, j, n, sh);
+      // sh is the next particle's; no barrier after the last one, whose
+      // release would hold the wave until its stores complete
+      if (r + gridDim.x < cnt) __syncthreads();
+    }
   }
 }
 
+template <bool STRIDED>
 __global__ __launch_bounds__(64) void nuts_merge_kernel(NutsArgs a, int j) {
   __shared__ double sh[kNutsMetricMax];
   const int64_t cnt = list_count(a);
-  for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
-    const View v = view_at(a, r);
+  if constexpr (!STRIDED) {
+    if ((int64_t)blockIdx.x >= cnt) return;
+    const View v = view_at(a, blockIdx.x);
     if (v.ok) merge_step(a, v, j, sh);
-    __syncthreads();  // sh is the next particle's
+  } else {
+    for (int64_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+      const View v = view_at(a, r);
+      if (v.ok) merge_step(a, v, j, sh);
+      if (r + gridDim.x < cnt) __syncthreads();
+    }
   }
 }
 
@@ -435,12 +454,11 @@ __global__ __launch_bounds__(64) void nuts_finalize_kernel(NutsArgs a) {
 }
 
 dim3 grid_of(int64_t N) { return dim3((unsigned)N); }  // one wave-sized workgroup per particle
-// With a.stride_grid, 32 wave-sized workgroups per compute unit (its full
-// occupancy), at most N; else one per particle, which the hardware hands out
-// faster than a fixed assignment in a full pass.
+// The strided leaf and merge grid: 32 wave-sized workgroups per compute unit
+// (the one-pass kernels' full occupancy), at most N.
 dim3 stride_grid(const NutsArgs& a) {
   const int64_t cap = 32 * (int64_t)(a.n_cu > 0 ? a.n_cu : 256);
-  return dim3((unsigned)std::max<int64_t>(1, a.stride_grid ? std::min(a.N, cap) : a.N));
+  return dim3((unsigned)std::max<int64_t>(1, std::min(a.N, cap)));
 }
 
 }  // namespace
@@ -450,11 +468,17 @@ hipError_t launch_nuts_init(const NutsArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_nuts_leaf(const NutsArgs& a, int j, int n, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_leaf_kernel, stride_grid(a), dim3(64), 0, st, a, j, n);
+  if (a.stride_grid)
+    hipLaunchKernelGGL(nuts_leaf_kernel<true>, stride_grid(a), dim3(64), 0, st, a, j, n);
+  else
+    hipLaunchKernelGGL(nuts_leaf_kernel<false>, grid_of(a.N), dim3(64), 0, st, a, j, n);
   return hipGetLastError();
 }
 hipError_t launch_nuts_merge(const NutsArgs& a, int j, hipStream_t st) {
-  hipLaunchKernelGGL(nuts_merge_kernel, stride_grid(a), dim3(64), 0, st, a, j);
+  if (a.stride_grid)
+    hipLaunchKernelGGL(nuts_merge_kernel<true>, stride_grid(a), dim3(64), 0, st, a, j);
+  else
+    hipLaunchKernelGGL(nuts_merge_kernel<false>, grid_of(a.N), dim3(64), 0, st, a, j);
   return hipGetLastError();
 }
 hipError_t launch_nuts_finalize(const NutsArgs& a, hipStream_t st) {
