@@ -989,20 +989,51 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
 // thread per particle measured slower in late NUTS leaves, where few
 // particles are active. The cost follows the active set.
 constexpr int kSrcGroup = 16;
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(256) void fd_src_kernel(PopArgs a, double T2) {
+  // The rows of a group's particle are contiguous ([K][34] doubles): each
+  // lane builds its source's row in registers, and the group writes the
+  // rows out through LDS in two halves of 17 words, so that a store of the
+  // group covers 128 consecutive bytes instead of one word of each of 16
+  // rows. The group's lanes are in one wave, whose LDS accesses complete in
+  // order.
+  constexpr int kHalf = kSrcWords / 2;
+  __shared__ double stage[256 / kSrcGroup][kSrcGroup][kHalf];
   const int sub = threadIdx.x & (kSrcGroup - 1);
+  double(*st)[kHalf] = stage[threadIdx.x / kSrcGroup];
   const int64_t n = fd_count(a);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kSrcGroup);
   for (int64_t rank = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSrcGroup; rank < n;
        rank += stride) {
     FdItem it;
     if (!fd_active_at(a, rank, it)) continue;
-    for (int k = sub; k < it.K; k += kSrcGroup) {
-      const int64_t m = it.m0 + k;
-      const Src s = make_src(a.theta + m * 8, a.fd_T_obs);
-      double* c = a.fd_src + m * kSrcWords;
-      src_store(c, s);
-      c[kQPartner] = T2 > 0.0 ? __builtin_bit_cast(double, (int64_t)floor(s.f0 * T2)) : c[kQOwn];
+    for (int c0 = 0; c0 < it.K; c0 += kSrcGroup) {
+      const int rows = it.K - c0 < kSrcGroup ? it.K - c0 : kSrcGroup;
+      double w[kSrcWords];
+      if (sub < rows) {
+        const Src s = make_src(a.theta + (it.m0 + c0 + sub) * 8, a.fd_T_obs);
+        src_store(w, s);
+        w[kQPartner] = T2 > 0.0 ? __builtin_bit_cast(double, (int64_t)floor(s.f0 * T2)) : w[kQOwn];
+      }
+      double* out = a.fd_src + (it.m0 + c0) * kSrcWords;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (sub < rows) {
+#pragma unroll
+          for (int x = 0; x < kHalf; ++x) st[sub][x] = w[h * kHalf + x];
+        }
+        wave_lds_sync();
+        for (int x = sub; x < rows * kHalf; x += kSrcGroup) {
+          const int r = x / kHalf, c = x - r * kHalf;
+          out[r * kSrcWords + h * kHalf + c] = st[r][c];
+        }
+        wave_lds_sync();
+      }
     }
   }
 }
