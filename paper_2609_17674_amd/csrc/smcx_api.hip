@@ -161,6 +161,20 @@ struct ProfScope {
   }
 };
 
+// A batched launch under the profiling events. On the frequency-domain model
+// the pass that writes the source constants runs before the first event
+// when profiling is on, so that the events time the likelihood kernel alone.
+template <class Launch>
+hipError_t profiled(smcx_problem* p, smcx::PopArgs a, hipStream_t st, Launch launch) {
+  if (p->fd && p->prof_on) {
+    hipError_t e = smcx::launch_fd_src(a, st);
+    if (e != hipSuccess) return e;
+    a.fd_src_ready = 1;
+  }
+  ProfScope ps(p, st);
+  return launch(a);
+}
+
 smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
                         const double* theta, const double* beta, const Tiling& t, int64_t s_lo,
                         int64_t s_hi, double k0) {
@@ -600,8 +614,9 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.k0_lo = k0_untempered(p);
   a.logl = logl;
   {
-    ProfScope ps(p, st);
-    e = smcx::launch_forward(p->model, t, a, st);
+    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+      return smcx::launch_forward(p->model, t, b, st);
+    });
   }
   if (e != hipSuccess) return hip_fail(e, "logl launch");
   return SMCX_OK;
@@ -633,8 +648,9 @@ int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   a.logl = logl;
   a.grad = grad;
   {
-    ProfScope ps(p, st);
-    e = smcx::launch_fused(p->model, t, a, st);
+    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+      return smcx::launch_fused(p->model, t, b, st);
+    });
   }
   if (e != hipSuccess) return hip_fail(e, "logl_grad launch");
   return SMCX_OK;
@@ -671,8 +687,9 @@ int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, i
   a.dlogl_birth = dlogl_birth;
   a.dlogl_death = dlogl_death;
   {
-    ProfScope ps(p, st);
-    e = smcx::launch_delta(p->model, t, a, st);
+    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+      return smcx::launch_delta(p->model, t, b, st);
+    });
   }
   if (e != hipSuccess) return hip_fail(e, "delta launch");
   return SMCX_OK;
@@ -708,8 +725,9 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, nullptr, t, T1, T2, k0);
     a.logl = logl_ext;
     {
-      ProfScope ps(p, st);
-      e = smcx::launch_forward(p->model, t, a, st);
+      e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+        return smcx::launch_forward(p->model, t, b, st);
+      });
     }
     if (e != hipSuccess) return hip_fail(e, "segment logl launch");
   }
@@ -806,8 +824,9 @@ int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.eps = eps;
   a.dir = dir;
   {
-    ProfScope ps(p, st);
-    e = smcx::launch_fused(p->model, t, a, st);
+    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+      return smcx::launch_fused(p->model, t, b, st);
+    });
   }
   if (e != hipSuccess) return hip_fail(e, "leapfrog gradient launch");
   return SMCX_OK;

@@ -1049,7 +1049,7 @@ unsigned fd_grid(const PopArgs& a, int64_t per_block, int64_t blocks_per_cu) {
   return (unsigned)std::max<int64_t>(1, a.stride_grid ? std::min(need, cap) : need);
 }
 
-hipError_t launch_fd_src(const PopArgs& a, hipStream_t st) {
+hipError_t launch_src_pass(const PopArgs& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   hipLaunchKernelGGL(fd_src_kernel, dim3(fd_grid(a, 256 / kSrcGroup, 8)), dim3(256), 0, st, a,
                      a.fd_bridge ? a.fd2_T_obs : 0.0);
@@ -1059,8 +1059,10 @@ hipError_t launch_fd_src(const PopArgs& a, hipStream_t st) {
 template <int MODE>
 hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
-  hipError_t e = launch_fd_src(a, st);
-  if (e != hipSuccess) return e;
+  if (!a.fd_src_ready) {
+    hipError_t e = launch_src_pass(a, st);
+    if (e != hipSuccess) return e;
+  }
   const dim3 block(256);
   if (MODE == 1 && a.stride_grid && a.fd_B <= 2 * kNs) {
     // three workgroups fit a compute unit at once: two rounds of them
@@ -1076,6 +1078,8 @@ hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
 }
 
 }  // namespace
+
+hipError_t launch_fd_src(const PopArgs& a, hipStream_t st) { return launch_src_pass(a, st); }
 
 hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
   if (a.fd_B < 1 || a.fd_B > 4 * kNs) return hipErrorInvalidValue;
@@ -1094,7 +1098,7 @@ hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t 
   PopArgs all = a;
   all.order = nullptr;
   all.active = nullptr;
-  hipError_t e = launch_fd_src(all, st);
+  hipError_t e = launch_src_pass(all, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a, a.fd_src,
                      f_offsets, f_size, F, blocks);

@@ -107,6 +107,7 @@ struct PopArgs {
   int stride_grid;         // 1: launches whose kernels step through the listed particles
                            // take a fixed grid per compute unit (few listed), 0: a
                            // workgroup per group of particles
+  int fd_src_ready;        // 1: the caller has written fd_src for this launch's particles
   // bridge between two records (eq. reuse_bridge): the partner handle's data
   int fd_bridge;           // 1: target (1 - beta) logL_partner + beta logL_own
   const double* fd2_data;
@@ -261,6 +262,9 @@ hipError_t launch_forward(int model, const Tiling& t, const PopArgs& a, hipStrea
 // Frequency-domain model (smcx_gblisa.hip): mode 0 logL, 1 logL + gradient
 // (leapfrog kick when p_half is set), 2 birth / death changes.
 hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st);
+// The source constants of the particles a launch of launch_fd works on
+// (launch_fd runs it first unless a.fd_src_ready).
+hipError_t launch_fd_src(const PopArgs& a, hipStream_t st);
 hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st);
 hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
                             int blocks, hipStream_t st);
