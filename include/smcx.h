@@ -180,6 +180,16 @@ int logl_grad_batch(smcx_problem* prob, int64_t N, const int64_t* offsets, int64
                     const double* theta, const double* beta, double* logl, double* grad,
                     void* hip_stream);
 
+/* logl_grad_batch for the particles with mask[i] != 0 only, as the mixture
+ * kernel of eq. kernel_mixture needs: the NUTS move starts from the
+ * gradient of the particles it moves. mask [N] uint8 (NULL: SMCX_EINVAL).
+ * The logl and grad entries of the other particles are not computed: on
+ * return they hold unspecified values. The selected particles' entries are
+ * bitwise those of logl_grad_batch. */
+int logl_grad_batch_masked(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                           const double* theta, const double* beta, const uint8_t* mask,
+                           double* logl, double* grad, void* hip_stream);
+
 /* Change of the tempered log-likelihood under the nested birth and death
  * moves of Sec. "Reversible Jump MCMC" (k' = k +- 1, unit Jacobian; the
  * acceptance ratio of eq. rj_acceptance needs exactly this change):
@@ -200,6 +210,17 @@ int delta_logl_birth_death(smcx_problem* prob, int64_t N, const int64_t* offsets
                            const double* theta, const double* beta, const double* theta_birth,
                            const int32_t* death_idx, double* dlogl_birth, double* dlogl_death,
                            void* hip_stream);
+
+/* delta_logl_birth_death for the particles with mask[i] != 0 only (in the
+ * mixture kernel of eq. kernel_mixture, those that propose a birth or a
+ * death). mask [N] uint8 (NULL: SMCX_EINVAL). The other particles'
+ * dlogl_birth and dlogl_death entries hold unspecified values on return;
+ * the selected ones are bitwise those of delta_logl_birth_death. */
+int delta_logl_birth_death_masked(smcx_problem* prob, int64_t N, const int64_t* offsets,
+                                  int64_t M, const double* theta, const double* beta,
+                                  const uint8_t* mask, const double* theta_birth,
+                                  const int32_t* death_idx, double* dlogl_birth,
+                                  double* dlogl_death, void* hip_stream);
 
 /* Data-assimilation reweighting (eq. reuse_bridge, eq. incremental_weight,
  * eq. ess and the evidence ratio of Sec. "Sequential Monte Carlo").

@@ -622,10 +622,9 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   return SMCX_OK;
 }
 
-int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                    const double* theta, const double* beta, double* logl, double* grad,
-                    void* hip_stream) {
-  g_last_error.clear();
+static int grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                      const double* theta, const double* beta, const uint8_t* mask, double* logl,
+                      double* grad, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
   if (M > 0 && !grad) return fail(SMCX_EINVAL, "grad is NULL");
@@ -647,6 +646,7 @@ int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   a.k0_lo = k0_untempered(p);
   a.logl = logl;
   a.grad = grad;
+  a.active = mask;
   {
     e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
       return smcx::launch_fused(p->model, t, b, st);
@@ -656,11 +656,25 @@ int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
   return SMCX_OK;
 }
 
-int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                           const double* theta, const double* beta, const double* theta_birth,
-                           const int32_t* death_idx, double* dlogl_birth, double* dlogl_death,
-                           void* hip_stream) {
+int logl_grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                    const double* theta, const double* beta, double* logl, double* grad,
+                    void* hip_stream) {
   g_last_error.clear();
+  return grad_batch(p, N, offsets, M, theta, beta, nullptr, logl, grad, hip_stream);
+}
+
+int logl_grad_batch_masked(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                           const double* theta, const double* beta, const uint8_t* mask,
+                           double* logl, double* grad, void* hip_stream) {
+  g_last_error.clear();
+  if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
+  return grad_batch(p, N, offsets, M, theta, beta, mask, logl, grad, hip_stream);
+}
+
+static int delta_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                       const double* theta, const double* beta, const uint8_t* mask,
+                       const double* theta_birth, const int32_t* death_idx, double* dlogl_birth,
+                       double* dlogl_death, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
   if (N > 0 && theta_birth && !dlogl_birth) return fail(SMCX_EINVAL, "dlogl_birth is NULL");
@@ -686,6 +700,7 @@ int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, i
   a.death_idx = death_idx;
   a.dlogl_birth = dlogl_birth;
   a.dlogl_death = dlogl_death;
+  a.active = mask;
   {
     e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
       return smcx::launch_delta(p->model, t, b, st);
@@ -693,6 +708,25 @@ int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, i
   }
   if (e != hipSuccess) return hip_fail(e, "delta launch");
   return SMCX_OK;
+}
+
+int delta_logl_birth_death(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                           const double* theta, const double* beta, const double* theta_birth,
+                           const int32_t* death_idx, double* dlogl_birth, double* dlogl_death,
+                           void* hip_stream) {
+  g_last_error.clear();
+  return delta_batch(p, N, offsets, M, theta, beta, nullptr, theta_birth, death_idx, dlogl_birth,
+                     dlogl_death, hip_stream);
+}
+
+int delta_logl_birth_death_masked(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                                  const double* theta, const double* beta, const uint8_t* mask,
+                                  const double* theta_birth, const int32_t* death_idx,
+                                  double* dlogl_birth, double* dlogl_death, void* hip_stream) {
+  g_last_error.clear();
+  if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
+  return delta_batch(p, N, offsets, M, theta, beta, mask, theta_birth, death_idx, dlogl_birth,
+                     dlogl_death, hip_stream);
 }
 
 int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const int64_t* offsets,

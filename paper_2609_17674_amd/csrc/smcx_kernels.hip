@@ -918,6 +918,7 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
   const int i = it.i;
   const int64_t m0 = it.m0;
   const int K = it.K;
+  if (a.active && !a.active[i]) return;
   const int j_death = a.death_idx ? a.death_idx[i] : -1;
   const bool birth = a.theta_birth != nullptr;
   if (!birth && j_death < 0) {  // nothing to evaluate: no birth, no death
@@ -1017,6 +1018,7 @@ __global__ __launch_bounds__(256) void delta_finalize_kernel(PopArgs a) {
   Item it;
   if (!combine_item(a, rank, true, it)) return;
   const int i = it.i;
+  if (a.active && !a.active[i]) return;
   if (!a.theta_birth && (!a.death_idx || a.death_idx[i] < 0)) return;  // settled by the main pass
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c = 0; c < a.nch; ++c) {

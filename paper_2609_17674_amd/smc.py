@@ -210,7 +210,9 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
             nuts = r < cfg.p_nuts
             move = torch.where(nuts, 0, torch.where(r < cfg.p_nuts + cfg.p_birth, 1, 2)).to(torch.int8)
             if M > 0:
-                l, g = smcx.logl_grad_batch(prob, off, th, beta_arr)
+                nuts_u8 = nuts.to(torch.uint8)
+                # the NUTS move starts from the gradient of the particles it moves
+                l, g = smcx.logl_grad_batch(prob, off, th, beta_arr, mask=nuts_u8)
                 mom = torch.randn((M, P), generator=gen, **f64)
                 dirs = (torch.randint(0, 2, (N, D), generator=gen, device=dev) * 2 - 1).to(torch.int8)
                 ul = torch.rand((N, (1 << D) - 1), generator=gen, **f64)
@@ -228,14 +230,17 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                                                     out=fbuf[:size])
                     metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
-                                                ul, ut, lo, hi, mask=nuts.to(torch.uint8),
+                                                ul, ut, lo, hi, mask=nuts_u8,
                                                 metric=metric, metric_blocks=wblocks)
                 steps += int(st.sum())
             Kc = off[1:] - off[:-1]
             tb = _prior_rows(prob, lo, hi, N, gen)
             di = torch.floor(torch.rand(N, generator=gen, **f64) * Kc).to(torch.int32)
-            di = torch.where(Kc > 0, di, torch.full_like(di, -1))
-            db, dd = smcx.delta_logl_birth_death(prob, off, th, beta_arr, tb, di)
+            # the death overlap only where a death is proposed (-1: none)
+            di = torch.where((Kc > 0) & (move == 2), di, torch.full_like(di, -1))
+            # scored only for the particles that propose a birth or a death
+            db, dd = smcx.delta_logl_birth_death(prob, off, th, beta_arr, tb, di,
+                                                 mask=(move != 0).to(torch.uint8))
             log_u = torch.log(torch.rand(N, generator=gen, **f64))
             acc, off, th_all = smcx.rj_apply(prob, off, th, move, tb, di, db, dd, log_u, cfg.k_lo,
                                              cfg.k_hi, log_ratio, m_cap=M + N)

@@ -54,7 +54,9 @@ def load_library():
         "smcx_device_status": [P, P],
         "logl_batch": [P, I64, P, I64, P, P, P, P],
         "logl_grad_batch": [P, I64, P, I64, P, P, P, P, P],
+        "logl_grad_batch_masked": [P, I64, P, I64, P, P, P, P, P, P],
         "delta_logl_birth_death": [P, I64, P, I64, P, P, P, P, P, P, P],
+        "delta_logl_birth_death_masked": [P, I64, P, I64, P, P, P, P, P, P, P, P],
         "reweight_extend": [P, I64, I64, I64, P, I64, P, D, P, P, P, P, P, P],
         "smcx_template_sum": [I, I64, P, I64, D, D, P, P],
         "smcx_plain_logl_grad": [P, I64, P, I64, P, P, P, P, P],
@@ -273,7 +275,10 @@ def logl_batch(prob: Problem, offsets, theta, beta=None, logl=None, stream=None)
 
 
 def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=None, stream=None,
-                    want_logl=True):
+                    want_logl=True, mask=None):
+    """(logl, grad) of logl_grad_batch; with mask (uint8 [N]) only the selected
+    particles are evaluated (logl_grad_batch_masked) and the other entries are
+    unspecified."""
     offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
     if logl is None and want_logl:
         logl = torch.empty(N, dtype=torch.float64, device=theta.device)
@@ -282,6 +287,13 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
     if grad is None:
         grad = torch.empty_like(theta)
     grad = _dev(grad, torch.float64, "grad", tuple(theta.shape))
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
+        _check(load_library().logl_grad_batch_masked(prob.handle, N, _ptr(offsets),
+                                                     theta.shape[0], _ptr(theta), _ptr(beta),
+                                                     _ptr(mask), _ptr(logl), _ptr(grad),
+                                                     _stream(stream)))
+        return logl, grad
     _check(load_library().logl_grad_batch(prob.handle, N, _ptr(offsets), theta.shape[0],
                                           _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
                                           _stream(stream)))
@@ -289,7 +301,11 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
 
 
 def delta_logl_birth_death(prob: Problem, offsets, theta, beta=None, theta_birth=None,
-                           death_idx=None, dlogl_birth=None, dlogl_death=None, stream=None):
+                           death_idx=None, dlogl_birth=None, dlogl_death=None, stream=None,
+                           mask=None):
+    """(dlogl_birth, dlogl_death) of delta_logl_birth_death; with mask (uint8
+    [N]) only the selected particles are evaluated
+    (delta_logl_birth_death_masked) and the other entries are unspecified."""
     offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
     dev = theta.device
     if theta_birth is not None:
@@ -302,11 +318,33 @@ def delta_logl_birth_death(prob: Problem, offsets, theta, beta=None, theta_birth
         if dlogl_death is None:
             dlogl_death = torch.empty(N, dtype=torch.float64, device=dev)
         dlogl_death = _dev(dlogl_death, torch.float64, "dlogl_death", (N,))
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
+        _check(load_library().delta_logl_birth_death_masked(
+            prob.handle, N, _ptr(offsets), theta.shape[0], _ptr(theta), _ptr(beta), _ptr(mask),
+            _ptr(theta_birth), _ptr(death_idx), _ptr(dlogl_birth), _ptr(dlogl_death),
+            _stream(stream)))
+        return dlogl_birth, dlogl_death
     _check(load_library().delta_logl_birth_death(prob.handle, N, _ptr(offsets), theta.shape[0],
                                                  _ptr(theta), _ptr(beta), _ptr(theta_birth), _ptr(death_idx),
                                                  _ptr(dlogl_birth), _ptr(dlogl_death),
                                                  _stream(stream)))
     return dlogl_birth, dlogl_death
+
+
+def logl_grad_batch_masked(prob: Problem, offsets, theta, mask, beta=None, logl=None, grad=None,
+                           stream=None):
+    """logl_grad_batch_masked: logl_grad_batch for the particles with mask != 0."""
+    return logl_grad_batch(prob, offsets, theta, beta, logl, grad, stream, mask=mask)
+
+
+def delta_logl_birth_death_masked(prob: Problem, offsets, theta, mask, beta=None,
+                                  theta_birth=None, death_idx=None, dlogl_birth=None,
+                                  dlogl_death=None, stream=None):
+    """delta_logl_birth_death_masked: delta_logl_birth_death for the particles
+    with mask != 0."""
+    return delta_logl_birth_death(prob, offsets, theta, beta, theta_birth, death_idx,
+                                  dlogl_birth, dlogl_death, stream, mask=mask)
 
 
 def reweight_extend(prob: Problem, T1: int, T2: int, offsets, theta, delta_beta: float,

@@ -33,7 +33,8 @@ def test_library_exports_every_declared_function(smcx):
 
 
 def test_binding_exposes_the_abi_names(smcx):
-    for n in ("logl_batch", "logl_grad_batch", "delta_logl_birth_death", "reweight_extend"):
+    for n in ("logl_batch", "logl_grad_batch", "delta_logl_birth_death", "reweight_extend",
+              "logl_grad_batch_masked", "delta_logl_birth_death_masked"):
         assert callable(getattr(smcx, n))
 
 
@@ -49,6 +50,11 @@ def test_null_handle_rejected_before_launch(smcx):
     assert rc == smcx.SMCX_EINVAL
     rc = lib.delta_logl_birth_death(None, 1, None, 0, None, None, None, None, None, None, None)
     assert rc == smcx.SMCX_EINVAL
+    rc = lib.logl_grad_batch_masked(None, 1, None, 0, None, None, None, None, None, None)
+    assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
+    rc = lib.delta_logl_birth_death_masked(None, 1, None, 0, None, None, None, None, None, None,
+                                           None, None)
+    assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
     rc = lib.reweight_extend(None, 0, 1, 1, None, 0, None, 0.1, None, None, None, None, None, None)
     assert rc == smcx.SMCX_EINVAL
     rc = lib.smcx_device_status(None, None)

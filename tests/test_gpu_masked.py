@@ -1,0 +1,63 @@
+"""The masked gradient and birth/death entry points (the mixture kernel of
+eq. kernel_mixture evaluates only the particles each move needs): on the
+selected particles their outputs equal those of the full calls bit for bit,
+on both model families and on the chunked time-domain tiling. The full calls
+are held to the oracle by the parity tests."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import parity as pm
+from paper_2609_17674_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(x), device="cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def _problem(lib, orc, kind):
+    if kind == "gb":
+        w = wl.make_gblisa(N=300, k_lo=0, k_hi=10, n_inj=6, beta="uniform", noise=True, seed=440)
+        d = w.noise + orc.gblisa_spectrum(w.inj, w.T_obs, w.k0, w.B)
+        prob = lib.Problem.frequency_domain(wl.GBLISA, dev(d), w.k0, w.T_obs, w.S, w.k_max, w.N,
+                                            max(w.M, 1))
+        return w, prob, dev(w.theta)
+    cfg = {"pulse": ("pulse_small", dict(N=120, k_lo=0, k_hi=6, rj=True)),
+           "pulse_chunks": ("pulse_batch", dict(N=200, T=4096, rj=True))}[kind]
+    w = wl.make_config(cfg[0], seed=441, **cfg[1])
+    prob = lib.Problem(w.model, pm.to_dev(pm.data_of(w)), w.t_start, w.dt, w.sigma, w.k_max, w.N,
+                       max(w.M, 1))
+    return w, prob, pm.to_dev(w.theta.reshape(-1, w.P))
+
+
+@pytest.mark.parametrize("kind", ["pulse", "pulse_chunks", "gb"])
+def test_masked_calls_equal_the_full_calls_on_the_selected_particles(lib, orc, kind):
+    w, prob, th = _problem(lib, orc, kind)
+    say("masked", kind, "N", w.N, "M", w.M)
+    off, be = dev(w.offsets), dev(w.beta)
+    tb, di = dev(w.extra["theta_birth"]), dev(w.extra["death_idx"])
+    mask = (np.random.default_rng(442).random(w.N) < 0.6).astype(np.uint8)
+    l, g = lib.logl_grad_batch(prob, off, th, be)
+    db, dd = lib.delta_logl_birth_death(prob, off, th, be, tb, di)
+    lm, gm = lib.logl_grad_batch_masked(prob, off, th, dev(mask), be)
+    dbm, ddm = lib.delta_logl_birth_death_masked(prob, off, th, dev(1 - mask), be, tb, di)
+    torch.cuda.synchronize()
+    prob.device_status()
+    l, g, lm, gm = (x.cpu().numpy() for x in (l, g, lm, gm))
+    db, dd, dbm, ddm = (x.cpu().numpy() for x in (db, dd, dbm, ddm))
+    sel, rest = mask == 1, mask == 0
+    assert sel.sum() > 10 and rest.sum() > 10
+    assert np.array_equal(lm[sel], l[sel])
+    rows = np.repeat(sel, np.diff(w.offsets))
+    assert np.array_equal(gm[rows], g[rows])
+    assert np.array_equal(dbm[rest], db[rest]) and np.array_equal(ddm[rest], dd[rest])
