@@ -433,6 +433,16 @@ int smcx_gauss_newton_metric(smcx_problem* prob, int64_t N, const int64_t* offse
                              const double* theta, const double* beta, const int64_t* f_offsets,
                              int64_t f_size, double* F, void* hip_stream);
 
+/* smcx_gauss_newton_metric for the particles with mask[i] != 0 (in the
+ * mixture kernel of eq. kernel_mixture, those the NUTS move takes); the
+ * others get zero matrices, which the ridge of smcx_metric_factor makes
+ * definite. mask [N] uint8 (NULL: SMCX_EINVAL). The selected particles'
+ * matrices are bitwise those of smcx_gauss_newton_metric. */
+int smcx_gauss_newton_metric_masked(smcx_problem* prob, int64_t N, const int64_t* offsets,
+                                    int64_t M, const double* theta, const double* beta,
+                                    const uint8_t* mask, const int64_t* f_offsets, int64_t f_size,
+                                    double* F, void* hip_stream);
+
 /* Factor of the NUTS mass matrix built from the metric (Sec. "No-U-Turn-
  * Sampler": mass matrix = Hessian of the negative log posterior). Per
  * particle M_i = F_i + diag(ridge), ridge[p] (host array, P values >= 0)
@@ -472,6 +482,13 @@ int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, in
 int smcx_gauss_newton_metric_blocks(smcx_problem* prob, int64_t N, const int64_t* offsets,
                                     int64_t M, const double* theta, const double* beta, double* F,
                                     void* hip_stream);
+
+/* smcx_gauss_newton_metric_blocks for the particles with mask[i] != 0; the
+ * other particles' blocks are zero (see smcx_gauss_newton_metric_masked).
+ * mask [N] uint8 (NULL: SMCX_EINVAL). */
+int smcx_gauss_newton_metric_blocks_masked(smcx_problem* prob, int64_t N, const int64_t* offsets,
+                                           int64_t M, const double* theta, const double* beta,
+                                           const uint8_t* mask, double* F, void* hip_stream);
 
 /* smcx_metric_factor for the block layout: for each of the M blocks,
  * W_m = L_m^{-1} with L_m L_m^T = F_m + diag(ridge) (ridge: host array of P

@@ -1296,10 +1296,9 @@ int smcx_rj_apply(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   return SMCX_OK;
 }
 
-int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                             const double* theta, const double* beta, const int64_t* f_offsets,
-                             int64_t f_size, double* F, void* hip_stream) {
-  g_last_error.clear();
+static int gn_metric(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                     const double* theta, const double* beta, const uint8_t* mask,
+                     const int64_t* f_offsets, int64_t f_size, double* F, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
   if (N == 0) return SMCX_OK;
@@ -1307,6 +1306,7 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   if (f_size < 0 || (f_size > 0 && !F)) return fail(SMCX_EINVAL, "bad f_size / F");
   if (p->fd) {
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
+    a.active = mask;
     hipError_t e = smcx::launch_fd_metric(a, f_offsets, f_size, F, 0, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "metric launch");
     return SMCX_OK;
@@ -1316,15 +1316,30 @@ int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets,
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
                                      p->k_max, offsets, theta, beta, f_offsets, f_size, F,
-                                     p->split, 0, p->flag, st);
+                                     p->split, 0, p->flag, st, mask);
   if (e != hipSuccess) return hip_fail(e, "metric launch");
   return SMCX_OK;
 }
 
-int smcx_gauss_newton_metric_blocks(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                                    const double* theta, const double* beta, double* F,
+int smcx_gauss_newton_metric(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                             const double* theta, const double* beta, const int64_t* f_offsets,
+                             int64_t f_size, double* F, void* hip_stream) {
+  g_last_error.clear();
+  return gn_metric(p, N, offsets, M, theta, beta, nullptr, f_offsets, f_size, F, hip_stream);
+}
+
+int smcx_gauss_newton_metric_masked(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                                    const double* theta, const double* beta, const uint8_t* mask,
+                                    const int64_t* f_offsets, int64_t f_size, double* F,
                                     void* hip_stream) {
   g_last_error.clear();
+  if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
+  return gn_metric(p, N, offsets, M, theta, beta, mask, f_offsets, f_size, F, hip_stream);
+}
+
+static int gn_metric_blocks(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                            const double* theta, const double* beta, const uint8_t* mask,
+                            double* F, void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, theta);
   if (rc) return rc;
   if (N == 0) return SMCX_OK;
@@ -1332,6 +1347,7 @@ int smcx_gauss_newton_metric_blocks(smcx_problem* p, int64_t N, const int64_t* o
   hipStream_t st = (hipStream_t)hip_stream;
   if (p->fd) {
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, beta, p->tiling[kGrad], 0, p->T, 0.0);
+    a.active = mask;
     hipError_t e = smcx::launch_fd_metric(a, nullptr, 0, F, 1, st);
     if (e != hipSuccess) return hip_fail(e, "metric launch");
     return SMCX_OK;
@@ -1340,9 +1356,24 @@ int smcx_gauss_newton_metric_blocks(smcx_problem* p, int64_t N, const int64_t* o
     return fail(SMCX_EINVAL, "the metric supports k_max * P <= 128 (k_max = %d)", p->k_max);
   hipError_t e = smcx::launch_metric(p->model, p->P, N, M, p->T, p->t_start, p->dt, p->inv_sigma2,
                                      p->k_max, offsets, theta, beta, nullptr, 0, F, p->split, 1,
-                                     p->flag, st);
+                                     p->flag, st, mask);
   if (e != hipSuccess) return hip_fail(e, "metric launch");
   return SMCX_OK;
+}
+
+int smcx_gauss_newton_metric_blocks(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                                    const double* theta, const double* beta, double* F,
+                                    void* hip_stream) {
+  g_last_error.clear();
+  return gn_metric_blocks(p, N, offsets, M, theta, beta, nullptr, F, hip_stream);
+}
+
+int smcx_gauss_newton_metric_blocks_masked(smcx_problem* p, int64_t N, const int64_t* offsets,
+                                           int64_t M, const double* theta, const double* beta,
+                                           const uint8_t* mask, double* F, void* hip_stream) {
+  g_last_error.clear();
+  if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
+  return gn_metric_blocks(p, N, offsets, M, theta, beta, mask, F, hip_stream);
 }
 
 int smcx_metric_factor_blocks(smcx_problem* p, int64_t M, const double* F, const double* ridge,

@@ -915,6 +915,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   }
   if (n == 0) return;
   double* Fi = F + fo;
+  if (a.active && !a.active[i]) {
+    // not selected: zero blocks, which the factor's ridge makes definite
+    const int64_t cnt = blocks ? (int64_t)K * 64 : (int64_t)n * n;
+    for (int64_t x = lane; x < cnt; x += 64) Fi[x] = 0.0;
+    return;
+  }
   if (!blocks)
     for (int64_t x = lane; x < (int64_t)n * n; x += 64) {
       const int r = (int)(x / n), c = (int)(x % n);
@@ -1094,10 +1100,11 @@ hipError_t launch_fd(int mode, const PopArgs& a, hipStream_t st) {
 hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t f_size, double* F,
                             int blocks, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
-  // the metric walks every particle in natural order (no ordering pass ran)
+  // the metric walks every particle in natural order (no ordering pass ran);
+  // a.active (or nullptr) selects the particles it evaluates
   PopArgs all = a;
   all.order = nullptr;
-  all.active = nullptr;
+  all.stride_grid = 0;
   hipError_t e = launch_src_pass(all, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a, a.fd_src,

@@ -231,7 +231,7 @@ hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, doub
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
                          int64_t f_size, double* F, int64_t split, int blocks, int* flag,
-                         hipStream_t st);
+                         hipStream_t st, const uint8_t* mask = nullptr);
 // Factor W = L^{-1} of F + diag(ridge) per particle (smcx_metric.hip); ridge is
 // a host array of P values; LDS bytes of one workgroup for k_max * P = nmax.
 // Factor of M independent P x P blocks ([M][P][P], one thread each).

@@ -50,6 +50,7 @@ struct MetricArgs {
   int64_t w0, w1;  // sample window of this launch; the first window writes F, later ones add
   int tempered;    // 1: the window's samples carry beta_i (0: before a bridge split)
   int blocks;      // 1: only each component's P x P block, at F + m P P (source row m)
+  const uint8_t* mask;  // [N] or nullptr: particles with mask[i] == 0 get zero blocks
 };
 
 // Per-lane description of one coordinate (component k, parameter p), set up
@@ -152,6 +153,15 @@ __global__ __launch_bounds__(256) void metric_kernel(MetricArgs a) {
     return;
   }
   if (n == 0) return;
+  if (a.mask && !a.mask[i]) {
+    // not selected: zero blocks (the factor's ridge makes them definite),
+    // written by the first window; later windows add nothing
+    if (a.w0 == 0) {
+      const int64_t cnt = a.blocks ? (int64_t)n * a.P : (int64_t)n * n;
+      for (int64_t e = lane; e < cnt; e += 64) a.F[fo + e] = 0.0;
+    }
+    return;
+  }
   const double* th = a.theta + o0 * a.P;
   Coord<MODEL> q[NB];
   double* my = scl + wid * 32 * NB;
@@ -451,9 +461,9 @@ hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, doub
                          double dt, double inv_sigma2, int32_t k_max, const int64_t* offsets,
                          const double* theta, const double* beta, const int64_t* f_offsets,
                          int64_t f_size, double* F, int64_t split, int blocks, int* flag,
-                         hipStream_t st) {
+                         hipStream_t st, const uint8_t* mask) {
   MetricArgs a{P, N, M, T, t_start, dt, inv_sigma2, (double)T * dt, k_max, offsets, theta,
-               beta, f_offsets, f_size, F, flag, 0, 0, 1, blocks};
+               beta, f_offsets, f_size, F, flag, 0, 0, 1, blocks, mask};
   const int nmax = k_max * P;
   const dim3 grid((unsigned)((N + 3) / 4)), block(256);
   const int nb = nmax <= 32 ? 1 : (nmax <= 64 ? 2 : 4);

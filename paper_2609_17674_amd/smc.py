@@ -219,7 +219,8 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                 ut = torch.rand((N, D), generator=gen, **f64)
                 metric = wblocks = None
                 if cfg.metric and blocks:
-                    F = smcx.gauss_newton_metric_blocks(prob, off, th, beta_arr, out=bbuf[:M])
+                    F = smcx.gauss_newton_metric_blocks(prob, off, th, beta_arr, out=bbuf[:M],
+                                                        mask=nuts_u8)
                     wblocks = smcx.metric_factor_blocks(prob, F, ridge, out=F)
                 elif cfg.metric:
                     fo = smcx.metric_offsets(prob, off)
@@ -227,7 +228,7 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                     if fbuf.numel() < size:
                         fbuf = torch.empty(size + size // 4, **f64)
                     _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
-                                                    out=fbuf[:size])
+                                                    out=fbuf[:size], mask=nuts_u8)
                     metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
                                                 ul, ut, lo, hi, mask=nuts_u8,

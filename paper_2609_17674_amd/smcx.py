@@ -66,6 +66,8 @@ def load_library():
                                  P, I32, P],
         "smcx_next_beta": [P, I64, P, P, D, D, P, P, P, P, P],
         "smcx_gauss_newton_metric": [P, I64, P, I64, P, P, P, I64, P, P],
+        "smcx_gauss_newton_metric_masked": [P, I64, P, I64, P, P, P, P, I64, P, P],
+        "smcx_gauss_newton_metric_blocks_masked": [P, I64, P, I64, P, P, P, P, P],
         "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, I32, P, P],
         "smcx_nuts_transition_metric": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, I64, P,
                                         P, P, P, P, P, P, I32, P],
@@ -480,9 +482,11 @@ def metric_offsets(prob: Problem, offsets) -> torch.Tensor:
 
 
 def gauss_newton_metric(prob: Problem, offsets, theta, beta=None, f_offsets=None, out=None,
-                        stream=None):
+                        stream=None, mask=None):
     """Gauss-Newton metric of every particle. Returns (f_offsets, F) with particle
-    i's (K P) x (K P) matrix at F[f_offsets[i]:f_offsets[i+1]] (row-major)."""
+    i's (K P) x (K P) matrix at F[f_offsets[i]:f_offsets[i+1]] (row-major). With
+    mask (uint8 [N]) the particles with mask == 0 get zero matrices
+    (smcx_gauss_newton_metric_masked)."""
     offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
     if f_offsets is None:
         f_offsets = metric_offsets(prob, offsets)
@@ -491,16 +495,24 @@ def gauss_newton_metric(prob: Problem, offsets, theta, beta=None, f_offsets=None
     if out is None:
         out = torch.empty(max(size, 1), dtype=torch.float64, device=theta.device)
     out = _dev(out, torch.float64, "F")
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
+        _check(load_library().smcx_gauss_newton_metric_masked(
+            prob.handle, N, _ptr(offsets), theta.shape[0], _ptr(theta), _ptr(beta), _ptr(mask),
+            _ptr(f_offsets), out.numel(), _ptr(out), _stream(stream)))
+        return f_offsets, out
     _check(load_library().smcx_gauss_newton_metric(prob.handle, N, _ptr(offsets), theta.shape[0],
                                                    _ptr(theta), _ptr(beta), _ptr(f_offsets),
                                                    out.numel(), _ptr(out), _stream(stream)))
     return f_offsets, out
 
 
-def gauss_newton_metric_blocks(prob: Problem, offsets, theta, beta=None, out=None, stream=None):
+def gauss_newton_metric_blocks(prob: Problem, offsets, theta, beta=None, out=None, stream=None,
+                               mask=None):
     """The per-source (P x P) diagonal blocks of the Gauss-Newton metric
     (smcx_gauss_newton_metric_blocks). Returns F [M, P, P], the block of source
-    row m at F[m]."""
+    row m at F[m]. With mask (uint8 [N]) the particles with mask == 0 get zero
+    blocks (smcx_gauss_newton_metric_blocks_masked)."""
     offsets, N, theta, beta = _pop(prob, offsets, theta, beta)
     M = theta.shape[0]
     if out is None:
@@ -508,10 +520,28 @@ def gauss_newton_metric_blocks(prob: Problem, offsets, theta, beta=None, out=Non
     out = _dev(out, torch.float64, "F")
     if out.numel() < M * prob.P * prob.P:
         raise ValueError(f"F needs {M} blocks of {prob.P} x {prob.P}")
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
+        _check(load_library().smcx_gauss_newton_metric_blocks_masked(
+            prob.handle, N, _ptr(offsets), M, _ptr(theta), _ptr(beta), _ptr(mask), _ptr(out),
+            _stream(stream)))
+        return out
     _check(load_library().smcx_gauss_newton_metric_blocks(prob.handle, N, _ptr(offsets), M,
                                                           _ptr(theta), _ptr(beta), _ptr(out),
                                                           _stream(stream)))
     return out
+
+
+def gauss_newton_metric_masked(prob: Problem, offsets, theta, mask, beta=None, f_offsets=None,
+                               out=None, stream=None):
+    """smcx_gauss_newton_metric_masked: zero matrices where mask == 0."""
+    return gauss_newton_metric(prob, offsets, theta, beta, f_offsets, out, stream, mask=mask)
+
+
+def gauss_newton_metric_blocks_masked(prob: Problem, offsets, theta, mask, beta=None, out=None,
+                                      stream=None):
+    """smcx_gauss_newton_metric_blocks_masked: zero blocks where mask == 0."""
+    return gauss_newton_metric_blocks(prob, offsets, theta, beta, out, stream, mask=mask)
 
 
 def metric_factor_blocks(prob: Problem, F, ridge, out=None, M=None, stream=None):

@@ -61,3 +61,29 @@ def test_masked_calls_equal_the_full_calls_on_the_selected_particles(lib, orc, k
     rows = np.repeat(sel, np.diff(w.offsets))
     assert np.array_equal(gm[rows], g[rows])
     assert np.array_equal(dbm[rest], db[rest]) and np.array_equal(ddm[rest], dd[rest])
+
+
+@pytest.mark.parametrize("kind", ["pulse", "pulse_chunks", "gb"])
+def test_masked_metric_equals_the_full_metric_on_the_selected_particles(lib, orc, kind):
+    """Dense and per-source layouts: the selected particles' matrices bitwise
+    those of the full call, zeros for the others."""
+    w, prob, th = _problem(lib, orc, kind)
+    say("masked_metric", kind, "N", w.N, "M", w.M)
+    off, be = dev(w.offsets), dev(w.beta)
+    mask = (np.random.default_rng(443).random(w.N) < 0.6).astype(np.uint8)
+    fo, F = lib.gauss_newton_metric(prob, off, th, be)
+    _, Fm = lib.gauss_newton_metric_masked(prob, off, th, dev(mask), be, f_offsets=fo,
+                                           out=torch.full_like(F, float("nan")))
+    B = lib.gauss_newton_metric_blocks(prob, off, th, be)
+    Bm = lib.gauss_newton_metric_blocks_masked(prob, off, th, dev(mask), be,
+                                               out=torch.full_like(B, float("nan")))
+    torch.cuda.synchronize()
+    prob.device_status()
+    fo, F, Fm, B, Bm = (x.cpu().numpy() for x in (fo, F, Fm, B, Bm))
+    for i in range(w.N):
+        a, b = fo[i], fo[i + 1]
+        r0, r1 = w.offsets[i], w.offsets[i + 1]
+        if mask[i]:
+            assert np.array_equal(Fm[a:b], F[a:b]) and np.array_equal(Bm[r0:r1], B[r0:r1]), i
+        else:
+            assert np.all(Fm[a:b] == 0.0) and np.all(Bm[r0:r1] == 0.0), i
