@@ -466,6 +466,16 @@ int smcx_metric_factor(smcx_problem* prob, int64_t N, const int64_t* offsets, in
                        const int64_t* f_offsets, int64_t f_size, const double* F,
                        const double* ridge, int32_t block, double* W, void* hip_stream);
 
+/* smcx_metric_factor for the particles with mask[i] != 0 (those the NUTS
+ * move of eq. kernel_mixture takes, whose transition reads nothing else of
+ * W); the other particles' W entries are not written. mask [N] uint8 (NULL:
+ * SMCX_EINVAL). The selected particles' factors are bitwise those of
+ * smcx_metric_factor. */
+int smcx_metric_factor_masked(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t M,
+                              const uint8_t* mask, const int64_t* f_offsets, int64_t f_size,
+                              const double* F, const double* ridge, int32_t block, double* W,
+                              void* hip_stream);
+
 /* Block-diagonal mass matrices kept per source (Sec. "No-U-Turn-Sampler";
  * the frequency-domain model's metric is exactly block diagonal, one P x P
  * block per source). The three calls below use one layout: a device FP64

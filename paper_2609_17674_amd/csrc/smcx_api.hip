@@ -1392,10 +1392,10 @@ int smcx_metric_factor_blocks(smcx_problem* p, int64_t M, const double* F, const
   return SMCX_OK;
 }
 
-int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
-                       const int64_t* f_offsets, int64_t f_size, const double* F,
-                       const double* ridge, int32_t block, double* W, void* hip_stream) {
-  g_last_error.clear();
+static int metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                         const uint8_t* mask, const int64_t* f_offsets, int64_t f_size,
+                         const double* F, const double* ridge, int32_t block, double* W,
+                         void* hip_stream) {
   int rc = check_pop(p, N, offsets, M, F ? F : W);  // theta is not read: only the sizes matter
   if (rc) return rc;
   if (N == 0) return SMCX_OK;
@@ -1415,9 +1415,27 @@ int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64
                 nmax, smcx::factor_lds_bytes(nmax), p->lds_max);
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_metric_factor(p->P, N, M, p->k_max, offsets, f_offsets, f_size, F,
-                                            ridge, block, W, p->flag, st);
+                                            ridge, block, W, p->flag, st, mask);
   if (e != hipSuccess) return hip_fail(e, "metric factor launch");
   return SMCX_OK;
+}
+
+int smcx_metric_factor(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                       const int64_t* f_offsets, int64_t f_size, const double* F,
+                       const double* ridge, int32_t block, double* W, void* hip_stream) {
+  g_last_error.clear();
+  return metric_factor(p, N, offsets, M, nullptr, f_offsets, f_size, F, ridge, block, W,
+                       hip_stream);
+}
+
+int smcx_metric_factor_masked(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
+                              const uint8_t* mask, const int64_t* f_offsets, int64_t f_size,
+                              const double* F, const double* ridge, int32_t block, double* W,
+                              void* hip_stream) {
+  g_last_error.clear();
+  if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
+  return metric_factor(p, N, offsets, M, mask, f_offsets, f_size, F, ridge, block, W,
+                       hip_stream);
 }
 
 }  // extern "C"

@@ -240,7 +240,7 @@ hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const 
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
                                 const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
                                 const double* F, const double* ridge, int block, double* W,
-                                int* flag, hipStream_t st);
+                                int* flag, hipStream_t st, const uint8_t* mask = nullptr);
 size_t factor_lds_bytes(int nmax);
 
 // SMC steps (smcx_smc.hip).

@@ -260,6 +260,7 @@ struct FactorArgs {
   double ridge[8];  // per parameter, P <= 8
   int block;        // 0: the whole block; b: its block-diagonal part in b x b blocks
   int* flag;
+  const uint8_t* mask;  // [N] or nullptr: particles with mask[i] == 0 are skipped
 };
 
 __device__ __forceinline__ int tri(int r, int c) { return r * (r + 1) / 2 + c; }
@@ -334,6 +335,7 @@ __global__ __launch_bounds__(64) void factor_kernel(FactorArgs a) {
     if (lane == 0) atomicOr(a.flag, kFlagOffsets);
     return;
   }
+  if (a.mask && !a.mask[i]) return;
   if (n == 0) return;
   const double* Fi = a.F + fo;
   double* Wi = a.W + fo;
@@ -437,7 +439,7 @@ size_t factor_lds_bytes(int nmax) { return (size_t)nmax * (nmax + 1) / 2 * sizeo
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
                                 const int64_t* offsets, const int64_t* f_offsets, int64_t f_size,
                                 const double* F, const double* ridge, int block, double* W,
-                                int* flag, hipStream_t st) {
+                                int* flag, hipStream_t st, const uint8_t* mask) {
   FactorArgs a{};
   a.P = P;
   a.N = N;
@@ -451,6 +453,7 @@ hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
   if (P > 8) return hipErrorInvalidValue;
   for (int p = 0; p < P; ++p) a.ridge[p] = ridge[p];
   a.flag = flag;
+  a.mask = mask;
   a.block = block;
   hipLaunchKernelGGL(factor_kernel, dim3((unsigned)N), dim3(64),
                      factor_lds_bytes(block > 0 ? block : k_max * P), st, a);

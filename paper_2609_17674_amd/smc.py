@@ -229,7 +229,8 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                         fbuf = torch.empty(size + size // 4, **f64)
                     _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
                                                     out=fbuf[:size], mask=nuts_u8)
-                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M))
+                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M,
+                                                     mask=nuts_u8))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
                                                 ul, ut, lo, hi, mask=nuts_u8,
                                                 metric=metric, metric_blocks=wblocks)

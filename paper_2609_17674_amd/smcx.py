@@ -69,6 +69,7 @@ def load_library():
         "smcx_gauss_newton_metric_masked": [P, I64, P, I64, P, P, P, P, I64, P, P],
         "smcx_gauss_newton_metric_blocks_masked": [P, I64, P, I64, P, P, P, P, P],
         "smcx_metric_factor": [P, I64, P, I64, P, I64, P, P, I32, P, P],
+        "smcx_metric_factor_masked": [P, I64, P, I64, P, P, I64, P, P, I32, P, P],
         "smcx_nuts_transition_metric": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, I64, P,
                                         P, P, P, P, P, P, I32, P],
         "smcx_gauss_newton_metric_blocks": [P, I64, P, I64, P, P, P, P],
@@ -657,11 +658,13 @@ class LogLGrad(torch.autograd.Function):
 
 
 def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None, block=0,
-                  stream=None):
+                  stream=None, mask=None):
     """Factor W = L^{-1} of F + diag(ridge) for every particle (smcx_metric_factor):
     ridge is a sequence of P values >= 0; out may be F itself (in place);
     block = b > 0 factors the block-diagonal part in b x b blocks.
-    Returns W with the blocks of f_offsets (zeros above each diagonal)."""
+    Returns W with the blocks of f_offsets (zeros above each diagonal). With mask
+    (uint8 [N]) only the selected particles are factored
+    (smcx_metric_factor_masked); the others' entries of out are not written."""
     offsets = _dev(offsets, torch.int64, "offsets")
     N = offsets.numel() - 1
     f_offsets = _dev(f_offsets, torch.int64, "f_offsets", (N + 1,))
@@ -675,11 +678,24 @@ def metric_factor(prob: Problem, offsets, f_offsets, F, ridge, out=None, M=None,
     rarr = (ctypes.c_double * prob.P)(*r)
     if M is None:
         M = int(offsets[-1]) if N > 0 else 0
+    if mask is not None:
+        mask = _dev(mask, torch.uint8, "mask", (N,))
+        _check(load_library().smcx_metric_factor_masked(
+            prob.handle, N, _ptr(offsets), int(M), _ptr(mask), _ptr(f_offsets),
+            min(F.numel(), out.numel()), _ptr(F), ctypes.cast(rarr, ctypes.c_void_p), int(block),
+            _ptr(out), _stream(stream)))
+        return out
     _check(load_library().smcx_metric_factor(prob.handle, N, _ptr(offsets), int(M), _ptr(f_offsets),
                                              min(F.numel(), out.numel()), _ptr(F),
                                              ctypes.cast(rarr, ctypes.c_void_p), int(block),
                                              _ptr(out), _stream(stream)))
     return out
+
+
+def metric_factor_masked(prob: Problem, offsets, f_offsets, F, ridge, mask, out=None, M=None,
+                         block=0, stream=None):
+    """smcx_metric_factor_masked: the factor for the particles with mask != 0."""
+    return metric_factor(prob, offsets, f_offsets, F, ridge, out, M, block, stream, mask=mask)
 
 
 def template_spectrum(model: int, theta, T_obs: float, k0: int, B: int, stream=None) -> torch.Tensor:

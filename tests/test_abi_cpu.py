@@ -55,6 +55,8 @@ def test_null_handle_rejected_before_launch(smcx):
     assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
     rc = lib.smcx_gauss_newton_metric_blocks_masked(None, 1, None, 0, None, None, None, None, None)
     assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
+    rc = lib.smcx_metric_factor_masked(None, 1, None, 0, None, None, 0, None, None, 0, None, None)
+    assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
     rc = lib.logl_grad_batch_masked(None, 1, None, 0, None, None, None, None, None, None)
     assert rc == smcx.SMCX_EINVAL and "mask" in smcx.last_error()
     rc = lib.delta_logl_birth_death_masked(None, 1, None, 0, None, None, None, None, None, None,

@@ -66,7 +66,8 @@ def test_masked_calls_equal_the_full_calls_on_the_selected_particles(lib, orc, k
 @pytest.mark.parametrize("kind", ["pulse", "pulse_chunks", "gb"])
 def test_masked_metric_equals_the_full_metric_on_the_selected_particles(lib, orc, kind):
     """Dense and per-source layouts: the selected particles' matrices bitwise
-    those of the full call, zeros for the others."""
+    those of the full call, zeros for the others; the masked dense factor
+    bitwise the full factor on the selected particles."""
     w, prob, th = _problem(lib, orc, kind)
     say("masked_metric", kind, "N", w.N, "M", w.M)
     off, be = dev(w.offsets), dev(w.beta)
@@ -79,11 +80,21 @@ def test_masked_metric_equals_the_full_metric_on_the_selected_particles(lib, orc
                                                out=torch.full_like(B, float("nan")))
     torch.cuda.synchronize()
     prob.device_status()
+    # the prior-precision floor the driver uses: 12 / width^2 per parameter
+    prior = wl.GBLISA_PRIOR if kind == "gb" else wl.PULSE_PRIOR
+    ridge = list(12.0 / (prior[:, 1] - prior[:, 0]) ** 2)
+    W = lib.metric_factor(prob, off, fo, F, ridge)
+    Wm = lib.metric_factor_masked(prob, off, fo, F, ridge, dev(mask),
+                                  out=torch.full_like(F, float("nan")))
+    torch.cuda.synchronize()
+    prob.device_status()
+    W, Wm = W.cpu().numpy(), Wm.cpu().numpy()
     fo, F, Fm, B, Bm = (x.cpu().numpy() for x in (fo, F, Fm, B, Bm))
     for i in range(w.N):
         a, b = fo[i], fo[i + 1]
         r0, r1 = w.offsets[i], w.offsets[i + 1]
         if mask[i]:
             assert np.array_equal(Fm[a:b], F[a:b]) and np.array_equal(Bm[r0:r1], B[r0:r1]), i
+            assert np.array_equal(Wm[a:b], W[a:b]), i
         else:
             assert np.all(Fm[a:b] == 0.0) and np.all(Bm[r0:r1] == 0.0), i
