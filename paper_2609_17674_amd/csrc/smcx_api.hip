@@ -613,11 +613,9 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.split = p->split;
   a.k0_lo = k0_untempered(p);
   a.logl = logl;
-  {
-    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
-      return smcx::launch_forward(p->model, t, b, st);
-    });
-  }
+  e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+    return smcx::launch_forward(p->model, t, b, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "logl launch");
   return SMCX_OK;
 }
@@ -647,11 +645,9 @@ static int grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_
   a.logl = logl;
   a.grad = grad;
   a.active = mask;
-  {
-    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
-      return smcx::launch_fused(p->model, t, b, st);
-    });
-  }
+  e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+    return smcx::launch_fused(p->model, t, b, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "logl_grad launch");
   return SMCX_OK;
 }
@@ -701,11 +697,9 @@ static int delta_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64
   a.dlogl_birth = dlogl_birth;
   a.dlogl_death = dlogl_death;
   a.active = mask;
-  {
-    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
-      return smcx::launch_delta(p->model, t, b, st);
-    });
-  }
+  e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+    return smcx::launch_delta(p->model, t, b, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "delta launch");
   return SMCX_OK;
 }
@@ -758,11 +752,9 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
     }
     smcx::PopArgs a = base_args(p, N, offsets, M, theta, nullptr, t, T1, T2, k0);
     a.logl = logl_ext;
-    {
-      e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
-        return smcx::launch_forward(p->model, t, b, st);
-      });
-    }
+    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+      return smcx::launch_forward(p->model, t, b, st);
+    });
     if (e != hipSuccess) return hip_fail(e, "segment logl launch");
   }
   hipError_t e = smcx::launch_reweight_reduce(N, delta_beta, logl_ext, logw_prev, logw, w_norm,
@@ -857,11 +849,9 @@ int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.p_out = p_out;
   a.eps = eps;
   a.dir = dir;
-  {
-    e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
-      return smcx::launch_fused(p->model, t, b, st);
-    });
-  }
+  e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
+    return smcx::launch_fused(p->model, t, b, st);
+  });
   if (e != hipSuccess) return hip_fail(e, "leapfrog gradient launch");
   return SMCX_OK;
 }
