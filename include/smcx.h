@@ -190,6 +190,35 @@ int logl_grad_batch_masked(smcx_problem* prob, int64_t N, const int64_t* offsets
                            const double* theta, const double* beta, const uint8_t* mask,
                            double* logl, double* grad, void* hip_stream);
 
+/* Bytes of the library's static scratch array (one copy per device). */
+#define SMCX_STATIC_SCRATCH_BYTES (32u << 20)
+
+/* logl_grad_batch for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It needs no problem handle and allocates nothing, here or in any library
+ * routine it calls. Its workspace (the FP32 copy of d, the K = 0 energy, the
+ * work list and the chunk partial sums) lives in a file-scope device array
+ * of SMCX_STATIC_SCRATCH_BYTES per device, held until the process ends.
+ *   model, T, t_start, dt, sigma, k_max   as smcx_problem_create (time-domain
+ *              models only); d [T] FP64 device data, read on every call
+ *   N, offsets, M, theta, beta, logl, grad   as logl_grad_batch (no n_max /
+ *              m_max: the sizes are bounded by the scratch instead)
+ * The pass is the default gradient tiling of the handle path, with longer
+ * sample chunks where the partial sums would not fit; results agree with
+ * logl_grad_batch to the library's tolerances (and are bitwise equal when
+ * the tiling is the same, except for K = 0 particles, whose ||d||^2 is summed
+ * on the device). Sizes whose workspace exceeds the scratch return
+ * SMCX_ENOMEM before any launch; other host-visible argument errors return
+ * SMCX_EINVAL. Invalid device data gives NaN outputs for the particle (there
+ * is no status call for this form). Every call on a device shares that
+ * device's scratch and leaves its contents behind: calls that may overlap on
+ * one device (several streams or threads) race and must be serialised by the
+ * caller. */
+int logl_grad_batch_static(int model, const double* d, int64_t T, double t_start, double dt,
+                           double sigma, int32_t k_max, int64_t N, const int64_t* offsets,
+                           int64_t M, const double* theta, const double* beta, double* logl,
+                           double* grad, void* hip_stream);
+
 /* Change of the tempered log-likelihood under the nested birth and death
  * moves of Sec. "Reversible Jump MCMC" (k' = k +- 1, unit Jacobian; the
  * acceptance ratio of eq. rj_acceptance needs exactly this change):

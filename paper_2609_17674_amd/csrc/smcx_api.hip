@@ -58,11 +58,12 @@ bool capturing(hipStream_t st) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+}  // namespace
 
 // Default tiling per (model, kind, T). It depends only on the model and the
 // length of the sample axis, never on N, so a particle's arithmetic (and
 // hence its result bit pattern) does not depend on the batch it is in.
-Tiling default_tiling(int model, int kind, int64_t T) {
+Tiling smcx::default_tiling(int model, int kind, int64_t T) {
   Tiling t;
   if (model == SMCX_PULSE) {
     if (kind == kDelta)
@@ -79,6 +80,8 @@ Tiling default_tiling(int model, int kind, int64_t T) {
   t.sorted = 1;
   return t;
 }
+
+namespace {
 
 // Workspace capacities fixed at create: any tiling with at most this many
 // chunks per particle fits the partial-sum buffers.
@@ -372,7 +375,7 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
   p->max_nch = cap_chunks(T);
   p->max_nch_grad = cap_chunks_grad(T);
   for (int k = 0; k < kNumKinds; ++k) {
-    p->tiling[k] = default_tiling(model, k, T);
+    p->tiling[k] = smcx::default_tiling(model, k, T);
     p->max_nch = std::max(p->max_nch, p->tiling[k].nch);
   }
   p->max_nch_grad = std::max(p->max_nch_grad, p->tiling[kGrad].nch);

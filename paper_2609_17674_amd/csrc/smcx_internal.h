@@ -67,6 +67,7 @@ struct PopArgs {
   int64_t m_max;
   double k0;               // logL of a particle without components (tempered part)
   double k0_lo;            // its untempered part: samples before the split (0 without one)
+  const double* k0_dev;    // device scalar used in place of k0 when set (nullptr: k0)
   int64_t split;           // posterior-start bridge: samples s < split are untempered
                            // (weight 1), later ones weighted by beta; 0 (or <= s_lo) = off
   const int32_t* order;    // [N] particles sorted by K descending, or nullptr: particle order
@@ -135,6 +136,7 @@ struct PrepArgs {
   int64_t M;           // rows of theta: offsets[N] must equal it
   double k0_value;     // untempered logL of a particle with no components (tempered part)
   double k0_lo;        // part of it before the bridge split, added untempered (0: no split)
+  const double* k0_dev;  // device scalar used in place of k0_value when set (nullptr: k0_value)
   double* logl;        // written for K = 0 (tempered) and invalid (NaN) particles
   double* logl2;       // optional second output set to the K=0 value (nullptr)
   int P;

@@ -548,7 +548,8 @@ __device__ __forceinline__ bool decode_item(const PopArgs& a, int64_t item, int 
   it.m0 = o0;
   it.K = (int)(o1 - o0);
   if (it.K == 0 && !with_k0) {
-    if (it.c == 0 && lane == 0 && a.logl) a.logl[i] = a.k0_lo + (a.beta ? a.beta[i] : 1.0) * a.k0;
+    if (it.c == 0 && lane == 0 && a.logl)
+      a.logl[i] = a.k0_lo + (a.beta ? a.beta[i] : 1.0) * (a.k0_dev ? *a.k0_dev : a.k0);
     return false;
   }
   return true;
@@ -617,7 +618,7 @@ __device__ __forceinline__ int prep_key(const PrepArgs& a, int64_t i, int64_t o0
     return -1;
   }
   if (K == 0 && !a.include_k0) {
-    if (settle && a.logl) a.logl[i] = a.k0_lo + beta_i * a.k0_value;
+    if (settle && a.logl) a.logl[i] = a.k0_lo + beta_i * (a.k0_dev ? *a.k0_dev : a.k0_value);
     return -1;
   }
   return (int)K;

@@ -67,4 +67,6 @@ struct smcx_problem {
 namespace smcx {
 // Set the thread's last-error message and return `code`.
 int set_error(int code, const char* fmt, ...);
+// Default tiling of call kind `kind` (Kind) for a data length T.
+Tiling default_tiling(int model, int kind, int64_t T);
 }  // namespace smcx

@@ -55,6 +55,7 @@ def load_library():
         "logl_batch": [P, I64, P, I64, P, P, P, P],
         "logl_grad_batch": [P, I64, P, I64, P, P, P, P, P],
         "logl_grad_batch_masked": [P, I64, P, I64, P, P, P, P, P, P],
+        "logl_grad_batch_static": [I, P, I64, D, D, D, I32, I64, P, I64, P, P, P, P, P],
         "delta_logl_birth_death": [P, I64, P, I64, P, P, P, P, P, P, P],
         "delta_logl_birth_death_masked": [P, I64, P, I64, P, P, P, P, P, P, P, P],
         "reweight_extend": [P, I64, I64, I64, P, I64, P, D, P, P, P, P, P, P],
@@ -300,6 +301,34 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
     _check(load_library().logl_grad_batch(prob.handle, N, _ptr(offsets), theta.shape[0],
                                           _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
                                           _stream(stream)))
+    return logl, grad
+
+
+def logl_grad_batch_static(model: int, d, t_start: float, dt: float, sigma: float, k_max: int,
+                           offsets, theta, beta=None, logl=None, grad=None, stream=None):
+    """(logl, grad) of logl_grad_batch_static: the fused pass without a problem
+    handle, its workspace in the library's static device scratch (nothing is
+    allocated by the call; outputs are allocated here only when not passed)."""
+    model = int(model)
+    P = N_PARAMS[model]
+    d = _dev(d, torch.float64, "d")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    N = offsets.numel() - 1
+    theta = _dev(theta, torch.float64, "theta")
+    if theta.dim() != 2 or theta.shape[1] != P:
+        raise ValueError(f"theta must be [M, {P}]")
+    if beta is not None:
+        beta = _dev(beta, torch.float64, "beta", (N,))
+    if logl is None:
+        logl = torch.empty(N, dtype=torch.float64, device=theta.device)
+    logl = _dev(logl, torch.float64, "logl", (N,))
+    if grad is None:
+        grad = torch.empty_like(theta)
+    grad = _dev(grad, torch.float64, "grad", tuple(theta.shape))
+    _check(load_library().logl_grad_batch_static(
+        model, _ptr(d), d.numel(), float(t_start), float(dt), float(sigma), int(k_max), N,
+        _ptr(offsets), theta.shape[0], _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
+        _stream(stream)))
     return logl, grad
 
 

@@ -128,6 +128,35 @@ def test_create_argument_checks(smcx):
     assert rc == smcx.SMCX_EINVAL
 
 
+def test_static_entry_point_host_checks(smcx):
+    """logl_grad_batch_static rejects bad arguments and sizes beyond its static
+    scratch before it touches the device (no GPU is needed to see this)."""
+    lib = _raw(smcx)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks fail first
+    base = dict(model=0, d=fake, T=1000, t0=0.0, dt=1e-3, sigma=1.0, k_max=10, N=4, off=fake,
+                M=8, th=fake, beta=None, logl=fake, grad=fake)
+
+    def call(**ov):
+        a = dict(base)
+        a.update(ov)
+        return lib.logl_grad_batch_static(a["model"], a["d"], a["T"], a["t0"], a["dt"],
+                                          a["sigma"], a["k_max"], a["N"], a["off"], a["M"],
+                                          a["th"], a["beta"], a["logl"], a["grad"], None)
+
+    for ov, word in [(dict(model=2), "model"), (dict(T=0), "T"), (dict(d=None), "d is NULL"),
+                     (dict(dt=0.0), "dt"), (dict(sigma=float("inf")), "sigma"),
+                     (dict(k_max=0), "k_max"), (dict(N=-1), "N"), (dict(M=-1), "M"),
+                     (dict(off=None), "offsets"), (dict(grad=None), "grad")]:
+        assert call(**ov) == smcx.SMCX_EINVAL, ov
+        assert word in smcx.last_error(), (ov, smcx.last_error())
+    assert call(N=0) == smcx.SMCX_OK
+    # the FP32 copy of 2^24 samples alone exceeds the scratch
+    assert call(T=1 << 24) == smcx.SMCX_ENOMEM
+    assert "static scratch" in smcx.last_error()
+    # a population whose work list and partial sums cannot fit
+    assert call(N=1 << 23, M=1 << 23) == smcx.SMCX_ENOMEM
+
+
 def test_template_sum_argument_checks(smcx):
     lib = _raw(smcx)
     assert lib.smcx_template_sum(3, 1, None, 10, 0.0, 1.0, None, None) == smcx.SMCX_EINVAL
