@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the batched population likelihood paths on one MI355X.
 
-Default workload (pulse_batch): a step is one logl_grad_batch call over the
-whole population (template synthesis, residual, FP64 inner products,
-adjoint gradient and ragged batching in one fused pass); the unit of work is
-one particle log-likelihood + gradient evaluation. The same population is
-then run through the plain one-particle-per-launch FP64 form on the same GPU,
-and through the FP64 CPU oracle on a bounded sample on the host cores; the
-oracle's results on that sample also give the reported error of the GPU
-path. Inputs are seeded synthetic workloads resident in device memory before
-the timed region starts.
+Default workload (gb_grad, the largest logL + gradient configuration: chirping
+sinusoids, T = 2^17 samples, N = 4096 particles, K ~ U{0..30}): a step is one
+logl_grad_batch call over the whole population (template synthesis with the
+phase in FP64, residual, FP64 inner products, adjoint gradient and ragged
+batching in one fused pass); the unit of work is one particle log-likelihood
++ gradient evaluation. The same population is then run through the plain
+one-particle-per-launch FP64 form on the same GPU, and through the FP64 CPU
+oracle on a bounded sample on the host cores (all threads, then one thread);
+the oracle's results on that sample also give the reported error of both GPU
+forms. The Gaussian-pulse population (pulse_batch: T = 4096, N = 16384,
+K ~ U{0..20}, beta ~ U[0,1]) is measured the same way and attached as
+"secondary", its accuracy over every particle. Inputs are seeded synthetic
+workloads resident in device memory before the timed region starts.
 
 Other workloads (--workload):
-  gb_grad       the same metric on the chirping-sinusoid population
+  pulse_batch   the pulse population alone
   gb_extend     data-assimilation reweighting: segment logL of every particle
                 on the new samples plus weights, ESS and evidence increment
   pulse_mutate  one NUTS transition of every particle (hipGraph-replayed
@@ -21,13 +25,10 @@ Other workloads (--workload):
                 (prior-start, timed per run; then one posterior-start run, and
                 one identity-metric run for comparison) on a 10-pulse problem
                 at N = 6000
-  metric        Gauss-Newton metric of the headline population (matrix cores)
+  metric        Gauss-Newton metric of the pulse population (matrix cores)
   gb_lisa       LISA Galactic binaries in the frequency domain (A+E, FP64),
                 N = 40000, one logL+grad call per step
   smc_gblisa    whole prior-start SMC runs on ten Galactic binaries, N = 40000
-  gb_durations  the Galactic-binary study over record lengths (3..12 months):
-                prior-start and bridged posterior-start runs at each length
-  pulse_durations  the same study for the pulse record (1/4 .. 1 of it)
 
 Prints one JSON line. Usage: python bench.py [--steps K] [--warmup W]
 [--workload ...] [--gpus 1].
@@ -43,19 +44,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle logL+grad evals/sec (ragged K) vs plain GPU form at ≤1e-6 rel err"
 
-# MI355X published peaks: 256 CUs at 2.4 GHz, FP32 vector 157.3 TFLOP/s
-# (128 FP32 FMA lanes per CU per clock), FP64 vector 78.6 TFLOP/s.
-PEAK_FP32_TFLOPS = 157.3
+# MI355X: 256 CUs at 2.4 GHz, four SIMDs per CU. The published FP32 vector
+# peak, 157.3 TFLOP/s, counts packed FP32 FMAs (two per lane and cycle);
+# this build compiles with packed FP32 instructions disabled, and the issue
+# probe (--workload issue_probe) measures what the vector units then do per
+# CU and clock: 63 lanes of v_fmac_f32 / v_fma_f32 (of 64), 96-105 of
+# v_mul_f32 / v_add_f32 / v_add_u32 (of 128), 58 of v_cvt_f32_i32 (of 64), 30
+# of v_exp_f32 / v_sin_f32 (of 32) and 50 of v_fma_f64 (of 64). So the FP32
+# ceiling without packed instructions is 64 FMA lanes per CU and clock:
+PEAK_FP32_TFLOPS = 78.6          # 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+PUBLISHED_FP32_TFLOPS = 157.3    # with packed FP32 FMAs (not used by this build)
+CLOCK_HZ = 2.4e9
 
-# Issue cost of one component-sample in FP32-FMA-equivalent VALU slots
-# (FP32 op = 1, FP64 op = 2, transcendental = 4, from the published
-# FP32:FP64 ratio and the measured exp/sin/cos issue rate on gfx950).
-#   pulse forward: add, fma, mul, exp2, fma                        4 + 4
-#   pulse adjoint: add, fma, mul, exp2, mul, add, fma, fma         7 + 4
-#   sinusoid forward: int add, cvt, fma, mul, sin, fma             5 + 4
-#   sinusoid adjoint: int add, cvt, fma, mul, sin, cos,
-#                     fma, mul, add, fma, fma                      9 + 8
-SLOTS = {(0, "grad"): 19, (1, "grad"): 26, (0, "fwd"): 8, (1, "fwd"): 9}
+# Issue cost of one component-sample in FP32-FMA slots (one slot = one lane
+# of a full-rate FMA issue): FMA and conversion 1, two-operand multiply or
+# add (FP32 or integer) 1/2, transcendental 2, from the rates above. The
+# operations are those the method needs per component-sample:
+#   pulse forward: add, fmac, mul, exp2, fmac                          5
+#   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
+#   sinusoid forward: int add, cvt, fmac (chirp), mul, sin, fmac       6
+#   sinusoid adjoint: int add, cvt, fmac, mul, sin, cos,
+#                     fmac, mul, add, fmac, fmac                       11
+SLOTS = {(0, "grad"): 12.0, (1, "grad"): 17.0, (0, "fwd"): 5.0, (1, "fwd"): 6.0}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
@@ -75,13 +85,20 @@ def log(*a):
 
 
 def roofline(model, kind, comp_samples, kern_ms, kernel):
+    """ALU roofline of the population kernel: its algorithmic work in FP32-FMA
+    slots (times 2 flops) per launch over the launch's time, against the FP32
+    FMA ceiling without packed instructions; the fraction of the published
+    (packed) figure is given beside it."""
     slots = SLOTS[(model, kind)] * comp_samples
     achieved = 2.0 * slots / (kern_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": kernel, "kernel_ms": round(kern_ms, 5),
-            "work": f"{comp_samples:.4e} component-samples x {SLOTS[(model, kind)]} "
-                    f"FP32-FMA-equivalent slots"}
+            "work": f"{comp_samples:.4e} component-samples x {SLOTS[(model, kind)]:g} "
+                    f"FP32-FMA slots x 2 flops",
+            "peak_basis": "FP32 FMA issue without packed instructions (64 lanes/CU/clock, "
+                          "measured 63 by the issue probe)",
+            "frac_of_published_fp32": round(achieved / PUBLISHED_FP32_TFLOPS, 4)}
 
 
 def component_samples(w, s_lo, s_hi):
@@ -128,6 +145,16 @@ def cpu_sample(w, per_eval_fn, budget_s, rng):
     return idx, wl.subsample(w, idx)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def setup(w, dev, smcx, torch):
     inj = torch.tensor(w.inj, device=dev)
     d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, inj, w.T, w.t_start, w.dt)
@@ -135,7 +162,12 @@ def setup(w, dev, smcx, torch):
     return d, prob, torch.tensor(w.offsets, device=dev), torch.tensor(w.theta, device=dev)
 
 
-def bench_grad(args, w, dev, smcx, np, torch):
+def bench_grad(args, w, dev, smcx, np, torch, cpu_seconds, cpu1_seconds, check_all=False):
+    """One logl_grad_batch call over the population per step. Besides the
+    timed value: the plain one-particle-per-launch FP64 form over the whole
+    population, the oracle on a bounded sample (all host threads, then one
+    thread on a smaller sample), and the error of both GPU forms against the
+    oracle on that sample (the whole population with check_all)."""
     d, prob, off, th = setup(w, dev, smcx, torch)
     beta = torch.tensor(w.beta, device=dev)
     logl = torch.empty(w.N, dtype=torch.float64, device=dev)
@@ -146,7 +178,7 @@ def bench_grad(args, w, dev, smcx, np, torch):
         tuned = (S, chunk, so, float("nan"))
     else:
         tuned = prob.autotune(smcx.KIND_GRAD, off, th, beta, reps=5)
-    log(f"[bench] tiling S={tuned[0]} chunk={tuned[1]} sorted={tuned[2]} "
+    log(f"[bench] {w.name}: tiling S={tuned[0]} chunk={tuned[1]} sorted={tuned[2]} "
         f"({tuned[3]:.4f} ms/call when tuned)")
 
     def step():
@@ -154,9 +186,9 @@ def bench_grad(args, w, dev, smcx, np, torch):
 
     ms, kern_ms, _ = timed(step, prob, args.steps, args.warmup)
     value = w.N / (ms * 1e-3)
-    log(f"[bench] {ms:.4f} ms/step, kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
+    log(f"[bench] {w.name}: {ms:.4f} ms/step, pop_kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
     rl = roofline(w.model, "grad", component_samples(w, 0, w.T), kern_ms,
-                  "pop_kernel (fused forward+adjoint)")
+                  f"pop_kernel<{w.model},{tuned[0]},true> (fused forward+adjoint)")
     pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
     if pmc and pmc["kernels_sha1"] == kernels_sha1():
         rl["traffic"] = pmc["bytes"]
@@ -177,7 +209,7 @@ def bench_grad(args, w, dev, smcx, np, torch):
         plain = {"value": w.N / (plain_ms * 1e-3), "unit": "evals/s", "ms_per_step": plain_ms,
                  "form": "one particle per forward+adjoint launch pair, FP64"}
         plain_l, plain_g = pl.cpu().numpy(), pg.cpu().numpy()
-        log(f"[bench] plain form {plain_ms:.1f} ms/step")
+        log(f"[bench] {w.name}: plain form {plain_ms:.1f} ms/step")
 
     cpu = accuracy = None
     if not args.no_cpu_baseline:
@@ -187,24 +219,47 @@ def bench_grad(args, w, dev, smcx, np, torch):
         oracle.build(force=False)
         d_host = d.cpu().numpy()
         rng = np.random.default_rng(2024)
-        idx, sub = cpu_sample(w, lambda s: oracle.logl_grad(w.model, d_host, w.t_start, w.dt,
-                                                            w.sigma, s.offsets, s.theta, s.beta),
-                              args.cpu_seconds, rng)
+
+        def orc(s):
+            return oracle.logl_grad(w.model, d_host, w.t_start, w.dt, w.sigma, s.offsets, s.theta,
+                                    s.beta)
+
+        if check_all:
+            idx = np.arange(w.N)
+            sub = w
+        else:
+            idx, sub = cpu_sample(w, orc, cpu_seconds, rng)
+        threads = oracle.get_threads()
         t0 = time.perf_counter()
-        ref_l, ref_g = oracle.logl_grad(w.model, d_host, w.t_start, w.dt, w.sigma, sub.offsets,
-                                        sub.theta, sub.beta)
+        ref_l, ref_g = orc(sub)
         cpu_s = time.perf_counter() - t0
         n = len(idx)
-        cpu = {"value": n / cpu_s, "unit": "evals/s", "cores": oracle.get_threads(),
-               "kind": "oracle",
+        # one host thread on a smaller sample of the same workload
+        oracle.set_threads(1)
+        try:
+            idx1, sub1 = cpu_sample(w, orc, cpu1_seconds, np.random.default_rng(2026))
+            t0 = time.perf_counter()
+            orc(sub1)
+            cpu1_s = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(threads)
+        cpu = {"value": n / cpu_s, "unit": "evals/s", "cores": threads, "kind": "oracle",
                "sample": f"{n} of {w.N} particles of the same workload (seeded), all {w.T} "
-                         f"samples, {cpu_s:.1f} s"}
-        log(f"[bench] cpu oracle {n} particles in {cpu_s:.1f} s")
+                         f"samples, {cpu_s:.1f} s on {threads} threads",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "value_1_thread": len(idx1) / cpu1_s,
+               "sample_1_thread": f"{len(idx1)} particles, {cpu1_s:.1f} s"}
+        log(f"[bench] {w.name}: cpu oracle {n} particles in {cpu_s:.1f} s ({threads} threads), "
+            f"{len(idx1)} in {cpu1_s:.1f} s (1 thread)")
         rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
         el = pm.logl_errors(out_l[idx], ref_l)
         rel, cos = pm.grad_errors(w.model, sub.offsets, sub.theta, out_g[rows], ref_g, w.T, w.dt)
-        accuracy = {"checked_particles": n, "logl_max_rel_err": float(el.max()),
+        Ks = np.diff(w.offsets)[idx]
+        accuracy = {"checked_particles": n, "max_K_checked": int(Ks.max()),
+                    "logl_max_rel_err": float(el.max()),
+                    "logl_p99_rel_err": float(np.percentile(el, 99)),
                     "grad_max_rel_err": float(rel.max()) if len(rel) else 0.0,
+                    "grad_p99_rel_err": float(np.percentile(rel, 99)) if len(rel) else 0.0,
                     "grad_min_cos": float(cos.min()) if len(cos) else 1.0}
         if plain is not None:
             pel = pm.logl_errors(plain_l[idx], ref_l)
@@ -416,10 +471,11 @@ def bench_metric(args, w, dev, smcx, np, torch):
     jvals = float(np.count_nonzero(K) * 32 * nb * w.T)                  # J~ entries formed
     tf = issued / (ms * 1e-3) / 1e12
     value = w.N / (ms * 1e-3)
-    # the J entries are synthesised on the vector units, 13 FP32-FMA-equivalent
-    # slots each (sub, fma, mul, exp2 = 4, two fma, mul, f16 convert, select),
-    # which is what bounds the kernel; the matrix cores carry the contraction
-    slots_tf = 2.0 * 13 * jvals / (ms * 1e-3) / 1e12
+    # the J entries are synthesised on the vector units, 8 FP32-FMA slots each
+    # (sub 1/2, fma 1, mul 1/2, exp2 2, two fma 2, mul 1/2, f16 convert 1,
+    # select 1/2), which is what bounds the kernel; the matrix cores carry the
+    # contraction
+    slots_tf = 2.0 * 8 * jvals / (ms * 1e-3) / 1e12
     log(f"[bench] metric {ms:.4f} ms/step, {value:.4e} particles/s, MFMA {tf:.1f} TFLOP/s issued")
     return dict(metric="particle Gauss-Newton metrics/sec (FP16 matrix cores, FP64 output)",
                 value=value, unit="particles/s", ms_per_step=ms,
@@ -428,7 +484,7 @@ def bench_metric(args, w, dev, smcx, np, torch):
                 roofline={"bound": "alu", "achieved": round(slots_tf, 3), "peak": PEAK_FP32_TFLOPS,
                           "unit": "TFLOP/s", "frac": round(slots_tf / PEAK_FP32_TFLOPS, 4),
                           "traffic": None, "kernel": "metric_kernel", "kernel_ms": round(ms, 5),
-                          "work": f"{jvals:.4e} J entries x 13 FP32-FMA-equivalent slots",
+                          "work": f"{jvals:.4e} J entries x 8 FP32-FMA slots x 2 flops",
                           "mfma_issued_tflops": round(tf, 2), "mfma_peak_fp16_tflops": 2500.0,
                           "mfma_frac": round(tf / 2500.0, 4),
                           "useful_tflops": round(useful / (ms * 1e-3) / 1e12, 2)})
@@ -561,117 +617,6 @@ def bench_smc_gblisa(args, dev, smcx, np, torch):
                         "leapfrog_grads_per_s": grads / total})
 
 
-def bench_gb_durations(args, dev, smcx, np, torch):
-    """The paper's Galactic-binary study over record lengths (Sec. "LISA
-    Galactic binaries": from three months to a year in steps of one month,
-    N = 40000, ten noise-free binaries): at each length a prior-start run, and
-    a posterior-start run bridged (eq. reuse_bridge) from the previous
-    length's final population. Reports SMC iterations and seconds of both."""
-    from paper_2609_17674_amd import smc
-    from paper_2609_17674_amd import workloads as wl
-    N, k_hi = args.gb_n, 10
-    w = wl.make_gblisa(N=16, k_lo=1, k_hi=k_hi, n_inj=10, noise=False)
-    inj = torch.tensor(w.inj, device=dev)
-    lo = torch.tensor(wl.GBLISA_PRIOR[:, 0].copy(), device=dev)
-    hi = torch.tensor(wl.GBLISA_PRIOR[:, 1].copy(), device=dev)
-    rows, prev, total_t, total_pi = [], None, 0.0, 0
-    for m in range(3, 13):
-        T = w.T_obs * m / 12.0
-        k0 = wl.gblisa_band(T)
-        d = smcx.template_spectrum(wl.GBLISA, inj, T, k0, w.B)
-        prob = smcx.Problem.frequency_domain(wl.GBLISA, d, k0, T, w.S, k_hi, N, N * k_hi)
-        cfg = dict(N=N, k_lo=1, k_hi=k_hi, max_iters=400, metric=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pr = smc.run_prior_start(prob, lo, hi, smc.SMCConfig(seed=400 + m, **cfg))
-        torch.cuda.synchronize()
-        t_pr = time.perf_counter() - t0
-        row = {"months": m, "prior_start": {"iterations": pr.iterations, "seconds": round(t_pr, 3),
-                                            "K_mode": int(np.argmax(pr.k_hist[-1]))}}
-        total_t += t_pr
-        total_pi += N * pr.iterations
-        if prev is not None:
-            pprob, pres = prev
-            t0 = time.perf_counter()
-            po = smc.run_bridge_start(prob, pprob, pres.offsets, pres.theta, lo, hi,
-                                      smc.SMCConfig(seed=500 + m, **cfg))
-            torch.cuda.synchronize()
-            t_po = time.perf_counter() - t0
-            row["posterior_start"] = {"iterations": po.iterations, "seconds": round(t_po, 3),
-                                      "K_mode": int(np.argmax(po.k_hist[-1]))}
-            total_t += t_po
-            total_pi += N * po.iterations
-            prev = (prob, po)
-        else:
-            prev = (prob, pr)
-        log(f"[bench] {m} months: {row}")
-        rows.append(row)
-    return dict(metric="particle-iterations/sec of the Galactic-binary duration study "
-                       "(prior-start and posterior-start SMC, 3..12 months)",
-                value=total_pi / total_t, unit="particle-iterations/s",
-                ms_per_step=1e3 * total_t, dtype="f64",
-                config={"workload": "gb_durations", "N": N, "n_injected": 10,
-                        "K_range": [1, k_hi], "bins": w.B, "runs": rows})
-
-
-def bench_pulse_durations(args, dev, smcx, np, torch):
-    """The paper's pulse study over record lengths (Sec. "Sequence of gaussian
-    pulses": iterations of prior-start and posterior-start SMC as the analysed
-    portion of the record grows): the ten-pulse record of smc_pulses (N = 6000,
-    K in [1, 10]) cut at 1/4, 3/8, .., 1 of its 4096 samples; at each length a
-    prior-start run and a posterior-start run from the previous length's final
-    population through the bridge split at the previous length."""
-    from paper_2609_17674_amd import smc
-    from paper_2609_17674_amd import workloads as wl
-    w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
-    d = torch.tensor(w.noise, device=dev) + smcx.template_sum(w.model, torch.tensor(w.inj, device=dev),
-                                                               w.T, w.t_start, w.dt)
-    N, k_hi = w.N, w.k_max
-    lo = torch.tensor(wl.PULSE_PRIOR[:, 0].copy(), device=dev)
-    hi = torch.tensor(wl.PULSE_PRIOR[:, 1].copy(), device=dev)
-    rows, prev, total_t, total_pi = [], None, 0.0, 0
-    for eighth in range(2, 9):
-        n = w.T * eighth // 8
-        prob = smcx.Problem(w.model, d[:n].contiguous(), w.t_start, w.dt, w.sigma, k_hi, N, N * k_hi)
-        for kind in (smcx.KIND_GRAD, smcx.KIND_LOGL):
-            prob.set_tiling(kind, 32, 4096, 1)
-        prob.set_tiling(smcx.KIND_DELTA, 16, 4096, 1)
-        cfg = dict(N=N, k_lo=1, k_hi=k_hi, max_iters=400, metric=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pr = smc.run_prior_start(prob, lo, hi, smc.SMCConfig(seed=600 + eighth, **cfg))
-        torch.cuda.synchronize()
-        t_pr = time.perf_counter() - t0
-        n_in = int(np.sum(w.inj[:, 1] < w.t_start + n * w.dt))
-        row = {"samples": n, "injected_in_record": n_in,
-               "prior_start": {"iterations": pr.iterations, "seconds": round(t_pr, 3),
-                               "K_mode": int(np.argmax(pr.k_hist[-1]))}}
-        total_t += t_pr
-        total_pi += N * pr.iterations
-        if prev is not None:
-            n_prev, pres = prev
-            t0 = time.perf_counter()
-            po = smc.run_posterior_start(prob, n_prev, pres.offsets, pres.theta, lo, hi,
-                                         smc.SMCConfig(seed=700 + eighth, **cfg))
-            torch.cuda.synchronize()
-            t_po = time.perf_counter() - t0
-            row["posterior_start"] = {"iterations": po.iterations, "seconds": round(t_po, 3),
-                                      "K_mode": int(np.argmax(po.k_hist[-1]))}
-            total_t += t_po
-            total_pi += N * po.iterations
-            prev = (n, po)
-        else:
-            prev = (n, pr)
-        log(f"[bench] {n} samples: {row}")
-        rows.append(row)
-    return dict(metric="particle-iterations/sec of the pulse duration study (prior-start and "
-                       "posterior-start SMC)",
-                value=total_pi / total_t, unit="particle-iterations/s",
-                ms_per_step=1e3 * total_t,
-                config={"workload": "pulse_durations", "N": N, "n_injected": len(w.inj),
-                        "K_range": [1, k_hi], "T": w.T, "runs": rows})
-
-
 def _gb_subset(w, idx):
     import numpy as np
     from types import SimpleNamespace
@@ -680,6 +625,35 @@ def _gb_subset(w, idx):
     off[1:] = np.cumsum(K)
     rows = np.concatenate([np.arange(w.offsets[i], w.offsets[i + 1]) for i in idx])
     return SimpleNamespace(offsets=off, theta=w.theta[rows], beta=w.beta[idx])
+
+
+def issue_probe(args, smcx, torch):
+    """VALU issue ceilings of this device: each instruction kind of the
+    population kernels at 1, 2, 4 and 8 waves per SIMD, in lane-instructions
+    per clock per compute unit (published engine clock 2.4 GHz)."""
+    props = torch.cuda.get_device_properties(0)
+    n_cu = props.multi_processor_count
+    inp = torch.rand(256, dtype=torch.float32, device="cuda")
+    out = torch.empty(n_cu * 8 * 256, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    table = {}
+    for kind in smcx.PROBE_KINDS:
+        row = {}
+        for wps in (1, 2, 4, 8):
+            blocks, iters = n_cu * wps, 2048
+            smcx.issue_probe(kind, blocks, 16, inp, out)
+            best = float("inf")
+            for _ in range(max(args.steps, 1)):
+                ev[0].record()
+                ops = smcx.issue_probe(kind, blocks, iters, inp, out)
+                ev[1].record()
+                torch.cuda.synchronize()
+                best = min(best, ev[0].elapsed_time(ev[1]))
+            row[wps] = round(ops / (best * 1e-3) / n_cu / CLOCK_HZ, 2)
+        table[kind] = row
+        log(f"[bench] {kind}: lanes/clk/CU by waves per SIMD {row}")
+    print(json.dumps({"issue_probe_lanes_per_clk_per_cu": table, "compute_units": n_cu,
+                      "clock_hz": CLOCK_HZ}), flush=True)
 
 
 def copy_probe(args, torch):
@@ -700,16 +674,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="pulse_batch",
-                    choices=["pulse_batch", "gb_grad", "gb_extend", "pulse_mutate", "smc_pulses",
-                             "metric", "gb_lisa", "smc_gblisa", "gb_durations", "pulse_durations",
-                             "copy_probe"])
-    ap.add_argument("--gb-n", type=int, default=40000, help="particles of the gb_durations study")
+    ap.add_argument("--workload", default="gb_grad",
+                    choices=["gb_grad", "pulse_batch", "gb_extend", "pulse_mutate", "smc_pulses",
+                             "metric", "gb_lisa", "smc_gblisa", "copy_probe", "issue_probe"])
     ap.add_argument("--tiling", default="",
                     help="S,chunk_len,sorted: fixed tiling of the timed call kind, no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu1-seconds", type=float, default=3.0,
+                    help="budget of the one-thread oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="gb_grad only: skip the pulse_batch line attached as 'secondary'")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -728,38 +704,37 @@ def main():
     if args.workload == "copy_probe":
         copy_probe(args, torch)
         return
+    if args.workload == "issue_probe":
+        issue_probe(args, smcx, torch)
+        return
+    secondary = None
     if args.workload == "gb_lisa":
         res = bench_gblisa(args, dev, smcx, np, torch)
-        w = None
     elif args.workload == "smc_gblisa":
         res = bench_smc_gblisa(args, dev, smcx, np, torch)
-        w = None
-    elif args.workload == "gb_durations":
-        res = bench_gb_durations(args, dev, smcx, np, torch)
-        w = None
-    elif args.workload == "pulse_durations":
-        res = bench_pulse_durations(args, dev, smcx, np, torch)
-        w = None
     elif args.workload == "smc_pulses":
         w = wl.make_config("pulse_batch", N=6000, n_inj=10, k_lo=1, k_hi=10)
-    elif args.workload == "metric":
-        w = wl.make_config("pulse_batch")
-    else:
-        w = wl.make_config(args.workload)
-    if w is not None:
-        log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
-    if args.workload in ("gb_lisa", "smc_gblisa", "gb_durations", "pulse_durations"):
-        pass
-    elif args.workload in ("pulse_batch", "gb_grad"):
-        res = bench_grad(args, w, dev, smcx, np, torch)
-    elif args.workload == "gb_extend":
-        res = bench_extend(args, w, dev, smcx, np, torch)
-    elif args.workload == "smc_pulses":
         res = bench_smc(args, w, dev, smcx, np, torch)
     elif args.workload == "metric":
-        res = bench_metric(args, w, dev, smcx, np, torch)
+        res = bench_metric(args, wl.make_config("pulse_batch"), dev, smcx, np, torch)
     else:
-        res = bench_mutate(args, w, dev, smcx, np, torch)
+        w = wl.make_config(args.workload)
+        log(f"[bench] workload {w.name}: N={w.N} T={w.T} M={w.M}")
+        if args.workload in ("pulse_batch", "gb_grad"):
+            res = bench_grad(args, w, dev, smcx, np, torch, args.cpu_seconds, args.cpu1_seconds,
+                             check_all=args.workload == "pulse_batch")
+            if args.workload == "gb_grad" and not args.no_secondary:
+                w2 = wl.make_config("pulse_batch")
+                log(f"[bench] secondary workload {w2.name}: N={w2.N} T={w2.T} M={w2.M}")
+                r2 = bench_grad(args, w2, dev, smcx, np, torch, args.cpu_seconds,
+                                args.cpu1_seconds, check_all=True)
+                secondary = {k: r2[k] for k in ("value", "unit", "ms_per_step", "config",
+                                                "plain_gpu", "speedup_vs_plain", "accuracy",
+                                                "roofline", "cpu_baseline")}
+        elif args.workload == "gb_extend":
+            res = bench_extend(args, w, dev, smcx, np, torch)
+        else:
+            res = bench_mutate(args, w, dev, smcx, np, torch)
     line = {
         "metric": res["metric"],
         "value": res["value"],
@@ -778,6 +753,8 @@ def main():
     for key in ("plain_gpu", "speedup_vs_plain", "accuracy", "roofline", "cpu_baseline"):
         if key in res:
             line[key] = res[key]
+    if secondary is not None:
+        line["secondary"] = secondary
     print(json.dumps(line), flush=True)
 
 

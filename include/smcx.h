@@ -92,7 +92,7 @@ typedef struct smcx_problem smcx_problem;
 enum {
   SMCX_OK = 0,
   SMCX_EINVAL = -1,   /* bad argument, detected before launch */
-  SMCX_ENOMEM = -2,   /* device allocation failed (create only) */
+  SMCX_ENOMEM = -2,   /* device allocation failed, or a size beyond a fixed workspace */
   SMCX_EDEVICE = -3,  /* HIP runtime error, or a device-side flag was raised */
   SMCX_ECAPTURE = -4  /* call not allowed while the stream is being captured */
 };
@@ -666,6 +666,33 @@ int smcx_rj_apply(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t
  * begin creates the events (host-side HIP objects, no device memory). */
 int smcx_profile_begin(smcx_problem* prob, int32_t max_launches);
 int smcx_profile_end(smcx_problem* prob, double* total_ms, int64_t* launches);
+
+/* Instruction kinds of smcx_issue_probe. */
+enum {
+  SMCX_PROBE_FMA_F32 = 0,   /* v_fma_f32 */
+  SMCX_PROBE_MUL_F32 = 1,   /* v_mul_f32 */
+  SMCX_PROBE_EXP_F32 = 2,   /* v_exp_f32 (base 2) */
+  SMCX_PROBE_SIN_F32 = 3,   /* v_sin_f32 (argument in revolutions) */
+  SMCX_PROBE_FMA_F64 = 4,   /* v_fma_f64 */
+  SMCX_PROBE_ADD_U32 = 5,   /* v_add_u32 */
+  SMCX_PROBE_CVT = 6,       /* v_cvt_f32_i32 */
+  SMCX_PROBE_SIN_4FMA = 7,  /* one v_sin_f32 and four v_fmac_f32 per step */
+  SMCX_PROBE_FMAC_F32 = 8,  /* v_fmac_f32 (the two-operand accumulator form) */
+  SMCX_PROBE_ADD_F32 = 9    /* v_add_f32 */
+};
+
+/* The measured VALU ceilings the roofline of the population kernels refers
+ * to (the vector issue limit of the chip, not an operation of the paper's
+ * method). Launches `blocks` workgroups of 256 lanes; every lane runs
+ * 32 * iters steps of eight independent dependency chains of instruction
+ * kind `op`, so the kernel time divided into *lane_ops (set on return: the
+ * number of lane-instructions the launch issues) is that kind's issue rate
+ * at the occupancy the grid gives (blocks = compute units x waves per SIMD).
+ * in: [256] FP32 device inputs (chain seeds); out: [blocks * 256] FP32
+ * device outputs (chain results, so that nothing is optimised away). The
+ * caller times the launch (events on hip_stream). */
+int smcx_issue_probe(int op, int32_t blocks, int32_t iters, const float* in, float* out,
+                     int64_t* lane_ops, void* hip_stream);
 
 #ifdef __cplusplus
 }

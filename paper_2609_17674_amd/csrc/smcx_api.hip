@@ -150,32 +150,45 @@ int check_pop(const smcx_problem* p, int64_t N, const int64_t* offsets, int64_t 
 }
 
 // Bracket the batched kernels of one call with events when profiling is on.
+// With `inner` the stop event is recorded by the launcher right after the
+// population kernel (before any pass that combines chunk partials).
 struct ProfScope {
   smcx_problem* p;
   hipStream_t st;
   bool on;
+  bool inner = false;
   ProfScope(smcx_problem* p_, hipStream_t st_) : p(p_), st(st_), on(false) {
     if (p->prof_on && 2 * (size_t)p->prof_n + 1 < p->prof_ev.size() && !capturing(st)) {
       on = hipEventRecord(p->prof_ev[2 * p->prof_n], st) == hipSuccess;
     }
   }
   ~ProfScope() {
-    if (on && hipEventRecord(p->prof_ev[2 * p->prof_n + 1], st) == hipSuccess) ++p->prof_n;
+    if (!on) return;
+    if (inner || hipEventRecord(p->prof_ev[2 * p->prof_n + 1], st) == hipSuccess) ++p->prof_n;
   }
 };
 
 // A batched launch under the profiling events. On the frequency-domain model
 // the pass that writes the source constants runs before the first event
 // when profiling is on, so that the events time the likelihood kernel alone.
+// `pop` marks launches of the time-domain population kernel, whose launcher
+// records the stop event itself (a.prof_stop).
 template <class Launch>
-hipError_t profiled(smcx_problem* p, smcx::PopArgs a, hipStream_t st, Launch launch) {
+hipError_t profiled(smcx_problem* p, smcx::PopArgs a, hipStream_t st, Launch launch,
+                    bool pop = false) {
   if (p->fd && p->prof_on) {
     hipError_t e = smcx::launch_fd_src(a, st);
     if (e != hipSuccess) return e;
     a.fd_src_ready = 1;
   }
   ProfScope ps(p, st);
-  return launch(a);
+  if (ps.on && pop && !p->fd) {
+    a.prof_stop = p->prof_ev[2 * p->prof_n + 1];
+    ps.inner = true;
+  }
+  hipError_t e = launch(a);
+  if (e != hipSuccess) ps.inner = false;
+  return e;
 }
 
 smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
@@ -618,7 +631,7 @@ int logl_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.logl = logl;
   e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
     return smcx::launch_forward(p->model, t, b, st);
-  });
+  }, true);
   if (e != hipSuccess) return hip_fail(e, "logl launch");
   return SMCX_OK;
 }
@@ -650,7 +663,7 @@ static int grad_batch(smcx_problem* p, int64_t N, const int64_t* offsets, int64_
   a.active = mask;
   e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
     return smcx::launch_fused(p->model, t, b, st);
-  });
+  }, true);
   if (e != hipSuccess) return hip_fail(e, "logl_grad launch");
   return SMCX_OK;
 }
@@ -757,7 +770,7 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
     a.logl = logl_ext;
     e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
       return smcx::launch_forward(p->model, t, b, st);
-    });
+    }, true);
     if (e != hipSuccess) return hip_fail(e, "segment logl launch");
   }
   hipError_t e = smcx::launch_reweight_reduce(N, delta_beta, logl_ext, logw_prev, logw, w_norm,
@@ -854,7 +867,7 @@ int smcx_leapfrog(smcx_problem* p, int64_t N, const int64_t* offsets, int64_t M,
   a.dir = dir;
   e = profiled(p, a, st, [&](const smcx::PopArgs& b) {
     return smcx::launch_fused(p->model, t, b, st);
-  });
+  }, true);
   if (e != hipSuccess) return hip_fail(e, "leapfrog gradient launch");
   return SMCX_OK;
 }

@@ -93,6 +93,8 @@ struct PopArgs {
   double* dlogl_birth;
   double* dlogl_death;
   int* flag;
+  void* prof_stop;         // hipEvent_t the launcher records right after the population
+                           // kernel (profiling), or nullptr
   // frequency-domain (LISA Galactic-binary) problems
   const double* fd_data;   // [2][Bp][2] band spectrum of A and E (re, im), Bp = 128 or 256
   double* fd_src;           // [M][34] source constants (the handle's workspace)

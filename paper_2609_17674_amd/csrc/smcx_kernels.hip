@@ -1164,7 +1164,7 @@ hipError_t launch_pop_model(const Tiling& t, const PopArgs& a, hipStream_t st) {
   const int wpb = waves_per_block(MODEL, a.k_max, GRAD);
   const size_t lds = pop_lds_bytes_per_wave(MODEL, a.k_max, GRAD) * wpb;
   const int64_t items = a.N * (int64_t)a.nch;
-  if (items == 0) return hipSuccess;
+  if (items == 0) return a.prof_stop ? hipEventRecord((hipEvent_t)a.prof_stop, st) : hipSuccess;
   const dim3 grid((unsigned)((items + wpb - 1) / wpb));
   const dim3 block(64 * wpb);
   switch (t.S) {
@@ -1175,6 +1175,7 @@ hipError_t launch_pop_model(const Tiling& t, const PopArgs& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && a.prof_stop) e = hipEventRecord((hipEvent_t)a.prof_stop, st);
   if (e != hipSuccess || a.nch == 1) return e;
   const dim3 fgrid((unsigned)((a.N + 3) / 4));
   hipLaunchKernelGGL((finalize_kernel<MODEL, GRAD>), fgrid, dim3(256), 0, st, a);

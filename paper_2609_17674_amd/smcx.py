@@ -56,6 +56,7 @@ def load_library():
         "logl_grad_batch": [P, I64, P, I64, P, P, P, P, P],
         "logl_grad_batch_masked": [P, I64, P, I64, P, P, P, P, P, P],
         "logl_grad_batch_static": [I, P, I64, D, D, D, I32, I64, P, I64, P, P, P, P, P],
+        "smcx_issue_probe": [I, I32, I32, P, P, ctypes.POINTER(I64), P],
         "delta_logl_birth_death": [P, I64, P, I64, P, P, P, P, P, P, P],
         "delta_logl_birth_death_masked": [P, I64, P, I64, P, P, P, P, P, P, P, P],
         "reweight_extend": [P, I64, I64, I64, P, I64, P, D, P, P, P, P, P, P],
@@ -302,6 +303,24 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
                                           _ptr(theta), _ptr(beta), _ptr(logl), _ptr(grad),
                                           _stream(stream)))
     return logl, grad
+
+
+PROBE_KINDS = {"fma_f32": 0, "mul_f32": 1, "exp_f32": 2, "sin_f32": 3, "fma_f64": 4,
+               "add_u32": 5, "cvt": 6, "sin_4fma": 7, "fmac_f32": 8, "add_f32": 9}
+
+
+def issue_probe(kind: str, blocks: int, iters: int, inp: torch.Tensor, out: torch.Tensor,
+                stream=None) -> int:
+    """Launch the VALU issue-rate probe (smcx_issue_probe); returns the number of
+    lane-instructions the launch issues. The caller times it on `stream`."""
+    inp = _dev(inp, torch.float32, "in")
+    out = _dev(out, torch.float32, "out")
+    if inp.numel() < 256 or out.numel() < int(blocks) * 256:
+        raise ValueError("in needs 256 entries and out blocks * 256")
+    n = ctypes.c_int64()
+    _check(load_library().smcx_issue_probe(PROBE_KINDS[kind], int(blocks), int(iters), _ptr(inp),
+                                           _ptr(out), ctypes.byref(n), _stream(stream)))
+    return int(n.value)
 
 
 def logl_grad_batch_static(model: int, d, t_start: float, dt: float, sigma: float, k_max: int,
