@@ -26,6 +26,14 @@ Parity status of each function (what pins it is listed in the tests under
 * ``nuts_transition_metric``: pinned by the identity factor (equal to the
   plain transition) and by the unit harmonic oscillator that a leapfrog step
   in whitened coordinates follows near a noise-free fit.
+* ``nuts_transition`` / ``nuts_transition_metric`` tree building: pinned by a
+  direct statement of the transition from its definition (tests/nuts_direct.py:
+  the whole trajectory laid out, every aligned block summed from its own
+  points, the proposal's law in closed form) for depths 1 to 6, U-turns inside
+  subtrees and of the whole trajectory, divergences at the prior box, the
+  proposal frequencies and the roles of the uniforms; and by an
+  importance-weighted stationarity check (the transition keeps the target's
+  moments). Planted mistakes in a copy of the tree code are caught.
 """
 from __future__ import annotations
 
@@ -45,16 +53,38 @@ PULSE = 0
 GBSINE = 1
 
 
+def _gcc(out: str, sources) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-o", tmp] + list(sources) + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math, no FMA contraction)."""
     newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_GB))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, _SRC_GB, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
+        _gcc(_LIB, [_SRC, _SRC_GB])
     return _LIB
+
+
+def build_variant(out_dir: str, edits) -> str:
+    """Compile a copy of the oracle with textual edits [(old, new), ...] applied
+    to smcx_oracle.c (each `old` must occur exactly once) into out_dir; for the
+    tests that plant a mistake in the oracle and check that a pin catches it.
+    Returns the library path; load it with bind()."""
+    src = open(_SRC).read()
+    for old, new in edits:
+        if src.count(old) != 1:
+            raise ValueError(f"edit target occurs {src.count(old)} times: {old!r}")
+        src = src.replace(old, new)
+    c_path = os.path.join(out_dir, "smcx_oracle_variant.c")
+    with open(c_path, "w") as f:
+        f.write(src)
+    out = os.path.join(out_dir, "liboracle_variant.so")
+    _gcc(out, [c_path, _SRC_GB])
+    return out
 
 
 _lib = None
@@ -65,54 +95,59 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        I64 = ctypes.c_int64
-        D = ctypes.c_double
-        I = ctypes.c_int
-        lib.oracle_n_params.argtypes = [I]
-        lib.oracle_set_threads.argtypes = [I]
-        lib.oracle_set_threads.restype = None
-        lib.oracle_get_threads.restype = I
-        lib.oracle_template_sum.argtypes = [I, I64, P, I64, D, D, P]
-        lib.oracle_logl.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P]
-        lib.oracle_logl_grad.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P]
-        lib.oracle_delta_logl_birth_death.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, P, P]
-        lib.oracle_reweight_extend.argtypes = [I, P, D, D, D, I64, I64, I64, P, P, D, P, P, P, P, P]
-        lib.oracle_next_beta.argtypes = [I64, P, P, D, D, P, P, P]
-        lib.oracle_resample_systematic.argtypes = [I, I64, P, P, P, D, I64, P, P, P]
-        lib.oracle_rj_apply.argtypes = [I, I64, P, P, P, P, P, P, P, P, ctypes.c_int32,
-                                        ctypes.c_int32, D, I64, P, P, P]
-        lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
-        lib.oracle_nuts_transition.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P, P, P, P,
-                                               P, P, P, P, P, P]
-        lib.oracle_logl_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P]
-        lib.oracle_logl_grad_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P, P]
-        lib.oracle_delta_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, I64, P, P]
-        lib.oracle_leapfrog_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, I64, P, P,
-                                              P, P]
-        lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
-                                                     P, P, P, I64, P, P, P, P, P, P]
-        lib.oracle_fisher.argtypes = [I, I64, D, D, D, I64, P, P, P, P, P]
-        lib.oracle_fisher_split.argtypes = [I, I64, D, D, D, I64, P, P, P, I64, P, P]
-        lib.oracle_nuts_transition_metric.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P,
-                                                      P, P, P, P, I64, P, P, P, P, P, P, P, P]
-        lib.oracle_metric_factor.argtypes = [I, I64, P, P, P, P, P, P]
-        lib.oracle_gblisa_tensors.argtypes = [D, P, P]
-        lib.oracle_gblisa_tensors.restype = None
-        lib.oracle_gblisa_positions.argtypes = [D, P]
-        lib.oracle_gblisa_positions.restype = None
-        lib.oracle_gblisa_response.argtypes = [D, D, D, D, P, P]
-        lib.oracle_gblisa_response.restype = None
-        lib.oracle_gblisa_strain.argtypes = [P, D, P]
-        lib.oracle_gblisa_strain.restype = None
-        lib.oracle_gblisa_spectrum.argtypes = [I64, P, D, I, I64, I64, P]
-        lib.oracle_gblisa_spectrum_dft.argtypes = [I64, P, D, I64, I64, I64, P]
-        lib.oracle_gblisa_logl_grad.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P]
-        lib.oracle_gblisa_delta.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P, P, P]
-        lib.oracle_gblisa_fisher.argtypes = [I64, I64, D, D, I, I64, P, P, P, P, P]
-        _lib = lib
+        _lib = bind(_LIB)
     return _lib
+
+
+def bind(path: str):
+    """Load an oracle library and declare its functions' argument types."""
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.oracle_n_params.argtypes = [I]
+    lib.oracle_set_threads.argtypes = [I]
+    lib.oracle_set_threads.restype = None
+    lib.oracle_get_threads.restype = I
+    lib.oracle_template_sum.argtypes = [I, I64, P, I64, D, D, P]
+    lib.oracle_logl.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P]
+    lib.oracle_logl_grad.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P]
+    lib.oracle_delta_logl_birth_death.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, P, P]
+    lib.oracle_reweight_extend.argtypes = [I, P, D, D, D, I64, I64, I64, P, P, D, P, P, P, P, P]
+    lib.oracle_next_beta.argtypes = [I64, P, P, D, D, P, P, P]
+    lib.oracle_resample_systematic.argtypes = [I, I64, P, P, P, D, I64, P, P, P]
+    lib.oracle_rj_apply.argtypes = [I, I64, P, P, P, P, P, P, P, P, ctypes.c_int32,
+                                    ctypes.c_int32, D, I64, P, P, P]
+    lib.oracle_leapfrog.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, P, P, P, P]
+    lib.oracle_nuts_transition.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P, P, P, P,
+                                           P, P, P, P, P, P]
+    lib.oracle_logl_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P]
+    lib.oracle_logl_grad_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, I64, P, P]
+    lib.oracle_delta_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, P, I64, P, P]
+    lib.oracle_leapfrog_split.argtypes = [I, P, I64, D, D, D, I64, P, P, P, P, D, P, I64, P, P,
+                                          P, P]
+    lib.oracle_nuts_transition_split.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P, P,
+                                                 P, P, P, I64, P, P, P, P, P, P]
+    lib.oracle_fisher.argtypes = [I, I64, D, D, D, I64, P, P, P, P, P]
+    lib.oracle_fisher_split.argtypes = [I, I64, D, D, D, I64, P, P, P, I64, P, P]
+    lib.oracle_nuts_transition_metric.argtypes = [I, P, I64, D, D, D, I64, P, P, D, I, P, P,
+                                                  P, P, P, P, I64, P, P, P, P, P, P, P, P]
+    lib.oracle_metric_factor.argtypes = [I, I64, P, P, P, P, P, P]
+    lib.oracle_gblisa_tensors.argtypes = [D, P, P]
+    lib.oracle_gblisa_tensors.restype = None
+    lib.oracle_gblisa_positions.argtypes = [D, P]
+    lib.oracle_gblisa_positions.restype = None
+    lib.oracle_gblisa_response.argtypes = [D, D, D, D, P, P]
+    lib.oracle_gblisa_response.restype = None
+    lib.oracle_gblisa_strain.argtypes = [P, D, P]
+    lib.oracle_gblisa_strain.restype = None
+    lib.oracle_gblisa_spectrum.argtypes = [I64, P, D, I, I64, I64, P]
+    lib.oracle_gblisa_spectrum_dft.argtypes = [I64, P, D, I64, I64, I64, P]
+    lib.oracle_gblisa_logl_grad.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P]
+    lib.oracle_gblisa_delta.argtypes = [P, I64, I64, D, D, I, I64, P, P, P, P, P, P, P]
+    lib.oracle_gblisa_fisher.argtypes = [I64, I64, D, D, I, I64, P, P, P, P, P]
+    return lib
 
 
 def _p(a: Optional[np.ndarray]):
