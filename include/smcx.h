@@ -539,6 +539,18 @@ int smcx_gauss_newton_metric_blocks_masked(smcx_problem* prob, int64_t N, const 
 int smcx_metric_factor_blocks(smcx_problem* prob, int64_t M, const double* F, const double* ridge,
                               double* W, void* hip_stream);
 
+/* The population-level mass matrix of a mutation step: the mean of the M
+ * per-source blocks F [M][P][P] (smcx_gauss_newton_metric_blocks' layout),
+ * written to F_mean [P][P]. Sec. "No-U-Turn-Sampler" sets the mass matrix to
+ * the Hessian of the negative log posterior without saying where it is
+ * taken; a matrix taken at each particle's own position would make the NUTS
+ * move not leave the tempered target invariant (the reverse move would use
+ * another matrix), while one matrix for the whole population, fixed for the
+ * step, does. Summed in a fixed order (bitwise reproducible); 1 <= M <=
+ * m_max. Uses the handle's workspace: order calls on one stream. */
+int smcx_metric_pool_blocks(smcx_problem* prob, int64_t M, const double* F, double* F_mean,
+                            void* hip_stream);
+
 /* Posterior-start bridge (eq. reuse_bridge). For white noise the bridge
  * p(theta|d1) (p(theta|d2)/p(theta|d1))^beta from the posterior on the first
  * `split` samples d1 to the posterior on all T samples d2 has the

@@ -406,6 +406,7 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
     p->prefix[s + 1] = p->prefix[s] + h[s] * h[s];
   }
   const size_t part_elems = (size_t)p->max_nch * (size_t)std::max<int64_t>(n_max, 1) * 4;
+  p->part_cap = part_elems;
   const size_t partg_elems = p->max_nch_grad > 1
                                  ? (size_t)p->max_nch_grad * (size_t)std::max<int64_t>(m_max, 1) * p->P
                                  : 1;
@@ -506,6 +507,7 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
   p->prefix = {0.0, energy};
   fd_table_host(T_obs, tab);
   const size_t n1 = (size_t)std::max<int64_t>(n_max, 1);
+  p->part_cap = n1 * 4;
   struct { void** ptr; size_t bytes; } allocs[] = {
       {(void**)&p->fd_data, 4 * Bp * sizeof(double)},
       {(void**)&p->fd_src, (size_t)std::max<int64_t>(m_max, 1) * 34 * sizeof(double)},
@@ -1380,6 +1382,20 @@ int smcx_gauss_newton_metric_blocks_masked(smcx_problem* p, int64_t N, const int
   g_last_error.clear();
   if (N > 0 && !mask) return fail(SMCX_EINVAL, "mask is NULL");
   return gn_metric_blocks(p, N, offsets, M, theta, beta, mask, F, hip_stream);
+}
+
+int smcx_metric_pool_blocks(smcx_problem* p, int64_t M, const double* F, double* F_mean,
+                            void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(SMCX_EINVAL, "problem handle is NULL");
+  if (M < 1 || M > p->m_max)
+    return fail(SMCX_EINVAL, "M = %lld outside [1, m_max = %lld]", (long long)M,
+                (long long)p->m_max);
+  if (!F || !F_mean) return fail(SMCX_EINVAL, "F or F_mean is NULL");
+  hipError_t e = smcx::launch_metric_pool(p->P, M, F, F_mean, p->part, p->part_cap,
+                                          (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "metric pool launch");
+  return SMCX_OK;
 }
 
 int smcx_metric_factor_blocks(smcx_problem* p, int64_t M, const double* F, const double* ridge,

@@ -239,6 +239,9 @@ hipError_t launch_metric(int model, int P, int64_t N, int64_t M, int64_t T, doub
 // Factor W = L^{-1} of F + diag(ridge) per particle (smcx_metric.hip); ridge is
 // a host array of P values; LDS bytes of one workgroup for k_max * P = nmax.
 // Factor of M independent P x P blocks ([M][P][P], one thread each).
+// Mean of M P x P blocks in a fixed order (part: scratch of part_cap doubles).
+hipError_t launch_metric_pool(int P, int64_t M, const double* F, double* F_mean, double* part,
+                              size_t part_cap, hipStream_t st);
 hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const double* ridge,
                                        double* W, int* flag, hipStream_t st);
 hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,

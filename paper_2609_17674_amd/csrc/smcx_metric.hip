@@ -22,6 +22,8 @@
 // 2^-10 sqrt(F~_aa F~_cc), plus FP32 accumulation over 512 steps.
 #include "smcx_internal.h"
 
+#include <algorithm>
+
 #include <math.h>
 
 namespace smcx {
@@ -418,6 +420,41 @@ __global__ __launch_bounds__(256) void factor_blocks_kernel(const double* F, dou
 
 }  // namespace
 
+// The population-level mass matrix: the mean of M P x P blocks. Stage one
+// sums contiguous row ranges, one lane per entry and four waves taking every
+// fourth row, the waves combined in order; stage two adds the range sums in
+// order and divides by M. The partition depends only on M and the scratch
+// size, so the result is reproducible bit for bit.
+constexpr int kPoolWaves = 4;
+
+__global__ __launch_bounds__(64 * kPoolWaves) void pool_partial_kernel(int PP, int64_t M,
+                                                                         int64_t rows, const double* F,
+                                                                         double* part) {
+  __shared__ double sh[kPoolWaves][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int64_t r1 = min(M, r0 + rows);
+  double s = 0.0;
+  if (lane < PP)
+    for (int64_t m = r0 + wid; m < r1; m += kPoolWaves) s += F[m * PP + lane];
+  sh[wid][lane] = s;
+  __syncthreads();
+  if (wid == 0 && lane < PP) {
+    double t = sh[0][lane];
+    for (int w = 1; w < kPoolWaves; ++w) t += sh[w][lane];
+    part[(size_t)blockIdx.x * PP + lane] = t;
+  }
+}
+
+__global__ __launch_bounds__(64) void pool_final_kernel(int PP, int G, int64_t M,
+                                                          const double* part, double* out) {
+  const int lane = threadIdx.x;
+  if (lane >= PP) return;
+  double t = 0.0;
+  for (int g = 0; g < G; ++g) t += part[(size_t)g * PP + lane];
+  out[lane] = t / (double)M;
+}
+
 hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const double* ridge,
                                        double* W, int* flag, hipStream_t st) {
   if (M == 0) return hipSuccess;
@@ -431,6 +468,28 @@ hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const 
     case 8: hipLaunchKernelGGL(factor_blocks_kernel<8>, grid, block, 0, st, F, W, M, rg, flag); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_metric_pool(int P, int64_t M, const double* F, double* F_mean, double* part,
+                              size_t part_cap, hipStream_t st) {
+  const int PP = P * P;
+  if (PP > 64 || M < 1) return hipErrorInvalidValue;
+  // about 256 rows per workgroup, at most 1024 workgroups and what the scratch
+  // holds; with no room for a range sum, one workgroup sums into F_mean itself
+  int64_t G = std::min<int64_t>((M + 255) / 256, 1024);
+  G = std::min<int64_t>(G, (int64_t)(part_cap / PP));
+  if (G < 1) {
+    G = 1;
+    part = F_mean;
+  }
+  const int64_t rows = (M + G - 1) / G;
+  G = (M + rows - 1) / rows;
+  hipLaunchKernelGGL(pool_partial_kernel, dim3((unsigned)G), dim3(64 * kPoolWaves), 0, st, PP, M,
+                     rows, F, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pool_final_kernel, dim3(1), dim3(64), 0, st, PP, (int)G, M, part, F_mean);
   return hipGetLastError();
 }
 

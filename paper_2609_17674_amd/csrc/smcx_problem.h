@@ -43,6 +43,7 @@ struct smcx_problem {
   smcx::SmcWork smc{};            // SMC-step workspace, [n_max] each
   int* flag = nullptr;
   double* part = nullptr;   // [max_nch][n_max][4]
+  size_t part_cap = 0;      // doubles in part
   double* part_g = nullptr; // [nch_grad][m_max][P]
   double* rbuf = nullptr;   // plain form residual [T]
   double* bpart = nullptr;  // plain form block partials

@@ -13,17 +13,19 @@ component uniform in the prior box) at beta = 0 and repeats until beta = 1:
    component, scored by ``delta_logl_birth_death`` and accepted or rejected
    by ``smcx_rj_apply``.
 
-With ``metric=True`` the NUTS moves use the mass matrix of Sec.
-"No-U-Turn-Sampler" (the Hessian of the negative log posterior): before each
-mutation step the Gauss-Newton metric of the tempered target is computed at
-every particle's current position (``smcx_gauss_newton_metric``), the prior's
-precision 12 / width^2 is added to its diagonal as a floor
-(``smcx_metric_factor``), and the transition runs in the whitened momentum
-(``smcx_nuts_transition_metric``) with the step ``eps_metric``, which is
-then in units of the target's own scale. The frequency-domain model's metric
-is block diagonal (one P x P block per source), and its runs keep only those
-blocks (``smcx_gauss_newton_metric_blocks``, ``smcx_metric_factor_blocks``,
-``smcx_nuts_transition_metric_blocks``).
+With ``metric=True`` the NUTS moves use a mass matrix from the Hessian of
+the negative log posterior (Sec. "No-U-Turn-Sampler"), fixed for the whole
+population during each mutation step so that the move leaves the tempered
+target invariant: before the step the Gauss-Newton blocks of every
+component are computed at the population's positions
+(``smcx_gauss_newton_metric_blocks``), averaged into one P x P block
+(``smcx_metric_pool_blocks``), floored by the prior's precision
+12 / width^2 on the diagonal and factored (``smcx_metric_factor_blocks``);
+every component of every particle then moves with that block in the
+whitened momentum (``smcx_nuts_transition_metric_blocks``) with the step
+``eps_metric``. A matrix taken at each particle's own position would adapt
+to it better but would not leave the target invariant (the reverse move
+would use the matrix at the end point).
 
 The posterior-start mode (``run_posterior_start``) starts instead from a
 population sampled on the first `split` samples of the data and follows the
@@ -187,9 +189,9 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
     if cfg.metric:
         ridge = (list(cfg.ridge) if cfg.ridge is not None
                  else (12.0 / (hi - lo) ** 2).cpu().tolist())
-        fbuf = torch.empty(1, **f64)
-        blocks = prob.model == smcx.GBLISA
-        bbuf = torch.empty((N * cfg.k_hi, P, P), **f64) if blocks else None
+        fbuf = torch.empty((N * cfg.k_hi, P, P), **f64)
+        wbuf = torch.empty_like(fbuf)
+        fmean = torch.empty((1, P, P), **f64)
     beta = 0.0
     res = SMCResult(off, th, [], [], 0.0, [], [], [])
     for it in range(cfg.max_iters):
@@ -217,23 +219,17 @@ def _run(prob, off, th, prior_lo, prior_hi, cfg, gen, weight_logl, on_iteration)
                 dirs = (torch.randint(0, 2, (N, D), generator=gen, device=dev) * 2 - 1).to(torch.int8)
                 ul = torch.rand((N, (1 << D) - 1), generator=gen, **f64)
                 ut = torch.rand((N, D), generator=gen, **f64)
-                metric = wblocks = None
-                if cfg.metric and blocks:
-                    F = smcx.gauss_newton_metric_blocks(prob, off, th, beta_arr, out=bbuf[:M],
-                                                        mask=nuts_u8)
-                    wblocks = smcx.metric_factor_blocks(prob, F, ridge, out=F)
-                elif cfg.metric:
-                    fo = smcx.metric_offsets(prob, off)
-                    size = max(int(fo[-1]), 1)
-                    if fbuf.numel() < size:
-                        fbuf = torch.empty(size + size // 4, **f64)
-                    _, F = smcx.gauss_newton_metric(prob, off, th, beta_arr, f_offsets=fo,
-                                                    out=fbuf[:size], mask=nuts_u8)
-                    metric = (fo, smcx.metric_factor(prob, off, fo, F, ridge, out=F, M=M,
-                                                     mask=nuts_u8))
+                wblocks = None
+                if cfg.metric:
+                    # one block for the whole population, fixed for this step
+                    F = smcx.gauss_newton_metric_blocks(prob, off, th, beta_arr, out=fbuf[:M])
+                    smcx.metric_pool_blocks(prob, F, M=M, out=fmean[0])
+                    smcx.metric_factor_blocks(prob, fmean, ridge, out=fmean, M=1)
+                    wblocks = wbuf[:M]
+                    wblocks.copy_(fmean.expand(M, P, P))
                 _, st, _ = smcx.nuts_transition(prob, off, beta_arr, eps, D, th, l, g, mom, dirs,
                                                 ul, ut, lo, hi, mask=nuts_u8,
-                                                metric=metric, metric_blocks=wblocks)
+                                                metric_blocks=wblocks)
                 steps += int(st.sum())
             Kc = off[1:] - off[:-1]
             tb = _prior_rows(prob, lo, hi, N, gen)

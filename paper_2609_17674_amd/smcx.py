@@ -76,6 +76,7 @@ def load_library():
                                         P, P, P, P, P, P, I32, P],
         "smcx_gauss_newton_metric_blocks": [P, I64, P, I64, P, P, P, P],
         "smcx_metric_factor_blocks": [P, I64, P, P, P, P],
+        "smcx_metric_pool_blocks": [P, I64, P, P, P],
         "smcx_nuts_transition_metric_blocks": [P, I64, P, I64, P, D, I32, P, P, P, P, P, P, P, P, P,
                                                P, P, P, P, P, I32, P],
         "smcx_resample_systematic": [P, I64, P, I64, P, P, D, I64, P, P, P, P],
@@ -613,6 +614,22 @@ def metric_factor_blocks(prob: Problem, F, ridge, out=None, M=None, stream=None)
     _check(load_library().smcx_metric_factor_blocks(prob.handle, int(M), _ptr(F),
                                                     ctypes.cast(rarr, ctypes.c_void_p), _ptr(out),
                                                     _stream(stream)))
+    return out
+
+
+def metric_pool_blocks(prob: Problem, F, M=None, out=None, stream=None) -> torch.Tensor:
+    """Mean of the first M P x P blocks of F (smcx_metric_pool_blocks): the
+    population-level mass matrix of a mutation step; returns [P, P]."""
+    F = _dev(F, torch.float64, "F")
+    if M is None:
+        M = F.shape[0]
+    if F.numel() < M * prob.P * prob.P:
+        raise ValueError(f"F holds fewer than {M} blocks of {prob.P} x {prob.P}")
+    if out is None:
+        out = torch.empty((prob.P, prob.P), dtype=torch.float64, device=F.device)
+    out = _dev(out, torch.float64, "F_mean", (prob.P, prob.P))
+    _check(load_library().smcx_metric_pool_blocks(prob.handle, int(M), _ptr(F), _ptr(out),
+                                                  _stream(stream)))
     return out
 
 

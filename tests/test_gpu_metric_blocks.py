@@ -251,3 +251,32 @@ def test_nuts_blocks_on_the_frequency_domain_model(lib, orc):
         assert np.all(np.abs(q[lo_:hi_].reshape(-1) - ref) <= tol), i
         checked += 1
     assert checked >= w.N // 2
+
+
+@pytest.mark.parametrize("P,Mb,n_max", [(3, 1, 4), (3, 70001, 20000), (4, 2049, 600), (8, 219244, 40000),
+                                        (8, 5000, 2)],
+                         ids=["P3_one", "P3_many", "P4", "P8_gb_lisa_size", "P8_small_workspace"])
+def test_metric_pool_is_the_population_mean(lib, P, Mb, n_max):
+    """smcx_metric_pool_blocks: the mean of the blocks, reproducible bit for
+    bit, for block counts that leave ragged ranges, and with a workspace that
+    holds only a few range sums."""
+    say("metric_pool", P, Mb, n_max)
+    rng = np.random.default_rng(600 + P)
+    F = rng.standard_normal((Mb, P, P)) * 10.0 ** rng.uniform(-3, 3, (1, P, P))
+    model = {3: PULSE, 4: GB, 8: GBLISA}[P]
+    if model == GBLISA:
+        w = wl.make_gblisa(N=4, n_inj=1, seed=502)
+        d = lib.template_spectrum(GBLISA, pm.to_dev(w.inj), w.T_obs, w.k0, w.B)
+        prob = lib.Problem.frequency_domain(GBLISA, d, w.k0, w.T_obs, w.S, 4, n_max, Mb)
+    else:
+        prob = lib.Problem(model, pm.to_dev(np.zeros(64)), 0.0, 1.0, 1.0, 4, n_max, Mb)
+    Fd = pm.to_dev(F)
+    a = lib.metric_pool_blocks(prob, Fd)
+    b = lib.metric_pool_blocks(prob, Fd)
+    torch.cuda.synchronize()
+    prob.device_status()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(a, b)
+    ref = F.mean(axis=0)
+    scale = np.abs(F).mean(axis=0)
+    assert np.all(np.abs(a - ref) <= 1e-13 * scale + 1e-300), np.max(np.abs(a - ref) / scale)
