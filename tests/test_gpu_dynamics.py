@@ -163,3 +163,53 @@ def test_nuts_matches_oracle_statistically(lib, orc):
     hist = np.bincount(depth, minlength=D + 1)
     rhist = np.bincount(rdepth, minlength=D + 1)
     assert np.abs(hist - rhist).sum() <= 0.2 * w.N
+
+
+def test_nuts_at_the_mutation_workload_shape(lib, orc):
+    """The C4 mutation step's data and settings (T = 4096 samples, eight
+    injected pulses, beta = 0.5, depth <= 8) with particles near the posterior
+    (each a random subset of the injected pulses, slightly perturbed) and a
+    step of 1.5e-4, so that trees grow up to the maximum depth instead of
+    diverging at the first leaves as prior draws do: the GPU transition
+    against the oracle's on the same draws, statistically as above."""
+    w = wl.make_config("pulse_mutate", N=4)
+    d = pm.data_of(w)
+    rng = np.random.default_rng(5)
+    N, D, eps = 160, 8, 1.5e-4
+    K = rng.integers(1, len(w.inj) + 1, N)
+    rows = [w.inj[rng.choice(len(w.inj), k, replace=False)]
+            * (1 + rng.standard_normal((k, 3)) * np.array([2e-3, 2e-4, 2e-3])) for k in K]
+    theta = np.concatenate(rows)
+    offsets = wl.counts_to_offsets(K)
+    beta = np.full(N, 0.5)
+    say("nuts_c4_shape", N, w.T, len(theta))
+    prob = lib.Problem(PULSE, pm.to_dev(d), w.t_start, w.dt, w.sigma, int(K.max()), N, len(theta))
+    lib.nuts_reserve(prob, D)
+    mom, dirs, ul, ut = wl.nuts_draws(N, len(theta), 3, D, 13)
+    dev = {k: pm.to_dev(v) for k, v in dict(mom=mom, dirs=dirs, ul=ul, ut=ut).items()}
+    off, th, be = pm.to_dev(offsets), pm.to_dev(theta), pm.to_dev(beta)
+    lo, hi = pm.to_dev(wl.PULSE_PRIOR[:, 0].copy()), pm.to_dev(wl.PULSE_PRIOR[:, 1].copy())
+    l0, g0 = lib.logl_grad_batch(prob, off, th, be)
+    q, l, g = th.clone(), l0.clone(), g0.clone()
+    depth, steps, status = lib.nuts_transition(prob, off, be, eps, D, q, l, g, dev["mom"], dev["dirs"],
+                                               dev["ul"], dev["ut"], lo, hi)
+    torch.cuda.synchronize()
+    prob.device_status()
+    ref_l0, ref_g0 = orc.logl_grad(PULSE, d, w.t_start, w.dt, w.sigma, offsets, theta, beta)
+    rq, rl, rg, rdepth, rsteps, rstatus = orc.nuts_transition(
+        PULSE, d, w.t_start, w.dt, w.sigma, offsets, beta, eps, D, theta, ref_l0, ref_g0, mom, dirs,
+        ul, ut, wl.PULSE_PRIOR[:, 0], wl.PULSE_PRIOR[:, 1])
+    depth, steps, status = depth.cpu().numpy(), steps.cpu().numpy(), status.cpu().numpy()
+    same = (depth == rdepth) & (status == rstatus) & (steps == rsteps)
+    print(f"[nuts] depth histogram GPU {np.bincount(depth, minlength=D + 1).tolist()}, oracle "
+          f"{np.bincount(rdepth, minlength=D + 1).tolist()}; same tree {same.mean():.3f}", flush=True)
+    assert np.mean(rdepth >= 3) >= 0.3, np.bincount(rdepth, minlength=D + 1)
+    assert same.mean() >= 0.85, same.mean()
+    assert np.mean(depth[same] >= 3) >= 0.3
+    qn = q.cpu().numpy()
+    close = [np.allclose(qn[offsets[i]:offsets[i + 1]], rq[offsets[i]:offsets[i + 1]],
+                         rtol=1e-5, atol=1e-8) for i in np.nonzero(same)[0]]
+    assert np.mean(close) >= 0.9, np.mean(close)
+    hist = np.bincount(depth, minlength=D + 1)
+    rhist = np.bincount(rdepth, minlength=D + 1)
+    assert np.abs(hist - rhist).sum() <= 0.2 * N

@@ -413,18 +413,24 @@ def test_autograd_function(lib, orc):
 
 
 # ---------------------------------------------------------------- full-size workloads
-def _sample(n, k, seed):
-    return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False))
+def _sample(n, k, seed, K=None):
+    """A seeded sample of k particles; with K given it always holds the first
+    particle with the largest K (the workload's k_max)."""
+    idx = np.random.default_rng(seed).choice(n, size=min(k, n), replace=False)
+    if K is not None:
+        idx[0] = int(np.argmax(K))
+    return np.unique(idx)
 
 
-@pytest.mark.parametrize("cfg,n_check", [("pulse_batch", 256), ("gb_grad", 24)])
+@pytest.mark.parametrize("cfg,n_check", [("pulse_batch", 256), ("gb_grad", 256)])
 def test_full_size_grad_sampled(lib, orc, cfg, n_check):
     w = wl.make_config(cfg)
     say("full_size_grad", cfg, "N", w.N, "T", w.T, "M", w.M)
     s = Setup(lib, w)
     logl, grad = run_grad(lib, s)
     assert np.all(np.isfinite(logl)) and np.all(np.isfinite(grad))
-    idx = _sample(w.N, n_check, 9)
+    idx = _sample(w.N, n_check, 9, w.K)
+    assert w.K[idx].max() == w.k_max and len(idx) >= n_check - 1
     sub = wl.subsample(w, idx)
     ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, sub.offsets, sub.theta,
                                  sub.beta)
@@ -441,7 +447,8 @@ def test_full_size_birth_death_sampled(lib, orc):
     db, dd = lib.delta_logl_birth_death(s.prob, s.off, s.th, s.beta, pm.to_dev(tb), pm.to_dev(di))
     torch.cuda.synchronize()
     s.prob.device_status()
-    idx = _sample(w.N, 128, 10)
+    idx = _sample(w.N, 256, 10, w.K)
+    assert w.K[idx].max() == w.k_max
     sub = wl.subsample(w, idx)
     rb, rd = orc.delta_logl_birth_death(w.model, s.d, w.t_start, w.dt, w.sigma, sub.offsets,
                                         sub.theta, sub.beta, tb[idx], di[idx])
@@ -462,7 +469,8 @@ def test_full_size_reweight_sampled(lib, orc):
     torch.cuda.synchronize()
     s.prob.device_status()
     le = le.cpu().numpy()
-    idx = _sample(w.N, 24, 11)
+    idx = _sample(w.N, 256, 11, w.K)
+    assert w.K[idx].max() == w.k_max
     sub = wl.subsample(w, idx)
     rle, _, _, _ = orc.reweight_extend(w.model, s.d, w.t_start, w.dt, w.sigma, T1, T2, sub.offsets,
                                        sub.theta, 1.0)

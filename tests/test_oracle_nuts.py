@@ -40,7 +40,7 @@ def test_depth_one_is_a_leapfrog_step_with_metropolis_acceptance(orc):
         if not H1 - H0 <= 1000:
             assert status[i] == 2 and np.array_equal(q[a:b], w.theta[a:b])
             continue
-        accept = ut[i, 0] < np.exp(H0 - H1)
+        accept = ut[i, 0] < np.exp(min(H0 - H1, 0.0))  # min(1, e^(H0-H1)) without overflow
         ref = q1 if accept else w.theta[a:b]
         assert np.allclose(q[a:b], ref, rtol=0, atol=1e-14)
         assert depth[i] == 1 and status[i] in (1, 3)

@@ -148,7 +148,7 @@ def test_split_nuts_depth_one_is_metropolis_on_the_split_energy(orc):
         if not H1 - H0 <= 1000:
             assert status[i] == 2 and np.array_equal(q[a:b], w.theta[a:b])
             continue
-        accept = ut[i, 0] < np.exp(H0 - H1)
+        accept = ut[i, 0] < np.exp(min(H0 - H1, 0.0))  # min(1, e^(H0-H1)) without overflow
         ref = qi if accept else w.theta[a:b]
         assert np.allclose(q[a:b], ref, rtol=0, atol=1e-14)
         assert np.array_equal(l[i], li[0]) if accept else l[i] == l0[i]
