@@ -62,10 +62,11 @@ CLOCK_HZ = 2.4e9
 # operations are those the method needs per component-sample:
 #   pulse forward: add, fmac, mul, exp2, fmac                          5
 #   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
-#   sinusoid forward: int add, cvt, fmac (chirp), mul, sin, fmac       6
-#   sinusoid adjoint: int add, cvt, fmac, mul, sin, cos,
-#                     fmac, mul, add, fmac, fmac                       11
-SLOTS = {(0, "grad"): 12.0, (1, "grad"): 17.0, (0, "fwd"): 5.0, (1, "fwd"): 6.0}
+#   sinusoid forward: int add, cvt, mul, sin, fmac                     5
+#   sinusoid adjoint: int add, cvt, mul, sin, cos, fmac, fmac, add, add 9
+# (sinusoids with the linear tile phase, which the workloads' chirps take;
+# the adjoint's three moment sums are running sums)
+SLOTS = {(0, "grad"): 12.0, (1, "grad"): 14.0, (0, "fwd"): 5.0, (1, "fwd"): 5.0}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and

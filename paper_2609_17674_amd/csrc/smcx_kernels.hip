@@ -197,6 +197,16 @@ __device__ __forceinline__ GbC gb_make(const double* th, double t_start, double 
   return r;
 }
 
+// Over a lane's S samples of a tile (j = 0 .. S-1) the chirp P2 j^2 departs
+// from its chord (S-1) P2 j, moved down by P2 (S-1)^2 / 8, by at most
+// |P2| (S-1)^2 / 8. Where that is at most 32 units of 2^-32 cycles (7e-8 rad)
+// for every component of a particle, the particle's tiles take the phase as
+// linear in j (gb_tile folds the chord into the step), which saves the chirp
+// term per sample.
+__device__ __forceinline__ bool gb_chord_ok(const GbC& c, int S) {
+  return fabs((double)c.c2) * (double)(S - 1) * (double)(S - 1) <= 256.0;
+}
+
 // Low 32 bits of y + 1.5*2^20: for |y| < 2^19 this is y mod 1 cycle as a
 // fixed-point number in units of 2^-32 cycles (the sum is rounded to that unit).
 __device__ __forceinline__ unsigned int fixed_cycles(double y) {
@@ -214,20 +224,26 @@ struct GbTile {
   unsigned int D;   // P1 mod 1, fixed point
   float c2;         // P2 in fixed-point units
 };
+template <bool LIN, int S>
 __device__ __forceinline__ GbTile gb_tile(const GbC& c, double u) {
-  const double P0 = fma(fma(c.a2, u, c.a1), u, c.a0);
-  const double P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
+  double P0 = fma(fma(c.a2, u, c.a1), u, c.a0);
+  double P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
+  if (LIN) {  // P2 j^2 by its chord (S-1) P2 j, centred: see gb_make
+    P0 = fma(-512.0 * (double)((S - 1) * (S - 1)), c.a2, P0);
+    P1 = fma(4096.0 * (double)(S - 1), c.a2, P1);
+  }
   GbTile t;
   t.F0 = fixed_cycles(P0 - rint(P0));
   t.D = fixed_cycles(P1 - rint(P1));
   t.c2 = c.c2;
   return t;
 }
-// Phase of sample j in revolutions (about [-0.5, 0.5)), F = F0 + j D mod 2^32.
-template <int J>
+// Phase of sample j in revolutions (about [-0.5, 0.5)), F = F0 + j D mod 2^32,
+// plus the chirp correction unless the tile's phase is linear.
+template <int J, bool LIN>
 __device__ __forceinline__ float gb_rev(const GbTile& t, unsigned int F) {
   float y = (float)(int)F;
-  if (J > 0) y = __builtin_fmaf((float)(J * J), t.c2, y);
+  if (!LIN && J > 0) y = __builtin_fmaf((float)(J * J), t.c2, y);
   return y * 0x1p-32f;
 }
 
@@ -292,52 +308,66 @@ __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const f
   }
 }
 
-template <int S, int J = 0>
+template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_fwd_j(const GbTile& t, unsigned int F, float A, float (&r)[S]) {
   if constexpr (J + 1 < S) {
     const unsigned int F1 = F + t.D;
-    const float s0 = __builtin_amdgcn_sinf(gb_rev<J>(t, F));
-    const float s1 = __builtin_amdgcn_sinf(gb_rev<J + 1>(t, F1));
+    const float s0 = __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
+    const float s1 = __builtin_amdgcn_sinf(gb_rev<J + 1, LIN>(t, F1));
     r[J] = __builtin_fmaf(-A, s0, r[J]);
     r[J + 1] = __builtin_fmaf(-A, s1, r[J + 1]);
-    gb_fwd_j<S, J + 2>(t, F1 + t.D, A, r);
+    gb_fwd_j<S, LIN, J + 2>(t, F1 + t.D, A, r);
   } else if constexpr (J < S) {
-    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(gb_rev<J>(t, F)), r[J]);
+    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F)), r[J]);
   }
 }
 
-template <int S, int J = 0>
+// Adjoint sums of one component over a lane's S samples: as = sum r sin, and
+// the running sums A_j = sum_{i<=j} r_i cos_i, B_j = sum_{i<=j} A_i,
+// C_j = sum_{i<=j} B_i, from which gb_moments takes sum x, sum j x, sum j^2 x
+// (x = r cos) with one FMA and two adds per sample instead of a multiply, an
+// add and two FMAs.
+template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_adj_j(const GbTile& t, unsigned int F, const float (&r)[S],
-                                         float& as, float& c0, float& c1, float& c2) {
+                                         float& as, float& A, float& B, float& C) {
   if constexpr (J < S) {
-    const float ph = gb_rev<J>(t, F);
+    const float ph = gb_rev<J, LIN>(t, F);
     const float s = __builtin_amdgcn_sinf(ph);
     const float c = __builtin_amdgcn_cosf(ph);
     as = __builtin_fmaf(r[J], s, as);
-    const float rc = r[J] * c;
-    c0 += rc;
-    c1 = __builtin_fmaf(rc, (float)J, c1);
-    c2 = __builtin_fmaf(rc, (float)(J * J), c2);
-    gb_adj_j<S, J + 1>(t, F + t.D, r, as, c0, c1, c2);
+    A = __builtin_fmaf(r[J], c, A);
+    B += A;
+    C += B;
+    gb_adj_j<S, LIN, J + 1>(t, F + t.D, r, as, A, B, C);
   }
 }
 
-template <int S, int J = 0>
+// sum x_j, sum j x_j, sum j^2 x_j over j < S from the final running sums:
+// B = sum (S - j) x_j and C = sum (S - j)(S - j + 1)/2 x_j.
+template <int S>
+__device__ __forceinline__ void gb_moments(float A, float B, float C, float& c0, float& c1,
+                                           float& c2) {
+  c0 = A;
+  c1 = __builtin_fmaf((float)S, A, -B);
+  c2 = __builtin_fmaf((float)(2 * S + 1), c1, __builtin_fmaf(-(float)(S * S + S), A, 2.f * C));
+}
+
+template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_sub2_j(const GbTile& t, unsigned int F, float A, float (&r1)[S],
                                           float (&r2)[S]) {
   if constexpr (J < S) {
-    const float s = __builtin_amdgcn_sinf(gb_rev<J>(t, F));
+    const float s = __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
     r1[J] = __builtin_fmaf(-A, s, r1[J]);
     r2[J] = __builtin_fmaf(-A, s, r2[J]);
-    gb_sub2_j<S, J + 1>(t, F + t.D, A, r1, r2);
+    gb_sub2_j<S, LIN, J + 1>(t, F + t.D, A, r1, r2);
   }
 }
 
-template <int S, int J = 0>
+template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_val_j(const GbTile& t, unsigned int F, float A, float (&h)[S]) {
   if constexpr (J < S) {
-    h[J] = A * __builtin_amdgcn_sinf(gb_rev<J>(t, F));
-    gb_val_j<S, J + 1>(t, F + t.D, A, h);
+    h[J] = A * __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
+    gb_val_j<S, LIN, J + 1>(t, F + t.D, A, h);
   }
 }
 
@@ -351,7 +381,9 @@ struct Model<SMCX_PULSE> {
   __device__ static C make(const double* th, const PopArgs& a, int /*S*/) {
     return pulse_make(th, a.t_start, a.dt);
   }
-  template <int S>
+  // pulses have one tile path (LIN is ignored)
+  __device__ static bool chord_ok(const C&, int) { return true; }
+  template <int S, bool LIN = true>
   __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
     const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
@@ -361,7 +393,7 @@ struct Model<SMCX_PULSE> {
       pulse_fwd_j<S>(c, sf0 - c.nf, r, groups);
     }
   }
-  template <int S>
+  template <int S, bool LIN = true>
   __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
                                  const float (&r)[S]) {
     const float sf0 = (float)(int)(tile + lane);
@@ -382,7 +414,7 @@ struct Model<SMCX_PULSE> {
     }
   }
   // Template values of one component on the tile (for birth/death).
-  template <int S>
+  template <int S, bool LIN = true>
   __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
     const float base = (float)(int)(tile + lane) - c.nf;
 #pragma unroll
@@ -392,7 +424,7 @@ struct Model<SMCX_PULSE> {
       h[j] = c.A * __builtin_amdgcn_exp2f(-(z * z));
     }
   }
-  template <int S>
+  template <int S, bool LIN = true>
   __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
     const float base = (float)(int)(tile + lane) - c.nf;
 #pragma unroll
@@ -423,25 +455,29 @@ struct Model<SMCX_GBSINE> {
   __device__ static C make(const double* th, const PopArgs& a, int S) {
     return gb_make(th, a.t_start, a.dt, a.s_lo, a.s_hi, S, a.flag);
   }
-  template <int S>
+  // LIN: every component of the particle takes the linear tile phase (gb_chord_ok)
+  __device__ static bool chord_ok(const C& c, int S) { return gb_chord_ok(c, S); }
+  template <int S, bool LIN>
   __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
     const double u = (double)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
-      const GbTile t = gb_tile(c, u);
-      gb_fwd_j<S>(t, t.F0, c.A, r);
+      const GbTile t = gb_tile<LIN, S>(c, u);
+      gb_fwd_j<S, LIN>(t, t.F0, c.A, r);
     }
   }
-  template <int S>
+  template <int S, bool LIN>
   __device__ static void adjoint(const C* cst, double* acc, int K, int64_t tile, int lane,
                                  const float (&r)[S]) {
     const double u = (double)(tile + lane);
     const float uf = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
-      const GbTile t = gb_tile(c, u);
-      float as = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-      gb_adj_j<S>(t, t.F0, r, as, c0, c1, c2);
+      const GbTile t = gb_tile<LIN, S>(c, u);
+      float as = 0.f, A = 0.f, B = 0.f, Cs = 0.f;
+      gb_adj_j<S, LIN>(t, t.F0, r, as, A, B, Cs);
+      float c0, c1, c2;
+      gb_moments<S>(A, B, Cs, c0, c1, c2);
       // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
       const float b1 = __builtin_fmaf(uf, c0, 64.f * c1);
       const float b2 = __builtin_fmaf(uf * uf, c0, __builtin_fmaf(128.f * uf, c1, 4096.f * c2));
@@ -457,15 +493,15 @@ struct Model<SMCX_GBSINE> {
       }
     }
   }
-  template <int S>
+  template <int S, bool LIN>
   __device__ static void values(const C& c, int64_t tile, int lane, float (&h)[S]) {
-    const GbTile t = gb_tile(c, (double)(tile + lane));
-    gb_val_j<S>(t, t.F0, c.A, h);
+    const GbTile t = gb_tile<LIN, S>(c, (double)(tile + lane));
+    gb_val_j<S, LIN>(t, t.F0, c.A, h);
   }
-  template <int S>
+  template <int S, bool LIN>
   __device__ static void sub2(const C& c, int64_t tile, int lane, float (&r1)[S], float (&r2)[S]) {
-    const GbTile t = gb_tile(c, (double)(tile + lane));
-    gb_sub2_j<S>(t, t.F0, c.A, r1, r2);
+    const GbTile t = gb_tile<LIN, S>(c, (double)(tile + lane));
+    gb_sub2_j<S, LIN>(t, t.F0, c.A, r1, r2);
   }
   // sums: S_sin = sum r sin, C0 = sum r cos, C1 = sum r cos s, C2 = sum r cos s^2.
   __device__ static void scale(const double* th, const double* sums, double bs, const PopArgs& a,
@@ -761,47 +797,21 @@ constexpr int pop_waves_per_simd() {
   return (MODEL == SMCX_GBSINE && GRAD) ? 4 : 5;
 }
 
-template <int MODEL, int S, bool GRAD>
-__global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void pop_kernel(PopArgs a) {
+// The tiles of one work item: forward (and adjoint) over samples [cs, ce);
+// returns the tempered (ss) and, with a split, untempered (ss_lo) sums of r^2
+// of the lane. LIN selects the sinusoids' linear tile phase.
+template <int MODEL, int S, bool GRAD, bool LIN>
+__device__ __forceinline__ void pop_tiles(const PopArgs& a, const typename Model<MODEL>::C* cst,
+                                          double* acc, int K, int lane, int64_t cs, int64_t ce,
+                                          bool split, double b, double& ss, double& ss_lo) {
   using M = Model<MODEL>;
-  using C = typename M::C;
-  constexpr int P = M::P;
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wpb = blockDim.x >> 6;
-  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
-  Item it;
-  if (!decode_item(a, item, lane, P, false, it)) return;
-  // one wave per item: make the item's fields scalar
-  const int c = __builtin_amdgcn_readfirstlane(it.c);
-  const int i = __builtin_amdgcn_readfirstlane(it.i);
-  const int64_t m0 = uniform_i64(it.m0);
-  const int K = __builtin_amdgcn_readfirstlane(it.K);
-  if (a.active && !a.active[i]) return;
-
-  unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
-  C* cst = reinterpret_cast<C*>(base);
-  double* acc = reinterpret_cast<double*>(base + (size_t)(a.k_max + 1) * sizeof(C));
-  for (int k = lane; k < K; k += 64) {
-    cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
-    if (GRAD)
-      for (int p = 0; p < P; ++p) acc[k * P + p] = 0.0;
-  }
-  wave_sync();
-
-  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
-  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
-  const bool split = a.split > a.s_lo;  // posterior-start bridge target
-  const double b = a.beta ? a.beta[i] : 1.0;
-  double ss = 0.0, ss_lo = 0.0;  // tempered and (with a split) untempered sums of r^2
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float r[S];
     // d32 is zero-padded by a full 4096-sample tile past T: no load guard
     const float* dp = a.d32 + tile + lane;
 #pragma unroll
     for (int j = 0; j < S; ++j) r[j] = dp[64 * j];
-    M::template forward<S>(cst, K, tile, lane, r);
+    M::template forward<S, LIN>(cst, K, tile, lane, r);
     if (tile + 64 * S > ce) {  // ragged tile: samples past the chunk contribute nothing
       const int nv = (int)(ce - tile) - lane;  // lane's samples j with 64 j < nv are inside
 #pragma unroll
@@ -826,7 +836,54 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
         if constexpr (GRAD) r[j] = lo ? r[j] : r[j] * bf;
       }
     }
-    if constexpr (GRAD) M::template adjoint<S>(cst, acc, K, tile, lane, r);
+    if constexpr (GRAD) M::template adjoint<S, LIN>(cst, acc, K, tile, lane, r);
+  }
+}
+
+template <int MODEL, int S, bool GRAD>
+__global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void pop_kernel(PopArgs a) {
+  using M = Model<MODEL>;
+  using C = typename M::C;
+  constexpr int P = M::P;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
+  Item it;
+  if (!decode_item(a, item, lane, P, false, it)) return;
+  // one wave per item: make the item's fields scalar
+  const int c = __builtin_amdgcn_readfirstlane(it.c);
+  const int i = __builtin_amdgcn_readfirstlane(it.i);
+  const int64_t m0 = uniform_i64(it.m0);
+  const int K = __builtin_amdgcn_readfirstlane(it.K);
+  if (a.active && !a.active[i]) return;
+
+  unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
+  C* cst = reinterpret_cast<C*>(base);
+  double* acc = reinterpret_cast<double*>(base + (size_t)(a.k_max + 1) * sizeof(C));
+  bool off_chord = false;  // a component whose chirp needs the exact tile phase
+  for (int k = lane; k < K; k += 64) {
+    cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
+    off_chord |= !M::chord_ok(cst[k], S);
+    if (GRAD)
+      for (int p = 0; p < P; ++p) acc[k * P + p] = 0.0;
+  }
+  const bool lin = __builtin_amdgcn_ballot_w64(off_chord) == 0;
+  wave_sync();
+
+  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
+  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
+  const bool split = a.split > a.s_lo;  // posterior-start bridge target
+  const double b = a.beta ? a.beta[i] : 1.0;
+  double ss = 0.0, ss_lo = 0.0;  // tempered and (with a split) untempered sums of r^2
+  if constexpr (MODEL != SMCX_GBSINE) {
+    pop_tiles<MODEL, S, GRAD, true>(a, cst, acc, K, lane, cs, ce, split, b, ss, ss_lo);
+  } else {
+    if (lin)
+      pop_tiles<MODEL, S, GRAD, true>(a, cst, acc, K, lane, cs, ce, split, b, ss, ss_lo);
+    else
+      pop_tiles<MODEL, S, GRAD, false>(a, cst, acc, K, lane, cs, ce, split, b, ss, ss_lo);
   }
   ss = lane63_d(wave_sum_d(ss));
   if (split) ss = lane63_d(wave_sum_d(ss_lo)) + b * ss;
@@ -903,40 +960,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(PopArgs a) {
 // One pass per (particle, chunk): r (all components) and r_-j (all but j)
 // in index order, the templates of the death candidate j and of the birth
 // candidate, and four FP64 inner products per lane.
-template <int MODEL, int S>
-__global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a) {
+// The tiles of one birth/death work item: the four inner products of the lane.
+template <int MODEL, int S, bool LIN>
+__device__ __forceinline__ void delta_tiles(const PopArgs& a, const typename Model<MODEL>::C* cst,
+                                            int K, int j_death, bool birth, int lane, int64_t cs,
+                                            int64_t ce, bool split, double bw, double& xb,
+                                            double& yb, double& xd, double& yd) {
   using M = Model<MODEL>;
   using C = typename M::C;
-  constexpr int P = M::P;
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wpb = blockDim.x >> 6;
-  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
-  Item it;
-  if (!decode_item(a, item, lane, P, true, it)) return;
-  const int c = it.c;
-  const int i = it.i;
-  const int64_t m0 = it.m0;
-  const int K = it.K;
-  if (a.active && !a.active[i]) return;
-  const int j_death = a.death_idx ? a.death_idx[i] : -1;
-  const bool birth = a.theta_birth != nullptr;
-  if (!birth && j_death < 0) {  // nothing to evaluate: no birth, no death
-    if (c == 0 && lane == 0) a.dlogl_death[i] = 0.0;
-    return;
-  }
-
-  C* cst = reinterpret_cast<C*>(lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, false));
-  for (int k = lane; k < K; k += 64) cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
-  if (birth && lane == 0) cst[K] = M::make(a.theta_birth + (int64_t)i * P, a, S);
-  wave_sync();
-
-  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
-  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
-  const bool split = a.split > a.s_lo;  // posterior-start bridge target
-  const double bw = a.beta ? a.beta[i] : 1.0;
-  double xb = 0.0, yb = 0.0, xd = 0.0, yd = 0.0;
   for (int64_t tile = cs; tile < ce; tile += 64 * S) {
     float rf[S], rn[S], hj[S];
     const float* dp = a.d32 + tile + lane;
@@ -949,19 +980,19 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
     for (int k = 0; k < K; ++k) {
       const C cc = cst[k];
       if (k == j_death) {
-        M::template values<S>(cc, tile, lane, hj);
+        M::template values<S, LIN>(cc, tile, lane, hj);
         // r (all components) still subtracts h_j, with the same fma as below
         float dummy[S];
 #pragma unroll
         for (int jj = 0; jj < S; ++jj) dummy[jj] = 0.f;
-        M::template sub2<S>(cc, tile, lane, rf, dummy);
+        M::template sub2<S, LIN>(cc, tile, lane, rf, dummy);
       } else {
-        M::template sub2<S>(cc, tile, lane, rf, rn);
+        M::template sub2<S, LIN>(cc, tile, lane, rf, rn);
       }
     }
     float hn[S];
     if (birth) {
-      M::template values<S>(cst[K], tile, lane, hn);
+      M::template values<S, LIN>(cst[K], tile, lane, hn);
     } else {
 #pragma unroll
       for (int jj = 0; jj < S; ++jj) hn[jj] = 0.f;
@@ -996,6 +1027,47 @@ __global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a)
       }
     }
   }
+}
+
+template <int MODEL, int S>
+__global__ __launch_bounds__(256, (S <= 8 ? 6 : 4)) void delta_kernel(PopArgs a) {
+  using M = Model<MODEL>;
+  using C = typename M::C;
+  constexpr int P = M::P;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
+  Item it;
+  if (!decode_item(a, item, lane, P, true, it)) return;
+  const int c = it.c;
+  const int i = it.i;
+  const int64_t m0 = it.m0;
+  const int K = it.K;
+  if (a.active && !a.active[i]) return;
+  const int j_death = a.death_idx ? a.death_idx[i] : -1;
+  const bool birth = a.theta_birth != nullptr;
+  if (!birth && j_death < 0) {  // nothing to evaluate: no birth, no death
+    if (c == 0 && lane == 0) a.dlogl_death[i] = 0.0;
+    return;
+  }
+
+  C* cst = reinterpret_cast<C*>(lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, false));
+  for (int k = lane; k < K; k += 64) cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
+  if (birth && lane == 0) cst[K] = M::make(a.theta_birth + (int64_t)i * P, a, S);
+  wave_sync();
+
+  const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;
+  const int64_t ce = min(cs + a.chunk_len, a.s_hi);
+  const bool split = a.split > a.s_lo;  // posterior-start bridge target
+  const double bw = a.beta ? a.beta[i] : 1.0;
+  double xb = 0.0, yb = 0.0, xd = 0.0, yd = 0.0;
+  // sinusoids take the exact tile phase here, whatever the components: the
+  // templates of a birth and of the matching death must not depend on which
+  // other components (or candidates) the two calls see
+  delta_tiles<MODEL, S, MODEL != SMCX_GBSINE>(a, cst, K, j_death, birth, lane, cs, ce, split, bw,
+                                              xb, yb, xd, yd);
   xb = lane63_d(wave_sum_d(xb));
   yb = lane63_d(wave_sum_d(yb));
   xd = lane63_d(wave_sum_d(xd));

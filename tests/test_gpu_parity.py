@@ -83,6 +83,34 @@ def test_gb_nonzero_start_time(lib, orc):
     pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
 
 
+@pytest.mark.parametrize("S", [8, 16, 32, 64])
+def test_gb_chirps_beyond_the_linear_tile_phase(lib, orc, S):
+    """Within a tile the sinusoid's phase is taken as linear in the lane's
+    sample index where the chirp allows it for every component of a particle;
+    particles holding a fast chirp (fdot up to 5e-14 Hz/s, far above the
+    workload's prior) take the exact quadratic phase. Both kinds, side by side
+    in one batch, against the oracle, for every tile size."""
+    w = wl.make_config("gb_grad", N=80, T=9000, k_hi=8)
+    rng = np.random.default_rng(40 + S)
+    th = w.theta.reshape(-1, w.P)
+    fast = np.nonzero(rng.random(w.N) < 0.5)[0]
+    for i in fast:
+        if w.K[i] > 0:
+            th[w.offsets[i] + rng.integers(w.K[i]), 2] = 10.0 ** rng.uniform(-15, np.log10(5e-14))
+    w.theta = th
+    say("gb_fast_chirps", S, "particles with a fast chirp", len(fast))
+    s = Setup(lib, w)
+    for kind in (lib.KIND_GRAD, lib.KIND_LOGL):
+        s.prob.set_tiling(kind, S, 4096, 1)
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+    l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    pm.assert_logl(l2.cpu().numpy(), ref_l)
+
+
 def test_sigma_and_no_beta(lib, orc):
     w = wl.make_config("pulse_small", N=40, T=700, sigma=2.5)
     w.noise *= 2.5
