@@ -63,10 +63,13 @@ CLOCK_HZ = 2.4e9
 #   pulse forward: add, fmac, mul, exp2, fmac                          5
 #   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
 #   sinusoid forward: int add, cvt, mul, sin, fmac                     5
-#   sinusoid adjoint: int add, cvt, mul, sin, cos, fmac, fmac, add, add 9
+#   sinusoid adjoint: the phasor turned by a complex multiply (mul,
+#                     fma, mul, fma) on 7 of 8 samples, taken from sin
+#                     and cos (int add, cvt, mul, sin, cos) on the 8th;
+#                     then fmac, fmac, add, add                 (7 x 6 + 9) / 8
 # (sinusoids with the linear tile phase, which the workloads' chirps take;
 # the adjoint's three moment sums are running sums)
-SLOTS = {(0, "grad"): 12.0, (1, "grad"): 14.0, (0, "fwd"): 5.0, (1, "fwd"): 5.0}
+SLOTS = {(0, "grad"): 12.0, (1, "grad"): 5.0 + 51.0 / 8.0, (0, "fwd"): 5.0, (1, "fwd"): 5.0}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and

@@ -342,6 +342,39 @@ __device__ __forceinline__ void gb_adj_j(const GbTile& t, unsigned int F, const 
   }
 }
 
+// The adjoint sums of gb_adj_j with the linear tile phase, where the phasor
+// e^{i phase} of sample j + 1 is that of sample j turned by w = e^{i 2 pi D}:
+// a complex multiply (two multiplies, two FMAs) instead of a sin and a cos.
+// Every kGbAnchor-th sample takes the phasor from the hardware sin and cos
+// again, so that the rounding of w and of the products (about 2e-7 rad per
+// step) builds up over at most kGbAnchor - 1 steps. The adjoint only feeds
+// the gradient, whose tolerance is a hundred times wider than this.
+constexpr int kGbAnchor = 8;
+
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, unsigned int F, float ws, float wc,
+                                             const float (&r)[S], float zr, float zi, float& as,
+                                             float& A, float& B, float& C) {
+  if constexpr (J < S) {
+    if constexpr (J % kGbAnchor == 0) {
+      const float ph = gb_rev<J, true>(t, F);
+      zi = __builtin_amdgcn_sinf(ph);
+      zr = __builtin_amdgcn_cosf(ph);
+    } else {
+      const float nr = __builtin_fmaf(-zi, ws, zr * wc);
+      const float ni = __builtin_fmaf(zr, ws, zi * wc);
+      zr = nr;
+      zi = ni;
+    }
+    as = __builtin_fmaf(r[J], zi, as);
+    A = __builtin_fmaf(r[J], zr, A);
+    B += A;
+    C += B;
+    const unsigned int Fn = (J + 1) % kGbAnchor == 0 ? F + (unsigned int)kGbAnchor * t.D : F;
+    gb_adj_rot_j<S, J + 1>(t, Fn, ws, wc, r, zr, zi, as, A, B, C);
+  }
+}
+
 // sum x_j, sum j x_j, sum j^2 x_j over j < S from the final running sums:
 // B = sum (S - j) x_j and C = sum (S - j)(S - j + 1)/2 x_j.
 template <int S>
@@ -475,7 +508,13 @@ struct Model<SMCX_GBSINE> {
       const C c = cst[k];
       const GbTile t = gb_tile<LIN, S>(c, u);
       float as = 0.f, A = 0.f, B = 0.f, Cs = 0.f;
-      gb_adj_j<S, LIN>(t, t.F0, r, as, A, B, Cs);
+      if constexpr (LIN) {
+        const float wd = (float)(int)t.D * 0x1p-32f;  // step in revolutions
+        gb_adj_rot_j<S>(t, t.F0, __builtin_amdgcn_sinf(wd), __builtin_amdgcn_cosf(wd), r, 0.f,
+                        0.f, as, A, B, Cs);
+      } else {
+        gb_adj_j<S, LIN>(t, t.F0, r, as, A, B, Cs);
+      }
       float c0, c1, c2;
       gb_moments<S>(A, B, Cs, c0, c1, c2);
       // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
