@@ -250,18 +250,17 @@ __device__ __forceinline__ float gb_rev(const GbTile& t, unsigned int F) {
 // ---------------------------------------------------------------- tile bodies
 // Pulse forward over the tile's block groups that meet the support; within a
 // group the blocks are independent, so each exp has other work behind it.
-template <int S, int J>
-__device__ __forceinline__ void pulse_fwd_one(const PulseC& c, float base, float (&r)[S]) {
-  const float d = base + (float)(64 * J);
-  const float z = __builtin_fmaf(d, c.a, -c.fa);
-  r[J] = __builtin_fmaf(-c.A, __builtin_amdgcn_exp2f(-(z * z)), r[J]);
-}
-
+// Within a group of blocks the exp argument's base z = a x - (fraction) a
+// steps by 64 a (exact: a power-of-two multiple of a) from block to block:
+// the group's first block forms z from the sample offset, the next ones add
+// the step (one add instead of an add and an FMA). The rounding of z then
+// grows by at most one unit of |z| per block.
 template <int S, int J, int G>
-__device__ __forceinline__ void pulse_fwd_group(const PulseC& c, float base, float (&r)[S]) {
+__device__ __forceinline__ void pulse_fwd_group(const PulseC& c, float a64, float z,
+                                                float (&r)[S]) {
   if constexpr (G > 0 && J < S) {
-    pulse_fwd_one<S, J>(c, base, r);
-    pulse_fwd_group<S, J + 1, G - 1>(c, base, r);
+    r[J] = __builtin_fmaf(-c.A, __builtin_amdgcn_exp2f(-(z * z)), r[J]);
+    pulse_fwd_group<S, J + 1, G - 1>(c, a64, z + a64, r);
   }
 }
 
@@ -269,31 +268,26 @@ template <int S, int J = 0>
 __device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S],
                                             GroupMask<S> groups) {
   if constexpr (J < S) {
-    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u))
-      pulse_fwd_group<S, J, kPulseGroup>(c, base, r);
+    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u)) {
+      const float z = __builtin_fmaf(base + (float)(64 * J), c.a, -c.fa);
+      pulse_fwd_group<S, J, kPulseGroup>(c, 64.f * c.a, z, r);
+    }
     pulse_fwd_j<S, J + kPulseGroup>(c, base, r, groups);
   }
 }
 
-template <int J>
-__device__ __forceinline__ void pulse_adj_one(const PulseC& c, float base, float rj, float& s0,
-                                              float& s1, float& s2) {
-  const float dj = base + (float)(64 * J);
-  const float z = __builtin_fmaf(dj, c.a, -c.fa);
-  const float nzz = -(z * z);  // the exp argument doubles as the width weight
-  const float e = __builtin_amdgcn_exp2f(nzz);
-  const float re = rj * e;
-  s0 += re;
-  s1 = __builtin_fmaf(re, z, s1);
-  s2 = __builtin_fmaf(re, nzz, s2);
-}
-
 template <int S, int J, int G>
-__device__ __forceinline__ void pulse_adj_group(const PulseC& c, float base, const float (&r)[S],
-                                                float& s0, float& s1, float& s2) {
+__device__ __forceinline__ void pulse_adj_group(const PulseC& c, float a64, float z,
+                                                const float (&r)[S], float& s0, float& s1,
+                                                float& s2) {
   if constexpr (G > 0 && J < S) {
-    pulse_adj_one<J>(c, base, r[J], s0, s1, s2);
-    pulse_adj_group<S, J + 1, G - 1>(c, base, r, s0, s1, s2);
+    const float nzz = -(z * z);  // the exp argument doubles as the width weight
+    const float e = __builtin_amdgcn_exp2f(nzz);
+    const float re = r[J] * e;
+    s0 += re;
+    s1 = __builtin_fmaf(re, z, s1);
+    s2 = __builtin_fmaf(re, nzz, s2);
+    pulse_adj_group<S, J + 1, G - 1>(c, a64, z + a64, r, s0, s1, s2);
   }
 }
 
@@ -302,8 +296,10 @@ __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const f
                                             float& s0, float& s1, float& s2,
                                             GroupMask<S> groups) {
   if constexpr (J < S) {
-    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u))
-      pulse_adj_group<S, J, kPulseGroup>(c, base, r, s0, s1, s2);
+    if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u)) {
+      const float z = __builtin_fmaf(base + (float)(64 * J), c.a, -c.fa);
+      pulse_adj_group<S, J, kPulseGroup>(c, 64.f * c.a, z, r, s0, s1, s2);
+    }
     pulse_adj_j<S, J + kPulseGroup>(c, base, r, s0, s1, s2, groups);
   }
 }
@@ -559,8 +555,10 @@ __host__ __device__ inline size_t const_bytes(int model) {
   return model == SMCX_PULSE ? sizeof(PulseC) : sizeof(GbC);
 }
 
+// LDS of one wave: the component constants, and for gradient passes the
+// adjoint accumulators and the particle's theta rows (P doubles each).
 __device__ __forceinline__ size_t lds_wave_bytes(int model, int32_t k_max, bool grad) {
-  const size_t per = const_bytes(model) + (grad ? (size_t)n_params(model) * 8 : 0);
+  const size_t per = const_bytes(model) + (grad ? 2 * (size_t)n_params(model) * 8 : 0);
   return ((size_t)(k_max + 1) * per + 15) & ~(size_t)15;
 }
 
@@ -901,12 +899,21 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
   unsigned char* base = lds + (size_t)wid * lds_wave_bytes(MODEL, a.k_max, GRAD);
   C* cst = reinterpret_cast<C*>(base);
   double* acc = reinterpret_cast<double*>(base + (size_t)(a.k_max + 1) * sizeof(C));
+  double* thl = acc + (size_t)(a.k_max + 1) * P;  // the particle's theta rows (GRAD)
+  const double* th = a.theta + m0 * P;
+  if constexpr (GRAD) {
+    // theta in whole lines, kept for the gradient's scaling at the end
+    for (int idx = lane; idx < K * P; idx += 64) {
+      thl[idx] = th[idx];
+      acc[idx] = 0.0;
+    }
+    wave_sync();
+    th = thl;
+  }
   bool off_chord = false;  // a component whose chirp needs the exact tile phase
   for (int k = lane; k < K; k += 64) {
-    cst[k] = M::make(a.theta + (m0 + k) * P, a, S);
+    cst[k] = M::make(th + k * P, a, S);
     off_chord |= !M::chord_ok(cst[k], S);
-    if (GRAD)
-      for (int p = 0; p < P; ++p) acc[k * P + p] = 0.0;
   }
   const bool lin = __builtin_amdgcn_ballot_w64(off_chord) == 0;
   wave_sync();
@@ -933,14 +940,26 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
     if constexpr (GRAD) {
       wave_sync();
       const double bs = outer * a.inv_sigma2;
-      const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
+      // scale each component's sums in place, then write the rows out in
+      // whole lines (lane idx of the particle's K P values)
       for (int k = lane; k < K; k += 64) {
         double g[P];
-        M::scale(a.theta + (m0 + k) * P, acc + k * P, bs, a, g);
-        for (int p = 0; p < P; ++p) a.grad[(m0 + k) * P + p] = g[p];
-        if (a.p_half)
-          for (int p = 0; p < P; ++p)
-            a.p_out[(m0 + k) * P + p] = fma(he, g[p], a.p_half[(m0 + k) * P + p]);
+        M::scale(thl + k * P, acc + k * P, bs, a, g);
+        for (int p = 0; p < P; ++p) acc[k * P + p] = g[p];
+      }
+      wave_sync();
+      double* gd = a.grad + m0 * P;
+      if (a.p_half) {
+        const double he = 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0);
+        const double* ph = a.p_half + m0 * P;
+        double* po = a.p_out + m0 * P;
+        for (int idx = lane; idx < K * P; idx += 64) {
+          const double g = acc[idx];
+          gd[idx] = g;
+          po[idx] = fma(he, g, ph[idx]);
+        }
+      } else {
+        for (int idx = lane; idx < K * P; idx += 64) gd[idx] = acc[idx];
       }
     }
   } else {
@@ -1263,7 +1282,7 @@ __global__ __launch_bounds__(256) void template_sum_kernel(int model, int64_t K,
 }
 
 int waves_per_block(int model, int32_t k_max, bool grad) {
-  const size_t per = ((size_t)(k_max + 1) * (const_bytes(model) + (grad ? n_params(model) * 8 : 0)) +
+  const size_t per = ((size_t)(k_max + 1) * (const_bytes(model) + (grad ? 2 * n_params(model) * 8 : 0)) +
                       15) & ~(size_t)15;
   int w = 4;
   while (w > 1 && per * w > 65536) --w;
@@ -1316,7 +1335,7 @@ hipError_t launch_delta_model(const Tiling& t, const PopArgs& a, hipStream_t st)
 }  // namespace
 
 size_t pop_lds_bytes_per_wave(int model, int32_t k_max, bool grad) {
-  const size_t per = const_bytes(model) + (grad ? (size_t)n_params(model) * 8 : 0);
+  const size_t per = const_bytes(model) + (grad ? 2 * (size_t)n_params(model) * 8 : 0);
   return ((size_t)(k_max + 1) * per + 15) & ~(size_t)15;
 }
 
