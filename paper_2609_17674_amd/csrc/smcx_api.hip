@@ -776,7 +776,7 @@ int reweight_extend(smcx_problem* p, int64_t T1, int64_t T2, int64_t N, const in
     if (e != hipSuccess) return hip_fail(e, "segment logl launch");
   }
   hipError_t e = smcx::launch_reweight_reduce(N, delta_beta, logl_ext, logw_prev, logw, w_norm,
-                                              scalars, nullptr, st);
+                                              scalars, p->part, p->part_cap, st);
   if (e != hipSuccess) return hip_fail(e, "reweight launch");
   return SMCX_OK;
 }
@@ -1255,7 +1255,7 @@ int smcx_next_beta(smcx_problem* p, int64_t N, const double* logl, const double*
   if (!(alpha > 0.0 && alpha <= 1.0)) return fail(SMCX_EINVAL, "alpha = %g outside (0, 1]", alpha);
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e = smcx::launch_next_beta(N, logl, logw_prev, beta_prev, alpha, beta_out, logw,
-                                        w_norm, scalars, st);
+                                        w_norm, scalars, p->part, p->part_cap, st);
   if (e != hipSuccess) return hip_fail(e, "next_beta launch");
   return SMCX_OK;
 }

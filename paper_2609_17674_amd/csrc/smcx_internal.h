@@ -251,9 +251,12 @@ hipError_t launch_metric_factor(int P, int64_t N, int64_t M, int32_t k_max,
 size_t factor_lds_bytes(int nmax);
 
 // SMC steps (smcx_smc.hip).
+// Next beta by the ESS condition; with uniform previous weights and a
+// workspace of work_cap doubles large enough, spread over the device.
 hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,
                             double beta_prev, double alpha, double* beta_out, double* logw,
-                            double* w_norm, double* scalars, hipStream_t st);
+                            double* w_norm, double* scalars, double* work, size_t work_cap,
+                            hipStream_t st);
 hipError_t launch_resample(const SmcWork& w, int model, int32_t k_max, int64_t N,
                            const int64_t* offsets, int64_t M, const double* theta,
                            const double* w_norm, double u, int64_t m_cap, int32_t* ancestors,
@@ -277,9 +280,11 @@ hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t 
                             int blocks, hipStream_t st);
 hipError_t launch_fused(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
 hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_t st);
+// Weights, ESS and evidence increment of reweight_extend; over many
+// workgroups when the workspace (part_cap doubles) holds their range sums.
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
                                   const double* logw_prev, double* logw, double* w_norm,
-                                  double* scalars, double* scratch, hipStream_t st);
+                                  double* scalars, double* part, size_t part_cap, hipStream_t st);
 hipError_t launch_drift(int model, int64_t N, int64_t M, const int64_t* offsets, double eps,
                         const int8_t* dir, const uint8_t* active, const double* q_in,
                         const double* p_in, const double* g_in, double* q_out, double* p_out,

@@ -1230,6 +1230,127 @@ __global__ __launch_bounds__(1024) void reweight_kernel(int64_t N, double delta_
   }
 }
 
+// The same reductions over many workgroups (three launches): each workgroup
+// takes a slice of particles in whole lines; range maxima and sums are
+// combined in slice order by every workgroup of the next launch, so all of
+// them use the same bits. exp(log w - m) is computed once and kept in w_norm
+// until the last launch divides it by the sum.
+constexpr int kRwBlock = 256;
+constexpr int kRwPer = 4;
+constexpr int kRwSlice = kRwBlock * kRwPer;
+
+struct RwArgs {
+  int64_t N;
+  double delta_beta;
+  const double* logl_ext;
+  const double* logw_prev;
+  double* logw;
+  double* w_norm;
+  double* scalars;
+  double* part;  // [G][5]: max log w, max logw_prev, sum e, sum e^2, sum e_prev
+  int G;
+};
+
+template <bool MAX>
+__device__ __forceinline__ double rw_block(double v, double* sh) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double u = __shfl_xor(v, o);
+    v = MAX ? fmax(v, u) : v + u;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int w = 1; w < kRwBlock / 64; ++w) r = MAX ? fmax(r, sh[w]) : r + sh[w];
+  return r;
+}
+
+__global__ __launch_bounds__(kRwBlock) void rw_max_kernel(RwArgs a) {
+  __shared__ double sh[kRwBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kRwSlice;
+  double m = -INFINITY, mp = -INFINITY;
+#pragma unroll
+  for (int u = 0; u < kRwPer; ++u) {
+    const int64_t i = base + u * kRwBlock + threadIdx.x;
+    if (i < a.N) {
+      const double lp = a.logw_prev ? a.logw_prev[i] : 0.0;
+      const double v = lp + a.delta_beta * a.logl_ext[i];
+      a.logw[i] = v;
+      m = fmax(m, v);
+      mp = fmax(mp, lp);
+    }
+  }
+  m = rw_block<true>(m, sh);
+  mp = rw_block<true>(mp, sh);
+  if (threadIdx.x == 0) {
+    a.part[5 * blockIdx.x] = m;
+    a.part[5 * blockIdx.x + 1] = mp;
+  }
+}
+
+__global__ __launch_bounds__(kRwBlock) void rw_sum_kernel(RwArgs a) {
+  __shared__ double sh[kRwBlock / 64];
+  double m = -INFINITY, mp = -INFINITY;
+  for (int g = 0; g < a.G; ++g) {
+    m = fmax(m, a.part[5 * g]);
+    mp = fmax(mp, a.part[5 * g + 1]);
+  }
+  const int64_t base = (int64_t)blockIdx.x * kRwSlice;
+  double s1 = 0.0, s2 = 0.0, sp = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRwPer; ++u) {
+    const int64_t i = base + u * kRwBlock + threadIdx.x;
+    if (i < a.N) {
+      const double e = exp(a.logw[i] - m);
+      a.w_norm[i] = e;
+      s1 += e;
+      s2 += e * e;
+      if (a.logw_prev) sp += exp(a.logw_prev[i] - mp);
+    }
+  }
+  s1 = rw_block<false>(s1, sh);
+  s2 = rw_block<false>(s2, sh);
+  sp = rw_block<false>(sp, sh);
+  if (threadIdx.x == 0) {
+    a.part[5 * blockIdx.x + 2] = s1;
+    a.part[5 * blockIdx.x + 3] = s2;
+    a.part[5 * blockIdx.x + 4] = sp;
+  }
+}
+
+__global__ __launch_bounds__(kRwBlock) void rw_weights_kernel(RwArgs a) {
+  __shared__ double tot[5];
+  if (threadIdx.x == 0) {
+    double m = -INFINITY, mp = -INFINITY, s1 = 0.0, s2 = 0.0, sp = 0.0;
+    for (int g = 0; g < a.G; ++g) {
+      m = fmax(m, a.part[5 * g]);
+      mp = fmax(mp, a.part[5 * g + 1]);
+      s1 += a.part[5 * g + 2];
+      s2 += a.part[5 * g + 3];
+      sp += a.part[5 * g + 4];
+    }
+    tot[0] = m;
+    tot[1] = mp;
+    tot[2] = s1;
+    tot[3] = s2;
+    tot[4] = sp;
+  }
+  __syncthreads();
+  const double s1 = tot[2];
+  const int64_t base = (int64_t)blockIdx.x * kRwSlice;
+#pragma unroll
+  for (int u = 0; u < kRwPer; ++u) {
+    const int64_t i = base + u * kRwBlock + threadIdx.x;
+    if (i < a.N) a.w_norm[i] = a.w_norm[i] / s1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double lse_prev = a.logw_prev ? tot[1] + log(tot[4]) : log((double)a.N);
+    a.scalars[0] = s1 * s1 / tot[3];
+    a.scalars[1] = tot[0] + log(s1) - lse_prev;
+    a.scalars[2] = tot[0];
+  }
+}
+
 // ---------------------------------------------------------------- leapfrog drift
 // First half of a leapfrog step, one wave per particle over its K*P values:
 //   p_half = p + (eps_i/2) g,  q' = q + eps_i p_half;
@@ -1373,9 +1494,18 @@ hipError_t launch_delta(int model, const Tiling& t, const PopArgs& a, hipStream_
 
 hipError_t launch_reweight_reduce(int64_t N, double delta_beta, const double* logl_ext,
                                   const double* logw_prev, double* logw, double* w_norm,
-                                  double* scalars, double* /*scratch*/, hipStream_t st) {
-  hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(1024), 0, st, N, delta_beta, logl_ext,
-                     logw_prev, logw, w_norm, scalars);
+                                  double* scalars, double* part, size_t part_cap, hipStream_t st) {
+  const int64_t G = (N + kRwSlice - 1) / kRwSlice;
+  if (N == 0 || !part || part_cap < (size_t)(5 * G)) {
+    hipLaunchKernelGGL(reweight_kernel, dim3(1), dim3(1024), 0, st, N, delta_beta, logl_ext,
+                       logw_prev, logw, w_norm, scalars);
+    return hipGetLastError();
+  }
+  RwArgs a{N, delta_beta, logl_ext, logw_prev, logw, w_norm, scalars, part, (int)G};
+  const dim3 grid((unsigned)G), block(kRwBlock);
+  hipLaunchKernelGGL(rw_max_kernel, grid, block, 0, st, a);
+  hipLaunchKernelGGL(rw_sum_kernel, grid, block, 0, st, a);
+  hipLaunchKernelGGL(rw_weights_kernel, grid, block, 0, st, a);
   return hipGetLastError();
 }
 

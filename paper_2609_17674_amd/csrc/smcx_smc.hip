@@ -110,6 +110,14 @@ __device__ double block_max(double a, double* sh) {
   return a;
 }
 
+// The search stops when the bracket is 1e-14 of the step or a few units in
+// the last place of beta, whichever is wider (a step much smaller than
+// beta_prev cannot be resolved to 1e-14 of itself).
+constexpr double kBracketUlps = 8.0 * 2.220446049250313e-16;
+// ... or when the lower end itself meets the condition to 1e-12 in log ESS
+// (ESS >= alpha N still holds there).
+constexpr double kRootTol = 1e-12;
+
 struct NextBetaArgs {
   int64_t N;
   const double* logl;
@@ -199,7 +207,9 @@ __global__ __launch_bounds__(kBlock) void next_beta_kernel(NextBetaArgs a) {
           if (side == -1) flo *= 0.5;
           side = -1;
         }
-        if (hi - lo <= 1e-14 * (hi - a.beta_prev)) break;
+        if (hi - lo <= fmax(1e-14 * (hi - a.beta_prev), kBracketUlps * hi) ||
+            (fx >= 0.0 && fx <= kRootTol))
+          break;
       }
       beta = lo;
     }
@@ -228,6 +238,252 @@ __global__ __launch_bounds__(kBlock) void next_beta_kernel(NextBetaArgs a) {
     a.scalars[1] = ess;
     a.scalars[2] = m + log(s1) - lse_prev;
     a.scalars[3] = (double)evals;
+  }
+}
+
+// ---------------------------------------------------------------- next beta, many workgroups
+// The same search for uniform previous weights (no logw_prev), spread over
+// the device: one launch per ESS evaluation. A launch's workgroups each sum
+// exp(db l_i - m) and its square over their slice of particles (m = db
+// max_i l_i, exact since db >= 0); the next launch's workgroups first add the
+// range sums in slice order and take the search's next step from them, every
+// workgroup computing the same bits (so they agree on the point to evaluate),
+// and workgroup 0 records the step. A fixed number of evaluation launches is
+// queued; the ones after the search has ended return at once, and a one-block
+// pass finishes a search that would still be running. The evaluation at the
+// bracket's lower end is kept, so the weights need no further pass.
+constexpr int kNbBlock = 256;
+constexpr int kNbPer = 4;                      // particles per thread per launch
+constexpr int kNbSlice = kNbBlock * kNbPer;    // particles per workgroup
+constexpr int kNbLaunches = 12;                // evaluation launches queued
+constexpr int kNbState = 16;                   // doubles per search state
+
+// search state (doubles): lo, hi, flo, fhi, x (point evaluated by the launch),
+// side, evals, phase (0: evaluate beta = 1; 1: bracketing search; 2: done),
+// beta, s1_lo, s2_lo (sums at beta), L (max l)
+enum { kLo, kHi, kFlo, kFhi, kX, kSide, kEvals, kPhase, kBeta, kS1, kS2, kL };
+
+struct NbMultiArgs {
+  int64_t N;
+  const double* logl;
+  double beta_prev, alpha, target;
+  double* beta_out;
+  double* logw;
+  double* w_norm;
+  double* scalars;
+  double* state;  // [2][kNbState]
+  double* pmax;   // [G]
+  double* psum;   // [2][G][2]
+  int G;
+};
+
+__device__ __forceinline__ double nb_max_l(const NbMultiArgs& a) {
+  double L = -INFINITY;
+  for (int g = 0; g < a.G; ++g) L = fmax(L, a.pmax[g]);
+  return L;
+}
+
+// The search's step after an evaluation at st[kX] with sums (s1, s2); the
+// same arithmetic as next_beta_kernel's bracketing search.
+__device__ void nb_advance(const NbMultiArgs& a, double* st, double s1, double s2) {
+  const double ess = s1 * s1 / s2;
+  if (st[kPhase] == 0.0) {  // the evaluation at beta = 1
+    if (ess >= a.target) {
+      st[kPhase] = 2.0;
+      st[kBeta] = 1.0;
+      st[kS1] = s1;
+      st[kS2] = s2;
+      return;
+    }
+    st[kLo] = a.beta_prev;
+    st[kHi] = 1.0;
+    st[kFlo] = log((double)a.N / a.target);
+    st[kFhi] = log(ess / a.target);
+    st[kSide] = 0.0;
+    st[kPhase] = 1.0;
+    // sums at beta_prev: uniform weights
+    st[kS1] = (double)a.N;
+    st[kS2] = (double)a.N;
+  } else {
+    const double x = st[kX];
+    const double fx = log(ess / a.target);
+    st[kEvals] += 1.0;
+    if (fx >= 0.0) {
+      st[kLo] = x;
+      st[kFlo] = fx;
+      if (st[kSide] == 1.0) st[kFhi] *= 0.5;
+      st[kSide] = 1.0;
+      st[kS1] = s1;
+      st[kS2] = s2;
+    } else {
+      st[kHi] = x;
+      st[kFhi] = fx == fx ? fx : -INFINITY;
+      if (st[kSide] == -1.0) st[kFlo] *= 0.5;
+      st[kSide] = -1.0;
+    }
+    if (st[kHi] - st[kLo] <= fmax(1e-14 * (st[kHi] - a.beta_prev), kBracketUlps * st[kHi]) ||
+        (fx >= 0.0 && fx <= kRootTol) || st[kEvals] >= 100.0) {
+      st[kPhase] = 2.0;
+      st[kBeta] = st[kLo];
+      return;
+    }
+  }
+  const double lo = st[kLo], hi = st[kHi], flo = st[kFlo], fhi = st[kFhi];
+  double x = fhi == fhi && flo - fhi > 0.0 ? hi - fhi * (hi - lo) / (fhi - flo) : 0.5 * (lo + hi);
+  if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+  if (!(x > lo && x < hi)) {
+    st[kPhase] = 2.0;
+    st[kBeta] = lo;
+    return;
+  }
+  st[kX] = x;
+}
+
+__global__ __launch_bounds__(kNbBlock) void nb_max_kernel(NbMultiArgs a) {
+  __shared__ double sh[kNbBlock / 64];
+  const int64_t base = (int64_t)blockIdx.x * kNbSlice;
+  double m = -INFINITY;
+#pragma unroll
+  for (int u = 0; u < kNbPer; ++u) {
+    const int64_t i = base + u * kNbBlock + threadIdx.x;
+    if (i < a.N) m = fmax(m, a.logl[i]);
+  }
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < kNbBlock / 64; ++w) r = fmax(r, sh[w]);
+    a.pmax[blockIdx.x] = r;
+  }
+}
+
+// Launch k: take the step after launch k - 1's evaluation (k > 0), then
+// evaluate the new point.
+__global__ __launch_bounds__(kNbBlock) void nb_eval_kernel(NbMultiArgs a, int k) {
+  __shared__ double st[kNbState];
+  __shared__ double sh[2 * (kNbBlock / 64)];
+  if (threadIdx.x == 0) {
+    if (k == 0) {
+      for (int q = 0; q < kNbState; ++q) st[q] = 0.0;
+      st[kX] = 1.0;
+      st[kL] = nb_max_l(a);
+    } else {
+      const double* prev = a.state + ((k - 1) & 1) * kNbState;
+      for (int q = 0; q < kNbState; ++q) st[q] = prev[q];
+      if (st[kPhase] != 2.0) {
+        const double* ps = a.psum + (size_t)((k - 1) & 1) * a.G * 2;
+        double s1 = 0.0, s2 = 0.0;
+        for (int g = 0; g < a.G; ++g) {
+          s1 += ps[2 * g];
+          s2 += ps[2 * g + 1];
+        }
+        nb_advance(a, st, s1, s2);
+      }
+    }
+    if (blockIdx.x == 0) {
+      double* cur = a.state + (k & 1) * kNbState;
+      for (int q = 0; q < kNbState; ++q) cur[q] = st[q];
+    }
+  }
+  __syncthreads();
+  if (st[kPhase] == 2.0) return;
+  const double db = st[kX] - a.beta_prev;
+  const double m = db * st[kL];
+  const int64_t base = (int64_t)blockIdx.x * kNbSlice;
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < kNbPer; ++u) {
+    const int64_t i = base + u * kNbBlock + threadIdx.x;
+    if (i < a.N) {
+      const double e = exp(db * a.logl[i] - m);
+      s1 += e;
+      s2 += e * e;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6] = s1;
+    sh[kNbBlock / 64 + (threadIdx.x >> 6)] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = 0.0, t2 = 0.0;
+    for (int w = 0; w < kNbBlock / 64; ++w) {
+      t1 += sh[w];
+      t2 += sh[kNbBlock / 64 + w];
+    }
+    double* ps = a.psum + (size_t)(k & 1) * a.G * 2;
+    ps[2 * blockIdx.x] = t1;
+    ps[2 * blockIdx.x + 1] = t2;
+  }
+}
+
+// One block: take the step after the last queued evaluation and, should the
+// search still be running, finish it with block-wide evaluations.
+__global__ __launch_bounds__(kBlock) void nb_finish_kernel(NbMultiArgs a) {
+  __shared__ double st[kNbState];
+  __shared__ double sh[2 * kBlockWaves];
+  constexpr int k = kNbLaunches;  // the step after launch kNbLaunches - 1
+  if (threadIdx.x == 0) {
+    const double* prev = a.state + ((k - 1) & 1) * kNbState;
+    for (int q = 0; q < kNbState; ++q) st[q] = prev[q];
+    if (st[kPhase] != 2.0) {
+      const double* ps = a.psum + (size_t)((k - 1) & 1) * a.G * 2;
+      double s1 = 0.0, s2 = 0.0;
+      for (int g = 0; g < a.G; ++g) {
+        s1 += ps[2 * g];
+        s2 += ps[2 * g + 1];
+      }
+      nb_advance(a, st, s1, s2);
+    }
+  }
+  __syncthreads();
+  while (st[kPhase] != 2.0) {
+    const double db = st[kX] - a.beta_prev;
+    const double m = db * st[kL];
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t i = threadIdx.x; i < a.N; i += kBlock) {
+      const double e = exp(db * a.logl[i] - m);
+      s1 += e;
+      s2 += e * e;
+    }
+    block_sum2(s1, s2, sh);  // the same bits in every thread
+    __syncthreads();
+    if (threadIdx.x == 0) nb_advance(a, st, s1, s2);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* cur = a.state + (k & 1) * kNbState;
+    for (int q = 0; q < kNbState; ++q) cur[q] = st[q];
+  }
+}
+
+// Weights at the chosen beta (eq. incremental_weight), normalised by the
+// kept sums, and the scalars.
+__global__ __launch_bounds__(kNbBlock) void nb_weights_kernel(NbMultiArgs a) {
+  const double* st = a.state + (kNbLaunches & 1) * kNbState;
+  const double beta = st[kBeta], db = beta - a.beta_prev;
+  const double m = db * st[kL], s1 = st[kS1];
+  const int64_t base = (int64_t)blockIdx.x * kNbSlice;
+#pragma unroll
+  for (int u = 0; u < kNbPer; ++u) {
+    const int64_t i = base + u * kNbBlock + threadIdx.x;
+    if (i < a.N) {
+      const double lw = db * a.logl[i];
+      a.logw[i] = lw;
+      a.w_norm[i] = exp(lw - m) / s1;
+      if (a.beta_out) a.beta_out[i] = beta;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scalars[0] = beta;
+    a.scalars[1] = s1 * s1 / st[kS2];
+    a.scalars[2] = m + log(s1) - log((double)a.N);
+    a.scalars[3] = st[kEvals];
   }
 }
 
@@ -413,9 +669,33 @@ hipError_t launch_rebuild(const RebuildArgs& r, hipStream_t st) {
 
 hipError_t launch_next_beta(int64_t N, const double* logl, const double* logw_prev,
                             double beta_prev, double alpha, double* beta_out, double* logw,
-                            double* w_norm, double* scalars, hipStream_t st) {
-  NextBetaArgs a{N, logl, logw_prev, beta_prev, alpha, beta_out, logw, w_norm, scalars};
-  hipLaunchKernelGGL(next_beta_kernel, dim3(1), dim3(kBlock), 0, st, a);
+                            double* w_norm, double* scalars, double* work, size_t work_cap,
+                            hipStream_t st) {
+  const int64_t G = (N + kNbSlice - 1) / kNbSlice;
+  if (logw_prev || !work || work_cap < (size_t)(2 * kNbState + 5 * G)) {
+    NextBetaArgs a{N, logl, logw_prev, beta_prev, alpha, beta_out, logw, w_norm, scalars};
+    hipLaunchKernelGGL(next_beta_kernel, dim3(1), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  }
+  NbMultiArgs a;
+  a.N = N;
+  a.logl = logl;
+  a.beta_prev = beta_prev;
+  a.alpha = alpha;
+  a.target = alpha * (double)N;
+  a.beta_out = beta_out;
+  a.logw = logw;
+  a.w_norm = w_norm;
+  a.scalars = scalars;
+  a.state = work;
+  a.pmax = work + 2 * kNbState;
+  a.psum = a.pmax + G;
+  a.G = (int)G;
+  const dim3 grid((unsigned)G), block(kNbBlock);
+  hipLaunchKernelGGL(nb_max_kernel, grid, block, 0, st, a);
+  for (int k = 0; k < kNbLaunches; ++k) hipLaunchKernelGGL(nb_eval_kernel, grid, block, 0, st, a, k);
+  hipLaunchKernelGGL(nb_finish_kernel, dim3(1), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(nb_weights_kernel, grid, block, 0, st, a);
   return hipGetLastError();
 }
 
