@@ -112,7 +112,16 @@ enum { SMCX_PULSE = 0, SMCX_GBSINE = 1, SMCX_GBLISA = 2 };
  *   hip_stream stream used for the set-up copies; the call synchronises it
  *   out        receives the handle
  * Returns SMCX_EINVAL for bad sizes, SMCX_ENOMEM if the workspace cannot be
- * allocated. This is the only call that allocates or synchronises. */
+ * allocated or exceeds the cap below. This is the only call that allocates
+ * or synchronises (with smcx_nuts_reserve).
+ *
+ * Workspace cap: when the environment variable SMCX_WORKSPACE_MAX holds a
+ * byte count (decimal, optional suffix k, m or g for 2^10, 2^20, 2^30), the
+ * calls that allocate a handle's device workspace (the two creates and
+ * smcx_nuts_reserve) first add up what the handle would then hold and return
+ * SMCX_ENOMEM, allocating nothing, when it exceeds the cap; an existing
+ * handle stays usable as it was. A value that does not parse gives
+ * SMCX_EINVAL. The variable is read at each such call. */
 int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_start, double dt,
                         double sigma, int32_t k_max, int64_t n_max, int64_t m_max,
                         void* hip_stream, smcx_problem** out);
@@ -319,7 +328,10 @@ int smcx_leapfrog(smcx_problem* prob, int64_t N, const int64_t* offsets, int64_t
 
 /* Reserve the device workspace of smcx_nuts_transition for trees of depth
  * up to max_depth (1..10): about (16 + 2 max_depth) m_max P doubles plus
- * small per-particle arrays. A set-up call: allocates, may synchronise. */
+ * small per-particle arrays. A set-up call: allocates, may synchronise.
+ * SMCX_ENOMEM when the grown workspace would exceed SMCX_WORKSPACE_MAX
+ * (the handle and its reserved depth are then unchanged) or an allocation
+ * fails (the reserved depth is then 0 until a reserve succeeds). */
 int smcx_nuts_reserve(smcx_problem* prob, int32_t max_depth);
 
 /* One No-U-Turn transition (Sec. "No-U-Turn-Sampler") for every particle,
@@ -690,7 +702,11 @@ enum {
   SMCX_PROBE_CVT = 6,       /* v_cvt_f32_i32 */
   SMCX_PROBE_SIN_4FMA = 7,  /* one v_sin_f32 and four v_fmac_f32 per step */
   SMCX_PROBE_FMAC_F32 = 8,  /* v_fmac_f32 (the two-operand accumulator form) */
-  SMCX_PROBE_ADD_F32 = 9    /* v_add_f32 */
+  SMCX_PROBE_ADD_F32 = 9,   /* v_add_f32 */
+  SMCX_PROBE_MUL_F64 = 10,  /* v_mul_f64 */
+  SMCX_PROBE_ADD_F64 = 11,  /* v_add_f64 */
+  SMCX_PROBE_DPP = 12,      /* v_mov_b32 with a DPP row rotation */
+  SMCX_PROBE_PERMLANE32 = 13 /* v_permlane32_swap_b32 */
 };
 
 /* The measured VALU ceilings the roofline of the population kernels refers

@@ -1,6 +1,7 @@
 // C ABI of libsmcx: problem handle, argument checks, workspace, launches.
 #include <hip/hip_runtime.h>
 
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,6 +58,29 @@ bool capturing(hipStream_t st) {
 }
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// The cap on one handle's device workspace: SMCX_WORKSPACE_MAX in bytes,
+// with an optional k, m or g suffix (2^10, 2^20, 2^30); unset means none.
+// Returns SMCX_OK when `bytes` fits, SMCX_ENOMEM when it does not and
+// SMCX_EINVAL for a value that does not parse; nothing is allocated either way.
+int check_workspace(size_t bytes, const char* what) {
+  const char* v = std::getenv("SMCX_WORKSPACE_MAX");
+  if (!v || !*v) return SMCX_OK;
+  char* end = nullptr;
+  errno = 0;
+  const unsigned long long n = std::strtoull(v, &end, 10);
+  unsigned shift = 0;
+  if (end && (*end == 'k' || *end == 'K')) shift = 10, ++end;
+  else if (end && (*end == 'm' || *end == 'M')) shift = 20, ++end;
+  else if (end && (*end == 'g' || *end == 'G')) shift = 30, ++end;
+  if (errno || end == v || *end || (shift && n > (~0ull >> shift)))
+    return fail(SMCX_EINVAL, "SMCX_WORKSPACE_MAX = '%s' is not a byte count", v);
+  const unsigned long long cap = n << shift;
+  if (bytes > cap)
+    return fail(SMCX_ENOMEM, "%s needs %zu bytes of device workspace, over SMCX_WORKSPACE_MAX = %llu",
+                what, bytes, cap);
+  return SMCX_OK;
+}
 
 }  // namespace
 
@@ -305,6 +329,14 @@ void fd_table_host(double T_obs, std::vector<double>& tab) {
       tab[smcx::kFdTwiddleInv + st * 128 + 2 * l + 1] = -sn;
     }
   }
+  // the phase table of the envelope: cos and sin of 2 pi k / 128 (from
+  // long double, so that each entry is the double nearest its value)
+  const long double kPiL = 3.141592653589793238462643383279502884L;
+  for (int k = -smcx::kFdTrigSteps / 2; k <= smcx::kFdTrigSteps / 2; ++k) {
+    const long double x = 2.0L * kPiL * k / smcx::kFdTrigSteps;
+    tab[smcx::kFdTrig + 2 * (k + smcx::kFdTrigSteps / 2)] = (double)std::cos(x);
+    tab[smcx::kFdTrig + 2 * (k + smcx::kFdTrigSteps / 2) + 1] = (double)std::sin(x);
+  }
 }
 
 // logL of a particle without components, split at the posterior-start bridge
@@ -431,6 +463,12 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
       {(void**)&p->rbuf, T * sizeof(double)},
       {(void**)&p->bpart, nb * sizeof(double)},
   };
+  size_t total = 0;
+  for (auto& al : allocs) total += al.bytes;
+  if (int rc = check_workspace(total, "the problem handle")) {
+    free_problem(p);
+    return rc;
+  }
   for (auto& al : allocs) {
     e = hipMalloc(al.ptr, al.bytes);
     if (e != hipSuccess) {
@@ -438,6 +476,7 @@ int smcx_problem_create(int model, const double* d_dev, int64_t T, double t_star
       return fail(SMCX_ENOMEM, "hipMalloc of %zu bytes failed: %s", al.bytes, hipGetErrorString(e));
     }
   }
+  p->ws_bytes = total;
   const int zero = 0;
   e = hipMemcpyAsync(p->d32, h32.data(), T_pad * sizeof(float), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(p->d64, d_dev, T * sizeof(double), hipMemcpyDeviceToDevice, st);
@@ -491,7 +530,7 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
   if (e != hipSuccess) { free_problem(p); return hip_fail(e, "hipDeviceGetAttribute"); }
   for (int k = 0; k < kNumKinds; ++k) p->tiling[k] = Tiling{16, 1024, 1, 1};
   p->max_nch = p->max_nch_grad = 1;
-  const int64_t Bp = B <= 128 ? 128 : 256;
+  const int64_t Bp = smcx::kFdBandStride;
   std::vector<double> h(4 * B), hp(4 * Bp, 0.0), tab;
   e = hipMemcpyAsync(h.data(), d_dev, 4 * B * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -510,7 +549,7 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
   p->part_cap = n1 * 4;
   struct { void** ptr; size_t bytes; } allocs[] = {
       {(void**)&p->fd_data, 4 * Bp * sizeof(double)},
-      {(void**)&p->fd_src, (size_t)std::max<int64_t>(m_max, 1) * 34 * sizeof(double)},
+      {(void**)&p->fd_src, (size_t)std::max<int64_t>(m_max, 1) * smcx::kFdSrcWords * sizeof(double)},
       {(void**)&p->fd_table, tab.size() * sizeof(double)},
       {(void**)&p->order, n1 * sizeof(int32_t)},
       {(void**)&p->n_active, sizeof(int32_t)},
@@ -525,6 +564,12 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
       {(void**)&p->part, n1 * 4 * sizeof(double)},
       {(void**)&p->part_g, sizeof(double)},
   };
+  size_t total = 0;
+  for (auto& al : allocs) total += al.bytes;
+  if (int rc = check_workspace(total, "the problem handle")) {
+    free_problem(p);
+    return rc;
+  }
   for (auto& al : allocs) {
     e = hipMalloc(al.ptr, al.bytes);
     if (e != hipSuccess) {
@@ -532,6 +577,7 @@ int smcx_problem_create_fd(int model, const double* d_dev, int64_t k0, int64_t B
       return fail(SMCX_ENOMEM, "hipMalloc of %zu bytes failed: %s", al.bytes, hipGetErrorString(e));
     }
   }
+  p->ws_bytes = total;
   const int zero = 0;
   e = hipMemcpyAsync(p->fd_data, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
@@ -880,24 +926,52 @@ int smcx_nuts_reserve(smcx_problem* p, int32_t max_depth) {
   if (max_depth < 1 || max_depth > smcx::kNutsMaxDepth)
     return fail(SMCX_EINVAL, "max_depth = %d outside [1, %d]", max_depth, smcx::kNutsMaxDepth);
   if (p->nuts_depth >= max_depth) return SMCX_OK;
+  const size_t stride = (size_t)std::max<int64_t>(p->m_max, 1) * p->P;
+  const size_t nN = (size_t)std::max<int64_t>(p->n_max, 1);
+  auto depth_bytes = [&](int D) {
+    return D > 0 ? stride * smcx::kNutsSlots(D) * sizeof(double) + (D + 1) * sizeof(int) : 0;
+  };
+  const size_t per_particle = nN * (sizeof(smcx::NutsState) + sizeof(double) + 2 + 2 * sizeof(int32_t));
+  // the cap is checked before anything is released: a refused reserve keeps
+  // the handle, and its smaller NUTS workspace, as they were
+  const size_t grown = p->ws_bytes - depth_bytes(p->nuts_depth) + depth_bytes(max_depth) +
+                       (p->nuts_state ? 0 : per_particle);
+  if (int rc = check_workspace(grown, "the NUTS workspace")) return rc;
   if (p->nuts_vec) {  // grow: release the smaller workspace first
     (void)hipDeviceSynchronize();
     (void)hipFree(p->nuts_vec);
     p->nuts_vec = nullptr;
     (void)hipFree(p->nuts_count);
     p->nuts_count = nullptr;
+    p->ws_bytes -= depth_bytes(p->nuts_depth);
+    p->nuts_depth = 0;
   }
-  const size_t stride = (size_t)std::max<int64_t>(p->m_max, 1) * p->P;
-  const size_t nN = (size_t)std::max<int64_t>(p->n_max, 1);
   hipError_t e = hipMalloc(&p->nuts_vec, stride * smcx::kNutsSlots(max_depth) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&p->nuts_count, (max_depth + 1) * sizeof(int));
-  if (e == hipSuccess && !p->nuts_state) e = hipMalloc(&p->nuts_state, nN * sizeof(smcx::NutsState));
-  if (e == hipSuccess && !p->nuts_logl) e = hipMalloc(&p->nuts_logl, nN * sizeof(double));
-  if (e == hipSuccess && !p->nuts_active) e = hipMalloc(&p->nuts_active, nN);
-  if (e == hipSuccess && !p->nuts_dir) e = hipMalloc(&p->nuts_dir, nN);
-  if (e == hipSuccess && !p->nuts_list) e = hipMalloc(&p->nuts_list, 2 * nN * sizeof(int32_t));
-  if (e == hipSuccess && !p->nuts_capture) e = hipStreamCreateWithFlags(&p->nuts_capture, hipStreamNonBlocking);
-  if (e != hipSuccess) return fail(SMCX_ENOMEM, "NUTS workspace allocation failed: %s", hipGetErrorString(e));
+  if (e != hipSuccess) {
+    (void)hipFree(p->nuts_vec);
+    p->nuts_vec = nullptr;
+    return fail(SMCX_ENOMEM, "NUTS workspace allocation failed: %s", hipGetErrorString(e));
+  }
+  p->ws_bytes += depth_bytes(max_depth);
+  if (!p->nuts_state) {
+    e = hipMalloc(&p->nuts_state, nN * sizeof(smcx::NutsState));
+    if (e == hipSuccess) e = hipMalloc(&p->nuts_logl, nN * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&p->nuts_active, nN);
+    if (e == hipSuccess) e = hipMalloc(&p->nuts_dir, nN);
+    if (e == hipSuccess) e = hipMalloc(&p->nuts_list, 2 * nN * sizeof(int32_t));
+    if (e != hipSuccess) {
+      for (void** q : {(void**)&p->nuts_state, (void**)&p->nuts_logl, (void**)&p->nuts_active,
+                       (void**)&p->nuts_dir, (void**)&p->nuts_list}) {
+        (void)hipFree(*q);
+        *q = nullptr;
+      }
+      return fail(SMCX_ENOMEM, "NUTS workspace allocation failed: %s", hipGetErrorString(e));
+    }
+    p->ws_bytes += per_particle;
+  }
+  if (!p->nuts_capture) e = hipStreamCreateWithFlags(&p->nuts_capture, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "NUTS capture stream");
   p->nuts_depth = max_depth;
   for (hipGraphExec_t g : p->nuts_graph)
     if (g) (void)hipGraphExecDestroy(g);

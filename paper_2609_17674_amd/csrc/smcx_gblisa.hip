@@ -54,23 +54,57 @@ struct LaneGeom {
   __device__ __forceinline__ double t() const { return g[14 * 64]; }
 };
 
-// The lane tables of a workgroup in LDS: the grid of the handle's record and,
-// under a bridge, of its partner's; the FFT twiddles, forward then inverse,
-// [stage][lane][re, im] each.
+// The lane tables of a workgroup, in the dynamic LDS of the launch: the FFT
+// twiddles, forward then inverse, [stage][lane][re, im] each; the phase
+// table of the envelope; the grid of the handle's record; under a bridge
+// that of its partner (otherwise geo[1] aliases geo[0] and takes no space).
+// The gradient kernel adds one residual copy per wave after them
+// (fd_lds_words).
+constexpr int kTwWords = 2 * 6 * 128;
+constexpr int kTrigWords = 2 * (kFdTrigSteps + 1);
+constexpr int kGeoWords = kGeoFields * 64;
 struct FdTables {
-  double geo[2][kGeoFields][64];
-  double tw[2 * 6 * 128];
+  const double* tw;
+  const double* trig;
+  const double* geo[2];
 };
 
+extern __shared__ double fd_lds[];
+
+// Doubles of dynamic LDS a frequency-domain launch needs: the tables, plus
+// resid_words per wave.
+constexpr size_t fd_lds_words(bool bridge, int waves, int resid_words) {
+  return (size_t)kTwWords + kTrigWords + (bridge ? 2 : 1) * kGeoWords + (size_t)waves * resid_words;
+}
+
 // Every thread of the workgroup calls this before any of them returns.
-__device__ __forceinline__ void stage_tables(FdTables& t, const double* own, const double* partner) {
-  for (int x = threadIdx.x; x < kGeoFields * 64; x += blockDim.x) {
+// Returns the first word after the tables.
+__device__ __forceinline__ double* stage_tables(FdTables& t, const double* own, const double* partner) {
+  double* tw = fd_lds;
+  double* trig = tw + kTwWords;
+  double* g0 = trig + kTrigWords;
+  double* g1 = partner ? g0 + kGeoWords : g0;
+  for (int x = threadIdx.x; x < kGeoWords; x += blockDim.x) {
     const int f = x >> 6, l = x & 63;
-    t.geo[0][f][l] = own[l * kFdTableStride + f];
-    if (partner) t.geo[1][f][l] = partner[l * kFdTableStride + f];
+    g0[x] = own[l * kFdTableStride + f];
+    if (partner) g1[x] = partner[l * kFdTableStride + f];
   }
-  for (int x = threadIdx.x; x < 2 * 6 * 128; x += blockDim.x) t.tw[x] = own[kFdTwiddleFwd + x];
+  for (int x = threadIdx.x; x < kTwWords; x += blockDim.x) tw[x] = own[kFdTwiddleFwd + x];
+  for (int x = threadIdx.x; x < kTrigWords; x += blockDim.x) trig[x] = own[kFdTrig + x];
   __syncthreads();
+  t.tw = tw;
+  t.trig = trig;
+  t.geo[0] = g0;
+  t.geo[1] = g1;
+  return (partner ? g1 : g0) + kGeoWords;
+}
+
+// Orders the LDS accesses of one wave around it (they complete in order;
+// this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 struct V3 {
@@ -90,6 +124,9 @@ struct Src {
   // X = 2 u.D v of a detector tensor D; as weights of its six components
   // (xx, yy, zz, xy, xz, yz): P = sum ep[e] D[e], X = sum ex[e] D[e].
   double ep[6], ex[6];
+  // The weights of the forms n.D u and n.D v in the same way (the
+  // zz weight of n.D v is zero, v having no z component: five words).
+  double wnu[6], wnv[5];
   V3 n, u, v;  // v = (-sin l, cos l, 0)
   int64_t q;
 };
@@ -100,10 +137,12 @@ struct Src {
 // restrict-qualified pointer, so they arrive by scalar loads into scalar
 // registers instead of occupying vector registers in every lane. Words 0-32
 // hold the constants with the carrier bin q of the handle's record, word 33
-// the carrier bin under the bridge partner's observation time.
-constexpr int kSrcWords = 34;
-constexpr int kQOwn = 32, kQPartner = 33;
+// the carrier bin under the bridge partner's observation time, words 34-44
+// the weights of n.D u and n.D v, word 45 is zero.
+constexpr int kSrcWords = kFdSrcWords;
+constexpr int kQOwn = 32, kQPartner = 33, kWnu = 34, kWnv = 40;
 
+// All words but the partner's carrier bin.
 __device__ __forceinline__ void src_store(double* c, const Src& s) {
   const double v[33] = {s.f0,    s.fd,    s.A,     s.cb,    s.sb,    s.cl,    s.sl,
                         s.c2p,   s.s2p,   s.ci,    s.si,    s.cyc0,  s.Ap,    s.Ax,
@@ -112,6 +151,11 @@ __device__ __forceinline__ void src_store(double* c, const Src& s) {
                         s.n.z,   s.u.x,   s.u.y,   s.u.z,   __builtin_bit_cast(double, s.q)};
 #pragma unroll
   for (int x = 0; x < 33; ++x) c[x] = v[x];
+#pragma unroll
+  for (int x = 0; x < 6; ++x) c[kWnu + x] = s.wnu[x];
+#pragma unroll
+  for (int x = 0; x < 5; ++x) c[kWnv + x] = s.wnv[x];
+  c[kSrcWords - 1] = 0.0;
 }
 
 __device__ __forceinline__ Src src_load(const double* c, int qslot) {
@@ -127,6 +171,10 @@ __device__ __forceinline__ Src src_load(const double* c, int qslot) {
   s.u = {c[29], c[30], c[31]};
   s.v = {-s.sl, s.cl, 0.0};
   s.q = __builtin_bit_cast(int64_t, c[qslot]);  // stored as its bit pattern
+#pragma unroll
+  for (int x = 0; x < 6; ++x) s.wnu[x] = c[kWnu + x];
+#pragma unroll
+  for (int x = 0; x < 5; ++x) s.wnv[x] = c[kWnv + x];
   return s;
 }
 
@@ -160,6 +208,18 @@ __device__ __forceinline__ Src make_src(const double* th, double T_obs) {
   s.ex[3] = 2.0 * (u.x * v.y + u.y * v.x);
   s.ex[4] = 2.0 * (u.x * v.z + u.z * v.x);
   s.ex[5] = 2.0 * (u.y * v.z + u.z * v.y);
+  const V3& n = s.n;
+  s.wnu[0] = n.x * u.x;
+  s.wnu[1] = n.y * u.y;
+  s.wnu[2] = n.z * u.z;
+  s.wnu[3] = n.x * u.y + n.y * u.x;
+  s.wnu[4] = n.x * u.z + n.z * u.x;
+  s.wnu[5] = n.y * u.z + n.z * u.y;
+  s.wnv[0] = n.x * v.x;  // xx, yy, xy, xz, yz
+  s.wnv[1] = n.y * v.y;
+  s.wnv[2] = n.x * v.y + n.y * v.x;
+  s.wnv[3] = n.z * v.x;
+  s.wnv[4] = n.z * v.y;
   return s;
 }
 
@@ -168,6 +228,7 @@ struct Env {
   double zr[2], zi[2];  // z_c
   double ar[2], ai[2];  // complex amplitude a_c
   double Fp[2], Fx[2];
+  double P[2], X[2];  // the polarisation patterns u.D u - v.D v and 2 u.D v
   double cph, sph, tau, doppler;  // doppler = cos(a - l) (R/c)
 };
 
@@ -184,6 +245,8 @@ __device__ __forceinline__ Env envelope_amp(const Src& s, const LaneGeom& g) {
       P = fma(s.ep[x], D, P);
       X = fma(s.ex[x], D, X);
     }
+    e.P[c] = P;
+    e.X[c] = X;
     e.Fp[c] = s.c2p * P + s.s2p * X;
     e.Fx[c] = -s.s2p * P + s.c2p * X;
     e.ar[c] = e.Fp[c] * s.Ap;
@@ -194,13 +257,34 @@ __device__ __forceinline__ Env envelope_amp(const Src& s, const LaneGeom& g) {
   return e;
 }
 
-__device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, int lane) {
+// cos and sin of 2 pi cyc, |cyc| <= 1/2: the table's nearest step k / 128
+// (trig: cos, sin of 2 pi k / 128 for k = -64..64) turned by the remainder
+// x = 2 pi (cyc - k / 128), |x| <= pi / 128, whose sine and cosine are
+// their Taylor series cut after x^7 and x^6 (the next terms are below
+// 1e-20 and 4e-18). The cut is relative to the double-precision ulp far
+// smaller than the rounding of the two products that turn the step.
+__device__ __forceinline__ void cis_cycles(double cyc, const double* trig, double* c, double* s) {
+  const double t = cyc * (double)kFdTrigSteps;  // exact
+  const double kf = rint(t);
+  const double x = (t - kf) * (kTwoPi / kFdTrigSteps);  // t - kf is exact
+  const double x2 = x * x;
+  const double sx = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
+  const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  // a NaN phase converts to some k; the index stays inside the table
+  const int k = min(max((int)kf + kFdTrigSteps / 2, 0), kFdTrigSteps);
+  const double ck = trig[2 * k], sk = trig[2 * k + 1];
+  *c = fma(ck, cx, -(sk * sx));
+  *s = fma(sk, cx, ck * sx);
+}
+
+__device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, const double* trig,
+                                        int lane) {
   Env e = envelope_amp(s, g);
   // phase in cycles, reduced before the product with 2 pi
   double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
                (double)(s.q & (kNs - 1)) * (double)lane / (double)kNs + s.cyc0;
   cyc -= rint(cyc);
-  sincospi(2.0 * cyc, &e.sph, &e.cph);
+  cis_cycles(cyc, trig, &e.cph, &e.sph);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     e.zr[c] = 0.5 * (e.ar[c] * e.cph - e.ai[c] * e.sph);
@@ -469,8 +553,9 @@ __device__ __forceinline__ double wave_sum(double v, int lane) {
 // The source's window spectrum (times T_obs / 64) across the wave: lane L
 // holds bin q - 32 + bin_lane(L).
 __device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* tw,
-                                                double scale, int lane, double re[2], double im[2]) {
-  const Env e = envelope(s, g, lane);
+                                                const double* trig, double scale, int lane,
+                                                double re[2], double im[2]) {
+  const Env e = envelope(s, g, trig, lane);
   const double sg = (lane & 1) ? -scale : scale;  // (-1)^j centres the window on q
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -500,6 +585,7 @@ __device__ __forceinline__ void window_at(const double re[2], const double im[2]
 struct FdSide {
   const double* data;
   const double* tw;  // twiddles in LDS, forward then inverse
+  const double* trig;  // phase table in LDS
   LaneGeom g;        // this lane's grid constants in LDS
   int64_t k0, B;
   double T_obs, scale, cnorm;
@@ -507,11 +593,11 @@ struct FdSide {
 };
 
 __device__ __forceinline__ FdSide own_side(const PopArgs& a, const FdTables& t, int lane) {
-  return {a.fd_data, t.tw, LaneGeom{&t.geo[0][0][lane]}, a.fd_k0, a.fd_B, a.fd_T_obs, a.fd_scale,
-          a.inv_sigma2, kQOwn};
+  return {a.fd_data, t.tw, t.trig, LaneGeom{t.geo[0] + lane}, a.fd_k0, a.fd_B, a.fd_T_obs,
+          a.fd_scale, a.inv_sigma2, kQOwn};
 }
 __device__ __forceinline__ FdSide partner_side(const PopArgs& a, const FdTables& t, int lane) {
-  return {a.fd2_data, t.tw, LaneGeom{&t.geo[1][0][lane]}, a.fd2_k0, a.fd2_B, a.fd2_T_obs,
+  return {a.fd2_data, t.tw, t.trig, LaneGeom{t.geo[1] + lane}, a.fd2_k0, a.fd2_B, a.fd2_T_obs,
           a.fd2_T_obs / 64.0, a.fd2_cnorm, kQPartner};
 }
 
@@ -522,32 +608,35 @@ struct Resid {
 
 template <int NR>
 __device__ __forceinline__ void load_resid(const FdSide& sd, int lane, Resid<NR>& R) {
-  const int Bp = kNs * NR;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int b = lane + kNs * r;
-      R.re[c][r] = sd.data[(c * Bp + b) * 2];
-      R.im[c][r] = sd.data[(c * Bp + b) * 2 + 1];
+      R.re[c][r] = sd.data[(c * kFdBandStride + b) * 2];
+      R.im[c][r] = sd.data[(c * kFdBandStride + b) * 2 + 1];
     }
 }
 
+// R -= sign h over the band (sign = +-1). Each band bin takes the window
+// value from the lane holding it, weighted by sign where the bin lies in both
+// the window and the band and by 0 elsewhere: one FMA per value, which
+// rounds as R - sign v.
 template <int NR>
 __device__ __forceinline__ void subtract_source(const FdSide& sd, const Src& s, const LaneGeom& g,
                                                 int lane, Resid<NR>& R, double sign) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.tw, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.tw, sd.trig, sd.scale, lane, re, im);
+  const int64_t lo = s.q - kNs / 2 - sd.k0;  // band index of window bin 0
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const int64_t b = lane + kNs * r;
-    double vr[2], vi[2];
-    window_at(re, im, sd.k0 + b, s.q, vr, vi);
-    const bool live = b < sd.B;
+    const int64_t b = lane + kNs * r, m = b - lo;
+    const double f = (m >= 0 && m < kNs && b < sd.B) ? -sign : 0.0;
+    const int from = bin_lane((int)(m & (kNs - 1)));
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      R.re[c][r] -= live ? sign * vr[c] : 0.0;
-      R.im[c][r] -= live ? sign * vi[c] : 0.0;
+      R.re[c][r] = fma(f, __shfl(re[c], from), R.re[c][r]);
+      R.im[c][r] = fma(f, __shfl(im[c], from), R.im[c][r]);
     }
   }
 }
@@ -557,7 +646,7 @@ template <int NR>
 __device__ __forceinline__ void overlap(const FdSide& sd, const Src& s, const LaneGeom& g, int lane,
                                         const Resid<NR>& R, double* rh, double* hh) {
   double re[2], im[2];
-  window_spectrum(s, g, sd.tw, sd.scale, lane, re, im);
+  window_spectrum(s, g, sd.tw, sd.trig, sd.scale, lane, re, im);
   double x = 0.0, y = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -627,7 +716,13 @@ __device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g
 // derivatives are linear in (dP, dX), which are bilinear in the detector
 // tensor D_c, so with the weights alpha, beta that the polarisation angle and
 // the amplitudes give dP and dX they contract to 2 n.D y1 (latitude) and
-// 2 (ul.D y1 + vl.D y2) (longitude), y1 = alpha u + beta v, y2 = beta u - alpha v.
+// 2 (ul.D y1 + vl.D y2) (longitude), y1 = alpha u + beta v, y2 = beta u - alpha v,
+// ul = sin(b) v and vl = -(cos(b) n + sin(b) u) the derivatives of u and v
+// with respect to the longitude. With D symmetric these reduce to two new
+// forms per channel, n.D u and n.D v, and the patterns P and X of the
+// envelope:
+//   latitude:  2 (alpha n.D u + beta n.D v)
+//   longitude: 2 (alpha (sin(b) X + cos(b) n.D v) - beta (sin(b) P + cos(b) n.D u)).
 __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
                                            const double wr[2], const double wi[2], double gp[8]) {
   const double Ap = s.Ap, Ax = s.Ax;
@@ -655,22 +750,19 @@ __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, cons
   gp[6] = -2.0 * s.A * s.si * t6;
   gp[7] = G;
   // the sky derivatives, one channel at a time (the barrier keeps the two
-  // channels' temporaries from being live together); v, ul and vl have no z
-  // component
+  // channels' temporaries from being live together)
   const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
-  const double vx = -s.sl, vy = s.cl;
-  const double ulx = -s.sb * s.sl, uly = s.sb * s.cl, vlx = -s.cl, vly = -s.sl;
+  static constexpr int kVx[5] = {0, 1, 3, 4, 5};  // the tensor entries of the n.D v weights
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const double al = kPa * ur[c] + kXa * ui[c], be = kPb * ur[c] - kXb * ui[c];
-    const V3 y1 = {al * s.u.x + be * vx, al * s.u.y + be * vy, al * s.u.z};
-    const V3 y2 = {be * s.u.x - al * vx, be * s.u.y - al * vy, be * s.u.z};
-    double D[6];
+    double nDu = 0.0, nDv = 0.0;
 #pragma unroll
-    for (int x = 0; x < 6; ++x) D[x] = g.d(c, x);
-    const V3 Dy1 = mul_sym(D, y1), Dy2 = mul_sym(D, y2);
-    gp[3] += 2.0 * dot3(s.n, Dy1);
-    gp[4] += 2.0 * ((ulx * Dy1.x + uly * Dy1.y) + (vlx * Dy2.x + vly * Dy2.y));
+    for (int x = 0; x < 6; ++x) nDu = fma(s.wnu[x], g.d(c, x), nDu);
+#pragma unroll
+    for (int x = 0; x < 5; ++x) nDv = fma(s.wnv[x], g.d(c, kVx[x]), nDv);
+    gp[3] += 2.0 * (al * nDu + be * nDv);
+    gp[4] += 2.0 * (al * (s.sb * e.X[c] + s.cb * nDv) - be * (s.sb * e.P[c] + s.cb * nDu));
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -701,14 +793,23 @@ __device__ __forceinline__ bool fd_active_at(const PopArgs& a, int64_t rank, FdI
   return fd_item_at(a, rank, it) && !(a.active && !a.active[it.i]);
 }
 
+// A wave's residual copy in LDS (the gradient pass): four rows (re, im of
+// A, re, im of E) of kNs NR band bins and one zero word that gathers from
+// outside the band read.
+template <int NR>
+constexpr int resid_row() { return kNs * NR + 2; }
+template <int NR>
+constexpr int resid_words() { return 4 * resid_row<NR>(); }
+
 // One particle on one data set, weighted by w; the first side writes the
 // outputs, a second one adds to them, and the leapfrog kick (p_half set)
-// follows the last side's gradient.
+// follows the last side's gradient. rl: the wave's residual copy in LDS
+// (MODE 1).
 template <int MODE, int NR>
 __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, const FdItem& it,
                                             int lane, double w, bool first, bool last,
-                                            const double* __restrict__ src, int k_first = 0,
-                                            int k_step = 1) {
+                                            const double* __restrict__ src, double* rl,
+                                            int k_first = 0, int k_step = 1) {
   const int64_t i = it.i;
   const double wc = w * sd.cnorm;  // weight * 4 / (T_obs S)
   const LaneGeom g = sd.g;
@@ -716,7 +817,13 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
   load_resid<NR>(sd, lane, R);
   for (int k = 0; k < it.K; ++k) {
     const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
-    subtract_source<NR>(sd, src_load(src + (int64_t)row * kSrcWords, sd.qslot), g, lane, R, 1.0);
+    // the lane index, opaque in each pass, so that the lane's grid constants
+    // are read from LDS for every source instead of held in 30 registers
+    // through the loop
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const LaneGeom gk{g.g + (ln - lane)};
+    subtract_source<NR>(sd, src_load(src + (int64_t)row * kSrcWords, sd.qslot), gk, lane, R, 1.0);
   }
   if constexpr (MODE == 2) {
     if (a.theta_birth && a.dlogl_birth) {
@@ -755,30 +862,32 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
   if constexpr (MODE == 1) {
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
     const int lr = bin_lane(lane);
+    // The residual goes to the wave's LDS copy ([re, im of A, re, im of E]
+    // [band position]); the loop gathers each source's window from there,
+    // and its registers are free for the adjoint.
+    constexpr int Bp = kNs * NR, rs = resid_row<NR>();
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        rl[(2 * c) * rs + lane + kNs * r] = R.re[c][r];
+        rl[(2 * c + 1) * rs + lane + kNs * r] = R.im[c][r];
+      }
+    if (lane < 4) rl[lane * rs + Bp] = 0.0;
+    wave_lds_sync();
     for (int k = k_first; k < it.K; k += k_step) {
       const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
       const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
       // residual window of the source in the inverse transform's input order
-      // The window covers 64 consecutive band positions, one per residue
-      // mod 64, so the lane holding a position's residual picks the register
-      // before the exchange: position bp = lane (mod 64) in the window.
       const int64_t lo = s.q - kNs / 2 - sd.k0;  // band index of window bin 0
-      const int regp = (int)((lo + ((lane - lo) & (kNs - 1))) >> 6);
       const int64_t bw = lo + lr;  // band index this lane gathers
-      const bool in = bw >= 0 && bw < sd.B;
-      const int src = (int)(bw & (kNs - 1));
+      const int bi = bw >= 0 && bw < sd.B ? (int)bw : Bp;  // the zero word outside the band
       double wr[2], wi[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        double pr = R.re[c][0], pi = R.im[c][0];
-#pragma unroll
-        for (int r = 1; r < NR; ++r) {
-          pr = regp == r ? R.re[c][r] : pr;
-          pi = regp == r ? R.im[c][r] : pi;
-        }
-        const double vr = __shfl(pr, src), vi = __shfl(pi, src);
-        wr[c] = in ? vr : 0.0;
-        wi[c] = in ? vi : 0.0;
+        wr[c] = rl[(2 * c) * rs + bi];
+        wi[c] = rl[(2 * c + 1) * rs + bi];
       }
       fft_inv(wr, wi, sd.tw + 6 * 128, lane);
       // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
@@ -791,7 +900,7 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
         }
       }
       // Re(conj(w) dz) per parameter
-      const Env e = envelope(s, g, lane);
+      const Env e = envelope(s, g, sd.trig, lane);
       double gp[8];
       grad_terms(s, g, e, wr, wi, gp);
       // lane 8p ends with parameter p's total
@@ -812,16 +921,16 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
 // data sets.
 template <int MODE, int NR>
 __device__ __forceinline__ void fd_run(const PopArgs& a, const FdTables& tabs, const FdItem& it,
-                                       int lane, const double* __restrict__ src, int k_first,
-                                       int k_step) {
+                                       int lane, const double* __restrict__ src, double* rl,
+                                       int k_first, int k_step) {
   const double b = a.beta ? a.beta[it.i] : 1.0;
   if (a.fd_bridge) {
     fd_particle<MODE, NR>(a, partner_side(a, tabs, lane), it, lane, 1.0 - b, true, false, src,
-                          k_first, k_step);
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, src, k_first,
+                          rl, k_first, k_step);
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, false, true, src, rl, k_first,
                           k_step);
   } else {
-    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, src, k_first,
+    fd_particle<MODE, NR>(a, own_side(a, tabs, lane), it, lane, b, true, true, src, rl, k_first,
                           k_step);
   }
 }
@@ -837,15 +946,16 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __rest
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   const int64_t n = fd_count(a);
-  __shared__ FdTables tabs;
+  FdTables tabs;
   FdItem it;
   if constexpr (!STRIDED) {
     const int64_t rank = (int64_t)blockIdx.x * waves + wave;
     const bool work = rank < n && fd_active_at(a, rank, it);
     // a workgroup without an active particle leaves at once
     if (!__syncthreads_or(work)) return;
-    stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
-    if (work) fd_run<MODE, NR>(a, tabs, it, lane, src, 0, 1);
+    double* rl = stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr) +
+                 wave * resid_words<NR>();
+    if (work) fd_run<MODE, NR>(a, tabs, it, lane, src, rl, 0, 1);
   } else {
     // Few listed particles (late NUTS leaves): the waves of a workgroup
     // share one particle. Each builds the whole residual and takes every
@@ -866,14 +976,15 @@ __global__ __launch_bounds__(256) void fd_kernel(PopArgs a, const double* __rest
       have = rank < n && fd_active_at(a, rank, it);
     }
     if (!__syncthreads_or(have)) return;
-    stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
+    double* rl = stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr) +
+                 wave * resid_words<NR>();
     while (have) {
       // the lane index, opaque to the compiler in each pass: nothing derived
       // from it (table addresses, lane geometry) stays live from one
       // particle to the next, which would cost a wave per SIMD
       int ln = lane;
       asm volatile("" : "+v"(ln));
-      fd_run<MODE, NR>(a, tabs, it, ln, src, k_first, k_step);
+      fd_run<MODE, NR>(a, tabs, it, ln, src, rl, k_first, k_step);
       have = false;
       for (; r0 < n && !have; r0 += stride) {
         const int64_t rank = split ? r0 : r0 + wave;
@@ -899,7 +1010,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                                                         int blocks) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  __shared__ FdTables tabs;
+  FdTables tabs;
   stage_tables(tabs, a.fd_table, a.fd_bridge ? a.fd2_table : nullptr);
   if (i >= a.N) return;
   const int64_t o0 = a.offsets[i], o1 = a.offsets[i + 1];
@@ -963,7 +1074,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 // The band spectrum of K sources (out [2][B][2]): one wave.
 __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, double* out) {
   const int lane = threadIdx.x;
-  __shared__ FdTables tabs;
+  FdTables tabs;
   stage_tables(tabs, a.fd_table, nullptr);
   const FdSide sd = own_side(a, tabs, lane);
   Resid<4> R;
@@ -995,11 +1106,6 @@ __global__ __launch_bounds__(64) void fd_spectrum_kernel(PopArgs a, int64_t K, d
 // thread per particle measured slower in late NUTS leaves, where few
 // particles are active. The cost follows the active set.
 constexpr int kSrcGroup = 16;
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __global__ __launch_bounds__(256) void fd_src_kernel(PopArgs a, double T2) {
   // The rows of a group's particle are contiguous ([K][34] doubles): each
@@ -1070,16 +1176,23 @@ hipError_t launch_fd_mode(const PopArgs& a, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   const dim3 block(256);
-  if (MODE == 1 && a.stride_grid && a.fd_B <= 2 * kNs) {
+  const bool br = a.fd_bridge != 0;
+  // two band bins per lane cover up to 128 bins; the wider of two bridged
+  // bands decides
+  const bool nr2 = a.fd_B <= 2 * kNs && !(br && a.fd2_B > 2 * kNs);
+  // LDS bytes: the tables, and for the gradient a residual copy per wave
+  const size_t lds2 = 8 * fd_lds_words(br, 4, MODE == 1 ? resid_words<2>() : 0);
+  const size_t lds4 = 8 * fd_lds_words(br, 4, MODE == 1 ? resid_words<4>() : 0);
+  if (MODE == 1 && a.stride_grid && nr2) {
     // three workgroups fit a compute unit at once: two rounds of them
-    hipLaunchKernelGGL((fd_kernel<1, 2, true>), dim3(fd_grid(a, 4, 6)), block, 0, st, a, a.fd_src);
+    hipLaunchKernelGGL((fd_kernel<1, 2, true>), dim3(fd_grid(a, 4, 6)), block, lds2, st, a, a.fd_src);
     return hipGetLastError();
   }
   const dim3 grid((unsigned)((a.N + 3) / 4));
-  if (a.fd_B <= 2 * kNs)
-    hipLaunchKernelGGL((fd_kernel<MODE, 2, false>), grid, block, 0, st, a, a.fd_src);
+  if (nr2)
+    hipLaunchKernelGGL((fd_kernel<MODE, 2, false>), grid, block, lds2, st, a, a.fd_src);
   else
-    hipLaunchKernelGGL((fd_kernel<MODE, 4, false>), grid, block, 0, st, a, a.fd_src);
+    hipLaunchKernelGGL((fd_kernel<MODE, 4, false>), grid, block, lds4, st, a, a.fd_src);
   return hipGetLastError();
 }
 
@@ -1107,14 +1220,16 @@ hipError_t launch_fd_metric(const PopArgs& a, const int64_t* f_offsets, int64_t 
   all.stride_grid = 0;
   hipError_t e = launch_src_pass(all, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256), 0, st, a, a.fd_src,
-                     f_offsets, f_size, F, blocks);
+  hipLaunchKernelGGL(fd_metric_kernel, dim3((unsigned)((a.N + 3) / 4)), dim3(256),
+                     8 * fd_lds_words(a.fd_bridge != 0, 4, 0), st, a, a.fd_src, f_offsets, f_size, F,
+                     blocks);
   return hipGetLastError();
 }
 
 hipError_t launch_fd_spectrum(const PopArgs& a, int64_t K, double* out, hipStream_t st) {
   if (a.fd_B < 1 || a.fd_B > 4 * kNs) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fd_spectrum_kernel, dim3(1), dim3(64), 0, st, a, K, out);
+  hipLaunchKernelGGL(fd_spectrum_kernel, dim3(1), dim3(64), 8 * fd_lds_words(false, 1, 0), st, a, K,
+                     out);
   return hipGetLastError();
 }
 

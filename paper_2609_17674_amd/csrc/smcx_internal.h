@@ -96,7 +96,7 @@ struct PopArgs {
   void* prof_stop;         // hipEvent_t the launcher records right after the population
                            // kernel (profiling), or nullptr
   // frequency-domain (LISA Galactic-binary) problems
-  const double* fd_data;   // [2][Bp][2] band spectrum of A and E (re, im), Bp = 128 or 256
+  const double* fd_data;   // [2][kFdBandStride][2] band spectrum of A and E (re, im), zero past B
   double* fd_src;           // [M][34] source constants (the handle's workspace)
   const double* fd_table;  // per-lane coarse-grid constants and FFT twiddles
   int64_t fd_k0;           // first bin of the band
@@ -118,15 +118,23 @@ struct PopArgs {
   int64_t fd2_k0, fd2_B;
   double fd2_T_obs, fd2_cnorm;
 };
+// Band spectra are stored at one stride, the largest band (256 bins), so
+// that a kernel sized for the wider of two bridged bands reads either.
+constexpr int kFdBandStride = 256;
+// Doubles per row of the frequency-domain source constants (one row per
+// row of theta).
+constexpr int kFdSrcWords = 46;
 // Layout of fd_table: [64][kFdTableStride] (tensors of A, E; cos, sin of
 // the orbital phase; t_j), then the per-lane twiddles of the six FFT stages,
 // [6][64][2] for the forward transform and [6][64][2] for the inverse (stage
 // s has span 32 >> s; see the transform in the frequency-domain kernels for
-// the lane layout).
+// the lane layout), then [129][2] cos and sin of 2 pi k / 128, k = -64..64.
 constexpr int kFdTableStride = 16;
 constexpr int kFdTwiddleFwd = 64 * kFdTableStride;
 constexpr int kFdTwiddleInv = kFdTwiddleFwd + 6 * 128;
-constexpr int kFdTableSize = kFdTwiddleInv + 6 * 128;
+constexpr int kFdTrig = kFdTwiddleInv + 6 * 128;
+constexpr int kFdTrigSteps = 128;
+constexpr int kFdTableSize = kFdTrig + 2 * (kFdTrigSteps + 1);
 
 // Sort particles by K (descending) and settle K = 0 / invalid particles.
 struct PrepArgs {

@@ -39,6 +39,20 @@ __device__ __forceinline__ void step(float (&x)[kChains], double (&y)[kChains],
       x[k] = __builtin_fmaf(b, c, x[k]);  // accumulator form: v_fmac_f32
     } else if constexpr (OP == SMCX_PROBE_ADD_F32) {
       x[k] = x[k] + b;
+    } else if constexpr (OP == SMCX_PROBE_MUL_F64) {
+      y[k] = y[k] * bd;
+    } else if constexpr (OP == SMCX_PROBE_ADD_F64) {
+      y[k] = y[k] + bd;
+    } else if constexpr (OP == SMCX_PROBE_DPP) {
+      // v_mov_b32 with a row rotation by one lane: the value walks round its row
+      u[k] = (unsigned)__builtin_amdgcn_mov_dpp((int)u[k], 0x121, 0xF, 0xF, false);
+    } else if constexpr (OP == SMCX_PROBE_PERMLANE32) {
+      // v_permlane32_swap_b32 between chains k and k + 1 (counted once per pair)
+      if ((k & 1) == 0) {
+        const auto r = __builtin_amdgcn_permlane32_swap(u[k], u[k + 1], false, false);
+        u[k] = r[0];
+        u[k + 1] = r[1];
+      }
     } else if constexpr (OP == SMCX_PROBE_SIN_4FMA) {
       // one transcendental and four FP32 FMAs (accumulator form) per chain
       // step: whether the transcendental unit overlaps with the FP32 issue
@@ -89,7 +103,8 @@ extern "C" int smcx_issue_probe(int op, int32_t blocks, int32_t iters, const flo
                                 float* out, int64_t* lane_ops, void* hip_stream) {
   if (blocks < 1 || iters < 1) return smcx::set_error(SMCX_EINVAL, "blocks and iters must be >= 1");
   if (!in || !out || !lane_ops) return smcx::set_error(SMCX_EINVAL, "a pointer is NULL");
-  const int64_t per_step = op == SMCX_PROBE_SIN_4FMA ? 5 : 1;
+  // lane-instructions per chain and step, times two
+  const int64_t per_step2 = op == SMCX_PROBE_SIN_4FMA ? 10 : op == SMCX_PROBE_PERMLANE32 ? 1 : 2;
   hipStream_t st = (hipStream_t)hip_stream;
   hipError_t e;
   switch (op) {
@@ -103,9 +118,13 @@ extern "C" int smcx_issue_probe(int op, int32_t blocks, int32_t iters, const flo
     case SMCX_PROBE_SIN_4FMA: e = launch<SMCX_PROBE_SIN_4FMA>(blocks, iters, in, out, st); break;
     case SMCX_PROBE_FMAC_F32: e = launch<SMCX_PROBE_FMAC_F32>(blocks, iters, in, out, st); break;
     case SMCX_PROBE_ADD_F32: e = launch<SMCX_PROBE_ADD_F32>(blocks, iters, in, out, st); break;
+    case SMCX_PROBE_MUL_F64: e = launch<SMCX_PROBE_MUL_F64>(blocks, iters, in, out, st); break;
+    case SMCX_PROBE_ADD_F64: e = launch<SMCX_PROBE_ADD_F64>(blocks, iters, in, out, st); break;
+    case SMCX_PROBE_DPP: e = launch<SMCX_PROBE_DPP>(blocks, iters, in, out, st); break;
+    case SMCX_PROBE_PERMLANE32: e = launch<SMCX_PROBE_PERMLANE32>(blocks, iters, in, out, st); break;
     default: return smcx::set_error(SMCX_EINVAL, "unknown probe %d", op);
   }
   if (e != hipSuccess) return smcx::set_error(SMCX_EDEVICE, "probe launch: %s", hipGetErrorString(e));
-  *lane_ops = (int64_t)blocks * 256 * iters * kReps * kChains * per_step;
+  *lane_ops = (int64_t)blocks * 256 * iters * kReps * kChains * per_step2 / 2;
   return SMCX_OK;
 }

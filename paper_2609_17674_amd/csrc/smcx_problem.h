@@ -31,7 +31,7 @@ struct smcx_problem {
   bool fd = false;
   int64_t fd_k0 = 0, fd_B = 0;
   double fd_T_obs = 0, fd_S = 0;
-  double* fd_data = nullptr;   // [2][Bp][2], Bp = 128 or 256, zero past B
+  double* fd_data = nullptr;   // [2][kFdBandStride][2], zero past B
   double* fd_src = nullptr;    // [m_max][34] source constants, rewritten by every launch
   double* fd_table = nullptr;  // kFdTableSize doubles
   smcx_problem* partner = nullptr;  // bridge partner (smcx_set_bridge_partner), or none
@@ -47,6 +47,7 @@ struct smcx_problem {
   double* part_g = nullptr; // [nch_grad][m_max][P]
   double* rbuf = nullptr;   // plain form residual [T]
   double* bpart = nullptr;  // plain form block partials
+  size_t ws_bytes = 0;      // device workspace this handle holds (all of the above and below)
   // NUTS workspace (smcx_nuts_reserve)
   int nuts_depth = 0;
   double* nuts_vec = nullptr;      // [nuts_slots][m_max * P] per-row state vectors

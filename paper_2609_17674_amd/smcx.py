@@ -307,7 +307,8 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
 
 
 PROBE_KINDS = {"fma_f32": 0, "mul_f32": 1, "exp_f32": 2, "sin_f32": 3, "fma_f64": 4,
-               "add_u32": 5, "cvt": 6, "sin_4fma": 7, "fmac_f32": 8, "add_f32": 9}
+               "add_u32": 5, "cvt": 6, "sin_4fma": 7, "fmac_f32": 8, "add_f32": 9,
+               "mul_f64": 10, "add_f64": 11, "dpp_mov": 12, "permlane32_swap": 13}
 
 
 def issue_probe(kind: str, blocks: int, iters: int, inp: torch.Tensor, out: torch.Tensor,
@@ -705,12 +706,16 @@ class LogLGrad(torch.autograd.Function):
     forward(theta [M,P], offsets [N+1], beta [N] or None, prob) -> logl [N]
     runs the fused forward + adjoint kernel once and keeps the gradient; the
     backward pass only applies the chain rule, scaling each particle's rows
-    by the incoming gradient of its log-likelihood.
+    by the incoming gradient of its log-likelihood. When theta does not need
+    a gradient (no_grad, or requires_grad False) only the forward kernel runs.
     """
 
     @staticmethod
     def forward(ctx, theta, offsets, beta, prob):
-        logl, grad = logl_grad_batch(prob, offsets, theta.detach().contiguous(), beta)
+        th = theta.detach().contiguous()
+        if not ctx.needs_input_grad[0]:
+            return logl_batch(prob, offsets, th, beta)
+        logl, grad = logl_grad_batch(prob, offsets, th, beta)
         ctx.save_for_backward(grad, offsets)
         return logl
 

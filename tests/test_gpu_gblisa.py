@@ -458,6 +458,49 @@ def test_bridge_between_two_records(lib, orc):
         p2.set_bridge_partner(p2)
 
 
+@pytest.mark.parametrize("B_own,B_partner", [(128, 128), (200, 96), (96, 200)],
+                         ids=["same", "wide_own", "wide_partner"])
+def test_bridge_bands_of_different_widths(lib, orc, B_own, B_partner):
+    """A bridge whose two bands differ in width, also across the 128-bin
+    line where the kernels go from two to four band bins per lane: the
+    launch is sized for the wider band and reads either side's data. logL,
+    gradient and birth/death against the oracle."""
+    w = wl.make_gblisa(N=120, k_lo=0, k_hi=6, n_inj=4, beta="uniform", noise=False, seed=421)
+    say("gblisa_bridge_widths", B_own, B_partner)
+    T2, T1 = w.T_obs, w.T_obs / 2
+    k2, k1 = wl.gblisa_band(T2, B_own), wl.gblisa_band(T1, B_partner)
+    d2 = orc.gblisa_spectrum(w.inj, T2, k2, B_own)
+    d1 = orc.gblisa_spectrum(w.inj, T1, k1, B_partner)
+    p2 = lib.Problem.frequency_domain(GBLISA, dev(d2), k2, T2, w.S, w.k_max, w.N, max(w.M, 1))
+    p1 = lib.Problem.frequency_domain(GBLISA, dev(d1), k1, T1, w.S, w.k_max, w.N, max(w.M, 1))
+    p2.set_bridge_partner(p1)
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l, g = lib.logl_grad_batch(p2, off, th, be)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(p2, off, th, be, dev(tb), dev(di))
+    torch.cuda.synchronize()
+    p2.device_status()
+    l, g, db, dd = (x.cpu().numpy() for x in (l, g, db, dd))
+    b = w.beta
+    one = np.ones(w.N)
+    r1l, r1g = orc.gblisa_logl_grad(d1, k1, T1, w.S, w.offsets, w.theta, one)
+    r2l, r2g = orc.gblisa_logl_grad(d2, k2, T2, w.S, w.offsets, w.theta, one)
+    assert np.all(np.abs(l - ((1 - b) * r1l + b * r2l)) <= 1e-9 * (np.abs(r1l) + np.abs(r2l)))
+    rows = np.repeat(np.arange(w.N), w.K)
+    rg = (1 - b[rows])[:, None] * r1g + b[rows][:, None] * r2g
+    for i in range(w.N):
+        a, c = w.offsets[i], w.offsets[i + 1]
+        if a == c:
+            continue
+        scale = np.linalg.norm((np.abs(r1g[a:c]) + np.abs(r2g[a:c])) / NAT)
+        assert np.linalg.norm((g[a:c] - rg[a:c]) / NAT) <= 1e-7 * scale, i
+    b1, dd1 = orc.gblisa_delta(d1, k1, T1, w.S, w.offsets, w.theta, one, tb, di)
+    b2, dd2 = orc.gblisa_delta(d2, k2, T2, w.S, w.offsets, w.theta, one, tb, di)
+    sc = np.abs(b1) + np.abs(b2) + np.abs(dd1) + np.abs(dd2) + 1.0
+    assert np.all(np.abs(db - ((1 - b) * b1 + b * b2)) <= 1e-9 * sc)
+    assert np.all(np.abs(dd - ((1 - b) * dd1 + b * dd2)) <= 1e-9 * sc)
+
+
 def test_block_diagonal_factor(lib, orc):
     """block = 8: the factor of the block-diagonal part of each metric block,
     which equals the oracle's full factor of that part (exact zeros between

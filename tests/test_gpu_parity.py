@@ -311,6 +311,40 @@ def test_host_argument_errors(lib):
         lib.reweight_extend(s.prob, 0, w.T + 1, s.off, s.th, 0.1)
 
 
+def test_workspace_cap(lib, orc, monkeypatch):
+    """SMCX_WORKSPACE_MAX: a create or NUTS reserve whose workspace would
+    exceed it returns SMCX_ENOMEM and allocates nothing; an existing handle
+    keeps working, also after a refused reserve."""
+    w = wl.make_config("pulse_small", N=16, k_lo=1, k_hi=5)
+    say("workspace_cap")
+    monkeypatch.setenv("SMCX_WORKSPACE_MAX", "4k")
+    with pytest.raises(lib.SmcxError) as ei:
+        Setup(lib, w)
+    assert ei.value.code == lib.SMCX_ENOMEM and "SMCX_WORKSPACE_MAX" in str(ei.value)
+    monkeypatch.setenv("SMCX_WORKSPACE_MAX", "lots")
+    with pytest.raises(lib.SmcxError) as ei:
+        Setup(lib, w)
+    assert ei.value.code == lib.SMCX_EINVAL
+    monkeypatch.setenv("SMCX_WORKSPACE_MAX", "1g")
+    s = Setup(lib, w, m_max=4096)  # room for a deep NUTS workspace to be refused
+    lib.nuts_reserve(s.prob, 2)
+    monkeypatch.setenv("SMCX_WORKSPACE_MAX", str(1 << 20))
+    with pytest.raises(lib.SmcxError) as ei:
+        lib.nuts_reserve(s.prob, 10)   # 36 slots of 4096 x 3 doubles: 3.4 MiB
+    assert ei.value.code == lib.SMCX_ENOMEM
+    monkeypatch.delenv("SMCX_WORKSPACE_MAX")
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+    # the depth reserved before the refusal is still there
+    mom, dirs, ul, ut = wl.nuts_draws(w.N, w.M, 3, 2, seed=8)
+    lib.nuts_transition(s.prob, s.off, s.beta, 1e-4, 2, s.th, pm.to_dev(ref_l), pm.to_dev(ref_g),
+                        pm.to_dev(mom), pm.to_dev(dirs), pm.to_dev(ul), pm.to_dev(ut))
+    torch.cuda.synchronize()
+    s.prob.device_status()
+
+
 # ---------------------------------------------------------------- birth / death
 @pytest.mark.parametrize("cfg,ov", [("pulse_mutate", dict(N=300, T=4096)),
                                     ("pulse_mutate", dict(N=64, T=9000)),
@@ -438,6 +472,15 @@ def test_autograd_function(lib, orc):
     _, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
     rows = np.repeat(wts.cpu().numpy(), w.K)[:, None]
     pm.assert_grad(w.model, w.offsets, w.theta, th.grad.cpu().numpy(), ref_g * rows, w.T, w.dt)
+    # without a gradient wanted, the forward kernel alone gives the same logL
+    with torch.no_grad():
+        l2 = lib.LogLGrad.apply(th, s.off, s.beta, s.prob)
+    l3 = lib.LogLGrad.apply(s.th, s.off, s.beta, s.prob)
+    torch.cuda.synchronize()
+    assert not l3.requires_grad
+    ref_l = orc.logl(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    for x in (logl.detach(), l2, l3):
+        pm.assert_logl(x.cpu().numpy(), ref_l)
 
 
 # ---------------------------------------------------------------- full-size workloads
