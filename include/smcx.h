@@ -420,7 +420,10 @@ int smcx_nuts_transition_metric_blocks(smcx_problem* prob, int64_t N, const int6
  *              create (at most min(64, ceil(T/1024)) chunks, and for GRAD
  *              with more than one chunk at most min(32, ceil(T/4096)))
  *   sorted     1: an ordering pass schedules particles longest-K first;
- *              0: particles are scheduled in index order
+ *              0: particles are scheduled in index order; 2: longest-K first
+ *              on a persistent grid (SMCX_KIND_LOGL and SMCX_KIND_GRAD: as
+ *              many workgroups as the device holds at once, each wave taking
+ *              the work items at a fixed stride; SMCX_KIND_DELTA runs as 1)
  * The tiling fixes the summation order inside a particle, so results are
  * bitwise reproducible for a fixed tiling (and independent of N and of the
  * other particles), and change only within rounding when it changes. The

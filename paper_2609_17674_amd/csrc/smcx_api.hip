@@ -235,6 +235,8 @@ smcx::PopArgs base_args(smcx_problem* p, int64_t N, const int64_t* offsets, int6
   a.k_max = p->k_max;
   a.m_max = p->m_max;
   a.order = t.sorted ? p->order : nullptr;
+  a.persist = t.sorted == 2;
+  a.n_cu = p->n_cu;
   a.n_active = p->n_active;
   a.nch = t.nch;
   a.chunk_len = t.chunk_len;
@@ -1257,7 +1259,7 @@ int smcx_set_tiling(smcx_problem* p, int32_t kind, int32_t S, int64_t chunk_len,
   if (!s_ok) return fail(SMCX_EINVAL, "S = %d not supported for this call kind", S);
   if (chunk_len <= 0 || chunk_len % (64 * (int64_t)S) != 0)
     return fail(SMCX_EINVAL, "chunk_len must be a positive multiple of 64*S");
-  if (sorted != 0 && sorted != 1) return fail(SMCX_EINVAL, "sorted must be 0 or 1");
+  if (sorted < 0 || sorted > 2) return fail(SMCX_EINVAL, "sorted must be 0, 1 or 2");
   Tiling t;
   t.S = S;
   t.chunk_len = chunk_len;

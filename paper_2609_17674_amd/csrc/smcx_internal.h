@@ -49,7 +49,8 @@ struct Tiling {
   int S;              // samples per lane per tile (8, 16, 32 or 64)
   int64_t chunk_len;  // samples per chunk (multiple of 64*S)
   int nch;            // chunks covering [s_lo, s_hi)
-  int sorted;         // 1: items ordered by K descending (ordering pass), 0: particle order
+  int sorted;         // 1: items ordered by K descending (ordering pass), 0: particle order,
+                      // 2: as 1 on a persistent grid (waves step through the items)
 };
 
 // Arguments of the batched population kernels (forward, fused forward +
@@ -107,6 +108,8 @@ struct PopArgs {
                            // give each particle a whole workgroup (0: never); at most
                            // the launch's workgroups
   int n_cu;                // compute units of the device (grid sizes)
+  int persist;             // 1: the population kernel's grid holds what the device runs
+                           // at once and each wave steps through the work items
   int stride_grid;         // 1: launches whose kernels step through the listed particles
                            // take a fixed grid per compute unit (few listed), 0: a
                            // workgroup per group of particles

@@ -33,6 +33,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace smcx {
@@ -877,16 +878,13 @@ __device__ __forceinline__ void pop_tiles(const PopArgs& a, const typename Model
   }
 }
 
+// One work item of the population kernel (a wave-uniform index).
 template <int MODEL, int S, bool GRAD>
-__global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void pop_kernel(PopArgs a) {
+__device__ __forceinline__ void pop_item(const PopArgs& a, int64_t item, int lane, int wid,
+                                         unsigned char* lds) {
   using M = Model<MODEL>;
   using C = typename M::C;
   constexpr int P = M::P;
-  extern __shared__ __align__(16) unsigned char lds[];
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wpb = blockDim.x >> 6;
-  const int64_t item = (int64_t)blockIdx.x * wpb + wid;
   Item it;
   if (!decode_item(a, item, lane, P, false, it)) return;
   // one wave per item: make the item's fields scalar
@@ -969,6 +967,31 @@ __global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void p
       double* dst = a.part_g + ((size_t)c * a.m_max + m0) * P;
       for (int idx = lane; idx < K * P; idx += 64) dst[idx] = acc[idx];
     }
+  }
+}
+
+// The population kernel: one wave per (particle, chunk) work item, or
+// (PERSIST) a grid of what the device holds at once whose waves take the
+// items at a fixed stride (item w, w + G, ... for wave w of G), which in the
+// longest-K-first order hands each wave a similar share of the work. The
+// two are separate kernels: the loop's state would otherwise raise the
+// register count of the one-item form.
+template <int MODEL, int S, bool GRAD, bool PERSIST>
+__global__ __launch_bounds__(256, (pop_waves_per_simd<MODEL, S, GRAD>())) void pop_kernel(PopArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wpb = blockDim.x >> 6;
+  const int64_t first = (int64_t)blockIdx.x * wpb + wid;
+  if constexpr (!PERSIST) {
+    pop_item<MODEL, S, GRAD>(a, first, lane, wid, lds);
+    return;
+  }
+  const int64_t n = (a.order ? (int64_t)*a.n_active : a.N) * a.nch;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  for (int64_t item = first; item < n; item += stride) {
+    pop_item<MODEL, S, GRAD>(a, item, lane, wid, lds);
+    wave_sync();  // the wave's LDS is reused by its next item
   }
 }
 
@@ -1410,22 +1433,39 @@ int waves_per_block(int model, int32_t k_max, bool grad) {
   return w;
 }
 
+template <int MODEL, int S, bool GRAD>
+const void* pop_fn(bool persist) {
+  return persist ? (const void*)pop_kernel<MODEL, S, GRAD, true>
+                 : (const void*)pop_kernel<MODEL, S, GRAD, false>;
+}
+
 template <int MODEL, bool GRAD>
 hipError_t launch_pop_model(const Tiling& t, const PopArgs& a, hipStream_t st) {
   const int wpb = waves_per_block(MODEL, a.k_max, GRAD);
   const size_t lds = pop_lds_bytes_per_wave(MODEL, a.k_max, GRAD) * wpb;
   const int64_t items = a.N * (int64_t)a.nch;
   if (items == 0) return a.prof_stop ? hipEventRecord((hipEvent_t)a.prof_stop, st) : hipSuccess;
-  const dim3 grid((unsigned)((items + wpb - 1) / wpb));
-  const dim3 block(64 * wpb);
+  int64_t blocks = (items + wpb - 1) / wpb;
+  const void* fn;
   switch (t.S) {
-    case 8: hipLaunchKernelGGL((pop_kernel<MODEL, 8, GRAD>), grid, block, lds, st, a); break;
-    case 16: hipLaunchKernelGGL((pop_kernel<MODEL, 16, GRAD>), grid, block, lds, st, a); break;
-    case 32: hipLaunchKernelGGL((pop_kernel<MODEL, 32, GRAD>), grid, block, lds, st, a); break;
-    case 64: hipLaunchKernelGGL((pop_kernel<MODEL, 64, GRAD>), grid, block, lds, st, a); break;
+    case 8: fn = pop_fn<MODEL, 8, GRAD>(a.persist); break;
+    case 16: fn = pop_fn<MODEL, 16, GRAD>(a.persist); break;
+    case 32: fn = pop_fn<MODEL, 32, GRAD>(a.persist); break;
+    case 64: fn = pop_fn<MODEL, 64, GRAD>(a.persist); break;
     default: return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
+  if (a.persist) {
+    // the workgroups the device holds at once (at least one per unit)
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * wpb, lds);
+    if (e != hipSuccess) return e;
+    blocks = std::min<int64_t>(blocks, (int64_t)std::max(per_cu, 1) * (a.n_cu > 0 ? a.n_cu : 256));
+  }
+  const dim3 grid((unsigned)blocks);
+  const dim3 block(64 * wpb);
+  void* args[] = {const_cast<PopArgs*>(&a)};
+  hipError_t e = hipLaunchKernel(fn, grid, block, args, lds, st);
+  if (e == hipSuccess) e = hipGetLastError();
   if (e == hipSuccess && a.prof_stop) e = hipEventRecord((hipEvent_t)a.prof_stop, st);
   if (e != hipSuccess || a.nch == 1) return e;
   const dim3 fgrid((unsigned)((a.N + 3) / 4));

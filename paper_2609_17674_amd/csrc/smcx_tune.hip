@@ -41,7 +41,9 @@ std::vector<Candidate> candidates(const smcx_problem* p, int kind) {
       const int nch = (int)((p->T + c - 1) / c);
       if (nch > p->max_nch) continue;
       if (kind == kGrad && nch > 1 && nch > p->max_nch_grad) continue;
-      for (int so : {0, 1}) out.push_back({S, c, so});
+      // the persistent grid (2) serves the logL and gradient kernels
+      for (int so : {0, 1, 2})
+        if (so < 2 || kind != kDelta) out.push_back({S, c, so});
     }
   }
   return out;

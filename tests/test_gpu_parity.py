@@ -510,6 +510,30 @@ def test_full_size_grad_sampled(lib, orc, cfg, n_check):
     pm.assert_grad(w.model, sub.offsets, sub.theta, grad[rows], ref_g, w.T, w.dt)
 
 
+@pytest.mark.parametrize("cfg", ["pulse_batch", "gb_grad"])
+def test_persistent_grid_matches_one_wave_per_item(lib, orc, cfg):
+    """The persistent schedule (sorted = 2) at full size, where each wave
+    takes several work items in turn, gives the same bits as one wave per
+    item (sorted = 1): the schedule does not touch a particle's summation
+    order. The one-wave-per-item result is held to the oracle elsewhere."""
+    w = wl.make_config(cfg)
+    say("persistent_grid", cfg, "N", w.N, "T", w.T)
+    s = Setup(lib, w)
+    outs = []
+    for so in (1, 2):
+        for kind in (lib.KIND_GRAD, lib.KIND_LOGL):
+            S, chunk, _ = s.prob.get_tiling(kind)
+            s.prob.set_tiling(kind, S, chunk, so)
+        l, g = run_grad(lib, s)
+        l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+        torch.cuda.synchronize()
+        outs.append((l, g, l2.cpu().numpy()))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
+    items = w.N * -(-w.T // s.prob.get_tiling(lib.KIND_GRAD)[1])
+    assert items > 256 * 16, "the grid must be smaller than the work list"
+
+
 def test_full_size_birth_death_sampled(lib, orc):
     w = wl.make_config("pulse_mutate")
     say("full_size_delta", w.N)
@@ -576,7 +600,7 @@ def test_every_tiling_is_parity_green_and_order_free(lib, orc, cfg, ov):
             tile = 64 * S
             for chunk in (tile, 3 * tile, ((w.T + tile - 1) // tile) * tile):
                 outs = []
-                for so in (0, 1):
+                for so in (0, 1, 2):
                     try:
                         s.prob.set_tiling(kind, S, chunk, so)
                     except lib.SmcxError:
@@ -603,9 +627,9 @@ def test_every_tiling_is_parity_green_and_order_free(lib, orc, cfg, ov):
                         outs.append((db, dd))
                     s.prob.device_status()
                     tested += 1
-                if len(outs) == 2:
-                    for x, y in zip(*outs):
-                        assert np.array_equal(x, y), "sorted and index order must agree bitwise"
+                for other in outs[1:]:
+                    for x, y in zip(outs[0], other):
+                        assert np.array_equal(x, y), "every schedule must agree bitwise"
     assert tested >= 20
 
 
