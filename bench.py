@@ -75,7 +75,8 @@ SLOTS = {(0, "grad"): 12.0, (1, "grad"): 5.0 + 51.0 / 8.0, (0, "fwd"): 5.0, (1, 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("pulse_batch", "64,4096,1"): {"bytes": 1.3154e+07, "kernels_sha1": "dd3c3c7461cc3b10"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4609e+07, "kernels_sha1": "629b5741b3d9d3d7"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3136e+07, "kernels_sha1": "629b5741b3d9d3d7"}}
 
 
 def kernels_sha1():
@@ -192,7 +193,8 @@ def bench_grad(args, w, dev, smcx, np, torch, cpu_seconds, cpu1_seconds, check_a
     value = w.N / (ms * 1e-3)
     log(f"[bench] {w.name}: {ms:.4f} ms/step, pop_kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
     rl = roofline(w.model, "grad", component_samples(w, 0, w.T), kern_ms,
-                  f"pop_kernel<{w.model},{tuned[0]},true> (fused forward+adjoint)")
+                  f"pop_kernel<{w.model},{tuned[0]},true,{'true' if tuned[2] == 2 else 'false'}> "
+                  f"(fused forward+adjoint)")
     pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
     if pmc and pmc["kernels_sha1"] == kernels_sha1():
         rl["traffic"] = pmc["bytes"]
@@ -431,7 +433,9 @@ def bench_smc(args, w, dev, smcx, np, torch):
                 config={"workload": "smc_pulses", "T": w.T, "N": N, "n_injected": len(w.inj),
                         "K_range": [1, k_hi], "alpha": 0.9, "p_moves": [0.6, 0.2, 0.2],
                         "n_mutations": 4, "nuts_max_depth": 6,
-                        "nuts_mass_matrix": "Gauss-Newton metric + prior precision, eps 0.3 whitened",
+                        "nuts_mass_matrix": "per-source Gauss-Newton block averaged over the "
+                                            "population once per mutation step, + prior "
+                                            "precision; eps 0.3 whitened",
                         "prior_start": {"iterations": iters, "seconds": [round(t, 3) for t, _ in runs],
                                         "final_K_hist": runs[-1][1].k_hist[-1],
                                         "log_evidence": [round(r.log_evidence, 2) for _, r in runs],
@@ -613,8 +617,9 @@ def bench_smc_gblisa(args, dev, smcx, np, torch):
                 config={"workload": "smc_gblisa", "T_obs_s": w.T_obs, "bins": w.B, "N": N,
                         "n_injected": 10, "K_range": [1, k_hi], "alpha": 0.9,
                         "p_moves": [0.6, 0.2, 0.2], "n_mutations": 4, "nuts_max_depth": 6,
-                        "nuts_mass_matrix": "per-source Gauss-Newton metric + prior precision, "
-                                            "eps 0.3 whitened",
+                        "nuts_mass_matrix": "per-source Gauss-Newton block averaged over the "
+                                            "population once per mutation step, + prior "
+                                            "precision; eps 0.3 whitened",
                         "iterations": iters, "seconds": [round(t, 3) for t, _ in runs],
                         "final_K_hist": runs[-1][1].k_hist[-1],
                         "log_evidence": [round(r.log_evidence, 2) for _, r in runs],

@@ -434,10 +434,17 @@ __global__ __launch_bounds__(64 * kPoolWaves) void pool_partial_kernel(int PP, i
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rows;
   const int64_t r1 = min(M, r0 + rows);
-  double s = 0.0;
-  if (lane < PP)
-    for (int64_t m = r0 + wid; m < r1; m += kPoolWaves) s += F[m * PP + lane];
-  sh[wid][lane] = s;
+  // four running sums per lane (rows r0 + wid + kPoolWaves (4 j + u) go to
+  // sum u), so that four loads are in flight; combined in a fixed order
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (lane < PP) {
+    int64_t m = r0 + wid;
+    for (; m + 3 * kPoolWaves < r1; m += 4 * kPoolWaves)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += F[(m + u * kPoolWaves) * PP + lane];
+    for (int u = 0; m < r1; m += kPoolWaves, ++u) s[u] += F[m * PP + lane];
+  }
+  sh[wid][lane] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
   if (wid == 0 && lane < PP) {
     double t = sh[0][lane];
@@ -446,13 +453,26 @@ __global__ __launch_bounds__(64 * kPoolWaves) void pool_partial_kernel(int PP, i
   }
 }
 
-__global__ __launch_bounds__(64) void pool_final_kernel(int PP, int G, int64_t M,
-                                                          const double* part, double* out) {
-  const int lane = threadIdx.x;
-  if (lane >= PP) return;
-  double t = 0.0;
-  for (int g = 0; g < G; ++g) t += part[(size_t)g * PP + lane];
-  out[lane] = t / (double)M;
+// The range sums of the G workgroups: 16 waves take every 16th range each,
+// then the first wave adds the 16 wave sums in order.
+constexpr int kFinalWaves = 16;
+__global__ __launch_bounds__(64 * kFinalWaves) void pool_final_kernel(int PP, int G, int64_t M,
+                                                                      const double* part,
+                                                                      double* out) {
+  __shared__ double sh[kFinalWaves][64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double s[2] = {0.0, 0.0};
+  if (lane < PP) {
+    int g = wid, u = 0;
+    for (; g < G; g += kFinalWaves, u ^= 1) s[u] += part[(size_t)g * PP + lane];
+  }
+  sh[wid][lane] = s[0] + s[1];
+  __syncthreads();
+  if (wid == 0 && lane < PP) {
+    double t = sh[0][lane];
+    for (int w = 1; w < kFinalWaves; ++w) t += sh[w][lane];
+    out[lane] = t / (double)M;
+  }
 }
 
 hipError_t launch_metric_factor_blocks(int P, int64_t M, const double* F, const double* ridge,
@@ -489,7 +509,8 @@ hipError_t launch_metric_pool(int P, int64_t M, const double* F, double* F_mean,
                      rows, F, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pool_final_kernel, dim3(1), dim3(64), 0, st, PP, (int)G, M, part, F_mean);
+  hipLaunchKernelGGL(pool_final_kernel, dim3(1), dim3(64 * kFinalWaves), 0, st, PP, (int)G, M, part,
+                     F_mean);
   return hipGetLastError();
 }
 
