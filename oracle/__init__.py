@@ -71,19 +71,24 @@ def build(force: bool = True) -> str:
 
 def build_variant(out_dir: str, edits) -> str:
     """Compile a copy of the oracle with textual edits [(old, new), ...] applied
-    to smcx_oracle.c (each `old` must occur exactly once) into out_dir; for the
-    tests that plant a mistake in the oracle and check that a pin catches it.
-    Returns the library path; load it with bind()."""
-    src = open(_SRC).read()
+    into out_dir: each `old` must occur exactly once in the two sources
+    together (smcx_oracle.c, gblisa_oracle.c) and is replaced where it
+    occurs. For the tests that plant a mistake in the oracle and check that a
+    pin catches it. Returns the library path; load it with bind()."""
+    srcs = {_SRC: open(_SRC).read(), _SRC_GB: open(_SRC_GB).read()}
     for old, new in edits:
-        if src.count(old) != 1:
-            raise ValueError(f"edit target occurs {src.count(old)} times: {old!r}")
-        src = src.replace(old, new)
-    c_path = os.path.join(out_dir, "smcx_oracle_variant.c")
-    with open(c_path, "w") as f:
-        f.write(src)
+        where = [k for k, v in srcs.items() for _ in range(v.count(old))]
+        if len(where) != 1:
+            raise ValueError(f"edit target occurs {len(where)} times: {old!r}")
+        srcs[where[0]] = srcs[where[0]].replace(old, new)
+    paths = []
+    for k, v in srcs.items():
+        c_path = os.path.join(out_dir, "variant_" + os.path.basename(k))
+        with open(c_path, "w") as f:
+            f.write(v)
+        paths.append(c_path)
     out = os.path.join(out_dir, "liboracle_variant.so")
-    _gcc(out, [c_path, _SRC_GB])
+    _gcc(out, paths)
     return out
 
 
