@@ -74,18 +74,48 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the 64 lanes; the total is valid in lane 63. The steps pair lanes
-// within quads, half rows and rows, then carry row sums up with the row
-// broadcasts (rows 1,3 add row 0,2; rows 2,3 add rows 0..1).
-__device__ __forceinline__ float wave_sum_f(float v) {
-  v += dpp_f<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp_f<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp_f<0x141>(v);       // row_half_mirror
-  v += dpp_f<0x140>(v);       // row_mirror
-  v += dpp_f<0x142, 0xA>(v);  // row_bcast:15
-  v += dpp_f<0x143, 0xC>(v);  // row_bcast:31
-  return v;
+// Sum over the 64 lanes (wave_sum_d); the total is valid in lane 63. The
+// steps pair lanes within quads, half rows and rows, then carry row sums up
+// with the row broadcasts (rows 1,3 add row 0,2; rows 2,3 add rows 0..1).
+//
+// Transposed wave sums of four values: one pair stage over lanes (L, L ^ 32)
+// takes two values and leaves one (after the row swap, a + b holds a's pair
+// sums in lanes 0-31 and b's in lanes 32-63), one over (L, L ^ 16) likewise
+// per row pair, then the four row-internal steps (quads, half rows, rows).
+// Row r of the result (lanes 16 r .. 16 r + 15) holds the total of value
+// row_value(r): 0, 2, 1, 3. Three row swaps and four DPP adds instead of
+// four separate six-step sums.
+template <int H>
+__device__ __forceinline__ float pair_sum_f(float a, float b) {
+  const unsigned ua = __builtin_bit_cast(unsigned, a), ub = __builtin_bit_cast(unsigned, b);
+  unsigned x, y;
+  if constexpr (H == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
+    x = r[0];
+    y = r[1];
+  } else {
+    static_assert(H == 16, "row swap span");
+    const auto r = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
+    x = r[0];
+    y = r[1];
+  }
+  // An empty asm (no instruction) makes the second result opaque: this
+  // compiler folds a float sum of the swap's two results into twice the
+  // first (seen in the gfx950 assembly; the FP64 form is not affected).
+  asm volatile("" : "+v"(y));
+  return __builtin_bit_cast(float, x) + __builtin_bit_cast(float, y);
 }
+__device__ __forceinline__ float transposed_sum4_f(float v0, float v1, float v2, float v3) {
+  float t = pair_sum_f<16>(pair_sum_f<32>(v0, v1), pair_sum_f<32>(v2, v3));
+  t += dpp_f<0xB1>(t);   // quad_perm [1,0,3,2]
+  t += dpp_f<0x4E>(t);   // quad_perm [2,3,0,1]
+  t += dpp_f<0x141>(t);  // row_half_mirror
+  t += dpp_f<0x140>(t);  // row_mirror
+  return t;
+}
+// the value whose total row `row` holds after transposed_sum4_f
+__device__ __forceinline__ int row_value(int row) { return ((row & 1) << 1) | (row >> 1); }
+
 __device__ __forceinline__ double wave_sum_d(double v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
@@ -433,14 +463,9 @@ struct Model<SMCX_PULSE> {
       if (groups == 0) continue;  // the component adds nothing on this tile
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2, groups);
-      s0 = wave_sum_f(s0);
-      s1 = wave_sum_f(s1);
-      s2 = wave_sum_f(s2);
-      if (lane == 63) {
-        acc[3 * k + 0] += (double)s0;
-        acc[3 * k + 1] += (double)s1;
-        acc[3 * k + 2] += (double)s2;
-      }
+      // the first lane of rows 0, 1, 2 adds the total of s0, s2, s1
+      const float tot = transposed_sum4_f(s0, s1, s2, 0.f);
+      if ((lane & 15) == 0 && lane < 48) acc[3 * k + row_value(lane >> 4)] += (double)tot;
     }
   }
   // Template values of one component on the tile (for birth/death).
@@ -517,16 +542,9 @@ struct Model<SMCX_GBSINE> {
       // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
       const float b1 = __builtin_fmaf(uf, c0, 64.f * c1);
       const float b2 = __builtin_fmaf(uf * uf, c0, __builtin_fmaf(128.f * uf, c1, 4096.f * c2));
-      as = wave_sum_f(as);
-      c0 = wave_sum_f(c0);
-      const float r1 = wave_sum_f(b1);
-      const float r2 = wave_sum_f(b2);
-      if (lane == 63) {
-        acc[4 * k + 0] += (double)as;
-        acc[4 * k + 1] += (double)c0;
-        acc[4 * k + 2] += (double)r1;
-        acc[4 * k + 3] += (double)r2;
-      }
+      // the first lane of each row adds the total of one of as, c0, b1, b2
+      const float tot = transposed_sum4_f(as, c0, b1, b2);
+      if ((lane & 15) == 0) acc[4 * k + row_value(lane >> 4)] += (double)tot;
     }
   }
   template <int S, bool LIN>
