@@ -463,9 +463,14 @@ struct Model<SMCX_PULSE> {
       if (groups == 0) continue;  // the component adds nothing on this tile
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2, groups);
-      // the first lane of rows 0, 1, 2 adds the total of s0, s2, s1
+      // the first lane of rows 0, 1, 2 adds the total of s0, s2, s1; the
+      // accumulator is read before the sum so that the read overlaps it
+      // (row 3 reads the next entry, which it does not use)
+      double* ap = acc + 3 * k + row_value(lane >> 4);
+      double prev = *ap;
       const float tot = transposed_sum4_f(s0, s1, s2, 0.f);
-      if ((lane & 15) == 0 && lane < 48) acc[3 * k + row_value(lane >> 4)] += (double)tot;
+      asm volatile("" : "+v"(prev));  // keeps the read out of the branch below
+      if ((lane & 15) == 0 && lane < 48) *ap = prev + (double)tot;
     }
   }
   // Template values of one component on the tile (for birth/death).
@@ -542,9 +547,13 @@ struct Model<SMCX_GBSINE> {
       // sample s = u + 64 j:  sum rc s = u c0 + 64 c1,  sum rc s^2 = u^2 c0 + 128 u c1 + 4096 c2
       const float b1 = __builtin_fmaf(uf, c0, 64.f * c1);
       const float b2 = __builtin_fmaf(uf * uf, c0, __builtin_fmaf(128.f * uf, c1, 4096.f * c2));
-      // the first lane of each row adds the total of one of as, c0, b1, b2
+      // the first lane of each row adds the total of one of as, c0, b1, b2;
+      // the accumulator is read before the sum so that the read overlaps it
+      double* ap = acc + 4 * k + row_value(lane >> 4);
+      double prev = *ap;
       const float tot = transposed_sum4_f(as, c0, b1, b2);
-      if ((lane & 15) == 0) acc[4 * k + row_value(lane >> 4)] += (double)tot;
+      asm volatile("" : "+v"(prev));  // keeps the read out of the branch below
+      if ((lane & 15) == 0) *ap = prev + (double)tot;
     }
   }
   template <int S, bool LIN>
