@@ -317,14 +317,16 @@ void fd_table_host(double T_obs, std::vector<double>& tab) {
   }
   // Stage s (span H = 32 >> s) of the transform: lane l's butterfly has index
   // l & (H - 1) in its block, root exp(-2 pi i (l & (H - 1)) (32 / H) / 64).
-  // For H <= 8 the forward root carries the sign of the lane's difference
+  // For H <= 2 the forward root carries the sign of the lane's difference
   // (-1 where bit H of the lane is set); the inverse takes the conjugate.
+  // (The kernels apply the span-1 roots, all 1 up to that sign, without
+  // reading them.)
   for (int st = 0; st < 6; ++st) {
     const int H = 32 >> st;
     for (int l = 0; l < 64; ++l) {
       const int k = (l & (H - 1)) * (32 / H);
       const double c = std::cos(2.0 * kPi * k / 64.0), sn = -std::sin(2.0 * kPi * k / 64.0);
-      const double sg = (H <= 8 && (l & H)) ? -1.0 : 1.0;
+      const double sg = (H <= 2 && (l & H)) ? -1.0 : 1.0;
       tab[smcx::kFdTwiddleFwd + st * 128 + 2 * l] = sg * c;
       tab[smcx::kFdTwiddleFwd + st * 128 + 2 * l + 1] = sg * sn;
       tab[smcx::kFdTwiddleInv + st * 128 + 2 * l] = c;

@@ -277,8 +277,9 @@ __device__ __forceinline__ void cis_cycles(double cyc, const double* trig, doubl
   *s = fma(sk, cx, ck * sx);
 }
 
+// zs: the factor of z (1/2 for the envelope itself).
 __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, const double* trig,
-                                        int lane) {
+                                        int lane, double zs = 0.5) {
   Env e = envelope_amp(s, g);
   // phase in cycles, reduced before the product with 2 pi
   double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
@@ -287,8 +288,8 @@ __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, const d
   cis_cycles(cyc, trig, &e.cph, &e.sph);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    e.zr[c] = 0.5 * (e.ar[c] * e.cph - e.ai[c] * e.sph);
-    e.zi[c] = 0.5 * (e.ar[c] * e.sph + e.ai[c] * e.cph);
+    e.zr[c] = zs * (e.ar[c] * e.cph - e.ai[c] * e.sph);
+    e.zi[c] = zs * (e.ar[c] * e.sph + e.ai[c] * e.cph);
   }
   return e;
 }
@@ -332,6 +333,39 @@ __device__ __forceinline__ double join_words(unsigned lo, unsigned hi) {
   return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
 }
 
+// Half-lane moves at distance H = 4 or 8, where a DPP row shift can write
+// only the lanes of one side (its bank mask selects groups of four lanes):
+// from_above gives the lanes with bit H clear the value src of lane L + H and
+// leaves old in the others; from_below gives the lanes with bit H set src of
+// lane L - H and leaves old in the rest. Two of them make a trade between
+// lane pairs with no select.
+template <int H, bool ABOVE>
+__device__ __forceinline__ double half_move(double old, double src) {
+  static_assert(H == 4 || H == 8, "bank-masked move distance");
+  constexpr int kCtrl = ABOVE ? 0x100 + H : 0x110 + H;  // row_shl:H or row_shr:H
+  constexpr int kBanks = ABOVE ? (H == 8 ? 0x3 : 0x5) : (H == 8 ? 0xC : 0xA);
+  const uint64_t uo = __builtin_bit_cast(uint64_t, old), us = __builtin_bit_cast(uint64_t, src);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)uo, (int)(unsigned)us,
+                                                            kCtrl, 0xF, kBanks, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(uo >> 32),
+                                                            (int)(unsigned)(us >> 32), kCtrl, 0xF,
+                                                            kBanks, false);
+  return join_words(lo, hi);
+}
+template <int H>
+__device__ __forceinline__ double from_above(double old, double src) { return half_move<H, true>(old, src); }
+template <int H>
+__device__ __forceinline__ double from_below(double old, double src) { return half_move<H, false>(old, src); }
+
+// v of lane L - N within the row of 16 lanes (lanes with L mod 16 < N get 0).
+template <int N>
+__device__ __forceinline__ double row_shr(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x110 + N, 0xF, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x110 + N, 0xF, 0xF, true);
+  return join_words(lo, hi);
+}
+
 // Transposed sums: a stage over lane pairs (L, L ^ H) takes two partial sums
 // per lane and leaves one, lanes with bit H clear keeping the first value's
 // pair sum and the others the second's. Each value's total is formed over
@@ -339,7 +373,8 @@ __device__ __forceinline__ double join_words(unsigned lo, unsigned hi) {
 // same; a stage costs one exchange per pair of values instead of one per
 // value. At H = 32 and 16 the row swaps do it without selects: after
 // swapping the upper rows of a with the lower rows of b, a + b holds a's pair
-// sum in the lower rows and b's in the upper ones.
+// sum in the lower rows and b's in the upper ones; at H = 8 and 4 the
+// half-lane moves do the same.
 template <int H>
 __device__ __forceinline__ double pair_sum(double a, double b, int lane) {
   if constexpr (H == 32 || H == 16) {
@@ -354,6 +389,9 @@ __device__ __forceinline__ double pair_sum(double a, double b, int lane) {
       const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
       return join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
     }
+  } else if constexpr (H == 8 || H == 4) {
+    // lanes with bit H clear: (own a, a of L + H); set: (b of L - H, own b)
+    return from_below<H>(a, b) + from_above<H>(b, a);
   } else {
     const bool up = lane & H;
     const double send = up ? a : b, keep = up ? b : a;
@@ -361,7 +399,9 @@ __device__ __forceinline__ double pair_sum(double a, double b, int lane) {
   }
 }
 
-// Wave totals of eight values: lane L ends with the total of v[L >> 3].
+// Wave totals of eight values: lane L with L mod 8 = 7 ends with the total
+// of v[L >> 3]. The last three levels add the value of lane L - 4, L - 2 and
+// L - 1, which pairs the same partial sums as a butterfly would.
 __device__ __forceinline__ double transposed_sum8(const double v[8], int lane) {
   double t5[4], t4[2];
 #pragma unroll
@@ -369,9 +409,9 @@ __device__ __forceinline__ double transposed_sum8(const double v[8], int lane) {
 #pragma unroll
   for (int i = 0; i < 2; ++i) t4[i] = pair_sum<16>(t5[i], t5[i + 2], lane);
   double t = pair_sum<8>(t4[0], t4[1], lane);
-  t += xor_lane<4>(t, lane);
-  t += xor_lane<2>(t, lane);
-  t += xor_lane<1>(t, lane);
+  t += row_shr<4>(t);
+  t += row_shr<2>(t);
+  t += row_shr<1>(t);
   return t;
 }
 
@@ -406,7 +446,8 @@ __device__ __forceinline__ double transposed_sum36(const double v[36], int lane)
 // partner's B, its B): a butterfly pair of one sub-transform. The lane then
 // forms both outputs of that butterfly, so no lane computes a result it
 // throws away. At H = 32 and 16 the row swaps make the trade, one
-// instruction per register; below, one DPP exchange and selects. After the
+// instruction per register; at H = 8 and 4 two half-lane moves; at H = 2
+// and 1 one DPP exchange and selects. After the
 // six forward stages lane 32c + i holds channel c's window bins bitrev5(i)
 // and 32 + bitrev5(i); one more row swap at span 32 leaves lane 32s + i with
 // both channels of bin 32s + bitrev5(i). Each trade is its own inverse, so
@@ -440,6 +481,14 @@ __device__ __forceinline__ void trade(Pair& p, int lane) {
   if constexpr (H >= 16) {
     row_swap<H>(p.ar, p.br);
     row_swap<H>(p.ai, p.bi);
+  } else if constexpr (H >= 4) {
+    // lanes with bit H clear keep A and take the B of lane L + H; the others
+    // keep B and take the A of lane L - H
+    const double nbr = from_above<H>(p.br, p.ar), nbi = from_above<H>(p.bi, p.ai);
+    p.ar = from_below<H>(p.ar, p.br);
+    p.ai = from_below<H>(p.ai, p.bi);
+    p.br = nbr;
+    p.bi = nbi;
   } else {
     const bool set = lane & H;
     const double rr = xor_lane<H>(set ? p.ar : p.br, lane), ri = xor_lane<H>(set ? p.ai : p.bi, lane);
@@ -451,13 +500,15 @@ __device__ __forceinline__ void trade(Pair& p, int lane) {
 }
 
 // Forward stage S (span 32 >> S), decimation in frequency: (a, b) ->
-// (a + b, (a - b) w). Below span 16 the lane keeps x (its A, or its B with
-// bit H set) and receives y, so the pair is (x, y) or (y, x); the sign of
-// the difference in the second case is folded into the lane's twiddle.
+// (a + b, (a - b) w). Down to span 4 the pair arrives in order (x the
+// element of the lower index). At spans 2 and 1 the lane keeps x (its A, or
+// its B with bit H set) and receives y, so the pair is (x, y) or (y, x); the
+// sign of the difference in the second case is folded into the lane's
+// twiddle, which at span 1 is that sign alone (the root is 1), applied by
+// flipping the sign bit.
 template <int S>
 __device__ __forceinline__ void fwd_stage(Pair& p, const double* tw, int lane) {
   constexpr int H = 32 >> S;
-  const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
   double xr, xi, yr, yi;
   if constexpr (H >= 16) {
     row_swap<H>(p.ar, p.br);
@@ -466,6 +517,12 @@ __device__ __forceinline__ void fwd_stage(Pair& p, const double* tw, int lane) {
     xi = p.ai;
     yr = p.br;
     yi = p.bi;
+  } else if constexpr (H >= 4) {
+    // lanes with bit H clear: (own A, A of lane L + H); set: (B of L - H, own B)
+    xr = from_below<H>(p.ar, p.br);
+    xi = from_below<H>(p.ai, p.bi);
+    yr = from_above<H>(p.br, p.ar);
+    yi = from_above<H>(p.bi, p.ai);
   } else {
     const bool set = lane & H;
     xr = set ? p.br : p.ar;
@@ -476,16 +533,28 @@ __device__ __forceinline__ void fwd_stage(Pair& p, const double* tw, int lane) {
   const double dr = xr - yr, di = xi - yi;
   p.ar = xr + yr;
   p.ai = xi + yi;
-  p.br = dr * wr - di * wi;
-  p.bi = dr * wi + di * wr;
+  if constexpr (H == 1) {
+    const uint64_t sgn = (uint64_t)(lane & 1) << 63;
+    p.br = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, dr) ^ sgn);
+    p.bi = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, di) ^ sgn);
+  } else {
+    const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
+    p.br = dr * wr - di * wi;
+    p.bi = dr * wi + di * wr;
+  }
 }
 
-// Inverse stage S: (s, d) -> (s + conj(w) d, s - conj(w) d), then the trade.
+// Inverse stage S: (s, d) -> (s + conj(w) d, s - conj(w) d), then the trade
+// (at span 1 the root is 1).
 template <int S>
 __device__ __forceinline__ void inv_stage(Pair& p, const double* tw, int lane) {
   constexpr int H = 32 >> S;
-  const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
-  const double tr = p.br * wr - p.bi * wi, ti = p.br * wi + p.bi * wr;
+  double tr = p.br, ti = p.bi;
+  if constexpr (H > 1) {
+    const double wr = tw[S * 128 + 2 * lane], wi = tw[S * 128 + 2 * lane + 1];
+    tr = p.br * wr - p.bi * wi;
+    ti = p.br * wi + p.bi * wr;
+  }
   const double sr = p.ar, si = p.ai;
   p.ar = sr + tr;
   p.ai = si + ti;
@@ -555,12 +624,12 @@ __device__ __forceinline__ double wave_sum(double v, int lane) {
 __device__ __forceinline__ void window_spectrum(const Src& s, const LaneGeom& g, const double* tw,
                                                 const double* trig, double scale, int lane,
                                                 double re[2], double im[2]) {
-  const Env e = envelope(s, g, trig, lane);
-  const double sg = (lane & 1) ? -scale : scale;  // (-1)^j centres the window on q
+  // (-1)^j centres the window on q
+  const Env e = envelope(s, g, trig, lane, (lane & 1) ? -0.5 * scale : 0.5 * scale);
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    re[c] = sg * e.zr[c];
-    im[c] = sg * e.zi[c];
+    re[c] = e.zr[c];
+    im[c] = e.zi[c];
   }
   fft_fwd(re, im, tw, lane);
 }
@@ -712,7 +781,9 @@ __device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g
 // i dphi_p z_c (amp_phase_derivs): per channel
 //   Re(conj(w) dz_p) = Re(da_p) ur + Im(da_p) ui + dphi_p (Im w Re z - Re w Im z),
 // ur = (Re w cos ph + Im w sin ph) / 2, ui = (Im w cos ph - Re w sin ph) / 2,
-// and the dphi terms of both channels share one factor G. The two sky
+// and the dphi terms of both channels share one factor
+// G = sum_c (Im w Re z - Re w Im z) = sum_c (Re a ui - Im a ur). The caller
+// passes w up to a sign, which half (+-1/2) restores. The two sky
 // derivatives are linear in (dP, dX), which are bilinear in the detector
 // tensor D_c, so with the weights alpha, beta that the polarisation angle and
 // the amplitudes give dP and dX they contract to 2 n.D y1 (latitude) and
@@ -724,17 +795,18 @@ __device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g
 //   latitude:  2 (alpha n.D u + beta n.D v)
 //   longitude: 2 (alpha (sin(b) X + cos(b) n.D v) - beta (sin(b) P + cos(b) n.D u)).
 __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
-                                           const double wr[2], const double wi[2], double gp[8]) {
+                                           const double wr[2], const double wi[2], double half,
+                                           double gp[8]) {
   const double Ap = s.Ap, Ax = s.Ax;
   // the terms that need the envelope, for both channels; the envelope's
   // values are dead after this
   double ur[2], ui[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    ur[c] = 0.5 * (wr[c] * e.cph + wi[c] * e.sph);
-    ui[c] = 0.5 * (wi[c] * e.cph - wr[c] * e.sph);
+    ur[c] = half * (wr[c] * e.cph + wi[c] * e.sph);
+    ui[c] = half * (wi[c] * e.cph - wr[c] * e.sph);
   }
-  const double G = (wi[0] * e.zr[0] - wr[0] * e.zi[0]) + (wi[1] * e.zr[1] - wr[1] * e.zi[1]);
+  const double G = (e.ar[0] * ui[0] - e.ai[0] * ur[0]) + (e.ar[1] * ui[1] - e.ai[1] * ur[1]);
   const double t2 = (e.ar[0] * ur[0] + e.ai[0] * ui[0]) + (e.ar[1] * ur[1] + e.ai[1] * ui[1]);
   const double t5 = (e.Fx[0] * Ap * ur[0] + e.Fp[0] * Ax * ui[0]) +
                     (e.Fx[1] * Ap * ur[1] + e.Fp[1] * Ax * ui[1]);
@@ -891,21 +963,14 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
       }
       fft_inv(wr, wi, sd.tw + 6 * 128, lane);
       // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
-      // of the window (indexed from q - 32)
-      if (lane & 1) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          wr[c] = -wr[c];
-          wi[c] = -wi[c];
-        }
-      }
+      // of the window (indexed from q - 32); the sign goes with the factor 1/2
       // Re(conj(w) dz) per parameter
       const Env e = envelope(s, g, sd.trig, lane);
       double gp[8];
-      grad_terms(s, g, e, wr, wi, gp);
-      // lane 8p ends with parameter p's total
+      grad_terms(s, g, e, wr, wi, (lane & 1) ? -0.5 : 0.5, gp);
+      // lane 8p + 7 ends with parameter p's total
       double gv = transposed_sum8(gp, lane) * (wc * sd.scale);
-      if ((lane & 7) == 0) {
+      if ((lane & 7) == 7) {
         const int64_t x = (it.m0 + k) * 8 + (lane >> 3);
         if (!first && a.grad) gv += a.grad[x];
         if (a.grad) a.grad[x] = gv;
