@@ -780,63 +780,73 @@ __device__ __forceinline__ void amp_phase_derivs(const Src& s, const LaneGeom& g
 // for the eight parameters, without forming dz_c,p = (da_c,p / 2) e^{i ph} +
 // i dphi_p z_c (amp_phase_derivs): per channel
 //   Re(conj(w) dz_p) = Re(da_p) ur + Im(da_p) ui + dphi_p (Im w Re z - Re w Im z),
-// ur = (Re w cos ph + Im w sin ph) / 2, ui = (Im w cos ph - Re w sin ph) / 2,
-// and the dphi terms of both channels share one factor
-// G = sum_c (Im w Re z - Re w Im z) = sum_c (Re a ui - Im a ur). The caller
-// passes w up to a sign, which half (+-1/2) restores. The two sky
+// ur = (Re w cos ph + Im w sin ph) / 2, ui = (Im w cos ph - Re w sin ph) / 2.
+// The caller passes w up to a sign, which half (+-1/2) restores. With the
+// amplitudes a_c = Ap Fp_c - i Ax Fx_c, every amplitude and phase term is a
+// combination of four channel sums S1 = sum Fp ur, S2 = sum Fp ui,
+// S3 = sum Fx ur, S4 = sum Fx ui: the phase factor shared by the dphi terms
+// is G = sum (Im w Re z - Re w Im z) = sum (Re a ui - Im a ur) = Ap S2 + Ax S3,
+// the amplitude's own term sum (Re a ur + Im a ui) = Ap S1 - Ax S4, the
+// polarisation angle's sum (Fx Ap ur + Fp Ax ui) = Ap S3 + Ax S2 and the
+// inclination's sum (cos(i) Fp ur + Fx ui) = cos(i) S1 + S4. The two sky
 // derivatives are linear in (dP, dX), which are bilinear in the detector
-// tensor D_c, so with the weights alpha, beta that the polarisation angle and
-// the amplitudes give dP and dX they contract to 2 n.D y1 (latitude) and
+// tensor D_c, so with the weights alpha_c = c2p Ap ur + s2p Ax ui,
+// beta_c = s2p Ap ur - c2p Ax ui that the polarisation angle and the
+// amplitudes give dP and dX they contract to 2 n.D y1 (latitude) and
 // 2 (ul.D y1 + vl.D y2) (longitude), y1 = alpha u + beta v, y2 = beta u - alpha v,
 // ul = sin(b) v and vl = -(cos(b) n + sin(b) u) the derivatives of u and v
-// with respect to the longitude. With D symmetric these reduce to two new
-// forms per channel, n.D u and n.D v, and the patterns P and X of the
-// envelope:
-//   latitude:  2 (alpha n.D u + beta n.D v)
-//   longitude: 2 (alpha (sin(b) X + cos(b) n.D v) - beta (sin(b) P + cos(b) n.D u)).
+// with respect to the longitude. With D symmetric these reduce to the forms
+// n.D u and n.D v and the patterns P and X:
+//   latitude:  2 sum (alpha n.D u + beta n.D v)
+//   longitude: 2 sum (alpha (sin(b) X + cos(b) n.D v) - beta (sin(b) P + cos(b) n.D u)),
+// where sum (alpha X - beta P) is the polarisation angle's sum above (P and X
+// rotated by 2 psi are Fp and Fx), and the rest is linear in the four sums
+// U1 = sum ur n.D u, U2 = sum ui n.D u, V1 = sum ur n.D v, V2 = sum ui n.D v.
 __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, const Env& e,
                                            const double wr[2], const double wi[2], double half,
                                            double gp[8]) {
   const double Ap = s.Ap, Ax = s.Ax;
-  // the terms that need the envelope, for both channels; the envelope's
-  // values are dead after this
+  const double hc = half * e.cph, hs = half * e.sph;
   double ur[2], ui[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    ur[c] = half * (wr[c] * e.cph + wi[c] * e.sph);
-    ui[c] = half * (wi[c] * e.cph - wr[c] * e.sph);
+    ur[c] = wr[c] * hc + wi[c] * hs;
+    ui[c] = wi[c] * hc - wr[c] * hs;
   }
-  const double G = (e.ar[0] * ui[0] - e.ai[0] * ur[0]) + (e.ar[1] * ui[1] - e.ai[1] * ur[1]);
-  const double t2 = (e.ar[0] * ur[0] + e.ai[0] * ui[0]) + (e.ar[1] * ur[1] + e.ai[1] * ui[1]);
-  const double t5 = (e.Fx[0] * Ap * ur[0] + e.Fp[0] * Ax * ui[0]) +
-                    (e.Fx[1] * Ap * ur[1] + e.Fp[1] * Ax * ui[1]);
-  const double t6 = (s.ci * e.Fp[0] * ur[0] + e.Fx[0] * ui[0]) +
-                    (s.ci * e.Fp[1] * ur[1] + e.Fx[1] * ui[1]);
+  const double S1 = e.Fp[0] * ur[0] + e.Fp[1] * ur[1], S2 = e.Fp[0] * ui[0] + e.Fp[1] * ui[1];
+  const double S3 = e.Fx[0] * ur[0] + e.Fx[1] * ur[1], S4 = e.Fx[0] * ui[0] + e.Fx[1] * ui[1];
+  const double G = Ap * S2 + Ax * S3;
+  const double t5 = Ap * S3 + Ax * S2;
   const double fi = s.f0 + s.fd * e.tau;
   gp[0] = kTwoPi * e.tau * G;
   gp[1] = 0.5 * kTwoPi * e.tau * e.tau * G;
-  gp[2] = kLn10 * t2;
-  gp[3] = kTwoPi * fi * (-s.sb * e.doppler) * G;
-  gp[4] = kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G;
+  gp[2] = kLn10 * (Ap * S1 - Ax * S4);
   gp[5] = 2.0 * t5;
-  gp[6] = -2.0 * s.A * s.si * t6;
+  gp[6] = -2.0 * s.A * s.si * (s.ci * S1 + S4);
   gp[7] = G;
   // the sky derivatives, one channel at a time (the barrier keeps the two
   // channels' temporaries from being live together)
-  const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
   static constexpr int kVx[5] = {0, 1, 3, 4, 5};  // the tensor entries of the n.D v weights
+  double U1 = 0.0, U2 = 0.0, V1 = 0.0, V2 = 0.0;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const double al = kPa * ur[c] + kXa * ui[c], be = kPb * ur[c] - kXb * ui[c];
     double nDu = 0.0, nDv = 0.0;
 #pragma unroll
     for (int x = 0; x < 6; ++x) nDu = fma(s.wnu[x], g.d(c, x), nDu);
 #pragma unroll
     for (int x = 0; x < 5; ++x) nDv = fma(s.wnv[x], g.d(c, kVx[x]), nDv);
-    gp[3] += 2.0 * (al * nDu + be * nDv);
-    gp[4] += 2.0 * (al * (s.sb * e.X[c] + s.cb * nDv) - be * (s.sb * e.P[c] + s.cb * nDu));
+    U1 = fma(ur[c], nDu, U1);
+    U2 = fma(ui[c], nDu, U2);
+    V1 = fma(ur[c], nDv, V1);
+    V2 = fma(ui[c], nDv, V2);
     __builtin_amdgcn_sched_barrier(0);
   }
+  const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
+  const double lat = (kPa * U1 + kXa * U2) + (kPb * V1 - kXb * V2);
+  const double lon = (kPa * V1 + kXa * V2) - (kPb * U1 - kXb * U2);
+  gp[3] = kTwoPi * fi * (-s.sb * e.doppler) * G + 2.0 * lat;
+  gp[4] = kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G +
+          2.0 * (s.sb * t5 + s.cb * lon);
 }
 
 struct FdItem {
