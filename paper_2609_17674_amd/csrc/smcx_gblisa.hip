@@ -120,10 +120,11 @@ __device__ __forceinline__ V3 mul_sym(const double* d, const V3& v) {
 struct Src {
   double f0, fd, A, cb, sb, cl, sl, c2p, s2p, ci, si, cyc0;
   double Ap, Ax;  // amplitudes of h+ and hx
-  // The polarisation patterns are the quadratic forms P = u.D u - v.D v and
-  // X = 2 u.D v of a detector tensor D; as weights of its six components
-  // (xx, yy, zz, xy, xz, yz): P = sum ep[e] D[e], X = sum ex[e] D[e].
-  double ep[6], ex[6];
+  // The antenna patterns Fp = cos(2 psi) P + sin(2 psi) X and
+  // Fx = -sin(2 psi) P + cos(2 psi) X of the quadratic forms P = u.D u - v.D v
+  // and X = 2 u.D v of a detector tensor D, as weights of its six components
+  // (xx, yy, zz, xy, xz, yz): Fp = sum fpw[e] D[e], Fx = sum fxw[e] D[e].
+  double fpw[6], fxw[6];
   // The weights of the forms n.D u and n.D v in the same way (the
   // zz weight of n.D v is zero, v having no z component: five words).
   double wnu[6], wnv[5];
@@ -145,9 +146,9 @@ constexpr int kQOwn = 32, kQPartner = 33, kWnu = 34, kWnv = 40;
 // All words but the partner's carrier bin.
 __device__ __forceinline__ void src_store(double* c, const Src& s) {
   const double v[33] = {s.f0,    s.fd,    s.A,     s.cb,    s.sb,    s.cl,    s.sl,
-                        s.c2p,   s.s2p,   s.ci,    s.si,    s.cyc0,  s.Ap,    s.Ax,
-                        s.ep[0], s.ep[1], s.ep[2], s.ep[3], s.ep[4], s.ep[5], s.ex[0],
-                        s.ex[1], s.ex[2], s.ex[3], s.ex[4], s.ex[5], s.n.x,   s.n.y,
+                        s.c2p,    s.s2p,    s.ci,     s.si,     s.cyc0,   s.Ap,     s.Ax,
+                        s.fpw[0], s.fpw[1], s.fpw[2], s.fpw[3], s.fpw[4], s.fpw[5], s.fxw[0],
+                        s.fxw[1], s.fxw[2], s.fxw[3], s.fxw[4], s.fxw[5], s.n.x,    s.n.y,
                         s.n.z,   s.u.x,   s.u.y,   s.u.z,   __builtin_bit_cast(double, s.q)};
 #pragma unroll
   for (int x = 0; x < 33; ++x) c[x] = v[x];
@@ -164,8 +165,8 @@ __device__ __forceinline__ Src src_load(const double* c, int qslot) {
   s.c2p = c[7]; s.s2p = c[8]; s.ci = c[9]; s.si = c[10]; s.cyc0 = c[11]; s.Ap = c[12]; s.Ax = c[13];
 #pragma unroll
   for (int e = 0; e < 6; ++e) {
-    s.ep[e] = c[14 + e];
-    s.ex[e] = c[20 + e];
+    s.fpw[e] = c[14 + e];
+    s.fxw[e] = c[20 + e];
   }
   s.n = {c[26], c[27], c[28]};
   s.u = {c[29], c[30], c[31]};
@@ -196,18 +197,17 @@ __device__ __forceinline__ Src make_src(const double* th, double T_obs) {
   s.Ax = -2.0 * s.A * s.ci;
   const V3& u = s.u;
   const V3& v = s.v;
-  s.ep[0] = u.x * u.x - v.x * v.x;
-  s.ep[1] = u.y * u.y - v.y * v.y;
-  s.ep[2] = u.z * u.z - v.z * v.z;
-  s.ep[3] = 2.0 * (u.x * u.y - v.x * v.y);
-  s.ep[4] = 2.0 * (u.x * u.z - v.x * v.z);
-  s.ep[5] = 2.0 * (u.y * u.z - v.y * v.z);
-  s.ex[0] = 2.0 * u.x * v.x;
-  s.ex[1] = 2.0 * u.y * v.y;
-  s.ex[2] = 2.0 * u.z * v.z;
-  s.ex[3] = 2.0 * (u.x * v.y + u.y * v.x);
-  s.ex[4] = 2.0 * (u.x * v.z + u.z * v.x);
-  s.ex[5] = 2.0 * (u.y * v.z + u.z * v.y);
+  // weights of P and X, then of the antenna patterns
+  const double ep[6] = {u.x * u.x - v.x * v.x,         u.y * u.y - v.y * v.y,
+                        u.z * u.z - v.z * v.z,         2.0 * (u.x * u.y - v.x * v.y),
+                        2.0 * (u.x * u.z - v.x * v.z), 2.0 * (u.y * u.z - v.y * v.z)};
+  const double ex[6] = {2.0 * u.x * v.x,               2.0 * u.y * v.y,
+                        2.0 * u.z * v.z,               2.0 * (u.x * v.y + u.y * v.x),
+                        2.0 * (u.x * v.z + u.z * v.x), 2.0 * (u.y * v.z + u.z * v.y)};
+  for (int x = 0; x < 6; ++x) {
+    s.fpw[x] = s.c2p * ep[x] + s.s2p * ex[x];
+    s.fxw[x] = -s.s2p * ep[x] + s.c2p * ex[x];
+  }
   const V3& n = s.n;
   s.wnu[0] = n.x * u.x;
   s.wnu[1] = n.y * u.y;
@@ -227,8 +227,7 @@ __device__ __forceinline__ Src make_src(const double* th, double T_obs) {
 struct Env {
   double zr[2], zi[2];  // z_c
   double ar[2], ai[2];  // complex amplitude a_c
-  double Fp[2], Fx[2];
-  double P[2], X[2];  // the polarisation patterns u.D u - v.D v and 2 u.D v
+  double Fp[2], Fx[2];  // antenna patterns
   double cph, sph, tau, doppler;  // doppler = cos(a - l) (R/c)
 };
 
@@ -238,17 +237,15 @@ __device__ __forceinline__ Env envelope_amp(const Src& s, const LaneGeom& g) {
   Env e;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    double P = 0.0, X = 0.0;
+    double Fp = 0.0, Fx = 0.0;
 #pragma unroll
     for (int x = 0; x < 6; ++x) {
       const double D = g.d(c, x);
-      P = fma(s.ep[x], D, P);
-      X = fma(s.ex[x], D, X);
+      Fp = fma(s.fpw[x], D, Fp);
+      Fx = fma(s.fxw[x], D, Fx);
     }
-    e.P[c] = P;
-    e.X[c] = X;
-    e.Fp[c] = s.c2p * P + s.s2p * X;
-    e.Fx[c] = -s.s2p * P + s.c2p * X;
+    e.Fp[c] = Fp;
+    e.Fx[c] = Fx;
     e.ar[c] = e.Fp[c] * s.Ap;
     e.ai[c] = -e.Fx[c] * s.Ax;
   }
@@ -257,12 +254,15 @@ __device__ __forceinline__ Env envelope_amp(const Src& s, const LaneGeom& g) {
   return e;
 }
 
-// cos and sin of 2 pi cyc, |cyc| <= 1/2: the table's nearest step k / 128
-// (trig: cos, sin of 2 pi k / 128 for k = -64..64) turned by the remainder
-// x = 2 pi (cyc - k / 128), |x| <= pi / 128, whose sine and cosine are
-// their Taylor series cut after x^7 and x^6 (the next terms are below
-// 1e-20 and 4e-18). The cut is relative to the double-precision ulp far
-// smaller than the rounding of the two products that turn the step.
+// cos and sin of 2 pi cyc: the nearest step k / 128 of the phase (t = 128 cyc
+// and its nearest integer are exact, and so is their difference), turned
+// by the remainder x = 2 pi (cyc - k / 128), |x| <= pi / 128, whose sine
+// and cosine are their Taylor series cut after x^7 and x^6 (the next terms
+// are below 1e-20 and 4e-18). The cut is relative to the double-precision
+// ulp far smaller than the rounding of the two products that turn the step.
+// The table (trig) holds cos, sin of 2 pi k / 128 for k = -64..64; the step
+// is taken modulo 128, so any phase (a NaN one converts to some integer)
+// indexes inside it.
 __device__ __forceinline__ void cis_cycles(double cyc, const double* trig, double* c, double* s) {
   const double t = cyc * (double)kFdTrigSteps;  // exact
   const double kf = rint(t);
@@ -270,8 +270,7 @@ __device__ __forceinline__ void cis_cycles(double cyc, const double* trig, doubl
   const double x2 = x * x;
   const double sx = fma(x * x2, fma(x2, fma(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), x);
   const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-  // a NaN phase converts to some k; the index stays inside the table
-  const int k = min(max((int)kf + kFdTrigSteps / 2, 0), kFdTrigSteps);
+  const int k = ((int)kf + kFdTrigSteps / 2) & (kFdTrigSteps - 1);  // entry of the step modulo 128
   const double ck = trig[2 * k], sk = trig[2 * k + 1];
   *c = fma(ck, cx, -(sk * sx));
   *s = fma(sk, cx, ck * sx);
@@ -281,15 +280,18 @@ __device__ __forceinline__ void cis_cycles(double cyc, const double* trig, doubl
 __device__ __forceinline__ Env envelope(const Src& s, const LaneGeom& g, const double* trig,
                                         int lane, double zs = 0.5) {
   Env e = envelope_amp(s, g);
-  // phase in cycles, reduced before the product with 2 pi
-  double cyc = s.f0 * e.tau + 0.5 * s.fd * e.tau * e.tau -
-               (double)(s.q & (kNs - 1)) * (double)lane / (double)kNs + s.cyc0;
-  cyc -= rint(cyc);
+  // phase in cycles (heterodyned at the carrier bin q), reduced by cis_cycles
+  // before the product with 2 pi
+  const double cyc = fma(e.tau, fma(0.5 * s.fd, e.tau, s.f0),
+                         fma(-(double)(int)(s.q & (kNs - 1)), (double)lane * (1.0 / kNs), s.cyc0));
   cis_cycles(cyc, trig, &e.cph, &e.sph);
+  // zs (a_c e^{i ph}) with a_c = Ap Fp_c - i Ax Fx_c
+  const double zp = zs * s.Ap, zx = zs * s.Ax;
+  const double pc = zp * e.cph, ps = zp * e.sph, xc = zx * e.cph, xs = zx * e.sph;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    e.zr[c] = zs * (e.ar[c] * e.cph - e.ai[c] * e.sph);
-    e.zi[c] = zs * (e.ar[c] * e.sph + e.ai[c] * e.cph);
+    e.zr[c] = e.Fp[c] * pc + e.Fx[c] * xs;
+    e.zi[c] = e.Fp[c] * ps - e.Fx[c] * xc;
   }
   return e;
 }
