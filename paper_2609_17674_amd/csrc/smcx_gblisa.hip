@@ -591,12 +591,17 @@ __device__ __forceinline__ void fft_fwd(double re[2], double im[2], const double
 }
 
 // Inverse (unnormalised, e^{+2 pi i m j / 64}) DFT of both channels: lane L
-// holds bin bin_lane(L) of each channel, lane j ends with sample j.
-// tw: the inverse twiddles.
+// holds bin bin_lane(L) of each channel, or with SPLIT lane 32c + i holds
+// channel c's bins bitrev5(i) in (re[0], im[0]) and 32 + bitrev5(i) in
+// (re[1], im[1]) (the layout of the forward stages before their last row
+// swap); lane j ends with sample j. tw: the inverse twiddles.
+template <bool SPLIT = false>
 __device__ __forceinline__ void fft_inv(double re[2], double im[2], const double* tw, int lane) {
   Pair p{re[0], im[0], re[1], im[1]};
-  row_swap<32>(p.ar, p.br);
-  row_swap<32>(p.ai, p.bi);
+  if constexpr (!SPLIT) {
+    row_swap<32>(p.ar, p.br);
+    row_swap<32>(p.ai, p.bi);
+  }
   inv_stage<5>(p, tw, lane);
   inv_stage<4>(p, tw, lane);
   inv_stage<3>(p, tw, lane);
@@ -689,6 +694,14 @@ __device__ __forceinline__ void load_resid(const FdSide& sd, int lane, Resid<NR>
     }
 }
 
+// Band index of the source's window bin 0 (wave-uniform), clamped to
+// [-2 kNs, B], which leaves every test of a band bin against the window and
+// the band as it was and keeps the index arithmetic in 32 bits.
+__device__ __forceinline__ int window_start(int64_t q, const FdSide& sd) {
+  const int64_t lo = q - kNs / 2 - sd.k0;
+  return (int)(lo < -2 * kNs ? -2 * kNs : (lo > sd.B ? sd.B : lo));
+}
+
 // R -= sign h over the band (sign = +-1). Each band bin takes the window
 // value from the lane holding it, weighted by sign where the bin lies in both
 // the window and the band and by 0 elsewhere: one FMA per value, which
@@ -698,12 +711,12 @@ __device__ __forceinline__ void subtract_source(const FdSide& sd, const Src& s, 
                                                 int lane, Resid<NR>& R, double sign) {
   double re[2], im[2];
   window_spectrum(s, g, sd.tw, sd.trig, sd.scale, lane, re, im);
-  const int64_t lo = s.q - kNs / 2 - sd.k0;  // band index of window bin 0
+  const int lo = window_start(s.q, sd);  // band index of window bin 0
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    const int64_t b = lane + kNs * r, m = b - lo;
-    const double f = (m >= 0 && m < kNs && b < sd.B) ? -sign : 0.0;
-    const int from = bin_lane((int)(m & (kNs - 1)));
+    const int b = lane + kNs * r, m = b - lo;
+    const double f = ((unsigned)m < (unsigned)kNs && b < (int)sd.B) ? -sign : 0.0;
+    const int from = bin_lane(m & (kNs - 1));
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       R.re[c][r] = fma(f, __shfl(re[c], from), R.re[c][r]);
@@ -819,9 +832,12 @@ __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, cons
   const double S3 = e.Fx[0] * ur[0] + e.Fx[1] * ur[1], S4 = e.Fx[0] * ui[0] + e.Fx[1] * ui[1];
   const double G = Ap * S2 + Ax * S3;
   const double t5 = Ap * S3 + Ax * S2;
-  const double fi = s.f0 + s.fd * e.tau;
-  gp[0] = kTwoPi * e.tau * G;
-  gp[1] = 0.5 * kTwoPi * e.tau * e.tau * G;
+  // the phase derivatives times G: 2 pi (tau, tau^2 / 2) and 2 pi f_i times
+  // the Doppler delay's derivatives, f_i = f0 + fdot tau
+  const double G2 = kTwoPi * G;
+  const double Gf = (s.f0 + s.fd * e.tau) * G2;
+  gp[0] = e.tau * G2;
+  gp[1] = (0.5 * e.tau) * gp[0];
   gp[2] = kLn10 * (Ap * S1 - Ax * S4);
   gp[5] = 2.0 * t5;
   gp[6] = -2.0 * s.A * s.si * (s.ci * S1 + S4);
@@ -846,9 +862,8 @@ __device__ __forceinline__ void grad_terms(const Src& s, const LaneGeom& g, cons
   const double kPa = s.c2p * Ap, kXa = s.s2p * Ax, kPb = s.s2p * Ap, kXb = s.c2p * Ax;
   const double lat = (kPa * U1 + kXa * U2) + (kPb * V1 - kXb * V2);
   const double lon = (kPa * V1 + kXa * V2) - (kPb * U1 - kXb * U2);
-  gp[3] = kTwoPi * fi * (-s.sb * e.doppler) * G + 2.0 * lat;
-  gp[4] = kTwoPi * fi * (s.cb * kAuLight * (g.sa() * s.cl - g.ca() * s.sl)) * G +
-          2.0 * (s.sb * t5 + s.cb * lon);
+  gp[3] = (-s.sb * e.doppler) * Gf + 2.0 * lat;
+  gp[4] = (s.cb * kAuLight) * (g.sa() * s.cl - g.ca() * s.sl) * Gf + 2.0 * (s.sb * t5 + s.cb * lon);
 }
 
 struct FdItem {
@@ -945,7 +960,9 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
   }
   if constexpr (MODE == 1) {
     const double he = a.p_half ? 0.5 * a.eps * (a.dir ? (double)a.dir[i] : 1.0) : 0.0;
-    const int lr = bin_lane(lane);
+    // the window bins this lane gathers, in the split layout of the inverse
+    // transform: channel lane >> 5, bins m0 and m0 + 32
+    const int wc0 = (lane >> 5) * 2, m0 = bitrev5(lane & 31);
     // The residual goes to the wave's LDS copy ([re, im of A, re, im of E]
     // [band position]); the loop gathers each source's window from there,
     // and its registers are free for the adjoint.
@@ -964,16 +981,16 @@ __device__ __forceinline__ void fd_particle(const PopArgs& a, const FdSide& sd, 
       const int row = __builtin_amdgcn_readfirstlane((int)(it.m0 + k));
       const Src s = src_load(src + (int64_t)row * kSrcWords, sd.qslot);
       // residual window of the source in the inverse transform's input order
-      const int64_t lo = s.q - kNs / 2 - sd.k0;  // band index of window bin 0
-      const int64_t bw = lo + lr;  // band index this lane gathers
-      const int bi = bw >= 0 && bw < sd.B ? (int)bw : Bp;  // the zero word outside the band
+      const int lo = window_start(s.q, sd);  // band index of window bin 0
       double wr[2], wi[2];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        wr[c] = rl[(2 * c) * rs + bi];
-        wi[c] = rl[(2 * c + 1) * rs + bi];
+      for (int h = 0; h < 2; ++h) {
+        const int bw = lo + m0 + 32 * h;  // band index this lane gathers
+        const int bi = (unsigned)bw < (unsigned)sd.B ? bw : Bp;  // the zero word outside the band
+        wr[h] = rl[wc0 * rs + bi];
+        wi[h] = rl[(wc0 + 1) * rs + bi];
       }
-      fft_inv(wr, wi, sd.tw + 6 * 128, lane);
+      fft_inv<true>(wr, wi, sd.tw + 6 * 128, lane);
       // w_j = sum_m R[q + m] e^{2 pi i m j / 64} = (-1)^j times the inverse DFT
       // of the window (indexed from q - 32); the sign goes with the factor 1/2
       // Re(conj(w) dz) per parameter
