@@ -97,6 +97,48 @@ def test_birth_death_match_oracle(lib, orc):
     assert np.all(dd[di == -1] == 0.0)
 
 
+# carrier bins relative to the band's first bin: windows that overlap either
+# edge, lie just outside it, or are far from it (beyond the kernels' clamp of
+# the window start to [-128, B])
+EDGE_OFFSETS = (-100000, -500, -97, -64, -63, -33, -31, 0, 31, 97, 98, 127, 128, 160, 161, 300,
+                1000000)
+
+
+def test_sources_outside_the_band(lib, orc):
+    w = wl.make_gblisa(N=96, k_lo=1, k_hi=6, n_inj=6, beta="uniform", noise=True, seed=420)
+    say("gblisa_edges", "N", w.N, "M", w.M)
+    th, tb = w.theta.copy(), w.extra["theta_birth"].copy()
+    # the first source of each particle and each particle's birth candidate
+    # take the edge bins in turn (f0 inside its bin)
+    for i in range(w.N):
+        off = EDGE_OFFSETS[i % len(EDGE_OFFSETS)]
+        th[w.offsets[i], 0] = (w.k0 + off + 0.37) / w.T_obs
+        tb[i, 0] = (w.k0 + EDGE_OFFSETS[(i + 5) % len(EDGE_OFFSETS)] + 0.61) / w.T_obs
+    d = _data(orc, w)
+    prob = _problem(lib, w, d)
+    off, be = dev(w.offsets), dev(w.beta)
+    l, g = lib.logl_grad_batch(prob, off, dev(th), be)
+    db, dd = lib.delta_logl_birth_death(prob, off, dev(th), be, dev(tb), dev(w.extra["death_idx"]))
+    torch.cuda.synchronize()
+    prob.device_status()
+    l, g, db, dd = (x.cpu().numpy() for x in (l, g, db, dd))
+    rl, rg = orc.gblisa_logl_grad(d, w.k0, w.T_obs, w.S, w.offsets, th, w.beta)
+    rb, rd = orc.gblisa_delta(d, w.k0, w.T_obs, w.S, w.offsets, th, w.beta, tb, w.extra["death_idx"])
+    assert np.all(np.isfinite(l)) and np.all(np.isfinite(g))
+    assert np.all(np.abs(l - rl) <= 1e-9 * np.abs(rl))
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg[a:b] / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn), i
+        # a window wholly outside the band has no gradient
+        q = int(np.floor(th[a, 0] * w.T_obs)) - w.k0
+        if q + 32 <= 0 or q - 32 >= w.B:
+            assert np.all(g[a] == 0.0) and np.all(rg[a] == 0.0), i
+    scale = np.abs(rb) + np.abs(rd) + 1e-6 * np.abs(rl) + 1.0
+    assert np.all(np.abs(db - rb) <= 1e-9 * scale)
+    assert np.all(np.abs(dd - rd) <= 1e-9 * scale)
+
+
 def test_particles_with_many_sources(lib, orc):
     """K up to 40: many sources per particle through the forward pass, the
     adjoint, birth/death and the metric (one lane per source in the pass that
