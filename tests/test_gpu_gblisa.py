@@ -139,6 +139,43 @@ def test_sources_outside_the_band(lib, orc):
     assert np.all(np.abs(dd - rd) <= 1e-9 * scale)
 
 
+@pytest.mark.parametrize("B", [1, 7, 40, 64, 65])
+def test_bands_narrower_than_a_window(lib, orc, B):
+    """Bands of fewer bins than a source's 64-bin window (and one just
+    wider): every window is cut by the band on one or both sides."""
+    w = wl.make_gblisa(N=64, k_lo=0, k_hi=6, n_inj=4, beta="uniform", noise=False, seed=440 + B)
+    # a band of B bins around the carrier bin of one injection, with the
+    # injections and white noise of those bins
+    k0 = int(np.floor(w.inj[1, 0] * w.T_obs)) - B // 2
+    d = orc.gblisa_spectrum(w.inj, w.T_obs, k0, B)
+    rng = np.random.default_rng(450 + B)
+    sd = np.sqrt(w.S * w.T_obs / 4.0)
+    d = d + sd * (rng.standard_normal(d.shape) + 1j * rng.standard_normal(d.shape))
+    say("gblisa_narrow_band", "B", B, "k0", k0, "N", w.N, "M", w.M)
+    prob = lib.Problem.frequency_domain(GBLISA, dev(d), k0, w.T_obs, w.S, w.k_max, w.N, max(w.M, 1))
+    off, th, be = dev(w.offsets), dev(w.theta), dev(w.beta)
+    l, g = lib.logl_grad_batch(prob, off, th, be)
+    tb, di = w.extra["theta_birth"], w.extra["death_idx"]
+    db, dd = lib.delta_logl_birth_death(prob, off, th, be, dev(tb), dev(di))
+    torch.cuda.synchronize()
+    prob.device_status()
+    l, g, db, dd = (x.cpu().numpy() for x in (l, g, db, dd))
+    rl, rg = orc.gblisa_logl_grad(d, k0, w.T_obs, w.S, w.offsets, w.theta, w.beta)
+    rb, rd = orc.gblisa_delta(d, k0, w.T_obs, w.S, w.offsets, w.theta, w.beta, tb, di)
+    # the band meets the windows of most sources
+    assert np.count_nonzero(rg[:, 0]) > w.M // 2
+    assert np.all(np.abs(l - rl) <= 1e-9 * np.abs(rl) + 1e-300)
+    for i in range(w.N):
+        a, b = w.offsets[i], w.offsets[i + 1]
+        if a == b:
+            continue
+        gn, rn = (g[a:b] / NAT).reshape(-1), (rg[a:b] / NAT).reshape(-1)
+        assert np.linalg.norm(gn - rn) <= 1e-7 * np.linalg.norm(rn) + 1e-300, i
+    scale = np.abs(rb) + np.abs(rd) + 1e-6 * np.abs(rl) + 1.0
+    assert np.all(np.abs(db - rb) <= 1e-9 * scale)
+    assert np.all(np.abs(dd - rd) <= 1e-9 * scale)
+
+
 def test_particles_with_many_sources(lib, orc):
     """K up to 40: many sources per particle through the forward pass, the
     adjoint, birth/death and the metric (one lane per source in the pass that
