@@ -16,7 +16,11 @@ Groups and their pins:
   (`test_oracle_fisher.py`, `test_oracle_metric_nuts.py`);
 * gb: the frequency-domain Galactic-binary model (`test_oracle_gblisa.py`:
   orbit, response identities, the DFT of the time-domain strain, likelihood
-  invariants, Richardson differences, metric blocks).
+  invariants, Richardson differences, metric blocks);
+* smc: the temperature search, the evidence increment, systematic
+  resampling and the birth/death accept/reject (`test_oracle_smc.py`: the
+  two-point closed form of the ESS root, scipy's log-sum-exp, the textbook
+  properties of systematic resampling, the stationary distribution of K).
 The NUTS tree has its own planted mistakes in `test_oracle_nuts_tree.py`.
 """
 import importlib
@@ -28,6 +32,7 @@ GROUPS = {
     "pins": ["test_oracle_pins"],
     "metric": ["test_oracle_fisher", "test_oracle_metric_nuts"],
     "gb": ["test_oracle_gblisa"],
+    "smc": ["test_oracle_smc"],
 }
 
 MUTANTS = {
@@ -96,6 +101,29 @@ MUTANTS = {
                             "Fi[(k * GB_P + pa) * n + k * GB_P + pb] = cnorm * s;"),
     "gb_metric_block_placement": ("gb", "Fi[(k * GB_P + pa) * n + k * GB_P + pb] = b * cnorm * s;",
                                   "Fi[(k * GB_P + pa) * n + pb] = b * cnorm * s;"),
+    # ---------------------------------------------------------------- SMC steps
+    "ess_ratio": ("smc", "return s1 * s1 / s2;", "return s1 / s2;"),
+    "ess_weight_square": ("smc", "double e = exp(lw - m);\n    s1 += e;\n    s2 += e * e;",
+                          "double e = exp(lw - m);\n    s1 += e;\n    s2 += e;"),
+    "tempering_increment": ("smc", "logw[i] = (logw_prev ? logw_prev[i] : 0.0) + db * logl[i];",
+                            "logw[i] = (logw_prev ? logw_prev[i] : 0.0) + beta * logl[i];"),
+    "bisection_side": ("smc", "if (e >= target) {\n        lo = mid;", "if (e < target) {\n        lo = mid;"),
+    "full_step_test": ("smc", "ess_at(N, logl, logw_prev, 1.0 - beta_prev, NULL, NULL)",
+                       "ess_at(N, logl, logw_prev, 1.0, NULL, NULL)"),
+    "evidence_uniform_normaliser": ("smc", "    lse_prev = log((double)N);\n  }\n  scalars[0] = beta;",
+                                    "    lse_prev = 0.0;\n  }\n  scalars[0] = beta;"),
+    "evidence_shift": ("smc", "scalars[2] = m + log(s1) - lse_prev;", "scalars[2] = log(s1) - lse_prev;"),
+    "resample_offset": ("smc", "floor(((double)j + u) * (double)total / (double)N)",
+                        "floor(((double)j + 0.5) * (double)total / (double)N)"),
+    "resample_search": ("smc", "while (C[a] <= U) ++a;", "while (C[a] < U) ++a;"),
+    "resample_copy_source": ("smc", "theta_out[offsets_out[j] * P + x] = theta[offsets[a] * P + x];",
+                             "theta_out[offsets_out[j] * P + x] = theta[offsets[j] * P + x];"),
+    "birth_ratio_sign": ("smc", "acc = log_u[i] < dlogl_birth[i] + log_pd_over_pb;",
+                         "acc = log_u[i] < dlogl_birth[i] - log_pd_over_pb;"),
+    "death_ratio_sign": ("smc", "acc = log_u[i] < dlogl_death[i] - log_pd_over_pb;",
+                         "acc = log_u[i] < dlogl_death[i] + log_pd_over_pb;"),
+    "birth_k_bound": ("smc", "K + 1 <= k_hi", "K + 1 < k_hi"),
+    "death_row_removed": ("smc", "if (k == skip) continue;", "if (k == skip + 1) continue;"),
 }
 
 # the pins that take longest run last: most mutants fail a fast one first

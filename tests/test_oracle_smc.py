@@ -34,10 +34,12 @@ def test_next_beta_equal_logl_goes_to_one(orc):
 
 @pytest.mark.parametrize("N0,N1,L,alpha,beta_prev", [(300, 700, 50.0, 0.9, 0.0),
                                                      (50, 950, 2000.0, 0.5, 0.25),
-                                                     (900, 100, 7.0, 0.95, 0.6)])
+                                                     (900, 100, 7.0, 0.95, 0.6),
+                                                     (900, 100, 1.77, 0.95, 0.6)])
 def test_next_beta_two_point_closed_form(orc, N0, N1, L, alpha, beta_prev):
     """ESS((N0 + N1 x)^2 / (N0 + N1 x^2)) = alpha N with x = exp(-db L) is a
-    quadratic in x."""
+    quadratic in x. In the last case the root lies beyond the step to one
+    (db = 0.70 > 1 - beta_prev), so beta is one at once, with no search."""
     N = N0 + N1
     logl = np.concatenate([np.zeros(N0), np.full(N1, -L)])
     a = N1 * (N1 - alpha * N)
@@ -52,6 +54,8 @@ def test_next_beta_two_point_closed_form(orc, N0, N1, L, alpha, beta_prev):
     assert abs(sc[0] - expect) <= 1e-12 * max(expect, 1e-3), (sc[0], expect)
     if expect < 1.0:
         assert alpha * N <= sc[1] <= alpha * N + 1e-6 * N
+    else:
+        assert sc[0] == 1.0 and sc[3] == 0 and sc[1] >= alpha * N
 
 
 def test_next_beta_random_population_brackets_the_root(orc):
