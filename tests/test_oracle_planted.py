@@ -20,7 +20,10 @@ Groups and their pins:
 * smc: the temperature search, the evidence increment, systematic
   resampling and the birth/death accept/reject (`test_oracle_smc.py`: the
   two-point closed form of the ESS root, scipy's log-sum-exp, the textbook
-  properties of systematic resampling, the stationary distribution of K).
+  properties of systematic resampling, the stationary distribution of K);
+* split: the posterior-start bridge target (`test_oracle_split.py`: 40-digit
+  brute force, its limits at split = 0 and T, birth + death = 0, depth-1
+  NUTS as Metropolis on the split energy).
 The NUTS tree has its own planted mistakes in `test_oracle_nuts_tree.py`.
 """
 import importlib
@@ -33,6 +36,7 @@ GROUPS = {
     "metric": ["test_oracle_fisher", "test_oracle_metric_nuts"],
     "gb": ["test_oracle_gblisa"],
     "smc": ["test_oracle_smc"],
+    "split": ["test_oracle_split"],
 }
 
 MUTANTS = {
@@ -124,6 +128,18 @@ MUTANTS = {
                          "acc = log_u[i] < dlogl_death[i] + log_pd_over_pb;"),
     "birth_k_bound": ("smc", "K + 1 <= k_hi", "K + 1 < k_hi"),
     "death_row_removed": ("smc", "if (k == skip) continue;", "if (k == skip + 1) continue;"),
+    # ---------------------------------------------------------------- posterior-start bridge
+    "split_boundary": ("split", "return s < split ? 1.0 : b;", "return s <= split ? 1.0 : b;"),
+    "split_swapped_weights": ("split", "return s < split ? 1.0 : b;", "return s < split ? b : 1.0;"),
+    "split_logl_unweighted": ("split", "ss += sample_weight(s, split, b) * (r * r);", "ss += r * r;"),
+    "split_gradient_unweighted": ("split", "for (int p = 0; p < P; ++p) g[k * P + p] += ws * (r * dh[p]);",
+                                  "for (int p = 0; p < P; ++p) g[k * P + p] += r * dh[p];"),
+    "split_birth_energy_unweighted": ("split", "        x += ws * (r * h);\n        y += ws * (h * h);\n      }\n      d_birth[i]",
+                                      "        x += ws * (r * h);\n        y += h * h;\n      }\n      d_birth[i]"),
+    "split_death_energy_sign": ("split", "d_death[i] = -((x - 0.5 * y) / (sigma * sigma));",
+                                "d_death[i] = -((x + 0.5 * y) / (sigma * sigma));"),
+    "split_nuts_wrong_target": ("split", "particle_logl_grad_split(model, d, T, t_start, dt, sigma, K, qF, b, split, &lF, gF);",
+                                "particle_logl_grad(model, d, T, t_start, dt, sigma, K, qF, b, &lF, gF);"),
 }
 
 # the pins that take longest run last: most mutants fail a fast one first
