@@ -79,6 +79,8 @@ MUTANTS = {
     "kick_wrong_side": ("metric", "matvec(Wi, n, 0, gF, wv);\n            for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * wv[x];",
                         "matvec(Wi, n, 1, gF, wv);\n            for (int64_t x = 0; x < n; ++x) pF[x] = pF[x] + 0.5 * e * wv[x];"),
     "drift_wrong_side": ("metric", "matvec(Wi, n, 1, pF, wv);", "matvec(Wi, n, 0, pF, wv);"),
+    "fisher_split_weight": ("metric", "double ws = split == 0 ? 1.0 : sample_weight(s, split, b);",
+                            "double ws = split == 0 ? 1.0 : b;"),
     # ---------------------------------------------------------------- frequency-domain GB
     "channel_A_coefficient": ("gb", "DA9[3 * i + j] = (M[2][i][j] - M[0][i][j]) / sqrt(2.0);",
                               "DA9[3 * i + j] = (M[2][i][j] - M[0][i][j]) / sqrt(3.0);"),
