@@ -75,8 +75,8 @@ SLOTS = {(0, "grad"): 12.0, (1, "grad"): 5.0 + 51.0 / 8.0, (0, "fwd"): 5.0, (1, 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4614e+07, "kernels_sha1": "128e5cc1bc5f7c2f"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3128e+07, "kernels_sha1": "128e5cc1bc5f7c2f"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4597e+07, "kernels_sha1": "d264f30770ac6537"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3151e+07, "kernels_sha1": "d264f30770ac6537"}}
 
 
 def kernels_sha1():

@@ -146,7 +146,8 @@ struct PulseC {
   float fa;  // (fractional part of the centre) * a
   float A;
   int lo, hi;  // first and last sample of the truncation support
-  int pad0, pad1;
+  unsigned int groups;  // block groups met on the current tile (written per tile)
+  int pad;
 };
 static_assert(sizeof(PulseC) == 32, "pulse constants are 32 bytes");
 
@@ -173,7 +174,8 @@ __device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, d
   }
   r.lo = (int)lo;
   r.hi = (int)hi;
-  r.pad0 = r.pad1 = 0;
+  r.groups = 0u;
+  r.pad = 0;
   return r;
 }
 
@@ -181,21 +183,18 @@ __device__ __forceinline__ PulseC pulse_make(const double* th, double t_start, d
 constexpr int kPulseGroup = 2;
 
 // Bit g set when block group g of the tile starting at sample `tile` meets the
-// support (wave-uniform). 32-bit masks where they suffice: they test in one
-// scalar instruction.
+// support of a component (computed by one lane per component at the start of
+// each tile, kept with the component's constants and read back by both passes
+// as a wave-uniform 32-bit mask, which tests in one scalar instruction).
 template <int S>
-using GroupMask = typename std::conditional<(S / kPulseGroup > 32), unsigned long long,
-                                            unsigned int>::type;
-
-template <int S>
-__device__ __forceinline__ GroupMask<S> pulse_groups(const PulseC& c, int tile) {
-  static_assert(S / kPulseGroup <= 64, "one bit per block group");
+__device__ __forceinline__ unsigned int pulse_groups(const PulseC& c, int tile) {
+  static_assert(S / kPulseGroup <= 32, "one bit per block group");
   // arithmetic shift: floor division by 64
-  const int jlo = __builtin_amdgcn_readfirstlane(max((c.lo - tile) >> 6, 0));
-  const int jhi = __builtin_amdgcn_readfirstlane(min(((c.hi - tile) >> 6) + 1, S));
-  if (jlo >= jhi) return 0;
+  const int jlo = max((c.lo - tile) >> 6, 0);
+  const int jhi = min(((c.hi - tile) >> 6) + 1, S);
+  if (jlo >= jhi) return 0u;
   const int glo = jlo / kPulseGroup, n = (jhi - 1) / kPulseGroup - glo + 1;
-  return (GroupMask<S>)((n >= 64 ? ~0ull : ((1ull << n) - 1ull)) << glo);
+  return (unsigned int)((n >= 32 ? 0xffffffffu : ((1u << n) - 1u)) << glo);
 }
 
 // Chirping sinusoid h = A sin(2 pi (a0 + a1 s + a2 s^2)) in sample index s.
@@ -297,7 +296,7 @@ __device__ __forceinline__ void pulse_fwd_group(const PulseC& c, float a64, floa
 
 template <int S, int J = 0>
 __device__ __forceinline__ void pulse_fwd_j(const PulseC& c, float base, float (&r)[S],
-                                            GroupMask<S> groups) {
+                                            unsigned int groups) {
   if constexpr (J < S) {
     if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u)) {
       const float z = __builtin_fmaf(base + (float)(64 * J), c.a, -c.fa);
@@ -325,7 +324,7 @@ __device__ __forceinline__ void pulse_adj_group(const PulseC& c, float a64, floa
 template <int S, int J = 0>
 __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const float (&r)[S],
                                             float& s0, float& s1, float& s2,
-                                            GroupMask<S> groups) {
+                                            unsigned int groups) {
   if constexpr (J < S) {
     if (__builtin_expect((groups >> (J / kPulseGroup)) & 1u, 1u)) {
       const float z = __builtin_fmaf(base + (float)(64 * J), c.a, -c.fa);
@@ -443,12 +442,21 @@ struct Model<SMCX_PULSE> {
   }
   // pulses have one tile path (LIN is ignored)
   __device__ static bool chord_ok(const C&, int) { return true; }
+  // the block groups of the tile that each component meets, one lane per
+  // component, for both passes over the tile
+  template <int S>
+  __device__ static void prepare(C* cst, int K, int64_t tile, int lane) {
+    for (int k = lane; k < K; k += 64) cst[k].groups = pulse_groups<S>(cst[k], (int)tile);
+    wave_sync();
+  }
   template <int S, bool LIN = true>
   __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
     const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
-      const GroupMask<S> groups = pulse_groups<S>(c, (int)tile);
+      // the constants are read together with the mask (one LDS round trip)
+      asm volatile("" ::"v"(c.nf), "v"(c.a), "v"(c.fa), "v"(c.A));
+      const unsigned int groups = __builtin_amdgcn_readfirstlane(c.groups);
       if (groups == 0) continue;
       pulse_fwd_j<S>(c, sf0 - c.nf, r, groups);
     }
@@ -459,7 +467,8 @@ struct Model<SMCX_PULSE> {
     const float sf0 = (float)(int)(tile + lane);
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
-      const GroupMask<S> groups = pulse_groups<S>(c, (int)tile);
+      asm volatile("" ::"v"(c.nf), "v"(c.a), "v"(c.fa));  // one LDS round trip
+      const unsigned int groups = __builtin_amdgcn_readfirstlane(c.groups);
       if (groups == 0) continue;  // the component adds nothing on this tile
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       pulse_adj_j<S>(c, sf0 - c.nf, r, s0, s1, s2, groups);
@@ -517,6 +526,9 @@ struct Model<SMCX_GBSINE> {
   }
   // LIN: every component of the particle takes the linear tile phase (gb_chord_ok)
   __device__ static bool chord_ok(const C& c, int S) { return gb_chord_ok(c, S); }
+  // sinusoids span every tile: nothing to prepare
+  template <int S>
+  __device__ static void prepare(C*, int, int64_t, int) {}
   template <int S, bool LIN>
   __device__ static void forward(const C* cst, int K, int64_t tile, int lane, float (&r)[S]) {
     const double u = (double)(tile + lane);
@@ -866,7 +878,7 @@ constexpr int pop_waves_per_simd() {
 // returns the tempered (ss) and, with a split, untempered (ss_lo) sums of r^2
 // of the lane. LIN selects the sinusoids' linear tile phase.
 template <int MODEL, int S, bool GRAD, bool LIN>
-__device__ __forceinline__ void pop_tiles(const PopArgs& a, const typename Model<MODEL>::C* cst,
+__device__ __forceinline__ void pop_tiles(const PopArgs& a, typename Model<MODEL>::C* cst,
                                           double* acc, int K, int lane, int64_t cs, int64_t ce,
                                           bool split, double b, double& ss, double& ss_lo) {
   using M = Model<MODEL>;
@@ -876,6 +888,7 @@ __device__ __forceinline__ void pop_tiles(const PopArgs& a, const typename Model
     const float* dp = a.d32 + tile + lane;
 #pragma unroll
     for (int j = 0; j < S; ++j) r[j] = dp[64 * j];
+    M::template prepare<S>(cst, K, tile, lane);
     M::template forward<S, LIN>(cst, K, tile, lane, r);
     if (tile + 64 * S > ce) {  // ragged tile: samples past the chunk contribute nothing
       const int nv = (int)(ce - tile) - lane;  // lane's samples j with 64 j < nv are inside
@@ -883,11 +896,15 @@ __device__ __forceinline__ void pop_tiles(const PopArgs& a, const typename Model
       for (int j = 0; j < S; ++j) r[j] = 64 * j < nv ? r[j] : 0.f;
     }
     if (!split) {
+      // four FP32 chains of S/4 squares, each added to the FP64 sum once per
+      // tile: a chain's relative rounding error is at most S/4 units of 2^-24
+      // (typically about sqrt(S/4), the roundings falling either way), and
+      // the errors of the many chains of a chunk are independent, so that the
+      // sum's relative error stays far below that of the FP32 residual
+      float q[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const double rd = (double)r[j];
-        ss = fma(rd, rd, ss);
-      }
+      for (int j = 0; j < S; ++j) q[j & 3] = __builtin_fmaf(r[j], r[j], q[j & 3]);
+      ss += ((double)q[0] + (double)q[1]) + ((double)q[2] + (double)q[3]);
     } else {
       // samples before the split count untempered; later ones carry beta,
       // which the adjoint then sees through the residual
