@@ -50,33 +50,35 @@ METRIC = "particle logL+grad evals/sec (ragged K) vs plain GPU form at ≤1e-6 r
 # probe (--workload issue_probe) measures what the vector units then do per
 # CU and clock: 63 lanes of v_fmac_f32 / v_fma_f32 (of 64), 96-105 of
 # v_mul_f32 / v_add_f32 / v_add_u32 (of 128), 58 of v_cvt_f32_i32 (of 64), 30
-# of v_exp_f32 / v_sin_f32 (of 32) and 50 of v_fma_f64 (of 64). So the FP32
+# of v_exp_f32 / v_sin_f32 (of 32), 61 of v_alignbit_b32 (of 64) and 50 of
+# v_fma_f64 (of 64). So the FP32
 # ceiling without packed instructions is 64 FMA lanes per CU and clock:
 PEAK_FP32_TFLOPS = 78.6          # 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 PUBLISHED_FP32_TFLOPS = 157.3    # with packed FP32 FMAs (not used by this build)
 CLOCK_HZ = 2.4e9
 
 # Issue cost of one component-sample in FP32-FMA slots (one slot = one lane
-# of a full-rate FMA issue): FMA and conversion 1, two-operand multiply or
-# add (FP32 or integer) 1/2, transcendental 2, from the rates above. The
-# operations are those the method needs per component-sample:
+# of a full-rate FMA issue): FMA, conversion and funnel shift 1, two-operand
+# multiply or add (FP32 or integer) 1/2, transcendental 2, from the rates
+# above. The operations are those the method needs per component-sample:
 #   pulse forward: add, fmac, mul, exp2, fmac                          5
 #   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
-#   sinusoid forward: int add, cvt, mul, sin, fmac                     5
+#   sinusoid forward: int add, phase float (one funnel shift), sin,
+#                     fmac                                             4.5
 #   sinusoid adjoint: the phasor turned by a complex multiply (mul,
 #                     fma, mul, fma) on 7 of 8 samples, taken from sin
-#                     and cos (int add, cvt, mul, sin, cos) on the 8th;
-#                     then fmac, fmac, add, add                 (7 x 6 + 9) / 8
+#                     and cos (int add, funnel shift, sin, cos) on the
+#                     8th; then fmac, fmac, add, add          (7 x 6 + 8.5) / 8
 # (sinusoids with the linear tile phase, which the workloads' chirps take;
 # the adjoint's three moment sums are running sums)
-SLOTS = {(0, "grad"): 12.0, (1, "grad"): 5.0 + 51.0 / 8.0, (0, "fwd"): 5.0, (1, "fwd"): 5.0}
+SLOTS = {(0, "grad"): 12.0, (1, "grad"): 4.5 + 50.5 / 8.0, (0, "fwd"): 5.0, (1, "fwd"): 4.5}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4597e+07, "kernels_sha1": "d264f30770ac6537"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3151e+07, "kernels_sha1": "d264f30770ac6537"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4593e+07, "kernels_sha1": "4b11843de0ef7b8d"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3148e+07, "kernels_sha1": "4b11843de0ef7b8d"}}
 
 
 def kernels_sha1():

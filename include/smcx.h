@@ -709,7 +709,8 @@ enum {
   SMCX_PROBE_MUL_F64 = 10,  /* v_mul_f64 */
   SMCX_PROBE_ADD_F64 = 11,  /* v_add_f64 */
   SMCX_PROBE_DPP = 12,      /* v_mov_b32 with a DPP row rotation */
-  SMCX_PROBE_PERMLANE32 = 13 /* v_permlane32_swap_b32 */
+  SMCX_PROBE_PERMLANE32 = 13, /* v_permlane32_swap_b32 */
+  SMCX_PROBE_ALIGNBIT = 14    /* v_alignbit_b32 */
 };
 
 /* The measured VALU ceilings the roofline of the population kernels refers

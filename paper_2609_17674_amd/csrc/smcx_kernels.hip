@@ -266,7 +266,17 @@ __device__ __forceinline__ GbTile gb_tile(const GbC& c, double u) {
   t.F0 = fixed_cycles(P0 - rint(P0));
   t.D = fixed_cycles(P1 - rint(P1));
   t.c2 = c.c2;
+  if (LIN) t.F0 += 256u;  // rounds the 23-bit phase of gb_rev1 to nearest
   return t;
+}
+// With the linear tile phase: the float 1 + F 2^-32 in [1, 2), one revolution
+// plus the phase, built from its bits in one funnel shift (the exponent of 1
+// above the top 23 bits of F). The sine in revolutions has period one, so
+// this is the phase rounded to 2^-23 revolutions (F0 carries the half unit),
+// at most 3.7e-7 rad from the fixed-point value, for a shift instead of a
+// convert and a multiply per sample.
+__device__ __forceinline__ float gb_rev1(unsigned int F) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, F, 9u));
 }
 // Phase of sample j in revolutions (about [-0.5, 0.5)), F = F0 + j D mod 2^32,
 // plus the chirp correction unless the tile's phase is linear.
@@ -338,13 +348,14 @@ template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_fwd_j(const GbTile& t, unsigned int F, float A, float (&r)[S]) {
   if constexpr (J + 1 < S) {
     const unsigned int F1 = F + t.D;
-    const float s0 = __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
-    const float s1 = __builtin_amdgcn_sinf(gb_rev<J + 1, LIN>(t, F1));
+    const float s0 = __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F));
+    const float s1 = __builtin_amdgcn_sinf(LIN ? gb_rev1(F1) : gb_rev<J + 1, LIN>(t, F1));
     r[J] = __builtin_fmaf(-A, s0, r[J]);
     r[J + 1] = __builtin_fmaf(-A, s1, r[J + 1]);
     gb_fwd_j<S, LIN, J + 2>(t, F1 + t.D, A, r);
   } else if constexpr (J < S) {
-    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F)), r[J]);
+    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F)),
+                          r[J]);
   }
 }
 
@@ -383,7 +394,7 @@ __device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, unsigned int F, fl
                                              float& A, float& B, float& C) {
   if constexpr (J < S) {
     if constexpr (J % kGbAnchor == 0) {
-      const float ph = gb_rev<J, true>(t, F);
+      const float ph = gb_rev1(F);
       zi = __builtin_amdgcn_sinf(ph);
       zr = __builtin_amdgcn_cosf(ph);
     } else {
@@ -415,7 +426,7 @@ template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_sub2_j(const GbTile& t, unsigned int F, float A, float (&r1)[S],
                                           float (&r2)[S]) {
   if constexpr (J < S) {
-    const float s = __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
+    const float s = __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F));
     r1[J] = __builtin_fmaf(-A, s, r1[J]);
     r2[J] = __builtin_fmaf(-A, s, r2[J]);
     gb_sub2_j<S, LIN, J + 1>(t, F + t.D, A, r1, r2);
@@ -425,7 +436,7 @@ __device__ __forceinline__ void gb_sub2_j(const GbTile& t, unsigned int F, float
 template <int S, bool LIN, int J = 0>
 __device__ __forceinline__ void gb_val_j(const GbTile& t, unsigned int F, float A, float (&h)[S]) {
   if constexpr (J < S) {
-    h[J] = A * __builtin_amdgcn_sinf(gb_rev<J, LIN>(t, F));
+    h[J] = A * __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F));
     gb_val_j<S, LIN, J + 1>(t, F + t.D, A, h);
   }
 }

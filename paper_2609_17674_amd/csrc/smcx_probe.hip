@@ -53,6 +53,10 @@ __device__ __forceinline__ void step(float (&x)[kChains], double (&y)[kChains],
         u[k] = r[0];
         u[k + 1] = r[1];
       }
+    } else if constexpr (OP == SMCX_PROBE_ALIGNBIT) {
+      // v_alignbit_b32, the funnel shift that builds the sinusoids' phase
+      // float (written out: repeated shifts of one value fold to a constant)
+      asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(u[k]) : "v"(ui));
     } else if constexpr (OP == SMCX_PROBE_SIN_4FMA) {
       // one transcendental and four FP32 FMAs (accumulator form) per chain
       // step: whether the transcendental unit overlaps with the FP32 issue
@@ -122,6 +126,7 @@ extern "C" int smcx_issue_probe(int op, int32_t blocks, int32_t iters, const flo
     case SMCX_PROBE_ADD_F64: e = launch<SMCX_PROBE_ADD_F64>(blocks, iters, in, out, st); break;
     case SMCX_PROBE_DPP: e = launch<SMCX_PROBE_DPP>(blocks, iters, in, out, st); break;
     case SMCX_PROBE_PERMLANE32: e = launch<SMCX_PROBE_PERMLANE32>(blocks, iters, in, out, st); break;
+    case SMCX_PROBE_ALIGNBIT: e = launch<SMCX_PROBE_ALIGNBIT>(blocks, iters, in, out, st); break;
     default: return smcx::set_error(SMCX_EINVAL, "unknown probe %d", op);
   }
   if (e != hipSuccess) return smcx::set_error(SMCX_EDEVICE, "probe launch: %s", hipGetErrorString(e));

@@ -308,7 +308,8 @@ def logl_grad_batch(prob: Problem, offsets, theta, beta=None, logl=None, grad=No
 
 PROBE_KINDS = {"fma_f32": 0, "mul_f32": 1, "exp_f32": 2, "sin_f32": 3, "fma_f64": 4,
                "add_u32": 5, "cvt": 6, "sin_4fma": 7, "fmac_f32": 8, "add_f32": 9,
-               "mul_f64": 10, "add_f64": 11, "dpp_mov": 12, "permlane32_swap": 13}
+               "mul_f64": 10, "add_f64": 11, "dpp_mov": 12, "permlane32_swap": 13,
+               "alignbit": 14}
 
 
 def issue_probe(kind: str, blocks: int, iters: int, inp: torch.Tensor, out: torch.Tensor,
