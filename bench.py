@@ -77,8 +77,8 @@ SLOTS = {(0, "grad"): 12.0, (1, "grad"): 4.5 + 50.5 / 8.0, (0, "fwd"): 5.0, (1, 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4593e+07, "kernels_sha1": "4b11843de0ef7b8d"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3148e+07, "kernels_sha1": "4b11843de0ef7b8d"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4582e+07, "kernels_sha1": "d799e5d3ad96c7cb"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3141e+07, "kernels_sha1": "d799e5d3ad96c7cb"}}
 
 
 def kernels_sha1():

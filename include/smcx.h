@@ -56,7 +56,10 @@
  * one problem handle must be ordered on one stream (they share workspace).
  *
  * Precision. Template synthesis and residual arithmetic run in FP32; the
- * Galactic-binary phase is formed and reduced modulo one cycle in FP64; the
+ * Galactic-binary phase is formed and reduced modulo one cycle in FP64 (it
+ * must stay below 2^19 cycles over the sample range, i.e. f t below about
+ * 5e5: a component beyond that, or whose chirp moves the phase by 1/64 cycle
+ * or more across a tile, gets NaN outputs and raises the device flag); the
  * per-particle inner products are accumulated in FP64 and all outputs are
  * FP64. In logl_batch, logl_grad_batch, reweight_extend and the leapfrog and
  * NUTS calls, a pulse is truncated to |t - t0| < sqrt(128 ln 2) |w| (about

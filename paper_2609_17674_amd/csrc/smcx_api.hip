@@ -652,7 +652,7 @@ int smcx_device_status(smcx_problem* p, void* hip_stream) {
   if (flag & smcx::kFlagKMax) msg += " a particle has K > k_max;";
   if (flag & smcx::kFlagMMax) msg += " offsets[N] differs from M;";
   if (flag & smcx::kFlagDeath) msg += " death index outside [-1, K);";
-  if (flag & smcx::kFlagPhase) msg += " sinusoid frequency too high for the sample spacing;";
+  if (flag & smcx::kFlagPhase) msg += " sinusoid phase of 2^19 cycles or more over the samples, or chirp too fast for the tile;";
   if (flag & smcx::kFlagCapacity) msg += " rebuilt population exceeds the output rows (m_cap);";
   if (flag & smcx::kFlagWeights) msg += " resampling weights have no positive entry;";
   if (flag & smcx::kFlagNotPD) msg += " a metric block is not positive definite (its factor is NaN);";

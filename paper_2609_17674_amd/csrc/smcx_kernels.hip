@@ -199,28 +199,34 @@ __device__ __forceinline__ unsigned int pulse_groups(const PulseC& c, int tile) 
 
 // Chirping sinusoid h = A sin(2 pi (a0 + a1 s + a2 s^2)) in sample index s.
 struct GbC {
-  double a0, a1, a2;  // phase polynomial in cycles
+  double a0m;         // a0 + kPhaseMagic: the phase at s = 0, offset (see gb_tile)
+  double a1, a2;      // the phase's linear and quadratic coefficients in cycles
+  double p1m;         // 64 a1 + kPhaseMagic: the phase step per 64 samples at s = 0
+  double a2x128;      // 128 a2: that step's growth per sample
   float A;
   float c2;  // 4096 a2 in units of 2^-32 cycles: the chirp per (sample step of 64)^2
 };
-static_assert(sizeof(GbC) == 32, "GB constants are 32 bytes");
+static_assert(sizeof(GbC) == 48, "GB constants are 48 bytes");
 
 __device__ __forceinline__ GbC gb_make(const double* th, double t_start, double dt, int64_t s_lo,
                                        int64_t s_hi, int S, int* flag) {
   const double A = th[0], f0 = th[1], fd = th[2], phi0 = th[3];
   GbC r;
-  r.a0 = f0 * t_start + 0.5 * fd * t_start * t_start + phi0 / kTwoPi;
+  const double a0 = f0 * t_start + 0.5 * fd * t_start * t_start + phi0 / kTwoPi;
   r.a1 = (f0 + fd * t_start) * dt;
   r.a2 = 0.5 * fd * dt * dt;
+  r.a0m = a0 + kPhaseMagic;
+  r.p1m = 64.0 * r.a1 + kPhaseMagic;
+  r.a2x128 = 128.0 * r.a2;
   r.A = (float)A;
   r.c2 = (float)(4096.0 * r.a2 * 4294967296.0);
-  // The phase must stay small enough that FP64 resolves it to well below
-  // 2^-32 cycles (|phase| < 2^20 cycles), and the in-tile chirp correction
-  // must stay a small fraction of a cycle.
+  // The phase must stay below 2^19 cycles, so that its offset value stays in
+  // the binade whose unit is 2^-32 cycles (gb_tile), and the in-tile chirp
+  // correction must stay a small fraction of a cycle.
   const double sh = (double)s_hi;
-  const double pmax = fabs(r.a0) + fabs(r.a1) * sh + fabs(r.a2) * sh * sh;
+  const double pmax = fabs(a0) + fabs(r.a1) * sh + fabs(r.a2) * sh * sh;
   const double chirp = fabs(4096.0 * r.a2) * (double)S * S;
-  if (!(pmax < 1048576.0 && chirp < 0.015625)) {
+  if (!(pmax < 524287.0 && chirp < 0.015625)) {
     if (pmax == pmax && chirp == chirp) atomicOr(flag, kFlagPhase);
     r.A = __builtin_nanf("");
   }
@@ -236,11 +242,21 @@ __device__ __forceinline__ GbC gb_make(const double* th, double t_start, double 
 __device__ __forceinline__ bool gb_chord_ok(const GbC& c, int S) {
   return fabs((double)c.c2) * (double)(S - 1) * (double)(S - 1) <= 256.0;
 }
+// Folds the chord into the constants: the phase at s = 0 moves down by
+// 512 (S-1)^2 a2 and the step per 64 samples up by 4096 (S-1) a2, so that
+// each tile's P0 and P1 (gb_tile) carry it without further work. The phase
+// also gains 2^-24 cycles, half the unit of the 23-bit phase float (gb_rev1),
+// which then rounds to nearest (an exact addition at the unit of a0m).
+__device__ __forceinline__ void gb_linearize(GbC& c, int S) {
+  c.a0m = fma(-512.0 * (double)((S - 1) * (S - 1)), c.a2, c.a0m) + 0x1p-24;
+  c.p1m = fma(4096.0 * (double)(S - 1), c.a2, c.p1m);
+}
 
-// Low 32 bits of y + 1.5*2^20: for |y| < 2^19 this is y mod 1 cycle as a
-// fixed-point number in units of 2^-32 cycles (the sum is rounded to that unit).
-__device__ __forceinline__ unsigned int fixed_cycles(double y) {
-  return (unsigned int)(__builtin_bit_cast(long long, y + kPhaseMagic) & 0xffffffffll);
+// Low 32 bits of x = y + 1.5*2^20 with |y| < 2^19: x lies in [2^20, 2^21),
+// whose unit is 2^-32, so these bits are y mod 1 cycle as a fixed-point
+// number in units of 2^-32 cycles (x is rounded to that unit).
+__device__ __forceinline__ unsigned int fixed_cycles(double x) {
+  return (unsigned int)(__builtin_bit_cast(long long, x) & 0xffffffffll);
 }
 
 // Per (component, lane, tile): the lane's samples are s = u + 64 j, so the
@@ -254,25 +270,24 @@ struct GbTile {
   unsigned int D;   // P1 mod 1, fixed point
   float c2;         // P2 in fixed-point units
 };
+// With LIN the constants carry the chord (gb_linearize): P2 j^2 is replaced
+// by its chord (S-1) P2 j, centred. |P0| and |P1| stay below 2^19 cycles
+// (gb_make), and the constant terms carry the offset 1.5*2^20, so that the
+// final FMA of each lands in the binade whose bits below the unit are the
+// phase modulo one cycle (one rounding to 2^-32 cycles, plus at most half a
+// unit from rounding a0 and 64 a1 with the offset).
 template <bool LIN, int S>
 __device__ __forceinline__ GbTile gb_tile(const GbC& c, double u) {
-  double P0 = fma(fma(c.a2, u, c.a1), u, c.a0);
-  double P1 = fma(128.0 * c.a2, u, 64.0 * c.a1);
-  if (LIN) {  // P2 j^2 by its chord (S-1) P2 j, centred: see gb_make
-    P0 = fma(-512.0 * (double)((S - 1) * (S - 1)), c.a2, P0);
-    P1 = fma(4096.0 * (double)(S - 1), c.a2, P1);
-  }
   GbTile t;
-  t.F0 = fixed_cycles(P0 - rint(P0));
-  t.D = fixed_cycles(P1 - rint(P1));
+  t.F0 = fixed_cycles(fma(fma(c.a2, u, c.a1), u, c.a0m));
+  t.D = fixed_cycles(fma(c.a2x128, u, c.p1m));
   t.c2 = c.c2;
-  if (LIN) t.F0 += 256u;  // rounds the 23-bit phase of gb_rev1 to nearest
   return t;
 }
 // With the linear tile phase: the float 1 + F 2^-32 in [1, 2), one revolution
 // plus the phase, built from its bits in one funnel shift (the exponent of 1
 // above the top 23 bits of F). The sine in revolutions has period one, so
-// this is the phase rounded to 2^-23 revolutions (F0 carries the half unit),
+// this is the phase rounded to 2^-23 revolutions (a0m carries the half unit),
 // at most 3.7e-7 rad from the fixed-point value, for a shift instead of a
 // convert and a multiply per sample.
 __device__ __forceinline__ float gb_rev1(unsigned int F) {
@@ -453,6 +468,7 @@ struct Model<SMCX_PULSE> {
   }
   // pulses have one tile path (LIN is ignored)
   __device__ static bool chord_ok(const C&, int) { return true; }
+  __device__ static void linearize(C&, int) {}
   // the block groups of the tile that each component meets, one lane per
   // component, for both passes over the tile
   template <int S>
@@ -537,6 +553,7 @@ struct Model<SMCX_GBSINE> {
   }
   // LIN: every component of the particle takes the linear tile phase (gb_chord_ok)
   __device__ static bool chord_ok(const C& c, int S) { return gb_chord_ok(c, S); }
+  __device__ static void linearize(C& c, int S) { gb_linearize(c, S); }
   // sinusoids span every tile: nothing to prepare
   template <int S>
   __device__ static void prepare(C*, int, int64_t, int) {}
@@ -969,6 +986,8 @@ __device__ __forceinline__ void pop_item(const PopArgs& a, int64_t item, int lan
     off_chord |= !M::chord_ok(cst[k], S);
   }
   const bool lin = __builtin_amdgcn_ballot_w64(off_chord) == 0;
+  if (lin)  // each lane its own components
+    for (int k = lane; k < K; k += 64) M::linearize(cst[k], S);
   wave_sync();
 
   const int64_t cs = a.s_lo + (int64_t)c * a.chunk_len;

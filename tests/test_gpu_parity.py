@@ -83,6 +83,37 @@ def test_gb_nonzero_start_time(lib, orc):
     pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
 
 
+def test_gb_phase_at_the_range_limit(lib, orc):
+    """A sinusoid's phase must stay below 2^19 cycles over the samples (the
+    fixed-point reduction relies on it). A start time that puts the largest
+    phases at about 0.9 of that limit is at parity; a particle holding one
+    component beyond it gets NaN outputs and raises the device flag, and the
+    others are untouched."""
+    w = wl.make_config("gb_grad", N=48, T=4000, k_lo=1, k_hi=8)
+    th = w.theta.reshape(-1, w.P)
+    w.t_start = 0.9 * 2.0 ** 19 / th[:, 1].max() - w.T * w.dt
+    phase_max = th[:, 1].max() * (w.t_start + w.T * w.dt)
+    assert 0.85 * 2 ** 19 < phase_max < 2 ** 19
+    say("gb_phase_limit", "t_start", w.t_start, "largest phase", phase_max)
+    s = Setup(lib, w)
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+    # one component of particle 5 moved beyond the limit
+    th2 = th.copy()
+    th2[w.offsets[5], 1] = 1.2 * 2.0 ** 19 / w.t_start
+    s.th = pm.to_dev(th2)
+    logl2, _ = lib.logl_grad_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    with pytest.raises(lib.SmcxError) as ei:
+        s.prob.device_status()
+    assert "2^19" in str(ei.value)
+    l2 = logl2.cpu().numpy()
+    assert np.isnan(l2[5]) and np.array_equal(np.delete(l2, 5), np.delete(logl, 5))
+    s.prob.device_status()  # cleared
+
+
 @pytest.mark.parametrize("S", [8, 16, 32, 64])
 def test_gb_chirps_beyond_the_linear_tile_phase(lib, orc, S):
     """Within a tile the sinusoid's phase is taken as linear in the lane's
