@@ -65,20 +65,25 @@ CLOCK_HZ = 2.4e9
 #   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
 #   sinusoid forward: int add, phase float (one funnel shift), sin,
 #                     fmac                                             4.5
-#   sinusoid adjoint: the phasor turned by a complex multiply (mul,
-#                     fma, mul, fma) on 7 of 8 samples, taken from sin
-#                     and cos (int add, funnel shift, sin, cos) on the
-#                     8th; then fmac, fmac, add, add          (7 x 6 + 8.5) / 8
+#   sinusoid adjoint: the phasor in groups of four samples, the first
+#                     turned from the previous group's first and the
+#                     second from the first by complex multiplies (mul,
+#                     fma, mul, fma: 3 each), the other two by the
+#                     three-term recurrence (fma, fma: 2 each), and the
+#                     tile's first taken from sin and cos (funnel shift,
+#                     sin, cos: 5); then fmac, fmac, add, add    5.5 + 2 / S
 # (sinusoids with the linear tile phase, which the workloads' chirps take;
-# the adjoint's three moment sums are running sums)
-SLOTS = {(0, "grad"): 12.0, (1, "grad"): 4.5 + 50.5 / 8.0, (0, "fwd"): 5.0, (1, "fwd"): 4.5}
+# the adjoint's three moment sums are running sums; S is the tile's samples
+# per lane)
+SLOTS = {(0, "grad"): lambda S: 12.0, (1, "grad"): lambda S: 4.5 + 5.5 + 2.0 / S,
+         (0, "fwd"): lambda S: 5.0, (1, "fwd"): lambda S: 4.5}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4582e+07, "kernels_sha1": "d799e5d3ad96c7cb"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3141e+07, "kernels_sha1": "d799e5d3ad96c7cb"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4588e+07, "kernels_sha1": "83ce50fc8b19c490"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3137e+07, "kernels_sha1": "83ce50fc8b19c490"}}
 
 
 def kernels_sha1():
@@ -91,17 +96,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(model, kind, comp_samples, kern_ms, kernel):
+def roofline(model, kind, comp_samples, kern_ms, kernel, S):
     """ALU roofline of the population kernel: its algorithmic work in FP32-FMA
     slots (times 2 flops) per launch over the launch's time, against the FP32
     FMA ceiling without packed instructions; the fraction of the published
-    (packed) figure is given beside it."""
-    slots = SLOTS[(model, kind)] * comp_samples
+    (packed) figure is given beside it. S: the launch's samples per lane and
+    tile."""
+    per = SLOTS[(model, kind)](S)
+    slots = per * comp_samples
     achieved = 2.0 * slots / (kern_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": kernel, "kernel_ms": round(kern_ms, 5),
-            "work": f"{comp_samples:.4e} component-samples x {SLOTS[(model, kind)]:g} "
+            "work": f"{comp_samples:.4e} component-samples x {per:g} "
                     f"FP32-FMA slots x 2 flops",
             "peak_basis": "FP32 FMA issue without packed instructions (64 lanes/CU/clock, "
                           "measured 63 by the issue probe)",
@@ -196,7 +203,7 @@ def bench_grad(args, w, dev, smcx, np, torch, cpu_seconds, cpu1_seconds, check_a
     log(f"[bench] {w.name}: {ms:.4f} ms/step, pop_kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
     rl = roofline(w.model, "grad", component_samples(w, 0, w.T), kern_ms,
                   f"pop_kernel<{w.model},{tuned[0]},true,{'true' if tuned[2] == 2 else 'false'}> "
-                  f"(fused forward+adjoint)")
+                  f"(fused forward+adjoint)", tuned[0])
     pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
     if pmc and pmc["kernels_sha1"] == kernels_sha1():
         rl["traffic"] = pmc["bytes"]
@@ -302,7 +309,7 @@ def bench_extend(args, w, dev, smcx, np, torch):
     value = w.N / (ms * 1e-3)
     log(f"[bench] reweight {ms:.3f} ms/step, segment kernel {kern_ms:.3f} ms")
     rl = roofline(w.model, "fwd", component_samples(w, T1, T2), kern_ms,
-                  "pop_kernel (segment forward)")
+                  "pop_kernel (segment forward)", tuned[0])
     cpu = accuracy = None
     if not args.no_cpu_baseline:
         import oracle

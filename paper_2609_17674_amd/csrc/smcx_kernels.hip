@@ -394,27 +394,52 @@ __device__ __forceinline__ void gb_adj_j(const GbTile& t, unsigned int F, const 
   }
 }
 
-// The adjoint sums of gb_adj_j with the linear tile phase, where the phasor
-// e^{i phase} of sample j + 1 is that of sample j turned by w = e^{i 2 pi D}:
-// a complex multiply (two multiplies, two FMAs) instead of a sin and a cos.
-// Every kGbAnchor-th sample takes the phasor from the hardware sin and cos
-// again, so that the rounding of w and of the products (about 2e-7 rad per
-// step) builds up over at most kGbAnchor - 1 steps. The adjoint only feeds
-// the gradient, whose tolerance is a hundred times wider than this.
-constexpr int kGbAnchor = 8;
+// The adjoint sums of gb_adj_j with the linear tile phase, the phasor
+// z_j = e^{i phase_j} by recurrences in groups of kGbGroup samples. The
+// first sample of the tile takes z from the hardware sin and cos; the first
+// of each later group is the previous group's first turned by
+// w4 = e^{i 2 pi kGbGroup D} (a complex multiply: two multiplies, two FMAs);
+// the second of a group is its first turned by w = e^{i 2 pi D}; the others
+// follow the three-term recurrence z_{j+1} = 2 cos(2 pi D) z_j - z_{j-1},
+// one FMA per part. A rounding error made at step k of the three-term
+// recurrence reaches step j multiplied by at most j - k (its propagator is
+// sin((j - k) 2 pi D) / sin(2 pi D)), which the short groups keep small;
+// over a tile of 32 samples the phasor stays within about 1e-6 of its exact
+// value (a few 1e-7 typically). The adjoint only feeds the gradient, whose
+// tolerance is 1e-5.
+constexpr int kGbGroup = 4;
 
 template <int S, int J = 0>
-__device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, unsigned int F, float ws, float wc,
-                                             const float (&r)[S], float zr, float zi, float& as,
-                                             float& A, float& B, float& C) {
+__device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, float ws, float wc, float wc2,
+                                             float w4s, float w4c, const float (&r)[S], float gr,
+                                             float gi, float zr, float zi, float pr, float pi,
+                                             float& as, float& A, float& B, float& C) {
   if constexpr (J < S) {
-    if constexpr (J % kGbAnchor == 0) {
-      const float ph = gb_rev1(F);
-      zi = __builtin_amdgcn_sinf(ph);
-      zr = __builtin_amdgcn_cosf(ph);
-    } else {
+    if constexpr (J == 0) {
+      const float ph = gb_rev1(t.F0);
+      gi = __builtin_amdgcn_sinf(ph);
+      gr = __builtin_amdgcn_cosf(ph);
+      zr = gr;
+      zi = gi;
+    } else if constexpr (J % kGbGroup == 0) {
+      const float nr = __builtin_fmaf(-gi, w4s, gr * w4c);
+      const float ni = __builtin_fmaf(gr, w4s, gi * w4c);
+      gr = nr;
+      gi = ni;
+      zr = gr;
+      zi = gi;
+    } else if constexpr (J % kGbGroup == 1) {
       const float nr = __builtin_fmaf(-zi, ws, zr * wc);
       const float ni = __builtin_fmaf(zr, ws, zi * wc);
+      pr = zr;
+      pi = zi;
+      zr = nr;
+      zi = ni;
+    } else {
+      const float nr = __builtin_fmaf(wc2, zr, -pr);
+      const float ni = __builtin_fmaf(wc2, zi, -pi);
+      pr = zr;
+      pi = zi;
       zr = nr;
       zi = ni;
     }
@@ -422,8 +447,7 @@ __device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, unsigned int F, fl
     A = __builtin_fmaf(r[J], zr, A);
     B += A;
     C += B;
-    const unsigned int Fn = (J + 1) % kGbAnchor == 0 ? F + (unsigned int)kGbAnchor * t.D : F;
-    gb_adj_rot_j<S, J + 1>(t, Fn, ws, wc, r, zr, zi, as, A, B, C);
+    gb_adj_rot_j<S, J + 1>(t, ws, wc, wc2, w4s, w4c, r, gr, gi, zr, zi, pr, pi, as, A, B, C);
   }
 }
 
@@ -577,8 +601,10 @@ struct Model<SMCX_GBSINE> {
       float as = 0.f, A = 0.f, B = 0.f, Cs = 0.f;
       if constexpr (LIN) {
         const float wd = (float)(int)t.D * 0x1p-32f;  // step in revolutions
-        gb_adj_rot_j<S>(t, t.F0, __builtin_amdgcn_sinf(wd), __builtin_amdgcn_cosf(wd), r, 0.f,
-                        0.f, as, A, B, Cs);
+        const float wd4 = (float)(int)(t.D * (unsigned int)kGbGroup) * 0x1p-32f;
+        const float wc = __builtin_amdgcn_cosf(wd);
+        gb_adj_rot_j<S>(t, __builtin_amdgcn_sinf(wd), wc, 2.f * wc, __builtin_amdgcn_sinf(wd4),
+                        __builtin_amdgcn_cosf(wd4), r, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, as, A, B, Cs);
       } else {
         gb_adj_j<S, LIN>(t, t.F0, r, as, A, B, Cs);
       }
