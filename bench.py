@@ -59,31 +59,37 @@ CLOCK_HZ = 2.4e9
 
 # Issue cost of one component-sample in FP32-FMA slots (one slot = one lane
 # of a full-rate FMA issue): FMA, conversion and funnel shift 1, two-operand
-# multiply or add (FP32 or integer) 1/2, transcendental 2, from the rates
-# above. The operations are those the method needs per component-sample:
-#   pulse forward: add, fmac, mul, exp2, fmac                          5
-#   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          7
-#   sinusoid forward: int add, phase float (one funnel shift), sin,
-#                     fmac                                             4.5
+# multiply or add (FP32 or integer) 1/2, from the rates above, and a
+# transcendental 1, the issue slot it takes from the other vector work. A
+# stream of transcendentals alone runs at their own unit's rate (two slots
+# each), but in these kernels that unit overlaps with the rest: charged at
+# two slots, the forward-only sinusoid pass would run at 1.04 of the
+# ceiling, and the counters put the unit's busy share at 15-34% of the
+# kernels' time, so it is never the limit. The operations are those the
+# method needs per component-sample:
+#   pulse forward: add, fmac, mul, exp2, fmac                          4
+#   pulse adjoint: add, fmac, mul, exp2, mul, add, fmac, fmac          6
+#   sinusoid forward: in groups of four samples, two sines from the
+#                     phase (int add, one funnel shift, sin: 2.5 each),
+#                     two by the three-term relation (fma: 1 each),
+#                     and four fmac                          (5 + 2 + 4) / 4
 #   sinusoid adjoint: the phasor in groups of four samples, the first
 #                     turned from the previous group's first and the
 #                     second from the first by complex multiplies (mul,
 #                     fma, mul, fma: 3 each), the other two by the
-#                     three-term recurrence (fma, fma: 2 each), and the
-#                     tile's first taken from sin and cos (funnel shift,
-#                     sin, cos: 5); then fmac, fmac, add, add    5.5 + 2 / S
+#                     three-term recurrence (fma, fma: 2 each), the
+#                     tile's first from sin and cos (funnel shift, sin,
+#                     cos: 3); then fmac, fmac, add, add              5.5
 # (sinusoids with the linear tile phase, which the workloads' chirps take;
-# the adjoint's three moment sums are running sums; S is the tile's samples
-# per lane)
-SLOTS = {(0, "grad"): lambda S: 12.0, (1, "grad"): lambda S: 4.5 + 5.5 + 2.0 / S,
-         (0, "fwd"): lambda S: 5.0, (1, "fwd"): lambda S: 4.5}
+# the adjoint's three moment sums are running sums)
+SLOTS = {(0, "grad"): 10.0, (1, "grad"): 2.75 + 5.5, (0, "fwd"): 4.0, (1, "fwd"): 2.75}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4588e+07, "kernels_sha1": "83ce50fc8b19c490"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3137e+07, "kernels_sha1": "83ce50fc8b19c490"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4607e+07, "kernels_sha1": "db7d5c955db12e3f"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3133e+07, "kernels_sha1": "db7d5c955db12e3f"}}
 
 
 def kernels_sha1():
@@ -96,13 +102,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(model, kind, comp_samples, kern_ms, kernel, S):
+def roofline(model, kind, comp_samples, kern_ms, kernel):
     """ALU roofline of the population kernel: its algorithmic work in FP32-FMA
     slots (times 2 flops) per launch over the launch's time, against the FP32
     FMA ceiling without packed instructions; the fraction of the published
-    (packed) figure is given beside it. S: the launch's samples per lane and
-    tile."""
-    per = SLOTS[(model, kind)](S)
+    (packed) figure is given beside it."""
+    per = SLOTS[(model, kind)]
     slots = per * comp_samples
     achieved = 2.0 * slots / (kern_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
@@ -203,7 +208,7 @@ def bench_grad(args, w, dev, smcx, np, torch, cpu_seconds, cpu1_seconds, check_a
     log(f"[bench] {w.name}: {ms:.4f} ms/step, pop_kernel {kern_ms:.4f} ms, {value:.4e} evals/s")
     rl = roofline(w.model, "grad", component_samples(w, 0, w.T), kern_ms,
                   f"pop_kernel<{w.model},{tuned[0]},true,{'true' if tuned[2] == 2 else 'false'}> "
-                  f"(fused forward+adjoint)", tuned[0])
+                  f"(fused forward+adjoint)")
     pmc = PMC_TRAFFIC.get((w.name, f"{tuned[0]},{tuned[1]},{tuned[2]}"))
     if pmc and pmc["kernels_sha1"] == kernels_sha1():
         rl["traffic"] = pmc["bytes"]
@@ -309,7 +314,7 @@ def bench_extend(args, w, dev, smcx, np, torch):
     value = w.N / (ms * 1e-3)
     log(f"[bench] reweight {ms:.3f} ms/step, segment kernel {kern_ms:.3f} ms")
     rl = roofline(w.model, "fwd", component_samples(w, T1, T2), kern_ms,
-                  "pop_kernel (segment forward)", tuned[0])
+                  "pop_kernel (segment forward)")
     cpu = accuracy = None
     if not args.no_cpu_baseline:
         import oracle

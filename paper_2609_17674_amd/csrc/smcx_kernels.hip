@@ -451,6 +451,32 @@ __device__ __forceinline__ void gb_adj_rot_j(const GbTile& t, float ws, float wc
   }
 }
 
+// The forward pass with the linear tile phase, in groups of four samples:
+// the second and third sines come from the hardware, the first and fourth
+// from the three-term relation s_{j+1} + s_{j-1} = 2 cos(2 pi D) s_j
+// applied once backwards and once forwards (one FMA each). Each derived
+// value is one step from hardware values, so its error stays within about
+// three times theirs: 6.6e-7 at most and 1.2e-7 rms against 1.6e-7 and
+// 0.7e-7 for the hardware sine alone (FP32 emulation with the hardware's
+// error), where two steps from the group's first two sines gave 1.4e-6.
+template <int S, int G = 0>
+__device__ __forceinline__ void gb_fwd_rec_j(unsigned int F1, unsigned int D, unsigned int D4,
+                                             float wc2, float A, float (&r)[S]) {
+  static_assert(kGbGroup == 4, "groups of four samples");
+  if constexpr (G < S / kGbGroup) {
+    constexpr int J = G * kGbGroup;
+    const float s1 = __builtin_amdgcn_sinf(gb_rev1(F1));
+    const float s2 = __builtin_amdgcn_sinf(gb_rev1(F1 + D));
+    const float s0 = __builtin_fmaf(wc2, s1, -s2);
+    const float s3 = __builtin_fmaf(wc2, s2, -s1);
+    r[J] = __builtin_fmaf(-A, s0, r[J]);
+    r[J + 1] = __builtin_fmaf(-A, s1, r[J + 1]);
+    r[J + 2] = __builtin_fmaf(-A, s2, r[J + 2]);
+    r[J + 3] = __builtin_fmaf(-A, s3, r[J + 3]);
+    gb_fwd_rec_j<S, G + 1>(F1 + D4, D, D4, wc2, A, r);
+  }
+}
+
 // sum x_j, sum j x_j, sum j^2 x_j over j < S from the final running sums:
 // B = sum (S - j) x_j and C = sum (S - j)(S - j + 1)/2 x_j.
 template <int S>
@@ -587,7 +613,13 @@ struct Model<SMCX_GBSINE> {
     for (int k = 0; k < K; ++k) {
       const C c = cst[k];
       const GbTile t = gb_tile<LIN, S>(c, u);
-      gb_fwd_j<S, LIN>(t, t.F0, c.A, r);
+      if constexpr (LIN) {
+        const float wd = (float)(int)t.D * 0x1p-32f;  // step in revolutions
+        gb_fwd_rec_j<S>(t.F0 + t.D, t.D, t.D * (unsigned int)kGbGroup,
+                        2.f * __builtin_amdgcn_cosf(wd), c.A, r);
+      } else {
+        gb_fwd_j<S, LIN>(t, t.F0, c.A, r);
+      }
     }
   }
   template <int S, bool LIN>
