@@ -114,6 +114,34 @@ def test_gb_phase_at_the_range_limit(lib, orc):
     s.prob.device_status()  # cleared
 
 
+@pytest.mark.parametrize("S", [8, 32])
+def test_gb_phase_steps_near_a_whole_and_a_half_cycle(lib, orc, S):
+    """With the linear tile phase the kernels step each lane's phasor by
+    D = 64 f dt cycles per sample with recurrences whose coefficient is
+    2 cos(2 pi D); at D near a whole or half cycle that coefficient is near
+    +-2 and the step angle is poorly resolved by it, the worst case for the
+    three-term relation. Frequencies that put D within 1e-6 of 0, 1/2 and
+    1/4 (and exactly on them), against the oracle."""
+    w = wl.make_config("gb_grad", N=40, T=5000, k_lo=1, k_hi=6)
+    th = w.theta.reshape(-1, w.P)
+    steps = np.array([0.0, 1e-6, 1.0 - 1e-6, 0.5, 0.5 - 1e-6, 0.5 + 1e-6, 0.25, 0.25 + 1e-6])
+    D = steps[np.arange(len(th)) % len(steps)]
+    th[:, 1] = (1.0 + D) / (64.0 * w.dt)   # 64 f dt = 1 + D cycles per block
+    th[:, 2] = 0.0                          # no chirp: D is the same in every tile
+    w.theta = th
+    say("gb_steps", S, "D values", steps)
+    s = Setup(lib, w)
+    for kind in (lib.KIND_GRAD, lib.KIND_LOGL):
+        s.prob.set_tiling(kind, S, 4096, 1)
+    logl, grad = run_grad(lib, s)
+    ref_l, ref_g = orc.logl_grad(w.model, s.d, w.t_start, w.dt, w.sigma, w.offsets, w.theta, w.beta)
+    pm.assert_logl(logl, ref_l)
+    pm.assert_grad(w.model, w.offsets, w.theta, grad, ref_g, w.T, w.dt)
+    l2 = lib.logl_batch(s.prob, s.off, s.th, s.beta)
+    torch.cuda.synchronize()
+    pm.assert_logl(l2.cpu().numpy(), ref_l)
+
+
 @pytest.mark.parametrize("S", [8, 16, 32, 64])
 def test_gb_chirps_beyond_the_linear_tile_phase(lib, orc, S):
     """Within a tile the sinusoid's phase is taken as linear in the lane's
