@@ -88,8 +88,8 @@ SLOTS = {(0, "grad"): 10.0, (1, "grad"): 2.75 + 5.5, (0, "fwd"): 4.0, (1, "fwd")
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs, scaled by the same counters' readings for a device copy of
 # known size. Valid only for the kernel source they were taken on (its hash).
-PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4607e+07, "kernels_sha1": "db7d5c955db12e3f"},
-               ("pulse_batch", "64,4096,1"): {"bytes": 1.3133e+07, "kernels_sha1": "db7d5c955db12e3f"}}
+PMC_TRAFFIC = {("gb_grad", "32,16384,1"): {"bytes": 2.4607e+07, "kernels_sha1": "bca9d37ca926281b"},
+               ("pulse_batch", "64,4096,1"): {"bytes": 1.3133e+07, "kernels_sha1": "bca9d37ca926281b"}}
 
 
 def kernels_sha1():

@@ -359,18 +359,19 @@ __device__ __forceinline__ void pulse_adj_j(const PulseC& c, float base, const f
   }
 }
 
-template <int S, bool LIN, int J = 0>
-__device__ __forceinline__ void gb_fwd_j(const GbTile& t, unsigned int F, float A, float (&r)[S]) {
+// The forward pass with the exact (quadratic) tile phase: a sine per sample.
+template <int S, int J = 0>
+__device__ __forceinline__ void gb_fwd_exact_j(const GbTile& t, unsigned int F, float A,
+                                               float (&r)[S]) {
   if constexpr (J + 1 < S) {
     const unsigned int F1 = F + t.D;
-    const float s0 = __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F));
-    const float s1 = __builtin_amdgcn_sinf(LIN ? gb_rev1(F1) : gb_rev<J + 1, LIN>(t, F1));
+    const float s0 = __builtin_amdgcn_sinf(gb_rev<J, false>(t, F));
+    const float s1 = __builtin_amdgcn_sinf(gb_rev<J + 1, false>(t, F1));
     r[J] = __builtin_fmaf(-A, s0, r[J]);
     r[J + 1] = __builtin_fmaf(-A, s1, r[J + 1]);
-    gb_fwd_j<S, LIN, J + 2>(t, F1 + t.D, A, r);
+    gb_fwd_exact_j<S, J + 2>(t, F1 + t.D, A, r);
   } else if constexpr (J < S) {
-    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(LIN ? gb_rev1(F) : gb_rev<J, LIN>(t, F)),
-                          r[J]);
+    r[J] = __builtin_fmaf(-A, __builtin_amdgcn_sinf(gb_rev<J, false>(t, F)), r[J]);
   }
 }
 
@@ -618,7 +619,7 @@ struct Model<SMCX_GBSINE> {
         gb_fwd_rec_j<S>(t.F0 + t.D, t.D, t.D * (unsigned int)kGbGroup,
                         2.f * __builtin_amdgcn_cosf(wd), c.A, r);
       } else {
-        gb_fwd_j<S, LIN>(t, t.F0, c.A, r);
+        gb_fwd_exact_j<S>(t, t.F0, c.A, r);
       }
     }
   }
