@@ -46,7 +46,7 @@ METRIC = "particle logL+grad evals/sec (ragged K) vs plain GPU form at ≤1e-6 r
 
 # MI355X: 256 CUs at 2.4 GHz, four SIMDs per CU. The published FP32 vector
 # peak, 157.3 TFLOP/s, counts packed FP32 FMAs (two per lane and cycle);
-# this build compiles with packed FP32 instructions disabled, and the issue
+# the library is compiled with packed FP32 instructions disabled, and the issue
 # probe (--workload issue_probe) measures what the vector units then do per
 # CU and clock: 63 lanes of v_fmac_f32 / v_fma_f32 (of 64), 96-105 of
 # v_mul_f32 / v_add_f32 / v_add_u32 (of 128), 58 of v_cvt_f32_i32 (of 64), 30
@@ -54,7 +54,7 @@ METRIC = "particle logL+grad evals/sec (ragged K) vs plain GPU form at ≤1e-6 r
 # v_fma_f64 (of 64). So the FP32
 # ceiling without packed instructions is 64 FMA lanes per CU and clock:
 PEAK_FP32_TFLOPS = 78.6          # 256 CUs x 64 lanes x 2 flops x 2.4 GHz
-PUBLISHED_FP32_TFLOPS = 157.3    # with packed FP32 FMAs (not used by this build)
+PUBLISHED_FP32_TFLOPS = 157.3    # with packed FP32 FMAs (which the library does not emit)
 CLOCK_HZ = 2.4e9
 
 # Issue cost of one component-sample in FP32-FMA slots (one slot = one lane
